@@ -1,0 +1,194 @@
+/*
+ * ieti.h -- C ABI of the MI355X (gfx950) inexact IETI-DP Poisson solver.
+ *
+ * Problem (Sec. 1, eq. (1)): find u in H^1_0(Omega) with
+ *     int grad u . grad v dx = int f v dx   for all v in H^1_0(Omega),
+ * Omega a multipatch domain whose patches are tensor-product B-spline images
+ * of (0,1)^d, d in {2,3} (Sec. 2).  The solver tears the patches apart,
+ * keeps the primal unknowns (patch vertices, optionally 3D edge averages)
+ * continuous through an energy-minimising primal subspace (Sec. 2, eq. (6))
+ * and solves the dual problem F lambda = d (eq. (4)) by CG with the scaled
+ * Dirichlet preconditioner.  Local solves are exact (banded Cholesky) or
+ * inexact multigrid-preconditioned (Sec. 3.2, eq. (7); the MG-MG variant of
+ * Sec. 3.3).
+ *
+ * Conventions
+ *  - Every call returns 0 on success or a negative IETI_E* code; no call
+ *    throws or exits.  ieti_strerror() names a code; ieti_last_error()
+ *    returns a thread-local message for the last failure.
+ *  - The caller owns every buffer it passes.  Setup copies what it needs;
+ *    no caller pointer is kept after a call returns.
+ *  - A handle owns all of its device memory and is not thread-safe: calls on
+ *    one handle must not overlap.  Different handles are independent.
+ *  - Coefficient ("torn") layout: patches in input order; inside patch k the
+ *    prod_i M_i coefficients, M_i = n_knots[i] - degree[i] - 1, direction 0
+ *    fastest.  Every copy of an interface coefficient holds the same value
+ *    in a returned solution; boundary coefficients are 0.
+ *  - Quadrature: (p_i+1) Gauss-Legendre points per element and direction.
+ *    Point order: patch by patch; inside a patch a tensor grid, direction 0
+ *    fastest; along direction i the points of element 0, then element 1, ...
+ */
+#ifndef IETI_H
+#define IETI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---- */
+#define IETI_OK               0
+#define IETI_EINVAL          -1  /* invalid argument (sizes, knots, degree, NaN/Inf in f, ...) */
+#define IETI_ENONCONFORMING  -2  /* patches meet along a side with different spline spaces or orientation */
+#define IETI_EGEOM           -3  /* geometry map not orientation preserving (det J <= 0 at a quadrature point) */
+#define IETI_ENOMEM          -4  /* host or device allocation failed, or HBM budget exceeded */
+#define IETI_ENOCONV         -5  /* outer CG did not reach tol in max_it iterations (u is still written) */
+#define IETI_EDEVICE         -6  /* HIP runtime error */
+#define IETI_ENOTSUP         -7  /* configuration outside what this build supports */
+
+/* ---- options ---- */
+#define IETI_LOCAL_MG     0   /* inexact local solves: flexible CG + multigrid V-cycle (MG-MG) */
+#define IETI_LOCAL_EXACT  1   /* exact local solves: banded Cholesky (D-D) */
+
+#define IETI_PRIMAL_VERTICES  1   /* primal unknowns at patch vertices */
+#define IETI_PRIMAL_EDGES     2   /* plus edge averages (3D) */
+
+typedef struct ieti_patch {
+    int32_t dim;               /* 2 or 3 */
+    int32_t degree[3];         /* spline degree per direction, 1..6 */
+    int32_t n_knots[3];        /* length of each knot vector */
+    const double* knots[3];    /* open knot vectors on [0,1]: p+1-fold end knots, simple interior knots (host) */
+    const double* ctrl;        /* prod_i M_i control points x dim doubles, direction 0 fastest (host) */
+} ieti_patch;
+
+typedef struct ieti_options {
+    int32_t local_solver;      /* IETI_LOCAL_MG (default) or IETI_LOCAL_EXACT */
+    int32_t mg_precision;      /* 32 or 64: arithmetic of V-cycles and their operator data (default 64) */
+    int32_t primal;            /* IETI_PRIMAL_VERTICES (default) or IETI_PRIMAL_VERTICES|IETI_PRIMAL_EDGES */
+    int32_t cheb_degree;       /* Chebyshev smoother degree per smoothing phase; 0 = tuned per spline degree */
+    double  cheb_lower;        /* lower end of the smoothing interval as a fraction of lambda_max; 0 = tuned */
+    int32_t prec_vcycles;      /* V-cycles for the Dirichlet problems in the preconditioner (default 2) */
+    int32_t max_it;            /* outer CG iteration limit (default 300) */
+    int32_t inner_max_it;      /* inner flexible-CG iteration limit (default 400) */
+    double  tol;               /* outer: ||r_k||_2 <= tol ||r_0||_2 (default 1e-8) */
+    double  inner_tol;         /* local Neumann solves in F, d and recovery (default 1e-10) */
+    double  basis_tol;         /* local solves building the primal basis (default 1e-12) */
+    int32_t check_every;       /* inner iterations between host convergence checks (default 4) */
+    int32_t use_graph;         /* capture fixed launch sequences as HIP graphs (default 1) */
+    int32_t device;            /* HIP device ordinal, -1 = current (default) */
+    void*   stream;            /* hipStream_t for all work, NULL = the library's own stream */
+    size_t  hbm_budget;        /* bytes of device memory the handle may use, 0 = unlimited */
+} ieti_options;
+
+typedef struct ieti_stats {
+    int32_t outer_iterations;
+    int32_t inner_iterations_max;      /* max over patches and calls */
+    double  inner_iterations_mean;     /* mean inner iterations per local solve (over patches and calls) */
+    double  residual_initial;          /* ||d||_2 */
+    double  residual_final;            /* ||r_k||_2 of the dual problem */
+    double  global_residual;           /* ||f - K u|| / ||f|| on the conforming system, FP64 */
+    double  time_rhs_ms;               /* load vector + d */
+    double  time_pcg_ms;               /* outer CG loop */
+    double  time_recovery_ms;          /* recovery of u + residual */
+    double  time_total_ms;             /* whole ieti_solve */
+    int64_t ndof_torn;                 /* sum of patch coefficient counts */
+    int64_t ndof_global;               /* conforming dofs without the boundary */
+    int64_t n_lambda;
+    int64_t n_primal;
+    int32_t breakdown;                 /* 1 if d vanished to rounding and lambda = 0 was returned */
+} ieti_stats;
+
+typedef struct ieti_handle ieti_handle;
+typedef struct ieti_plan ieti_plan;
+
+/* Fills *opt with the defaults listed above. */
+void ieti_default_options(ieti_options* opt);
+
+/*
+ * Host-side planning only (no device call): validates the patches, finds the
+ * interfaces (sides whose corner control points coincide; same orientation
+ * required), numbers boundary, primal and dual coefficients, builds the jump
+ * operators and the multigrid hierarchy and assembles all operator data in
+ * FP64.  primal_vertices: n_primal_vertices points (dim doubles each, host)
+ * selecting which interior patch vertices are primal; NULL = all of them.
+ * Every patch without a boundary side must keep at least one primal vertex.
+ */
+int ieti_plan_create(const ieti_patch* patches, int32_t n_patches,
+                     const double* primal_vertices, int32_t n_primal_vertices,
+                     const ieti_options* opt, ieti_plan** out);
+void ieti_plan_destroy(ieti_plan* plan);
+
+/* Sizes of a plan (host).  Any pointer may be NULL. */
+int ieti_plan_sizes(const ieti_plan* plan, int64_t* ndof_torn, int64_t* ndof_global, int64_t* n_lambda,
+                    int64_t* n_primal, int64_t* n_qp, int32_t* max_levels);
+
+/*
+ * Copies one internal host array of a plan into out (host) for inspection by
+ * tests; *count receives the number of elements written (or needed when out
+ * is NULL).  which: see IETI_ARR_* below; patch and level select the block.
+ */
+#define IETI_ARR_STENCIL      1  /* double: half stencil of K, nst x ndof (offset-major), level `level` */
+#define IETI_ARR_STENCIL_OFFS 2  /* int32: the nst offsets (o0,o1,o2) of patch/level, 3 per entry */
+#define IETI_ARR_PROLONG      3  /* double: dense M_fine x M_coarse 1D prolongation of direction `level>>8`, fine level `level&255` */
+#define IETI_ARR_SHAPE        4  /* int32: M0, M1, M2 of patch/level */
+#define IETI_ARR_MASKS        5  /* int32: [boundary side bits, primal corner bits, n_levels] of a patch */
+#define IETI_ARR_LAMBDA_MAP   6  /* int64: per multiplier (pos_plus, pos_minus) in the torn layout */
+#define IETI_ARR_QP_WEIGHT    7  /* double: w_q |det J_q| of patch at level 0 */
+#define IETI_ARR_LMAX         8  /* double: [lambda_max Neumann, lambda_max Dirichlet] of D^{-1}K, patch/level */
+#define IETI_ARR_PRIMAL_MAP   9  /* int64: per local primal constraint of `patch`: global primal index */
+int ieti_plan_array(const ieti_plan* plan, int32_t which, int32_t patch, int32_t level, void* out,
+                    int64_t* count);
+
+/* Physical coordinates of all quadrature points (n_qp x dim doubles, host). */
+int ieti_plan_quadrature(const ieti_plan* plan, double* x_qp_host);
+
+/*
+ * Setup: plans (as ieti_plan_create) and builds the device state: operator
+ * data in FP64 and the multigrid precision, the primal basis by batched
+ * local solves to basis_tol, the coarse matrix S_PiPi and its factorisation.
+ */
+int ieti_setup(const ieti_patch* patches, int32_t n_patches,
+               const double* primal_vertices, int32_t n_primal_vertices,
+               const ieti_options* opt, ieti_handle** out);
+
+/* Physical quadrature points, n_qp x dim doubles; x_qp is a device pointer if on_device != 0. */
+int ieti_quadrature(const ieti_handle* h, double* x_qp, int32_t on_device, int64_t* n_qp);
+
+/*
+ * Solve for one right-hand side.  f_qp: f at the ieti_quadrature points
+ * (n_qp doubles, device pointer).  u: ndof_torn doubles (device pointer),
+ * the torn layout described above.  stats may be NULL.  Runs on the
+ * handle's stream and synchronises it before returning.
+ */
+int ieti_solve(ieti_handle* h, const double* f_qp, double* u, ieti_stats* stats);
+
+/* Number of quadrature points and torn dofs of a handle. */
+int ieti_sizes(const ieti_handle* h, int64_t* n_qp, int64_t* ndof_torn, int64_t* device_bytes);
+
+void ieti_destroy(ieti_handle* h);
+
+/*
+ * Kernel timing for roofline reports.  With profiling enabled, every launch
+ * of the kernel classes below is bracketed by HIP events on the handle's
+ * stream, and its algorithmic bytes (each array the kernel must stream
+ * counted once: vectors and the half-stencil operator data) are added up.
+ * Enabling resets the counters.  Query returns launches, summed kernel time
+ * (ms) and summed algorithmic bytes of a class since the last reset.
+ */
+#define IETI_KPROF_SMOOTH_FINE  0   /* Chebyshev sweep (stencil + fused update) on the finest level */
+#define IETI_KPROF_APPLY64      1   /* FP64 stiffness apply + fused dot products of the flexible CG */
+#define IETI_KPROF_RESID_FINE   2   /* residual sweep on the finest level before restriction */
+#define IETI_KPROF_COUNT        3
+int ieti_profile_enable(ieti_handle* h, int32_t enable);
+int ieti_profile_query(const ieti_handle* h, int32_t kernel, int64_t* launches, double* total_ms,
+                       double* total_bytes);
+
+const char* ieti_strerror(int code);
+const char* ieti_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IETI_H */

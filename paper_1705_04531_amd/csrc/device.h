@@ -1,0 +1,44 @@
+// Device-side descriptors shared by the HIP kernels and the runtime.
+#pragma once
+#include <cstdint>
+
+namespace ieti {
+
+constexpr int TILE = 256;        // coefficients per work-group tile (one per thread)
+constexpr int PW = 8;            // padded width of 1D transfer bands (degree <= 6)
+constexpr int NPMAX = 20;        // local primal constraints per patch (8 vertices + 12 edges)
+
+// One patch at one multigrid level.
+struct PatchLev {
+    int32_t M[3];          // basis functions per direction (1 in unused directions)
+    int32_t p[3];          // degree per direction (0 in unused directions)
+    int32_t dim, nst;
+    uint32_t mbits[3];     // per mode (N, D, K): side bits | corner bits << 8
+    int32_t patch;         // patch id
+    int32_t coarse;        // index of the same patch in the next coarser level, -1 if coarsest here
+    int32_t fine;          // index of the same patch in the next finer level, -1 on level 0
+    int64_t n;             // prod M
+    int64_t voff;          // first coefficient in the level's vectors
+    int64_t coff;          // first entry (s = 0) in the level's stencil array
+    int64_t cstride;       // distance between consecutive stencil entries s, s+1
+    double lmax[2];        // lambda_max(D^{-1}K), modes N and D
+    double clo;            // lower end of the Chebyshev interval (x lambda_max)
+    int64_t toff[3];       // prolongation table offsets per direction (fine = this level)
+    int64_t roff[3];       // restriction table offsets per direction (coarse = next level)
+    int64_t invoff;        // coarsest level: offset of the dense inverses (mode N, then mode D)
+};
+
+// Level-0 quadrature layout of one patch (load vector).
+struct PatchQ {
+    int32_t nel[3];        // elements per direction
+    int32_t Q[3];          // quadrature points per direction
+    int64_t qoff;          // first quadrature point of the patch
+    int64_t boff[3];       // 1D basis tables: Q[d] x (p+1) values per direction
+};
+
+struct Tile {
+    int32_t pl;            // index into the level's PatchLev array
+    int32_t start;         // first coefficient of the tile
+};
+
+}  // namespace ieti

@@ -1,0 +1,1224 @@
+// Host-side planning of an IETI-DP solve (no device calls).
+//
+//  * interfaces and the torn numbering (Sec. 2: patches, interface Gamma,
+//    tearing of the interface unknowns);
+//  * primal constraints -- vertex values and optional 3D edge averages
+//    (the strongly enforced continuity conditions of Sec. 2 / Sec. 4) --
+//    and the fully redundant Lagrange multipliers of the jump operator B;
+//  * the multigrid hierarchy of every patch: nested h-levels obtained by
+//    removing every second breakpoint, the canonical embedding between them
+//    (knot insertion), Galerkin stiffness of each level on the fine geometry
+//    (Sec. 4: nested grids, p fixed), dense inverses on the coarsest level;
+//  * Chebyshev smoothing intervals (power iteration on D^{-1} K).
+//
+// Operator data are half stencils: for coefficient i and offset o with o in
+// the "upper" half (last nonzero component positive, diagonal first),
+// coef[s][i] = K(i, i + o_s); the lower half follows from symmetry.
+#include "plan.h"
+
+#include <algorithm>
+#include <array>
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <map>
+#include <memory>
+#include <numeric>
+#include <thread>
+
+namespace ieti {
+
+static thread_local std::string g_last_error;
+void set_last_error(const std::string& s) { g_last_error = s; }
+const char* last_error() { return g_last_error.c_str(); }
+
+void default_options(ieti_options* o) {
+    std::memset(o, 0, sizeof(*o));
+    o->local_solver = IETI_LOCAL_MG;
+    o->mg_precision = 64;
+    o->primal = IETI_PRIMAL_VERTICES;
+    o->cheb_degree = 0;
+    o->cheb_lower = 0.0;
+    o->prec_vcycles = 2;
+    o->max_it = 300;
+    o->inner_max_it = 400;
+    o->tol = 1e-8;
+    o->inner_tol = 1e-10;
+    o->basis_tol = 1e-12;
+    o->check_every = 4;
+    o->use_graph = 1;
+    o->device = -1;
+    o->stream = nullptr;
+    o->hbm_budget = 0;
+}
+
+// Smoother choice per spline degree, from a sweep of inner flexible-CG
+// iterations x matrix-vector products to reach 1e-10 (degree of the
+// Chebyshev polynomial per smoothing phase, lower end of its interval).
+int cheb_degree_for(const ieti_options& o, int pmax) {
+    if (o.cheb_degree > 0) return o.cheb_degree;
+    if (pmax <= 2) return 2;
+    if (pmax == 3) return 3;
+    return 4;
+}
+double cheb_lower_for(const ieti_options& o, int pmax) {
+    if (o.cheb_lower > 0) return o.cheb_lower;
+    if (pmax <= 2) return 0.1;
+    if (pmax == 3) return 0.05;
+    return 0.02;
+}
+
+// ----------------------------------------------------------------------------
+// thread pool helper
+static void parallel_for(int n, const std::function<void(int)>& fn) {
+    int nt = (int)std::min<unsigned>(std::max(1u, std::thread::hardware_concurrency()), 16u);
+    nt = std::min(nt, n);
+    if (nt <= 1) {
+        for (int i = 0; i < n; ++i) fn(i);
+        return;
+    }
+    std::atomic<int> next(0);
+    std::vector<std::thread> th;
+    std::vector<std::string> errs(nt);
+    std::vector<int> codes(nt, 0);
+    for (int t = 0; t < nt; ++t) {
+        th.emplace_back([&, t] {
+            try {
+                for (int i = next++; i < n; i = next++) fn(i);
+            } catch (const Error& e) {
+                codes[t] = e.code;
+                errs[t] = e.what();
+            } catch (const std::exception& e) {
+                codes[t] = IETI_EINVAL;
+                errs[t] = e.what();
+            }
+        });
+    }
+    for (auto& x : th) x.join();
+    for (int t = 0; t < nt; ++t)
+        if (codes[t]) throw Error(codes[t], errs[t]);
+}
+
+// ----------------------------------------------------------------------------
+// B-splines
+
+// Span k with t[k] <= x < t[k+1] among the non-empty spans p..m-1 (m basis functions).
+static int find_span(const std::vector<double>& t, int p, double x) {
+    int m = (int)t.size() - p - 1;
+    if (x >= t[m]) return m - 1;
+    if (x <= t[p]) return p;
+    int lo = p, hi = m;
+    while (hi - lo > 1) {
+        int mid = (lo + hi) / 2;
+        if (x < t[mid]) hi = mid; else lo = mid;
+    }
+    return lo;
+}
+
+// Values and first derivatives of the p+1 basis functions k-p..k that are
+// nonzero on span k, built degree by degree from the Cox-de Boor recursion.
+static void basis_on_span(const std::vector<double>& t, int p, int k, double x, double* N, double* dN) {
+    double prev[16], cur[16];
+    prev[0] = 1.0;   // degree 0: function k
+    for (int q = 1; q <= p; ++q) {
+        // degree q: functions k-q .. k; prev holds degree q-1 functions k-q+1 .. k
+        for (int r = 0; r <= q; ++r) {
+            int i = k - q + r;
+            double v = 0.0;
+            if (r >= 1) v += (x - t[i]) / (t[i + q] - t[i]) * prev[r - 1];
+            if (r <= q - 1) v += (t[i + q + 1] - x) / (t[i + q + 1] - t[i + 1]) * prev[r];
+            cur[r] = v;
+        }
+        if (q == p && dN) {
+            for (int r = 0; r <= p; ++r) {
+                int i = k - p + r;
+                double d = 0.0;
+                if (r >= 1) d += p / (t[i + p] - t[i]) * prev[r - 1];
+                if (r <= p - 1) d -= p / (t[i + p + 1] - t[i + 1]) * prev[r];
+                dN[r] = d;
+            }
+        }
+        for (int r = 0; r <= q; ++r) prev[r] = cur[r];
+    }
+    if (p == 0 && dN) dN[0] = 0.0;
+    for (int r = 0; r <= p; ++r) N[r] = prev[r];
+}
+
+static std::vector<double> breakpoints(const std::vector<double>& t) {
+    std::vector<double> b;
+    for (double v : t)
+        if (b.empty() || v > b.back()) b.push_back(v);
+    return b;
+}
+
+// Gauss-Legendre nodes/weights on [0,1] by Newton's method on P_n.
+static void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+    x.assign(n, 0.0);
+    w.assign(n, 0.0);
+    const double pi = 3.14159265358979323846;
+    for (int i = 0; i < n; ++i) {
+        double z = std::cos(pi * (i + 0.75) / (n + 0.5));
+        double dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= n; ++k) {
+                double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            if (n == 1) { p1 = z; p0 = 1.0; }
+            dp = n * (z * p1 - p0) / (z * z - 1.0);
+            double dz = p1 / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-16) break;
+        }
+        double p0 = 1.0, p1 = z;
+        for (int k = 2; k <= n; ++k) {
+            double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+            p0 = p1;
+            p1 = p2;
+        }
+        if (n == 1) { p1 = z; p0 = 1.0; }
+        dp = n * (z * p1 - p0) / (z * z - 1.0);
+        x[n - 1 - i] = 0.5 * (z + 1.0);
+        w[n - 1 - i] = 1.0 / ((1.0 - z * z) * dp * dp);   // = 2/((1-z^2)P'^2) scaled by 1/2
+    }
+}
+
+// Canonical embedding S_p(coarse) -> S_p(fine) by inserting the missing knots
+// one at a time (Boehm): each insertion of x into span k maps coefficients by
+// Q_i = a_i P_i + (1 - a_i) P_{i-1}, a_i = 1 (i <= k-p), (x - t_i)/(t_{i+p} - t_i)
+// (k-p < i <= k), 0 (i > k).  Returns the dense Mf x Mc matrix (row-major).
+static std::vector<double> prolongation(const std::vector<double>& coarse, const std::vector<double>& fine, int p,
+                                        int& Mf, int& Mc) {
+    Mc = (int)coarse.size() - p - 1;
+    std::vector<double> t = coarse;
+    int rows = Mc;
+    std::vector<double> P((size_t)Mc * Mc, 0.0);
+    for (int i = 0; i < Mc; ++i) P[(size_t)i * Mc + i] = 1.0;
+    std::vector<double> bc = breakpoints(coarse), bf = breakpoints(fine);
+    for (double x : bf) {
+        if (std::binary_search(bc.begin(), bc.end(), x)) continue;
+        int k = find_span(t, p, x);
+        std::vector<double> Q((size_t)(rows + 1) * Mc, 0.0);
+        for (int i = 0; i <= rows; ++i) {
+            double a;
+            if (i <= k - p) a = 1.0;
+            else if (i > k) a = 0.0;
+            else a = (x - t[i]) / (t[i + p] - t[i]);
+            for (int c = 0; c < Mc; ++c) {
+                double v = 0.0;
+                if (a != 0.0 && i < rows) v += a * P[(size_t)i * Mc + c];
+                if (a != 1.0 && i >= 1) v += (1.0 - a) * P[(size_t)(i - 1) * Mc + c];
+                Q[(size_t)i * Mc + c] = v;
+            }
+        }
+        t.insert(t.begin() + k + 1, x);
+        P.swap(Q);
+        ++rows;
+    }
+    Mf = rows;
+    if ((int)fine.size() - p - 1 != Mf) throw Error(IETI_EINVAL, "knot insertion did not reach the fine knot vector");
+    for (auto& v : P)
+        if (std::fabs(v) < 1e-15) v = 0.0;
+    return P;
+}
+
+// ----------------------------------------------------------------------------
+// per-direction quadrature tables of one level
+
+struct DirTable {
+    int p = 0, nel = 0, Q = 0;          // Q = nel * (p + 1) points
+    std::vector<double> xi, w;          // parameter points and weights
+    std::vector<int> first;             // first nonzero space function of the element of each point
+    std::vector<double> N, dN;          // (p+1) per point: space basis
+    int pg = 0;
+    std::vector<int> gfirst;            // first nonzero geometry function at each point
+    std::vector<double> G, dG;          // (pg+1) per point: geometry basis
+};
+
+static DirTable make_dir(const std::vector<double>& tl, int p, const std::vector<double>& tg, int pg) {
+    DirTable d;
+    d.p = p;
+    d.pg = pg;
+    std::vector<double> b = breakpoints(tl);
+    d.nel = (int)b.size() - 1;
+    std::vector<double> gx, gw;
+    gauss_legendre(p + 1, gx, gw);
+    d.Q = d.nel * (p + 1);
+    d.xi.resize(d.Q);
+    d.w.resize(d.Q);
+    d.first.resize(d.Q);
+    d.N.resize((size_t)d.Q * (p + 1));
+    d.dN.resize((size_t)d.Q * (p + 1));
+    d.gfirst.resize(d.Q);
+    d.G.resize((size_t)d.Q * (pg + 1));
+    d.dG.resize((size_t)d.Q * (pg + 1));
+    for (int e = 0; e < d.nel; ++e) {
+        double a = b[e], c = b[e + 1];
+        // span of element e in the space knots: last k with t[k] == a
+        int k = find_span(tl, p, 0.5 * (a + c));
+        for (int g = 0; g <= p; ++g) {
+            int q = e * (p + 1) + g;
+            double x = a + (c - a) * gx[g];
+            d.xi[q] = x;
+            d.w[q] = (c - a) * gw[g];
+            d.first[q] = k - p;
+            basis_on_span(tl, p, k, x, &d.N[(size_t)q * (p + 1)], &d.dN[(size_t)q * (p + 1)]);
+            int kg = find_span(tg, pg, x);
+            d.gfirst[q] = kg - pg;
+            basis_on_span(tg, pg, kg, x, &d.G[(size_t)q * (pg + 1)], &d.dG[(size_t)q * (pg + 1)]);
+        }
+    }
+    return d;
+}
+
+// 1D Galerkin matrices between the level's functions: A[u][v](i,j) = sum_q w X_u(i) X_v(j),
+// X_0 = value, X_1 = derivative.  Dense M x M.
+static void one_d_matrices(const DirTable& d, int M, std::vector<double> A[2][2]) {
+    for (int u = 0; u < 2; ++u)
+        for (int v = 0; v < 2; ++v) A[u][v].assign((size_t)M * M, 0.0);
+    int p = d.p;
+    for (int q = 0; q < d.Q; ++q) {
+        const double* N = &d.N[(size_t)q * (p + 1)];
+        const double* dN = &d.dN[(size_t)q * (p + 1)];
+        for (int a = 0; a <= p; ++a)
+            for (int b = 0; b <= p; ++b) {
+                int i = d.first[q] + a, j = d.first[q] + b;
+                double X[2] = {N[a], dN[a]}, Y[2] = {N[b], dN[b]};
+                for (int u = 0; u < 2; ++u)
+                    for (int v = 0; v < 2; ++v) A[u][v][(size_t)i * M + j] += d.w[q] * X[u] * Y[v];
+            }
+    }
+}
+
+// half-stencil offsets: diagonal first; then o2 = 0, o1 = 0, o0 > 0; o2 = 0, o1 > 0; o2 > 0
+static void half_offsets(int dim, const int* p, std::vector<int32_t>& offs) {
+    offs.clear();
+    int p2 = dim == 3 ? p[2] : 0;
+    for (int o2 = 0; o2 <= p2; ++o2)
+        for (int o1 = (o2 == 0 ? 0 : -p[1]); o1 <= p[1]; ++o1)
+            for (int o0 = (o2 == 0 && o1 == 0 ? 0 : -p[0]); o0 <= p[0]; ++o0) {
+                offs.push_back(o0);
+                offs.push_back(o1);
+                offs.push_back(o2);
+            }
+}
+
+static inline int64_t lin(const int* M, int i0, int i1, int i2) { return i0 + (int64_t)M[0] * (i1 + (int64_t)M[1] * i2); }
+
+// Assemble the half stencil of level `L` of patch `P` (space = L.knots, geometry = patch level 0).
+// On level 0 also the quadrature weights w |det J| and the physical points.
+static void assemble_level(Patch& P, Level& L, bool level0) {
+    const int dim = P.dim;
+    DirTable dt[3];
+    for (int d = 0; d < dim; ++d) dt[d] = make_dir(L.knots[d], P.p[d], P.knots[d], P.p[d]);
+    int Mg[3] = {1, 1, 1};
+    for (int d = 0; d < dim; ++d) Mg[d] = (int)P.knots[d].size() - P.p[d] - 1;
+    half_offsets(dim, P.p, L.offs);
+    L.nst = (int)L.offs.size() / 3;
+    L.coef.assign((size_t)L.nst * L.n, 0.0);
+    // slot table: (o0+p0) + (2p0+1)((o1+p1) + (2p1+1)(o2+p2)) -> s
+    int w0 = 2 * P.p[0] + 1, w1 = 2 * P.p[1] + 1, w2 = dim == 3 ? 2 * P.p[2] + 1 : 1;
+    int p2 = dim == 3 ? P.p[2] : 0;
+    std::vector<int> slot((size_t)w0 * w1 * w2, -1);
+    for (int s = 0; s < L.nst; ++s) {
+        int o0 = L.offs[3 * s], o1 = L.offs[3 * s + 1], o2 = L.offs[3 * s + 2];
+        slot[(o0 + P.p[0]) + (size_t)w0 * ((o1 + P.p[1]) + (size_t)w1 * (o2 + p2))] = s;
+    }
+    const int Q0 = dt[0].Q, Q1 = dt[1].Q, Q2 = dim == 3 ? dt[2].Q : 1;
+    if (level0) {
+        for (int d = 0; d < dim; ++d) P.qpN[d] = dt[d].N;
+        P.n_qp = (int64_t)Q0 * Q1 * Q2;
+        P.qpw.assign(P.n_qp, 0.0);
+        P.qpx.assign(P.n_qp * dim, 0.0);
+    }
+    if (P.affine) {
+        // constant Jacobian A: columns = ctrl(corner e_d) - ctrl(corner 0)
+        double A[3][3] = {{0}}, c0[3] = {0};
+        for (int c = 0; c < dim; ++c) c0[c] = P.ctrl[c];
+        for (int d = 0; d < dim; ++d) {
+            int idx[3] = {0, 0, 0};
+            idx[d] = Mg[d] - 1;
+            int64_t k = lin(Mg, idx[0], idx[1], idx[2]);
+            for (int c = 0; c < dim; ++c) A[c][d] = P.ctrl[k * dim + c] - c0[c];
+        }
+        double det, Ai[3][3];
+        if (dim == 2) {
+            det = A[0][0] * A[1][1] - A[0][1] * A[1][0];
+            Ai[0][0] = A[1][1] / det; Ai[0][1] = -A[0][1] / det;
+            Ai[1][0] = -A[1][0] / det; Ai[1][1] = A[0][0] / det;
+        } else {
+            det = A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1]) - A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0]) +
+                  A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0]);
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j) {
+                    int i1 = (j + 1) % 3, i2 = (j + 2) % 3, j1 = (i + 1) % 3, j2 = (i + 2) % 3;
+                    Ai[i][j] = (A[i1][j1] * A[i2][j2] - A[i1][j2] * A[i2][j1]) / det;
+                }
+        }
+        if (!(det > 0)) throw Error(IETI_EGEOM, "geometry map is not orientation preserving");
+        double Gh[3][3];
+        for (int a = 0; a < dim; ++a)
+            for (int b = 0; b < dim; ++b) {
+                double s = 0;
+                for (int c = 0; c < dim; ++c) s += Ai[a][c] * Ai[b][c];
+                Gh[a][b] = det * s;
+            }
+        std::vector<double> A1[3][2][2];
+        for (int d = 0; d < dim; ++d) one_d_matrices(dt[d], L.M[d], A1[d]);
+        for (int i2 = 0; i2 < L.M[2]; ++i2)
+            for (int i1 = 0; i1 < L.M[1]; ++i1)
+                for (int i0 = 0; i0 < L.M[0]; ++i0) {
+                    int64_t i = lin(L.M, i0, i1, i2);
+                    int ii[3] = {i0, i1, i2};
+                    for (int s = 0; s < L.nst; ++s) {
+                        int o[3] = {L.offs[3 * s], L.offs[3 * s + 1], L.offs[3 * s + 2]};
+                        int jj[3];
+                        bool ok = true;
+                        for (int d = 0; d < dim; ++d) {
+                            jj[d] = ii[d] + o[d];
+                            if (jj[d] < 0 || jj[d] >= L.M[d]) ok = false;
+                        }
+                        if (!ok) continue;
+                        double v = 0.0;
+                        for (int a = 0; a < dim; ++a)
+                            for (int b = 0; b < dim; ++b) {
+                                double prod = Gh[a][b];
+                                for (int d = 0; d < dim; ++d)
+                                    prod *= A1[d][d == a ? 1 : 0][d == b ? 1 : 0][(size_t)ii[d] * L.M[d] + jj[d]];
+                                v += prod;
+                            }
+                        L.coef[(size_t)s * L.n + i] = v;
+                    }
+                }
+        if (level0) {
+            for (int q2 = 0; q2 < Q2; ++q2)
+                for (int q1 = 0; q1 < Q1; ++q1)
+                    for (int q0 = 0; q0 < Q0; ++q0) {
+                        int64_t q = q0 + (int64_t)Q0 * (q1 + (int64_t)Q1 * q2);
+                        double wq = dt[0].w[q0] * dt[1].w[q1] * (dim == 3 ? dt[2].w[q2] : 1.0);
+                        P.qpw[q] = wq * det;
+                        double xi[3] = {dt[0].xi[q0], dt[1].xi[q1], dim == 3 ? dt[2].xi[q2] : 0.0};
+                        for (int c = 0; c < dim; ++c) {
+                            double x = c0[c];
+                            for (int d = 0; d < dim; ++d) x += A[c][d] * xi[d];
+                            P.qpx[q * dim + c] = x;
+                        }
+                    }
+        }
+        return;
+    }
+
+    // ---- curved patch: element-by-element with the metric at every quadrature point
+    const int pl[3] = {P.p[0], P.p[1], dim == 3 ? P.p[2] : 0};
+    const int nq1[3] = {pl[0] + 1, pl[1] + 1, pl[2] + 1};
+    const int nloc = nq1[0] * nq1[1] * nq1[2];
+    const int nqe = nloc;   // (p+1)^d points per element
+    const int pg[3] = {P.p[0], P.p[1], dim == 3 ? P.p[2] : 0};
+    std::vector<double> grad((size_t)nloc * nqe * 3), h((size_t)nloc * nqe * 3), Ke((size_t)nloc * nloc);
+    const int ne[3] = {dt[0].nel, dt[1].nel, dim == 3 ? dt[2].nel : 1};
+    for (int e2 = 0; e2 < ne[2]; ++e2)
+        for (int e1 = 0; e1 < ne[1]; ++e1)
+            for (int e0 = 0; e0 < ne[0]; ++e0) {
+                int first[3];
+                // qp loop
+                for (int g2 = 0; g2 < nq1[2]; ++g2)
+                    for (int g1 = 0; g1 < nq1[1]; ++g1)
+                        for (int g0 = 0; g0 < nq1[0]; ++g0) {
+                            int qd[3] = {e0 * nq1[0] + g0, e1 * nq1[1] + g1, e2 * nq1[2] + g2};
+                            int ql = g0 + nq1[0] * (g1 + nq1[1] * g2);
+                            for (int d = 0; d < dim; ++d) first[d] = dt[d].first[qd[d]];
+                            if (dim == 2) first[2] = 0;
+                            // geometry: x and J
+                            double x[3] = {0, 0, 0}, J[3][3] = {{0}};
+                            const double* Gv[3];
+                            const double* Gd[3];
+                            int gf[3] = {0, 0, 0};
+                            for (int d = 0; d < dim; ++d) {
+                                Gv[d] = &dt[d].G[(size_t)qd[d] * (pg[d] + 1)];
+                                Gd[d] = &dt[d].dG[(size_t)qd[d] * (pg[d] + 1)];
+                                gf[d] = dt[d].gfirst[qd[d]];
+                            }
+                            for (int a2 = 0; a2 <= pg[2]; ++a2)
+                                for (int a1 = 0; a1 <= pg[1]; ++a1)
+                                    for (int a0 = 0; a0 <= pg[0]; ++a0) {
+                                        int64_t k = lin(Mg, gf[0] + a0, gf[1] + a1, dim == 3 ? gf[2] + a2 : 0);
+                                        double v0 = Gv[0][a0], v1 = Gv[1][a1], v2 = dim == 3 ? Gv[2][a2] : 1.0;
+                                        double d0 = Gd[0][a0], d1 = Gd[1][a1], d2 = dim == 3 ? Gd[2][a2] : 0.0;
+                                        double bv = v0 * v1 * v2;
+                                        double bd[3] = {d0 * v1 * v2, v0 * d1 * v2, v0 * v1 * d2};
+                                        for (int c = 0; c < dim; ++c) {
+                                            double cp = P.ctrl[k * dim + c];
+                                            x[c] += cp * bv;
+                                            for (int a = 0; a < dim; ++a) J[c][a] += cp * bd[a];
+                                        }
+                                    }
+                            double det, Ji[3][3];
+                            if (dim == 2) {
+                                det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+                                Ji[0][0] = J[1][1] / det; Ji[0][1] = -J[0][1] / det;
+                                Ji[1][0] = -J[1][0] / det; Ji[1][1] = J[0][0] / det;
+                            } else {
+                                det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                                      J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                                      J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+                                for (int i = 0; i < 3; ++i)
+                                    for (int j = 0; j < 3; ++j) {
+                                        int i1 = (j + 1) % 3, i2 = (j + 2) % 3, j1 = (i + 1) % 3, j2 = (i + 2) % 3;
+                                        Ji[i][j] = (J[i1][j1] * J[i2][j2] - J[i1][j2] * J[i2][j1]) / det;
+                                    }
+                            }
+                            if (!(det > 0)) throw Error(IETI_EGEOM, "geometry map is not orientation preserving");
+                            double wq = dt[0].w[qd[0]] * dt[1].w[qd[1]] * (dim == 3 ? dt[2].w[qd[2]] : 1.0);
+                            double Gm[3][3];
+                            for (int a = 0; a < dim; ++a)
+                                for (int b = 0; b < dim; ++b) {
+                                    double s = 0;
+                                    for (int c = 0; c < dim; ++c) s += Ji[a][c] * Ji[b][c];
+                                    Gm[a][b] = wq * det * s;
+                                }
+                            if (level0) {
+                                int64_t q = qd[0] + (int64_t)Q0 * (qd[1] + (int64_t)Q1 * (dim == 3 ? qd[2] : 0));
+                                P.qpw[q] = wq * det;
+                                for (int c = 0; c < dim; ++c) P.qpx[q * dim + c] = x[c];
+                            }
+                            // space basis gradients (parameter domain) and G * grad
+                            const double* Nv[3];
+                            const double* Nd[3];
+                            for (int d = 0; d < dim; ++d) {
+                                Nv[d] = &dt[d].N[(size_t)qd[d] * (pl[d] + 1)];
+                                Nd[d] = &dt[d].dN[(size_t)qd[d] * (pl[d] + 1)];
+                            }
+                            for (int a2 = 0; a2 < nq1[2]; ++a2)
+                                for (int a1 = 0; a1 < nq1[1]; ++a1)
+                                    for (int a0 = 0; a0 < nq1[0]; ++a0) {
+                                        int al = a0 + nq1[0] * (a1 + nq1[1] * a2);
+                                        double v0 = Nv[0][a0], v1 = Nv[1][a1], v2 = dim == 3 ? Nv[2][a2] : 1.0;
+                                        double d0 = Nd[0][a0], d1 = Nd[1][a1], d2 = dim == 3 ? Nd[2][a2] : 0.0;
+                                        double gr[3] = {d0 * v1 * v2, v0 * d1 * v2, v0 * v1 * d2};
+                                        double* gp = &grad[((size_t)al * nqe + ql) * 3];
+                                        double* hp = &h[((size_t)al * nqe + ql) * 3];
+                                        for (int c = 0; c < 3; ++c) gp[c] = c < dim ? gr[c] : 0.0;
+                                        for (int a = 0; a < 3; ++a) {
+                                            double s = 0;
+                                            for (int b = 0; b < dim; ++b) s += (a < dim ? Gm[a][b] : 0.0) * gr[b];
+                                            hp[a] = a < dim ? s : 0.0;
+                                        }
+                                    }
+                        }
+                // element matrix and scatter into the half stencil
+                for (int d = 0; d < dim; ++d) first[d] = dt[d].first[e0 * 0 + (d == 0 ? e0 : d == 1 ? e1 : e2) * nq1[d]];
+                if (dim == 2) first[2] = 0;
+                for (int al = 0; al < nloc; ++al) {
+                    int a0 = al % nq1[0], a1 = (al / nq1[0]) % nq1[1], a2 = al / (nq1[0] * nq1[1]);
+                    const double* hp = &h[(size_t)al * nqe * 3];
+                    for (int bl = 0; bl < nloc; ++bl) {
+                        int b0 = bl % nq1[0], b1 = (bl / nq1[0]) % nq1[1], b2 = bl / (nq1[0] * nq1[1]);
+                        int o0 = b0 - a0, o1 = b1 - a1, o2 = b2 - a2;
+                        int s = slot[(o0 + P.p[0]) + (size_t)w0 * ((o1 + P.p[1]) + (size_t)w1 * (o2 + p2))];
+                        if (s < 0) continue;
+                        const double* gp = &grad[(size_t)bl * nqe * 3];
+                        double v = 0.0;
+                        for (int t = 0; t < nqe * 3; ++t) v += hp[t] * gp[t];
+                        int64_t i = lin(L.M, first[0] + a0, first[1] + a1, first[2] + a2);
+                        L.coef[(size_t)s * L.n + i] += v;
+                    }
+                }
+            }
+}
+
+// y = m (K m x) with the half stencil, FP64, on the host.
+static void host_apply(const Patch& P, const Level& L, const std::vector<uint8_t>& mask, const double* x, double* y) {
+    std::fill(y, y + L.n, 0.0);
+    for (int i2 = 0; i2 < L.M[2]; ++i2)
+        for (int i1 = 0; i1 < L.M[1]; ++i1)
+            for (int i0 = 0; i0 < L.M[0]; ++i0) {
+                int64_t i = lin(L.M, i0, i1, i2);
+                if (mask[i]) continue;
+                for (int s = 0; s < L.nst; ++s) {
+                    int j0 = i0 + L.offs[3 * s], j1 = i1 + L.offs[3 * s + 1], j2 = i2 + L.offs[3 * s + 2];
+                    if (j0 < 0 || j0 >= L.M[0] || j1 < 0 || j1 >= L.M[1] || j2 < 0 || j2 >= L.M[2]) continue;
+                    int64_t j = lin(L.M, j0, j1, j2);
+                    if (mask[j]) continue;
+                    double c = L.coef[(size_t)s * L.n + i];
+                    y[i] += c * x[j];
+                    if (s) y[j] += c * x[i];
+                }
+            }
+}
+
+// mask[i] = 1 where coefficient i is held at zero in the given mode
+static std::vector<uint8_t> level_mask(const Patch& P, const Level& L, int mode) {
+    uint32_t sides = mode == MODE_D ? (P.dim == 3 ? 0x3Fu : 0xFu) : P.bside;
+    uint32_t corners = mode == MODE_N ? (P.pcorner | P.dcorner) : mode == MODE_K ? P.dcorner : 0u;
+    std::vector<uint8_t> m(L.n, 0);
+    for (int i2 = 0; i2 < L.M[2]; ++i2)
+        for (int i1 = 0; i1 < L.M[1]; ++i1)
+            for (int i0 = 0; i0 < L.M[0]; ++i0) {
+                int ii[3] = {i0, i1, i2};
+                bool msk = false;
+                int cbits = 0, nend = 0;
+                for (int d = 0; d < P.dim; ++d) {
+                    bool lo = ii[d] == 0, hi = ii[d] == L.M[d] - 1;
+                    if ((lo && (sides >> (2 * d) & 1)) || (hi && (sides >> (2 * d + 1) & 1))) msk = true;
+                    if (lo || hi) { ++nend; if (hi) cbits |= 1 << d; }
+                }
+                if (nend == P.dim && (corners >> cbits & 1)) msk = true;
+                m[lin(L.M, i0, i1, i2)] = msk;
+            }
+    return m;
+}
+
+// lambda_max of D^{-1} K (masked) by power iteration
+static double power_lmax(const Patch& P, const Level& L, int mode) {
+    auto mask = level_mask(P, L, mode);
+    std::vector<double> x(L.n), y(L.n);
+    uint64_t s = 0x9E3779B97F4A7C15ull;
+    for (int64_t i = 0; i < L.n; ++i) {
+        s ^= s << 13; s ^= s >> 7; s ^= s << 17;
+        x[i] = mask[i] ? 0.0 : ((s >> 11) * (1.0 / 9007199254740992.0) - 0.5);
+    }
+    double lam = 0.0;
+    for (int it = 0; it < 40; ++it) {
+        host_apply(P, L, mask, x.data(), y.data());
+        double nx = 0, ny = 0;
+        for (int64_t i = 0; i < L.n; ++i) {
+            if (mask[i]) { y[i] = 0; continue; }
+            y[i] /= L.coef[i];
+            nx += x[i] * x[i];
+            ny += y[i] * y[i];
+        }
+        if (ny == 0 || nx == 0) return 1.0;
+        lam = std::sqrt(ny / nx);
+        double sc = 1.0 / std::sqrt(ny);
+        for (int64_t i = 0; i < L.n; ++i) x[i] = y[i] * sc;
+    }
+    return lam;
+}
+
+// dense inverse of the masked level matrix (masked rows/cols zero) by Cholesky
+static std::vector<double> dense_inverse(const Patch& P, const Level& L, int mode) {
+    auto mask = level_mask(P, L, mode);
+    int64_t n = L.n;
+    std::vector<double> A((size_t)n * n, 0.0);
+    std::vector<double> e(n, 0.0), col(n);
+    for (int64_t j = 0; j < n; ++j) {
+        if (mask[j]) { A[(size_t)j * n + j] = 1.0; continue; }
+        e[j] = 1.0;
+        host_apply(P, L, mask, e.data(), col.data());
+        e[j] = 0.0;
+        for (int64_t i = 0; i < n; ++i) A[(size_t)i * n + j] = col[i];
+    }
+    // Cholesky A = C C^T (lower, in place)
+    for (int64_t j = 0; j < n; ++j) {
+        double s = A[(size_t)j * n + j];
+        for (int64_t k = 0; k < j; ++k) s -= A[(size_t)j * n + k] * A[(size_t)j * n + k];
+        if (!(s > 0)) throw Error(IETI_EINVAL, "coarsest-level matrix is not positive definite");
+        double c = std::sqrt(s);
+        A[(size_t)j * n + j] = c;
+        for (int64_t i = j + 1; i < n; ++i) {
+            double t = A[(size_t)i * n + j];
+            for (int64_t k = 0; k < j; ++k) t -= A[(size_t)i * n + k] * A[(size_t)j * n + k];
+            A[(size_t)i * n + j] = t / c;
+        }
+    }
+    std::vector<double> inv((size_t)n * n, 0.0), z(n);
+    for (int64_t j = 0; j < n; ++j) {
+        if (mask[j]) continue;
+        std::fill(z.begin(), z.end(), 0.0);
+        z[j] = 1.0;
+        for (int64_t i = 0; i < n; ++i) {   // C y = e_j
+            double t = z[i];
+            for (int64_t k = 0; k < i; ++k) t -= A[(size_t)i * n + k] * z[k];
+            z[i] = t / A[(size_t)i * n + i];
+        }
+        for (int64_t i = n - 1; i >= 0; --i) {   // C^T x = y
+            double t = z[i];
+            for (int64_t k = i + 1; k < n; ++k) t -= A[(size_t)k * n + i] * z[k];
+            z[i] = t / A[(size_t)i * n + i];
+        }
+        for (int64_t i = 0; i < n; ++i) inv[(size_t)i * n + j] = mask[i] ? 0.0 : z[i];
+    }
+    return inv;
+}
+
+// ----------------------------------------------------------------------------
+// topology
+
+struct UF {
+    std::vector<int64_t> p;
+    explicit UF(int64_t n) : p(n) { std::iota(p.begin(), p.end(), 0); }
+    int64_t find(int64_t x) {
+        while (p[x] != x) { p[x] = p[p[x]]; x = p[x]; }
+        return x;
+    }
+    void unite(int64_t a, int64_t b) {
+        a = find(a); b = find(b);
+        if (a != b) p[std::max(a, b)] = std::min(a, b);
+    }
+};
+
+static void validate_patch(const ieti_patch& ip, int dim0, int k) {
+    auto fail = [&](const std::string& m) { throw Error(IETI_EINVAL, "patch " + std::to_string(k) + ": " + m); };
+    if (ip.dim != 2 && ip.dim != 3) fail("dim must be 2 or 3");
+    if (ip.dim != dim0) fail("all patches must have the same dimension");
+    if (!ip.ctrl) fail("null control points");
+    for (int d = 0; d < ip.dim; ++d) {
+        int p = ip.degree[d];
+        if (p < 1 || p > 6) fail("degree must be in 1..6");
+        if (!ip.knots[d]) fail("null knot vector");
+        int nk = ip.n_knots[d];
+        if (nk < 2 * (p + 1)) fail("knot vector too short");
+        const double* t = ip.knots[d];
+        for (int i = 0; i < nk; ++i)
+            if (!std::isfinite(t[i])) fail("non-finite knot");
+        for (int i = 0; i <= p; ++i)
+            if (t[i] != 0.0 || t[nk - 1 - i] != 1.0) fail("knot vectors must be open on [0,1]");
+        for (int i = p; i < nk - p - 1; ++i)
+            if (!(t[i + 1] > t[i])) fail("interior knots must be simple and increasing");
+    }
+}
+
+Plan* build_plan(const ieti_patch* in, int n, const double* pv, int n_pv, const ieti_options* optp) {
+    if (!in || n <= 0) throw Error(IETI_EINVAL, "no patches");
+    ieti_options opt;
+    if (optp) opt = *optp; else default_options(&opt);
+    if (opt.mg_precision != 32 && opt.mg_precision != 64) throw Error(IETI_EINVAL, "mg_precision must be 32 or 64");
+    if (opt.local_solver != IETI_LOCAL_MG && opt.local_solver != IETI_LOCAL_EXACT)
+        throw Error(IETI_EINVAL, "unknown local solver");
+    if (!(opt.tol > 0) || !(opt.inner_tol > 0) || !(opt.basis_tol > 0) || opt.max_it <= 0 || opt.inner_max_it <= 0)
+        throw Error(IETI_EINVAL, "tolerances and iteration limits must be positive");
+    if (opt.prec_vcycles < 1) throw Error(IETI_EINVAL, "prec_vcycles must be >= 1");
+    if (opt.check_every < 1) opt.check_every = 1;
+    const int dim = in[0].dim;
+    for (int k = 0; k < n; ++k) validate_patch(in[k], dim, k);
+    auto P = std::make_unique<Plan>();
+    Plan& pl = *P;
+    pl.dim = dim;
+    pl.N = n;
+    pl.opt = opt;
+    pl.patches.resize(n);
+    int64_t off = 0;
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int k = 0; k < n; ++k) {
+        Patch& pa = pl.patches[k];
+        pa.dim = dim;
+        int64_t nd = 1;
+        int M[3] = {1, 1, 1};
+        for (int d = 0; d < dim; ++d) {
+            pa.p[d] = in[k].degree[d];
+            pa.knots[d].assign(in[k].knots[d], in[k].knots[d] + in[k].n_knots[d]);
+            M[d] = in[k].n_knots[d] - pa.p[d] - 1;
+            nd *= M[d];
+        }
+        pa.ctrl.assign(in[k].ctrl, in[k].ctrl + nd * dim);
+        for (double v : pa.ctrl)
+            if (!std::isfinite(v)) throw Error(IETI_EINVAL, "non-finite control point");
+        for (int64_t i = 0; i < nd; ++i)
+            for (int c = 0; c < dim; ++c) {
+                lo[c] = std::min(lo[c], pa.ctrl[i * dim + c]);
+                hi[c] = std::max(hi[c], pa.ctrl[i * dim + c]);
+            }
+        Level L0;
+        for (int d = 0; d < 3; ++d) {
+            L0.M[d] = M[d];
+            if (d < dim) {
+                L0.knots[d] = pa.knots[d];
+                L0.nel[d] = (int)breakpoints(pa.knots[d]).size() - 1;
+            }
+        }
+        L0.n = nd;
+        pa.lv.push_back(L0);
+        pa.torn_off = off;
+        off += nd;
+    }
+    pl.ndof_torn = off;
+    double diam = 0;
+    for (int c = 0; c < dim; ++c) diam = std::max(diam, hi[c] - lo[c]);
+    const double tol = 1e-9 * std::max(diam, 1e-300);
+
+    // ---- corners -> vertices
+    const int ncorner = 1 << dim;
+    std::vector<std::array<double, 3>> vcoord;
+    std::vector<std::vector<int>> cvert(n, std::vector<int>(ncorner));
+    auto corner_index = [&](const Patch& pa, int c) {
+        int idx[3] = {0, 0, 0};
+        for (int d = 0; d < dim; ++d) idx[d] = (c >> d & 1) ? pa.lv[0].M[d] - 1 : 0;
+        return lin(pa.lv[0].M, idx[0], idx[1], idx[2]);
+    };
+    for (int k = 0; k < n; ++k)
+        for (int c = 0; c < ncorner; ++c) {
+            const Patch& pa = pl.patches[k];
+            int64_t i = corner_index(pa, c);
+            std::array<double, 3> x = {0, 0, 0};
+            for (int d = 0; d < dim; ++d) x[d] = pa.ctrl[i * dim + d];
+            int found = -1;
+            for (size_t v = 0; v < vcoord.size() && found < 0; ++v) {
+                double dd = 0;
+                for (int d = 0; d < dim; ++d) dd = std::max(dd, std::fabs(vcoord[v][d] - x[d]));
+                if (dd <= tol) found = (int)v;
+            }
+            if (found < 0) { found = (int)vcoord.size(); vcoord.push_back(x); }
+            cvert[k][c] = found;
+        }
+
+    // ---- sides: match by their corner vertex sequences
+    struct SideRef { int k, d, e; };
+    std::map<std::vector<int>, std::vector<SideRef>> sides;
+    for (int k = 0; k < n; ++k)
+        for (int d = 0; d < dim; ++d)
+            for (int e = 0; e < 2; ++e) {
+                std::vector<int> seq;
+                for (int c = 0; c < ncorner; ++c)
+                    if ((c >> d & 1) == e) seq.push_back(cvert[k][c]);
+                std::vector<int> key = seq;
+                std::sort(key.begin(), key.end());
+                sides[key].push_back({k, d, e});
+            }
+    UF uf(pl.ndof_torn);
+    for (auto& kv : sides) {
+        auto& v = kv.second;
+        if (v.size() == 1) {
+            pl.patches[v[0].k].bside |= 1u << (2 * v[0].d + v[0].e);
+            continue;
+        }
+        if (v.size() > 2) throw Error(IETI_ENONCONFORMING, "more than two patches share a side");
+        SideRef a = v[0], b = v[1];
+        if (a.e == 1 && b.e == 0) {} else if (a.e == 0 && b.e == 1) std::swap(a, b);
+        else throw Error(IETI_ENONCONFORMING, "interface orientation not supported");
+        if (a.d != b.d) throw Error(IETI_ENONCONFORMING, "interface orientation not supported");
+        // same orientation: corner sequences in the same order
+        std::vector<int> sa, sb;
+        for (int c = 0; c < ncorner; ++c) {
+            if ((c >> a.d & 1) == 1) sa.push_back(cvert[a.k][c]);
+            if ((c >> b.d & 1) == 0) sb.push_back(cvert[b.k][c]);
+        }
+        if (sa != sb) throw Error(IETI_ENONCONFORMING, "interface orientation not supported");
+        const Patch& A = pl.patches[a.k];
+        const Patch& B = pl.patches[b.k];
+        for (int d = 0; d < dim; ++d) {
+            if (d == a.d) continue;
+            if (A.p[d] != B.p[d] || A.knots[d].size() != B.knots[d].size())
+                throw Error(IETI_ENONCONFORMING, "spline spaces differ along an interface");
+            for (size_t i = 0; i < A.knots[d].size(); ++i)
+                if (std::fabs(A.knots[d][i] - B.knots[d][i]) > 1e-12)
+                    throw Error(IETI_ENONCONFORMING, "knot vectors differ along an interface");
+        }
+        const int* MA = A.lv[0].M;
+        const int* MB = B.lv[0].M;
+        int t1 = a.d == 0 ? 1 : 0, t2 = a.d == 2 ? 1 : 2;
+        int n1 = MA[t1], n2 = dim == 3 ? MA[t2] : 1;
+        for (int j2 = 0; j2 < n2; ++j2)
+            for (int j1 = 0; j1 < n1; ++j1) {
+                int ia[3] = {0, 0, 0}, ib[3] = {0, 0, 0};
+                ia[a.d] = MA[a.d] - 1;
+                ib[a.d] = 0;
+                ia[t1] = ib[t1] = j1;
+                if (dim == 3) ia[t2] = ib[t2] = j2;
+                int64_t la = lin(MA, ia[0], ia[1], ia[2]), lb = lin(MB, ib[0], ib[1], ib[2]);
+                double dd = 0;
+                for (int c = 0; c < dim; ++c) dd = std::max(dd, std::fabs(A.ctrl[la * dim + c] - B.ctrl[lb * dim + c]));
+                if (dd > tol) throw Error(IETI_ENONCONFORMING, "patches do not meet along an interface");
+                uf.unite(A.torn_off + la, B.torn_off + lb);
+            }
+    }
+
+    // ---- groups of shared coefficients and boundary status
+    auto on_bside = [&](const Patch& pa, int64_t i) {
+        int M0 = pa.lv[0].M[0], M1 = pa.lv[0].M[1];
+        int ii[3] = {(int)(i % M0), (int)((i / M0) % M1), (int)(i / ((int64_t)M0 * M1))};
+        for (int d = 0; d < dim; ++d) {
+            if (ii[d] == 0 && (pa.bside >> (2 * d) & 1)) return true;
+            if (ii[d] == pa.lv[0].M[d] - 1 && (pa.bside >> (2 * d + 1) & 1)) return true;
+        }
+        return false;
+    };
+    std::vector<std::pair<int64_t, int64_t>> rp;   // (root, position) for shared coefficients
+    auto pos_patch = [&](int64_t pos) {
+        int lo_ = 0, hi_ = n - 1;
+        while (lo_ < hi_) {
+            int mid = (lo_ + hi_ + 1) / 2;
+            if (pl.patches[mid].torn_off <= pos) lo_ = mid; else hi_ = mid - 1;
+        }
+        return lo_;
+    };
+    for (int64_t pos = 0; pos < pl.ndof_torn; ++pos) {
+        int64_t r = uf.find(pos);
+        if (r != pos) rp.push_back({r, pos});
+    }
+    // include roots of groups
+    {
+        std::vector<uint8_t> isroot(pl.ndof_torn, 0);
+        for (auto& x : rp) isroot[x.first] = 1;
+        for (int64_t pos = 0; pos < pl.ndof_torn; ++pos)
+            if (isroot[pos]) rp.push_back({pos, pos});
+    }
+    std::sort(rp.begin(), rp.end());
+    rp.erase(std::unique(rp.begin(), rp.end()), rp.end());
+    struct Group { std::vector<int64_t> pos; bool dir = false; };
+    std::vector<Group> groups;
+    for (size_t i = 0; i < rp.size();) {
+        size_t j = i;
+        Group g;
+        while (j < rp.size() && rp[j].first == rp[i].first) { g.pos.push_back(rp[j].second); ++j; }
+        std::sort(g.pos.begin(), g.pos.end());
+        for (int64_t pos : g.pos) {
+            int k = pos_patch(pos);
+            if (on_bside(pl.patches[k], pos - pl.patches[k].torn_off)) g.dir = true;
+        }
+        groups.push_back(std::move(g));
+        i = j;
+    }
+    std::vector<int64_t> group_of(pl.ndof_torn, -1);
+    for (size_t gi = 0; gi < groups.size(); ++gi)
+        for (int64_t pos : groups[gi].pos) group_of[pos] = (int64_t)gi;
+
+    // boundary coefficients at corners that lie on no boundary side of their patch
+    for (int k = 0; k < n; ++k) {
+        Patch& pa = pl.patches[k];
+        for (int c = 0; c < ncorner; ++c) {
+            int64_t li = corner_index(pa, c);
+            int64_t g = group_of[pa.torn_off + li];
+            if (g >= 0 && groups[g].dir && !on_bside(pa, li)) pa.dcorner |= 1u << c;
+        }
+    }
+
+    // ---- primal vertices
+    std::vector<uint8_t> gprimal(groups.size(), 0);
+    std::vector<int64_t> vgroups;
+    for (int k = 0; k < n; ++k) {
+        const Patch& pa = pl.patches[k];
+        for (int c = 0; c < ncorner; ++c) {
+            int64_t g = group_of[pa.torn_off + corner_index(pa, c)];
+            if (g < 0 || groups[g].dir || gprimal[g]) continue;
+            bool take = true;
+            if (pv) {
+                take = false;
+                int64_t li = corner_index(pa, c);
+                for (int v = 0; v < n_pv && !take; ++v) {
+                    double dd = 0;
+                    for (int d = 0; d < dim; ++d) dd = std::max(dd, std::fabs(pv[v * dim + d] - pa.ctrl[li * dim + d]));
+                    if (dd <= tol) take = true;
+                }
+            }
+            if (take) { gprimal[g] = 1; vgroups.push_back(g); }
+        }
+    }
+    std::sort(vgroups.begin(), vgroups.end());
+    std::map<int64_t, int64_t> vindex;
+    for (size_t i = 0; i < vgroups.size(); ++i) vindex[vgroups[i]] = (int64_t)i;
+    pl.n_primal_vertices = (int64_t)vgroups.size();
+    // ---- edge averages (3D)
+    std::map<int64_t, int64_t> eindex;   // group of first interior edge coefficient -> global primal
+    struct LocalEdge { int k; int e; std::vector<int64_t> loc; int64_t key; };
+    std::vector<LocalEdge> ledges;
+    if (dim == 3 && (opt.primal & IETI_PRIMAL_EDGES)) {
+        for (int k = 0; k < n; ++k) {
+            const Patch& pa = pl.patches[k];
+            const int* M = pa.lv[0].M;
+            int eid = 0;
+            for (int fr = 0; fr < 3; ++fr) {
+                int oa = fr == 0 ? 1 : 0, ob = fr == 2 ? 1 : 2;
+                for (int ea = 0; ea < 2; ++ea)
+                    for (int eb = 0; eb < 2; ++eb, ++eid) {
+                        LocalEdge le;
+                        le.k = k;
+                        le.e = eid;
+                        for (int t = 1; t < M[fr] - 1; ++t) {
+                            int ii[3];
+                            ii[fr] = t;
+                            ii[oa] = ea ? M[oa] - 1 : 0;
+                            ii[ob] = eb ? M[ob] - 1 : 0;
+                            le.loc.push_back(lin(M, ii[0], ii[1], ii[2]));
+                        }
+                        if (le.loc.empty()) continue;
+                        int64_t g = group_of[pa.torn_off + le.loc[0]];
+                        if (g < 0 || groups[g].dir) continue;
+                        le.key = g;
+                        eindex[g] = 0;
+                        ledges.push_back(le);
+                    }
+            }
+        }
+        int64_t c = (int64_t)vgroups.size();
+        for (auto& kv : eindex) kv.second = c++;
+    }
+    pl.n_primal = (int64_t)vgroups.size() + (int64_t)eindex.size();
+    for (int k = 0; k < n; ++k) {
+        Patch& pa = pl.patches[k];
+        for (int c = 0; c < ncorner; ++c) {
+            int64_t g = group_of[pa.torn_off + corner_index(pa, c)];
+            if (g >= 0 && gprimal[g]) {
+                pa.pcorner |= 1u << c;
+                pa.primal_global.push_back(vindex[g]);
+                pa.primal_corner.push_back(c);
+                pa.primal_edge.emplace_back();
+            }
+        }
+    }
+    for (auto& le : ledges) {
+        Patch& pa = pl.patches[le.k];
+        pa.primal_global.push_back(eindex[le.key]);
+        pa.primal_corner.push_back(-1);
+        pa.primal_edge.push_back(le.loc);
+    }
+    // floating patches need a primal vertex (K_rr must be definite)
+    for (int k = 0; k < n; ++k)
+        if (pl.patches[k].bside == 0 && pl.patches[k].pcorner == 0 && pl.patches[k].dcorner == 0)
+            throw Error(IETI_EINVAL, "patch " + std::to_string(k) + " has no boundary side and no primal vertex");
+    {
+        std::vector<std::vector<std::pair<int64_t, int64_t>>> contrib(pl.n_primal);
+        for (int k = 0; k < n; ++k)
+            for (size_t j = 0; j < pl.patches[k].primal_global.size(); ++j)
+                contrib[pl.patches[k].primal_global[j]].push_back({k, (int64_t)j});
+        pl.pri_ptr.push_back(0);
+        for (auto& c : contrib) {
+            for (auto& x : c) { pl.pri_patch.push_back(x.first); pl.pri_local.push_back(x.second); }
+            pl.pri_ptr.push_back((int64_t)pl.pri_patch.size());
+        }
+    }
+
+    // ---- consistency: boundary status must follow from side/corner masks
+    for (size_t gi = 0; gi < groups.size(); ++gi)
+        for (int64_t pos : groups[gi].pos) {
+            int k = pos_patch(pos);
+            const Patch& pa = pl.patches[k];
+            int64_t li = pos - pa.torn_off;
+            bool masked = on_bside(pa, li);
+            if (!masked) {
+                for (int c = 0; c < ncorner; ++c)
+                    if ((pa.dcorner >> c & 1) && corner_index(pa, c) == li) masked = true;
+            }
+            if (masked != groups[gi].dir) throw Error(IETI_ENOTSUP, "boundary coefficient inside a patch side");
+        }
+
+    // ---- multipliers (fully redundant) and B^T slots
+    std::map<int64_t, std::vector<std::pair<int64_t, double>>> slot_map;   // pos -> (lambda, sign)
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+        const Group& g = groups[gi];
+        if (g.dir || gprimal[gi] || g.pos.size() < 2) continue;
+        int m = (int)g.pos.size();
+        for (int a = 0; a < m; ++a)
+            for (int b = a + 1; b < m; ++b) {
+                int64_t l = (int64_t)pl.lam_plus.size();
+                pl.lam_plus.push_back(g.pos[a]);
+                pl.lam_minus.push_back(g.pos[b]);
+                pl.lam_mult.push_back(m);
+                slot_map[g.pos[a]].push_back({l, 1.0});
+                slot_map[g.pos[b]].push_back({l, -1.0});
+            }
+    }
+    pl.n_lambda = (int64_t)pl.lam_plus.size();
+    pl.slot_ptr.push_back(0);
+    for (auto& kv : slot_map) {
+        pl.slot_pos.push_back(kv.first);
+        int m = (int)groups[group_of[kv.first]].pos.size();
+        pl.slot_mult.push_back(m);
+        for (auto& x : kv.second) { pl.slot_lam.push_back(x.first); pl.slot_sgn.push_back(x.second); }
+        pl.slot_ptr.push_back((int64_t)pl.slot_lam.size());
+    }
+    pl.grp_ptr.push_back(0);
+    int64_t nshared = 0;
+    for (auto& g : groups) {
+        if (g.dir || g.pos.size() < 2) continue;
+        for (int64_t pos : g.pos) pl.grp_pos.push_back(pos);
+        pl.grp_ptr.push_back((int64_t)pl.grp_pos.size());
+        ++nshared;
+    }
+    // global dofs: shared non-boundary groups + coefficients held by one patch only and not on the boundary
+    int64_t nsingle = 0;
+    for (int k = 0; k < n; ++k) {
+        const Patch& pa = pl.patches[k];
+        for (int64_t i = 0; i < pa.lv[0].n; ++i)
+            if (group_of[pa.torn_off + i] < 0 && !on_bside(pa, i)) ++nsingle;
+    }
+    pl.ndof_global = nshared + nsingle;
+
+    // ---- affine detection, multigrid levels, assembly
+    for (int k = 0; k < n; ++k) {
+        Patch& pa = pl.patches[k];
+        const int* M = pa.lv[0].M;
+        double A[3][3] = {{0}}, c0[3] = {0};
+        for (int c = 0; c < dim; ++c) c0[c] = pa.ctrl[c];
+        for (int d = 0; d < dim; ++d) {
+            int idx[3] = {0, 0, 0};
+            idx[d] = M[d] - 1;
+            int64_t i = lin(M, idx[0], idx[1], idx[2]);
+            for (int c = 0; c < dim; ++c) A[c][d] = pa.ctrl[i * dim + c] - c0[c];
+        }
+        std::vector<double> gr[3];
+        for (int d = 0; d < dim; ++d) {
+            int p = pa.p[d];
+            for (int i = 0; i < M[d]; ++i) {
+                double s = 0;
+                for (int j = 1; j <= p; ++j) s += pa.knots[d][i + j];
+                gr[d].push_back(s / p);
+            }
+        }
+        bool aff = true;
+        for (int i2 = 0; i2 < M[2] && aff; ++i2)
+            for (int i1 = 0; i1 < M[1] && aff; ++i1)
+                for (int i0 = 0; i0 < M[0] && aff; ++i0) {
+                    double xi[3] = {gr[0][i0], gr[1][i1], dim == 3 ? gr[2][i2] : 0.0};
+                    int64_t i = lin(M, i0, i1, i2);
+                    for (int c = 0; c < dim; ++c) {
+                        double x = c0[c];
+                        for (int d = 0; d < dim; ++d) x += A[c][d] * xi[d];
+                        if (std::fabs(x - pa.ctrl[i * dim + c]) > 1e-13 * std::max(diam, 1.0)) aff = false;
+                    }
+                }
+        pa.affine = aff;
+        // levels: halve while every direction has an even number (>= 6) of elements
+        while (true) {
+            const Level& f = pa.lv.back();
+            bool ok = true;
+            for (int d = 0; d < dim; ++d)
+                if (f.nel[d] % 2 || f.nel[d] / 2 < 3) ok = false;
+            if (!ok) break;
+            Level c;
+            for (int d = 0; d < dim; ++d) {
+                std::vector<double> b = breakpoints(f.knots[d]), bc;
+                for (size_t i = 0; i < b.size(); i += 2) bc.push_back(b[i]);
+                std::vector<double> t(pa.p[d] + 1, bc.front());
+                for (size_t i = 1; i + 1 < bc.size(); ++i) t.push_back(bc[i]);
+                for (int i = 0; i <= pa.p[d]; ++i) t.push_back(bc.back());
+                c.knots[d] = t;
+                c.nel[d] = (int)bc.size() - 1;
+                c.M[d] = (int)t.size() - pa.p[d] - 1;
+            }
+            c.n = (int64_t)c.M[0] * c.M[1] * c.M[2];
+            pa.lv.push_back(c);
+        }
+        for (Level& L : pa.lv) {
+            L.guard = pa.p[0] + (int64_t)pa.p[1] * L.M[0] + (dim == 3 ? (int64_t)pa.p[2] * L.M[0] * L.M[1] : 0);
+        }
+        pl.max_levels = std::max(pl.max_levels, (int)pa.lv.size());
+    }
+    parallel_for(n, [&](int k) {
+        Patch& pa = pl.patches[k];
+        for (size_t l = 0; l < pa.lv.size(); ++l) assemble_level(pa, pa.lv[l], l == 0);
+        for (size_t l = 0; l + 1 < pa.lv.size(); ++l) {
+            Level& f = pa.lv[l];
+            const Level& c = pa.lv[l + 1];
+            for (int d = 0; d < dim; ++d) {
+                int Mf, Mc;
+                f.P[d] = prolongation(c.knots[d], f.knots[d], pa.p[d], Mf, Mc);
+                f.Mc[d] = Mc;
+            }
+        }
+        if (opt.local_solver == IETI_LOCAL_MG)
+            for (size_t l = 0; l + 1 < pa.lv.size(); ++l) {
+                pa.lv[l].lmax[MODE_N] = power_lmax(pa, pa.lv[l], MODE_N);
+                pa.lv[l].lmax[MODE_D] = power_lmax(pa, pa.lv[l], MODE_D);
+            }
+        Level& cl = pa.lv.back();
+        if (opt.local_solver == IETI_LOCAL_MG) {
+            cl.inv[MODE_N] = dense_inverse(pa, cl, MODE_N);
+            cl.inv[MODE_D] = dense_inverse(pa, cl, MODE_D);
+        }
+    });
+    int64_t nq = 0;
+    for (auto& pa : pl.patches) nq += pa.n_qp;
+    pl.n_qp = nq;
+    return P.release();
+}
+
+}  // namespace ieti
+
+// ----------------------------------------------------------------------------
+// C ABI: host-only planning entry points
+
+using namespace ieti;
+
+extern "C" {
+
+void ieti_default_options(ieti_options* opt) {
+    if (opt) default_options(opt);
+}
+
+int ieti_plan_create(const ieti_patch* patches, int32_t n_patches, const double* primal_vertices,
+                     int32_t n_primal_vertices, const ieti_options* opt, ieti_plan** out) {
+    if (!out) return IETI_EINVAL;
+    *out = nullptr;
+    try {
+        *out = reinterpret_cast<ieti_plan*>(build_plan(patches, n_patches, primal_vertices, n_primal_vertices, opt));
+        return IETI_OK;
+    } catch (const Error& e) {
+        set_last_error(e.what());
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        set_last_error("host allocation failed");
+        return IETI_ENOMEM;
+    } catch (const std::exception& e) {
+        set_last_error(e.what());
+        return IETI_EINVAL;
+    }
+}
+
+void ieti_plan_destroy(ieti_plan* plan) { delete reinterpret_cast<Plan*>(plan); }
+
+int ieti_plan_sizes(const ieti_plan* plan, int64_t* ndof_torn, int64_t* ndof_global, int64_t* n_lambda,
+                    int64_t* n_primal, int64_t* n_qp, int32_t* max_levels) {
+    if (!plan) return IETI_EINVAL;
+    const Plan& p = *reinterpret_cast<const Plan*>(plan);
+    if (ndof_torn) *ndof_torn = p.ndof_torn;
+    if (ndof_global) *ndof_global = p.ndof_global;
+    if (n_lambda) *n_lambda = p.n_lambda;
+    if (n_primal) *n_primal = p.n_primal;
+    if (n_qp) *n_qp = p.n_qp;
+    if (max_levels) *max_levels = p.max_levels;
+    return IETI_OK;
+}
+
+int ieti_plan_array(const ieti_plan* plan, int32_t which, int32_t patch, int32_t level, void* out, int64_t* count) {
+    if (!plan || !count) return IETI_EINVAL;
+    const Plan& p = *reinterpret_cast<const Plan*>(plan);
+    auto emit = [&](const void* src, int64_t cnt, size_t elem) {
+        if (out) std::memcpy(out, src, (size_t)cnt * elem);
+        *count = cnt;
+        return IETI_OK;
+    };
+    if (which == IETI_ARR_LAMBDA_MAP) {
+        std::vector<int64_t> v(2 * p.n_lambda);
+        for (int64_t l = 0; l < p.n_lambda; ++l) { v[2 * l] = p.lam_plus[l]; v[2 * l + 1] = p.lam_minus[l]; }
+        return emit(v.data(), (int64_t)v.size(), sizeof(int64_t));
+    }
+    if (patch < 0 || patch >= p.N) return IETI_EINVAL;
+    const Patch& pa = p.patches[patch];
+    if (which == IETI_ARR_MASKS) {
+        int32_t v[3] = {(int32_t)pa.bside, (int32_t)(pa.pcorner | pa.dcorner), (int32_t)pa.lv.size()};
+        return emit(v, 3, sizeof(int32_t));
+    }
+    if (which == IETI_ARR_QP_WEIGHT) return emit(pa.qpw.data(), (int64_t)pa.qpw.size(), sizeof(double));
+    if (which == IETI_ARR_PRIMAL_MAP) return emit(pa.primal_global.data(), (int64_t)pa.primal_global.size(), sizeof(int64_t));
+    int lev = which == IETI_ARR_PROLONG ? (level & 255) : level;
+    if (lev < 0 || lev >= (int)pa.lv.size()) return IETI_EINVAL;
+    const Level& L = pa.lv[lev];
+    switch (which) {
+    case IETI_ARR_STENCIL: return emit(L.coef.data(), (int64_t)L.coef.size(), sizeof(double));
+    case IETI_ARR_STENCIL_OFFS: return emit(L.offs.data(), (int64_t)L.offs.size(), sizeof(int32_t));
+    case IETI_ARR_SHAPE: return emit(L.M, 3, sizeof(int32_t));
+    case IETI_ARR_LMAX: return emit(L.lmax, 2, sizeof(double));
+    case IETI_ARR_PROLONG: {
+        int d = level >> 8;
+        if (d < 0 || d >= p.dim || L.P[d].empty()) return IETI_EINVAL;
+        return emit(L.P[d].data(), (int64_t)L.P[d].size(), sizeof(double));
+    }
+    default: return IETI_EINVAL;
+    }
+}
+
+int ieti_plan_quadrature(const ieti_plan* plan, double* x) {
+    if (!plan || !x) return IETI_EINVAL;
+    const Plan& p = *reinterpret_cast<const Plan*>(plan);
+    int64_t o = 0;
+    for (const auto& pa : p.patches) {
+        std::memcpy(x + o, pa.qpx.data(), pa.qpx.size() * sizeof(double));
+        o += (int64_t)pa.qpx.size();
+    }
+    return IETI_OK;
+}
+
+}  // extern "C"

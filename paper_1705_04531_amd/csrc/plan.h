@@ -1,0 +1,98 @@
+// Host-side plan of an IETI-DP solve: topology, numbering, multigrid
+// hierarchy and FP64 operator data.  Built once per ieti_setup; the device
+// runtime uploads it.  Internal header (not part of the C ABI).
+#pragma once
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/ieti.h"
+
+namespace ieti {
+
+// Internal error carrying an ABI status code; caught at the ABI boundary.
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+// Masking modes of the patch stiffness (which coefficients are held at 0).
+enum Mode : int {
+    MODE_N = 0,   // local Neumann problem: boundary sides + primal (and boundary) vertices
+    MODE_D = 1,   // local Dirichlet problem: every side of the patch
+    MODE_K = 2,   // patch stiffness with only the boundary coefficients removed
+};
+
+// One multigrid level of one patch.
+struct Level {
+    int M[3] = {1, 1, 1};          // basis functions per direction (1 in unused directions)
+    int nel[3] = {1, 1, 1};        // elements per direction
+    int64_t n = 0;                 // prod M
+    int64_t guard = 0;             // largest linear stencil offset p0 + p1 M0 + p2 M0 M1
+    std::vector<double> knots[3];
+    int nst = 0;                   // entries of the half stencil
+    std::vector<int32_t> offs;     // 3 * nst offsets (o0, o1, o2); entry 0 is the diagonal
+    std::vector<double> coef;      // nst * n, offset-major: K(i, i + o_s) at coef[s * n + i]
+    double lmax[2] = {0, 0};       // lambda_max(D^{-1} K) for MODE_N, MODE_D
+    // prolongation from the next coarser level into this one: dense Mf x Mc per direction
+    std::vector<double> P[3];
+    int Mc[3] = {1, 1, 1};
+    // coarsest level only: dense inverses (n x n, masked rows/cols zero) for MODE_N, MODE_D
+    std::vector<double> inv[2];
+};
+
+struct Patch {
+    int dim = 2;
+    int p[3] = {0, 0, 0};
+    std::vector<double> knots[3];
+    std::vector<double> ctrl;      // n * dim
+    uint32_t bside = 0;            // bit 2d+e: side xi_d = e is on the boundary
+    uint32_t pcorner = 0;          // bit c: corner c (c = e0 + 2 e1 + 4 e2) is a primal vertex
+    uint32_t dcorner = 0;          // bit c: corner c is a boundary coefficient though on no boundary side
+    bool affine = false;
+    std::vector<Level> lv;         // lv[0] finest
+    std::vector<double> qpw;       // w_q |det J_q| at the level-0 quadrature points
+    std::vector<double> qpx;       // physical quadrature points, n_qp * dim
+    std::vector<double> qpN[3];    // level-0 space basis at the quadrature points, Q_d x (p_d+1)
+    int64_t n_qp = 0;
+    int64_t torn_off = 0;          // first coefficient in the torn layout
+    // local primal constraints: vertices (corner order) then edge averages (edge order)
+    std::vector<int64_t> primal_global;
+    std::vector<int> primal_corner;              // corner id, or -1 for an edge constraint
+    std::vector<std::vector<int64_t>> primal_edge;  // local coefficients averaged by an edge constraint
+};
+
+struct Plan {
+    int dim = 2;
+    int N = 0;
+    ieti_options opt{};
+    std::vector<Patch> patches;
+    int64_t ndof_torn = 0, ndof_global = 0, n_qp = 0;
+    int64_t n_lambda = 0, n_primal = 0, n_primal_vertices = 0;
+    int max_levels = 0;
+    // multipliers: torn positions of the +1 and -1 entries, multiplicity of the coefficient
+    std::vector<int64_t> lam_plus, lam_minus;
+    std::vector<int32_t> lam_mult;
+    // B^T: interface slots (torn position) with their multipliers, CSR
+    std::vector<int64_t> slot_pos, slot_ptr;
+    std::vector<int64_t> slot_lam;
+    std::vector<double> slot_sgn;                 // +1 / -1
+    std::vector<int32_t> slot_mult;
+    // groups of copies of shared non-boundary coefficients (torn positions), CSR
+    std::vector<int64_t> grp_ptr, grp_pos;
+    // global primal: contributors (patch, local constraint) per global primal, CSR
+    std::vector<int64_t> pri_ptr, pri_patch, pri_local;
+};
+
+Plan* build_plan(const ieti_patch* patches, int n, const double* primal_vertices, int n_pv,
+                 const ieti_options* opt);
+
+// helpers shared with the runtime
+void default_options(ieti_options* o);
+int cheb_degree_for(const ieti_options& o, int pmax);
+double cheb_lower_for(const ieti_options& o, int pmax);
+void set_last_error(const std::string& s);
+
+}  // namespace ieti

@@ -1,0 +1,1191 @@
+// Device runtime of the IETI-DP solver: uploads a plan, builds the primal
+// basis, and runs ieti_solve (right-hand side d, outer CG on F lambda = d
+// with the scaled Dirichlet preconditioner, recovery of u).
+//
+//   F p   = B K~^{-1} B^T p                 (Sec. 2, eq. (4))
+//   K~^{-1} g = [K_rr^{-1} g_r - Psi_E C_E K_rr^{-1} g_r] + Psi S_PiPi^{-1} Psi^T g
+//         (local Neumann problem of eq. (7): unconstrained minimiser, then the
+//          energy-minimising projection; primal part with the basis of eq. (6))
+//   M^{-1} r = B_D S B_D^T r,  S v = K v - K_{.I} K_II^{-1} K_{I.} v  (Sec. 2, 3.1)
+//
+// K_rr is the patch stiffness with boundary coefficients and primal
+// vertices removed, positive definite on every patch.  Inexact local solves:
+// flexible CG (FP64) preconditioned by one multigrid V-cycle (FP32 or FP64),
+// to a relative residual inner_tol (Sec. 3.2 / Sec. 4: MG-MG).  The
+// Dirichlet problems in the preconditioner use prec_vcycles V-cycles.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "kernels.h"
+#include "plan.h"
+
+namespace ieti {
+const char* last_error();
+}
+
+namespace ieti {
+
+#define HIPCHECK(x)                                                                                    \
+    do {                                                                                               \
+        hipError_t e_ = (x);                                                                           \
+        if (e_ != hipSuccess) throw Error(IETI_EDEVICE, std::string(#x) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+static inline int64_t align64(int64_t x) { return (x + 63) & ~int64_t(63); }
+static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+static inline unsigned tile_grid(int ntiles) { return (unsigned)(8 * ((ntiles + 7) / 8)); }
+
+// ------------------------------------------------------------------ device memory arena
+
+struct Arena {
+    std::vector<void*> ptrs;
+    size_t bytes = 0;
+    size_t budget = 0;
+    ~Arena() {
+        for (void* p : ptrs) (void)hipFree(p);
+    }
+    template <typename T>
+    T* alloc(int64_t n, hipStream_t st, bool zero = true) {
+        if (n <= 0) n = 1;
+        size_t b = (size_t)n * sizeof(T);
+        if (budget && bytes + b > budget) throw Error(IETI_ENOMEM, "device memory budget exceeded");
+        void* p = nullptr;
+        if (hipMalloc(&p, b) != hipSuccess) throw Error(IETI_ENOMEM, "hipMalloc failed");
+        ptrs.push_back(p);
+        bytes += b;
+        if (zero) HIPCHECK(hipMemsetAsync(p, 0, b, st));
+        return (T*)p;
+    }
+    template <typename T>
+    T* upload(const std::vector<T>& v, hipStream_t st) {
+        T* p = alloc<T>((int64_t)v.size(), st, false);
+        if (!v.empty()) HIPCHECK(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
+        return p;
+    }
+};
+
+// ------------------------------------------------------------------ solver base
+
+// Event-bracketed launches of the profiled kernel classes.
+struct KProf {
+    bool on = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
+    std::vector<std::pair<int, double>> pending;   // (class, bytes) of used pool entries
+    int64_t launches[IETI_KPROF_COUNT] = {0, 0, 0};
+    double ms[IETI_KPROF_COUNT] = {0, 0, 0};
+    double bytes[IETI_KPROF_COUNT] = {0, 0, 0};
+    ~KProf() {
+        for (auto& e : pool) {
+            (void)hipEventDestroy(e.first);
+            (void)hipEventDestroy(e.second);
+        }
+    }
+    void reset() {
+        for (int c = 0; c < IETI_KPROF_COUNT; ++c) launches[c] = 0, ms[c] = 0, bytes[c] = 0;
+    }
+    std::pair<hipEvent_t, hipEvent_t> next(int cls, double b) {
+        size_t i = pending.size();
+        if (i == pool.size()) {
+            hipEvent_t a, c;
+            HIPCHECK(hipEventCreate(&a));
+            HIPCHECK(hipEventCreate(&c));
+            pool.push_back({a, c});
+        }
+        pending.push_back({cls, b});
+        return pool[i];
+    }
+    // after a stream synchronisation: fold the recorded pairs into the totals
+    void collect() {
+        for (size_t i = 0; i < pending.size(); ++i) {
+            float t = 0.f;
+            HIPCHECK(hipEventElapsedTime(&t, pool[i].first, pool[i].second));
+            int c = pending[i].first;
+            launches[c] += 1;
+            ms[c] += t;
+            bytes[c] += pending[i].second;
+        }
+        pending.clear();
+    }
+};
+
+struct SolverBase {
+    KProf prof;
+    virtual ~SolverBase() = default;
+    virtual void setup() = 0;
+    virtual int solve(const double* f_qp, double* u, ieti_stats* st) = 0;
+    virtual void quadrature(double* x, bool on_device) = 0;
+    std::unique_ptr<Plan> plan;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    Arena arena;
+};
+
+struct DevLevel {
+    double words_all = 0, words_smooth = 0;       // sum of n over the launch's patches
+    double st_all = 0, st_smooth = 0;             // sum of n * nst (half-stencil words)
+    std::vector<PatchLev> hL;
+    PatchLev* L = nullptr;
+    int64_t len = 0, clen = 0;
+    std::vector<Tile> h_all, h_smooth;
+    Tile* tiles_all = nullptr;
+    Tile* tiles_smooth = nullptr;
+    int nt_all = 0, nt_smooth = 0;
+    std::vector<int32_t> h_coarse;
+    int32_t* coarse_list = nullptr;
+    int n_coarse = 0;
+    int32_t* plo = nullptr;
+    int32_t* rlo = nullptr;
+    void* pval = nullptr;
+    void* rval = nullptr;
+    void* coefT = nullptr;
+    void* inv = nullptr;
+    void *vb = nullptr, *vx = nullptr, *vxa = nullptr, *vd = nullptr, *vr = nullptr;
+};
+
+template <typename T>
+struct Solver : SolverBase {
+    std::vector<DevLevel> lev;
+    int N = 0, dim = 2, nlev = 0;
+    int cheb_m = 2;
+    double cheb_hi = 1.1;
+    // level 0 FP64
+    double* coef64 = nullptr;
+    int64_t len0 = 0;
+    double *f64 = nullptr, *b64 = nullptr, *e64 = nullptr, *w64 = nullptr, *s64 = nullptr, *u64 = nullptr;
+    double *fx = nullptr, *fr = nullptr, *fd = nullptr, *fq = nullptr;
+    T *rT = nullptr, *zT = nullptr, *bT = nullptr, *xIT = nullptr, *x2T = nullptr, *r2T = nullptr;
+    double* partial = nullptr;
+    int32_t* tile_ptr = nullptr;
+    double *bb = nullptr, *dq = nullptr, *beta = nullptr, *alpha = nullptr;
+    int *active = nullptr, *its = nullptr, *nactive = nullptr;
+    int* h_nactive = nullptr;   // pinned
+    // jump operators
+    int64_t nslots = 0, nlam = 0;
+    int64_t *slot_dev = nullptr, *slot_ptr = nullptr, *slot_lam = nullptr;
+    double *slot_wB = nullptr, *slot_wBD = nullptr;
+    int32_t* slot_patch = nullptr;
+    int64_t* row_ptr = nullptr;
+    int64_t *lam_plus = nullptr, *lam_minus = nullptr;
+    double* lam_wBD = nullptr;
+    // primal
+    int64_t npi = 0;
+    int npk_max = 0;
+    int32_t* npk = nullptr;
+    int64_t *Rk = nullptr, *unit_dev = nullptr, *edge_ptr = nullptr, *edge_dev = nullptr;
+    int64_t *pri_ptr = nullptr, *pri_patch = nullptr, *pri_local = nullptr;
+    double *psi = nullptr, *psiG = nullptr, *Sinv = nullptr, *gpi = nullptr, *upi = nullptr;
+    double *cbuf = nullptr, *ebuf = nullptr, *coefbuf = nullptr;
+    // groups and output
+    int64_t ngroups = 0;
+    int64_t *grp_ptr = nullptr, *grp_dev = nullptr;
+    int64_t* torn_off = nullptr;
+    // load vector
+    PatchQ* PQ = nullptr;
+    double *basis = nullptr, *qpw = nullptr;
+    double* qpx = nullptr;
+    // lambda space
+    double *lam = nullptr, *lr = nullptr, *lz = nullptr, *lp = nullptr, *lq = nullptr, *ltmp = nullptr;
+    double* sc = nullptr;
+    double* h_sc = nullptr;    // pinned
+    // statistics of the current solve
+    int64_t inner_calls = 0, inner_sum = 0;
+    int inner_max = 0;
+    std::vector<int> h_its;
+
+    // ---------------------------------------------------------------- launch helpers
+    void sync() { HIPCHECK(hipStreamSynchronize(stream)); }
+    void check_launch() { HIPCHECK(hipGetLastError()); }
+
+    template <typename TC, typename TX, typename TY, int EPI>
+    void stencil(int l, bool smooth_only, int mode, const void* coef, const void* x, void* y, const void* b, void* d,
+                 const int* act, double alpha_, int cheb_k, double* part = nullptr, const double* r64 = nullptr) {
+        DevLevel& D = lev[l];
+        StencilArgs a{};
+        a.L = D.L;
+        a.tiles = smooth_only ? D.tiles_smooth : D.tiles_all;
+        a.ntiles = smooth_only ? D.nt_smooth : D.nt_all;
+        if (a.ntiles == 0) return;
+        a.mode = mode;
+        a.coef = coef;
+        a.x = x;
+        a.y = y;
+        a.b = b;
+        a.d = d;
+        a.active = act;
+        a.alpha = alpha_;
+        a.cheb_k = cheb_k;
+        a.cheb_hi = cheb_hi;
+        a.partial = part;
+        a.r64 = r64;
+        int cls = -1;
+        if (prof.on && l == 0) {
+            if (EPI == EPI_CHEB) cls = IETI_KPROF_SMOOTH_FINE;
+            else if (EPI == EPI_DOTS) cls = IETI_KPROF_APPLY64;
+            else if (EPI == EPI_RESID && smooth_only) cls = IETI_KPROF_RESID_FINE;
+        }
+        std::pair<hipEvent_t, hipEvent_t> ev{};
+        if (cls >= 0) {
+            // algorithmic bytes: every vector the epilogue touches and the half stencil, once per coefficient
+            const double n = smooth_only ? D.words_smooth : D.words_all;
+            const double nst = smooth_only ? D.st_smooth : D.st_all;
+            double vec_words = EPI == EPI_CHEB ? (cheb_k > 0 ? 5.0 : 4.0) : 3.0;
+            double bytes = nst * sizeof(TC) + n * (vec_words - 1.0) * sizeof(TY) + n * sizeof(TX);
+            if (EPI == EPI_DOTS) bytes = nst * sizeof(TC) + n * (sizeof(TX) + sizeof(TY) + sizeof(double));
+            ev = prof.next(cls, bytes);
+            HIPCHECK(hipEventRecord(ev.first, stream));
+        }
+        if (l == 0)
+            hipLaunchKernelGGL((k_stencil<TC, TX, TY, EPI, true>), dim3(tile_grid(a.ntiles)), dim3(TILE), 0, stream, a);
+        else
+            hipLaunchKernelGGL((k_stencil<TC, TX, TY, EPI, false>), dim3(tile_grid(a.ntiles)), dim3(TILE), 0, stream,
+                               a);
+        check_launch();
+        if (cls >= 0) HIPCHECK(hipEventRecord(ev.second, stream));
+    }
+    template <typename V>
+    void fill(V* p, int64_t n, V v) {
+        hipLaunchKernelGGL(k_fill<V>, dim3(nblk(n, 256)), dim3(256), 0, stream, p, n, v);
+        check_launch();
+    }
+
+    // ---------------------------------------------------------------- multigrid V-cycle
+    // x0 = V(b0) on all patches (mode N or D); the result lands in x0.
+    void vcycle(int mode, const int* act, const T* b0, T* x0) {
+        std::vector<T*> cur(nlev, nullptr);
+        int deepest = 0;
+        for (int l = 0; l < nlev; ++l) {
+            DevLevel& D = lev[l];
+            const T* B = l == 0 ? b0 : (const T*)D.vb;
+            T* S = l == 0 ? (T*)D.vxa : (T*)D.vx;       // start buffer
+            T* F = l == 0 ? x0 : (T*)D.vxa;              // buffer holding the final result
+            if (D.n_coarse) {
+                hipLaunchKernelGGL(k_coarse<T>, dim3(D.n_coarse), dim3(TILE), 0, stream, D.L, D.coarse_list,
+                                   D.n_coarse, (const T*)D.inv, B, F, mode, act);
+                check_launch();
+            }
+            cur[l] = F;
+            deepest = l;
+            if (D.nt_smooth == 0) break;
+            // pre-smoothing: Chebyshev from zero
+            T* X = S;
+            T* XA = F;
+            hipLaunchKernelGGL(k_cheb_zero<T>, dim3(tile_grid(D.nt_smooth)), dim3(TILE), 0, stream, D.L,
+                               D.tiles_smooth, D.nt_smooth, (const T*)D.coefT, B, X, (T*)D.vd, mode, cheb_hi, act);
+            check_launch();
+            for (int k = 1; k < cheb_m; ++k) {
+                stencil<T, T, T, EPI_CHEB>(l, true, mode, D.coefT, X, XA, B, D.vd, act, 0.0, k);
+                std::swap(X, XA);
+            }
+            stencil<T, T, T, EPI_RESID>(l, true, mode, D.coefT, X, D.vr, B, nullptr, act, 0.0, 0);
+            cur[l] = X;
+            DevLevel& C = lev[l + 1];
+            hipLaunchKernelGGL(k_restrict<T>, dim3(tile_grid(C.nt_all)), dim3(TILE), 0, stream, D.L, C.L, C.tiles_all,
+                               C.nt_all, D.rlo, (const T*)D.rval, (const T*)D.vr, (T*)C.vb, mode, act);
+            check_launch();
+        }
+        for (int l = deepest - 1; l >= 0; --l) {
+            DevLevel& D = lev[l];
+            const T* B = l == 0 ? b0 : (const T*)D.vb;
+            T* X = cur[l];
+            T* A0 = l == 0 ? (T*)D.vxa : (T*)D.vx;   // the level's two x buffers
+            T* A1 = l == 0 ? x0 : (T*)D.vxa;
+            T* XA = (X == A0) ? A1 : A0;
+            hipLaunchKernelGGL(k_prolong<T>, dim3(tile_grid(D.nt_smooth)), dim3(TILE), 0, stream, D.L, lev[l + 1].L,
+                               D.tiles_smooth, D.nt_smooth, D.plo, (const T*)D.pval, (const T*)cur[l + 1], X, mode,
+                               act);
+            check_launch();
+            for (int k = 0; k < cheb_m; ++k) {
+                stencil<T, T, T, EPI_CHEB>(l, true, mode, D.coefT, X, XA, B, D.vd, act, 0.0, k);
+                std::swap(X, XA);
+            }
+            cur[l] = X;
+        }
+        if (cur[0] != x0) throw Error(IETI_EDEVICE, "internal: V-cycle result buffer mismatch");
+    }
+
+    // ---------------------------------------------------------------- batched flexible CG: fx = K_rr^{-1} b
+    // b: level-0 FP64 (masked to mode N here).  All patches in every launch.
+    void fcg(const double* b, double tol, int maxit) {
+        DevLevel& D = lev[0];
+        const int nt = D.nt_all;
+        hipLaunchKernelGGL(k_fcg_init<T>, dim3(tile_grid(nt)), dim3(TILE), 0, stream, D.L, D.tiles_all, nt, b, fx,
+                           fr, rT, fd, fq, partial, (int)MODE_N);
+        check_launch();
+        fill<int>(nactive, 1, 0);
+        hipLaunchKernelGGL(k_fcg_scalars, dim3(nblk(N, 256)), dim3(256), 0, stream, N, tile_ptr, partial, 1, 0, bb,
+                           dq, beta, alpha, active, its, tol * tol, maxit, 1, nactive);
+        check_launch();
+        const int every = std::max(1, plan->opt.check_every);
+        for (int it = 0; it < maxit; ++it) {
+            if (it % every == 0) {
+                HIPCHECK(hipMemcpyAsync(h_nactive, nactive, sizeof(int), hipMemcpyDeviceToHost, stream));
+                sync();
+                if (*h_nactive == 0) break;
+            }
+            vcycle(MODE_N, active, rT, zT);
+            if (it > 0) {
+                hipLaunchKernelGGL(k_fcg_zq<T>, dim3(tile_grid(nt)), dim3(TILE), 0, stream, D.L, D.tiles_all, nt, zT,
+                                   fq, partial, active);
+                check_launch();
+            }
+            hipLaunchKernelGGL(k_fcg_scalars, dim3(nblk(N, 256)), dim3(256), 0, stream, N, tile_ptr, partial, 1, 1,
+                               bb, dq, beta, alpha, active, its, tol * tol, maxit, it == 0 ? 1 : 0, nactive);
+            check_launch();
+            hipLaunchKernelGGL(k_fcg_dir<T>, dim3(tile_grid(nt)), dim3(TILE), 0, stream, D.L, D.tiles_all, nt, zT, fd,
+                               beta, (int)MODE_N, active);
+            check_launch();
+            stencil<double, double, double, EPI_DOTS>(0, false, MODE_N, coef64, fd, fq, nullptr, nullptr, active, 0.0,
+                                                      0, partial, fr);
+            hipLaunchKernelGGL(k_fcg_scalars, dim3(nblk(N, 256)), dim3(256), 0, stream, N, tile_ptr, partial, 2, 2,
+                               bb, dq, beta, alpha, active, its, tol * tol, maxit, 0, nactive);
+            check_launch();
+            hipLaunchKernelGGL(k_fcg_update<T>, dim3(tile_grid(nt)), dim3(TILE), 0, stream, D.L, D.tiles_all, nt, fd,
+                               fq, fx, fr, rT, alpha, partial, active);
+            check_launch();
+            fill<int>(nactive, 1, 0);
+            hipLaunchKernelGGL(k_fcg_scalars, dim3(nblk(N, 256)), dim3(256), 0, stream, N, tile_ptr, partial, 1, 3,
+                               bb, dq, beta, alpha, active, its, tol * tol, maxit, 0, nactive);
+            check_launch();
+        }
+        HIPCHECK(hipMemcpyAsync(h_its.data(), its, sizeof(int) * N, hipMemcpyDeviceToHost, stream));
+        sync();
+        for (int k = 0; k < N; ++k) {
+            inner_sum += h_its[k];
+            inner_max = std::max(inner_max, h_its[k]);
+        }
+        inner_calls += N;
+    }
+
+    // ---------------------------------------------------------------- K~^{-1} g, primal part on the slots or on all rows
+    // g: level-0 FP64 (local load-type vector); the FCG solves with m_N g.
+    // full == false: only the interface slots of the result are corrected (F apply).
+    void ktilde_inv(const double* g, bool full, double tol, double* out_full) {
+        if (full) {
+            DevLevel& D = lev[0];
+            hipLaunchKernelGGL((k_convert<double, double>), dim3(tile_grid(D.nt_all)), dim3(TILE), 0, stream, D.L,
+                               D.tiles_all, D.nt_all, g, e64, (int)MODE_N, 1.0);
+            check_launch();
+            fcg(e64, tol, plan->opt.inner_max_it);
+        } else {
+            fcg(g, tol, plan->opt.inner_max_it);
+        }
+        if (npi > 0) {
+            hipLaunchKernelGGL(k_pri_dots, dim3(N), dim3(TILE), 0, stream, N, npk, row_ptr, slot_dev,
+                               full ? lev[0].L : nullptr, full ? psi : psiG, len0, g, fx, edge_ptr, edge_dev, cbuf,
+                               ebuf);
+            check_launch();
+            hipLaunchKernelGGL(k_pri_coarse, dim3(1), dim3(1024), 0, stream, npi, pri_ptr, pri_patch, pri_local, cbuf,
+                               Sinv, gpi, upi, N, npk, Rk, ebuf, coefbuf);
+            check_launch();
+        }
+        if (full) {
+            DevLevel& D = lev[0];
+            if (npi > 0) {
+                hipLaunchKernelGGL(k_pri_apply_full, dim3(tile_grid(D.nt_all)), dim3(TILE), 0, stream, D.L,
+                                   D.tiles_all, D.nt_all, npk, psi, len0, coefbuf, fx, out_full);
+            } else {
+                HIPCHECK(hipMemcpyAsync(out_full, fx, sizeof(double) * len0, hipMemcpyDeviceToDevice, stream));
+            }
+            check_launch();
+        } else if (npi > 0) {
+            hipLaunchKernelGGL(k_pri_apply_slots, dim3(nblk(nslots, 256)), dim3(256), 0, stream, nslots, slot_patch,
+                               slot_dev, npk, psiG, coefbuf, fx);
+            check_launch();
+        }
+    }
+
+    void scatter(const double* lamv, bool scaled, double* v) {
+        fill<double>(v, len0, 0.0);
+        if (nslots == 0) return;
+        hipLaunchKernelGGL(k_scatter, dim3(nblk(nslots, 256)), dim3(256), 0, stream, nslots, slot_dev, slot_ptr,
+                           slot_lam, scaled ? slot_wBD : slot_wB, lamv, v);
+        check_launch();
+    }
+    void gather(const double* v, bool scaled, double* out, bool plus_only = false, bool minus_only = false) {
+        if (nlam == 0) return;
+        const int64_t* pl = minus_only ? lam_minus : lam_plus;
+        const int64_t* mi = (plus_only || minus_only) ? nullptr : lam_minus;
+        hipLaunchKernelGGL(k_gather, dim3(nblk(nlam, 256)), dim3(256), 0, stream, nlam, pl, mi,
+                           scaled ? lam_wBD : nullptr, v, out);
+        check_launch();
+    }
+
+    // q = F p
+    void applyF(const double* p, double* q) {
+        scatter(p, false, b64);
+        ktilde_inv(b64, false, plan->opt.inner_tol, nullptr);
+        gather(fx, false, q);
+    }
+
+    // z = B_D S B_D^T r
+    void applyPrec(const double* r, double* z) {
+        DevLevel& D = lev[0];
+        scatter(r, true, w64);
+        // b_I = -m_D (K v)
+        stencil<double, double, T, EPI_APPLY>(0, false, MODE_D, coef64, w64, bT, nullptr, nullptr, nullptr, -1.0, 0);
+        vcycle(MODE_D, nullptr, bT, xIT);
+        for (int c = 1; c < plan->opt.prec_vcycles; ++c) {
+            stencil<T, T, T, EPI_RESID>(0, false, MODE_D, D.coefT, xIT, r2T, bT, nullptr, nullptr, 0.0, 0);
+            vcycle(MODE_D, nullptr, r2T, x2T);
+            hipLaunchKernelGGL(k_add<T>, dim3(tile_grid(D.nt_all)), dim3(TILE), 0, stream, D.L, D.tiles_all, D.nt_all,
+                               (const T*)x2T, xIT);
+            check_launch();
+        }
+        // w = v + x_I;  s = K w (mode K); z = B_D s
+        hipLaunchKernelGGL(k_add_conv<T>, dim3(tile_grid(D.nt_all)), dim3(TILE), 0, stream, D.L, D.tiles_all,
+                           D.nt_all, (const T*)xIT, w64);
+        check_launch();
+        stencil<double, double, double, EPI_APPLY>(0, false, MODE_K, coef64, w64, s64, nullptr, nullptr, nullptr, 1.0,
+                                                   0);
+        gather(s64, true, z);
+    }
+
+    // ---------------------------------------------------------------- setup
+    void setup() override;
+    int solve(const double* f_qp, double* u, ieti_stats* st) override;
+    void quadrature(double* x, bool on_device) override {
+        const Plan& pl = *plan;
+        if (on_device) {
+            HIPCHECK(hipMemcpyAsync(x, qpx, sizeof(double) * pl.n_qp * pl.dim, hipMemcpyDeviceToDevice, stream));
+            sync();
+        } else {
+            int64_t o = 0;
+            for (const auto& pa : pl.patches) {
+                std::memcpy(x + o, pa.qpx.data(), pa.qpx.size() * sizeof(double));
+                o += (int64_t)pa.qpx.size();
+            }
+        }
+    }
+    ~Solver() override {
+        if (h_nactive) (void)hipHostFree(h_nactive);
+        if (h_sc) (void)hipHostFree(h_sc);
+    }
+};
+
+template <typename T>
+void Solver<T>::setup() {
+    Plan& pl = *plan;
+    N = pl.N;
+    dim = pl.dim;
+    nlev = pl.max_levels;
+    hipStream_t st = stream;
+    arena.budget = pl.opt.hbm_budget;
+    int pmax = 0;
+    for (auto& pa : pl.patches)
+        for (int d = 0; d < dim; ++d) pmax = std::max(pmax, pa.p[d]);
+    cheb_m = cheb_degree_for(pl.opt, pmax);
+    lev.resize(nlev);
+    // ---- descriptors, layouts, tiles
+    for (int l = 0; l < nlev; ++l) {
+        DevLevel& D = lev[l];
+        int64_t cur = 0, ccur = 0;
+        for (int k = 0; k < N; ++k) {
+            const Patch& pa = pl.patches[k];
+            if ((int)pa.lv.size() <= l) continue;
+            const Level& L = pa.lv[l];
+            PatchLev P{};
+            for (int d = 0; d < 3; ++d) {
+                P.M[d] = L.M[d];
+                P.p[d] = d < dim ? pa.p[d] : 0;
+            }
+            P.dim = dim;
+            P.nst = L.nst;
+            const uint32_t all = dim == 3 ? 0x3Fu : 0xFu;
+            P.mbits[MODE_N] = pa.bside | ((pa.pcorner | pa.dcorner) << 8);
+            P.mbits[MODE_D] = all;
+            P.mbits[MODE_K] = pa.bside | (pa.dcorner << 8);
+            P.patch = k;
+            P.coarse = -1;
+            P.fine = -1;
+            P.n = L.n;
+            P.voff = align64(cur + L.guard);
+            cur = P.voff + L.n + L.guard;
+            P.cstride = align64(L.n + 2 * L.guard);
+            P.coff = align64(ccur) + L.guard;
+            ccur = align64(ccur) + (int64_t)L.nst * P.cstride;
+            P.lmax[0] = L.lmax[0];
+            P.lmax[1] = L.lmax[1];
+            int pk = 0;
+            for (int d = 0; d < dim; ++d) pk = std::max(pk, pa.p[d]);
+            P.clo = cheb_lower_for(pl.opt, pk);
+            D.hL.push_back(P);
+        }
+        D.len = align64(cur) + 64;
+        D.clen = align64(ccur) + 64;
+    }
+    // cross-level indices
+    for (int l = 0; l + 1 < nlev; ++l) {
+        DevLevel& F = lev[l];
+        DevLevel& C = lev[l + 1];
+        for (size_t c = 0; c < C.hL.size(); ++c)
+            for (size_t f = 0; f < F.hL.size(); ++f)
+                if (F.hL[f].patch == C.hL[c].patch) {
+                    F.hL[f].coarse = (int)c;
+                    C.hL[c].fine = (int)f;
+                }
+    }
+    for (int l = 0; l < nlev; ++l) {
+        DevLevel& D = lev[l];
+        for (size_t i = 0; i < D.hL.size(); ++i) {
+            const PatchLev& P = D.hL[i];
+            bool smooth = P.coarse >= 0;
+            for (int64_t s = 0; s < P.n; s += TILE) {
+                D.h_all.push_back({(int32_t)i, (int32_t)s});
+                if (smooth) D.h_smooth.push_back({(int32_t)i, (int32_t)s});
+            }
+            if (!smooth) D.h_coarse.push_back((int32_t)i);
+        }
+        D.nt_all = (int)D.h_all.size();
+        D.nt_smooth = (int)D.h_smooth.size();
+        for (const PatchLev& P : D.hL) {
+            D.words_all += (double)P.n;
+            D.st_all += (double)P.n * P.nst;
+            if (P.coarse >= 0) {
+                D.words_smooth += (double)P.n;
+                D.st_smooth += (double)P.n * P.nst;
+            }
+        }
+        D.n_coarse = (int)D.h_coarse.size();
+    }
+    // ---- transfer tables, stencils, inverses
+    for (int l = 0; l < nlev; ++l) {
+        DevLevel& D = lev[l];
+        std::vector<int32_t> plo, rlo;
+        std::vector<T> pval, rval;
+        std::vector<T> coefT(D.clen, T(0));
+        std::vector<double> c64;
+        if (l == 0) c64.assign(D.clen, 0.0);
+        std::vector<T> inv;
+        for (auto& P : D.hL) {
+            const Patch& pa = pl.patches[P.patch];
+            const Level& L = pa.lv[l];
+            for (int s = 0; s < L.nst; ++s)
+                for (int64_t i = 0; i < L.n; ++i) {
+                    double v = L.coef[(size_t)s * L.n + i];
+                    coefT[P.coff + s * P.cstride + i] = T(v);
+                    if (l == 0) c64[P.coff + s * P.cstride + i] = v;
+                }
+            if (P.coarse >= 0) {
+                for (int d = 0; d < dim; ++d) {
+                    const int Mf = L.M[d], Mc = L.Mc[d], w = pa.p[d] + 2;
+                    if (w > PW) throw Error(IETI_ENOTSUP, "degree too high for the transfer tables");
+                    const std::vector<double>& Pm = L.P[d];
+                    P.toff[d] = (int64_t)plo.size();
+                    for (int r = 0; r < Mf; ++r) {
+                        int cmin = Mc, cmax = -1;
+                        for (int c = 0; c < Mc; ++c)
+                            if (Pm[(size_t)r * Mc + c] != 0.0) { cmin = std::min(cmin, c); cmax = std::max(cmax, c); }
+                        if (cmax < 0) cmin = cmax = 0;
+                        if (cmax - cmin + 1 > w) throw Error(IETI_ENOTSUP, "prolongation row wider than p+2");
+                        int lo = std::max(0, std::min(cmin, Mc - w));
+                        plo.push_back(lo);
+                        for (int a = 0; a < PW; ++a) {
+                            int c = lo + a;
+                            pval.push_back(a < w && c < Mc ? T(Pm[(size_t)r * Mc + c]) : T(0));
+                        }
+                    }
+                    P.roff[d] = (int64_t)rlo.size();
+                    for (int c = 0; c < Mc; ++c) {
+                        int rmin = Mf, rmax = -1;
+                        for (int r = 0; r < Mf; ++r)
+                            if (Pm[(size_t)r * Mc + c] != 0.0) { rmin = std::min(rmin, r); rmax = std::max(rmax, r); }
+                        if (rmax < 0) rmin = rmax = 0;
+                        if (rmax - rmin + 1 > w) throw Error(IETI_ENOTSUP, "restriction column wider than p+2");
+                        int lo = std::max(0, std::min(rmin, Mf - w));
+                        rlo.push_back(lo);
+                        for (int a = 0; a < PW; ++a) {
+                            int r = lo + a;
+                            rval.push_back(a < w && r < Mf ? T(Pm[(size_t)r * Mc + c]) : T(0));
+                        }
+                    }
+                }
+            } else if (pl.opt.local_solver == IETI_LOCAL_MG) {
+                P.invoff = (int64_t)inv.size();
+                for (int m = 0; m < 2; ++m)
+                    for (double v : L.inv[m]) inv.push_back(T(v));
+            }
+        }
+        D.L = arena.upload(D.hL, st);
+        D.tiles_all = arena.upload(D.h_all, st);
+        D.tiles_smooth = arena.upload(D.h_smooth, st);
+        D.coarse_list = arena.upload(D.h_coarse, st);
+        D.plo = arena.upload(plo, st);
+        D.rlo = arena.upload(rlo, st);
+        D.pval = arena.upload(pval, st);
+        D.rval = arena.upload(rval, st);
+        D.coefT = arena.upload(coefT, st);
+        D.inv = arena.upload(inv, st);
+        if (l == 0) {
+            if (std::is_same<T, double>::value) coef64 = (double*)D.coefT;
+            else coef64 = arena.upload(c64, st);
+        }
+        D.vb = arena.alloc<T>(D.len, st);
+        D.vx = arena.alloc<T>(D.len, st);
+        D.vxa = arena.alloc<T>(D.len, st);
+        D.vd = arena.alloc<T>(D.len, st);
+        D.vr = arena.alloc<T>(D.len, st);
+        HIPCHECK(hipStreamSynchronize(st));   // host vectors above go out of scope
+    }
+    DevLevel& D0 = lev[0];
+    len0 = D0.len;
+    for (double** p : {&f64, &b64, &e64, &w64, &s64, &u64, &fx, &fr, &fd, &fq}) *p = arena.alloc<double>(len0, st);
+    for (T** p : {&rT, &zT, &bT, &xIT, &x2T, &r2T}) *p = arena.alloc<T>(len0, st);
+    partial = arena.alloc<double>(2 * (int64_t)D0.nt_all + 2, st);
+    {
+        std::vector<int32_t> tp(N + 1, 0);
+        for (auto& t : D0.h_all) tp[D0.hL[t.pl].patch + 1]++;
+        for (int k = 0; k < N; ++k) tp[k + 1] += tp[k];
+        tile_ptr = arena.upload(tp, st);
+    }
+    bb = arena.alloc<double>(N, st);
+    dq = arena.alloc<double>(N, st);
+    beta = arena.alloc<double>(N, st);
+    alpha = arena.alloc<double>(N, st);
+    active = arena.alloc<int>(N, st);
+    its = arena.alloc<int>(N, st);
+    nactive = arena.alloc<int>(1, st);
+    h_its.assign(N, 0);
+    HIPCHECK(hipHostMalloc((void**)&h_nactive, sizeof(int)));
+    HIPCHECK(hipHostMalloc((void**)&h_sc, 16 * sizeof(double)));
+
+    // ---- jump operators (device positions on level 0)
+    auto devpos = [&](int64_t torn) {
+        int lo = 0, hi = N - 1;
+        while (lo < hi) {
+            int mid = (lo + hi + 1) / 2;
+            if (pl.patches[mid].torn_off <= torn) lo = mid; else hi = mid - 1;
+        }
+        return D0.hL[lo].voff + (torn - pl.patches[lo].torn_off);
+    };
+    auto patch_of = [&](int64_t torn) {
+        int lo = 0, hi = N - 1;
+        while (lo < hi) {
+            int mid = (lo + hi + 1) / 2;
+            if (pl.patches[mid].torn_off <= torn) lo = mid; else hi = mid - 1;
+        }
+        return lo;
+    };
+    nslots = (int64_t)pl.slot_pos.size();
+    nlam = pl.n_lambda;
+    {
+        std::vector<int64_t> sd(nslots), rp(N + 1, 0);
+        std::vector<int32_t> sp(nslots);
+        std::vector<double> wb(pl.slot_lam.size()), wbd(pl.slot_lam.size());
+        for (int64_t s = 0; s < nslots; ++s) {
+            sd[s] = devpos(pl.slot_pos[s]);
+            sp[s] = patch_of(pl.slot_pos[s]);
+            rp[sp[s] + 1]++;
+            for (int64_t e = pl.slot_ptr[s]; e < pl.slot_ptr[s + 1]; ++e) {
+                wb[e] = pl.slot_sgn[e];
+                wbd[e] = pl.slot_sgn[e] / (double)pl.slot_mult[s];
+            }
+        }
+        for (int k = 0; k < N; ++k) rp[k + 1] += rp[k];
+        slot_dev = arena.upload(sd, st);
+        slot_patch = arena.upload(sp, st);
+        row_ptr = arena.upload(rp, st);
+        slot_ptr = arena.upload(pl.slot_ptr, st);
+        slot_lam = arena.upload(pl.slot_lam, st);
+        slot_wB = arena.upload(wb, st);
+        slot_wBD = arena.upload(wbd, st);
+        std::vector<int64_t> lp(nlam), lm(nlam);
+        std::vector<double> lw(nlam);
+        for (int64_t l = 0; l < nlam; ++l) {
+            lp[l] = devpos(pl.lam_plus[l]);
+            lm[l] = devpos(pl.lam_minus[l]);
+            lw[l] = 1.0 / (double)pl.lam_mult[l];
+        }
+        lam_plus = arena.upload(lp, st);
+        lam_minus = arena.upload(lm, st);
+        lam_wBD = arena.upload(lw, st);
+        std::vector<int64_t> gp = pl.grp_ptr, gd(pl.grp_pos.size());
+        for (size_t i = 0; i < gd.size(); ++i) gd[i] = devpos(pl.grp_pos[i]);
+        ngroups = (int64_t)gp.size() - 1;
+        grp_ptr = arena.upload(gp, st);
+        grp_dev = arena.upload(gd, st);
+        std::vector<int64_t> to(N);
+        for (int k = 0; k < N; ++k) to[k] = pl.patches[k].torn_off;
+        torn_off = arena.upload(to, st);
+        HIPCHECK(hipStreamSynchronize(st));
+    }
+    // ---- lambda space
+    int64_t nl = std::max<int64_t>(nlam, 1);
+    lam = arena.alloc<double>(nl, st);
+    lr = arena.alloc<double>(nl, st);
+    lz = arena.alloc<double>(nl, st);
+    lp = arena.alloc<double>(nl, st);
+    lq = arena.alloc<double>(nl, st);
+    ltmp = arena.alloc<double>(nl, st);
+    sc = arena.alloc<double>(16, st);
+    // ---- load-vector tables
+    {
+        std::vector<PatchQ> pq(N);
+        std::vector<double> bas, w, x;
+        int64_t qo = 0;
+        for (int k = 0; k < N; ++k) {
+            const Patch& pa = pl.patches[k];
+            PatchQ& Q = pq[k];
+            for (int d = 0; d < 3; ++d) {
+                Q.nel[d] = d < dim ? pa.lv[0].nel[d] : 1;
+                Q.Q[d] = d < dim ? Q.nel[d] * (pa.p[d] + 1) : 1;
+                Q.boff[d] = (int64_t)bas.size();
+                if (d < dim) bas.insert(bas.end(), pa.qpN[d].begin(), pa.qpN[d].end());
+            }
+            Q.qoff = qo;
+            qo += pa.n_qp;
+            w.insert(w.end(), pa.qpw.begin(), pa.qpw.end());
+            x.insert(x.end(), pa.qpx.begin(), pa.qpx.end());
+        }
+        PQ = arena.upload(pq, st);
+        basis = arena.upload(bas, st);
+        qpw = arena.upload(w, st);
+        qpx = arena.upload(x, st);
+        HIPCHECK(hipStreamSynchronize(st));
+    }
+    // ---- primal space
+    npi = pl.n_primal;
+    {
+        std::vector<int32_t> nk(N);
+        std::vector<int64_t> R((size_t)N * NPMAX, 0), ud((size_t)N * NPMAX, -1), ep((size_t)N * NPMAX + 1, 0), ed;
+        for (int k = 0; k < N; ++k) {
+            const Patch& pa = pl.patches[k];
+            nk[k] = (int32_t)pa.primal_global.size();
+            if (nk[k] > NPMAX) throw Error(IETI_ENOTSUP, "too many primal constraints on a patch");
+            npk_max = std::max(npk_max, nk[k]);
+            for (int j = 0; j < NPMAX; ++j) {
+                ep[(size_t)k * NPMAX + j] = (int64_t)ed.size();
+                if (j < nk[k]) {
+                    R[(size_t)k * NPMAX + j] = pa.primal_global[j];
+                    if (pa.primal_corner[j] >= 0) {
+                        int c = pa.primal_corner[j];
+                        int idx[3] = {0, 0, 0};
+                        for (int d = 0; d < dim; ++d) idx[d] = (c >> d & 1) ? pa.lv[0].M[d] - 1 : 0;
+                        int64_t li = idx[0] + (int64_t)pa.lv[0].M[0] * (idx[1] + (int64_t)pa.lv[0].M[1] * idx[2]);
+                        ud[(size_t)k * NPMAX + j] = D0.hL[k].voff + li;
+                    } else {
+                        for (int64_t li : pa.primal_edge[j]) ed.push_back(D0.hL[k].voff + li);
+                    }
+                }
+            }
+        }
+        ep[(size_t)N * NPMAX] = (int64_t)ed.size();
+        npk = arena.upload(nk, st);
+        Rk = arena.upload(R, st);
+        unit_dev = arena.upload(ud, st);
+        edge_ptr = arena.upload(ep, st);
+        edge_dev = arena.upload(ed, st);
+        pri_ptr = arena.upload(pl.pri_ptr, st);
+        pri_patch = arena.upload(pl.pri_patch, st);
+        pri_local = arena.upload(pl.pri_local, st);
+        cbuf = arena.alloc<double>((int64_t)N * NPMAX, st);
+        ebuf = arena.alloc<double>((int64_t)N * NPMAX, st);
+        coefbuf = arena.alloc<double>((int64_t)N * NPMAX, st);
+        gpi = arena.alloc<double>(std::max<int64_t>(npi, 1), st);
+        upi = arena.alloc<double>(std::max<int64_t>(npi, 1), st);
+        psiG = arena.alloc<double>(std::max<int64_t>(nslots, 1) * NPMAX, st);
+        HIPCHECK(hipStreamSynchronize(st));
+    }
+    if (npi > 0) {
+        const int nj = npk_max;
+        psi = arena.alloc<double>((int64_t)nj * len0, st);
+        // raw columns Y_j = K_rr^{-1} rhs_j (device scratch for setup)
+        double* Y = nullptr;
+        HIPCHECK(hipMalloc((void**)&Y, sizeof(double) * (size_t)nj * len0));
+        std::unique_ptr<double, void (*)(double*)> Yguard(Y, [](double* p) { (void)hipFree(p); });
+        HIPCHECK(hipMemsetAsync(Y, 0, sizeof(double) * (size_t)nj * len0, st));
+        for (int j = 0; j < nj; ++j) {
+            fill<double>(e64, len0, 0.0);
+            hipLaunchKernelGGL(k_unit, dim3(nblk(N, 256)), dim3(256), 0, st, N, unit_dev, j, e64);
+            check_launch();
+            stencil<double, double, double, EPI_APPLY>(0, false, MODE_N, coef64, e64, b64, nullptr, nullptr, nullptr,
+                                                       -1.0, 0);
+            hipLaunchKernelGGL(k_edge_rhs, dim3(N), dim3(256), 0, st, N, edge_ptr, edge_dev, j, b64);
+            check_launch();
+            fcg(b64, pl.opt.basis_tol, pl.opt.inner_max_it);
+            HIPCHECK(hipMemcpyAsync(Y + (size_t)j * len0, fx, sizeof(double) * len0, hipMemcpyDeviceToDevice, st));
+        }
+        // edge means of the raw columns -> combination coefficients (host, tiny dense algebra)
+        double* A = arena.alloc<double>((int64_t)N * NPMAX * NPMAX, st);
+        hipLaunchKernelGGL(k_edge_avg, dim3(N), dim3(TILE), 0, st, N, npk, edge_ptr, edge_dev, Y, len0, A);
+        check_launch();
+        std::vector<double> hA((size_t)N * NPMAX * NPMAX), hT((size_t)N * NPMAX * NPMAX, 0.0);
+        HIPCHECK(hipMemcpyAsync(hA.data(), A, hA.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+        sync();
+        for (int k = 0; k < N; ++k) {
+            const Patch& pa = pl.patches[k];
+            const int nkj = (int)pa.primal_global.size();
+            std::vector<int> V, E;
+            for (int j = 0; j < nkj; ++j) (pa.primal_corner[j] >= 0 ? V : E).push_back(j);
+            const int ne = (int)E.size();
+            auto Aat = [&](int col, int e) { return hA[((size_t)k * NPMAX + col) * NPMAX + e]; };
+            // H[e][e'] = mean over edge e of raw column e'
+            std::vector<double> H((size_t)ne * ne), Hi((size_t)ne * ne, 0.0);
+            for (int a = 0; a < ne; ++a)
+                for (int b = 0; b < ne; ++b) H[(size_t)a * ne + b] = Aat(E[b], E[a]);
+            // invert H by Gauss-Jordan with partial pivoting
+            for (int a = 0; a < ne; ++a) Hi[(size_t)a * ne + a] = 1.0;
+            for (int c = 0; c < ne; ++c) {
+                int piv = c;
+                for (int r = c + 1; r < ne; ++r)
+                    if (std::fabs(H[(size_t)r * ne + c]) > std::fabs(H[(size_t)piv * ne + c])) piv = r;
+                if (H[(size_t)piv * ne + c] == 0.0) throw Error(IETI_EINVAL, "singular edge-average system");
+                for (int q = 0; q < ne; ++q) {
+                    std::swap(H[(size_t)c * ne + q], H[(size_t)piv * ne + q]);
+                    std::swap(Hi[(size_t)c * ne + q], Hi[(size_t)piv * ne + q]);
+                }
+                double dv = H[(size_t)c * ne + c];
+                for (int q = 0; q < ne; ++q) {
+                    H[(size_t)c * ne + q] /= dv;
+                    Hi[(size_t)c * ne + q] /= dv;
+                }
+                for (int r = 0; r < ne; ++r)
+                    if (r != c) {
+                        double f = H[(size_t)r * ne + c];
+                        if (f == 0.0) continue;
+                        for (int q = 0; q < ne; ++q) {
+                            H[(size_t)r * ne + q] -= f * H[(size_t)c * ne + q];
+                            Hi[(size_t)r * ne + q] -= f * Hi[(size_t)c * ne + q];
+                        }
+                    }
+            }
+            auto Tset = [&](int jp, int j, double v) { hT[((size_t)k * NPMAX + jp) * NPMAX + j] = v; };
+            // edge columns: psi_e = sum_e' Y_e' Hinv[e'][e]
+            for (int a = 0; a < ne; ++a)
+                for (int b = 0; b < ne; ++b) Tset(E[b], E[a], Hi[(size_t)b * ne + a]);
+            // vertex columns: psi_v = e_v + Y_v - Psi_E (C_E Y_v)
+            for (int v : V) {
+                Tset(v, v, 1.0);
+                for (int b = 0; b < ne; ++b) {
+                    double s = 0.0;
+                    for (int a = 0; a < ne; ++a) s += Hi[(size_t)b * ne + a] * Aat(v, E[a]);
+                    Tset(E[b], v, -s);
+                }
+            }
+        }
+        double* Tm = arena.upload(hT, st);
+        hipLaunchKernelGGL(k_combine, dim3(tile_grid(D0.nt_all)), dim3(TILE), 0, st, D0.L, D0.tiles_all, D0.nt_all,
+                           npk, unit_dev, Y, Tm, len0, psi);
+        check_launch();
+        // local coarse matrices S_k = Psi^T K Psi  (K without the boundary), assembled on the host
+        for (int j = 0; j < nj; ++j)
+            stencil<double, double, double, EPI_APPLY>(0, false, MODE_K, coef64, psi + (size_t)j * len0,
+                                                       Y + (size_t)j * len0, nullptr, nullptr, nullptr, 1.0, 0);
+        double* Sk = arena.alloc<double>((int64_t)N * NPMAX * NPMAX, st);
+        for (int j = 0; j < nj; ++j) {
+            hipLaunchKernelGGL(k_patch_gram, dim3(N), dim3(TILE), 0, st, N, D0.L, npk, psi, Y, len0, j, Sk);
+            check_launch();
+        }
+        std::vector<double> hS((size_t)N * NPMAX * NPMAX);
+        HIPCHECK(hipMemcpyAsync(hS.data(), Sk, hS.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+        sync();
+        std::vector<double> S((size_t)npi * npi, 0.0);
+        for (int k = 0; k < N; ++k) {
+            const Patch& pa = pl.patches[k];
+            const int nkj = (int)pa.primal_global.size();
+            for (int a = 0; a < nkj; ++a)
+                for (int b = 0; b < nkj; ++b)
+                    S[(size_t)pa.primal_global[a] * npi + pa.primal_global[b]] +=
+                        0.5 * (hS[((size_t)k * NPMAX + a) * NPMAX + b] + hS[((size_t)k * NPMAX + b) * NPMAX + a]);
+        }
+        // Cholesky S = C C^T and explicit inverse (FP64)
+        const int64_t n = npi;
+        std::vector<double> Cf = S;
+        for (int64_t j = 0; j < n; ++j) {
+            double s = Cf[(size_t)j * n + j];
+            for (int64_t k = 0; k < j; ++k) s -= Cf[(size_t)j * n + k] * Cf[(size_t)j * n + k];
+            if (!(s > 0)) throw Error(IETI_EINVAL, "coarse matrix S_PiPi is not positive definite");
+            double c = std::sqrt(s);
+            Cf[(size_t)j * n + j] = c;
+            for (int64_t i = j + 1; i < n; ++i) {
+                double t = Cf[(size_t)i * n + j];
+                for (int64_t k = 0; k < j; ++k) t -= Cf[(size_t)i * n + k] * Cf[(size_t)j * n + k];
+                Cf[(size_t)i * n + j] = t / c;
+            }
+        }
+        std::vector<double> Si((size_t)n * n), z(n);
+        for (int64_t j = 0; j < n; ++j) {
+            std::fill(z.begin(), z.end(), 0.0);
+            z[j] = 1.0;
+            for (int64_t i = 0; i < n; ++i) {
+                double t = z[i];
+                for (int64_t k = 0; k < i; ++k) t -= Cf[(size_t)i * n + k] * z[k];
+                z[i] = t / Cf[(size_t)i * n + i];
+            }
+            for (int64_t i = n - 1; i >= 0; --i) {
+                double t = z[i];
+                for (int64_t k = i + 1; k < n; ++k) t -= Cf[(size_t)k * n + i] * z[k];
+                z[i] = t / Cf[(size_t)i * n + i];
+            }
+            for (int64_t i = 0; i < n; ++i) Si[(size_t)i * n + j] = z[i];
+        }
+        Sinv = arena.upload(Si, st);
+        hipLaunchKernelGGL(k_psi_slots, dim3(nblk(std::max<int64_t>(nslots, 1), 256)), dim3(256), 0, st, nslots,
+                           slot_patch, slot_dev, npk, psi, len0, psiG);
+        check_launch();
+        sync();
+    }
+    sync();
+}
+
+template <typename T>
+int Solver<T>::solve(const double* f_qp, double* u_out, ieti_stats* stp) {
+    const Plan& pl = *plan;
+    using clk = std::chrono::steady_clock;
+    auto ms = [](clk::time_point a, clk::time_point b) { return std::chrono::duration<double, std::milli>(b - a).count(); };
+    inner_calls = inner_sum = 0;
+    inner_max = 0;
+    ieti_stats st{};
+    st.ndof_torn = pl.ndof_torn;
+    st.ndof_global = pl.ndof_global;
+    st.n_lambda = pl.n_lambda;
+    st.n_primal = pl.n_primal;
+    DevLevel& D0 = lev[0];
+    sync();
+    auto t0 = clk::now();
+    // ---- load vector and d = B K~^{-1} f
+    hipLaunchKernelGGL(k_loadvec, dim3(tile_grid(D0.nt_all)), dim3(TILE), 0, stream, D0.L, PQ, D0.tiles_all,
+                       D0.nt_all, basis, qpw, f_qp, f64);
+    check_launch();
+    // reject non-finite data: |f|^2 must be finite
+    hipLaunchKernelGGL(k_sq, dim3(tile_grid(D0.nt_all)), dim3(TILE), 0, stream, D0.L, D0.tiles_all, D0.nt_all, f64,
+                       (int)MODE_K, partial);
+    check_launch();
+    hipLaunchKernelGGL(k_sum, dim3(1), dim3(1024), 0, stream, partial, (int64_t)D0.nt_all, sc + 8);
+    check_launch();
+    ktilde_inv(f64, true, pl.opt.inner_tol, u64);
+    const int64_t nl = nlam;
+    double r0 = 0.0, scale = 0.0;
+    if (nl > 0) {
+        gather(u64, false, lr);
+        gather(u64, false, lz, true);
+        gather(u64, false, ltmp, false, true);
+        hipLaunchKernelGGL(k_norms, dim3(1), dim3(1024), 0, stream, nl, lr, lz, ltmp, sc + 10);
+        check_launch();
+    }
+    HIPCHECK(hipMemcpyAsync(h_sc, sc, 16 * sizeof(double), hipMemcpyDeviceToHost, stream));
+    sync();
+    if (!std::isfinite(h_sc[8])) throw Error(IETI_EINVAL, "right-hand side is not finite");
+    if (nl > 0) {
+        r0 = std::sqrt(h_sc[10]);
+        scale = std::sqrt(h_sc[11] + h_sc[12]);
+    }
+    auto t1 = clk::now();
+    st.residual_initial = r0;
+    // ---- outer CG
+    fill<double>(lam, std::max<int64_t>(nl, 1), 0.0);
+    int it = 0;
+    bool conv = true;
+    double rnorm = r0;
+    const double zero_thr = (pl.opt.local_solver == IETI_LOCAL_EXACT ? 1e-13 : 10.0 * pl.opt.inner_tol) * scale;
+    if (nl > 0 && r0 > zero_thr && r0 > 0.0) {
+        applyPrec(lr, lz);
+        hipLaunchKernelGGL(k_pcg, dim3(1), dim3(1024), 0, stream, 0, nl, lam, lr, lz, lp, lq, sc);
+        check_launch();
+        conv = false;
+        while (it < pl.opt.max_it) {
+            applyF(lp, lq);
+            hipLaunchKernelGGL(k_pcg, dim3(1), dim3(1024), 0, stream, 1, nl, lam, lr, lz, lp, lq, sc);
+            check_launch();
+            HIPCHECK(hipMemcpyAsync(h_sc, sc, 8 * sizeof(double), hipMemcpyDeviceToHost, stream));
+            sync();
+            ++it;
+            rnorm = std::sqrt(h_sc[3]);
+            if (h_sc[4] != 0.0) { st.breakdown = 1; conv = true; break; }
+            if (rnorm <= pl.opt.tol * r0) { conv = true; break; }
+            applyPrec(lr, lz);
+            hipLaunchKernelGGL(k_pcg, dim3(1), dim3(1024), 0, stream, 2, nl, lam, lr, lz, lp, lq, sc);
+            check_launch();
+        }
+    } else if (nl > 0) {
+        st.breakdown = 1;
+    }
+    sync();
+    auto t2 = clk::now();
+    st.outer_iterations = it;
+    st.residual_final = rnorm;
+    // ---- recovery u = K~^{-1} (f - B^T lambda), averaged copies, global residual
+    scatter(lam, false, b64);
+    hipLaunchKernelGGL(k_sub, dim3(tile_grid(D0.nt_all)), dim3(TILE), 0, stream, D0.L, D0.tiles_all, D0.nt_all, f64,
+                       b64, w64);
+    check_launch();
+    ktilde_inv(w64, true, pl.opt.inner_tol, u64);
+    if (ngroups > 0) {
+        hipLaunchKernelGGL(k_group_mean, dim3(nblk(ngroups, 256)), dim3(256), 0, stream, ngroups, grp_ptr, grp_dev,
+                           u64);
+        check_launch();
+    }
+    stencil<double, double, double, EPI_RESID>(0, false, MODE_K, coef64, u64, s64, f64, nullptr, nullptr, 0.0, 0);
+    // |r| and |f| of the assembled (conforming) vectors
+    HIPCHECK(hipMemcpyAsync(e64, f64, sizeof(double) * len0, hipMemcpyDeviceToDevice, stream));
+    std::vector<double> acc(2, 0.0);
+    for (int which = 0; which < 2; ++which) {
+        double* v = which == 0 ? s64 : e64;
+        if (ngroups > 0) {
+            hipLaunchKernelGGL(k_group_assemble, dim3(nblk(ngroups, 256)), dim3(256), 0, stream, ngroups, grp_ptr,
+                               grp_dev, v);
+            check_launch();
+        }
+        hipLaunchKernelGGL(k_sq, dim3(tile_grid(D0.nt_all)), dim3(TILE), 0, stream, D0.L, D0.tiles_all, D0.nt_all, v,
+                           (int)MODE_K, partial);
+        check_launch();
+        hipLaunchKernelGGL(k_sum, dim3(1), dim3(1024), 0, stream, partial, (int64_t)D0.nt_all, sc + 12 + which);
+        check_launch();
+    }
+    HIPCHECK(hipMemcpyAsync(h_sc + 12, sc + 12, 2 * sizeof(double), hipMemcpyDeviceToHost, stream));
+    sync();
+    acc[0] = h_sc[12];
+    acc[1] = h_sc[13];
+    st.global_residual = acc[1] > 0 ? std::sqrt(std::max(acc[0], 0.0) / acc[1]) : 0.0;
+    hipLaunchKernelGGL(k_copy_out, dim3(tile_grid(D0.nt_all)), dim3(TILE), 0, stream, D0.L, D0.tiles_all, D0.nt_all,
+                       torn_off, u64, u_out);
+    check_launch();
+    sync();
+    auto t3 = clk::now();
+    if (prof.on) prof.collect();
+    st.time_rhs_ms = ms(t0, t1);
+    st.time_pcg_ms = ms(t1, t2);
+    st.time_recovery_ms = ms(t2, t3);
+    st.time_total_ms = ms(t0, t3);
+    st.inner_iterations_max = inner_max;
+    st.inner_iterations_mean = inner_calls ? (double)inner_sum / (double)inner_calls : 0.0;
+    if (stp) *stp = st;
+    return conv ? IETI_OK : IETI_ENOCONV;
+}
+
+}  // namespace ieti
+
+// ------------------------------------------------------------------ C ABI
+
+using namespace ieti;
+
+struct ieti_handle {
+    std::unique_ptr<SolverBase> s;
+};
+
+template <typename F>
+static int guarded(F&& f) {
+    try {
+        return f();
+    } catch (const Error& e) {
+        set_last_error(e.what());
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        set_last_error("host allocation failed");
+        return IETI_ENOMEM;
+    } catch (const std::exception& e) {
+        set_last_error(e.what());
+        return IETI_EINVAL;
+    }
+}
+
+extern "C" {
+
+int ieti_setup(const ieti_patch* patches, int32_t n_patches, const double* primal_vertices, int32_t n_primal_vertices,
+               const ieti_options* opt, ieti_handle** out) {
+    if (!out) return IETI_EINVAL;
+    *out = nullptr;
+    return guarded([&] {
+        std::unique_ptr<Plan> plan(build_plan(patches, n_patches, primal_vertices, n_primal_vertices, opt));
+        if (plan->opt.local_solver != IETI_LOCAL_MG) throw Error(IETI_ENOTSUP, "exact local solves are not built");
+        if (plan->opt.device >= 0) HIPCHECK(hipSetDevice(plan->opt.device));
+        std::unique_ptr<SolverBase> s;
+        if (plan->opt.mg_precision == 32) s.reset(new Solver<float>());
+        else s.reset(new Solver<double>());
+        s->plan = std::move(plan);
+        if (s->plan->opt.stream) {
+            s->stream = (hipStream_t)s->plan->opt.stream;
+        } else {
+            HIPCHECK(hipStreamCreate(&s->stream));
+            s->own_stream = true;
+        }
+        s->setup();
+        auto* h = new ieti_handle();
+        h->s = std::move(s);
+        *out = h;
+        return IETI_OK;
+    });
+}
+
+int ieti_quadrature(const ieti_handle* h, double* x, int32_t on_device, int64_t* n_qp) {
+    if (!h) return IETI_EINVAL;
+    return guarded([&] {
+        if (n_qp) *n_qp = h->s->plan->n_qp;
+        if (x) h->s->quadrature(x, on_device != 0);
+        return IETI_OK;
+    });
+}
+
+int ieti_solve(ieti_handle* h, const double* f_qp, double* u, ieti_stats* stats) {
+    if (!h || !f_qp || !u) return IETI_EINVAL;
+    return guarded([&] { return h->s->solve(f_qp, u, stats); });
+}
+
+int ieti_profile_enable(ieti_handle* h, int32_t enable) {
+    if (!h) return IETI_EINVAL;
+    return guarded([&] {
+        HIPCHECK(hipStreamSynchronize(h->s->stream));
+        h->s->prof.collect();
+        h->s->prof.reset();
+        h->s->prof.on = enable != 0;
+        return IETI_OK;
+    });
+}
+
+int ieti_profile_query(const ieti_handle* h, int32_t kernel, int64_t* launches, double* total_ms,
+                       double* total_bytes) {
+    if (!h || kernel < 0 || kernel >= IETI_KPROF_COUNT) return IETI_EINVAL;
+    const KProf& p = h->s->prof;
+    if (launches) *launches = p.launches[kernel];
+    if (total_ms) *total_ms = p.ms[kernel];
+    if (total_bytes) *total_bytes = p.bytes[kernel];
+    return IETI_OK;
+}
+
+int ieti_sizes(const ieti_handle* h, int64_t* n_qp, int64_t* ndof_torn, int64_t* device_bytes) {
+    if (!h) return IETI_EINVAL;
+    if (n_qp) *n_qp = h->s->plan->n_qp;
+    if (ndof_torn) *ndof_torn = h->s->plan->ndof_torn;
+    if (device_bytes) *device_bytes = (int64_t)h->s->arena.bytes;
+    return IETI_OK;
+}
+
+void ieti_destroy(ieti_handle* h) {
+    if (!h) return;
+    try {
+        if (h->s) {
+            (void)hipStreamSynchronize(h->s->stream);
+            hipStream_t st = h->s->stream;
+            bool own = h->s->own_stream;
+            h->s.reset();
+            if (own) (void)hipStreamDestroy(st);
+        }
+    } catch (...) {
+    }
+    delete h;
+}
+
+const char* ieti_strerror(int code) {
+    switch (code) {
+    case IETI_OK: return "ok";
+    case IETI_EINVAL: return "invalid argument";
+    case IETI_ENONCONFORMING: return "non-conforming interface";
+    case IETI_EGEOM: return "invalid geometry";
+    case IETI_ENOMEM: return "out of memory";
+    case IETI_ENOCONV: return "no convergence";
+    case IETI_EDEVICE: return "device error";
+    case IETI_ENOTSUP: return "not supported";
+    default: return "unknown error";
+    }
+}
+
+const char* ieti_last_error(void) { return ieti::last_error(); }
+
+}  // extern "C"
