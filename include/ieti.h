@@ -53,7 +53,7 @@ extern "C" {
 #define IETI_LOCAL_EXACT  1   /* exact local solves: banded Cholesky (D-D) */
 
 #define IETI_PRIMAL_VERTICES  1   /* primal unknowns at patch vertices */
-#define IETI_PRIMAL_EDGES     2   /* plus edge averages (3D) */
+#define IETI_PRIMAL_EDGES     2   /* plus edge averages (3D: patch edges; 2D: patch sides) */
 
 typedef struct ieti_patch {
     int32_t dim;               /* 2 or 3 */

@@ -5,7 +5,8 @@ Written in the notation of Sec. 2-3:
 * tearing: every patch keeps its own copy of its coefficients; the
   boundary (Dirichlet) coefficients are dropped (V_0 = H^1_0);
 * primal ("strongly enforced") continuity: the values at patch vertices and,
-  in 3D on request, the averages over patch edges; C^(k) evaluates them on
+  on request, the averages over patch edges (in 2D the patch sides, the
+  choice of the paper's 2D experiments, Sec. 4); C^(k) evaluates them on
   patch k and R_Pi^(k) maps local to global primal unknowns;
 * the primal basis of W_Pi solves the saddle-point systems of eq. (6) with
   the stiffness K^(k) in place of S^(k) (Pechstein's approach), for every
@@ -55,7 +56,17 @@ def _local_corners(shape) -> List[int]:
 
 
 def _local_edges(shape) -> List[np.ndarray]:
-    """Coefficients strictly inside each of the 12 edges of a 3D patch."""
+    """Coefficients strictly inside each edge of a patch: the 12 edges of a 3D
+    patch, or the 4 sides of a 2D patch (the edges of a 2D decomposition)."""
+    if len(shape) == 2:
+        out = []
+        for free in range(2):
+            other = 1 - free
+            for e in (0, shape[other] - 1):
+                run = np.arange(1, shape[free] - 1)
+                idx = run * (1 if free == 0 else shape[0]) + e * (shape[0] if other == 1 else 1)
+                out.append(idx.astype(np.int64))
+        return out
     assert len(shape) == 3
     out = []
     for free in range(3):
@@ -100,7 +111,7 @@ class IetiDP:
                     vertex_g.add(g)
         vertex_g = sorted(vertex_g)
         edges = {}
-        if wl.dim == 3 and primal == "vertices+edges":
+        if primal == "vertices+edges":
             for k in range(N):
                 for loc in _local_edges(lay.shapes[k]):
                     g = lay.gid[k][loc]

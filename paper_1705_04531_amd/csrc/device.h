@@ -8,11 +8,22 @@ constexpr int TILE = 256;        // coefficients per work-group tile (one per th
 constexpr int PW = 8;            // padded width of 1D transfer bands (degree <= 6)
 constexpr int NPMAX = 20;        // local primal constraints per patch (8 vertices + 12 edges)
 
+// Degree classes with their own unrolled kernels: 2D (p0, p1) in {2,3,4}^2 ->
+// (p0-2) + 3 (p1-2); 3D p0=p1=p2 in {2,3} -> 9 + (p-2); anything else runs
+// generic loops (class NCLASS).
+constexpr int NCLASS = 11;
+inline int degree_class(int dim, int p0, int p1, int p2) {
+    if (dim == 2 && p0 >= 2 && p0 <= 4 && p1 >= 2 && p1 <= 4) return (p0 - 2) + 3 * (p1 - 2);
+    if (dim == 3 && p0 == p1 && p1 == p2 && p0 >= 2 && p0 <= 3) return 9 + (p0 - 2);
+    return NCLASS;
+}
+
 // One patch at one multigrid level.
 struct PatchLev {
     int32_t M[3];          // basis functions per direction (1 in unused directions)
     int32_t p[3];          // degree per direction (0 in unused directions)
     int32_t dim, nst;
+    int32_t pclass;        // compile-time degree class of the kernels, -1 = generic loops
     uint32_t mbits[3];     // per mode (N, D, K): side bits | corner bits << 8
     int32_t patch;         // patch id
     int32_t coarse;        // index of the same patch in the next coarser level, -1 if coarsest here
@@ -39,6 +50,10 @@ struct PatchQ {
 struct Tile {
     int32_t pl;            // index into the level's PatchLev array
     int32_t start;         // first coefficient of the tile
+    int32_t gid;           // index of the tile in the level's list of all tiles (partial sums)
+    int32_t pad;
 };
+
+constexpr int KMAX = 8;    // Chebyshev steps with precomputed coefficients
 
 }  // namespace ieti

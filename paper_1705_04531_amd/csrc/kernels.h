@@ -9,6 +9,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "device.h"
 
 namespace ieti {
@@ -28,31 +30,29 @@ __device__ __forceinline__ int tile_index(int ntiles) {
     return t < ntiles ? t : -1;
 }
 
-__device__ __forceinline__ bool masked(const PatchLev& P, int mode, int i0, int i1, int i2) {
-    const uint32_t mb = P.mbits[mode];
+__device__ __forceinline__ bool masked_bits(uint32_t mb, int dim, int M0, int M1, int M2, int i0, int i1, int i2) {
     const uint32_t sides = mb & 0xFFu, corners = mb >> 8;
-    const int ii[3] = {i0, i1, i2};
-    bool m = false;
-    int cb = 0, nend = 0;
-    for (int d = 0; d < P.dim; ++d) {
-        const bool lo = ii[d] == 0, hi = ii[d] == P.M[d] - 1;
-        if (lo && ((sides >> (2 * d)) & 1u)) m = true;
-        if (hi && ((sides >> (2 * d + 1)) & 1u)) m = true;
-        if (lo || hi) {
-            ++nend;
-            if (hi) cb |= 1 << d;
-        }
-    }
-    if (nend == P.dim && ((corners >> cb) & 1u)) m = true;
+    const bool lo0 = i0 == 0, hi0 = i0 == M0 - 1, lo1 = i1 == 0, hi1 = i1 == M1 - 1;
+    const bool lo2 = dim == 3 && i2 == 0, hi2 = dim == 3 && i2 == M2 - 1;
+    bool m = (lo0 && (sides & 1u)) || (hi0 && (sides & 2u)) || (lo1 && (sides & 4u)) || (hi1 && (sides & 8u)) ||
+             (lo2 && (sides & 16u)) || (hi2 && (sides & 32u));
+    const bool corner = (lo0 || hi0) && (lo1 || hi1) && (dim == 2 || lo2 || hi2);
+    const int cb = (hi0 ? 1 : 0) | (hi1 ? 2 : 0) | (hi2 ? 4 : 0);
+    if (corner && ((corners >> cb) & 1u)) m = true;
     return m;
 }
 
+__device__ __forceinline__ bool masked(const PatchLev& P, int mode, int i0, int i1, int i2) {
+    return masked_bits(P.mbits[mode], P.dim, P.M[0], P.M[1], P.M[2], i0, i1, i2);
+}
+
 __device__ __forceinline__ void unlin(const PatchLev& P, int64_t i, int& i0, int& i1, int& i2) {
-    const int64_t M01 = (int64_t)P.M[0] * P.M[1];
-    i2 = (int)(i / M01);
-    const int64_t r = i - (int64_t)i2 * M01;
-    i1 = (int)(r / P.M[0]);
-    i0 = (int)(r - (int64_t)i1 * P.M[0]);
+    const int M0 = P.M[0], M01 = P.M[0] * P.M[1];
+    const int ii = (int)i;
+    i2 = ii / M01;
+    const int r = ii - i2 * M01;
+    i1 = r / M0;
+    i0 = r - i1 * M0;
 }
 
 // deterministic block sum of NV doubles (blockDim.x == TILE); result valid in thread 0
@@ -78,22 +78,135 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* lds) {
     __syncthreads();
 }
 
-// Chebyshev step coefficients: d_k = s1 d_{k-1} + s2 D^{-1} r_k on [lo, hi] * lmax
-__device__ __forceinline__ void cheb_coeffs(double lmax, double lo, double hi, int k, double& s1, double& s2) {
-    const double a = lo * lmax, b = hi * lmax;
-    const double theta = 0.5 * (a + b), delta = 0.5 * (b - a), sigma = theta / delta;
-    if (k == 0) {
-        s1 = 0.0;
-        s2 = 1.0 / theta;
-        return;
+// ------------------------------------------------------------------ degree classes
+//
+// Loops over stencil offsets and transfer bands are unrolled for the common
+// degrees (one kernel instance per class, see degree_class) so that every
+// load of a work-item is in flight at once and no instance carries the
+// register needs of another.  P0 < 0 selects generic loops.
+
+// sum_o K(i, i+o) x(i+o) over the full stencil from the half stencil at i
+// (upper half) and at i-o (lower half, by symmetry); diag = K(i, i).
+// P0 < 0: degrees p0..p2 at run time.
+template <int P0, int P1, int P2, typename TC, typename TX>
+__device__ __forceinline__ TC stencil_sum(const TC* __restrict__ c, const TX* __restrict__ xp, int cs, int M0,
+                                          int M01, int p0, int p1, int p2, TC& diag) {
+    TC acc = TC(0);
+    if constexpr (P0 >= 0) {
+        int s = 0;
+#pragma unroll
+        for (int o2 = 0; o2 <= P2; ++o2)
+#pragma unroll
+            for (int o1 = (o2 == 0 ? 0 : -P1); o1 <= P1; ++o1)
+#pragma unroll
+                for (int o0 = ((o2 == 0 && o1 == 0) ? 0 : -P0); o0 <= P0; ++o0) {
+                    const int off = o0 + o1 * M0 + o2 * M01;
+                    const TC cu = c[s * cs];
+                    if (s == 0) {
+                        diag = cu;
+                        acc += cu * TC(xp[0]);
+                    } else {
+                        acc += cu * TC(xp[off]) + c[s * cs - off] * TC(xp[-off]);
+                    }
+                    ++s;
+                }
+    } else {
+        int s = 0;
+        for (int o2 = 0; o2 <= p2; ++o2)
+            for (int o1 = (o2 == 0 ? 0 : -p1); o1 <= p1; ++o1) {
+                const int o0s = (o2 == 0 && o1 == 0) ? 0 : -p0;
+                const int base = o1 * M0 + o2 * M01;
+                for (int o0 = o0s; o0 <= p0; ++o0, ++s) {
+                    const int off = base + o0;
+                    const TC cu = c[s * cs];
+                    if (s == 0) {
+                        diag = cu;
+                        acc += cu * TC(xp[0]);
+                    } else {
+                        acc += cu * TC(xp[off]) + c[s * cs - off] * TC(xp[-off]);
+                    }
+                }
+            }
     }
-    double rho_prev = 1.0 / sigma, rho = rho_prev;
-    for (int j = 1; j <= k; ++j) {
-        rho_prev = rho;
-        rho = 1.0 / (2.0 * sigma - rho_prev);
+    return acc;
+}
+
+// As stencil_sum, but only the innermost offset loop is unrolled (fewer
+// registers; used inside the coarse-level kernel).
+template <int P0, typename TC, typename TX>
+__device__ __forceinline__ TC stencil_sum_rows(const TC* __restrict__ c, const TX* __restrict__ xp, int cs, int M0,
+                                               int M01, int p0, int p1, int p2, TC& diag) {
+    TC acc = TC(0);
+    int s = 0;
+    for (int o2 = 0; o2 <= p2; ++o2)
+        for (int o1 = (o2 == 0 ? 0 : -p1); o1 <= p1; ++o1) {
+            const int base = o1 * M0 + o2 * M01;
+            if (o2 == 0 && o1 == 0) {
+                // row of the diagonal: offsets 0..p0
+                const TC c0 = c[0];
+                diag = c0;
+                acc += c0 * TC(xp[0]);
+                if constexpr (P0 >= 0) {
+#pragma unroll
+                    for (int o0 = 1; o0 <= P0; ++o0)
+                        acc += c[o0 * cs] * TC(xp[o0]) + c[o0 * cs - o0] * TC(xp[-o0]);
+                    s = P0 + 1;
+                } else {
+                    for (int o0 = 1; o0 <= p0; ++o0) acc += c[o0 * cs] * TC(xp[o0]) + c[o0 * cs - o0] * TC(xp[-o0]);
+                    s = p0 + 1;
+                }
+            } else {
+                if constexpr (P0 >= 0) {
+#pragma unroll
+                    for (int o0 = -P0; o0 <= P0; ++o0) {
+                        const int off = base + o0;
+                        const int sj = s + o0 + P0;
+                        acc += c[sj * cs] * TC(xp[off]) + c[sj * cs - off] * TC(xp[-off]);
+                    }
+                    s += 2 * P0 + 1;
+                } else {
+                    for (int o0 = -p0; o0 <= p0; ++o0) {
+                        const int off = base + o0;
+                        const int sj = s + o0 + p0;
+                        acc += c[sj * cs] * TC(xp[off]) + c[sj * cs - off] * TC(xp[-off]);
+                    }
+                    s += 2 * p0 + 1;
+                }
+            }
+        }
+    return acc;
+}
+
+// Tensor transfer sum over a band: sum_{a} v0[a0] v1[a1] v2[a2] src[row(a1,a2) + lo0 + a0]
+// with compile-time band widths W = p + 2 (W < 0: run time w0..w2).
+template <int W0, int W1, int W2, typename T>
+__device__ __forceinline__ double band_sum(const T* __restrict__ v0, const T* __restrict__ v1,
+                                           const T* __restrict__ v2, const T* __restrict__ src, int M0, int M01,
+                                           int w0, int w1, int w2, int dim) {
+    double acc = 0.0;
+    if constexpr (W0 > 0) {
+#pragma unroll
+        for (int a2 = 0; a2 < W2; ++a2) {
+            const double f2 = W2 > 1 ? (double)v2[a2] : 1.0;
+#pragma unroll
+            for (int a1 = 0; a1 < W1; ++a1) {
+                const double f12 = f2 * (double)v1[a1];
+                const T* row = src + a1 * M0 + a2 * M01;
+#pragma unroll
+                for (int a0 = 0; a0 < W0; ++a0) acc += f12 * (double)v0[a0] * (double)row[a0];
+            }
+        }
+    } else {
+        for (int a2 = 0; a2 < w2; ++a2) {
+            const double f2 = dim == 3 ? (double)v2[a2] : 1.0;
+            for (int a1 = 0; a1 < w1; ++a1) {
+                const double f12 = f2 * (double)v1[a1];
+                const T* row = src + a1 * M0 + a2 * M01;
+                for (int a0 = 0; a0 < w0; ++a0) acc += f12 * (double)v0[a0] * (double)row[a0];
+            }
+        }
     }
-    s1 = rho * rho_prev;
-    s2 = 2.0 * rho / delta;
+    return acc;
 }
 
 // ------------------------------------------------------------------ stencil apply
@@ -118,53 +231,41 @@ struct StencilArgs {
     const int* active;     // per patch, or null
     double alpha;          // EPI_APPLY
     int cheb_k;            // EPI_CHEB step
-    double cheb_hi;        // upper end of the smoothing interval (x lambda_max); lower end per patch
+    const double* cheb;    // EPI_CHEB: (s1, s2) per (patch-level, mode, step)
     double* partial;       // EPI_DOTS: 2 per tile
     const double* r64;     // EPI_DOTS
+    const double* dotq;    // EPI_CHEB: if set, dpart[tile] = sum of y . dotq over the tile
+    double* dpart;
 };
 
 // One thread per output coefficient; reads K(i, i+o) at i and K(i-o, i) at
 // i-o (symmetry) for the lower half of the stencil.  FINE marks launches on
 // the finest level (the bandwidth-bound sweeps) so that profilers report
 // them apart from the latency-bound coarse-level launches.
-template <typename TC, typename TX, typename TY, int EPI, bool FINE>
+template <int P0, int P1, int P2, typename TC, typename TX, typename TY, int EPI, bool FINE>
 __global__ __launch_bounds__(TILE) void k_stencil(StencilArgs a) {
     __shared__ double lds[2 * TILE / WAVE];
     const int t = tile_index(a.ntiles);
     if (t < 0) return;
     const Tile tl = a.tiles[t];
-    const PatchLev P = a.L[tl.pl];
+    const PatchLev& P = a.L[tl.pl];
     if (a.active && !a.active[P.patch]) return;
-    const int64_t i = (int64_t)tl.start + threadIdx.x;
+    const int n = (int)P.n;
+    const int i = tl.start + (int)threadIdx.x;
     const TC* __restrict__ coef = (const TC*)a.coef;
     const TX* __restrict__ x = (const TX*)a.x;
     TY* __restrict__ y = (TY*)a.y;
-    double dv[2] = {0.0, 0.0};
-    if (i < P.n) {
-        int i0, i1, i2;
-        unlin(P, i, i0, i1, i2);
-        const bool m = masked(P, a.mode, i0, i1, i2);
+    double dv0 = 0.0, dv1 = 0.0;
+    if (i < n) {
+        const int M0 = P.M[0], M1 = P.M[1], M01 = M0 * M1;
+        const int i2 = i / M01, r = i - i2 * M01, i1 = r / M0, i0 = r - i1 * M0;
+        const bool m = masked_bits(P.mbits[a.mode], P.dim, M0, M1, P.M[2], i0, i1, i2);
         const int64_t vi = P.voff + i;
         TC acc = TC(0), diag = TC(1);
         if (!m) {
             const TC* c = coef + P.coff + i;
             const TX* xp = x + vi;
-            const int64_t cs = P.cstride;
-            const int64_t M0 = P.M[0], M01 = (int64_t)P.M[0] * P.M[1];
-            const int p0 = P.p[0], p1 = P.p[1], p2 = P.p[2];
-            int s = 0;
-            for (int o2 = 0; o2 <= p2; ++o2)
-                for (int o1 = (o2 == 0 ? 0 : -p1); o1 <= p1; ++o1) {
-                    const int o0s = (o2 == 0 && o1 == 0) ? 0 : -p0;
-                    const int64_t base = o1 * M0 + o2 * M01;
-                    for (int o0 = o0s; o0 <= p0; ++o0, ++s) {
-                        const int64_t off = base + o0;
-                        const TC cu = c[s * cs];
-                        acc += cu * TC(xp[off]);
-                        if (s) acc += c[s * cs - off] * TC(xp[-off]);
-                        else diag = cu;
-                    }
-                }
+            acc = stencil_sum<P0, P1, P2>(c, xp, (int)P.cstride, M0, M01, P.p[0], P.p[1], P.p[2], diag);
         }
         if constexpr (EPI == EPI_APPLY) {
             y[vi] = m ? TY(0) : TY(a.alpha * (double)acc);
@@ -178,26 +279,36 @@ __global__ __launch_bounds__(TILE) void k_stencil(StencilArgs a) {
                 y[vi] = TY(0);
                 d[vi] = TY(0);
             } else {
-                double s1, s2;
-                cheb_coeffs(P.lmax[a.mode], P.clo, a.cheb_hi, a.cheb_k, s1, s2);
-                const TC r = TC(b[vi]) - acc;
-                const TC dn = (s1 != 0.0 ? TC(s1) * TC(d[vi]) : TC(0)) + TC(s2) * r / diag;
+                const double* cc = a.cheb + 2 * (((int64_t)tl.pl * 2 + a.mode) * KMAX + a.cheb_k);
+                const TC s1 = TC(cc[0]), s2 = TC(cc[1]);
+                const TC rr = TC(b[vi]) - acc;
+                const TC dn = (a.cheb_k > 0 ? s1 * TC(d[vi]) : TC(0)) + s2 * rr / diag;
                 d[vi] = TY(dn);
-                y[vi] = TY(TC(x[vi]) + dn);
+                const TY yn = TY(TC(x[vi]) + dn);
+                y[vi] = yn;
+                if (a.dotq) dv0 = (double)yn * a.dotq[vi];
             }
         } else if constexpr (EPI == EPI_DOTS) {
             const double q = m ? 0.0 : (double)acc;
             y[vi] = TY(q);
             const double xv = (double)x[vi];
-            dv[0] = xv * q;
-            dv[1] = xv * a.r64[vi];
+            dv0 = xv * q;
+            dv1 = xv * a.r64[vi];
         }
     }
     if constexpr (EPI == EPI_DOTS) {
+        double dv[2] = {dv0, dv1};
         block_sum<2>(dv, lds);
         if (threadIdx.x == 0) {
-            a.partial[2 * t] = dv[0];
-            a.partial[2 * t + 1] = dv[1];
+            a.partial[2 * tl.gid] = dv[0];
+            a.partial[2 * tl.gid + 1] = dv[1];
+        }
+    }
+    if constexpr (EPI == EPI_CHEB) {
+        if (a.dotq) {
+            double dv[1] = {dv0};
+            block_sum<1>(dv, lds);
+            if (threadIdx.x == 0) a.dpart[tl.gid] = dv[0];
         }
     }
 }
@@ -207,15 +318,15 @@ __global__ __launch_bounds__(TILE) void k_stencil(StencilArgs a) {
 // First Chebyshev step from a zero guess: x = d = m b / (theta diag)
 template <typename T>
 __global__ __launch_bounds__(TILE) void k_cheb_zero(const PatchLev* L, const Tile* tiles, int ntiles, const T* coef,
-                                                    const T* b, T* x, T* d, int mode, double hi,
+                                                    const T* b, T* x, T* d, int mode, const double* cheb,
                                                     const int* active) {
     const int t = tile_index(ntiles);
     if (t < 0) return;
     const Tile tl = tiles[t];
-    const PatchLev P = L[tl.pl];
+    const PatchLev& P = L[tl.pl];
     if (active && !active[P.patch]) return;
-    const int64_t i = (int64_t)tl.start + threadIdx.x;
-    if (i >= P.n) return;
+    const int i = tl.start + (int)threadIdx.x;
+    if (i >= (int)P.n) return;
     int i0, i1, i2;
     unlin(P, i, i0, i1, i2);
     const int64_t vi = P.voff + i;
@@ -224,110 +335,92 @@ __global__ __launch_bounds__(TILE) void k_cheb_zero(const PatchLev* L, const Til
         d[vi] = T(0);
         return;
     }
-    const double lm = P.lmax[mode];
-    const double theta = 0.5 * (P.clo + hi) * lm;
-    const double v = (double)b[vi] / (theta * (double)coef[P.coff + i]);
+    const double s2 = cheb[2 * (((int64_t)tl.pl * 2 + mode) * KMAX) + 1];
+    const double v = s2 * (double)b[vi] / (double)coef[P.coff + i];
     x[vi] = T(v);
     d[vi] = T(v);
 }
 
 // Restriction b_c = m_c P^T r_f, one thread per coarse coefficient.
-template <typename T>
+template <int P0, int P1, int P2, typename T>
 __global__ __launch_bounds__(TILE) void k_restrict(const PatchLev* Lf, const PatchLev* Lc, const Tile* tiles,
                                                    int ntiles, const int32_t* rlo, const T* rval, const T* rf, T* bc,
                                                    int mode, const int* active) {
     const int t = tile_index(ntiles);
     if (t < 0) return;
     const Tile tl = tiles[t];
-    const PatchLev C = Lc[tl.pl];
+    const PatchLev& C = Lc[tl.pl];
     if (active && !active[C.patch]) return;
-    const int64_t I = (int64_t)tl.start + threadIdx.x;
-    if (I >= C.n) return;
-    const PatchLev F = Lf[C.fine];
+    const int I = tl.start + (int)threadIdx.x;
+    if (I >= (int)C.n) return;
+    const PatchLev& F = Lf[C.fine];
     int I0, I1, I2;
     unlin(C, I, I0, I1, I2);
     if (masked(C, mode, I0, I1, I2)) {
         bc[C.voff + I] = T(0);
         return;
     }
-    const int Ic[3] = {I0, I1, I2};
-    int lo[3] = {0, 0, 0}, w[3] = {1, 1, 1};
-    const T* v[3] = {nullptr, nullptr, nullptr};
-    for (int d = 0; d < F.dim; ++d) {
-        lo[d] = rlo[F.roff[d] + Ic[d]];
-        v[d] = rval + (F.roff[d] + Ic[d]) * PW;
-        w[d] = F.p[d] + 2;
-    }
-    const int64_t M0 = F.M[0], M01 = (int64_t)F.M[0] * F.M[1];
-    double acc = 0.0;
-    for (int a2 = 0; a2 < w[2]; ++a2) {
-        const double v2 = F.dim == 3 ? (double)v[2][a2] : 1.0;
-        if (v2 == 0.0) continue;
-        for (int a1 = 0; a1 < w[1]; ++a1) {
-            const double v12 = v2 * (double)v[1][a1];
-            if (v12 == 0.0) continue;
-            const int64_t row = F.voff + (lo[1] + a1) * M0 + (F.dim == 3 ? (lo[2] + a2) * M01 : 0) + lo[0];
-            for (int a0 = 0; a0 < w[0]; ++a0) acc += v12 * (double)v[0][a0] * (double)rf[row + a0];
-        }
-    }
+    const bool three = F.dim == 3;
+    const int lo0 = rlo[F.roff[0] + I0], lo1 = rlo[F.roff[1] + I1], lo2 = three ? rlo[F.roff[2] + I2] : 0;
+    const T* v0 = rval + (F.roff[0] + I0) * PW;
+    const T* v1 = rval + (F.roff[1] + I1) * PW;
+    const T* v2 = three ? rval + (F.roff[2] + I2) * PW : v1;
+    const int M0 = F.M[0], M01 = F.M[0] * F.M[1];
+    const T* src = rf + F.voff + lo0 + (int64_t)lo1 * M0 + (int64_t)lo2 * M01;
+    constexpr int W0 = P0 >= 0 ? P0 + 2 : -1, W1 = P0 >= 0 ? P1 + 2 : -1, W2 = P0 >= 0 ? (P2 > 0 ? P2 + 2 : 1) : -1;
+    const double acc = band_sum<W0, W1, W2>(v0, v1, v2, src, M0, M01, F.p[0] + 2, F.p[1] + 2,
+                                            three ? F.p[2] + 2 : 1, F.dim);
     bc[C.voff + I] = T(acc);
 }
 
 // Prolongation x_f += m_f P e_c, one thread per fine coefficient.
-template <typename T>
+template <int P0, int P1, int P2, typename T>
 __global__ __launch_bounds__(TILE) void k_prolong(const PatchLev* Lf, const PatchLev* Lc, const Tile* tiles,
                                                   int ntiles, const int32_t* plo, const T* pval, const T* ec, T* xf,
                                                   int mode, const int* active) {
     const int t = tile_index(ntiles);
     if (t < 0) return;
     const Tile tl = tiles[t];
-    const PatchLev F = Lf[tl.pl];
+    const PatchLev& F = Lf[tl.pl];
     if (active && !active[F.patch]) return;
-    const int64_t i = (int64_t)tl.start + threadIdx.x;
-    if (i >= F.n) return;
+    const int i = tl.start + (int)threadIdx.x;
+    if (i >= (int)F.n) return;
     int i0, i1, i2;
     unlin(F, i, i0, i1, i2);
     if (masked(F, mode, i0, i1, i2)) return;
-    const PatchLev C = Lc[F.coarse];
-    const int ii[3] = {i0, i1, i2};
-    int lo[3] = {0, 0, 0}, w[3] = {1, 1, 1};
-    const T* v[3] = {nullptr, nullptr, nullptr};
-    for (int d = 0; d < F.dim; ++d) {
-        lo[d] = plo[F.toff[d] + ii[d]];
-        v[d] = pval + (F.toff[d] + ii[d]) * PW;
-        w[d] = F.p[d] + 2;
-    }
-    const int64_t M0 = C.M[0], M01 = (int64_t)C.M[0] * C.M[1];
-    double acc = 0.0;
-    for (int a2 = 0; a2 < w[2]; ++a2) {
-        const double v2 = F.dim == 3 ? (double)v[2][a2] : 1.0;
-        if (v2 == 0.0) continue;
-        for (int a1 = 0; a1 < w[1]; ++a1) {
-            const double v12 = v2 * (double)v[1][a1];
-            if (v12 == 0.0) continue;
-            const int64_t row = C.voff + (lo[1] + a1) * M0 + (F.dim == 3 ? (lo[2] + a2) * M01 : 0) + lo[0];
-            for (int a0 = 0; a0 < w[0]; ++a0) acc += v12 * (double)v[0][a0] * (double)ec[row + a0];
-        }
-    }
+    const PatchLev& C = Lc[F.coarse];
+    const bool three = F.dim == 3;
+    const int lo0 = plo[F.toff[0] + i0], lo1 = plo[F.toff[1] + i1], lo2 = three ? plo[F.toff[2] + i2] : 0;
+    const T* v0 = pval + (F.toff[0] + i0) * PW;
+    const T* v1 = pval + (F.toff[1] + i1) * PW;
+    const T* v2 = three ? pval + (F.toff[2] + i2) * PW : v1;
+    const int M0 = C.M[0], M01 = C.M[0] * C.M[1];
+    const T* src = ec + C.voff + lo0 + (int64_t)lo1 * M0 + (int64_t)lo2 * M01;
+    constexpr int W0 = P0 >= 0 ? P0 + 2 : -1, W1 = P0 >= 0 ? P1 + 2 : -1, W2 = P0 >= 0 ? (P2 > 0 ? P2 + 2 : 1) : -1;
+    const double acc = band_sum<W0, W1, W2>(v0, v1, v2, src, M0, M01, F.p[0] + 2, F.p[1] + 2,
+                                            three ? F.p[2] + 2 : 1, F.dim);
     const int64_t vi = F.voff + i;
     xf[vi] = T((double)xf[vi] + acc);
 }
 
-// Coarsest level: x = A^{-1} b with the stored dense inverse; one work-group per patch.
+// Coarsest level: x = A^{-1} b with the stored dense inverse; one work-group per
+// patch, one wave per row, lanes over the columns.
 template <typename T>
 __global__ __launch_bounds__(TILE) void k_coarse(const PatchLev* L, const int32_t* list, int nlist, const T* inv,
                                                  const T* b, T* x, int mode, const int* active) {
     if ((int)blockIdx.x >= nlist) return;
-    const PatchLev P = L[list[blockIdx.x]];
+    const PatchLev& P = L[list[blockIdx.x]];
     if (active && !active[P.patch]) return;
-    const int64_t n = P.n;
+    const int n = (int)P.n;
     const T* A = inv + P.invoff + (int64_t)mode * n * n;
     const T* bb = b + P.voff;
-    for (int64_t r = threadIdx.x; r < n; r += blockDim.x) {
+    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
+    for (int r = w; r < n; r += nw) {
+        const T* row = A + (int64_t)r * n;
         double acc = 0.0;
-        const T* row = A + r * n;
-        for (int64_t j = 0; j < n; ++j) acc += (double)row[j] * (double)bb[j];
-        x[P.voff + r] = T(acc);
+        for (int j = lane; j < n; j += WAVE) acc += (double)row[j] * (double)bb[j];
+        for (int o = WAVE / 2; o > 0; o >>= 1) acc += __shfl_down(acc, o, WAVE);
+        if (lane == 0) x[P.voff + r] = T(acc);
     }
 }
 
@@ -345,7 +438,7 @@ __global__ __launch_bounds__(TILE) void k_add(const PatchLev* L, const Tile* til
     const int t = tile_index(ntiles);
     if (t < 0) return;
     const Tile tl = tiles[t];
-    const PatchLev P = L[tl.pl];
+    const PatchLev& P = L[tl.pl];
     const int64_t i = (int64_t)tl.start + threadIdx.x;
     if (i >= P.n) return;
     y[P.voff + i] = T((double)y[P.voff + i] + (double)x[P.voff + i]);
@@ -358,7 +451,7 @@ __global__ __launch_bounds__(TILE) void k_convert(const PatchLev* L, const Tile*
     const int t = tile_index(ntiles);
     if (t < 0) return;
     const Tile tl = tiles[t];
-    const PatchLev P = L[tl.pl];
+    const PatchLev& P = L[tl.pl];
     const int64_t i = (int64_t)tl.start + threadIdx.x;
     if (i >= P.n) return;
     int i0, i1, i2;
@@ -374,7 +467,7 @@ __global__ __launch_bounds__(TILE) void k_add_conv(const PatchLev* L, const Tile
     const int t = tile_index(ntiles);
     if (t < 0) return;
     const Tile tl = tiles[t];
-    const PatchLev P = L[tl.pl];
+    const PatchLev& P = L[tl.pl];
     const int64_t i = (int64_t)tl.start + threadIdx.x;
     if (i >= P.n) return;
     y[P.voff + i] += (double)x[P.voff + i];
@@ -386,7 +479,7 @@ __global__ __launch_bounds__(TILE) void k_sub(const PatchLev* L, const Tile* til
     const int t = tile_index(ntiles);
     if (t < 0) return;
     const Tile tl = tiles[t];
-    const PatchLev P = L[tl.pl];
+    const PatchLev& P = L[tl.pl];
     const int64_t i = (int64_t)tl.start + threadIdx.x;
     if (i >= P.n) return;
     z[P.voff + i] = a[P.voff + i] - b[P.voff + i];
@@ -430,7 +523,7 @@ __global__ __launch_bounds__(TILE) void k_fcg_init(const PatchLev* L, const Tile
     const int t = tile_index(ntiles);
     if (t < 0) return;
     const Tile tl = tiles[t];
-    const PatchLev P = L[tl.pl];
+    const PatchLev& P = L[tl.pl];
     const int64_t i = (int64_t)tl.start + threadIdx.x;
     double v[1] = {0.0};
     if (i < P.n) {
@@ -446,7 +539,7 @@ __global__ __launch_bounds__(TILE) void k_fcg_init(const PatchLev* L, const Tile
         v[0] = rv * rv;
     }
     block_sum<1>(v, lds);
-    if (threadIdx.x == 0) partial[t] = v[0];
+    if (threadIdx.x == 0) partial[tl.gid] = v[0];
 }
 
 // per-tile partial of z . q
@@ -457,49 +550,72 @@ __global__ __launch_bounds__(TILE) void k_fcg_zq(const PatchLev* L, const Tile* 
     const int t = tile_index(ntiles);
     if (t < 0) return;
     const Tile tl = tiles[t];
-    const PatchLev P = L[tl.pl];
+    const PatchLev& P = L[tl.pl];
     if (!active[P.patch]) return;
     const int64_t i = (int64_t)tl.start + threadIdx.x;
     double v[1] = {0.0};
     if (i < P.n) v[0] = (double)z[P.voff + i] * q[P.voff + i];
     block_sum<1>(v, lds);
-    if (threadIdx.x == 0) partial[t] = v[0];
+    if (threadIdx.x == 0) partial[tl.gid] = v[0];
 }
 
-// d = m (z - beta d)
+// d = m (z - beta d), beta = first ? 0 : sum over the patch's tiles of (z . q_prev) / dq
 template <typename T>
 __global__ __launch_bounds__(TILE) void k_fcg_dir(const PatchLev* L, const Tile* tiles, int ntiles, const T* z,
-                                                  double* d, const double* beta, int mode, const int* active) {
+                                                  double* d, const double* pzq, const int32_t* tile_beg,
+                                                  const int32_t* tile_end, const double* dq, int first, int mode,
+                                                  const int* active) {
     const int t = tile_index(ntiles);
     if (t < 0) return;
     const Tile tl = tiles[t];
-    const PatchLev P = L[tl.pl];
-    if (!active[P.patch]) return;
-    const int64_t i = (int64_t)tl.start + threadIdx.x;
-    if (i >= P.n) return;
+    const PatchLev& P = L[tl.pl];
+    const int k = P.patch;
+    if (!active[k]) return;
+    double bt = 0.0;
+    if (!first) {
+        double s = 0.0;
+        for (int u = tile_beg[k]; u < tile_end[k]; ++u) s += pzq[u];
+        bt = s / dq[k];
+    }
+    const int i = tl.start + (int)threadIdx.x;
+    if (i >= (int)P.n) return;
     int i0, i1, i2;
     unlin(P, i, i0, i1, i2);
     const int64_t vi = P.voff + i;
-    const double bt = beta[P.patch];
     d[vi] = masked(P, mode, i0, i1, i2) ? 0.0 : (double)z[vi] - bt * d[vi];
 }
 
-// x += alpha d, r -= alpha q, rT = r, partial = |r|^2
+// alpha = sum(d.r) / sum(d.q) over the patch's tiles; x += alpha d, r -= alpha q,
+// rT = r, prr = |r|^2 per tile.  The patch's first tile stores dq (for the next
+// beta) and flags a breakdown (dq <= 0: alpha = 0).
 template <typename T>
 __global__ __launch_bounds__(TILE) void k_fcg_update(const PatchLev* L, const Tile* tiles, int ntiles,
                                                      const double* d, const double* q, double* x, double* r, T* rT,
-                                                     const double* alpha, double* partial, const int* active) {
+                                                     const double* pdots, const int32_t* tile_beg,
+                                                     const int32_t* tile_end, double* dq, int* brk, double* prr,
+                                                     const int* active) {
     __shared__ double lds[TILE / WAVE];
     const int t = tile_index(ntiles);
     if (t < 0) return;
     const Tile tl = tiles[t];
-    const PatchLev P = L[tl.pl];
-    if (!active[P.patch]) return;
-    const int64_t i = (int64_t)tl.start + threadIdx.x;
+    const PatchLev& P = L[tl.pl];
+    const int k = P.patch;
+    if (!active[k]) return;
+    double sdq = 0.0, sdr = 0.0;
+    for (int u = tile_beg[k]; u < tile_end[k]; ++u) {
+        sdq += pdots[2 * u];
+        sdr += pdots[2 * u + 1];
+    }
+    const bool ok = sdq > 0.0;
+    const double al = ok ? sdr / sdq : 0.0;
+    if (threadIdx.x == 0 && tl.gid == tile_beg[k]) {
+        dq[k] = sdq;
+        if (!ok) brk[k] = 1;
+    }
+    const int i = tl.start + (int)threadIdx.x;
     double v[1] = {0.0};
-    if (i < P.n) {
+    if (i < (int)P.n) {
         const int64_t vi = P.voff + i;
-        const double al = alpha[P.patch];
         x[vi] += al * d[vi];
         const double rv = r[vi] - al * q[vi];
         r[vi] = rv;
@@ -507,45 +623,45 @@ __global__ __launch_bounds__(TILE) void k_fcg_update(const PatchLev* L, const Ti
         v[0] = rv * rv;
     }
     block_sum<1>(v, lds);
-    if (threadIdx.x == 0) partial[t] = v[0];
+    if (threadIdx.x == 0) prr[tl.gid] = v[0];
 }
 
-// Per-patch scalars from tile partials (one thread per patch, fixed summation order).
-//  stage 0 (init):   bb = sum |r|^2; active = bb > 0; its = 0
-//  stage 1 (beta):   beta = first ? 0 : sum(z.q) / dq
-//  stage 2 (alpha):  dq = sum(d.q); alpha = sum(d.r) / dq   (dq <= 0 stops the patch)
-//  stage 3 (check):  rr = sum |r|^2; its += 1; active = rr > tol^2 bb && its < maxit
-__global__ void k_fcg_scalars(int npatch, const int32_t* tile_ptr, const double* partial, int stride, int stage,
-                              double* bb, double* dq, double* beta, double* alpha, int* active, int* its,
-                              double tol2, int maxit, int first, int* nactive) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= npatch) return;
-    if (stage != 0 && !active[k]) return;
-    double s0 = 0.0, s1 = 0.0;
-    for (int t = tile_ptr[k]; t < tile_ptr[k + 1]; ++t) {
-        s0 += partial[(int64_t)stride * t];
-        if (stride > 1) s1 += partial[(int64_t)stride * t + 1];
-    }
-    if (stage == 0) {
-        bb[k] = s0;
-        active[k] = s0 > 0.0 ? 1 : 0;
-        its[k] = 0;
-        if (active[k]) atomicAdd(nactive, 1);
-    } else if (stage == 1) {
-        beta[k] = first ? 0.0 : s0 / dq[k];
-    } else if (stage == 2) {
-        dq[k] = s0;
-        if (!(s0 > 0.0)) {
-            alpha[k] = 0.0;
-            active[k] = 0;
+// Per-patch convergence, one work-group: init: bb = |r|^2, its = 0, active = bb > 0;
+// check: its += 1, active = |r|^2 > tol^2 bb && its < maxit && no breakdown.
+// nactive[0] = number of active patches afterwards.
+__global__ __launch_bounds__(256) void k_fcg_check(int npatch, const int32_t* tile_beg, const int32_t* tile_end,
+                                                   const double* prr, int init, double* bb, int* active, int* its,
+                                                   int* brk, double tol2, int maxit, int* nactive) {
+    // nactive[1]: sum over patches of iterations of finished solves, nactive[2]: max, nactive[3]: patch solves
+    __shared__ int cnt[256 / WAVE];
+    int c = 0;
+    for (int k = threadIdx.x; k < npatch; k += blockDim.x) {
+        if (!init && !active[k]) continue;
+        double s = 0.0;
+        for (int u = tile_beg[k]; u < tile_end[k]; ++u) s += prr[u];
+        if (init) {
+            bb[k] = s;
+            its[k] = 0;
+            brk[k] = 0;
+            active[k] = s > 0.0 ? 1 : 0;
         } else {
-            alpha[k] = s1 / s0;
+            its[k] += 1;
+            active[k] = (s > tol2 * bb[k] && its[k] < maxit && !brk[k]) ? 1 : 0;
+            if (!active[k]) {
+                atomicAdd(&nactive[1], its[k]);
+                atomicMax(&nactive[2], its[k]);
+                atomicAdd(&nactive[3], 1);
+            }
         }
-    } else {
-        its[k] += 1;
-        const bool go = s0 > tol2 * bb[k] && its[k] < maxit;
-        active[k] = go ? 1 : 0;
-        if (go) atomicAdd(nactive, 1);
+        c += active[k];
+    }
+    for (int o = WAVE / 2; o > 0; o >>= 1) c += __shfl_down(c, o, WAVE);
+    if ((threadIdx.x & (WAVE - 1)) == 0) cnt[threadIdx.x / WAVE] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int tot = 0;
+        for (int w = 0; w < (int)(blockDim.x / WAVE); ++w) tot += cnt[w];
+        nactive[0] = tot;
     }
 }
 
@@ -589,7 +705,7 @@ __global__ __launch_bounds__(TILE) void k_pri_dots(int npatch, const int32_t* np
     for (int j = 0; j < nj; ++j) {
         double v[1] = {0.0};
         if (L0) {
-            const PatchLev P = L0[k];
+            const PatchLev& P = L0[k];
             for (int64_t r = threadIdx.x; r < P.n; r += blockDim.x)
                 v[0] += psi[(int64_t)j * psi_stride + P.voff + r] * g[P.voff + r];
         } else {
@@ -651,7 +767,7 @@ __global__ __launch_bounds__(TILE) void k_pri_apply_full(const PatchLev* L, cons
     const int t = tile_index(ntiles);
     if (t < 0) return;
     const Tile tl = tiles[t];
-    const PatchLev P = L[tl.pl];
+    const PatchLev& P = L[tl.pl];
     const int64_t i = (int64_t)tl.start + threadIdx.x;
     if (i >= P.n) return;
     const int64_t vi = P.voff + i;
@@ -670,7 +786,7 @@ __global__ __launch_bounds__(TILE) void k_loadvec(const PatchLev* L, const Patch
     const int t = tile_index(ntiles);
     if (t < 0) return;
     const Tile tl = tiles[t];
-    const PatchLev P = L[tl.pl];
+    const PatchLev& P = L[tl.pl];
     const PatchQ Q = PQ[P.patch];
     const int64_t i = (int64_t)tl.start + threadIdx.x;
     if (i >= P.n) return;
@@ -732,7 +848,7 @@ __global__ __launch_bounds__(TILE) void k_sq(const PatchLev* L, const Tile* tile
     const int t = tile_index(ntiles);
     if (t < 0) return;
     const Tile tl = tiles[t];
-    const PatchLev P = L[tl.pl];
+    const PatchLev& P = L[tl.pl];
     const int64_t i = (int64_t)tl.start + threadIdx.x;
     double acc[1] = {0.0};
     if (i < P.n) {
@@ -741,7 +857,7 @@ __global__ __launch_bounds__(TILE) void k_sq(const PatchLev* L, const Tile* tile
         if (!masked(P, mode, i0, i1, i2)) acc[0] = v[P.voff + i] * v[P.voff + i];
     }
     block_sum<1>(acc, lds);
-    if (threadIdx.x == 0) partial[t] = acc[0];
+    if (threadIdx.x == 0) partial[tl.gid] = acc[0];
 }
 
 // out (torn layout) = v (guarded level-0 layout)
@@ -750,7 +866,7 @@ __global__ __launch_bounds__(TILE) void k_copy_out(const PatchLev* L, const Tile
     const int t = tile_index(ntiles);
     if (t < 0) return;
     const Tile tl = tiles[t];
-    const PatchLev P = L[tl.pl];
+    const PatchLev& P = L[tl.pl];
     const int64_t i = (int64_t)tl.start + threadIdx.x;
     if (i >= P.n) return;
     out[torn_off[P.patch] + i] = v[P.voff + i];
@@ -863,7 +979,7 @@ __global__ __launch_bounds__(TILE) void k_combine(const PatchLev* L, const Tile*
     const int t = tile_index(ntiles);
     if (t < 0) return;
     const Tile tl = tiles[t];
-    const PatchLev P = L[tl.pl];
+    const PatchLev& P = L[tl.pl];
     const int64_t i = (int64_t)tl.start + threadIdx.x;
     if (i >= P.n) return;
     const int64_t vi = P.voff + i;
@@ -883,7 +999,7 @@ __global__ __launch_bounds__(TILE) void k_patch_gram(int npatch, const PatchLev*
     __shared__ double lds[TILE / WAVE];
     const int k = blockIdx.x;
     if (k >= npatch) return;
-    const PatchLev P = L[k];
+    const PatchLev& P = L[k];
     const int nj = npk[k];
     if (j >= nj) return;
     for (int i = 0; i < nj; ++i) {
@@ -892,6 +1008,250 @@ __global__ __launch_bounds__(TILE) void k_patch_gram(int npatch, const PatchLev*
             v[0] += psi[(int64_t)i * stride + P.voff + r] * t[(int64_t)j * stride + P.voff + r];
         block_sum<1>(v, lds);
         if (threadIdx.x == 0) S[((int64_t)k * NPMAX + i) * NPMAX + j] = v[0];
+    }
+}
+
+
+// ------------------------------------------------------------------ coarse part of a V-cycle in one kernel
+//
+// One work-group per patch runs levels 1 .. L-1 of the V-cycle with all level
+// vectors in LDS (rhs b, iterate x, its partner y, Chebyshev direction d per
+// level; x and y carry zero guards for the stencil reads) and the operator
+// data read from global memory: Chebyshev pre-smoothing, residual,
+// restriction, dense solve on the coarsest level, prolongation, Chebyshev
+// post-smoothing.  It replaces about ten launches per coarse level, each of
+// them too small to fill the chip.
+
+constexpr int LMAX = 12;     // multigrid levels per patch
+constexpr int VC_THREADS = 512;
+
+struct CoarseArgs {
+    const PatchLev* L[LMAX];
+    const void* coef[LMAX];
+    const int32_t* plo[LMAX];
+    const void* pval[LMAX];
+    const int32_t* rlo[LMAX];
+    const void* rval[LMAX];
+    const void* inv[LMAX];
+    const double* cheb[LMAX];
+    const int32_t* chain;     // chain[k * LMAX + l]: index of patch k in level l (-1: no such level)
+    const int32_t* plist;     // patches of this launch, one work-group each
+    int nlist;
+    const void* b1;           // level-1 right-hand side (global, level-1 layout)
+    void* x1;                 // level-1 correction (global, level-1 layout)
+    int mode;
+    int m;                    // Chebyshev degree per smoothing phase
+    const int* active;
+};
+
+template <int P0, int P1, int P2, typename T>
+__device__ __forceinline__ void vc_sweep(const PatchLev& P, const T* __restrict__ coef, const T* xs, T* ys,
+                                         const T* bs, T* ds, int mode, const double* cc, int k, bool resid) {
+    const int n = (int)P.n, M0 = P.M[0], M1 = P.M[1], M01 = M0 * M1, cs = (int)P.cstride;
+    const double s1 = cc[2 * k], s2 = cc[2 * k + 1];
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const int i2 = i / M01, r = i - i2 * M01, i1 = r / M0, i0 = r - i1 * M0;
+        if (masked_bits(P.mbits[mode], P.dim, M0, M1, P.M[2], i0, i1, i2)) {
+            ys[i] = T(0);
+            if (!resid) ds[i] = T(0);
+            continue;
+        }
+        T diag = T(1);
+        // 2D: every load of a coefficient in flight at once; 3D: one stencil row at a time (registers)
+        T acc;
+        if constexpr (P2 == 0)
+            acc = stencil_sum<P0, P1, P2>(coef + P.coff + i, xs + i, cs, M0, M01, P.p[0], P.p[1], P.p[2], diag);
+        else
+            acc = stencil_sum_rows<P0>(coef + P.coff + i, xs + i, cs, M0, M01, P.p[0], P.p[1], P.p[2], diag);
+        const T rr = bs[i] - acc;
+        if (resid) {
+            ys[i] = rr;
+        } else {
+            const T dn = (k > 0 ? T(s1) * ds[i] : T(0)) + T(s2) * rr / diag;
+            ds[i] = dn;
+            ys[i] = xs[i] + dn;
+        }
+    }
+}
+
+// y = A b for a dense n x n block (row-major, global) with x, b in LDS: one
+// wave per row at a time, lanes over the columns, shuffle reduction.
+template <typename T>
+__device__ __forceinline__ void wave_gemv(const T* __restrict__ A, int n, const T* b, T* y) {
+    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
+    for (int r = w; r < n; r += nw) {
+        const T* row = A + (int64_t)r * n;
+        T acc = T(0);
+        for (int j = lane; j < n; j += WAVE) acc += row[j] * b[j];
+        for (int o = WAVE / 2; o > 0; o >>= 1) acc += __shfl_down(acc, o, WAVE);
+        if (lane == 0) y[r] = acc;
+    }
+}
+
+template <int P0, int P1, int P2, typename T>
+__global__ __launch_bounds__(VC_THREADS) void k_vcoarse(CoarseArgs a) {
+    extern __shared__ unsigned char vc_lds_raw[];
+    __shared__ int sh_pl[LMAX];        // patch-level index per level
+    __shared__ int sh_off[LMAX][4];    // LDS offsets of x, y (guarded, pointing at entry 0), b, d
+    __shared__ int sh_cur[LMAX];       // which of x (0) / y (1) holds the level's current iterate
+    __shared__ int sh_nl, sh_total;
+    T* lds = (T*)vc_lds_raw;
+    if ((int)blockIdx.x >= a.nlist) return;
+    const int k = a.plist[blockIdx.x];
+    if (a.active && !a.active[k]) return;
+    if (threadIdx.x == 0) {
+        int nl = 1;
+        while (nl < LMAX && a.chain[k * LMAX + nl] >= 0) ++nl;
+        int off = 0;
+        for (int l = 0; l < nl; ++l) {
+            const int pl = a.chain[k * LMAX + l];
+            sh_pl[l] = pl;
+            if (l == 0) continue;
+            const PatchLev& P = a.L[l][pl];
+            const int n = (int)P.n;
+            const int g = P.p[0] + P.p[1] * P.M[0] + P.p[2] * P.M[0] * P.M[1];
+            sh_off[l][0] = off + g;
+            off += n + 2 * g;
+            sh_off[l][1] = off + g;
+            off += n + 2 * g;
+            sh_off[l][2] = off;
+            off += n;
+            sh_off[l][3] = off;
+            off += n;
+        }
+        sh_nl = nl;
+        sh_total = off;
+    }
+    __syncthreads();
+    const int nl = sh_nl;
+    for (int i = threadIdx.x; i < sh_total; i += blockDim.x) lds[i] = T(0);
+    __syncthreads();
+    {
+        const PatchLev& P = a.L[1][sh_pl[1]];
+        const T* b1 = (const T*)a.b1 + P.voff;
+        T* bl = lds + sh_off[1][2];
+        for (int i = threadIdx.x; i < (int)P.n; i += blockDim.x) bl[i] = b1[i];
+    }
+    __syncthreads();
+    const int mode = a.mode;
+    // ---- down
+    for (int l = 1; l < nl; ++l) {
+        const int pl = sh_pl[l];
+        const PatchLev& P = a.L[l][pl];
+        const T* coef = (const T*)a.coef[l];
+        T* xl = lds + sh_off[l][0];
+        T* yl = lds + sh_off[l][1];
+        T* bl = lds + sh_off[l][2];
+        T* dl = lds + sh_off[l][3];
+        if (l == nl - 1) {
+            const int n = (int)P.n;
+            wave_gemv<T>((const T*)a.inv[l] + P.invoff + (int64_t)mode * n * n, n, bl, xl);
+            if (threadIdx.x == 0) sh_cur[l] = 0;
+            __syncthreads();
+            break;
+        }
+        const double* cc = a.cheb[l] + 2 * (((int64_t)pl * 2 + mode) * KMAX);
+        {
+            const int n = (int)P.n, M0 = P.M[0], M1 = P.M[1], M01 = M0 * M1;
+            const T s20 = T(cc[1]);
+            for (int i = threadIdx.x; i < n; i += blockDim.x) {
+                const int i2 = i / M01, r = i - i2 * M01, i1 = r / M0, i0 = r - i1 * M0;
+                T v = T(0);
+                if (!masked_bits(P.mbits[mode], P.dim, M0, M1, P.M[2], i0, i1, i2))
+                    v = s20 * bl[i] / coef[P.coff + i];
+                xl[i] = v;
+                dl[i] = v;
+            }
+        }
+        __syncthreads();
+        T* X = xl;
+        T* Y = yl;
+        int c = 0;
+        for (int step = 1; step < a.m; ++step) {
+            vc_sweep<P0, P1, P2, T>(P, coef, X, Y, bl, dl, mode, cc, step, false);
+            __syncthreads();
+            T* tmp = X; X = Y; Y = tmp;
+            c ^= 1;
+        }
+        if (threadIdx.x == 0) sh_cur[l] = c;
+        vc_sweep<P0, P1, P2, T>(P, coef, X, Y, bl, dl, mode, cc, 0, true);
+        __syncthreads();
+        {
+            const PatchLev& C = a.L[l + 1][sh_pl[l + 1]];
+            T* bc = lds + sh_off[l + 1][2];
+            const int32_t* rlo = a.rlo[l];
+            const T* rval = (const T*)a.rval[l];
+            const bool three = P.dim == 3;
+            const int M0 = P.M[0], M01 = P.M[0] * P.M[1];
+            const int n = (int)C.n, C0 = C.M[0], C1 = C.M[1], C01 = C0 * C1;
+            for (int I = threadIdx.x; I < n; I += blockDim.x) {
+                const int I2 = I / C01, r = I - I2 * C01, I1 = r / C0, I0 = r - I1 * C0;
+                T v = T(0);
+                if (!masked_bits(C.mbits[mode], C.dim, C0, C1, C.M[2], I0, I1, I2)) {
+                    const int lo0 = rlo[P.roff[0] + I0], lo1 = rlo[P.roff[1] + I1];
+                    const int lo2 = three ? rlo[P.roff[2] + I2] : 0;
+                    const T* v0 = rval + (P.roff[0] + I0) * PW;
+                    const T* v1 = rval + (P.roff[1] + I1) * PW;
+                    const T* v2 = three ? rval + (P.roff[2] + I2) * PW : v1;
+                    constexpr int W0 = P0 >= 0 ? P0 + 2 : -1, W1 = P0 >= 0 ? P1 + 2 : -1;
+                    constexpr int W2 = P0 >= 0 ? (P2 > 0 ? P2 + 2 : 1) : -1;
+                    v = T(band_sum<W0, W1, W2>(v0, v1, v2, Y + lo0 + lo1 * M0 + lo2 * M01, M0, M01, P.p[0] + 2,
+                                               P.p[1] + 2, three ? P.p[2] + 2 : 1, P.dim));
+                }
+                bc[I] = v;
+            }
+        }
+        __syncthreads();
+    }
+    // ---- up
+    for (int lu = nl - 2; lu >= 1; --lu) {
+        const int pl = sh_pl[lu];
+        const PatchLev& P = a.L[lu][pl];
+        const T* coef = (const T*)a.coef[lu];
+        const double* cc = a.cheb[lu] + 2 * (((int64_t)pl * 2 + mode) * KMAX);
+        const int cu = sh_cur[lu];
+        T* X = lds + sh_off[lu][cu];
+        T* Y = lds + sh_off[lu][1 - cu];
+        T* bl = lds + sh_off[lu][2];
+        T* dl = lds + sh_off[lu][3];
+        const T* E = lds + sh_off[lu + 1][sh_cur[lu + 1]];
+        {
+            const PatchLev& C = a.L[lu + 1][sh_pl[lu + 1]];
+            const int32_t* plo = a.plo[lu];
+            const T* pval = (const T*)a.pval[lu];
+            const bool three = P.dim == 3;
+            const int n = (int)P.n, M0 = P.M[0], M1 = P.M[1], M01 = M0 * M1;
+            const int C0 = C.M[0], C01 = C.M[0] * C.M[1];
+            for (int i = threadIdx.x; i < n; i += blockDim.x) {
+                const int i2 = i / M01, r = i - i2 * M01, i1 = r / M0, i0 = r - i1 * M0;
+                if (masked_bits(P.mbits[mode], P.dim, M0, M1, P.M[2], i0, i1, i2)) continue;
+                const int lo0 = plo[P.toff[0] + i0], lo1 = plo[P.toff[1] + i1];
+                const int lo2 = three ? plo[P.toff[2] + i2] : 0;
+                const T* v0 = pval + (P.toff[0] + i0) * PW;
+                const T* v1 = pval + (P.toff[1] + i1) * PW;
+                const T* v2 = three ? pval + (P.toff[2] + i2) * PW : v1;
+                constexpr int W0 = P0 >= 0 ? P0 + 2 : -1, W1 = P0 >= 0 ? P1 + 2 : -1;
+                constexpr int W2 = P0 >= 0 ? (P2 > 0 ? P2 + 2 : 1) : -1;
+                X[i] += T(band_sum<W0, W1, W2>(v0, v1, v2, E + lo0 + lo1 * C0 + lo2 * C01, C0, C01, P.p[0] + 2,
+                                               P.p[1] + 2, three ? P.p[2] + 2 : 1, P.dim));
+            }
+        }
+        __syncthreads();
+        int c = cu;
+        for (int step = 0; step < a.m; ++step) {
+            vc_sweep<P0, P1, P2, T>(P, coef, X, Y, bl, dl, mode, cc, step, false);
+            __syncthreads();
+            T* tmp = X; X = Y; Y = tmp;
+            c ^= 1;
+        }
+        if (threadIdx.x == 0) sh_cur[lu] = c;
+        __syncthreads();
+    }
+    {
+        const PatchLev& P = a.L[1][sh_pl[1]];
+        const T* X = lds + sh_off[1][sh_cur[1]];
+        T* x1 = (T*)a.x1 + P.voff;
+        for (int i = threadIdx.x; i < (int)P.n; i += blockDim.x) x1[i] = X[i];
     }
 }
 

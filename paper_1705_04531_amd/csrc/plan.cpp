@@ -914,11 +914,33 @@ Plan* build_plan(const ieti_patch* in, int n, const double* pv, int n_pv, const 
     std::map<int64_t, int64_t> eindex;   // group of first interior edge coefficient -> global primal
     struct LocalEdge { int k; int e; std::vector<int64_t> loc; int64_t key; };
     std::vector<LocalEdge> ledges;
-    if (dim == 3 && (opt.primal & IETI_PRIMAL_EDGES)) {
+    if (opt.primal & IETI_PRIMAL_EDGES) {
         for (int k = 0; k < n; ++k) {
             const Patch& pa = pl.patches[k];
             const int* M = pa.lv[0].M;
             int eid = 0;
+            if (dim == 2) {
+                // the edges of a 2D decomposition are the patch sides (corners excluded)
+                for (int fr = 0; fr < 2; ++fr)
+                    for (int e = 0; e < 2; ++e, ++eid) {
+                        LocalEdge le;
+                        le.k = k;
+                        le.e = eid;
+                        for (int t = 1; t < M[fr] - 1; ++t) {
+                            int ii[3] = {0, 0, 0};
+                            ii[fr] = t;
+                            ii[1 - fr] = e ? M[1 - fr] - 1 : 0;
+                            le.loc.push_back(lin(M, ii[0], ii[1], 0));
+                        }
+                        if (le.loc.empty()) continue;
+                        int64_t g = group_of[pa.torn_off + le.loc[0]];
+                        if (g < 0 || groups[g].dir) continue;
+                        le.key = g;
+                        eindex[g] = 0;
+                        ledges.push_back(le);
+                    }
+                continue;
+            }
             for (int fr = 0; fr < 3; ++fr) {
                 int oa = fr == 0 ? 1 : 0, ob = fr == 2 ? 1 : 2;
                 for (int ea = 0; ea < 2; ++ea)

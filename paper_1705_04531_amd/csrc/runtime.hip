@@ -43,6 +43,65 @@ static inline int64_t align64(int64_t x) { return (x + 63) & ~int64_t(63); }
 static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 static inline unsigned tile_grid(int ntiles) { return (unsigned)(8 * ((ntiles + 7) / 8)); }
 
+// one kernel instance per degree class (see degree_class)
+#define IETI_CLASS_SWITCH(cls, L)                \
+    switch (cls) {                               \
+    case 0: L(2, 2, 0); break;                   \
+    case 1: L(3, 2, 0); break;                   \
+    case 2: L(4, 2, 0); break;                   \
+    case 3: L(2, 3, 0); break;                   \
+    case 4: L(3, 3, 0); break;                   \
+    case 5: L(4, 3, 0); break;                   \
+    case 6: L(2, 4, 0); break;                   \
+    case 7: L(3, 4, 0); break;                   \
+    case 8: L(4, 4, 0); break;                   \
+    case 9: L(2, 2, 2); break;                   \
+    case 10: L(3, 3, 3); break;                  \
+    default: L(-1, -1, -1); break;               \
+    }
+
+template <typename TC, typename TX, typename TY, int EPI, bool FINE>
+static void launch_stencil(int cls, hipStream_t st, const StencilArgs& a) {
+#define IETI_LS(A, B, C) \
+    hipLaunchKernelGGL((k_stencil<A, B, C, TC, TX, TY, EPI, FINE>), dim3(tile_grid(a.ntiles)), dim3(TILE), 0, st, a)
+    IETI_CLASS_SWITCH(cls, IETI_LS)
+#undef IETI_LS
+}
+
+template <typename T>
+static void launch_vcoarse(int cls, hipStream_t st, const CoarseArgs& a, size_t lds_bytes, bool set_attr) {
+#define IETI_LV(A, B, C)                                                                                  \
+    do {                                                                                                  \
+        if (set_attr)                                                                                     \
+            HIPCHECK(hipFuncSetAttribute((const void*)k_vcoarse<A, B, C, T>,                              \
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes));    \
+        else                                                                                              \
+            hipLaunchKernelGGL((k_vcoarse<A, B, C, T>), dim3(a.nlist), dim3(VC_THREADS), lds_bytes, st, a); \
+    } while (0)
+    IETI_CLASS_SWITCH(cls, IETI_LV)
+#undef IETI_LV
+}
+
+template <typename T>
+static void launch_restrict(int cls, hipStream_t st, const PatchLev* Lf, const PatchLev* Lc, const Tile* tiles,
+                            int nt, const int32_t* rlo, const T* rval, const T* rf, T* bc, int mode, const int* act) {
+#define IETI_LR(A, B, C)                                                                                      \
+    hipLaunchKernelGGL((k_restrict<A, B, C, T>), dim3(tile_grid(nt)), dim3(TILE), 0, st, Lf, Lc, tiles, nt, rlo, \
+                       rval, rf, bc, mode, act)
+    IETI_CLASS_SWITCH(cls, IETI_LR)
+#undef IETI_LR
+}
+
+template <typename T>
+static void launch_prolong(int cls, hipStream_t st, const PatchLev* Lf, const PatchLev* Lc, const Tile* tiles, int nt,
+                           const int32_t* plo, const T* pval, const T* ec, T* xf, int mode, const int* act) {
+#define IETI_LP(A, B, C)                                                                                     \
+    hipLaunchKernelGGL((k_prolong<A, B, C, T>), dim3(tile_grid(nt)), dim3(TILE), 0, st, Lf, Lc, tiles, nt, plo, \
+                       pval, ec, xf, mode, act)
+    IETI_CLASS_SWITCH(cls, IETI_LP)
+#undef IETI_LP
+}
+
 // ------------------------------------------------------------------ device memory arena
 
 struct Arena {
@@ -138,6 +197,10 @@ struct DevLevel {
     Tile* tiles_all = nullptr;
     Tile* tiles_smooth = nullptr;
     int nt_all = 0, nt_smooth = 0;
+    // tiles of each degree class are contiguous: [cls_beg[c], cls_end[c]) in tiles_all / tiles_smooth
+    int cls_beg_all[NCLASS + 1] = {0}, cls_end_all[NCLASS + 1] = {0};
+    int cls_beg_sm[NCLASS + 1] = {0}, cls_end_sm[NCLASS + 1] = {0};
+    double* cheb = nullptr;                       // (s1, s2) per (patch-level, mode, step)
     std::vector<int32_t> h_coarse;
     int32_t* coarse_list = nullptr;
     int n_coarse = 0;
@@ -163,9 +226,9 @@ struct Solver : SolverBase {
     double *fx = nullptr, *fr = nullptr, *fd = nullptr, *fq = nullptr;
     T *rT = nullptr, *zT = nullptr, *bT = nullptr, *xIT = nullptr, *x2T = nullptr, *r2T = nullptr;
     double* partial = nullptr;
-    int32_t* tile_ptr = nullptr;
+    int32_t *tile_beg = nullptr, *tile_end = nullptr;
     double *bb = nullptr, *dq = nullptr, *beta = nullptr, *alpha = nullptr;
-    int *active = nullptr, *its = nullptr, *nactive = nullptr;
+    int *active = nullptr, *its = nullptr, *nactive = nullptr, *brk = nullptr;
     int* h_nactive = nullptr;   // pinned
     // jump operators
     int64_t nslots = 0, nlam = 0;
@@ -195,10 +258,17 @@ struct Solver : SolverBase {
     double *lam = nullptr, *lr = nullptr, *lz = nullptr, *lp = nullptr, *lq = nullptr, *ltmp = nullptr;
     double* sc = nullptr;
     double* h_sc = nullptr;    // pinned
+    // fused coarse V-cycle: one work-group per patch for levels >= 1
+    bool fused = false;
+    int32_t* chain = nullptr;
+    std::vector<int32_t> h_plist[NCLASS + 1];
+    int32_t* plist[NCLASS + 1] = {nullptr};
+    size_t vc_lds[NCLASS + 1] = {0};
     // statistics of the current solve
     int64_t inner_calls = 0, inner_sum = 0;
     int inner_max = 0;
     std::vector<int> h_its;
+    int hint_solve = 1, hint_basis = 1;   // inner iterations of the last batched solve per tolerance
 
     // ---------------------------------------------------------------- launch helpers
     void sync() { HIPCHECK(hipStreamSynchronize(stream)); }
@@ -206,13 +276,14 @@ struct Solver : SolverBase {
 
     template <typename TC, typename TX, typename TY, int EPI>
     void stencil(int l, bool smooth_only, int mode, const void* coef, const void* x, void* y, const void* b, void* d,
-                 const int* act, double alpha_, int cheb_k, double* part = nullptr, const double* r64 = nullptr) {
+                 const int* act, double alpha_, int cheb_k, double* part = nullptr, const double* r64 = nullptr,
+                 const double* dotq = nullptr, double* dpart = nullptr) {
         DevLevel& D = lev[l];
+        const int ntot = smooth_only ? D.nt_smooth : D.nt_all;
+        if (ntot == 0) return;
+        if (cheb_k >= KMAX) throw Error(IETI_ENOTSUP, "Chebyshev degree too high");
         StencilArgs a{};
         a.L = D.L;
-        a.tiles = smooth_only ? D.tiles_smooth : D.tiles_all;
-        a.ntiles = smooth_only ? D.nt_smooth : D.nt_all;
-        if (a.ntiles == 0) return;
         a.mode = mode;
         a.coef = coef;
         a.x = x;
@@ -222,9 +293,11 @@ struct Solver : SolverBase {
         a.active = act;
         a.alpha = alpha_;
         a.cheb_k = cheb_k;
-        a.cheb_hi = cheb_hi;
+        a.cheb = D.cheb;
         a.partial = part;
         a.r64 = r64;
+        a.dotq = dotq;
+        a.dpart = dpart;
         int cls = -1;
         if (prof.on && l == 0) {
             if (EPI == EPI_CHEB) cls = IETI_KPROF_SMOOTH_FINE;
@@ -242,12 +315,17 @@ struct Solver : SolverBase {
             ev = prof.next(cls, bytes);
             HIPCHECK(hipEventRecord(ev.first, stream));
         }
-        if (l == 0)
-            hipLaunchKernelGGL((k_stencil<TC, TX, TY, EPI, true>), dim3(tile_grid(a.ntiles)), dim3(TILE), 0, stream, a);
-        else
-            hipLaunchKernelGGL((k_stencil<TC, TX, TY, EPI, false>), dim3(tile_grid(a.ntiles)), dim3(TILE), 0, stream,
-                               a);
-        check_launch();
+        const Tile* base = smooth_only ? D.tiles_smooth : D.tiles_all;
+        for (int c = 0; c <= NCLASS; ++c) {
+            const int tb = smooth_only ? D.cls_beg_sm[c] : D.cls_beg_all[c];
+            const int te = smooth_only ? D.cls_end_sm[c] : D.cls_end_all[c];
+            if (te <= tb) continue;
+            a.tiles = base + tb;
+            a.ntiles = te - tb;
+            if (l == 0) launch_stencil<TC, TX, TY, EPI, true>(c, stream, a);
+            else launch_stencil<TC, TX, TY, EPI, false>(c, stream, a);
+            check_launch();
+        }
         if (cls >= 0) HIPCHECK(hipEventRecord(ev.second, stream));
     }
     template <typename V>
@@ -258,7 +336,11 @@ struct Solver : SolverBase {
 
     // ---------------------------------------------------------------- multigrid V-cycle
     // x0 = V(b0) on all patches (mode N or D); the result lands in x0.
-    void vcycle(int mode, const int* act, const T* b0, T* x0) {
+    void vcycle(int mode, const int* act, const T* b0, T* x0, const double* dotq = nullptr, double* dpart = nullptr) {
+        if (fused) {
+            vcycle_fused(mode, act, b0, x0, dotq, dpart);
+            return;
+        }
         std::vector<T*> cur(nlev, nullptr);
         int deepest = 0;
         for (int l = 0; l < nlev; ++l) {
@@ -278,7 +360,7 @@ struct Solver : SolverBase {
             T* X = S;
             T* XA = F;
             hipLaunchKernelGGL(k_cheb_zero<T>, dim3(tile_grid(D.nt_smooth)), dim3(TILE), 0, stream, D.L,
-                               D.tiles_smooth, D.nt_smooth, (const T*)D.coefT, B, X, (T*)D.vd, mode, cheb_hi, act);
+                               D.tiles_smooth, D.nt_smooth, (const T*)D.coefT, B, X, (T*)D.vd, mode, D.cheb, act);
             check_launch();
             for (int k = 1; k < cheb_m; ++k) {
                 stencil<T, T, T, EPI_CHEB>(l, true, mode, D.coefT, X, XA, B, D.vd, act, 0.0, k);
@@ -287,9 +369,13 @@ struct Solver : SolverBase {
             stencil<T, T, T, EPI_RESID>(l, true, mode, D.coefT, X, D.vr, B, nullptr, act, 0.0, 0);
             cur[l] = X;
             DevLevel& C = lev[l + 1];
-            hipLaunchKernelGGL(k_restrict<T>, dim3(tile_grid(C.nt_all)), dim3(TILE), 0, stream, D.L, C.L, C.tiles_all,
-                               C.nt_all, D.rlo, (const T*)D.rval, (const T*)D.vr, (T*)C.vb, mode, act);
-            check_launch();
+            for (int c = 0; c <= NCLASS; ++c) {
+                const int tb = C.cls_beg_all[c], te = C.cls_end_all[c];
+                if (te <= tb) continue;
+                launch_restrict<T>(c, stream, D.L, C.L, C.tiles_all + tb, te - tb, D.rlo, (const T*)D.rval,
+                                   (const T*)D.vr, (T*)C.vb, mode, act);
+                check_launch();
+            }
         }
         for (int l = deepest - 1; l >= 0; --l) {
             DevLevel& D = lev[l];
@@ -298,17 +384,92 @@ struct Solver : SolverBase {
             T* A0 = l == 0 ? (T*)D.vxa : (T*)D.vx;   // the level's two x buffers
             T* A1 = l == 0 ? x0 : (T*)D.vxa;
             T* XA = (X == A0) ? A1 : A0;
-            hipLaunchKernelGGL(k_prolong<T>, dim3(tile_grid(D.nt_smooth)), dim3(TILE), 0, stream, D.L, lev[l + 1].L,
-                               D.tiles_smooth, D.nt_smooth, D.plo, (const T*)D.pval, (const T*)cur[l + 1], X, mode,
-                               act);
-            check_launch();
+            for (int c = 0; c <= NCLASS; ++c) {
+                const int tb = D.cls_beg_sm[c], te = D.cls_end_sm[c];
+                if (te <= tb) continue;
+                launch_prolong<T>(c, stream, D.L, lev[l + 1].L, D.tiles_smooth + tb, te - tb, D.plo, (const T*)D.pval,
+                                  (const T*)cur[l + 1], X, mode, act);
+                check_launch();
+            }
             for (int k = 0; k < cheb_m; ++k) {
-                stencil<T, T, T, EPI_CHEB>(l, true, mode, D.coefT, X, XA, B, D.vd, act, 0.0, k);
+                const bool last0 = l == 0 && k == cheb_m - 1;
+                stencil<T, T, T, EPI_CHEB>(l, true, mode, D.coefT, X, XA, B, D.vd, act, 0.0, k, nullptr, nullptr,
+                                           last0 ? dotq : nullptr, last0 ? dpart : nullptr);
                 std::swap(X, XA);
             }
             cur[l] = X;
         }
         if (cur[0] != x0) throw Error(IETI_EDEVICE, "internal: V-cycle result buffer mismatch");
+        if (dotq && deepest == 0) throw Error(IETI_ENOTSUP, "internal: fused dot needs a smoothed level 0");
+    }
+
+    // Level 0 with the batched sweep kernels, levels >= 1 in one kernel per degree class.
+    void vcycle_fused(int mode, const int* act, const T* b0, T* x0, const double* dotq, double* dpart) {
+        DevLevel& D = lev[0];
+        T* S = (T*)D.vxa;
+        T* F = x0;
+        if (D.n_coarse) {
+            hipLaunchKernelGGL(k_coarse<T>, dim3(D.n_coarse), dim3(TILE), 0, stream, D.L, D.coarse_list, D.n_coarse,
+                               (const T*)D.inv, b0, F, mode, act);
+            check_launch();
+        }
+        if (D.nt_smooth == 0) return;
+        T* X = S;
+        T* XA = F;
+        hipLaunchKernelGGL(k_cheb_zero<T>, dim3(tile_grid(D.nt_smooth)), dim3(TILE), 0, stream, D.L, D.tiles_smooth,
+                           D.nt_smooth, (const T*)D.coefT, b0, X, (T*)D.vd, mode, D.cheb, act);
+        check_launch();
+        for (int k = 1; k < cheb_m; ++k) {
+            stencil<T, T, T, EPI_CHEB>(0, true, mode, D.coefT, X, XA, b0, D.vd, act, 0.0, k);
+            std::swap(X, XA);
+        }
+        stencil<T, T, T, EPI_RESID>(0, true, mode, D.coefT, X, D.vr, b0, nullptr, act, 0.0, 0);
+        DevLevel& C = lev[1];
+        for (int c = 0; c <= NCLASS; ++c) {
+            const int tb = C.cls_beg_all[c], te = C.cls_end_all[c];
+            if (te <= tb) continue;
+            launch_restrict<T>(c, stream, D.L, C.L, C.tiles_all + tb, te - tb, D.rlo, (const T*)D.rval,
+                               (const T*)D.vr, (T*)C.vb, mode, act);
+            check_launch();
+        }
+        CoarseArgs a{};
+        for (int l = 0; l < nlev && l < LMAX; ++l) {
+            a.L[l] = lev[l].L;
+            a.coef[l] = lev[l].coefT;
+            a.plo[l] = lev[l].plo;
+            a.pval[l] = lev[l].pval;
+            a.rlo[l] = lev[l].rlo;
+            a.rval[l] = lev[l].rval;
+            a.inv[l] = lev[l].inv;
+            a.cheb[l] = lev[l].cheb;
+        }
+        a.chain = chain;
+        a.b1 = C.vb;
+        a.x1 = C.vxa;
+        a.mode = mode;
+        a.m = cheb_m;
+        a.active = act;
+        for (int c = 0; c <= NCLASS; ++c) {
+            if (h_plist[c].empty()) continue;
+            a.plist = plist[c];
+            a.nlist = (int)h_plist[c].size();
+            launch_vcoarse<T>(c, stream, a, vc_lds[c], false);
+            check_launch();
+        }
+        for (int c = 0; c <= NCLASS; ++c) {
+            const int tb = D.cls_beg_sm[c], te = D.cls_end_sm[c];
+            if (te <= tb) continue;
+            launch_prolong<T>(c, stream, D.L, C.L, D.tiles_smooth + tb, te - tb, D.plo, (const T*)D.pval,
+                              (const T*)C.vxa, X, mode, act);
+            check_launch();
+        }
+        for (int k = 0; k < cheb_m; ++k) {
+            const bool last = k == cheb_m - 1;
+            stencil<T, T, T, EPI_CHEB>(0, true, mode, D.coefT, X, XA, b0, D.vd, act, 0.0, k, nullptr, nullptr,
+                                       last ? dotq : nullptr, last ? dpart : nullptr);
+            std::swap(X, XA);
+        }
+        if (X != x0) throw Error(IETI_EDEVICE, "internal: V-cycle result buffer mismatch");
     }
 
     // ---------------------------------------------------------------- batched flexible CG: fx = K_rr^{-1} b
@@ -316,52 +477,54 @@ struct Solver : SolverBase {
     void fcg(const double* b, double tol, int maxit) {
         DevLevel& D = lev[0];
         const int nt = D.nt_all;
+        double* pzq = partial;              // nt
+        double* pdots = partial + nt;       // 2 nt
+        double* prr = partial + 3 * nt;     // nt
         hipLaunchKernelGGL(k_fcg_init<T>, dim3(tile_grid(nt)), dim3(TILE), 0, stream, D.L, D.tiles_all, nt, b, fx,
-                           fr, rT, fd, fq, partial, (int)MODE_N);
+                           fr, rT, fd, fq, prr, (int)MODE_N);
         check_launch();
-        fill<int>(nactive, 1, 0);
-        hipLaunchKernelGGL(k_fcg_scalars, dim3(nblk(N, 256)), dim3(256), 0, stream, N, tile_ptr, partial, 1, 0, bb,
-                           dq, beta, alpha, active, its, tol * tol, maxit, 1, nactive);
+        hipLaunchKernelGGL(k_fcg_check, dim3(1), dim3(256), 0, stream, N, tile_beg, tile_end, prr, 1, bb, active, its,
+                           brk, tol * tol, maxit, nactive);
         check_launch();
+        // patches whose finest level is also their coarsest cannot fuse z . q into the smoother
+        const bool fuse_zq = lev[0].n_coarse == 0;
+        // host checks: first near the iteration count the previous solve at this tolerance needed, then
+        // every check_every iterations (a sync costs more than an extra iteration of finished patches)
         const int every = std::max(1, plan->opt.check_every);
+        int& hint = tol < 1e-11 ? hint_basis : hint_solve;
+        int next_check = std::max(1, hint - 1);
+        int last_it = 0;
         for (int it = 0; it < maxit; ++it) {
-            if (it % every == 0) {
+            if (it == next_check) {
                 HIPCHECK(hipMemcpyAsync(h_nactive, nactive, sizeof(int), hipMemcpyDeviceToHost, stream));
                 sync();
                 if (*h_nactive == 0) break;
+                next_check = it + every;
             }
-            vcycle(MODE_N, active, rT, zT);
-            if (it > 0) {
-                hipLaunchKernelGGL(k_fcg_zq<T>, dim3(tile_grid(nt)), dim3(TILE), 0, stream, D.L, D.tiles_all, nt, zT,
-                                   fq, partial, active);
-                check_launch();
+            last_it = it + 1;
+            if (fuse_zq && it > 0) {
+                vcycle(MODE_N, active, rT, zT, fq, pzq);
+            } else {
+                vcycle(MODE_N, active, rT, zT);
+                if (it > 0) {
+                    hipLaunchKernelGGL(k_fcg_zq<T>, dim3(tile_grid(nt)), dim3(TILE), 0, stream, D.L, D.tiles_all, nt,
+                                       zT, fq, pzq, active);
+                    check_launch();
+                }
             }
-            hipLaunchKernelGGL(k_fcg_scalars, dim3(nblk(N, 256)), dim3(256), 0, stream, N, tile_ptr, partial, 1, 1,
-                               bb, dq, beta, alpha, active, its, tol * tol, maxit, it == 0 ? 1 : 0, nactive);
-            check_launch();
             hipLaunchKernelGGL(k_fcg_dir<T>, dim3(tile_grid(nt)), dim3(TILE), 0, stream, D.L, D.tiles_all, nt, zT, fd,
-                               beta, (int)MODE_N, active);
+                               pzq, tile_beg, tile_end, dq, it == 0 ? 1 : 0, (int)MODE_N, active);
             check_launch();
             stencil<double, double, double, EPI_DOTS>(0, false, MODE_N, coef64, fd, fq, nullptr, nullptr, active, 0.0,
-                                                      0, partial, fr);
-            hipLaunchKernelGGL(k_fcg_scalars, dim3(nblk(N, 256)), dim3(256), 0, stream, N, tile_ptr, partial, 2, 2,
-                               bb, dq, beta, alpha, active, its, tol * tol, maxit, 0, nactive);
-            check_launch();
+                                                      0, pdots, fr);
             hipLaunchKernelGGL(k_fcg_update<T>, dim3(tile_grid(nt)), dim3(TILE), 0, stream, D.L, D.tiles_all, nt, fd,
-                               fq, fx, fr, rT, alpha, partial, active);
+                               fq, fx, fr, rT, pdots, tile_beg, tile_end, dq, brk, prr, active);
             check_launch();
-            fill<int>(nactive, 1, 0);
-            hipLaunchKernelGGL(k_fcg_scalars, dim3(nblk(N, 256)), dim3(256), 0, stream, N, tile_ptr, partial, 1, 3,
-                               bb, dq, beta, alpha, active, its, tol * tol, maxit, 0, nactive);
+            hipLaunchKernelGGL(k_fcg_check, dim3(1), dim3(256), 0, stream, N, tile_beg, tile_end, prr, 0, bb, active,
+                               its, brk, tol * tol, maxit, nactive);
             check_launch();
         }
-        HIPCHECK(hipMemcpyAsync(h_its.data(), its, sizeof(int) * N, hipMemcpyDeviceToHost, stream));
-        sync();
-        for (int k = 0; k < N; ++k) {
-            inner_sum += h_its[k];
-            inner_max = std::max(inner_max, h_its[k]);
-        }
-        inner_calls += N;
+        hint = last_it;
     }
 
     // ---------------------------------------------------------------- K~^{-1} g, primal part on the slots or on all rows
@@ -498,6 +661,7 @@ void Solver<T>::setup() {
             }
             P.dim = dim;
             P.nst = L.nst;
+            P.pclass = degree_class(dim, P.p[0], P.p[1], P.p[2]);
             const uint32_t all = dim == 3 ? 0x3Fu : 0xFu;
             P.mbits[MODE_N] = pa.bside | ((pa.pcorner | pa.dcorner) << 8);
             P.mbits[MODE_D] = all;
@@ -532,19 +696,30 @@ void Solver<T>::setup() {
                     C.hL[c].fine = (int)f;
                 }
     }
+    const double hi = cheb_hi;
     for (int l = 0; l < nlev; ++l) {
         DevLevel& D = lev[l];
-        for (size_t i = 0; i < D.hL.size(); ++i) {
-            const PatchLev& P = D.hL[i];
-            bool smooth = P.coarse >= 0;
-            for (int64_t s = 0; s < P.n; s += TILE) {
-                D.h_all.push_back({(int32_t)i, (int32_t)s});
-                if (smooth) D.h_smooth.push_back({(int32_t)i, (int32_t)s});
+        for (int c = 0; c <= NCLASS; ++c) {
+            D.cls_beg_all[c] = (int)D.h_all.size();
+            for (size_t i = 0; i < D.hL.size(); ++i) {
+                const PatchLev& P = D.hL[i];
+                if (P.pclass != c) continue;
+                for (int64_t s = 0; s < P.n; s += TILE)
+                    D.h_all.push_back({(int32_t)i, (int32_t)s, (int32_t)D.h_all.size(), 0});
             }
-            if (!smooth) D.h_coarse.push_back((int32_t)i);
+            D.cls_end_all[c] = (int)D.h_all.size();
         }
+        for (int c = 0; c <= NCLASS; ++c) {
+            D.cls_beg_sm[c] = (int)D.h_smooth.size();
+            for (int t = D.cls_beg_all[c]; t < D.cls_end_all[c]; ++t)
+                if (D.hL[D.h_all[t].pl].coarse >= 0) D.h_smooth.push_back(D.h_all[t]);
+            D.cls_end_sm[c] = (int)D.h_smooth.size();
+        }
+        for (size_t i = 0; i < D.hL.size(); ++i)
+            if (D.hL[i].coarse < 0) D.h_coarse.push_back((int32_t)i);
         D.nt_all = (int)D.h_all.size();
         D.nt_smooth = (int)D.h_smooth.size();
+        D.n_coarse = (int)D.h_coarse.size();
         for (const PatchLev& P : D.hL) {
             D.words_all += (double)P.n;
             D.st_all += (double)P.n * P.nst;
@@ -553,7 +728,29 @@ void Solver<T>::setup() {
                 D.st_smooth += (double)P.n * P.nst;
             }
         }
-        D.n_coarse = (int)D.h_coarse.size();
+        // Chebyshev coefficients d_k = s1 d_{k-1} + s2 D^{-1} r_k on [clo, hi] * lambda_max
+        std::vector<double> ch(D.hL.size() * 2 * KMAX * 2, 0.0);
+        for (size_t i = 0; i < D.hL.size(); ++i)
+            for (int m = 0; m < 2; ++m) {
+                const double lm = D.hL[i].lmax[m] > 0 ? D.hL[i].lmax[m] : 1.0;
+                const double aa = D.hL[i].clo * lm, bb = hi * lm;
+                const double theta = 0.5 * (aa + bb), delta = 0.5 * (bb - aa), sigma = theta / delta;
+                double rho_prev = 1.0 / sigma, rho = rho_prev;
+                for (int k = 0; k < KMAX; ++k) {
+                    double s1 = 0.0, s2 = 1.0 / theta;
+                    if (k > 0) {
+                        rho_prev = rho;
+                        rho = 1.0 / (2.0 * sigma - rho_prev);
+                        s1 = rho * rho_prev;
+                        s2 = 2.0 * rho / delta;
+                    }
+                    const size_t o = 2 * ((i * 2 + m) * KMAX + k);
+                    ch[o] = s1;
+                    ch[o + 1] = s2;
+                }
+            }
+        D.cheb = arena.upload(ch, st);
+        HIPCHECK(hipStreamSynchronize(st));
     }
     // ---- transfer tables, stencils, inverses
     for (int l = 0; l < nlev; ++l) {
@@ -634,16 +831,57 @@ void Solver<T>::setup() {
         D.vr = arena.alloc<T>(D.len, st);
         HIPCHECK(hipStreamSynchronize(st));   // host vectors above go out of scope
     }
+    // ---- fused coarse V-cycle
+    if (nlev > 1 && nlev <= LMAX) {
+        int dev = 0;
+        HIPCHECK(hipGetDevice(&dev));
+        int max_lds = 0;
+        HIPCHECK(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+        std::vector<int32_t> ch((size_t)N * LMAX, -1);
+        for (int l = 0; l < nlev; ++l)
+            for (size_t i = 0; i < lev[l].hL.size(); ++i) ch[(size_t)lev[l].hL[i].patch * LMAX + l] = (int32_t)i;
+        bool ok = true;
+        for (int k = 0; k < N; ++k) {
+            const Patch& pa = pl.patches[k];
+            const int nl = (int)pa.lv.size();
+            if (nl < 2) continue;
+            size_t words = 0;
+            for (int l = 1; l < nl; ++l) {
+                const Level& L = pa.lv[l];
+                words += 2 * (size_t)(L.n + 2 * L.guard) + 2 * (size_t)L.n;
+            }
+            const size_t bytes = words * sizeof(T);
+            if ((int64_t)bytes > max_lds) ok = false;
+            const int c = lev[0].hL[k].pclass;
+            h_plist[c].push_back(k);
+            vc_lds[c] = std::max(vc_lds[c], bytes);
+        }
+        if (ok) {
+            chain = arena.upload(ch, st);
+            for (int c = 0; c <= NCLASS; ++c) {
+                if (h_plist[c].empty()) continue;
+                plist[c] = arena.upload(h_plist[c], st);
+                CoarseArgs dummy{};
+                launch_vcoarse<T>(c, st, dummy, vc_lds[c], true);
+            }
+            fused = true;
+        }
+        HIPCHECK(hipStreamSynchronize(st));
+    }
     DevLevel& D0 = lev[0];
     len0 = D0.len;
     for (double** p : {&f64, &b64, &e64, &w64, &s64, &u64, &fx, &fr, &fd, &fq}) *p = arena.alloc<double>(len0, st);
     for (T** p : {&rT, &zT, &bT, &xIT, &x2T, &r2T}) *p = arena.alloc<T>(len0, st);
-    partial = arena.alloc<double>(2 * (int64_t)D0.nt_all + 2, st);
+    partial = arena.alloc<double>(4 * (int64_t)D0.nt_all + 4, st);
     {
-        std::vector<int32_t> tp(N + 1, 0);
-        for (auto& t : D0.h_all) tp[D0.hL[t.pl].patch + 1]++;
-        for (int k = 0; k < N; ++k) tp[k + 1] += tp[k];
-        tile_ptr = arena.upload(tp, st);
+        std::vector<int32_t> tb(N, 0), te(N, 0);
+        for (size_t t = 0; t < D0.h_all.size(); ++t) {
+            const int k = D0.hL[D0.h_all[t].pl].patch;
+            if (te[k] == 0) tb[k] = (int32_t)t;
+            te[k] = (int32_t)t + 1;
+        }
+        tile_beg = arena.upload(tb, st);
+        tile_end = arena.upload(te, st);
     }
     bb = arena.alloc<double>(N, st);
     dq = arena.alloc<double>(N, st);
@@ -651,7 +889,8 @@ void Solver<T>::setup() {
     alpha = arena.alloc<double>(N, st);
     active = arena.alloc<int>(N, st);
     its = arena.alloc<int>(N, st);
-    nactive = arena.alloc<int>(1, st);
+    brk = arena.alloc<int>(N, st);
+    nactive = arena.alloc<int>(4, st);
     h_its.assign(N, 0);
     HIPCHECK(hipHostMalloc((void**)&h_nactive, sizeof(int)));
     HIPCHECK(hipHostMalloc((void**)&h_sc, 16 * sizeof(double)));
@@ -942,6 +1181,7 @@ int Solver<T>::solve(const double* f_qp, double* u_out, ieti_stats* stp) {
     auto ms = [](clk::time_point a, clk::time_point b) { return std::chrono::duration<double, std::milli>(b - a).count(); };
     inner_calls = inner_sum = 0;
     inner_max = 0;
+    fill<int>(nactive, 4, 0);
     ieti_stats st{};
     st.ndof_torn = pl.ndof_torn;
     st.ndof_global = pl.ndof_global;
@@ -1054,6 +1294,13 @@ int Solver<T>::solve(const double* f_qp, double* u_out, ieti_stats* stp) {
     st.time_pcg_ms = ms(t1, t2);
     st.time_recovery_ms = ms(t2, t3);
     st.time_total_ms = ms(t0, t3);
+    {
+        int h4[4];
+        HIPCHECK(hipMemcpy(h4, nactive, sizeof(h4), hipMemcpyDeviceToHost));
+        inner_sum = h4[1];
+        inner_max = h4[2];
+        inner_calls = h4[3];
+    }
     st.inner_iterations_max = inner_max;
     st.inner_iterations_mean = inner_calls ? (double)inner_sum / (double)inner_calls : 0.0;
     if (stp) *stp = st;

@@ -73,7 +73,7 @@ class Workload:
     u_exact: Callable[[np.ndarray], np.ndarray]
     local_solver: str = "mg"         # "exact" (banded Cholesky) or "mg" (inexact, multigrid)
     mg_precision: int = 64           # 64 or 32 (multigrid arithmetic)
-    primal: str = "vertices"         # "vertices" or "vertices+edges" (3D edge averages)
+    primal: str = "vertices"         # "vertices" or "vertices+edges" (edge averages; in 2D the patch sides)
     tol: float = 1e-8                # outer PCG: ||r_k||_2 <= tol ||r_0||_2
     inner_tol: float = 1e-10         # local Neumann solves inside F
     seed: int | None = None
@@ -272,9 +272,9 @@ def square_2x2() -> Workload:
 def deformed_8x8(seed: int = 0) -> Workload:
     """Deformed square, 8x8 patches, p=3, 64x64 elements each, FP64 multigrid local solves."""
     return deformed_square((8, 8), 3, 64, seed=seed, name="deformed8x8_p3_n64", local_solver="mg",
-                           mg_precision=64,
+                           mg_precision=64, primal="vertices+edges",
                            description="2D Poisson on the deformed square, 8x8 patches, p=3, 64^2 elements, "
-                                       "FP64 MG V(2,2) Chebyshev local solves")
+                                       "FP64 MG V(2,2) Chebyshev local solves, primal vertices + edge averages")
 
 
 def deformed_16x16_mixed(seed: int = 0) -> Workload:
@@ -292,7 +292,7 @@ def deformed_16x16_mixed(seed: int = 0) -> Workload:
         nel.append([int(v) for v in rng.choice([32, 48, 64, 96], size=16)])
         deg.append([int(v) for v in rng.choice([2, 3, 4], size=16)])
     wl = deformed_square((16, 16), deg, nel, amp_factor=xi, name="deformed16x16_mixed", local_solver="mg",
-                         mg_precision=32,
+                         mg_precision=32, primal="vertices+edges",
                          description="2D Poisson on the deformed square, 16x16 patches, per-column/per-row "
                                      "elements in {32,48,64,96} and degree in {2,3,4}, FP32 MG")
     wl.seed = seed
@@ -328,7 +328,7 @@ def serving_stream(seed: int = 0, n_requests: int = 512,
         t += float(rng.exponential(1.0))
         f, u = sine_series_rhs(coef)
         wl = deformed_square((g, g), p, n, amp_factor=xi, name=f"req{i}_g{g}_p{p}_n{n}", local_solver="mg",
-                             mg_precision=32)
+                             mg_precision=32, primal="vertices+edges")
         wl.f, wl.u_exact = f, u
         wl.extra["coef"] = coef
         out.append(Request(index=i, arrival_unit=t, workload=wl))
