@@ -13,6 +13,7 @@
 // flexible CG (FP64) preconditioned by one multigrid V-cycle (FP32 or FP64),
 // to a relative residual inner_tol (Sec. 3.2 / Sec. 4: MG-MG).  The
 // Dirichlet problems in the preconditioner use prec_vcycles V-cycles.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -60,10 +61,19 @@ static inline unsigned tile_grid(int ntiles) { return (unsigned)(8 * ((ntiles + 
     default: L(-1, -1, -1); break;               \
     }
 
+// With ev0/ev1 set, the launch records them at kernel start and end (profiling).
 template <typename TC, typename TX, typename TY, int EPI, bool FINE>
-static void launch_stencil(int cls, hipStream_t st, const StencilArgs& a) {
-#define IETI_LS(A, B, C) \
-    hipLaunchKernelGGL((k_stencil<A, B, C, TC, TX, TY, EPI, FINE>), dim3(tile_grid(a.ntiles)), dim3(TILE), 0, st, a)
+static void launch_stencil(int cls, hipStream_t st, const StencilArgs& a, hipEvent_t ev0 = nullptr,
+                           hipEvent_t ev1 = nullptr) {
+#define IETI_LS(A, B, C)                                                                                              \
+    do {                                                                                                              \
+        if (ev0)                                                                                                      \
+            hipExtLaunchKernelGGL((k_stencil<A, B, C, TC, TX, TY, EPI, FINE>), dim3(tile_grid(a.ntiles)), dim3(TILE), \
+                                  0, st, ev0, ev1, 0, a);                                                             \
+        else                                                                                                          \
+            hipLaunchKernelGGL((k_stencil<A, B, C, TC, TX, TY, EPI, FINE>), dim3(tile_grid(a.ntiles)), dim3(TILE), 0, \
+                               st, a);                                                                                \
+    } while (0)
     IETI_CLASS_SWITCH(cls, IETI_LS)
 #undef IETI_LS
 }
@@ -188,8 +198,9 @@ struct SolverBase {
 };
 
 struct DevLevel {
-    double words_all = 0, words_smooth = 0;       // sum of n over the launch's patches
-    double st_all = 0, st_smooth = 0;             // sum of n * nst (half-stencil words)
+    // per degree class: sum of n and of n * nst (half-stencil words) over the launch's patches
+    double words_all[NCLASS + 1] = {0}, words_smooth[NCLASS + 1] = {0};
+    double st_all[NCLASS + 1] = {0}, st_smooth[NCLASS + 1] = {0};
     std::vector<PatchLev> hL;
     PatchLev* L = nullptr;
     int64_t len = 0, clen = 0;
@@ -298,22 +309,11 @@ struct Solver : SolverBase {
         a.r64 = r64;
         a.dotq = dotq;
         a.dpart = dpart;
-        int cls = -1;
+        int pcls = -1;
         if (prof.on && l == 0) {
-            if (EPI == EPI_CHEB) cls = IETI_KPROF_SMOOTH_FINE;
-            else if (EPI == EPI_DOTS) cls = IETI_KPROF_APPLY64;
-            else if (EPI == EPI_RESID && smooth_only) cls = IETI_KPROF_RESID_FINE;
-        }
-        std::pair<hipEvent_t, hipEvent_t> ev{};
-        if (cls >= 0) {
-            // algorithmic bytes: every vector the epilogue touches and the half stencil, once per coefficient
-            const double n = smooth_only ? D.words_smooth : D.words_all;
-            const double nst = smooth_only ? D.st_smooth : D.st_all;
-            double vec_words = EPI == EPI_CHEB ? (cheb_k > 0 ? 5.0 : 4.0) : 3.0;
-            double bytes = nst * sizeof(TC) + n * (vec_words - 1.0) * sizeof(TY) + n * sizeof(TX);
-            if (EPI == EPI_DOTS) bytes = nst * sizeof(TC) + n * (sizeof(TX) + sizeof(TY) + sizeof(double));
-            ev = prof.next(cls, bytes);
-            HIPCHECK(hipEventRecord(ev.first, stream));
+            if (EPI == EPI_CHEB) pcls = IETI_KPROF_SMOOTH_FINE;
+            else if (EPI == EPI_DOTS) pcls = IETI_KPROF_APPLY64;
+            else if (EPI == EPI_RESID && smooth_only) pcls = IETI_KPROF_RESID_FINE;
         }
         const Tile* base = smooth_only ? D.tiles_smooth : D.tiles_all;
         for (int c = 0; c <= NCLASS; ++c) {
@@ -322,11 +322,20 @@ struct Solver : SolverBase {
             if (te <= tb) continue;
             a.tiles = base + tb;
             a.ntiles = te - tb;
-            if (l == 0) launch_stencil<TC, TX, TY, EPI, true>(c, stream, a);
-            else launch_stencil<TC, TX, TY, EPI, false>(c, stream, a);
+            std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+            if (pcls >= 0) {
+                // algorithmic bytes: every vector the epilogue touches and the half stencil, once per coefficient
+                const double n = smooth_only ? D.words_smooth[c] : D.words_all[c];
+                const double nst = smooth_only ? D.st_smooth[c] : D.st_all[c];
+                const double vec_words = EPI == EPI_CHEB ? (cheb_k > 0 ? 5.0 : 4.0) : 3.0;
+                double bytes = nst * sizeof(TC) + n * (vec_words - 1.0) * sizeof(TY) + n * sizeof(TX);
+                if (EPI == EPI_DOTS) bytes = nst * sizeof(TC) + n * (sizeof(TX) + sizeof(TY) + sizeof(double));
+                ev = prof.next(pcls, bytes);
+            }
+            if (l == 0) launch_stencil<TC, TX, TY, EPI, true>(c, stream, a, ev.first, ev.second);
+            else launch_stencil<TC, TX, TY, EPI, false>(c, stream, a, ev.first, ev.second);
             check_launch();
         }
-        if (cls >= 0) HIPCHECK(hipEventRecord(ev.second, stream));
     }
     template <typename V>
     void fill(V* p, int64_t n, V v) {
@@ -721,11 +730,12 @@ void Solver<T>::setup() {
         D.nt_smooth = (int)D.h_smooth.size();
         D.n_coarse = (int)D.h_coarse.size();
         for (const PatchLev& P : D.hL) {
-            D.words_all += (double)P.n;
-            D.st_all += (double)P.n * P.nst;
+            const int c = P.pclass;
+            D.words_all[c] += (double)P.n;
+            D.st_all[c] += (double)P.n * P.nst;
             if (P.coarse >= 0) {
-                D.words_smooth += (double)P.n;
-                D.st_smooth += (double)P.n * P.nst;
+                D.words_smooth[c] += (double)P.n;
+                D.st_smooth[c] += (double)P.n * P.nst;
             }
         }
         // Chebyshev coefficients d_k = s1 d_{k-1} + s2 D^{-1} r_k on [clo, hi] * lambda_max
