@@ -53,10 +53,19 @@ def cpu_baseline(sample_grid=(4, 4)):
         parts, lam, info = ie.solve(tol=1e-8)
         t2 = time.perf_counter()
     solve_s = t2 - t1
+    cpu = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {
         "value": wl.ndof_torn / solve_s / 1e6,
         "unit": "MDoF/s",
         "cores": 1,
+        "host_cpu": f"{cpu}, {len(os.sched_getaffinity(0))} threads available",
         "kind": "oracle",
         "sample": (f"{sample_grid[0]}x{sample_grid[1]} patches of the same deformed square, p=3, 64^2 elements "
                    f"({wl.ndof_torn} torn dofs); exact local solves (SuperLU), CG to 1e-8 in {info['iterations']} "
@@ -65,15 +74,89 @@ def cpu_baseline(sample_grid=(4, 4)):
     }
 
 
+def serve(args):
+    """Serving stream: requests of mixed size (2D deformed square, grid {2,4,8}^2, p {2,3,4},
+    n_el {16,...,128}, sine-series f) through the request loop.  Pass 1 submits all at once
+    (saturated throughput X); pass 2 replays the stream's Poisson arrivals at 0.8 X and reports
+    latency percentiles; the baseline solves the same requests one after another with FP64
+    exact local solves."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_1705_04531_amd import Server, _abi, options_for, quadrature_points
+
+    reqs = W.serving_stream(seed=0, n_requests=args.requests)
+    inputs = []
+    for r in reqs:
+        x = quadrature_points(r.workload.patches)
+        inputs.append((r.workload, r.workload.f(x)))
+    ndof = sum(wl.ndof_torn for wl, _ in inputs)
+    opt = options_for(inputs[0][0])
+
+    def run(rate, slots, options):
+        srv = Server(options, slots=slots)
+        tick = []
+        t0 = time.perf_counter()
+        for i, (wl, f) in enumerate(inputs):
+            if rate:
+                delay = t0 + reqs[i].arrival_unit / rate - time.perf_counter()
+                if delay > 0:
+                    time.sleep(delay)
+            tick.append(srv.submit(wl.patches, f))
+        lat, bad = [], 0
+        for t in tick:
+            rc, u, st, times = srv.poll(t, wait=True)
+            bad += rc != 0
+            lat.append(times[2] - times[0])
+        span = time.perf_counter() - t0
+        srv.close()
+        return span, np.array(lat), bad
+
+    torch.cuda.synchronize()
+    span_sat, lat_sat, bad = run(0.0, args.slots, opt)
+    X = len(inputs) / span_sat
+    span, lat, bad2 = run(0.8 * X, args.slots, opt)
+    base_span, base_lat, bad3 = run(0.0, 1, options_for(inputs[0][0], local_solver=_abi.IETI_LOCAL_EXACT,
+                                                         mg_precision=64))
+    out = {
+        "metric": "serving solves/s and p50/p99 latency (Poisson arrivals at 0.8x saturated throughput)",
+        "value": round(len(inputs) / span, 3),
+        "unit": "solves/s",
+        "higher_is_better": True,
+        "n_gpus": 1,
+        "dtype": "f64 outer / f32 MG",
+        "data": "synthetic",
+        "config": {"workload": f"serving stream, {len(inputs)} requests (seed 0), {ndof} torn dofs in total",
+                   "slots": args.slots, "arrival_rate_per_s": round(0.8 * X, 3)},
+        "p50_ms": round(float(np.percentile(lat, 50)), 2),
+        "p99_ms": round(float(np.percentile(lat, 99)), 2),
+        "saturated_solves_per_s": round(X, 3),
+        "saturated_p50_ms": round(float(np.percentile(lat_sat, 50)), 2),
+        "sequential_fp64_exact": {"solves_per_s": round(len(inputs) / base_span, 3),
+                                  "p50_ms": round(float(np.percentile(base_lat, 50)), 2)},
+        "speedup_vs_sequential": round(base_span / span_sat, 3),
+        "failed": int(bad + bad2 + bad3),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true", help="skip the exact-local comparison form")
+    ap.add_argument("--serve", action="store_true", help="serving benchmark instead of the solve benchmark")
+    ap.add_argument("--requests", type=int, default=64)
+    ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 512 MiB FP64 tensor 3 times (scale for the FETCH_SIZE/WRITE_SIZE counters)")
     args = ap.parse_args()
+    if args.serve:
+        serve(args)
+        return
     if args.calibrate_copy:
         import torch
         a = torch.ones(64 << 20, dtype=torch.float64, device="cuda")
@@ -119,6 +202,30 @@ def main():
     solver.profile(False)
     ms_per_step = elapsed / args.steps * 1e3
     value = wl.ndof_torn / (ms_per_step * 1e-3) / 1e6
+    u_mg = u.clone()
+    solver.close()
+
+    # the plain FP64 exact-local form (banded Cholesky local solves, D-D) on the same workload
+    plain = None
+    if not args.no_plain:
+        t0 = time.perf_counter()
+        ps = Solver(wl.patches, options_for(wl, local_solver=_abi.IETI_LOCAL_EXACT))
+        torch.cuda.synchronize()
+        psetup = time.perf_counter() - t0
+        up = torch.empty_like(u)
+        ps.solve(f, up)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            _, pst = ps.solve(f, up)
+        torch.cuda.synchronize()
+        pms = (time.perf_counter() - t0) / args.steps * 1e3
+        diff = float(torch.linalg.norm(u_mg - up) / torch.linalg.norm(up))
+        plain = {"ms_per_step": round(pms, 3), "setup_s": round(psetup, 3),
+                 "outer_iterations": pst["outer_iterations"],
+                 "speedup_inexact_over_plain": round(pms / ms_per_step, 3),
+                 "rel_l2_diff_inexact_vs_plain": diff}
+        ps.close()
 
     dom = prof[_abi.IETI_KPROF_SMOOTH_FINE]
     achieved = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9 if dom["ms"] > 0 else 0.0
@@ -168,6 +275,8 @@ def main():
                                       max(prof[_abi.IETI_KPROF_APPLY64]["ms"], 1e-9) * 1e-6, 1)},
         },
     }
+    if plain is not None:
+        out["plain_form"] = plain
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

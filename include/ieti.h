@@ -47,6 +47,7 @@ extern "C" {
 #define IETI_ENOCONV         -5  /* outer CG did not reach tol in max_it iterations (u is still written) */
 #define IETI_EDEVICE         -6  /* HIP runtime error */
 #define IETI_ENOTSUP         -7  /* configuration outside what this build supports */
+#define IETI_PENDING          1  /* serving: request not finished yet */
 
 /* ---- options ---- */
 #define IETI_LOCAL_MG     0   /* inexact local solves: flexible CG + multigrid V-cycle (MG-MG) */
@@ -138,6 +139,9 @@ int ieti_plan_sizes(const ieti_plan* plan, int64_t* ndof_torn, int64_t* ndof_glo
 #define IETI_ARR_QP_WEIGHT    7  /* double: w_q |det J_q| of patch at level 0 */
 #define IETI_ARR_LMAX         8  /* double: [lambda_max Neumann, lambda_max Dirichlet] of D^{-1}K, patch/level */
 #define IETI_ARR_PRIMAL_MAP   9  /* int64: per local primal constraint of `patch`: global primal index */
+#define IETI_ARR_BAND        10  /* double: exact solves only: blocked band Cholesky data of `patch`, level = 0 (Neumann)
+                                    or 1 (Dirichlet); per 64-row block [L_off 64 x b | U_off 64 x b | inv(L_diag) 64 x 64],
+                                    b = p0 + p1 M0 (+ p2 M0 M1) */
 int ieti_plan_array(const ieti_plan* plan, int32_t which, int32_t patch, int32_t level, void* out,
                     int64_t* count);
 
@@ -184,6 +188,36 @@ void ieti_destroy(ieti_handle* h);
 int ieti_profile_enable(ieti_handle* h, int32_t enable);
 int ieti_profile_query(const ieti_handle* h, int32_t kernel, int64_t* launches, double* total_ms,
                        double* total_bytes);
+
+/*
+ * Physical quadrature points of a set of patches without planning (host;
+ * geometry evaluation only): the points at which a serving request's f must be
+ * sampled.  x_host may be NULL to query *n_qp.
+ */
+int ieti_quadrature_points(const ieti_patch* patches, int32_t n_patches, double* x_host, int64_t* n_qp);
+
+/*
+ * Serving: a request loop for many independent solves.  max_slots worker
+ * streams (1..16) each take the oldest waiting request, plan it, wait until
+ * opt->hbm_budget (0 = unlimited) admits its estimated device footprint, set it
+ * up, solve and copy u back; admitted requests overlap on the device and a
+ * slot takes the next request as soon as it finishes.  Submit copies patches
+ * and f (host, at ieti_quadrature_points order); u (host, ndof_torn doubles)
+ * must stay valid until the request is polled done.  Poll returns
+ * IETI_PENDING while running (or blocks with wait != 0), then the solve's
+ * status once; times_ms (3 doubles, may be NULL) receives submit, admission
+ * and completion times on the server clock.  Requests are independent: a
+ * result does not depend on what else is in flight.
+ */
+typedef struct ieti_server ieti_server;
+/* Device bytes the server reserves for a request with this plan (host). */
+int ieti_plan_device_bytes(const ieti_plan* plan, size_t* bytes);
+int ieti_server_create(const ieti_options* opt, int32_t max_slots, ieti_server** out);
+int ieti_server_submit(ieti_server* s, const ieti_patch* patches, int32_t n_patches, const double* f_qp,
+                       int64_t n_qp, double* u, int64_t* ticket);
+int ieti_server_poll(ieti_server* s, int64_t ticket, int32_t wait, ieti_stats* stats, double* times_ms);
+int ieti_server_load(ieti_server* s, int32_t* queued, int32_t* running, size_t* bytes_in_use);
+void ieti_server_destroy(ieti_server* s);
 
 const char* ieti_strerror(int code);
 const char* ieti_last_error(void);

@@ -15,6 +15,7 @@ IETI_ENOMEM = -4
 IETI_ENOCONV = -5
 IETI_EDEVICE = -6
 IETI_ENOTSUP = -7
+IETI_PENDING = 1
 
 IETI_LOCAL_MG = 0
 IETI_LOCAL_EXACT = 1
@@ -30,6 +31,7 @@ IETI_ARR_LAMBDA_MAP = 6
 IETI_ARR_QP_WEIGHT = 7
 IETI_ARR_LMAX = 8
 IETI_ARR_PRIMAL_MAP = 9
+IETI_ARR_BAND = 10
 
 IETI_KPROF_SMOOTH_FINE = 0
 IETI_KPROF_APPLY64 = 1
@@ -109,6 +111,14 @@ SIGNATURES = {
     "ieti_destroy": (None, [_P]),
     "ieti_profile_enable": (C.c_int, [_P, C.c_int32]),
     "ieti_profile_query": (C.c_int, [_P, C.c_int32, _I64P, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "ieti_quadrature_points": (C.c_int, [C.POINTER(IetiPatch), C.c_int32, C.POINTER(C.c_double), _I64P]),
+    "ieti_plan_device_bytes": (C.c_int, [_P, C.POINTER(C.c_size_t)]),
+    "ieti_server_create": (C.c_int, [C.POINTER(IetiOptions), C.c_int32, C.POINTER(_P)]),
+    "ieti_server_submit": (C.c_int, [_P, C.POINTER(IetiPatch), C.c_int32, C.POINTER(C.c_double), C.c_int64,
+                                     C.POINTER(C.c_double), _I64P]),
+    "ieti_server_poll": (C.c_int, [_P, C.c_int64, C.c_int32, C.POINTER(IetiStats), C.POINTER(C.c_double)]),
+    "ieti_server_load": (C.c_int, [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_size_t)]),
+    "ieti_server_destroy": (None, [_P]),
     "ieti_strerror": (C.c_char_p, [C.c_int]),
     "ieti_last_error": (C.c_char_p, []),
 }

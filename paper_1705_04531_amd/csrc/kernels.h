@@ -1255,4 +1255,83 @@ __global__ __launch_bounds__(VC_THREADS) void k_vcoarse(CoarseArgs a) {
     }
 }
 
+
+// ------------------------------------------------------------------ exact local solves (banded Cholesky)
+//
+// x = (L L^T)^{-1} b for every patch, one work-group per patch, the patch's
+// vector in LDS with zero guards of b entries on both sides.  Forward then
+// backward substitution in blocks of BNB rows: the off-diagonal part of a
+// block row is a GEMV with the already solved entries (8 threads per row,
+// shuffle reduction), the diagonal block is applied through its stored
+// inverse.  Layout of the factor data per block row:
+//   [L_off (BNB x b) | U_off (BNB x b) | inv(L_diag) (BNB x BNB)].
+
+constexpr int BNB = 64;
+constexpr int BAND_THREADS = 512;
+
+__device__ __forceinline__ double sum8(double v) {
+    v += __shfl_xor(v, 1, WAVE);
+    v += __shfl_xor(v, 2, WAVE);
+    v += __shfl_xor(v, 4, WAVE);
+    return v;
+}
+
+__global__ __launch_bounds__(BAND_THREADS) void k_band_solve(const PatchLev* L, const int64_t* band_off,
+                                                           const int32_t* band_b, const double* band, int mode,
+                                                           const double* rhs, double* x, const int* active) {
+    extern __shared__ double bs_lds[];
+    const int k = blockIdx.x;
+    if (active && !active[k]) return;
+    const PatchLev& P = L[k];
+    const int n = (int)P.n;
+    const int b = band_b[k];
+    const int nblk = (n + BNB - 1) / BNB;
+    const int64_t bsz = (int64_t)BNB * (2 * b + BNB);
+    const double* F = band + band_off[2 * k + mode];
+    double* xs = bs_lds + b;                    // xs[-b .. nblk*BNB + b)
+    double* t = bs_lds + 2 * b + nblk * BNB;    // BNB scratch
+    const int tot = 2 * b + nblk * BNB;
+    for (int i = threadIdx.x; i < tot; i += blockDim.x) {
+        const int j = i - b;
+        bs_lds[i] = (j >= 0 && j < n) ? rhs[P.voff + j] : 0.0;
+    }
+    __syncthreads();
+    const int ii = threadIdx.x >> 3, l8 = threadIdx.x & 7;
+    // forward: L y = rhs
+    for (int r = 0; r < nblk; ++r) {
+        const double* blk = F + r * bsz;
+        const double* row = blk + (int64_t)ii * b;
+        const double* xw = xs + r * BNB - b;
+        double acc = 0.0;
+        for (int c = l8; c < b; c += 8) acc += row[c] * xw[c];
+        acc = sum8(acc);
+        if (l8 == 0) t[ii] = xs[r * BNB + ii] - acc;
+        __syncthreads();
+        const double* inv = blk + 2 * (int64_t)BNB * b + (int64_t)ii * BNB;
+        double a2 = 0.0;
+        for (int c = l8; c < BNB; c += 8) a2 += inv[c] * t[c];
+        a2 = sum8(a2);
+        if (l8 == 0) xs[r * BNB + ii] = a2;
+        __syncthreads();
+    }
+    // backward: L^T x = y
+    for (int r = nblk - 1; r >= 0; --r) {
+        const double* blk = F + r * bsz;
+        const double* row = blk + (int64_t)BNB * b + (int64_t)ii * b;
+        const double* xw = xs + (r + 1) * BNB;
+        double acc = 0.0;
+        for (int c = l8; c < b; c += 8) acc += row[c] * xw[c];
+        acc = sum8(acc);
+        if (l8 == 0) t[ii] = xs[r * BNB + ii] - acc;
+        __syncthreads();
+        const double* inv = blk + 2 * (int64_t)BNB * b;
+        double a2 = 0.0;
+        for (int c = l8; c < BNB; c += 8) a2 += inv[(int64_t)c * BNB + ii] * t[c];
+        a2 = sum8(a2);
+        if (l8 == 0) xs[r * BNB + ii] = a2;
+        __syncthreads();
+    }
+    for (int i = threadIdx.x; i < n; i += blockDim.x) x[P.voff + i] = xs[i];
+}
+
 }  // namespace ieti

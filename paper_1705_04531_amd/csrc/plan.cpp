@@ -644,6 +644,79 @@ static std::vector<double> dense_inverse(const Patch& P, const Level& L, int mod
     return inv;
 }
 
+// Banded Cholesky A = L L^T of the masked level-0 stiffness (masked rows and
+// columns replaced by the identity), then the blocked layout of the GPU
+// triangular solves: for every block row r of BAND_NB rows
+//   L_off[ii][c] = L(i, r*nb - b + c)      (columns left of the block)
+//   U_off[ii][c] = L((r+1)*nb + c, i)      (L^T right of the block)
+//   Linv[ii][cc] = inv(L_rr)(ii, cc)       (diagonal block inverse)
+// with i = r*nb + ii; entries outside the band or the matrix are 0.
+static void band_factor(const Patch& P, const Level& L, int mode, int64_t b, std::vector<double>& out) {
+    const int64_t n = L.n, w = b + 1;
+    auto mask = level_mask(P, L, mode);
+    std::vector<double> A((size_t)n * w, 0.0);   // A[i][j - i + b], j in [i-b, i]
+    for (int i2 = 0; i2 < L.M[2]; ++i2)
+        for (int i1 = 0; i1 < L.M[1]; ++i1)
+            for (int i0 = 0; i0 < L.M[0]; ++i0) {
+                const int64_t j = lin(L.M, i0, i1, i2);
+                for (int s = 0; s < L.nst; ++s) {
+                    const int k0 = i0 + L.offs[3 * s], k1 = i1 + L.offs[3 * s + 1], k2 = i2 + L.offs[3 * s + 2];
+                    if (k0 < 0 || k0 >= L.M[0] || k1 < 0 || k1 >= L.M[1] || k2 < 0 || k2 >= L.M[2]) continue;
+                    const int64_t i = lin(L.M, k0, k1, k2);   // i >= j (upper-half offset)
+                    double v = L.coef[(size_t)s * L.n + j];
+                    if (mask[i] || mask[j]) v = (i == j) ? 1.0 : 0.0;
+                    A[(size_t)i * w + (j - i + b)] = v;
+                }
+            }
+    // row-oriented Cholesky in band storage (L overwrites A)
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t j0 = std::max<int64_t>(0, i - b);
+        for (int64_t j = j0; j <= i; ++j) {
+            double s = A[(size_t)i * w + (j - i + b)];
+            const int64_t k0 = std::max(j0, j - b);
+            const double* Li = &A[(size_t)i * w + (k0 - i + b)];
+            const double* Lj = &A[(size_t)j * w + (k0 - j + b)];
+            for (int64_t k = 0; k < j - k0; ++k) s -= Li[k] * Lj[k];
+            if (j == i) {
+                if (!(s > 0)) throw Error(IETI_EINVAL, "local stiffness is not positive definite");
+                A[(size_t)i * w + b] = std::sqrt(s);
+            } else {
+                A[(size_t)i * w + (j - i + b)] = s / A[(size_t)j * w + b];
+            }
+        }
+    }
+    auto Lat = [&](int64_t i, int64_t j) -> double {   // L(i, j), 0 outside the band / matrix
+        if (i < 0 || j < 0 || i >= n || j >= n || j > i || i - j > b) return 0.0;
+        return A[(size_t)i * w + (j - i + b)];
+    };
+    const int64_t nb = BAND_NB, nblk = (n + nb - 1) / nb, bs = nb * (2 * b + nb);
+    out.assign((size_t)(nblk * bs), 0.0);
+    std::vector<double> D((size_t)nb * nb), Di((size_t)nb * nb);
+    for (int64_t r = 0; r < nblk; ++r) {
+        double* blk = &out[(size_t)(r * bs)];
+        for (int64_t ii = 0; ii < nb; ++ii) {
+            const int64_t i = r * nb + ii;
+            for (int64_t c = 0; c < b; ++c) {
+                blk[ii * b + c] = Lat(i, r * nb - b + c);
+                blk[nb * b + ii * b + c] = Lat((r + 1) * nb + c, i);
+            }
+        }
+        // diagonal block (identity on padding rows) and its inverse (forward substitution)
+        for (int64_t ii = 0; ii < nb; ++ii)
+            for (int64_t cc = 0; cc < nb; ++cc) {
+                const int64_t i = r * nb + ii, j = r * nb + cc;
+                D[ii * nb + cc] = i >= n ? (ii == cc ? 1.0 : 0.0) : (j <= i ? Lat(i, j) : 0.0);
+            }
+        for (int64_t c = 0; c < nb; ++c)
+            for (int64_t ii = 0; ii < nb; ++ii) {
+                double s = ii == c ? 1.0 : 0.0;
+                for (int64_t k = c; k < ii; ++k) s -= D[ii * nb + k] * Di[k * nb + c];
+                Di[ii * nb + c] = ii < c ? 0.0 : s / D[ii * nb + ii];
+            }
+        std::copy(Di.begin(), Di.end(), blk + 2 * nb * b);
+    }
+}
+
 // ----------------------------------------------------------------------------
 // topology
 
@@ -1093,7 +1166,7 @@ Plan* build_plan(const ieti_patch* in, int n, const double* pv, int n_pv, const 
                 }
         pa.affine = aff;
         // levels: halve while every direction has an even number (>= 6) of elements
-        while (true) {
+        while (opt.local_solver == IETI_LOCAL_MG) {
             const Level& f = pa.lv.back();
             bool ok = true;
             for (int d = 0; d < dim; ++d)
@@ -1139,6 +1212,12 @@ Plan* build_plan(const ieti_patch* in, int n, const double* pv, int n_pv, const 
         if (opt.local_solver == IETI_LOCAL_MG) {
             cl.inv[MODE_N] = dense_inverse(pa, cl, MODE_N);
             cl.inv[MODE_D] = dense_inverse(pa, cl, MODE_D);
+        } else {
+            const Level& L0 = pa.lv[0];
+            pa.band_b = L0.guard;
+            pa.band_nblk = (L0.n + BAND_NB - 1) / BAND_NB;
+            band_factor(pa, L0, MODE_N, pa.band_b, pa.band[MODE_N]);
+            band_factor(pa, L0, MODE_D, pa.band_b, pa.band[MODE_D]);
         }
     });
     int64_t nq = 0;
@@ -1215,6 +1294,10 @@ int ieti_plan_array(const ieti_plan* plan, int32_t which, int32_t patch, int32_t
     }
     if (which == IETI_ARR_QP_WEIGHT) return emit(pa.qpw.data(), (int64_t)pa.qpw.size(), sizeof(double));
     if (which == IETI_ARR_PRIMAL_MAP) return emit(pa.primal_global.data(), (int64_t)pa.primal_global.size(), sizeof(int64_t));
+    if (which == IETI_ARR_BAND) {
+        if (level < 0 || level > 1 || pa.band[level].empty()) return IETI_EINVAL;
+        return emit(pa.band[level].data(), (int64_t)pa.band[level].size(), sizeof(double));
+    }
     int lev = which == IETI_ARR_PROLONG ? (level & 255) : level;
     if (lev < 0 || lev >= (int)pa.lv.size()) return IETI_EINVAL;
     const Level& L = pa.lv[lev];
@@ -1229,6 +1312,59 @@ int ieti_plan_array(const ieti_plan* plan, int32_t which, int32_t patch, int32_t
         return emit(L.P[d].data(), (int64_t)L.P[d].size(), sizeof(double));
     }
     default: return IETI_EINVAL;
+    }
+}
+
+int ieti_quadrature_points(const ieti_patch* patches, int32_t n, double* x, int64_t* n_qp) {
+    if (!patches || n <= 0) return IETI_EINVAL;
+    try {
+        const int dim = patches[0].dim;
+        int64_t o = 0;
+        for (int k = 0; k < n; ++k) {
+            validate_patch(patches[k], dim, k);
+            const ieti_patch& ip = patches[k];
+            std::vector<double> t[3];
+            int M[3] = {1, 1, 1};
+            DirTable dt[3];
+            for (int d = 0; d < dim; ++d) {
+                t[d].assign(ip.knots[d], ip.knots[d] + ip.n_knots[d]);
+                M[d] = ip.n_knots[d] - ip.degree[d] - 1;
+                dt[d] = make_dir(t[d], ip.degree[d], t[d], ip.degree[d]);
+            }
+            const int Q0 = dt[0].Q, Q1 = dt[1].Q, Q2 = dim == 3 ? dt[2].Q : 1;
+            const int pg2 = dim == 3 ? ip.degree[2] : 0;
+            if (x) {
+                for (int q2 = 0; q2 < Q2; ++q2)
+                    for (int q1 = 0; q1 < Q1; ++q1)
+                        for (int q0 = 0; q0 < Q0; ++q0) {
+                            const int qd[3] = {q0, q1, q2};
+                            double xx[3] = {0, 0, 0};
+                            for (int a2 = 0; a2 <= pg2; ++a2)
+                                for (int a1 = 0; a1 <= ip.degree[1]; ++a1)
+                                    for (int a0 = 0; a0 <= ip.degree[0]; ++a0) {
+                                        const int g0 = dt[0].gfirst[qd[0]] + a0, g1 = dt[1].gfirst[qd[1]] + a1;
+                                        const int g2 = dim == 3 ? dt[2].gfirst[qd[2]] + a2 : 0;
+                                        double bv = dt[0].G[(size_t)qd[0] * (ip.degree[0] + 1) + a0] *
+                                                    dt[1].G[(size_t)qd[1] * (ip.degree[1] + 1) + a1];
+                                        if (dim == 3) bv *= dt[2].G[(size_t)qd[2] * (ip.degree[2] + 1) + a2];
+                                        const int64_t i = lin(M, g0, g1, g2);
+                                        for (int c = 0; c < dim; ++c) xx[c] += ip.ctrl[i * dim + c] * bv;
+                                    }
+                            for (int c = 0; c < dim; ++c) x[o * dim + c] = xx[c];
+                            ++o;
+                        }
+            } else {
+                o += (int64_t)Q0 * Q1 * Q2;
+            }
+        }
+        if (n_qp) *n_qp = o;
+        return IETI_OK;
+    } catch (const Error& e) {
+        set_last_error(e.what());
+        return e.code;
+    } catch (const std::exception& e) {
+        set_last_error(e.what());
+        return IETI_EINVAL;
     }
 }
 

@@ -58,6 +58,10 @@ struct Patch {
     std::vector<double> qpN[3];    // level-0 space basis at the quadrature points, Q_d x (p_d+1)
     int64_t n_qp = 0;
     int64_t torn_off = 0;          // first coefficient in the torn layout
+    // exact local solves: banded Cholesky factor L of the masked stiffness (modes N, D) in
+    // 64-row blocks: per block row [L_off (64 x b) | U_off (64 x b) | inv(L_diag) (64 x 64)]
+    int64_t band_b = 0, band_nblk = 0;
+    std::vector<double> band[2];
     // local primal constraints: vertices (corner order) then edge averages (edge order)
     std::vector<int64_t> primal_global;
     std::vector<int> primal_corner;              // corner id, or -1 for an edge constraint
@@ -85,6 +89,8 @@ struct Plan {
     // global primal: contributors (patch, local constraint) per global primal, CSR
     std::vector<int64_t> pri_ptr, pri_patch, pri_local;
 };
+
+constexpr int BAND_NB = 64;   // row block of the blocked banded triangular solves
 
 Plan* build_plan(const ieti_patch* patches, int n, const double* primal_vertices, int n_pv,
                  const ieti_options* opt);

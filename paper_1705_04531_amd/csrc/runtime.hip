@@ -19,6 +19,11 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
 #include <cstring>
 #include <memory>
 #include <string>
@@ -269,6 +274,12 @@ struct Solver : SolverBase {
     double *lam = nullptr, *lr = nullptr, *lz = nullptr, *lp = nullptr, *lq = nullptr, *ltmp = nullptr;
     double* sc = nullptr;
     double* h_sc = nullptr;    // pinned
+    // exact local solves (banded Cholesky factors, blocked triangular solves)
+    bool exact = false;
+    int64_t* band_off = nullptr;
+    int32_t* band_b = nullptr;
+    double* band = nullptr;
+    size_t band_lds = 0;
     // fused coarse V-cycle: one work-group per patch for levels >= 1
     bool fused = false;
     int32_t* chain = nullptr;
@@ -536,6 +547,18 @@ struct Solver : SolverBase {
         hint = last_it;
     }
 
+    void band_solve(int mode, const double* rhs, double* x) {
+        hipLaunchKernelGGL(k_band_solve, dim3(N), dim3(BAND_THREADS), band_lds, stream, lev[0].L, band_off, band_b,
+                           band, mode, rhs, x, nullptr);
+        check_launch();
+    }
+
+    // fx = K_rr^{-1} b (b masked to mode N): exact or multigrid-preconditioned flexible CG
+    void local_solve(const double* b, double tol) {
+        if (exact) band_solve(MODE_N, b, fx);
+        else fcg(b, tol, plan->opt.inner_max_it);
+    }
+
     // ---------------------------------------------------------------- K~^{-1} g, primal part on the slots or on all rows
     // g: level-0 FP64 (local load-type vector); the FCG solves with m_N g.
     // full == false: only the interface slots of the result are corrected (F apply).
@@ -545,9 +568,9 @@ struct Solver : SolverBase {
             hipLaunchKernelGGL((k_convert<double, double>), dim3(tile_grid(D.nt_all)), dim3(TILE), 0, stream, D.L,
                                D.tiles_all, D.nt_all, g, e64, (int)MODE_N, 1.0);
             check_launch();
-            fcg(e64, tol, plan->opt.inner_max_it);
+            local_solve(e64, tol);
         } else {
-            fcg(g, tol, plan->opt.inner_max_it);
+            local_solve(g, tol);
         }
         if (npi > 0) {
             hipLaunchKernelGGL(k_pri_dots, dim3(N), dim3(TILE), 0, stream, N, npk, row_ptr, slot_dev,
@@ -603,8 +626,13 @@ struct Solver : SolverBase {
         scatter(r, true, w64);
         // b_I = -m_D (K v)
         stencil<double, double, T, EPI_APPLY>(0, false, MODE_D, coef64, w64, bT, nullptr, nullptr, nullptr, -1.0, 0);
-        vcycle(MODE_D, nullptr, bT, xIT);
-        for (int c = 1; c < plan->opt.prec_vcycles; ++c) {
+        if (exact) {
+            if (!std::is_same<T, double>::value) throw Error(IETI_EDEVICE, "internal: exact solves need FP64");
+            band_solve(MODE_D, (const double*)bT, (double*)xIT);
+        } else {
+            vcycle(MODE_D, nullptr, bT, xIT);
+        }
+        for (int c = 1; !exact && c < plan->opt.prec_vcycles; ++c) {
             stencil<T, T, T, EPI_RESID>(0, false, MODE_D, D.coefT, xIT, r2T, bT, nullptr, nullptr, 0.0, 0);
             vcycle(MODE_D, nullptr, r2T, x2T);
             hipLaunchKernelGGL(k_add<T>, dim3(tile_grid(D.nt_all)), dim3(TILE), 0, stream, D.L, D.tiles_all, D.nt_all,
@@ -878,6 +906,37 @@ void Solver<T>::setup() {
         }
         HIPCHECK(hipStreamSynchronize(st));
     }
+    // ---- exact local solves
+    if (pl.opt.local_solver == IETI_LOCAL_EXACT) {
+        exact = true;
+        int dev = 0, max_lds = 0;
+        HIPCHECK(hipGetDevice(&dev));
+        HIPCHECK(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+        std::vector<int64_t> offs(2 * (size_t)N);
+        std::vector<int32_t> bw(N);
+        int64_t tot = 0;
+        for (int k = 0; k < N; ++k) {
+            const Patch& pa = pl.patches[k];
+            bw[k] = (int32_t)pa.band_b;
+            for (int m = 0; m < 2; ++m) {
+                offs[2 * k + m] = tot;
+                tot += (int64_t)pa.band[m].size();
+            }
+            const size_t lds = sizeof(double) * (size_t)(2 * pa.band_b + pa.band_nblk * BNB + BNB);
+            band_lds = std::max(band_lds, lds);
+        }
+        if ((int64_t)band_lds > max_lds) throw Error(IETI_ENOTSUP, "patch too large for exact local solves in LDS");
+        band = arena.alloc<double>(tot, st, false);
+        for (int k = 0; k < N; ++k)
+            for (int m = 0; m < 2; ++m)
+                HIPCHECK(hipMemcpyAsync(band + offs[2 * k + m], pl.patches[k].band[m].data(),
+                                        pl.patches[k].band[m].size() * sizeof(double), hipMemcpyHostToDevice, st));
+        band_off = arena.upload(offs, st);
+        band_b = arena.upload(bw, st);
+        HIPCHECK(hipFuncSetAttribute((const void*)k_band_solve, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)band_lds));
+        HIPCHECK(hipStreamSynchronize(st));
+    }
     DevLevel& D0 = lev[0];
     len0 = D0.len;
     for (double** p : {&f64, &b64, &e64, &w64, &s64, &u64, &fx, &fr, &fd, &fq}) *p = arena.alloc<double>(len0, st);
@@ -1058,7 +1117,7 @@ void Solver<T>::setup() {
                                                        -1.0, 0);
             hipLaunchKernelGGL(k_edge_rhs, dim3(N), dim3(256), 0, st, N, edge_ptr, edge_dev, j, b64);
             check_launch();
-            fcg(b64, pl.opt.basis_tol, pl.opt.inner_max_it);
+            local_solve(b64, pl.opt.basis_tol);
             HIPCHECK(hipMemcpyAsync(Y + (size_t)j * len0, fx, sizeof(double) * len0, hipMemcpyDeviceToDevice, st));
         }
         // edge means of the raw columns -> combination coefficients (host, tiny dense algebra)
@@ -1345,28 +1404,60 @@ static int guarded(F&& f) {
 
 extern "C" {
 
+}  // extern "C"
+
+// A handle around a plan: device state built on the plan's stream (or a new one).
+static ieti_handle* make_handle(std::unique_ptr<Plan> plan) {
+    if (plan->opt.device >= 0) HIPCHECK(hipSetDevice(plan->opt.device));
+    std::unique_ptr<SolverBase> s;
+    if (plan->opt.mg_precision == 32 && plan->opt.local_solver == IETI_LOCAL_MG) s.reset(new Solver<float>());
+    else s.reset(new Solver<double>());
+    s->plan = std::move(plan);
+    if (s->plan->opt.stream) {
+        s->stream = (hipStream_t)s->plan->opt.stream;
+    } else {
+        HIPCHECK(hipStreamCreate(&s->stream));
+        s->own_stream = true;
+    }
+    s->setup();
+    auto* h = new ieti_handle();
+    h->s = std::move(s);
+    return h;
+}
+
+// Device bytes a handle built from this plan will hold (upper estimate used for
+// admission; mirrors the allocations of Solver::setup with a margin).
+static size_t estimate_device_bytes(const Plan& pl) {
+    const bool exact = pl.opt.local_solver == IETI_LOCAL_EXACT;
+    const double T = (pl.opt.mg_precision == 32 && !exact) ? 4.0 : 8.0;
+    double b = 0.0;
+    int npk = 0;
+    for (const Patch& pa : pl.patches) {
+        npk = std::max(npk, (int)pa.primal_global.size());
+        for (size_t l = 0; l < pa.lv.size(); ++l) {
+            const Level& L = pa.lv[l];
+            const double len = (double)(L.n + 2 * L.guard + 64);
+            b += L.nst * len * T + 5.0 * len * T;                      // operator data, MG vectors
+            if (l == 0) b += (T == 4.0 ? L.nst * len * 8.0 : 0.0) + 10.0 * len * 8.0 + 6.0 * len * T;
+            if (!L.inv[0].empty()) b += 2.0 * L.n * L.n * T;
+        }
+        b += 2.0 * npk * (double)(pa.lv[0].n + 2 * pa.lv[0].guard + 64) * 8.0;   // Psi + setup scratch
+        b += (double)(pa.band[0].size() + pa.band[1].size()) * 8.0;
+        b += (double)pa.n_qp * (16.0 + 8.0 * pa.dim);
+    }
+    b += (double)pl.n_lambda * 8.0 * 8.0 + (double)pl.n_primal * pl.n_primal * 8.0;
+    return (size_t)(1.15 * b) + (16u << 20);
+}
+
+extern "C" {
+
 int ieti_setup(const ieti_patch* patches, int32_t n_patches, const double* primal_vertices, int32_t n_primal_vertices,
                const ieti_options* opt, ieti_handle** out) {
     if (!out) return IETI_EINVAL;
     *out = nullptr;
     return guarded([&] {
         std::unique_ptr<Plan> plan(build_plan(patches, n_patches, primal_vertices, n_primal_vertices, opt));
-        if (plan->opt.local_solver != IETI_LOCAL_MG) throw Error(IETI_ENOTSUP, "exact local solves are not built");
-        if (plan->opt.device >= 0) HIPCHECK(hipSetDevice(plan->opt.device));
-        std::unique_ptr<SolverBase> s;
-        if (plan->opt.mg_precision == 32) s.reset(new Solver<float>());
-        else s.reset(new Solver<double>());
-        s->plan = std::move(plan);
-        if (s->plan->opt.stream) {
-            s->stream = (hipStream_t)s->plan->opt.stream;
-        } else {
-            HIPCHECK(hipStreamCreate(&s->stream));
-            s->own_stream = true;
-        }
-        s->setup();
-        auto* h = new ieti_handle();
-        h->s = std::move(s);
-        *out = h;
+        *out = make_handle(std::move(plan));
         return IETI_OK;
     });
 }
@@ -1439,6 +1530,7 @@ const char* ieti_strerror(int code) {
     case IETI_ENOCONV: return "no convergence";
     case IETI_EDEVICE: return "device error";
     case IETI_ENOTSUP: return "not supported";
+    case IETI_PENDING: return "pending";
     default: return "unknown error";
     }
 }
@@ -1446,3 +1538,212 @@ const char* ieti_strerror(int code) {
 const char* ieti_last_error(void) { return ieti::last_error(); }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------ serving
+
+// One request: deep copies of its patches and f, the caller's output buffer.
+struct SrvReq {
+    int64_t ticket = 0;
+    std::vector<std::vector<double>> knots, ctrl;
+    std::vector<ieti_patch> patches;
+    std::vector<double> f;
+    double* u_out = nullptr;
+    int status = IETI_PENDING;
+    ieti_stats st{};
+    double t_submit = 0, t_admit = 0, t_done = 0;
+};
+
+struct ieti_server {
+    ieti_options opt{};
+    int slots = 1;
+    size_t budget = 0;      // 0: unlimited
+    size_t in_use = 0;
+    int device = 0;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_mem, cv_done;
+    std::deque<SrvReq*> queue;
+    std::map<int64_t, std::unique_ptr<SrvReq>> reqs;
+    int64_t next = 1;
+    bool stop = false;
+    int running = 0;
+    std::vector<std::thread> workers;
+    std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+    double now_ms() const {
+        return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+};
+
+// A worker owns one stream.  It takes the oldest waiting request, plans it on
+// the host, waits until the HBM budget admits the request's estimated device
+// footprint, builds the device state, solves, copies u to the caller and
+// frees everything.  Admitted requests of different workers overlap on the GPU.
+static void server_worker(ieti_server* S) {
+    (void)hipSetDevice(S->device);
+    hipStream_t st = nullptr;
+    if (hipStreamCreate(&st) != hipSuccess) return;
+    for (;;) {
+        SrvReq* r = nullptr;
+        {
+            std::unique_lock<std::mutex> lk(S->mu);
+            S->cv_work.wait(lk, [&] { return S->stop || !S->queue.empty(); });
+            if (S->queue.empty()) break;
+            r = S->queue.front();
+            S->queue.pop_front();
+            ++S->running;
+        }
+        size_t bytes = 0;
+        bool admitted = false;
+        int rc = IETI_OK;
+        double* fd = nullptr;
+        double* ud = nullptr;
+        ieti_handle* h = nullptr;
+        try {
+            ieti_options o = S->opt;
+            o.stream = st;
+            o.hbm_budget = 0;
+            o.device = S->device;
+            std::unique_ptr<Plan> plan(build_plan(r->patches.data(), (int)r->patches.size(), nullptr, 0, &o));
+            if ((int64_t)r->f.size() != plan->n_qp) throw Error(IETI_EINVAL, "f has the wrong number of values");
+            bytes = estimate_device_bytes(*plan) + (size_t)(plan->n_qp + plan->ndof_torn) * sizeof(double);
+            {
+                std::unique_lock<std::mutex> lk(S->mu);
+                if (S->budget && bytes > S->budget) throw Error(IETI_ENOMEM, "request larger than the HBM budget");
+                S->cv_mem.wait(lk, [&] { return !S->budget || S->in_use + bytes <= S->budget; });
+                S->in_use += bytes;
+                admitted = true;
+                r->t_admit = S->now_ms();
+            }
+            const int64_t nq = plan->n_qp, nt = plan->ndof_torn;
+            h = make_handle(std::move(plan));
+            HIPCHECK(hipMalloc((void**)&fd, sizeof(double) * nq));
+            HIPCHECK(hipMalloc((void**)&ud, sizeof(double) * nt));
+            HIPCHECK(hipMemcpyAsync(fd, r->f.data(), sizeof(double) * nq, hipMemcpyHostToDevice, st));
+            rc = h->s->solve(fd, ud, &r->st);
+            HIPCHECK(hipMemcpyAsync(r->u_out, ud, sizeof(double) * nt, hipMemcpyDeviceToHost, st));
+            HIPCHECK(hipStreamSynchronize(st));
+        } catch (const Error& e) {
+            rc = e.code;
+            set_last_error(e.what());
+        } catch (const std::exception& e) {
+            rc = IETI_EINVAL;
+            set_last_error(e.what());
+        }
+        if (h) ieti_destroy(h);
+        if (fd) (void)hipFree(fd);
+        if (ud) (void)hipFree(ud);
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            if (admitted) S->in_use -= bytes;
+            r->t_done = S->now_ms();
+            r->status = rc;
+            --S->running;
+        }
+        S->cv_mem.notify_all();
+        S->cv_done.notify_all();
+    }
+    (void)hipStreamDestroy(st);
+}
+
+extern "C" {
+
+int ieti_plan_device_bytes(const ieti_plan* plan, size_t* bytes) {
+    if (!plan || !bytes) return IETI_EINVAL;
+    const Plan& pl = *reinterpret_cast<const Plan*>(plan);
+    *bytes = estimate_device_bytes(pl) + (size_t)(pl.n_qp + pl.ndof_torn) * sizeof(double);
+    return IETI_OK;
+}
+
+int ieti_server_create(const ieti_options* opt, int32_t max_slots, ieti_server** out) {
+    if (!out || max_slots < 1 || max_slots > 16) return IETI_EINVAL;
+    *out = nullptr;
+    return guarded([&] {
+        auto* S = new ieti_server();
+        if (opt) S->opt = *opt; else default_options(&S->opt);
+        S->slots = max_slots;
+        S->budget = S->opt.hbm_budget;
+        int dev = S->opt.device;
+        if (dev < 0) HIPCHECK(hipGetDevice(&dev));
+        S->device = dev;
+        for (int i = 0; i < max_slots; ++i) S->workers.emplace_back(server_worker, S);
+        *out = S;
+        return IETI_OK;
+    });
+}
+
+int ieti_server_submit(ieti_server* S, const ieti_patch* patches, int32_t n_patches, const double* f_qp,
+                       int64_t n_qp, double* u, int64_t* ticket) {
+    if (!S || !patches || n_patches <= 0 || !f_qp || n_qp <= 0 || !u || !ticket) return IETI_EINVAL;
+    return guarded([&] {
+        auto r = std::make_unique<SrvReq>();
+        for (int k = 0; k < n_patches; ++k) {
+            ieti_patch p = patches[k];
+            if (p.dim != 2 && p.dim != 3) throw Error(IETI_EINVAL, "dim must be 2 or 3");
+            int64_t nc = 1;
+            for (int d = 0; d < p.dim; ++d) {
+                if (!p.knots[d] || p.n_knots[d] <= 2 * p.degree[d] + 1) throw Error(IETI_EINVAL, "bad knot vector");
+                r->knots.emplace_back(p.knots[d], p.knots[d] + p.n_knots[d]);
+                nc *= p.n_knots[d] - p.degree[d] - 1;
+            }
+            r->ctrl.emplace_back(p.ctrl, p.ctrl + nc * p.dim);
+            r->patches.push_back(p);
+        }
+        size_t kk = 0;
+        for (int k = 0; k < n_patches; ++k) {
+            ieti_patch& p = r->patches[k];
+            for (int d = 0; d < p.dim; ++d) p.knots[d] = r->knots[kk++].data();
+            p.ctrl = r->ctrl[k].data();
+        }
+        r->f.assign(f_qp, f_qp + n_qp);
+        r->u_out = u;
+        std::lock_guard<std::mutex> lk(S->mu);
+        r->ticket = S->next++;
+        r->t_submit = S->now_ms();
+        *ticket = r->ticket;
+        S->queue.push_back(r.get());
+        S->reqs[r->ticket] = std::move(r);
+        S->cv_work.notify_one();
+        return IETI_OK;
+    });
+}
+
+int ieti_server_poll(ieti_server* S, int64_t ticket, int32_t wait, ieti_stats* st, double* times_ms) {
+    if (!S) return IETI_EINVAL;
+    std::unique_lock<std::mutex> lk(S->mu);
+    auto it = S->reqs.find(ticket);
+    if (it == S->reqs.end()) return IETI_EINVAL;
+    SrvReq* r = it->second.get();
+    if (wait) S->cv_done.wait(lk, [&] { return r->status != IETI_PENDING; });
+    if (r->status == IETI_PENDING) return IETI_PENDING;
+    if (st) *st = r->st;
+    if (times_ms) {
+        times_ms[0] = r->t_submit;
+        times_ms[1] = r->t_admit;
+        times_ms[2] = r->t_done;
+    }
+    const int rc = r->status;
+    S->reqs.erase(it);
+    return rc;
+}
+
+int ieti_server_load(ieti_server* S, int32_t* queued, int32_t* running, size_t* bytes_in_use) {
+    if (!S) return IETI_EINVAL;
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (queued) *queued = (int32_t)S->queue.size();
+    if (running) *running = S->running;
+    if (bytes_in_use) *bytes_in_use = S->in_use;
+    return IETI_OK;
+}
+
+void ieti_server_destroy(ieti_server* S) {
+    if (!S) return;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->stop = true;
+    }
+    S->cv_work.notify_all();
+    for (auto& t : S->workers) t.join();
+    delete S;
+}
+
+}  // extern "C"
+

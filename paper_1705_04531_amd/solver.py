@@ -102,6 +102,12 @@ class Plan:
               "ieti_plan_array")
         return out
 
+    def device_bytes(self) -> int:
+        """Device bytes a serving slot reserves for a request with this plan."""
+        b = C.c_size_t()
+        check(lib().ieti_plan_device_bytes(self.h, C.byref(b)), "ieti_plan_device_bytes")
+        return int(b.value)
+
     def quadrature(self) -> np.ndarray:
         n = self.sizes()["n_qp"]
         x = np.empty((n, self.dim), dtype=np.float64)
@@ -170,3 +176,63 @@ class Solver:
         if rc != _abi.IETI_OK and not (rc == _abi.IETI_ENOCONV and not raise_on_noconv):
             check(rc, "ieti_solve")
         return u, st.as_dict()
+
+
+def quadrature_points(patches: Sequence) -> np.ndarray:
+    """Physical quadrature points of a set of patches (host, no planning)."""
+    pa = _PatchArray(patches)
+    n = C.c_int64()
+    check(lib().ieti_quadrature_points(pa.arr, len(pa), None, C.byref(n)), "ieti_quadrature_points")
+    x = np.empty((n.value, patches[0].dim), dtype=np.float64)
+    check(lib().ieti_quadrature_points(pa.arr, len(pa), x.ctypes.data_as(C.POINTER(C.c_double)), C.byref(n)),
+          "ieti_quadrature_points")
+    return x
+
+
+class Server:
+    """Request loop: independent solves admitted by free slots and HBM budget, overlapping on the device."""
+
+    def __init__(self, options: IetiOptions | None = None, slots: int = 4):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the IETI-DP server runs only on the device")
+        torch.cuda.init()
+        opt = options if options is not None else default_options()
+        h = C.c_void_p()
+        check(lib().ieti_server_create(C.byref(opt), slots, C.byref(h)), "ieti_server_create")
+        self.h = h
+        self._live = {}
+
+    def submit(self, patches: Sequence, f_qp: np.ndarray) -> int:
+        pa = _PatchArray(patches)
+        f = np.ascontiguousarray(f_qp, dtype=np.float64)
+        nt = sum(int(np.prod([len(k) - d - 1 for k, d in zip(p.knots, p.degree)])) for p in patches)
+        u = np.empty(nt, dtype=np.float64)
+        t = C.c_int64()
+        check(lib().ieti_server_submit(self.h, pa.arr, len(pa), f.ctypes.data_as(C.POINTER(C.c_double)), f.size,
+                                       u.ctypes.data_as(C.POINTER(C.c_double)), C.byref(t)), "ieti_server_submit")
+        self._live[t.value] = u
+        return t.value
+
+    def poll(self, ticket: int, wait: bool = False):
+        """None while pending, else (status, u, stats, (t_submit, t_admit, t_done) in ms)."""
+        st = IetiStats()
+        times = (C.c_double * 3)()
+        rc = lib().ieti_server_poll(self.h, ticket, 1 if wait else 0, C.byref(st), times)
+        if rc == _abi.IETI_PENDING:
+            return None
+        u = self._live.pop(ticket)
+        return rc, u, st.as_dict(), tuple(times)
+
+    def load(self):
+        q, r, b = C.c_int32(), C.c_int32(), C.c_size_t()
+        check(lib().ieti_server_load(self.h, C.byref(q), C.byref(r), C.byref(b)), "ieti_server_load")
+        return int(q.value), int(r.value), int(b.value)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().ieti_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()

@@ -113,3 +113,53 @@ def test_plan_errors(lib):
     with pytest.raises(_abi.IetiError) as e:
         Plan(wl.patches, default_options(mg_precision=16))
     assert e.value.code == _abi.IETI_EINVAL
+
+
+def _mask_from_bits(shape, sides, corners, mode):
+    dim = len(shape)
+    idx = np.stack(np.meshgrid(*[np.arange(m) for m in shape], indexing="ij"), -1).reshape(-1, dim, order="F")
+    m = np.zeros(len(idx), dtype=bool)
+    sb = sides if mode == 0 else (0x3F if dim == 3 else 0xF)
+    for d in range(dim):
+        m |= (idx[:, d] == 0) & bool(sb >> (2 * d) & 1)
+        m |= (idx[:, d] == shape[d] - 1) & bool(sb >> (2 * d + 1) & 1)
+    if mode == 0:
+        corner = np.all((idx == 0) | (idx == np.array(shape) - 1), axis=1)
+        cb = sum(((idx[:, d] == shape[d] - 1).astype(int) << d) for d in range(dim))
+        m |= corner & ((corners >> cb) & 1).astype(bool)
+    return m
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_band_cholesky_factor(lib, mode):
+    """The blocked banded Cholesky data of the exact local solver reproduce the
+    masked patch stiffness (oracle assembly): L L^T = K with masked rows and
+    columns replaced by the identity."""
+    wl = W.deformed_square((2, 2), 3, 6, seed=0)
+    pl = Plan(wl.patches, default_options(local_solver=_abi.IETI_LOCAL_EXACT))
+    nb = 64
+    for k in (0, 3):
+        p = wl.patches[k]
+        shape = p.shape
+        n = int(np.prod(shape))
+        b = p.degree[0] + p.degree[1] * shape[0]
+        data = pl.array(_abi.IETI_ARR_BAND, k, mode)
+        nblk = (n + nb - 1) // nb
+        bs = nb * (2 * b + nb)
+        assert data.size == nblk * bs
+        L = np.zeros((nblk * nb, nblk * nb + b))   # columns shifted by b
+        for r in range(nblk):
+            blk = data[r * bs:(r + 1) * bs]
+            Loff = blk[:nb * b].reshape(nb, b)
+            Linv = blk[2 * nb * b:].reshape(nb, nb)
+            L[r * nb:(r + 1) * nb, r * nb:r * nb + b] = Loff          # columns r*nb - b .. r*nb - 1
+            L[r * nb:(r + 1) * nb, b + r * nb:b + (r + 1) * nb] = np.linalg.inv(Linv)
+        Ld = L[:n, b:b + n]
+        K = assembly.assemble_patch(p).K.toarray()
+        bits = pl.array(_abi.IETI_ARR_MASKS, k, 0, dtype=np.int32)
+        m = _mask_from_bits(shape, int(bits[0]), int(bits[1]), mode)
+        A = K.copy()
+        A[m, :] = 0.0
+        A[:, m] = 0.0
+        A[m, m] = 1.0
+        assert np.abs(Ld @ Ld.T - A).max() <= 1e-12 * np.abs(A).max()

@@ -1,0 +1,33 @@
+"""Full-size parity in the benchmark's launch configuration: the GPU solution of
+the 8x8-patch, p=3, 64^2 workload against the oracle's global direct solution,
+sampled at 2000 seeded coefficients (tests/golden/make_golden.py)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_util import run_gpu, split_torn
+from oracle import conforming
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.mark.parametrize("name", ["deformed8x8_p3_n64", "deformed16x16_mixed"])
+def test_full_config_against_oracle_samples(require_gpu, name):
+    path = os.path.join(HERE, "golden", f"full_{name}.json")
+    if not os.path.exists(path):
+        pytest.skip(f"golden file for {name} not generated")
+    g = json.load(open(path))
+    wl = W.CONFIGS[name]()
+    u, st = run_gpu(wl)                       # same options as the benchmark (tol 1e-8)
+    lay = conforming.layout(wl)
+    ug = conforming.global_from_torn(lay, split_torn(wl, u))
+    idx = np.array(g["indices"])
+    ref = np.array(g["values"])
+    err = np.linalg.norm(ug[idx] - ref) / np.linalg.norm(ref)
+    nrm = abs(np.linalg.norm(ug) - g["norm2"]) / g["norm2"]
+    print(f"{name}: sampled rel err {err:.3e}, norm rel diff {nrm:.3e}, outer {st['outer_iterations']}", flush=True)
+    assert err <= 1e-8 and nrm <= 1e-8

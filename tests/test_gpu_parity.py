@@ -58,3 +58,24 @@ def test_config_tolerance(require_gpu, name, make):
     err = rel_err(wl, u, u_ref, lay)
     print(f"{name} tol=1e-8: err={err:.3e} outer={st['outer_iterations']}", flush=True)
     assert err <= 2e-8
+
+
+EXACT_CASES = [
+    ("square2x2_p2_n16", lambda: W.square_2x2()),
+    ("square2x2_sine_exact", lambda: with_sine_rhs(W.deformed_square((2, 2), 2, 16, name="square2x2_sine"))),
+    ("deformed3x3_mixed_edges", CASES_2D[3][1]),
+    ("deformed4x4_p3_n24", CASES_2D[2][1]),
+]
+
+
+@pytest.mark.parametrize("name,make", EXACT_CASES, ids=[c[0] for c in EXACT_CASES])
+def test_exact_local_matches_oracle(require_gpu, name, make):
+    """Exact local solves (banded Cholesky, the D-D form) reproduce the oracle."""
+    from paper_1705_04531_amd import _abi
+    wl = make()
+    u_ref, lay, _ = oracle_solution(wl)
+    u, st = run_gpu(wl, local_solver=_abi.IETI_LOCAL_EXACT, tol=1e-10)
+    err = rel_err(wl, u, u_ref, lay)
+    print(f"{name} exact: err={err:.3e} outer={st['outer_iterations']} breakdown={st['breakdown']}", flush=True)
+    assert err <= 1e-9
+    assert st["inner_iterations_mean"] == 0
