@@ -81,6 +81,11 @@ typedef struct ieti_options {
     int32_t device;            /* HIP device ordinal, -1 = current (default) */
     void*   stream;            /* hipStream_t for all work, NULL = the library's own stream */
     size_t  hbm_budget;        /* bytes of device memory the handle may use, 0 = unlimited */
+    int32_t coarse_level;      /* first multigrid level run by the per-patch fused coarse kernel: 0 = chosen
+                                  from the LDS size (default), -1 = none (every level by batched launches) */
+    int32_t coarse_dofs;       /* multigrid: a patch level with at most this many coefficients is not
+                                  coarsened further (dense exact solve there); 0 = no such limit. Coarsening
+                                  also stops where a direction's element count is odd or below 6 (default 600) */
 } ieti_options;
 
 typedef struct ieti_stats {

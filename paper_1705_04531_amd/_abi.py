@@ -66,6 +66,8 @@ class IetiOptions(C.Structure):
         ("device", C.c_int32),
         ("stream", C.c_void_p),
         ("hbm_budget", C.c_size_t),
+        ("coarse_level", C.c_int32),
+        ("coarse_dofs", C.c_int32),
     ]
 
 

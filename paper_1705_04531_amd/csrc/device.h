@@ -18,6 +18,23 @@ inline int degree_class(int dim, int p0, int p1, int p2) {
     return NCLASS;
 }
 
+// Calls L(P0, P1, P2) with the compile-time degrees of class cls (-1: generic).
+#define IETI_CLASS_SWITCH(cls, L)                \
+    switch (cls) {                               \
+    case 0: L(2, 2, 0); break;                   \
+    case 1: L(3, 2, 0); break;                   \
+    case 2: L(4, 2, 0); break;                   \
+    case 3: L(2, 3, 0); break;                   \
+    case 4: L(3, 3, 0); break;                   \
+    case 5: L(4, 3, 0); break;                   \
+    case 6: L(2, 4, 0); break;                   \
+    case 7: L(3, 4, 0); break;                   \
+    case 8: L(4, 4, 0); break;                   \
+    case 9: L(2, 2, 2); break;                   \
+    case 10: L(3, 3, 3); break;                  \
+    default: L(-1, -1, -1); break;               \
+    }
+
 // One patch at one multigrid level.
 struct PatchLev {
     int32_t M[3];          // basis functions per direction (1 in unused directions)

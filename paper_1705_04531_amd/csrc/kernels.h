@@ -78,6 +78,50 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* lds) {
     __syncthreads();
 }
 
+// dst[j] = src[j], j < n, by the whole work-group with U loads per thread in
+// flight before the first store (a plain copy loop waits out one memory
+// latency per element and thread).
+template <int U, typename T>
+__device__ __forceinline__ void group_copy(T* dst, const T* __restrict__ src, int n) {
+    const int nt = blockDim.x;
+    for (int base = threadIdx.x; base < n; base += U * nt) {
+        T v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int j = base + u * nt;
+            if (j < n) v[u] = src[j];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int j = base + u * nt;
+            if (j < n) dst[j] = v[u];
+        }
+    }
+}
+
+// As group_copy for ne rows of w elements, row e from src + e * sstride to
+// dst + e * w.
+template <int U, typename T>
+__device__ __forceinline__ void group_copy_rows(T* dst, const T* __restrict__ src, int ne, int w, int64_t sstride) {
+    const int nt = blockDim.x, n = ne * w;
+    for (int base = threadIdx.x; base < n; base += U * nt) {
+        T v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int j = base + u * nt;
+            if (j < n) {
+                const int e = j / w;
+                v[u] = src[(int64_t)e * sstride + (j - e * w)];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int j = base + u * nt;
+            if (j < n) dst[j] = v[u];
+        }
+    }
+}
+
 // ------------------------------------------------------------------ degree classes
 //
 // Loops over stencil offsets and transfer bands are unrolled for the common
@@ -126,6 +170,45 @@ __device__ __forceinline__ TC stencil_sum(const TC* __restrict__ c, const TX* __
                         acc += cu * TC(xp[off]) + c[s * cs - off] * TC(xp[-off]);
                     }
                 }
+            }
+    }
+    return acc;
+}
+
+// As stencil_sum for 3D classes, one o2-plane of the stencil per loop trip
+// (the plane's offsets unrolled): bounds the registers of a 125-point
+// stencil while keeping a plane's loads in flight together.
+template <int P0, int P1, int P2, typename TC, typename TX>
+__device__ __forceinline__ TC stencil_sum_planes(const TC* __restrict__ c, const TX* __restrict__ xp, int cs, int M0,
+                                                 int M01, TC& diag) {
+    TC acc = TC(0);
+    int s = 0;
+#pragma unroll
+    for (int o1 = 0; o1 <= P1; ++o1)
+#pragma unroll
+        for (int o0 = (o1 == 0 ? 0 : -P0); o0 <= P0; ++o0) {
+            const int off = o0 + o1 * M0;
+            const TC cu = c[s * cs];
+            if (s == 0) {
+                diag = cu;
+                acc += cu * TC(xp[0]);
+            } else {
+                acc += cu * TC(xp[off]) + c[s * cs - off] * TC(xp[-off]);
+            }
+            ++s;
+        }
+    constexpr int PLANE = (2 * P1 + 1) * (2 * P0 + 1);
+#pragma unroll 1
+    for (int o2 = 1; o2 <= P2; ++o2) {
+        const TC* cp = c + (s + (o2 - 1) * PLANE) * cs;
+        const int zo = o2 * M01;
+#pragma unroll
+        for (int o1 = -P1; o1 <= P1; ++o1)
+#pragma unroll
+            for (int o0 = -P0; o0 <= P0; ++o0) {
+                const int off = zo + o1 * M0 + o0;
+                const int sj = (o1 + P1) * (2 * P0 + 1) + (o0 + P0);
+                acc += cp[sj * cs] * TC(xp[off]) + cp[sj * cs - off] * TC(xp[-off]);
             }
     }
     return acc;
@@ -242,9 +325,25 @@ struct StencilArgs {
 // i-o (symmetry) for the lower half of the stencil.  FINE marks launches on
 // the finest level (the bandwidth-bound sweeps) so that profilers report
 // them apart from the latency-bound coarse-level launches.
+// Finest-level sweeps stage the tile's x window [start - reach, start + TILE
+// + reach), reach = p2 M0 M1 + p1 M0 + p0 (the guard length), in LDS: each x
+// value then passes the vector memory pipeline once per tile instead of once
+// per stencil entry.  The window is clipped to the patch block and its
+// guards, so the loads stay inside the vector.  Launches of these instances
+// must supply (TILE + 2 reach) elements of dynamic LDS; the host uses the
+// FINE = false instance where that is too large.  2D issues every
+// coefficient load before the window barrier; 3D (125-point stencils) keeps
+// the compiler's interleaving of loads and FMAs (registers).
+template <int P0, int P2, bool FINE>
+__host__ __device__ constexpr bool stencil_stages_x() {
+    return FINE && P0 >= 0;
+}
+
 template <int P0, int P1, int P2, typename TC, typename TX, typename TY, int EPI, bool FINE>
 __global__ __launch_bounds__(TILE) void k_stencil(StencilArgs a) {
     __shared__ double lds[2 * TILE / WAVE];
+    extern __shared__ unsigned char st_lds_raw[];
+    constexpr bool STAGE = stencil_stages_x<P0, P2, FINE>();
     const int t = tile_index(a.ntiles);
     if (t < 0) return;
     const Tile tl = a.tiles[t];
@@ -256,17 +355,73 @@ __global__ __launch_bounds__(TILE) void k_stencil(StencilArgs a) {
     const TX* __restrict__ x = (const TX*)a.x;
     TY* __restrict__ y = (TY*)a.y;
     double dv0 = 0.0, dv1 = 0.0;
-    if (i < n) {
-        const int M0 = P.M[0], M1 = P.M[1], M01 = M0 * M1;
+    const int M0 = P.M[0], M1 = P.M[1], M01 = M0 * M1;
+    const bool live = i < n;
+    bool m = true;
+    if (live) {
         const int i2 = i / M01, r = i - i2 * M01, i1 = r / M0, i0 = r - i1 * M0;
-        const bool m = masked_bits(P.mbits[a.mode], P.dim, M0, M1, P.M[2], i0, i1, i2);
-        const int64_t vi = P.voff + i;
-        TC acc = TC(0), diag = TC(1);
+        m = masked_bits(P.mbits[a.mode], P.dim, M0, M1, P.M[2], i0, i1, i2);
+    }
+    const int64_t vi = P.voff + i;
+    TC acc = TC(0), diag = TC(1);
+    TX xi = TX(0);
+    if constexpr (STAGE && P2 > 0) {
+        const int reach = P2 * M01 + P1 * M0 + P0;
+        TX* win = (TX*)st_lds_raw;
+        const int w_len = min(tl.start + TILE, n) + 2 * reach - tl.start;   // clipped to the patch and its guards
+        group_copy<4>(win, x + P.voff + tl.start - reach, w_len);
+        __syncthreads();
+        const TX* xw = win + reach + (int)threadIdx.x;
+        if (live) xi = xw[0];
+        if (!m) acc = stencil_sum_planes<P0, P1, P2>(coef + P.coff + i, xw, (int)P.cstride, M0, M01, diag);
+    } else if constexpr (STAGE) {
+        // every coefficient load is issued before the window barrier
+        constexpr int NH = (P0 + 1) + P1 * (2 * P0 + 1);
+        TC cu[NH], cw[NH];
+        const TC* c = coef + P.coff + i;
+        const int cs = (int)P.cstride;
         if (!m) {
-            const TC* c = coef + P.coff + i;
-            const TX* xp = x + vi;
-            acc = stencil_sum<P0, P1, P2>(c, xp, (int)P.cstride, M0, M01, P.p[0], P.p[1], P.p[2], diag);
+            int s = 0;
+#pragma unroll
+            for (int o1 = 0; o1 <= P1; ++o1)
+#pragma unroll
+                for (int o0 = (o1 == 0 ? 0 : -P0); o0 <= P0; ++o0) {
+                    cu[s] = c[s * cs];
+                    cw[s] = s == 0 ? TC(0) : c[s * cs - (o0 + o1 * M0)];
+                    ++s;
+                }
         }
+        const int reach = P1 * M0 + P0;
+        TX* win = (TX*)st_lds_raw;
+        const int w_len = min(tl.start + TILE, n) + 2 * reach - tl.start;   // clipped to the patch and its guards
+        group_copy<4>(win, x + P.voff + tl.start - reach, w_len);
+        __syncthreads();
+        const TX* xw = win + reach + (int)threadIdx.x;
+        if (live) xi = xw[0];
+        if (!m) {
+            diag = cu[0];
+            acc += cu[0] * TC(xi);
+            int s = 1;
+#pragma unroll
+            for (int o1 = 0; o1 <= P1; ++o1)
+#pragma unroll
+                for (int o0 = (o1 == 0 ? 1 : -P0); o0 <= P0; ++o0) {
+                    const int off = o0 + o1 * M0;
+                    acc += cu[s] * TC(xw[off]) + cw[s] * TC(xw[-off]);
+                    ++s;
+                }
+        }
+    } else {
+        if (live) xi = x[vi];
+        if constexpr (P0 >= 0 && P2 > 0) {
+            if (!m) acc = stencil_sum_planes<P0, P1, P2>(coef + P.coff + i, x + vi, (int)P.cstride, M0, M01, diag);
+        } else {
+            if (!m)
+                acc = stencil_sum<P0, P1, P2>(coef + P.coff + i, x + vi, (int)P.cstride, M0, M01, P.p[0], P.p[1],
+                                              P.p[2], diag);
+        }
+    }
+    if (live) {
         if constexpr (EPI == EPI_APPLY) {
             y[vi] = m ? TY(0) : TY(a.alpha * (double)acc);
         } else if constexpr (EPI == EPI_RESID) {
@@ -284,14 +439,14 @@ __global__ __launch_bounds__(TILE) void k_stencil(StencilArgs a) {
                 const TC rr = TC(b[vi]) - acc;
                 const TC dn = (a.cheb_k > 0 ? s1 * TC(d[vi]) : TC(0)) + s2 * rr / diag;
                 d[vi] = TY(dn);
-                const TY yn = TY(TC(x[vi]) + dn);
+                const TY yn = TY(TC(xi) + dn);
                 y[vi] = yn;
                 if (a.dotq) dv0 = (double)yn * a.dotq[vi];
             }
         } else if constexpr (EPI == EPI_DOTS) {
             const double q = m ? 0.0 : (double)acc;
             y[vi] = TY(q);
-            const double xv = (double)x[vi];
+            const double xv = (double)xi;
             dv0 = xv * q;
             dv1 = xv * a.r64[vi];
         }
@@ -403,8 +558,30 @@ __global__ __launch_bounds__(TILE) void k_prolong(const PatchLev* Lf, const Patc
     xf[vi] = T((double)xf[vi] + acc);
 }
 
-// Coarsest level: x = A^{-1} b with the stored dense inverse; one work-group per
-// patch, one wave per row, lanes over the columns.
+// y = A b for a dense n x n matrix stored by columns (entry (r, j) at
+// At[j * n + r]): one thread per row, so that every column load is
+// contiguous across the lanes; the column loop is unrolled to keep many
+// loads in flight.  Accumulates in double.
+template <typename T, typename TB, typename TY>
+__device__ __forceinline__ void col_gemv(const T* __restrict__ At, int n, const TB* b, TY* y) {
+    constexpr int U = 16;
+    for (int r = threadIdx.x; r < n; r += blockDim.x) {
+        double acc = 0.0;
+        int j = 0;
+        for (; j + U <= n; j += U) {
+            T a[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) a[u] = At[(int64_t)(j + u) * n + r];
+#pragma unroll
+            for (int u = 0; u < U; ++u) acc += (double)a[u] * (double)b[j + u];
+        }
+        for (; j < n; ++j) acc += (double)At[(int64_t)j * n + r] * (double)b[j];
+        y[r] = TY(acc);
+    }
+}
+
+// Coarsest level: x = A^{-1} b with the stored dense inverse (by columns);
+// one work-group per patch.
 template <typename T>
 __global__ __launch_bounds__(TILE) void k_coarse(const PatchLev* L, const int32_t* list, int nlist, const T* inv,
                                                  const T* b, T* x, int mode, const int* active) {
@@ -412,16 +589,7 @@ __global__ __launch_bounds__(TILE) void k_coarse(const PatchLev* L, const int32_
     const PatchLev& P = L[list[blockIdx.x]];
     if (active && !active[P.patch]) return;
     const int n = (int)P.n;
-    const T* A = inv + P.invoff + (int64_t)mode * n * n;
-    const T* bb = b + P.voff;
-    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
-    for (int r = w; r < n; r += nw) {
-        const T* row = A + (int64_t)r * n;
-        double acc = 0.0;
-        for (int j = lane; j < n; j += WAVE) acc += (double)row[j] * (double)bb[j];
-        for (int o = WAVE / 2; o > 0; o >>= 1) acc += __shfl_down(acc, o, WAVE);
-        if (lane == 0) x[P.voff + r] = T(acc);
-    }
+    col_gemv(inv + P.invoff + (int64_t)mode * n * n, n, b + P.voff, x + P.voff);
 }
 
 // ------------------------------------------------------------------ elementwise helpers
@@ -1014,13 +1182,18 @@ __global__ __launch_bounds__(TILE) void k_patch_gram(int npatch, const PatchLev*
 
 // ------------------------------------------------------------------ coarse part of a V-cycle in one kernel
 //
-// One work-group per patch runs levels 1 .. L-1 of the V-cycle with all level
-// vectors in LDS (rhs b, iterate x, its partner y, Chebyshev direction d per
-// level; x and y carry zero guards for the stencil reads) and the operator
-// data read from global memory: Chebyshev pre-smoothing, residual,
-// restriction, dense solve on the coarsest level, prolongation, Chebyshev
-// post-smoothing.  It replaces about ten launches per coarse level, each of
-// them too small to fill the chip.
+// One work-group per patch runs levels l0 .. L-1 of the V-cycle with all
+// level vectors in LDS (rhs b, iterate x, its partner y, Chebyshev direction
+// d per level; x and y carry zero guards for the stencil reads): Chebyshev
+// pre-smoothing, residual, restriction, dense solve on the coarsest level,
+// prolongation, Chebyshev post-smoothing.  It replaces about ten launches per
+// coarse level, each of them too small to fill the chip.  With STAGE set,
+// the half stencils of these levels (each entry with a front guard of the
+// stencil reach, for the lower-half reads) and the coarsest inverse of the
+// current mode are copied to LDS once per V-cycle, so that the sweeps read
+// no operator data from memory: a work-group is bound by the vector memory
+// throughput of its one CU otherwise.  STAGE is a template parameter so that
+// each instance holds one copy of the sweep (register pressure).
 
 constexpr int LMAX = 12;     // multigrid levels per patch
 constexpr int VC_THREADS = 512;
@@ -1037,17 +1210,32 @@ struct CoarseArgs {
     const int32_t* chain;     // chain[k * LMAX + l]: index of patch k in level l (-1: no such level)
     const int32_t* plist;     // patches of this launch, one work-group each
     int nlist;
-    const void* b1;           // level-1 right-hand side (global, level-1 layout)
-    void* x1;                 // level-1 correction (global, level-1 layout)
+    int l0;                   // first level run by this kernel (>= 1)
+    const void* b1;           // level-l0 right-hand side (global, level-l0 layout)
+    void* x1;                 // level-l0 correction (global, level-l0 layout)
     int mode;
     int m;                    // Chebyshev degree per smoothing phase
     const int* active;
 };
 
-template <int P0, int P1, int P2, typename T>
-__device__ __forceinline__ void vc_sweep(const PatchLev& P, const T* __restrict__ coef, const T* xs, T* ys,
-                                         const T* bs, T* ds, int mode, const double* cc, int k, bool resid) {
-    const int n = (int)P.n, M0 = P.M[0], M1 = P.M[1], M01 = M0 * M1, cs = (int)P.cstride;
+// LDS words the kernel needs for one patch chain: per level x, y (guarded),
+// b, d; staged, also nst * (n + guard) stencil words per smoothed level and
+// n * n for the coarsest inverse.
+__host__ __device__ inline int64_t vcoarse_level_words(int64_t n, int64_t guard, int nst, bool coarsest,
+                                                       bool stage) {
+    int64_t w = 2 * (n + 2 * guard) + 2 * n;
+    if (stage) w += coarsest ? n * n : (int64_t)nst * (n + guard);
+    return w;
+}
+
+// one Chebyshev step (or, with resid, the residual) on a level held in LDS;
+// c points at entry 0 of dof 0 of the half stencil, entries cs apart.  ROWS:
+// one stencil row at a time (operator data in LDS, where the short latency
+// needs no deep load queue and the full unroll would spill registers).
+template <int P0, int P1, int P2, typename T, bool ROWS>
+__device__ __forceinline__ void vc_sweep(const PatchLev& P, const T* c, int cs, const T* xs, T* ys, const T* bs,
+                                         T* ds, int mode, const double* cc, int k, bool resid) {
+    const int n = (int)P.n, M0 = P.M[0], M1 = P.M[1], M01 = M0 * M1;
     const double s1 = cc[2 * k], s2 = cc[2 * k + 1];
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
         const int i2 = i / M01, r = i - i2 * M01, i1 = r / M0, i0 = r - i1 * M0;
@@ -1057,12 +1245,12 @@ __device__ __forceinline__ void vc_sweep(const PatchLev& P, const T* __restrict_
             continue;
         }
         T diag = T(1);
-        // 2D: every load of a coefficient in flight at once; 3D: one stencil row at a time (registers)
+        // 2D from memory: every load of a coefficient in flight at once; else one stencil row at a time
         T acc;
-        if constexpr (P2 == 0)
-            acc = stencil_sum<P0, P1, P2>(coef + P.coff + i, xs + i, cs, M0, M01, P.p[0], P.p[1], P.p[2], diag);
+        if constexpr (P2 == 0 && !ROWS)
+            acc = stencil_sum<P0, P1, P2>(c + i, xs + i, cs, M0, M01, P.p[0], P.p[1], P.p[2], diag);
         else
-            acc = stencil_sum_rows<P0>(coef + P.coff + i, xs + i, cs, M0, M01, P.p[0], P.p[1], P.p[2], diag);
+            acc = stencil_sum_rows<P0>(c + i, xs + i, cs, M0, M01, P.p[0], P.p[1], P.p[2], diag);
         const T rr = bs[i] - acc;
         if (resid) {
             ys[i] = rr;
@@ -1074,39 +1262,32 @@ __device__ __forceinline__ void vc_sweep(const PatchLev& P, const T* __restrict_
     }
 }
 
-// y = A b for a dense n x n block (row-major, global) with x, b in LDS: one
-// wave per row at a time, lanes over the columns, shuffle reduction.
-template <typename T>
-__device__ __forceinline__ void wave_gemv(const T* __restrict__ A, int n, const T* b, T* y) {
-    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
-    for (int r = w; r < n; r += nw) {
-        const T* row = A + (int64_t)r * n;
-        T acc = T(0);
-        for (int j = lane; j < n; j += WAVE) acc += row[j] * b[j];
-        for (int o = WAVE / 2; o > 0; o >>= 1) acc += __shfl_down(acc, o, WAVE);
-        if (lane == 0) y[r] = acc;
-    }
-}
+// work-group state of k_vcoarse
+struct VcShared {
+    int pl[LMAX];        // patch-level index per level
+    int off[LMAX][5];    // LDS offsets of x, y (guarded, at entry 0), b, d, operator data
+    int cur[LMAX];       // which of x (0) / y (1) holds the level's current iterate
+    int nl, vec;
+};
 
-template <int P0, int P1, int P2, typename T>
-__global__ __launch_bounds__(VC_THREADS) void k_vcoarse(CoarseArgs a) {
-    extern __shared__ unsigned char vc_lds_raw[];
-    __shared__ int sh_pl[LMAX];        // patch-level index per level
-    __shared__ int sh_off[LMAX][4];    // LDS offsets of x, y (guarded, pointing at entry 0), b, d
-    __shared__ int sh_cur[LMAX];       // which of x (0) / y (1) holds the level's current iterate
-    __shared__ int sh_nl, sh_total;
-    T* lds = (T*)vc_lds_raw;
-    if ((int)blockIdx.x >= a.nlist) return;
-    const int k = a.plist[blockIdx.x];
-    if (a.active && !a.active[k]) return;
+// the cycle of patch k from level a.l0 on, for the degree class P0..P2
+template <int P0, int P1, int P2, typename T, bool STAGE>
+__device__ __forceinline__ void vcoarse_body(const CoarseArgs& a, int k, T* lds, VcShared& sh) {
+    int* sh_pl = sh.pl;
+    int (*sh_off)[5] = sh.off;
+    int* sh_cur = sh.cur;
+    int& sh_nl = sh.nl;
+    int& sh_vec = sh.vec;
+    const int l0 = a.l0;
+    constexpr bool stage = STAGE;
+    const int mode = a.mode;
     if (threadIdx.x == 0) {
-        int nl = 1;
+        int nl = l0 + 1;
         while (nl < LMAX && a.chain[k * LMAX + nl] >= 0) ++nl;
         int off = 0;
-        for (int l = 0; l < nl; ++l) {
+        for (int l = l0; l < nl; ++l) {
             const int pl = a.chain[k * LMAX + l];
             sh_pl[l] = pl;
-            if (l == 0) continue;
             const PatchLev& P = a.L[l][pl];
             const int n = (int)P.n;
             const int g = P.p[0] + P.p[1] * P.M[0] + P.p[2] * P.M[0] * P.M[1];
@@ -1119,46 +1300,71 @@ __global__ __launch_bounds__(VC_THREADS) void k_vcoarse(CoarseArgs a) {
             sh_off[l][3] = off;
             off += n;
         }
+        sh_vec = off;
+        for (int l = l0; l < nl && stage; ++l) {
+            const PatchLev& P = a.L[l][sh_pl[l]];
+            const int n = (int)P.n;
+            const int g = P.p[0] + P.p[1] * P.M[0] + P.p[2] * P.M[0] * P.M[1];
+            if (l == nl - 1) {
+                sh_off[l][4] = off;
+                off += n * n;
+            } else {
+                sh_off[l][4] = off + g;
+                off += (int)P.nst * (n + g);
+            }
+        }
         sh_nl = nl;
-        sh_total = off;
     }
     __syncthreads();
     const int nl = sh_nl;
-    for (int i = threadIdx.x; i < sh_total; i += blockDim.x) lds[i] = T(0);
-    __syncthreads();
+    for (int i = threadIdx.x; i < sh_vec; i += blockDim.x) lds[i] = T(0);
     {
-        const PatchLev& P = a.L[1][sh_pl[1]];
-        const T* b1 = (const T*)a.b1 + P.voff;
-        T* bl = lds + sh_off[1][2];
-        for (int i = threadIdx.x; i < (int)P.n; i += blockDim.x) bl[i] = b1[i];
+        const PatchLev& P = a.L[l0][sh_pl[l0]];
+        group_copy<4>(lds + sh_off[l0][2], (const T*)a.b1 + P.voff, (int)P.n);
+    }
+    if (stage) {
+        for (int l = l0; l < nl; ++l) {
+            const PatchLev& P = a.L[l][sh_pl[l]];
+            const int n = (int)P.n;
+            if (l == nl - 1) {
+                group_copy<16>(lds + sh_off[l][4], (const T*)a.inv[l] + P.invoff + (int64_t)mode * n * n, n * n);
+            } else {
+                // entry e, dofs -g .. n-1 (the front guard holds zeros in memory too)
+                const int g = P.p[0] + P.p[1] * P.M[0] + P.p[2] * P.M[0] * P.M[1];
+                group_copy_rows<16>(lds + sh_off[l][4] - g, (const T*)a.coef[l] + P.coff - g, (int)P.nst, n + g,
+                                    P.cstride);
+            }
+        }
     }
     __syncthreads();
-    const int mode = a.mode;
     // ---- down
-    for (int l = 1; l < nl; ++l) {
+    for (int l = l0; l < nl; ++l) {
         const int pl = sh_pl[l];
         const PatchLev& P = a.L[l][pl];
-        const T* coef = (const T*)a.coef[l];
+        const int n = (int)P.n;
+        const int g = P.p[0] + P.p[1] * P.M[0] + P.p[2] * P.M[0] * P.M[1];
+        const T* cg = (const T*)a.coef[l] + P.coff;   // half stencil in memory
+        const T* cl = lds + sh_off[l][4];              // staged copy (stage only)
         T* xl = lds + sh_off[l][0];
         T* yl = lds + sh_off[l][1];
         T* bl = lds + sh_off[l][2];
         T* dl = lds + sh_off[l][3];
         if (l == nl - 1) {
-            const int n = (int)P.n;
-            wave_gemv<T>((const T*)a.inv[l] + P.invoff + (int64_t)mode * n * n, n, bl, xl);
+            if constexpr (STAGE) col_gemv(cl, n, bl, xl);
+            else col_gemv((const T*)a.inv[l] + P.invoff + (int64_t)mode * n * n, n, bl, xl);
             if (threadIdx.x == 0) sh_cur[l] = 0;
             __syncthreads();
             break;
         }
         const double* cc = a.cheb[l] + 2 * (((int64_t)pl * 2 + mode) * KMAX);
         {
-            const int n = (int)P.n, M0 = P.M[0], M1 = P.M[1], M01 = M0 * M1;
+            const int M0 = P.M[0], M1 = P.M[1], M01 = M0 * M1;
             const T s20 = T(cc[1]);
             for (int i = threadIdx.x; i < n; i += blockDim.x) {
                 const int i2 = i / M01, r = i - i2 * M01, i1 = r / M0, i0 = r - i1 * M0;
                 T v = T(0);
                 if (!masked_bits(P.mbits[mode], P.dim, M0, M1, P.M[2], i0, i1, i2))
-                    v = s20 * bl[i] / coef[P.coff + i];
+                    v = s20 * bl[i] / (stage ? cl[i] : cg[i]);
                 xl[i] = v;
                 dl[i] = v;
             }
@@ -1167,15 +1373,17 @@ __global__ __launch_bounds__(VC_THREADS) void k_vcoarse(CoarseArgs a) {
         T* X = xl;
         T* Y = yl;
         int c = 0;
-        for (int step = 1; step < a.m; ++step) {
-            vc_sweep<P0, P1, P2, T>(P, coef, X, Y, bl, dl, mode, cc, step, false);
+        for (int step = 1; step <= a.m; ++step) {
+            const bool resid = step == a.m;
+            if (resid && threadIdx.x == 0) sh_cur[l] = c;
+            if constexpr (STAGE) vc_sweep<P0, P1, P2, T, true>(P, cl, n + g, X, Y, bl, dl, mode, cc, resid ? 0 : step, resid);
+            else vc_sweep<P0, P1, P2, T, (P0 > 3 || P1 > 3)>(P, cg, (int)P.cstride, X, Y, bl, dl, mode, cc, resid ? 0 : step, resid);
             __syncthreads();
-            T* tmp = X; X = Y; Y = tmp;
-            c ^= 1;
+            if (!resid) {
+                T* tmp = X; X = Y; Y = tmp;
+                c ^= 1;
+            }
         }
-        if (threadIdx.x == 0) sh_cur[l] = c;
-        vc_sweep<P0, P1, P2, T>(P, coef, X, Y, bl, dl, mode, cc, 0, true);
-        __syncthreads();
         {
             const PatchLev& C = a.L[l + 1][sh_pl[l + 1]];
             T* bc = lds + sh_off[l + 1][2];
@@ -1183,8 +1391,8 @@ __global__ __launch_bounds__(VC_THREADS) void k_vcoarse(CoarseArgs a) {
             const T* rval = (const T*)a.rval[l];
             const bool three = P.dim == 3;
             const int M0 = P.M[0], M01 = P.M[0] * P.M[1];
-            const int n = (int)C.n, C0 = C.M[0], C1 = C.M[1], C01 = C0 * C1;
-            for (int I = threadIdx.x; I < n; I += blockDim.x) {
+            const int nc = (int)C.n, C0 = C.M[0], C1 = C.M[1], C01 = C0 * C1;
+            for (int I = threadIdx.x; I < nc; I += blockDim.x) {
                 const int I2 = I / C01, r = I - I2 * C01, I1 = r / C0, I0 = r - I1 * C0;
                 T v = T(0);
                 if (!masked_bits(C.mbits[mode], C.dim, C0, C1, C.M[2], I0, I1, I2)) {
@@ -1204,10 +1412,13 @@ __global__ __launch_bounds__(VC_THREADS) void k_vcoarse(CoarseArgs a) {
         __syncthreads();
     }
     // ---- up
-    for (int lu = nl - 2; lu >= 1; --lu) {
+    for (int lu = nl - 2; lu >= l0; --lu) {
         const int pl = sh_pl[lu];
         const PatchLev& P = a.L[lu][pl];
-        const T* coef = (const T*)a.coef[lu];
+        const int n = (int)P.n;
+        const int g = P.p[0] + P.p[1] * P.M[0] + P.p[2] * P.M[0] * P.M[1];
+        const T* cg = (const T*)a.coef[lu] + P.coff;
+        const T* cl = lds + sh_off[lu][4];
         const double* cc = a.cheb[lu] + 2 * (((int64_t)pl * 2 + mode) * KMAX);
         const int cu = sh_cur[lu];
         T* X = lds + sh_off[lu][cu];
@@ -1220,7 +1431,7 @@ __global__ __launch_bounds__(VC_THREADS) void k_vcoarse(CoarseArgs a) {
             const int32_t* plo = a.plo[lu];
             const T* pval = (const T*)a.pval[lu];
             const bool three = P.dim == 3;
-            const int n = (int)P.n, M0 = P.M[0], M1 = P.M[1], M01 = M0 * M1;
+            const int M0 = P.M[0], M1 = P.M[1], M01 = M0 * M1;
             const int C0 = C.M[0], C01 = C.M[0] * C.M[1];
             for (int i = threadIdx.x; i < n; i += blockDim.x) {
                 const int i2 = i / M01, r = i - i2 * M01, i1 = r / M0, i0 = r - i1 * M0;
@@ -1239,7 +1450,8 @@ __global__ __launch_bounds__(VC_THREADS) void k_vcoarse(CoarseArgs a) {
         __syncthreads();
         int c = cu;
         for (int step = 0; step < a.m; ++step) {
-            vc_sweep<P0, P1, P2, T>(P, coef, X, Y, bl, dl, mode, cc, step, false);
+            if constexpr (STAGE) vc_sweep<P0, P1, P2, T, true>(P, cl, n + g, X, Y, bl, dl, mode, cc, step, false);
+            else vc_sweep<P0, P1, P2, T, (P0 > 3 || P1 > 3)>(P, cg, (int)P.cstride, X, Y, bl, dl, mode, cc, step, false);
             __syncthreads();
             T* tmp = X; X = Y; Y = tmp;
             c ^= 1;
@@ -1248,10 +1460,46 @@ __global__ __launch_bounds__(VC_THREADS) void k_vcoarse(CoarseArgs a) {
         __syncthreads();
     }
     {
-        const PatchLev& P = a.L[1][sh_pl[1]];
-        const T* X = lds + sh_off[1][sh_cur[1]];
-        T* x1 = (T*)a.x1 + P.voff;
-        for (int i = threadIdx.x; i < (int)P.n; i += blockDim.x) x1[i] = X[i];
+        const PatchLev& P = a.L[l0][sh_pl[l0]];
+        group_copy<4>((T*)a.x1 + P.voff, lds + sh_off[l0][sh_cur[l0]], (int)P.n);
+    }
+}
+
+// One launch for the patches of all degree classes of a family (FAM 0: the
+// 2D classes 0..8; FAM 1: the 3D classes and the generic one): each
+// work-group takes its patch's class instance (a uniform branch).  Two
+// families because the compiler spills registers when all twelve instances
+// share one kernel.
+__host__ __device__ constexpr int vcoarse_family(int cls) { return cls <= 8 ? 0 : 1; }
+
+template <typename T, bool STAGE, int FAM>
+__global__ __launch_bounds__(VC_THREADS) void k_vcoarse(CoarseArgs a) {
+    extern __shared__ unsigned char vc_lds_raw[];
+    __shared__ VcShared sh;
+    if ((int)blockIdx.x >= a.nlist) return;
+    const int k = a.plist[blockIdx.x];
+    if (a.active && !a.active[k]) return;
+    const int cls = a.L[a.l0][a.chain[k * LMAX + a.l0]].pclass;
+    T* lds = (T*)vc_lds_raw;
+    if constexpr (FAM == 0) {
+        switch (cls) {
+        case 0: vcoarse_body<2, 2, 0, T, STAGE>(a, k, lds, sh); break;
+        case 1: vcoarse_body<3, 2, 0, T, STAGE>(a, k, lds, sh); break;
+        case 2: vcoarse_body<4, 2, 0, T, STAGE>(a, k, lds, sh); break;
+        case 3: vcoarse_body<2, 3, 0, T, STAGE>(a, k, lds, sh); break;
+        case 4: vcoarse_body<3, 3, 0, T, STAGE>(a, k, lds, sh); break;
+        case 5: vcoarse_body<4, 3, 0, T, STAGE>(a, k, lds, sh); break;
+        case 6: vcoarse_body<2, 4, 0, T, STAGE>(a, k, lds, sh); break;
+        case 7: vcoarse_body<3, 4, 0, T, STAGE>(a, k, lds, sh); break;
+        case 8: vcoarse_body<4, 4, 0, T, STAGE>(a, k, lds, sh); break;
+        default: break;
+        }
+    } else {
+        switch (cls) {
+        case 9: vcoarse_body<2, 2, 2, T, STAGE>(a, k, lds, sh); break;
+        case 10: vcoarse_body<3, 3, 3, T, STAGE>(a, k, lds, sh); break;
+        default: vcoarse_body<-1, -1, -1, T, STAGE>(a, k, lds, sh); break;
+        }
     }
 }
 

@@ -48,6 +48,8 @@ void default_options(ieti_options* o) {
     o->basis_tol = 1e-12;
     o->check_every = 4;
     o->use_graph = 1;
+    o->coarse_level = 0;
+    o->coarse_dofs = 600;
     o->device = -1;
     o->stream = nullptr;
     o->hbm_budget = 0;
@@ -765,6 +767,8 @@ Plan* build_plan(const ieti_patch* in, int n, const double* pv, int n_pv, const 
         throw Error(IETI_EINVAL, "tolerances and iteration limits must be positive");
     if (opt.prec_vcycles < 1) throw Error(IETI_EINVAL, "prec_vcycles must be >= 1");
     if (opt.check_every < 1) opt.check_every = 1;
+    if (opt.coarse_level < -1) throw Error(IETI_EINVAL, "coarse_level must be >= -1");
+    if (opt.coarse_dofs < 0) throw Error(IETI_EINVAL, "coarse_dofs must be >= 0");
     const int dim = in[0].dim;
     for (int k = 0; k < n; ++k) validate_patch(in[k], dim, k);
     auto P = std::make_unique<Plan>();
@@ -1166,9 +1170,10 @@ Plan* build_plan(const ieti_patch* in, int n, const double* pv, int n_pv, const 
                 }
         pa.affine = aff;
         // levels: halve while every direction has an even number (>= 6) of elements
+        // and the level is larger than coarse_dofs
         while (opt.local_solver == IETI_LOCAL_MG) {
             const Level& f = pa.lv.back();
-            bool ok = true;
+            bool ok = opt.coarse_dofs == 0 || f.n > opt.coarse_dofs;
             for (int d = 0; d < dim; ++d)
                 if (f.nel[d] % 2 || f.nel[d] / 2 < 3) ok = false;
             if (!ok) break;

@@ -50,51 +50,46 @@ static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / 
 static inline unsigned tile_grid(int ntiles) { return (unsigned)(8 * ((ntiles + 7) / 8)); }
 
 // one kernel instance per degree class (see degree_class)
-#define IETI_CLASS_SWITCH(cls, L)                \
-    switch (cls) {                               \
-    case 0: L(2, 2, 0); break;                   \
-    case 1: L(3, 2, 0); break;                   \
-    case 2: L(4, 2, 0); break;                   \
-    case 3: L(2, 3, 0); break;                   \
-    case 4: L(3, 3, 0); break;                   \
-    case 5: L(4, 3, 0); break;                   \
-    case 6: L(2, 4, 0); break;                   \
-    case 7: L(3, 4, 0); break;                   \
-    case 8: L(4, 4, 0); break;                   \
-    case 9: L(2, 2, 2); break;                   \
-    case 10: L(3, 3, 3); break;                  \
-    default: L(-1, -1, -1); break;               \
-    }
 
 // With ev0/ev1 set, the launch records them at kernel start and end (profiling).
+// dynamic LDS a launch may take without raising the kernel's limit
+constexpr size_t STAGE_X_MAX_BYTES = 65536;
+
 template <typename TC, typename TX, typename TY, int EPI, bool FINE>
-static void launch_stencil(int cls, hipStream_t st, const StencilArgs& a, hipEvent_t ev0 = nullptr,
+static void launch_stencil(int cls, hipStream_t st, const StencilArgs& a, int reach, hipEvent_t ev0 = nullptr,
                            hipEvent_t ev1 = nullptr) {
 #define IETI_LS(A, B, C)                                                                                              \
     do {                                                                                                              \
+        const size_t lds = stencil_stages_x<A, C, FINE>() ? (size_t)(TILE + 2 * reach) * sizeof(TX) : 0;          \
         if (ev0)                                                                                                      \
             hipExtLaunchKernelGGL((k_stencil<A, B, C, TC, TX, TY, EPI, FINE>), dim3(tile_grid(a.ntiles)), dim3(TILE), \
-                                  0, st, ev0, ev1, 0, a);                                                             \
+                                  lds, st, ev0, ev1, 0, a);                                                           \
         else                                                                                                          \
-            hipLaunchKernelGGL((k_stencil<A, B, C, TC, TX, TY, EPI, FINE>), dim3(tile_grid(a.ntiles)), dim3(TILE), 0, \
-                               st, a);                                                                                \
+            hipLaunchKernelGGL((k_stencil<A, B, C, TC, TX, TY, EPI, FINE>), dim3(tile_grid(a.ntiles)), dim3(TILE),    \
+                               lds, st, a);                                                                           \
     } while (0)
     IETI_CLASS_SWITCH(cls, IETI_LS)
 #undef IETI_LS
 }
 
+template <typename T, bool STAGE, int FAM>
+static void launch_vcoarse(hipStream_t st, const CoarseArgs& a, size_t lds_bytes, bool set_attr) {
+    if (set_attr)
+        HIPCHECK(hipFuncSetAttribute((const void*)k_vcoarse<T, STAGE, FAM>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes));
+    else
+        hipLaunchKernelGGL((k_vcoarse<T, STAGE, FAM>), dim3(a.nlist), dim3(VC_THREADS), lds_bytes, st, a);
+}
+
 template <typename T>
-static void launch_vcoarse(int cls, hipStream_t st, const CoarseArgs& a, size_t lds_bytes, bool set_attr) {
-#define IETI_LV(A, B, C)                                                                                  \
-    do {                                                                                                  \
-        if (set_attr)                                                                                     \
-            HIPCHECK(hipFuncSetAttribute((const void*)k_vcoarse<A, B, C, T>,                              \
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes));    \
-        else                                                                                              \
-            hipLaunchKernelGGL((k_vcoarse<A, B, C, T>), dim3(a.nlist), dim3(VC_THREADS), lds_bytes, st, a); \
-    } while (0)
-    IETI_CLASS_SWITCH(cls, IETI_LV)
-#undef IETI_LV
+static void launch_vcoarse(int fam, bool stage, hipStream_t st, const CoarseArgs& a, size_t lds_bytes, bool set_attr) {
+    if (fam == 0) {
+        if (stage) launch_vcoarse<T, true, 0>(st, a, lds_bytes, set_attr);
+        else launch_vcoarse<T, false, 0>(st, a, lds_bytes, set_attr);
+    } else {
+        if (stage) launch_vcoarse<T, true, 1>(st, a, lds_bytes, set_attr);
+        else launch_vcoarse<T, false, 1>(st, a, lds_bytes, set_attr);
+    }
 }
 
 template <typename T>
@@ -206,6 +201,8 @@ struct DevLevel {
     // per degree class: sum of n and of n * nst (half-stencil words) over the launch's patches
     double words_all[NCLASS + 1] = {0}, words_smooth[NCLASS + 1] = {0};
     double st_all[NCLASS + 1] = {0}, st_smooth[NCLASS + 1] = {0};
+    // per degree class: largest linear stencil reach (the guard length; x window staged in LDS)
+    int reach[NCLASS + 1] = {0};
     std::vector<PatchLev> hL;
     PatchLev* L = nullptr;
     int64_t len = 0, clen = 0;
@@ -280,12 +277,13 @@ struct Solver : SolverBase {
     int32_t* band_b = nullptr;
     double* band = nullptr;
     size_t band_lds = 0;
-    // fused coarse V-cycle: one work-group per patch for levels >= 1
-    bool fused = false;
+    // fused coarse V-cycle: one work-group per patch for levels >= fuse_l0 (nlev: none)
+    int fuse_l0 = 0;
+    bool fuse_stage = false;
     int32_t* chain = nullptr;
-    std::vector<int32_t> h_plist[NCLASS + 1];
-    int32_t* plist[NCLASS + 1] = {nullptr};
-    size_t vc_lds[NCLASS + 1] = {0};
+    std::vector<int32_t> h_plist[2];   // patches of the fused kernel per class family, largest chain first
+    int32_t* plist[2] = {nullptr, nullptr};
+    size_t vc_lds[2] = {0, 0};
     // statistics of the current solve
     int64_t inner_calls = 0, inner_sum = 0;
     int inner_max = 0;
@@ -343,8 +341,9 @@ struct Solver : SolverBase {
                 if (EPI == EPI_DOTS) bytes = nst * sizeof(TC) + n * (sizeof(TX) + sizeof(TY) + sizeof(double));
                 ev = prof.next(pcls, bytes);
             }
-            if (l == 0) launch_stencil<TC, TX, TY, EPI, true>(c, stream, a, ev.first, ev.second);
-            else launch_stencil<TC, TX, TY, EPI, false>(c, stream, a, ev.first, ev.second);
+            const bool window_fits = (size_t)(TILE + 2 * D.reach[c]) * sizeof(TX) <= STAGE_X_MAX_BYTES;
+            if (l == 0 && window_fits) launch_stencil<TC, TX, TY, EPI, true>(c, stream, a, D.reach[c], ev.first, ev.second);
+            else launch_stencil<TC, TX, TY, EPI, false>(c, stream, a, D.reach[c], ev.first, ev.second);
             check_launch();
         }
     }
@@ -355,16 +354,20 @@ struct Solver : SolverBase {
     }
 
     // ---------------------------------------------------------------- multigrid V-cycle
-    // x0 = V(b0) on all patches (mode N or D); the result lands in x0.
+    // x0 = V(b0) on all patches (mode N or D); the result lands in x0.  Levels
+    // below fuse_l0 run as batched launches over all patches; from fuse_l0 on,
+    // one work-group per patch runs the rest of the cycle (k_vcoarse).
     void vcycle(int mode, const int* act, const T* b0, T* x0, const double* dotq = nullptr, double* dpart = nullptr) {
-        if (fused) {
-            vcycle_fused(mode, act, b0, x0, dotq, dpart);
-            return;
-        }
         std::vector<T*> cur(nlev, nullptr);
         int deepest = 0;
         for (int l = 0; l < nlev; ++l) {
             DevLevel& D = lev[l];
+            if (l > 0 && l == fuse_l0) {
+                vcoarse(l, mode, act);
+                cur[l] = (T*)D.vxa;
+                deepest = l;
+                break;
+            }
             const T* B = l == 0 ? b0 : (const T*)D.vb;
             T* S = l == 0 ? (T*)D.vxa : (T*)D.vx;       // start buffer
             T* F = l == 0 ? x0 : (T*)D.vxa;              // buffer holding the final result
@@ -423,35 +426,8 @@ struct Solver : SolverBase {
         if (dotq && deepest == 0) throw Error(IETI_ENOTSUP, "internal: fused dot needs a smoothed level 0");
     }
 
-    // Level 0 with the batched sweep kernels, levels >= 1 in one kernel per degree class.
-    void vcycle_fused(int mode, const int* act, const T* b0, T* x0, const double* dotq, double* dpart) {
-        DevLevel& D = lev[0];
-        T* S = (T*)D.vxa;
-        T* F = x0;
-        if (D.n_coarse) {
-            hipLaunchKernelGGL(k_coarse<T>, dim3(D.n_coarse), dim3(TILE), 0, stream, D.L, D.coarse_list, D.n_coarse,
-                               (const T*)D.inv, b0, F, mode, act);
-            check_launch();
-        }
-        if (D.nt_smooth == 0) return;
-        T* X = S;
-        T* XA = F;
-        hipLaunchKernelGGL(k_cheb_zero<T>, dim3(tile_grid(D.nt_smooth)), dim3(TILE), 0, stream, D.L, D.tiles_smooth,
-                           D.nt_smooth, (const T*)D.coefT, b0, X, (T*)D.vd, mode, D.cheb, act);
-        check_launch();
-        for (int k = 1; k < cheb_m; ++k) {
-            stencil<T, T, T, EPI_CHEB>(0, true, mode, D.coefT, X, XA, b0, D.vd, act, 0.0, k);
-            std::swap(X, XA);
-        }
-        stencil<T, T, T, EPI_RESID>(0, true, mode, D.coefT, X, D.vr, b0, nullptr, act, 0.0, 0);
-        DevLevel& C = lev[1];
-        for (int c = 0; c <= NCLASS; ++c) {
-            const int tb = C.cls_beg_all[c], te = C.cls_end_all[c];
-            if (te <= tb) continue;
-            launch_restrict<T>(c, stream, D.L, C.L, C.tiles_all + tb, te - tb, D.rlo, (const T*)D.rval,
-                               (const T*)D.vr, (T*)C.vb, mode, act);
-            check_launch();
-        }
+    // levels >= l0 of every patch that has level l0: lev[l0].vb -> lev[l0].vxa
+    void vcoarse(int l0, int mode, const int* act) {
         CoarseArgs a{};
         for (int l = 0; l < nlev && l < LMAX; ++l) {
             a.L[l] = lev[l].L;
@@ -464,32 +440,19 @@ struct Solver : SolverBase {
             a.cheb[l] = lev[l].cheb;
         }
         a.chain = chain;
-        a.b1 = C.vb;
-        a.x1 = C.vxa;
+        a.l0 = l0;
+        a.b1 = lev[l0].vb;
+        a.x1 = lev[l0].vxa;
         a.mode = mode;
         a.m = cheb_m;
         a.active = act;
-        for (int c = 0; c <= NCLASS; ++c) {
-            if (h_plist[c].empty()) continue;
-            a.plist = plist[c];
-            a.nlist = (int)h_plist[c].size();
-            launch_vcoarse<T>(c, stream, a, vc_lds[c], false);
+        for (int fam = 0; fam < 2; ++fam) {
+            if (h_plist[fam].empty()) continue;
+            a.plist = plist[fam];
+            a.nlist = (int)h_plist[fam].size();
+            launch_vcoarse<T>(fam, fuse_stage, stream, a, vc_lds[fam], false);
             check_launch();
         }
-        for (int c = 0; c <= NCLASS; ++c) {
-            const int tb = D.cls_beg_sm[c], te = D.cls_end_sm[c];
-            if (te <= tb) continue;
-            launch_prolong<T>(c, stream, D.L, C.L, D.tiles_smooth + tb, te - tb, D.plo, (const T*)D.pval,
-                              (const T*)C.vxa, X, mode, act);
-            check_launch();
-        }
-        for (int k = 0; k < cheb_m; ++k) {
-            const bool last = k == cheb_m - 1;
-            stencil<T, T, T, EPI_CHEB>(0, true, mode, D.coefT, X, XA, b0, D.vd, act, 0.0, k, nullptr, nullptr,
-                                       last ? dotq : nullptr, last ? dpart : nullptr);
-            std::swap(X, XA);
-        }
-        if (X != x0) throw Error(IETI_EDEVICE, "internal: V-cycle result buffer mismatch");
     }
 
     // ---------------------------------------------------------------- batched flexible CG: fx = K_rr^{-1} b
@@ -759,6 +722,7 @@ void Solver<T>::setup() {
         D.n_coarse = (int)D.h_coarse.size();
         for (const PatchLev& P : D.hL) {
             const int c = P.pclass;
+            D.reach[c] = std::max(D.reach[c], P.p[2] * P.M[0] * P.M[1] + P.p[1] * P.M[0] + P.p[0]);
             D.words_all[c] += (double)P.n;
             D.st_all[c] += (double)P.n * P.nst;
             if (P.coarse >= 0) {
@@ -843,9 +807,12 @@ void Solver<T>::setup() {
                     }
                 }
             } else if (pl.opt.local_solver == IETI_LOCAL_MG) {
+                // stored by columns: entry (r, j) at j * n + r
                 P.invoff = (int64_t)inv.size();
+                const int64_t n = L.n;
                 for (int m = 0; m < 2; ++m)
-                    for (double v : L.inv[m]) inv.push_back(T(v));
+                    for (int64_t j = 0; j < n; ++j)
+                        for (int64_t r = 0; r < n; ++r) inv.push_back(T(L.inv[m][(size_t)(r * n + j)]));
             }
         }
         D.L = arena.upload(D.hL, st);
@@ -870,39 +837,68 @@ void Solver<T>::setup() {
         HIPCHECK(hipStreamSynchronize(st));   // host vectors above go out of scope
     }
     // ---- fused coarse V-cycle
-    if (nlev > 1 && nlev <= LMAX) {
+    // Start level with coarse_level = 0: level 1, with the operator data
+    // staged in LDS when every chain fits, else read from memory (batched
+    // launches of a coarse level cost more than the fused kernel's sweeps);
+    // the lowest level from which the vectors fit if level 1 does not.
+    fuse_l0 = nlev;
+    if (nlev > 1 && nlev <= LMAX && pl.opt.local_solver == IETI_LOCAL_MG && pl.opt.coarse_level >= 0) {
         int dev = 0;
         HIPCHECK(hipGetDevice(&dev));
         int max_lds = 0;
         HIPCHECK(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-        std::vector<int32_t> ch((size_t)N * LMAX, -1);
-        for (int l = 0; l < nlev; ++l)
-            for (size_t i = 0; i < lev[l].hL.size(); ++i) ch[(size_t)lev[l].hL[i].patch * LMAX + l] = (int32_t)i;
-        bool ok = true;
-        for (int k = 0; k < N; ++k) {
+        const int64_t budget = (int64_t)max_lds - 1024;   // static shared memory of the kernel
+        auto chain_bytes = [&](int k, int f, bool stage) -> int64_t {
             const Patch& pa = pl.patches[k];
             const int nl = (int)pa.lv.size();
-            if (nl < 2) continue;
-            size_t words = 0;
-            for (int l = 1; l < nl; ++l) {
+            int64_t w = 0;
+            for (int l = f; l < nl; ++l) {
                 const Level& L = pa.lv[l];
-                words += 2 * (size_t)(L.n + 2 * L.guard) + 2 * (size_t)L.n;
+                w += vcoarse_level_words(L.n, L.guard, L.nst, l == nl - 1, stage);
             }
-            const size_t bytes = words * sizeof(T);
-            if ((int64_t)bytes > max_lds) ok = false;
-            const int c = lev[0].hL[k].pclass;
-            h_plist[c].push_back(k);
-            vc_lds[c] = std::max(vc_lds[c], bytes);
+            return w * (int64_t)sizeof(T);
+        };
+        auto feasible = [&](int f, bool stage) {
+            for (int k = 0; k < N; ++k)
+                if ((int)pl.patches[k].lv.size() > f && chain_bytes(k, f, stage) > budget) return false;
+            return true;
+        };
+        int f = nlev;
+        bool stage = false;
+        if (pl.opt.coarse_level > 0) {
+            f = std::min(pl.opt.coarse_level, nlev - 1);
+            stage = feasible(f, true);
+            if (!stage && !feasible(f, false)) f = nlev;
+        } else if (feasible(1, true)) {
+            f = 1;
+            stage = true;
+        } else {
+            for (int g = 1; g < nlev && f == nlev; ++g)
+                if (feasible(g, false)) f = g;
         }
-        if (ok) {
+        if (f < nlev) {
+            fuse_l0 = f;
+            fuse_stage = stage;
+            std::vector<int32_t> ch((size_t)N * LMAX, -1);
+            for (int l = 0; l < nlev; ++l)
+                for (size_t i = 0; i < lev[l].hL.size(); ++i) ch[(size_t)lev[l].hL[i].patch * LMAX + l] = (int32_t)i;
             chain = arena.upload(ch, st);
-            for (int c = 0; c <= NCLASS; ++c) {
-                if (h_plist[c].empty()) continue;
-                plist[c] = arena.upload(h_plist[c], st);
-                CoarseArgs dummy{};
-                launch_vcoarse<T>(c, st, dummy, vc_lds[c], true);
+            std::vector<std::pair<int64_t, int32_t>> order[2];
+            for (int k = 0; k < N; ++k) {
+                if ((int)pl.patches[k].lv.size() <= f) continue;
+                const int64_t b = chain_bytes(k, f, stage);
+                const int fam = vcoarse_family(lev[0].hL[k].pclass);
+                order[fam].push_back({-b, k});
+                vc_lds[fam] = std::max(vc_lds[fam], (size_t)b);
             }
-            fused = true;
+            for (int fam = 0; fam < 2; ++fam) {
+                std::sort(order[fam].begin(), order[fam].end());
+                for (auto& o : order[fam]) h_plist[fam].push_back(o.second);
+                if (h_plist[fam].empty()) continue;
+                plist[fam] = arena.upload(h_plist[fam], st);
+                CoarseArgs dummy{};
+                launch_vcoarse<T>(fam, stage, st, dummy, vc_lds[fam], true);
+            }
         }
         HIPCHECK(hipStreamSynchronize(st));
     }

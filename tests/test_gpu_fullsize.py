@@ -1,6 +1,7 @@
 """Full-size parity in the benchmark's launch configuration: the GPU solution of
-the 8x8-patch, p=3, 64^2 workload against the oracle's global direct solution,
-sampled at 2000 seeded coefficients (tests/golden/make_golden.py)."""
+each benchmark workload against the oracle's solution, sampled at 2000 seeded
+global coefficients (tests/golden/make_golden.py; 2D: the global direct solve,
+3D cube: the oracle's exact-local IETI-DP to 1e-13)."""
 import json
 import os
 
@@ -15,7 +16,7 @@ pytestmark = pytest.mark.gpu
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
-@pytest.mark.parametrize("name", ["deformed8x8_p3_n64", "deformed16x16_mixed"])
+@pytest.mark.parametrize("name", ["deformed8x8_p3_n64", "deformed16x16_mixed", "cube4x4x4_p2_n24"])
 def test_full_config_against_oracle_samples(require_gpu, name):
     path = os.path.join(HERE, "golden", f"full_{name}.json")
     if not os.path.exists(path):
