@@ -340,13 +340,9 @@ __host__ __device__ constexpr bool stencil_stages_x() {
 }
 
 template <int P0, int P1, int P2, typename TC, typename TX, typename TY, int EPI, bool FINE>
-__global__ __launch_bounds__(TILE) void k_stencil(StencilArgs a) {
-    __shared__ double lds[2 * TILE / WAVE];
-    extern __shared__ unsigned char st_lds_raw[];
+__device__ __forceinline__ void stencil_body(const StencilArgs& a, const Tile& tl, double* lds,
+                                             unsigned char* st_lds_raw) {
     constexpr bool STAGE = stencil_stages_x<P0, P2, FINE>();
-    const int t = tile_index(a.ntiles);
-    if (t < 0) return;
-    const Tile tl = a.tiles[t];
     const PatchLev& P = a.L[tl.pl];
     if (a.active && !a.active[P.patch]) return;
     const int n = (int)P.n;
@@ -468,6 +464,40 @@ __global__ __launch_bounds__(TILE) void k_stencil(StencilArgs a) {
     }
 }
 
+template <int P0, int P1, int P2, typename TC, typename TX, typename TY, int EPI, bool FINE>
+__global__ __launch_bounds__(TILE) void k_stencil(StencilArgs a) {
+    __shared__ double lds[2 * TILE / WAVE];
+    extern __shared__ unsigned char st_lds_raw[];
+    const int t = tile_index(a.ntiles);
+    if (t < 0) return;
+    const Tile tl = a.tiles[t];
+    stencil_body<P0, P1, P2, TC, TX, TY, EPI, FINE>(a, tl, lds, st_lds_raw);
+}
+
+// Finest-level sweep over the tiles of several 2D degree classes in one
+// launch (levels that mix degrees): each work-group takes its tile's class
+// instance (a uniform branch).  Registers are those of the largest class.
+template <typename TC, typename TX, typename TY, int EPI>
+__global__ __launch_bounds__(TILE) void k_stencil_2d(StencilArgs a) {
+    __shared__ double lds[2 * TILE / WAVE];
+    extern __shared__ unsigned char st_lds_raw[];
+    const int t = tile_index(a.ntiles);
+    if (t < 0) return;
+    const Tile tl = a.tiles[t];
+    switch (a.L[tl.pl].pclass) {
+    case 0: stencil_body<2, 2, 0, TC, TX, TY, EPI, true>(a, tl, lds, st_lds_raw); break;
+    case 1: stencil_body<3, 2, 0, TC, TX, TY, EPI, true>(a, tl, lds, st_lds_raw); break;
+    case 2: stencil_body<4, 2, 0, TC, TX, TY, EPI, true>(a, tl, lds, st_lds_raw); break;
+    case 3: stencil_body<2, 3, 0, TC, TX, TY, EPI, true>(a, tl, lds, st_lds_raw); break;
+    case 4: stencil_body<3, 3, 0, TC, TX, TY, EPI, true>(a, tl, lds, st_lds_raw); break;
+    case 5: stencil_body<4, 3, 0, TC, TX, TY, EPI, true>(a, tl, lds, st_lds_raw); break;
+    case 6: stencil_body<2, 4, 0, TC, TX, TY, EPI, true>(a, tl, lds, st_lds_raw); break;
+    case 7: stencil_body<3, 4, 0, TC, TX, TY, EPI, true>(a, tl, lds, st_lds_raw); break;
+    case 8: stencil_body<4, 4, 0, TC, TX, TY, EPI, true>(a, tl, lds, st_lds_raw); break;
+    default: break;
+    }
+}
+
 // ------------------------------------------------------------------ smoother start, transfers, coarse solve
 
 // First Chebyshev step from a zero guess: x = d = m b / (theta diag)
@@ -496,7 +526,37 @@ __global__ __launch_bounds__(TILE) void k_cheb_zero(const PatchLev* L, const Til
     d[vi] = T(v);
 }
 
-// Restriction b_c = m_c P^T r_f, one thread per coarse coefficient.
+// Transfer band sum for the degree class of F: P0 = -2 selects the 2D class
+// of F at run time (launches over several classes), else as band_sum.
+template <int P0, int P1, int P2, typename T>
+__device__ __forceinline__ double band_sum_cls(const PatchLev& F, const T* v0, const T* v1, const T* v2, const T* src,
+                                               int M0, int M01) {
+    const bool three = F.dim == 3;
+    if constexpr (P0 == -2) {
+        switch (F.pclass) {
+        case 0: return band_sum<4, 4, 1>(v0, v1, v2, src, M0, M01, 4, 4, 1, 2);
+        case 1: return band_sum<5, 4, 1>(v0, v1, v2, src, M0, M01, 5, 4, 1, 2);
+        case 2: return band_sum<6, 4, 1>(v0, v1, v2, src, M0, M01, 6, 4, 1, 2);
+        case 3: return band_sum<4, 5, 1>(v0, v1, v2, src, M0, M01, 4, 5, 1, 2);
+        case 4: return band_sum<5, 5, 1>(v0, v1, v2, src, M0, M01, 5, 5, 1, 2);
+        case 5: return band_sum<6, 5, 1>(v0, v1, v2, src, M0, M01, 6, 5, 1, 2);
+        case 6: return band_sum<4, 6, 1>(v0, v1, v2, src, M0, M01, 4, 6, 1, 2);
+        case 7: return band_sum<5, 6, 1>(v0, v1, v2, src, M0, M01, 5, 6, 1, 2);
+        case 8: return band_sum<6, 6, 1>(v0, v1, v2, src, M0, M01, 6, 6, 1, 2);
+        default:
+            return band_sum<-1, -1, -1>(v0, v1, v2, src, M0, M01, F.p[0] + 2, F.p[1] + 2, three ? F.p[2] + 2 : 1,
+                                        F.dim);
+        }
+    } else {
+        constexpr int W0 = P0 >= 0 ? P0 + 2 : -1, W1 = P0 >= 0 ? P1 + 2 : -1;
+        constexpr int W2 = P0 >= 0 ? (P2 > 0 ? P2 + 2 : 1) : -1;
+        return band_sum<W0, W1, W2>(v0, v1, v2, src, M0, M01, F.p[0] + 2, F.p[1] + 2, three ? F.p[2] + 2 : 1,
+                                    F.dim);
+    }
+}
+
+// Restriction b_c = m_c P^T r_f, one thread per coarse coefficient (P0 = -2:
+// tiles of several 2D classes).
 template <int P0, int P1, int P2, typename T>
 __global__ __launch_bounds__(TILE) void k_restrict(const PatchLev* Lf, const PatchLev* Lc, const Tile* tiles,
                                                    int ntiles, const int32_t* rlo, const T* rval, const T* rf, T* bc,
@@ -522,13 +582,11 @@ __global__ __launch_bounds__(TILE) void k_restrict(const PatchLev* Lf, const Pat
     const T* v2 = three ? rval + (F.roff[2] + I2) * PW : v1;
     const int M0 = F.M[0], M01 = F.M[0] * F.M[1];
     const T* src = rf + F.voff + lo0 + (int64_t)lo1 * M0 + (int64_t)lo2 * M01;
-    constexpr int W0 = P0 >= 0 ? P0 + 2 : -1, W1 = P0 >= 0 ? P1 + 2 : -1, W2 = P0 >= 0 ? (P2 > 0 ? P2 + 2 : 1) : -1;
-    const double acc = band_sum<W0, W1, W2>(v0, v1, v2, src, M0, M01, F.p[0] + 2, F.p[1] + 2,
-                                            three ? F.p[2] + 2 : 1, F.dim);
-    bc[C.voff + I] = T(acc);
+    bc[C.voff + I] = T(band_sum_cls<P0, P1, P2>(F, v0, v1, v2, src, M0, M01));
 }
 
-// Prolongation x_f += m_f P e_c, one thread per fine coefficient.
+// Prolongation x_f += m_f P e_c, one thread per fine coefficient (P0 = -2:
+// tiles of several 2D classes).
 template <int P0, int P1, int P2, typename T>
 __global__ __launch_bounds__(TILE) void k_prolong(const PatchLev* Lf, const PatchLev* Lc, const Tile* tiles,
                                                   int ntiles, const int32_t* plo, const T* pval, const T* ec, T* xf,
@@ -551,9 +609,7 @@ __global__ __launch_bounds__(TILE) void k_prolong(const PatchLev* Lf, const Patc
     const T* v2 = three ? pval + (F.toff[2] + i2) * PW : v1;
     const int M0 = C.M[0], M01 = C.M[0] * C.M[1];
     const T* src = ec + C.voff + lo0 + (int64_t)lo1 * M0 + (int64_t)lo2 * M01;
-    constexpr int W0 = P0 >= 0 ? P0 + 2 : -1, W1 = P0 >= 0 ? P1 + 2 : -1, W2 = P0 >= 0 ? (P2 > 0 ? P2 + 2 : 1) : -1;
-    const double acc = band_sum<W0, W1, W2>(v0, v1, v2, src, M0, M01, F.p[0] + 2, F.p[1] + 2,
-                                            three ? F.p[2] + 2 : 1, F.dim);
+    const double acc = band_sum_cls<P0, P1, P2>(F, v0, v1, v2, src, M0, M01);
     const int64_t vi = F.voff + i;
     xf[vi] = T((double)xf[vi] + acc);
 }

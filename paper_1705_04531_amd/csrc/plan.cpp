@@ -55,19 +55,21 @@ void default_options(ieti_options* o) {
     o->hbm_budget = 0;
 }
 
-// Smoother choice per spline degree, from a sweep of inner flexible-CG
-// iterations x matrix-vector products to reach 1e-10 (degree of the
-// Chebyshev polynomial per smoothing phase, lower end of its interval).
+// Smoother choice per spline degree (degree of the Chebyshev polynomial per
+// smoothing phase, lower end of its interval as a fraction of lambda_max),
+// from measured solve times on MI355X over a grid of both parameters: higher
+// degrees pay off because a V-cycle's coarse part costs about as much as
+// several finest-level sweeps.
 int cheb_degree_for(const ieti_options& o, int pmax) {
     if (o.cheb_degree > 0) return o.cheb_degree;
-    if (pmax <= 2) return 2;
-    if (pmax == 3) return 3;
+    if (pmax <= 2) return 3;
+    if (pmax == 3) return 5;
     return 4;
 }
 double cheb_lower_for(const ieti_options& o, int pmax) {
     if (o.cheb_lower > 0) return o.cheb_lower;
-    if (pmax <= 2) return 0.1;
-    if (pmax == 3) return 0.05;
+    if (pmax <= 2) return 0.08;
+    if (pmax == 3) return 0.03;
     return 0.02;
 }
 

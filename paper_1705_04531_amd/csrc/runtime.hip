@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
@@ -51,6 +52,25 @@ static inline unsigned tile_grid(int ntiles) { return (unsigned)(8 * ((ntiles + 
 
 // one kernel instance per degree class (see degree_class)
 
+// Launch groups over class-ordered tiles: {class, first tile, end tile}.  With
+// multi set and at least two 2D classes present, the 2D classes 0..8 (whose
+// tiles are contiguous) form one group, class MULTI_2D.
+constexpr int MULTI_2D = -2;
+
+static std::vector<std::array<int, 3>> launch_groups(const int* beg, const int* end, bool multi) {
+    std::vector<std::array<int, 3>> g;
+    int n2d = 0;
+    for (int c = 0; c <= 8; ++c) n2d += end[c] > beg[c] ? 1 : 0;
+    int c0 = 0;
+    if (multi && n2d >= 2) {
+        g.push_back({MULTI_2D, beg[0], end[8]});
+        c0 = 9;
+    }
+    for (int c = c0; c <= NCLASS; ++c)
+        if (end[c] > beg[c]) g.push_back({c, beg[c], end[c]});
+    return g;
+}
+
 // With ev0/ev1 set, the launch records them at kernel start and end (profiling).
 // dynamic LDS a launch may take without raising the kernel's limit
 constexpr size_t STAGE_X_MAX_BYTES = 65536;
@@ -58,6 +78,15 @@ constexpr size_t STAGE_X_MAX_BYTES = 65536;
 template <typename TC, typename TX, typename TY, int EPI, bool FINE>
 static void launch_stencil(int cls, hipStream_t st, const StencilArgs& a, int reach, hipEvent_t ev0 = nullptr,
                            hipEvent_t ev1 = nullptr) {
+    if (cls == MULTI_2D) {   // the finest level's 2D classes in one launch (always staged)
+        const size_t lds = (size_t)(TILE + 2 * reach) * sizeof(TX);
+        if (ev0)
+            hipExtLaunchKernelGGL((k_stencil_2d<TC, TX, TY, EPI>), dim3(tile_grid(a.ntiles)), dim3(TILE), lds, st, ev0,
+                                  ev1, 0, a);
+        else
+            hipLaunchKernelGGL((k_stencil_2d<TC, TX, TY, EPI>), dim3(tile_grid(a.ntiles)), dim3(TILE), lds, st, a);
+        return;
+    }
 #define IETI_LS(A, B, C)                                                                                              \
     do {                                                                                                              \
         const size_t lds = stencil_stages_x<A, C, FINE>() ? (size_t)(TILE + 2 * reach) * sizeof(TX) : 0;          \
@@ -95,6 +124,11 @@ static void launch_vcoarse(int fam, bool stage, hipStream_t st, const CoarseArgs
 template <typename T>
 static void launch_restrict(int cls, hipStream_t st, const PatchLev* Lf, const PatchLev* Lc, const Tile* tiles,
                             int nt, const int32_t* rlo, const T* rval, const T* rf, T* bc, int mode, const int* act) {
+    if (cls == MULTI_2D) {
+        hipLaunchKernelGGL((k_restrict<-2, 0, 0, T>), dim3(tile_grid(nt)), dim3(TILE), 0, st, Lf, Lc, tiles, nt, rlo,
+                           rval, rf, bc, mode, act);
+        return;
+    }
 #define IETI_LR(A, B, C)                                                                                      \
     hipLaunchKernelGGL((k_restrict<A, B, C, T>), dim3(tile_grid(nt)), dim3(TILE), 0, st, Lf, Lc, tiles, nt, rlo, \
                        rval, rf, bc, mode, act)
@@ -105,6 +139,11 @@ static void launch_restrict(int cls, hipStream_t st, const PatchLev* Lf, const P
 template <typename T>
 static void launch_prolong(int cls, hipStream_t st, const PatchLev* Lf, const PatchLev* Lc, const Tile* tiles, int nt,
                            const int32_t* plo, const T* pval, const T* ec, T* xf, int mode, const int* act) {
+    if (cls == MULTI_2D) {
+        hipLaunchKernelGGL((k_prolong<-2, 0, 0, T>), dim3(tile_grid(nt)), dim3(TILE), 0, st, Lf, Lc, tiles, nt, plo,
+                           pval, ec, xf, mode, act);
+        return;
+    }
 #define IETI_LP(A, B, C)                                                                                     \
     hipLaunchKernelGGL((k_prolong<A, B, C, T>), dim3(tile_grid(nt)), dim3(TILE), 0, st, Lf, Lc, tiles, nt, plo, \
                        pval, ec, xf, mode, act)
@@ -325,25 +364,32 @@ struct Solver : SolverBase {
             else if (EPI == EPI_RESID && smooth_only) pcls = IETI_KPROF_RESID_FINE;
         }
         const Tile* base = smooth_only ? D.tiles_smooth : D.tiles_all;
-        for (int c = 0; c <= NCLASS; ++c) {
-            const int tb = smooth_only ? D.cls_beg_sm[c] : D.cls_beg_all[c];
-            const int te = smooth_only ? D.cls_end_sm[c] : D.cls_end_all[c];
-            if (te <= tb) continue;
-            a.tiles = base + tb;
-            a.ntiles = te - tb;
+        const int* beg = smooth_only ? D.cls_beg_sm : D.cls_beg_all;
+        const int* end = smooth_only ? D.cls_end_sm : D.cls_end_all;
+        int reach2d = 0;
+        for (int c = 0; c <= 8; ++c) reach2d = std::max(reach2d, D.reach[c]);
+        const bool multi = l == 0 && (size_t)(TILE + 2 * reach2d) * sizeof(TX) <= STAGE_X_MAX_BYTES;
+        for (const auto& g : launch_groups(beg, end, multi)) {
+            const int c = g[0];
+            a.tiles = base + g[1];
+            a.ntiles = g[2] - g[1];
             std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
             if (pcls >= 0) {
                 // algorithmic bytes: every vector the epilogue touches and the half stencil, once per coefficient
-                const double n = smooth_only ? D.words_smooth[c] : D.words_all[c];
-                const double nst = smooth_only ? D.st_smooth[c] : D.st_all[c];
+                double n = 0.0, nst = 0.0;
+                for (int cc = c == MULTI_2D ? 0 : c; cc <= (c == MULTI_2D ? 8 : c); ++cc) {
+                    n += smooth_only ? D.words_smooth[cc] : D.words_all[cc];
+                    nst += smooth_only ? D.st_smooth[cc] : D.st_all[cc];
+                }
                 const double vec_words = EPI == EPI_CHEB ? (cheb_k > 0 ? 5.0 : 4.0) : 3.0;
                 double bytes = nst * sizeof(TC) + n * (vec_words - 1.0) * sizeof(TY) + n * sizeof(TX);
                 if (EPI == EPI_DOTS) bytes = nst * sizeof(TC) + n * (sizeof(TX) + sizeof(TY) + sizeof(double));
                 ev = prof.next(pcls, bytes);
             }
-            const bool window_fits = (size_t)(TILE + 2 * D.reach[c]) * sizeof(TX) <= STAGE_X_MAX_BYTES;
-            if (l == 0 && window_fits) launch_stencil<TC, TX, TY, EPI, true>(c, stream, a, D.reach[c], ev.first, ev.second);
-            else launch_stencil<TC, TX, TY, EPI, false>(c, stream, a, D.reach[c], ev.first, ev.second);
+            const int reach = c == MULTI_2D ? reach2d : D.reach[c];
+            const bool window_fits = (size_t)(TILE + 2 * reach) * sizeof(TX) <= STAGE_X_MAX_BYTES;
+            if (l == 0 && window_fits) launch_stencil<TC, TX, TY, EPI, true>(c, stream, a, reach, ev.first, ev.second);
+            else launch_stencil<TC, TX, TY, EPI, false>(c, stream, a, reach, ev.first, ev.second);
             check_launch();
         }
     }
@@ -392,10 +438,8 @@ struct Solver : SolverBase {
             stencil<T, T, T, EPI_RESID>(l, true, mode, D.coefT, X, D.vr, B, nullptr, act, 0.0, 0);
             cur[l] = X;
             DevLevel& C = lev[l + 1];
-            for (int c = 0; c <= NCLASS; ++c) {
-                const int tb = C.cls_beg_all[c], te = C.cls_end_all[c];
-                if (te <= tb) continue;
-                launch_restrict<T>(c, stream, D.L, C.L, C.tiles_all + tb, te - tb, D.rlo, (const T*)D.rval,
+            for (const auto& g : launch_groups(C.cls_beg_all, C.cls_end_all, true)) {
+                launch_restrict<T>(g[0], stream, D.L, C.L, C.tiles_all + g[1], g[2] - g[1], D.rlo, (const T*)D.rval,
                                    (const T*)D.vr, (T*)C.vb, mode, act);
                 check_launch();
             }
@@ -407,11 +451,9 @@ struct Solver : SolverBase {
             T* A0 = l == 0 ? (T*)D.vxa : (T*)D.vx;   // the level's two x buffers
             T* A1 = l == 0 ? x0 : (T*)D.vxa;
             T* XA = (X == A0) ? A1 : A0;
-            for (int c = 0; c <= NCLASS; ++c) {
-                const int tb = D.cls_beg_sm[c], te = D.cls_end_sm[c];
-                if (te <= tb) continue;
-                launch_prolong<T>(c, stream, D.L, lev[l + 1].L, D.tiles_smooth + tb, te - tb, D.plo, (const T*)D.pval,
-                                  (const T*)cur[l + 1], X, mode, act);
+            for (const auto& g : launch_groups(D.cls_beg_sm, D.cls_end_sm, true)) {
+                launch_prolong<T>(g[0], stream, D.L, lev[l + 1].L, D.tiles_smooth + g[1], g[2] - g[1], D.plo,
+                                  (const T*)D.pval, (const T*)cur[l + 1], X, mode, act);
                 check_launch();
             }
             for (int k = 0; k < cheb_m; ++k) {
