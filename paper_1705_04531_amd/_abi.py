@@ -54,6 +54,7 @@ class IetiOptions(C.Structure):
         ("mg_precision", C.c_int32),
         ("primal", C.c_int32),
         ("cheb_degree", C.c_int32),
+        ("cheb_degree_coarse", C.c_int32),
         ("cheb_lower", C.c_double),
         ("prec_vcycles", C.c_int32),
         ("max_it", C.c_int32),

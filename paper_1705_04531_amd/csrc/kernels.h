@@ -912,65 +912,95 @@ __global__ void k_gather(int64_t nlam, const int64_t* plus, const int64_t* minus
 
 // ------------------------------------------------------------------ primal space
 
-// Per patch k (one work-group): c[k][j] = psi_j . g over the patch's rows and,
-// for edge constraints, e[k][j] = mean of y over the edge.  Rows are either
-// the patch's interface slots (compact psiG, slot-major with NPMAX stride;
-// row_ptr/row_dev give the slots of each patch) or, with L0 != null, all
-// coefficients of the patch (full psi: NPMAX level-0 vectors).
+// Per patch k (one work-group): c[k][j] = psi_j . g over the patch's rows,
+// all j in one pass over g, and, for edge constraints, e[k][j] = mean of y
+// over the edge.  Rows are either the patch's interface slots (compact psiG,
+// slot-major with NPMAX stride; row_ptr/row_dev give the slots of each patch)
+// or, with L0 != null, all coefficients of the patch (psi, j-major).
 __global__ __launch_bounds__(TILE) void k_pri_dots(int npatch, const int32_t* npk, const int64_t* row_ptr,
                                                    const int64_t* row_dev, const PatchLev* L0, const double* psi,
                                                    int64_t psi_stride, const double* g, const double* y,
                                                    const int64_t* edge_ptr, const int64_t* edge_dev, double* c,
                                                    double* e) {
-    __shared__ double lds[TILE / WAVE];
+    __shared__ double lds[NPMAX * TILE / WAVE];
     const int k = blockIdx.x;
     if (k >= npatch) return;
     const int nj = npk[k];
-    for (int j = 0; j < nj; ++j) {
-        double v[1] = {0.0};
-        if (L0) {
-            const PatchLev& P = L0[k];
-            for (int64_t r = threadIdx.x; r < P.n; r += blockDim.x)
-                v[0] += psi[(int64_t)j * psi_stride + P.voff + r] * g[P.voff + r];
-        } else {
-            for (int64_t r = row_ptr[k] + threadIdx.x; r < row_ptr[k + 1]; r += blockDim.x)
-                v[0] += psi[r * NPMAX + j] * g[row_dev[r]];
+    double v[NPMAX];
+#pragma unroll
+    for (int j = 0; j < NPMAX; ++j) v[j] = 0.0;
+    if (L0) {
+        const PatchLev& P = L0[k];
+        for (int64_t r = threadIdx.x; r < P.n; r += blockDim.x) {
+            const double gv = g[P.voff + r];
+#pragma unroll
+            for (int j = 0; j < NPMAX; ++j)
+                if (j < nj) v[j] += psi[(int64_t)j * psi_stride + P.voff + r] * gv;
         }
-        block_sum<1>(v, lds);
-        if (threadIdx.x == 0) c[k * NPMAX + j] = v[0];
-        const int64_t eb = edge_ptr[k * NPMAX + j], ee = edge_ptr[k * NPMAX + j + 1];
-        if (y && ee > eb) {
-            double w[1] = {0.0};
-            for (int64_t r = eb + threadIdx.x; r < ee; r += blockDim.x) w[0] += y[edge_dev[r]];
-            block_sum<1>(w, lds);
-            if (threadIdx.x == 0) e[k * NPMAX + j] = w[0] / (double)(ee - eb);
-        } else if (threadIdx.x == 0) {
-            e[k * NPMAX + j] = 0.0;
+    } else {
+        for (int64_t r = row_ptr[k] + threadIdx.x; r < row_ptr[k + 1]; r += blockDim.x) {
+            const double gv = g[row_dev[r]];
+#pragma unroll
+            for (int j = 0; j < NPMAX; ++j)
+                if (j < nj) v[j] += psi[r * NPMAX + j] * gv;
         }
     }
+    block_sum<NPMAX>(v, lds);
+    if (threadIdx.x == 0)
+        for (int j = 0; j < nj; ++j) c[k * NPMAX + j] = v[j];
+    if (!y) {
+        if (threadIdx.x == 0)
+            for (int j = 0; j < nj; ++j) e[k * NPMAX + j] = 0.0;
+        return;
+    }
+#pragma unroll
+    for (int j = 0; j < NPMAX; ++j) {
+        v[j] = 0.0;
+        if (j < nj) {
+            const int64_t eb = edge_ptr[k * NPMAX + j], ee = edge_ptr[k * NPMAX + j + 1];
+            for (int64_t r = eb + threadIdx.x; r < ee; r += blockDim.x) v[j] += y[edge_dev[r]];
+        }
+    }
+    block_sum<NPMAX>(v, lds);
+    if (threadIdx.x == 0)
+        for (int j = 0; j < nj; ++j) {
+            const int64_t cnt = edge_ptr[k * NPMAX + j + 1] - edge_ptr[k * NPMAX + j];
+            e[k * NPMAX + j] = cnt > 0 ? v[j] / (double)cnt : 0.0;
+        }
 }
 
-// One work-group: gPi = sum of contributions, uPi = Sinv gPi, coef[k][j] = uPi[R_kj] - e[k][j]
-__global__ __launch_bounds__(1024) void k_pri_coarse(int64_t npi, const int64_t* pri_ptr, const int64_t* pri_patch,
-                                                     const int64_t* pri_local, const double* c, const double* Sinv,
-                                                     double* gpi, double* upi, int npatch, const int32_t* npk,
-                                                     const int64_t* Rk, const double* e, double* coef) {
+// u_Pi = S_PiPi^{-1} g_Pi, 64 rows per work-group: every work-group first
+// assembles g_Pi (sum of the patch contributions c) in LDS, then its four
+// waves split the columns of the inverse (stored by columns: entry (r, K) at
+// Sinv[K * npi + r]) and their partial sums are added in a fixed order.
+__global__ __launch_bounds__(256) void k_pri_coarse(int64_t npi, const int64_t* pri_ptr, const int64_t* pri_patch,
+                                                    const int64_t* pri_local, const double* c, const double* Sinv,
+                                                    double* upi) {
+    extern __shared__ double sg[];
+    __shared__ double part[4][WAVE];
     for (int64_t J = threadIdx.x; J < npi; J += blockDim.x) {
         double s = 0.0;
         for (int64_t q = pri_ptr[J]; q < pri_ptr[J + 1]; ++q) s += c[pri_patch[q] * NPMAX + pri_local[q]];
-        gpi[J] = s;
+        sg[J] = s;
     }
     __syncthreads();
-    for (int64_t J = threadIdx.x; J < npi; J += blockDim.x) {
-        double s = 0.0;
-        for (int64_t K = 0; K < npi; ++K) s += Sinv[J * npi + K] * gpi[K];
-        upi[J] = s;
-    }
+    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+    const int64_t r = (int64_t)blockIdx.x * WAVE + lane;
+    double s = 0.0;
+    if (r < npi)
+        for (int64_t K = w; K < npi; K += 4) s += Sinv[K * npi + r] * sg[K];
+    part[w][lane] = s;
     __syncthreads();
-    for (int64_t q = threadIdx.x; q < (int64_t)npatch * NPMAX; q += blockDim.x) {
-        const int k = (int)(q / NPMAX), j = (int)(q % NPMAX);
-        coef[q] = j < npk[k] ? upi[Rk[q]] - e[q] : 0.0;
-    }
+    if (w == 0 && r < npi) upi[r] = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
+}
+
+// coef[k][j] = uPi[R_kj] - e[k][j]
+__global__ void k_pri_coef(int npatch, const int32_t* npk, const int64_t* Rk, const double* upi, const double* e,
+                           double* coef) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= (int64_t)npatch * NPMAX) return;
+    const int k = (int)(q / NPMAX), j = (int)(q % NPMAX);
+    coef[q] = j < npk[k] ? upi[Rk[q]] - e[q] : 0.0;
 }
 
 // y[slot] += sum_j psiG[slot][j] coef[k][j]

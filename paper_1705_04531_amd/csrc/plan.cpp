@@ -39,6 +39,7 @@ void default_options(ieti_options* o) {
     o->mg_precision = 64;
     o->primal = IETI_PRIMAL_VERTICES;
     o->cheb_degree = 0;
+    o->cheb_degree_coarse = 0;
     o->cheb_lower = 0.0;
     o->prec_vcycles = 2;
     o->max_it = 300;
@@ -59,12 +60,17 @@ void default_options(ieti_options* o) {
 // smoothing phase, lower end of its interval as a fraction of lambda_max),
 // from measured solve times on MI355X over a grid of both parameters: higher
 // degrees pay off because a V-cycle's coarse part costs about as much as
-// several finest-level sweeps.
+// several finest-level sweeps; the coarse levels, whose sweeps are latency
+// bound, take a lower degree.
 int cheb_degree_for(const ieti_options& o, int pmax) {
     if (o.cheb_degree > 0) return o.cheb_degree;
     if (pmax <= 2) return 3;
     if (pmax == 3) return 5;
     return 4;
+}
+int cheb_degree_coarse_for(const ieti_options& o, int pmax) {
+    if (o.cheb_degree_coarse > 0) return o.cheb_degree_coarse;
+    return pmax == 3 ? 3 : 2;
 }
 double cheb_lower_for(const ieti_options& o, int pmax) {
     if (o.cheb_lower > 0) return o.cheb_lower;
@@ -771,6 +777,8 @@ Plan* build_plan(const ieti_patch* in, int n, const double* pv, int n_pv, const 
     if (opt.check_every < 1) opt.check_every = 1;
     if (opt.coarse_level < -1) throw Error(IETI_EINVAL, "coarse_level must be >= -1");
     if (opt.coarse_dofs < 0) throw Error(IETI_EINVAL, "coarse_dofs must be >= 0");
+    if (opt.cheb_degree < 0 || opt.cheb_degree > 8 || opt.cheb_degree_coarse < 0 || opt.cheb_degree_coarse > 8)
+        throw Error(IETI_EINVAL, "Chebyshev degrees must be in 0..8");
     const int dim = in[0].dim;
     for (int k = 0; k < n; ++k) validate_patch(in[k], dim, k);
     auto P = std::make_unique<Plan>();

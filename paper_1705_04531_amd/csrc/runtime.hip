@@ -269,7 +269,8 @@ template <typename T>
 struct Solver : SolverBase {
     std::vector<DevLevel> lev;
     int N = 0, dim = 2, nlev = 0;
-    int cheb_m = 2;
+    int cheb_m = 2;     // Chebyshev degree per smoothing phase, finest level
+    int cheb_mc = 2;    // coarse levels
     double cheb_hi = 1.1;
     // level 0 FP64
     double* coef64 = nullptr;
@@ -296,7 +297,7 @@ struct Solver : SolverBase {
     int32_t* npk = nullptr;
     int64_t *Rk = nullptr, *unit_dev = nullptr, *edge_ptr = nullptr, *edge_dev = nullptr;
     int64_t *pri_ptr = nullptr, *pri_patch = nullptr, *pri_local = nullptr;
-    double *psi = nullptr, *psiG = nullptr, *Sinv = nullptr, *gpi = nullptr, *upi = nullptr;
+    double *psi = nullptr, *psiG = nullptr, *Sinv = nullptr, *upi = nullptr;
     double *cbuf = nullptr, *ebuf = nullptr, *coefbuf = nullptr;
     // groups and output
     int64_t ngroups = 0;
@@ -431,7 +432,8 @@ struct Solver : SolverBase {
             hipLaunchKernelGGL(k_cheb_zero<T>, dim3(tile_grid(D.nt_smooth)), dim3(TILE), 0, stream, D.L,
                                D.tiles_smooth, D.nt_smooth, (const T*)D.coefT, B, X, (T*)D.vd, mode, D.cheb, act);
             check_launch();
-            for (int k = 1; k < cheb_m; ++k) {
+            const int m = l == 0 ? cheb_m : cheb_mc;
+            for (int k = 1; k < m; ++k) {
                 stencil<T, T, T, EPI_CHEB>(l, true, mode, D.coefT, X, XA, B, D.vd, act, 0.0, k);
                 std::swap(X, XA);
             }
@@ -456,8 +458,9 @@ struct Solver : SolverBase {
                                   (const T*)D.pval, (const T*)cur[l + 1], X, mode, act);
                 check_launch();
             }
-            for (int k = 0; k < cheb_m; ++k) {
-                const bool last0 = l == 0 && k == cheb_m - 1;
+            const int m = l == 0 ? cheb_m : cheb_mc;
+            for (int k = 0; k < m; ++k) {
+                const bool last0 = l == 0 && k == m - 1;
                 stencil<T, T, T, EPI_CHEB>(l, true, mode, D.coefT, X, XA, B, D.vd, act, 0.0, k, nullptr, nullptr,
                                            last0 ? dotq : nullptr, last0 ? dpart : nullptr);
                 std::swap(X, XA);
@@ -486,7 +489,7 @@ struct Solver : SolverBase {
         a.b1 = lev[l0].vb;
         a.x1 = lev[l0].vxa;
         a.mode = mode;
-        a.m = cheb_m;
+        a.m = cheb_mc;
         a.active = act;
         for (int fam = 0; fam < 2; ++fam) {
             if (h_plist[fam].empty()) continue;
@@ -582,8 +585,11 @@ struct Solver : SolverBase {
                                full ? lev[0].L : nullptr, full ? psi : psiG, len0, g, fx, edge_ptr, edge_dev, cbuf,
                                ebuf);
             check_launch();
-            hipLaunchKernelGGL(k_pri_coarse, dim3(1), dim3(1024), 0, stream, npi, pri_ptr, pri_patch, pri_local, cbuf,
-                               Sinv, gpi, upi, N, npk, Rk, ebuf, coefbuf);
+            hipLaunchKernelGGL(k_pri_coarse, dim3(nblk(npi, WAVE)), dim3(256), npi * sizeof(double), stream, npi,
+                               pri_ptr, pri_patch, pri_local, cbuf, Sinv, upi);
+            check_launch();
+            hipLaunchKernelGGL(k_pri_coef, dim3(nblk((int64_t)N * NPMAX, 256)), dim3(256), 0, stream, N, npk, Rk, upi,
+                               ebuf, coefbuf);
             check_launch();
         }
         if (full) {
@@ -687,6 +693,8 @@ void Solver<T>::setup() {
     for (auto& pa : pl.patches)
         for (int d = 0; d < dim; ++d) pmax = std::max(pmax, pa.p[d]);
     cheb_m = cheb_degree_for(pl.opt, pmax);
+    cheb_mc = cheb_degree_coarse_for(pl.opt, pmax);
+    if (cheb_m > KMAX || cheb_mc > KMAX) throw Error(IETI_ENOTSUP, "Chebyshev degree above 8");
     lev.resize(nlev);
     // ---- descriptors, layouts, tiles
     for (int l = 0; l < nlev; ++l) {
@@ -1098,6 +1106,8 @@ void Solver<T>::setup() {
     }
     // ---- primal space
     npi = pl.n_primal;
+    // the coarse GEMV keeps g_Pi in LDS (64 KB)
+    if (npi > 8192) throw Error(IETI_ENOTSUP, "more than 8192 primal unknowns (dense coarse problem)");
     {
         std::vector<int32_t> nk(N);
         std::vector<int64_t> R((size_t)N * NPMAX, 0), ud((size_t)N * NPMAX, -1), ep((size_t)N * NPMAX + 1, 0), ed;
@@ -1134,7 +1144,6 @@ void Solver<T>::setup() {
         cbuf = arena.alloc<double>((int64_t)N * NPMAX, st);
         ebuf = arena.alloc<double>((int64_t)N * NPMAX, st);
         coefbuf = arena.alloc<double>((int64_t)N * NPMAX, st);
-        gpi = arena.alloc<double>(std::max<int64_t>(npi, 1), st);
         upi = arena.alloc<double>(std::max<int64_t>(npi, 1), st);
         psiG = arena.alloc<double>(std::max<int64_t>(nslots, 1) * NPMAX, st);
         HIPCHECK(hipStreamSynchronize(st));
@@ -1270,7 +1279,7 @@ void Solver<T>::setup() {
                 for (int64_t k = i + 1; k < n; ++k) t -= Cf[(size_t)k * n + i] * z[k];
                 z[i] = t / Cf[(size_t)i * n + i];
             }
-            for (int64_t i = 0; i < n; ++i) Si[(size_t)i * n + j] = z[i];
+            for (int64_t i = 0; i < n; ++i) Si[(size_t)j * n + i] = z[i];   // by columns
         }
         Sinv = arena.upload(Si, st);
         hipLaunchKernelGGL(k_psi_slots, dim3(nblk(std::max<int64_t>(nslots, 1), 256)), dim3(256), 0, st, nslots,
