@@ -299,6 +299,8 @@ enum Epi : int {
     EPI_RESID = 1,   // y = m (b - K x)
     EPI_CHEB = 2,    // r = b - K x; d = s1 d + s2 r / diag; y = x + d  (y, d written)
     EPI_DOTS = 3,    // y = m (K x); partial[tile] = (x . y, x . r64)
+    EPI_CHEB0 = 4,   // the first two Chebyshev steps from x = 0: x1 = d1 = m s2_0 b / diag (not stored),
+                     // then EPI_CHEB step 1 from x1 (finest-level staged instances only; x unused)
 };
 
 struct StencilArgs {
@@ -339,6 +341,43 @@ __host__ __device__ constexpr bool stencil_stages_x() {
     return FINE && P0 >= 0;
 }
 
+// The x window of a staged sweep: a copy of x, or for EPI_CHEB0 the first
+// Chebyshev iterate x1 = m s2_0 b / diag computed from b and the stencil's
+// diagonal (0 outside the patch).
+template <int EPI, typename TC, typename TX, typename TY>
+__device__ __forceinline__ void fill_window(TX* win, const StencilArgs& a, const PatchLev& P, const Tile& tl,
+                                            int reach, int w_len) {
+    if constexpr (EPI == EPI_CHEB0) {
+        const TY* b = (const TY*)a.b;
+        const TC* dg = (const TC*)a.coef + P.coff;
+        const double s2 = a.cheb[2 * (((int64_t)tl.pl * 2 + a.mode) * KMAX) + 1];
+        const int n = (int)P.n, M0 = P.M[0], M1 = P.M[1], M01 = M0 * M1;
+        constexpr int U = 4;
+        for (int base = threadIdx.x; base < w_len; base += U * TILE) {
+            double bv[U], dv[U];
+            bool on[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int j = base + u * TILE, g = tl.start - reach + j;
+                on[u] = j < w_len && g >= 0 && g < n;
+                if (on[u]) {
+                    const int g2 = g / M01, r = g - g2 * M01, g1 = r / M0, g0 = r - g1 * M0;
+                    on[u] = !masked_bits(P.mbits[a.mode], P.dim, M0, M1, P.M[2], g0, g1, g2);
+                }
+                bv[u] = on[u] ? (double)b[P.voff + g] : 0.0;
+                dv[u] = on[u] ? (double)dg[g] : 1.0;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int j = base + u * TILE;
+                if (j < w_len) win[j] = on[u] ? TX(s2 * bv[u] / dv[u]) : TX(0);
+            }
+        }
+    } else {
+        group_copy<4>(win, (const TX*)a.x + P.voff + tl.start - reach, w_len);
+    }
+}
+
 template <int P0, int P1, int P2, typename TC, typename TX, typename TY, int EPI, bool FINE>
 __device__ __forceinline__ void stencil_body(const StencilArgs& a, const Tile& tl, double* lds,
                                              unsigned char* st_lds_raw) {
@@ -365,7 +404,7 @@ __device__ __forceinline__ void stencil_body(const StencilArgs& a, const Tile& t
         const int reach = P2 * M01 + P1 * M0 + P0;
         TX* win = (TX*)st_lds_raw;
         const int w_len = min(tl.start + TILE, n) + 2 * reach - tl.start;   // clipped to the patch and its guards
-        group_copy<4>(win, x + P.voff + tl.start - reach, w_len);
+        fill_window<EPI, TC, TX, TY>(win, a, P, tl, reach, w_len);
         __syncthreads();
         const TX* xw = win + reach + (int)threadIdx.x;
         if (live) xi = xw[0];
@@ -390,7 +429,7 @@ __device__ __forceinline__ void stencil_body(const StencilArgs& a, const Tile& t
         const int reach = P1 * M0 + P0;
         TX* win = (TX*)st_lds_raw;
         const int w_len = min(tl.start + TILE, n) + 2 * reach - tl.start;   // clipped to the patch and its guards
-        group_copy<4>(win, x + P.voff + tl.start - reach, w_len);
+        fill_window<EPI, TC, TX, TY>(win, a, P, tl, reach, w_len);
         __syncthreads();
         const TX* xw = win + reach + (int)threadIdx.x;
         if (live) xi = xw[0];
@@ -423,7 +462,7 @@ __device__ __forceinline__ void stencil_body(const StencilArgs& a, const Tile& t
         } else if constexpr (EPI == EPI_RESID) {
             const TY* b = (const TY*)a.b;
             y[vi] = m ? TY(0) : TY(TC(b[vi]) - acc);
-        } else if constexpr (EPI == EPI_CHEB) {
+        } else if constexpr (EPI == EPI_CHEB || EPI == EPI_CHEB0) {
             const TY* b = (const TY*)a.b;
             TY* d = (TY*)a.d;
             if (m) {
@@ -433,7 +472,9 @@ __device__ __forceinline__ void stencil_body(const StencilArgs& a, const Tile& t
                 const double* cc = a.cheb + 2 * (((int64_t)tl.pl * 2 + a.mode) * KMAX + a.cheb_k);
                 const TC s1 = TC(cc[0]), s2 = TC(cc[1]);
                 const TC rr = TC(b[vi]) - acc;
-                const TC dn = (a.cheb_k > 0 ? s1 * TC(d[vi]) : TC(0)) + s2 * rr / diag;
+                // EPI_CHEB0: the previous direction d1 equals x1
+                const TC dprev = EPI == EPI_CHEB0 ? TC(xi) : (a.cheb_k > 0 ? TC(d[vi]) : TC(0));
+                const TC dn = (EPI == EPI_CHEB0 || a.cheb_k > 0 ? s1 * dprev : TC(0)) + s2 * rr / diag;
                 d[vi] = TY(dn);
                 const TY yn = TY(TC(xi) + dn);
                 y[vi] = yn;
@@ -455,7 +496,7 @@ __device__ __forceinline__ void stencil_body(const StencilArgs& a, const Tile& t
             a.partial[2 * tl.gid + 1] = dv[1];
         }
     }
-    if constexpr (EPI == EPI_CHEB) {
+    if constexpr (EPI == EPI_CHEB || EPI == EPI_CHEB0) {
         if (a.dotq) {
             double dv[1] = {dv0};
             block_sum<1>(dv, lds);
@@ -811,7 +852,10 @@ __global__ __launch_bounds__(TILE) void k_fcg_dir(const PatchLev* L, const Tile*
 
 // alpha = sum(d.r) / sum(d.q) over the patch's tiles; x += alpha d, r -= alpha q,
 // rT = r, prr = |r|^2 per tile.  The patch's first tile stores dq (for the next
-// beta) and flags a breakdown (dq <= 0: alpha = 0).
+// beta) and flags a breakdown (dq <= 0: alpha = 0).  (The convergence test
+// stays a kernel of its own: folding it in through a per-patch arrival
+// counter needs a device-scope release fence per work-group, which writes
+// back the XCD's L2 and costs more than the launch.)
 template <typename T>
 __global__ __launch_bounds__(TILE) void k_fcg_update(const PatchLev* L, const Tile* tiles, int ntiles,
                                                      const double* d, const double* q, double* x, double* r, T* rT,
@@ -946,8 +990,11 @@ __global__ __launch_bounds__(TILE) void k_pri_dots(int npatch, const int32_t* np
         }
     }
     block_sum<NPMAX>(v, lds);
-    if (threadIdx.x == 0)
-        for (int j = 0; j < nj; ++j) c[k * NPMAX + j] = v[j];
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int j = 0; j < NPMAX; ++j)
+            if (j < nj) c[k * NPMAX + j] = v[j];
+    }
     if (!y) {
         if (threadIdx.x == 0)
             for (int j = 0; j < nj; ++j) e[k * NPMAX + j] = 0.0;
@@ -962,11 +1009,14 @@ __global__ __launch_bounds__(TILE) void k_pri_dots(int npatch, const int32_t* np
         }
     }
     block_sum<NPMAX>(v, lds);
-    if (threadIdx.x == 0)
-        for (int j = 0; j < nj; ++j) {
-            const int64_t cnt = edge_ptr[k * NPMAX + j + 1] - edge_ptr[k * NPMAX + j];
-            e[k * NPMAX + j] = cnt > 0 ? v[j] / (double)cnt : 0.0;
-        }
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int j = 0; j < NPMAX; ++j)
+            if (j < nj) {
+                const int64_t cnt = edge_ptr[k * NPMAX + j + 1] - edge_ptr[k * NPMAX + j];
+                e[k * NPMAX + j] = cnt > 0 ? v[j] / (double)cnt : 0.0;
+            }
+    }
 }
 
 // u_Pi = S_PiPi^{-1} g_Pi, 64 rows per work-group: every work-group first

@@ -271,6 +271,7 @@ struct Solver : SolverBase {
     int N = 0, dim = 2, nlev = 0;
     int cheb_m = 2;     // Chebyshev degree per smoothing phase, finest level
     int cheb_mc = 2;    // coarse levels
+    bool stage_all0 = false;   // every finest-level smoothing tile runs a staged (x window in LDS) instance
     double cheb_hi = 1.1;
     // level 0 FP64
     double* coef64 = nullptr;
@@ -389,8 +390,14 @@ struct Solver : SolverBase {
             }
             const int reach = c == MULTI_2D ? reach2d : D.reach[c];
             const bool window_fits = (size_t)(TILE + 2 * reach) * sizeof(TX) <= STAGE_X_MAX_BYTES;
-            if (l == 0 && window_fits) launch_stencil<TC, TX, TY, EPI, true>(c, stream, a, reach, ev.first, ev.second);
-            else launch_stencil<TC, TX, TY, EPI, false>(c, stream, a, reach, ev.first, ev.second);
+            if constexpr (EPI == EPI_CHEB0) {   // staged finest-level instances only (vcycle checks stage_all0)
+                launch_stencil<TC, TX, TY, EPI, true>(c, stream, a, reach, ev.first, ev.second);
+            } else {
+                if (l == 0 && window_fits)
+                    launch_stencil<TC, TX, TY, EPI, true>(c, stream, a, reach, ev.first, ev.second);
+                else
+                    launch_stencil<TC, TX, TY, EPI, false>(c, stream, a, reach, ev.first, ev.second);
+            }
             check_launch();
         }
     }
@@ -426,14 +433,21 @@ struct Solver : SolverBase {
             cur[l] = F;
             deepest = l;
             if (D.nt_smooth == 0) break;
-            // pre-smoothing: Chebyshev from zero
+            // pre-smoothing: Chebyshev from zero (on the finest level the zero start is fused into step 1)
             T* X = S;
             T* XA = F;
-            hipLaunchKernelGGL(k_cheb_zero<T>, dim3(tile_grid(D.nt_smooth)), dim3(TILE), 0, stream, D.L,
-                               D.tiles_smooth, D.nt_smooth, (const T*)D.coefT, B, X, (T*)D.vd, mode, D.cheb, act);
-            check_launch();
             const int m = l == 0 ? cheb_m : cheb_mc;
-            for (int k = 1; k < m; ++k) {
+            int k1 = 1;
+            if (l == 0 && m >= 2 && stage_all0) {
+                stencil<T, T, T, EPI_CHEB0>(0, true, mode, D.coefT, nullptr, XA, B, D.vd, act, 0.0, 1);
+                std::swap(X, XA);
+                k1 = 2;
+            } else {
+                hipLaunchKernelGGL(k_cheb_zero<T>, dim3(tile_grid(D.nt_smooth)), dim3(TILE), 0, stream, D.L,
+                                   D.tiles_smooth, D.nt_smooth, (const T*)D.coefT, B, X, (T*)D.vd, mode, D.cheb, act);
+                check_launch();
+            }
+            for (int k = k1; k < m; ++k) {
                 stencil<T, T, T, EPI_CHEB>(l, true, mode, D.coefT, X, XA, B, D.vd, act, 0.0, k);
                 std::swap(X, XA);
             }
@@ -802,6 +816,13 @@ void Solver<T>::setup() {
                 }
             }
         D.cheb = arena.upload(ch, st);
+        if (l == 0) {
+            stage_all0 = true;
+            for (int c = 0; c <= NCLASS; ++c) {
+                if (D.cls_end_sm[c] <= D.cls_beg_sm[c]) continue;
+                if (c == NCLASS || (size_t)(TILE + 2 * D.reach[c]) * sizeof(T) > STAGE_X_MAX_BYTES) stage_all0 = false;
+            }
+        }
         HIPCHECK(hipStreamSynchronize(st));
     }
     // ---- transfer tables, stencils, inverses
