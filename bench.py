@@ -234,6 +234,21 @@ def main():
                  "speedup_inexact_over_plain": round(pms / ms_per_step, 3),
                  "rel_l2_diff_inexact_vs_plain": diff}
         ps.close()
+        # D-MG: exact Neumann solves in F, V-cycles (FP64 and FP32) for the preconditioner's Dirichlet problems
+        for prec in (64, 32):
+            ds = Solver(wl.patches, options_for(wl, local_solver=_abi.IETI_LOCAL_EXACT_MG, mg_precision=prec))
+            ud = torch.empty_like(u)
+            ds.solve(f, ud)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                _, dst = ds.solve(f, ud)
+            torch.cuda.synchronize()
+            dms = (time.perf_counter() - t0) / args.steps * 1e3
+            plain[f"exact_neumann_mg{prec}_dirichlet"] = {
+                "ms_per_step": round(dms, 3), "outer_iterations": dst["outer_iterations"],
+                "rel_l2_diff_vs_plain": float(torch.linalg.norm(ud - up) / torch.linalg.norm(up))}
+            ds.close()
 
     dom = prof[_abi.IETI_KPROF_SMOOTH_FINE]
     achieved = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9 if dom["ms"] > 0 else 0.0

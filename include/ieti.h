@@ -52,6 +52,8 @@ extern "C" {
 /* ---- options ---- */
 #define IETI_LOCAL_MG     0   /* inexact local solves: flexible CG + multigrid V-cycle (MG-MG) */
 #define IETI_LOCAL_EXACT  1   /* exact local solves: banded Cholesky (D-D) */
+#define IETI_LOCAL_EXACT_MG 2 /* exact Neumann solves in F, d and the recovery; multigrid V-cycles for the
+                                 Dirichlet problems of the preconditioner (D-MG, Sec. 3.3) */
 
 #define IETI_PRIMAL_VERTICES  1   /* primal unknowns at patch vertices */
 #define IETI_PRIMAL_EDGES     2   /* plus edge averages (3D: patch edges; 2D: patch sides) */
@@ -65,7 +67,7 @@ typedef struct ieti_patch {
 } ieti_patch;
 
 typedef struct ieti_options {
-    int32_t local_solver;      /* IETI_LOCAL_MG (default) or IETI_LOCAL_EXACT */
+    int32_t local_solver;      /* IETI_LOCAL_MG (default), IETI_LOCAL_EXACT or IETI_LOCAL_EXACT_MG */
     int32_t mg_precision;      /* 32 or 64: arithmetic of V-cycles and their operator data (default 64) */
     int32_t primal;            /* IETI_PRIMAL_VERTICES (default) or IETI_PRIMAL_VERTICES|IETI_PRIMAL_EDGES */
     int32_t cheb_degree;       /* Chebyshev smoother degree per smoothing phase; 0 = tuned per spline degree */

@@ -19,6 +19,7 @@ IETI_PENDING = 1
 
 IETI_LOCAL_MG = 0
 IETI_LOCAL_EXACT = 1
+IETI_LOCAL_EXACT_MG = 2
 IETI_PRIMAL_VERTICES = 1
 IETI_PRIMAL_EDGES = 2
 

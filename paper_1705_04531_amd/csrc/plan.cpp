@@ -769,7 +769,8 @@ Plan* build_plan(const ieti_patch* in, int n, const double* pv, int n_pv, const 
     ieti_options opt;
     if (optp) opt = *optp; else default_options(&opt);
     if (opt.mg_precision != 32 && opt.mg_precision != 64) throw Error(IETI_EINVAL, "mg_precision must be 32 or 64");
-    if (opt.local_solver != IETI_LOCAL_MG && opt.local_solver != IETI_LOCAL_EXACT)
+    if (opt.local_solver != IETI_LOCAL_MG && opt.local_solver != IETI_LOCAL_EXACT &&
+        opt.local_solver != IETI_LOCAL_EXACT_MG)
         throw Error(IETI_EINVAL, "unknown local solver");
     if (!(opt.tol > 0) || !(opt.inner_tol > 0) || !(opt.basis_tol > 0) || opt.max_it <= 0 || opt.inner_max_it <= 0)
         throw Error(IETI_EINVAL, "tolerances and iteration limits must be positive");
@@ -1181,7 +1182,9 @@ Plan* build_plan(const ieti_patch* in, int n, const double* pv, int n_pv, const 
         pa.affine = aff;
         // levels: halve while every direction has an even number (>= 6) of elements
         // and the level is larger than coarse_dofs
-        while (opt.local_solver == IETI_LOCAL_MG) {
+        const bool mg = opt.local_solver != IETI_LOCAL_EXACT;              // some problems by multigrid
+        const bool neumann_mg = opt.local_solver == IETI_LOCAL_MG;         // the Neumann problems too
+        while (mg) {
             const Level& f = pa.lv.back();
             bool ok = opt.coarse_dofs == 0 || f.n > opt.coarse_dofs;
             for (int d = 0; d < dim; ++d)
@@ -1207,6 +1210,8 @@ Plan* build_plan(const ieti_patch* in, int n, const double* pv, int n_pv, const 
         pl.max_levels = std::max(pl.max_levels, (int)pa.lv.size());
     }
     parallel_for(n, [&](int k) {
+        const bool mg = opt.local_solver != IETI_LOCAL_EXACT;
+        const bool neumann_mg = opt.local_solver == IETI_LOCAL_MG;
         Patch& pa = pl.patches[k];
         for (size_t l = 0; l < pa.lv.size(); ++l) assemble_level(pa, pa.lv[l], l == 0);
         for (size_t l = 0; l + 1 < pa.lv.size(); ++l) {
@@ -1218,21 +1223,22 @@ Plan* build_plan(const ieti_patch* in, int n, const double* pv, int n_pv, const 
                 f.Mc[d] = Mc;
             }
         }
-        if (opt.local_solver == IETI_LOCAL_MG)
+        if (mg)
             for (size_t l = 0; l + 1 < pa.lv.size(); ++l) {
-                pa.lv[l].lmax[MODE_N] = power_lmax(pa, pa.lv[l], MODE_N);
+                if (neumann_mg) pa.lv[l].lmax[MODE_N] = power_lmax(pa, pa.lv[l], MODE_N);
                 pa.lv[l].lmax[MODE_D] = power_lmax(pa, pa.lv[l], MODE_D);
             }
         Level& cl = pa.lv.back();
-        if (opt.local_solver == IETI_LOCAL_MG) {
-            cl.inv[MODE_N] = dense_inverse(pa, cl, MODE_N);
+        if (mg) {
+            if (neumann_mg) cl.inv[MODE_N] = dense_inverse(pa, cl, MODE_N);
             cl.inv[MODE_D] = dense_inverse(pa, cl, MODE_D);
-        } else {
+        }
+        if (!neumann_mg) {
             const Level& L0 = pa.lv[0];
             pa.band_b = L0.guard;
             pa.band_nblk = (L0.n + BAND_NB - 1) / BAND_NB;
             band_factor(pa, L0, MODE_N, pa.band_b, pa.band[MODE_N]);
-            band_factor(pa, L0, MODE_D, pa.band_b, pa.band[MODE_D]);
+            if (!mg) band_factor(pa, L0, MODE_D, pa.band_b, pa.band[MODE_D]);
         }
     });
     int64_t nq = 0;

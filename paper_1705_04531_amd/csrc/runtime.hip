@@ -312,8 +312,9 @@ struct Solver : SolverBase {
     double *lam = nullptr, *lr = nullptr, *lz = nullptr, *lp = nullptr, *lq = nullptr, *ltmp = nullptr;
     double* sc = nullptr;
     double* h_sc = nullptr;    // pinned
-    // exact local solves (banded Cholesky factors, blocked triangular solves)
-    bool exact = false;
+    // exact local solves (banded Cholesky factors, blocked triangular solves): Neumann problems
+    // (exact), also the preconditioner's Dirichlet problems (prec_exact)
+    bool exact = false, prec_exact = false;
     int64_t* band_off = nullptr;
     int32_t* band_b = nullptr;
     double* band = nullptr;
@@ -651,13 +652,13 @@ struct Solver : SolverBase {
         scatter(r, true, w64);
         // b_I = -m_D (K v)
         stencil<double, double, T, EPI_APPLY>(0, false, MODE_D, coef64, w64, bT, nullptr, nullptr, nullptr, -1.0, 0);
-        if (exact) {
+        if (prec_exact) {
             if (!std::is_same<T, double>::value) throw Error(IETI_EDEVICE, "internal: exact solves need FP64");
             band_solve(MODE_D, (const double*)bT, (double*)xIT);
         } else {
             vcycle(MODE_D, nullptr, bT, xIT);
         }
-        for (int c = 1; !exact && c < plan->opt.prec_vcycles; ++c) {
+        for (int c = 1; !prec_exact && c < plan->opt.prec_vcycles; ++c) {
             stencil<T, T, T, EPI_RESID>(0, false, MODE_D, D.coefT, xIT, r2T, bT, nullptr, nullptr, 0.0, 0);
             vcycle(MODE_D, nullptr, r2T, x2T);
             hipLaunchKernelGGL(k_add<T>, dim3(tile_grid(D.nt_all)), dim3(TILE), 0, stream, D.L, D.tiles_all, D.nt_all,
@@ -877,13 +878,14 @@ void Solver<T>::setup() {
                         }
                     }
                 }
-            } else if (pl.opt.local_solver == IETI_LOCAL_MG) {
-                // stored by columns: entry (r, j) at j * n + r
+            } else if (pl.opt.local_solver != IETI_LOCAL_EXACT) {
+                // stored by columns: entry (r, j) at j * n + r; a mode without multigrid (D-MG: Neumann) holds zeros
                 P.invoff = (int64_t)inv.size();
                 const int64_t n = L.n;
                 for (int m = 0; m < 2; ++m)
                     for (int64_t j = 0; j < n; ++j)
-                        for (int64_t r = 0; r < n; ++r) inv.push_back(T(L.inv[m][(size_t)(r * n + j)]));
+                        for (int64_t r = 0; r < n; ++r)
+                            inv.push_back(L.inv[m].empty() ? T(0) : T(L.inv[m][(size_t)(r * n + j)]));
             }
         }
         D.L = arena.upload(D.hL, st);
@@ -913,7 +915,7 @@ void Solver<T>::setup() {
     // launches of a coarse level cost more than the fused kernel's sweeps);
     // the lowest level from which the vectors fit if level 1 does not.
     fuse_l0 = nlev;
-    if (nlev > 1 && nlev <= LMAX && pl.opt.local_solver == IETI_LOCAL_MG && pl.opt.coarse_level >= 0) {
+    if (nlev > 1 && nlev <= LMAX && pl.opt.local_solver != IETI_LOCAL_EXACT && pl.opt.coarse_level >= 0) {
         int dev = 0;
         HIPCHECK(hipGetDevice(&dev));
         int max_lds = 0;
@@ -974,8 +976,9 @@ void Solver<T>::setup() {
         HIPCHECK(hipStreamSynchronize(st));
     }
     // ---- exact local solves
-    if (pl.opt.local_solver == IETI_LOCAL_EXACT) {
+    if (pl.opt.local_solver != IETI_LOCAL_MG) {
         exact = true;
+        prec_exact = pl.opt.local_solver == IETI_LOCAL_EXACT;
         int dev = 0, max_lds = 0;
         HIPCHECK(hipGetDevice(&dev));
         HIPCHECK(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
@@ -1361,7 +1364,7 @@ int Solver<T>::solve(const double* f_qp, double* u_out, ieti_stats* stp) {
     int it = 0;
     bool conv = true;
     double rnorm = r0;
-    const double zero_thr = (pl.opt.local_solver == IETI_LOCAL_EXACT ? 1e-13 : 10.0 * pl.opt.inner_tol) * scale;
+    const double zero_thr = (exact ? 1e-13 : 10.0 * pl.opt.inner_tol) * scale;
     if (nl > 0 && r0 > zero_thr && r0 > 0.0) {
         applyPrec(lr, lz);
         hipLaunchKernelGGL(k_pcg, dim3(1), dim3(1024), 0, stream, 0, nl, lam, lr, lz, lp, lq, sc);
@@ -1478,7 +1481,7 @@ extern "C" {
 static ieti_handle* make_handle(std::unique_ptr<Plan> plan) {
     if (plan->opt.device >= 0) HIPCHECK(hipSetDevice(plan->opt.device));
     std::unique_ptr<SolverBase> s;
-    if (plan->opt.mg_precision == 32 && plan->opt.local_solver == IETI_LOCAL_MG) s.reset(new Solver<float>());
+    if (plan->opt.mg_precision == 32 && plan->opt.local_solver != IETI_LOCAL_EXACT) s.reset(new Solver<float>());
     else s.reset(new Solver<double>());
     s->plan = std::move(plan);
     if (s->plan->opt.stream) {

@@ -163,3 +163,20 @@ def test_band_cholesky_factor(lib, mode):
         A[:, m] = 0.0
         A[m, m] = 1.0
         assert np.abs(Ld @ Ld.T - A).max() <= 1e-12 * np.abs(A).max()
+
+
+def test_exact_neumann_mg_dirichlet_plan(lib):
+    """D-MG plans hold the banded factor of the Neumann problems only and a
+    multigrid hierarchy (for the Dirichlet problems); MG plans hold no factor."""
+    wl = W.deformed_square((2, 2), 3, 32, seed=0)      # 1225 coefficients per patch: two levels
+    pl = Plan(wl.patches, default_options(local_solver=_abi.IETI_LOCAL_EXACT_MG))
+    assert pl.sizes()["max_levels"] >= 2
+    assert pl.array(_abi.IETI_ARR_BAND, 0, 0).size > 0
+    with pytest.raises(_abi.IetiError):          # no Dirichlet factor
+        pl.array(_abi.IETI_ARR_BAND, 0, 1)
+    pm = Plan(wl.patches, default_options(local_solver=_abi.IETI_LOCAL_MG))
+    assert pm.sizes()["max_levels"] == pl.sizes()["max_levels"]
+    with pytest.raises(_abi.IetiError):          # no factor at all
+        pm.array(_abi.IETI_ARR_BAND, 0, 0)
+    with pytest.raises(_abi.IetiError):
+        Plan(wl.patches, default_options(local_solver=3))

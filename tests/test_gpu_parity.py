@@ -79,3 +79,19 @@ def test_exact_local_matches_oracle(require_gpu, name, make):
     print(f"{name} exact: err={err:.3e} outer={st['outer_iterations']} breakdown={st['breakdown']}", flush=True)
     assert err <= 1e-9
     assert st["inner_iterations_mean"] == 0
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+@pytest.mark.parametrize("name,make", EXACT_CASES[1:], ids=[c[0] for c in EXACT_CASES[1:]])
+def test_exact_neumann_mg_dirichlet_matches_oracle(require_gpu, name, make, prec):
+    """D-MG: exact Neumann solves in F with multigrid V-cycles for the Dirichlet
+    problems of the preconditioner reproduce the oracle (the preconditioner
+    changes only the iteration count)."""
+    from paper_1705_04531_amd import _abi
+    wl = make()
+    u_ref, lay, _ = oracle_solution(wl)
+    u, st = run_gpu(wl, local_solver=_abi.IETI_LOCAL_EXACT_MG, mg_precision=prec, tol=1e-10)
+    err = rel_err(wl, u, u_ref, lay)
+    print(f"{name} D-MG prec={prec}: err={err:.3e} outer={st['outer_iterations']}", flush=True)
+    assert err <= 1e-9
+    assert st["inner_iterations_mean"] == 0
