@@ -87,6 +87,9 @@ typedef struct ieti_options {
     size_t  hbm_budget;        /* bytes of device memory the handle may use, 0 = unlimited */
     int32_t coarse_level;      /* first multigrid level run by the per-patch fused coarse kernel: 0 = chosen
                                   from the LDS size (default), -1 = none (every level by batched launches) */
+    int32_t autotune;          /* 1: at setup, time one batched local solve per candidate smoother (finest and
+                                  coarse Chebyshev degrees, interval lower end) around the tuned table and keep
+                                  the fastest; 0: the table (default) */
     int32_t coarse_dofs;       /* multigrid: a patch level with at most this many coefficients is not
                                   coarsened further (dense exact solve there); 0 = no such limit. Coarsening
                                   also stops where a direction's element count is odd or below 6 (default 600) */
@@ -108,6 +111,9 @@ typedef struct ieti_stats {
     int64_t n_lambda;
     int64_t n_primal;
     int32_t breakdown;                 /* 1 if d vanished to rounding and lambda = 0 was returned */
+    int32_t cheb_degree;               /* smoother in use: Chebyshev degree on the finest level, */
+    int32_t cheb_degree_coarse;        /* on the coarser levels, */
+    double  cheb_lower;                /* and the interval's lower end over the tuned table's (1 = table) */
 } ieti_stats;
 
 typedef struct ieti_handle ieti_handle;

@@ -69,6 +69,7 @@ class IetiOptions(C.Structure):
         ("stream", C.c_void_p),
         ("hbm_budget", C.c_size_t),
         ("coarse_level", C.c_int32),
+        ("autotune", C.c_int32),
         ("coarse_dofs", C.c_int32),
     ]
 
@@ -90,6 +91,9 @@ class IetiStats(C.Structure):
         ("n_lambda", C.c_int64),
         ("n_primal", C.c_int64),
         ("breakdown", C.c_int32),
+        ("cheb_degree", C.c_int32),
+        ("cheb_degree_coarse", C.c_int32),
+        ("cheb_lower", C.c_double),
     ]
 
     def as_dict(self):

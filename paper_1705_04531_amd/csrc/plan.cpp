@@ -51,6 +51,7 @@ void default_options(ieti_options* o) {
     o->use_graph = 1;
     o->coarse_level = 0;
     o->coarse_dofs = 600;
+    o->autotune = 0;
     o->device = -1;
     o->stream = nullptr;
     o->hbm_budget = 0;

@@ -675,6 +675,86 @@ struct Solver : SolverBase {
     }
 
     // ---------------------------------------------------------------- setup
+    // Chebyshev coefficients d_k = s1 d_{k-1} + s2 D^{-1} r_k on [lower_scale clo, hi] lambda_max,
+    // per (patch-level, mode, step)
+    static std::vector<double> cheb_table(const DevLevel& D, double hi, double lower_scale) {
+        std::vector<double> ch(D.hL.size() * 2 * KMAX * 2, 0.0);
+        for (size_t i = 0; i < D.hL.size(); ++i)
+            for (int m = 0; m < 2; ++m) {
+                const double lm = D.hL[i].lmax[m] > 0 ? D.hL[i].lmax[m] : 1.0;
+                const double aa = std::min(D.hL[i].clo * lower_scale, 0.5) * lm, bb = hi * lm;
+                const double theta = 0.5 * (aa + bb), delta = 0.5 * (bb - aa), sigma = theta / delta;
+                double rho_prev = 1.0 / sigma, rho = rho_prev;
+                for (int k = 0; k < KMAX; ++k) {
+                    double s1 = 0.0, s2 = 1.0 / theta;
+                    if (k > 0) {
+                        rho_prev = rho;
+                        rho = 1.0 / (2.0 * sigma - rho_prev);
+                        s1 = rho * rho_prev;
+                        s2 = 2.0 * rho / delta;
+                    }
+                    const size_t o = 2 * ((i * 2 + m) * KMAX + k);
+                    ch[o] = s1;
+                    ch[o + 1] = s2;
+                }
+            }
+        return ch;
+    }
+    double cheb_lower_scale = 1.0;
+    void set_smoother(int m, int mc, double lower_scale) {
+        cheb_m = m;
+        cheb_mc = mc;
+        cheb_lower_scale = lower_scale;
+        for (int l = 0; l < nlev; ++l) {
+            const std::vector<double> ch = cheb_table(lev[l], cheb_hi, lower_scale);
+            HIPCHECK(hipMemcpyAsync(lev[l].cheb, ch.data(), ch.size() * sizeof(double), hipMemcpyHostToDevice, stream));
+        }
+        sync();
+    }
+    // Times one batched Neumann solve (a seeded right-hand side, to inner_tol) per
+    // candidate smoother around the tuned table and keeps the fastest.
+    void autotune_smoother() {
+        if (exact || nlev < 2) return;
+        std::vector<double> h(len0);
+        uint64_t x = 0x9E3779B97F4A7C15ull;
+        for (auto& v : h) {
+            x ^= x << 13; x ^= x >> 7; x ^= x << 17;
+            v = (double)(x >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+        }
+        HIPCHECK(hipMemcpyAsync(e64, h.data(), len0 * sizeof(double), hipMemcpyHostToDevice, stream));
+        sync();
+        hipEvent_t e0, e1;
+        HIPCHECK(hipEventCreate(&e0));
+        HIPCHECK(hipEventCreate(&e1));
+        const int m0 = cheb_m, mc0 = cheb_mc;
+        int best_m = m0, best_mc = mc0;
+        double best_s = 1.0, best_ms = 1e300;
+        const double scales[3] = {0.67, 1.0, 1.5};
+        for (int m = std::max(2, m0 - 1); m <= std::min(KMAX - 1, m0 + 1); ++m)
+            for (int mc = 2; mc <= 3; ++mc)
+                for (double sc : scales) {
+                    set_smoother(m, mc, sc);
+                    double ms = 1e300;
+                    for (int rep = 0; rep < 2; ++rep) {
+                        HIPCHECK(hipEventRecord(e0, stream));
+                        fcg(e64, plan->opt.inner_tol, plan->opt.inner_max_it);
+                        HIPCHECK(hipEventRecord(e1, stream));
+                        HIPCHECK(hipEventSynchronize(e1));
+                        float t = 0.f;
+                        HIPCHECK(hipEventElapsedTime(&t, e0, e1));
+                        ms = std::min(ms, (double)t);
+                    }
+                    if (ms < best_ms) {
+                        best_ms = ms;
+                        best_m = m;
+                        best_mc = mc;
+                        best_s = sc;
+                    }
+                }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        set_smoother(best_m, best_mc, best_s);
+    }
     void setup() override;
     int solve(const double* f_qp, double* u, ieti_stats* st) override;
     void quadrature(double* x, bool on_device) override {
@@ -795,28 +875,7 @@ void Solver<T>::setup() {
                 D.st_smooth[c] += (double)P.n * P.nst;
             }
         }
-        // Chebyshev coefficients d_k = s1 d_{k-1} + s2 D^{-1} r_k on [clo, hi] * lambda_max
-        std::vector<double> ch(D.hL.size() * 2 * KMAX * 2, 0.0);
-        for (size_t i = 0; i < D.hL.size(); ++i)
-            for (int m = 0; m < 2; ++m) {
-                const double lm = D.hL[i].lmax[m] > 0 ? D.hL[i].lmax[m] : 1.0;
-                const double aa = D.hL[i].clo * lm, bb = hi * lm;
-                const double theta = 0.5 * (aa + bb), delta = 0.5 * (bb - aa), sigma = theta / delta;
-                double rho_prev = 1.0 / sigma, rho = rho_prev;
-                for (int k = 0; k < KMAX; ++k) {
-                    double s1 = 0.0, s2 = 1.0 / theta;
-                    if (k > 0) {
-                        rho_prev = rho;
-                        rho = 1.0 / (2.0 * sigma - rho_prev);
-                        s1 = rho * rho_prev;
-                        s2 = 2.0 * rho / delta;
-                    }
-                    const size_t o = 2 * ((i * 2 + m) * KMAX + k);
-                    ch[o] = s1;
-                    ch[o + 1] = s2;
-                }
-            }
-        D.cheb = arena.upload(ch, st);
+        D.cheb = arena.upload(cheb_table(D, hi, 1.0), st);
         if (l == 0) {
             stage_all0 = true;
             for (int c = 0; c <= NCLASS; ++c) {
@@ -1312,6 +1371,7 @@ void Solver<T>::setup() {
         sync();
     }
     sync();
+    if (pl.opt.autotune) autotune_smoother();
 }
 
 template <typename T>
@@ -1327,6 +1387,9 @@ int Solver<T>::solve(const double* f_qp, double* u_out, ieti_stats* stp) {
     st.ndof_global = pl.ndof_global;
     st.n_lambda = pl.n_lambda;
     st.n_primal = pl.n_primal;
+    st.cheb_degree = exact && prec_exact ? 0 : cheb_m;
+    st.cheb_degree_coarse = exact && prec_exact ? 0 : cheb_mc;
+    st.cheb_lower = cheb_lower_scale;
     DevLevel& D0 = lev[0];
     sync();
     auto t0 = clk::now();

@@ -26,14 +26,19 @@ CASES_3D = [
 ]
 
 
+@pytest.mark.parametrize("hierarchy", ["default", "full"])
 @pytest.mark.parametrize("prec", [64, 32])
 @pytest.mark.parametrize("name,make", CASES_2D + CASES_3D, ids=[c[0] for c in CASES_2D + CASES_3D])
-def test_solution_matches_oracle(require_gpu, name, make, prec):
+def test_solution_matches_oracle(require_gpu, name, make, prec, hierarchy):
+    """hierarchy "default": coarsening stops at 600 coefficients (most of these small
+    patches are then solved on one level); "full": coarse_dofs = 0 forces the whole
+    h-hierarchy, so the V-cycle kernels (smoothing, transfers, fused coarse levels) run."""
     wl = make()
     u_ref, lay, _ = oracle_solution(wl)
-    u, st = run_gpu(wl, mg_precision=prec, tol=1e-10)
+    extra = {"coarse_dofs": 0} if hierarchy == "full" else {}
+    u, st = run_gpu(wl, mg_precision=prec, tol=1e-10, **extra)
     err = rel_err(wl, u, u_ref, lay)
-    print(f"{name} prec={prec}: err={err:.3e} outer={st['outer_iterations']} "
+    print(f"{name} prec={prec} {hierarchy}: err={err:.3e} outer={st['outer_iterations']} "
           f"inner mean={st['inner_iterations_mean']:.1f} max={st['inner_iterations_max']} "
           f"res={st['global_residual']:.2e}", flush=True)
     assert err <= 1e-8
@@ -95,3 +100,19 @@ def test_exact_neumann_mg_dirichlet_matches_oracle(require_gpu, name, make, prec
     print(f"{name} D-MG prec={prec}: err={err:.3e} outer={st['outer_iterations']}", flush=True)
     assert err <= 1e-9
     assert st["inner_iterations_mean"] == 0
+
+
+def test_autotuned_smoother_matches_oracle(require_gpu):
+    """The setup-time smoother autotuner changes only the speed: the solution
+    still matches the oracle, and the chosen smoother lies in the candidate
+    grid around the tuned table."""
+    wl = CASES_2D[2][1]()
+    u_ref, lay, _ = oracle_solution(wl)
+    u0, st0 = run_gpu(wl, tol=1e-10)
+    u, st = run_gpu(wl, tol=1e-10, autotune=1)
+    err = rel_err(wl, u, u_ref, lay)
+    print(f"autotune: err={err:.3e} degree {st0['cheb_degree']}/{st0['cheb_degree_coarse']} -> "
+          f"{st['cheb_degree']}/{st['cheb_degree_coarse']} lower x{st['cheb_lower']}", flush=True)
+    assert err <= 1e-9
+    assert abs(st["cheb_degree"] - st0["cheb_degree"]) <= 1 and st["cheb_degree_coarse"] in (2, 3)
+    assert st["cheb_lower"] in (0.67, 1.0, 1.5) and st0["cheb_lower"] == 1.0
