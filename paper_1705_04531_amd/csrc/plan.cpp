@@ -48,7 +48,7 @@ void default_options(ieti_options* o) {
     o->inner_tol = 1e-10;
     o->basis_tol = 1e-12;
     o->check_every = 4;
-    o->use_graph = 1;
+    o->use_graph = 0;
     o->coarse_level = 0;
     o->coarse_dofs = 600;
     o->autotune = 0;
@@ -1184,7 +1184,6 @@ Plan* build_plan(const ieti_patch* in, int n, const double* pv, int n_pv, const 
         // levels: halve while every direction has an even number (>= 6) of elements
         // and the level is larger than coarse_dofs
         const bool mg = opt.local_solver != IETI_LOCAL_EXACT;              // some problems by multigrid
-        const bool neumann_mg = opt.local_solver == IETI_LOCAL_MG;         // the Neumann problems too
         while (mg) {
             const Level& f = pa.lv.back();
             bool ok = opt.coarse_dofs == 0 || f.n > opt.coarse_dofs;

@@ -520,9 +520,7 @@ struct Solver : SolverBase {
     void fcg(const double* b, double tol, int maxit) {
         DevLevel& D = lev[0];
         const int nt = D.nt_all;
-        double* pzq = partial;              // nt
-        double* pdots = partial + nt;       // 2 nt
-        double* prr = partial + 3 * nt;     // nt
+        double* prr = partial + 3 * nt;     // nt (pzq, pdots: see fcg_iteration)
         hipLaunchKernelGGL(k_fcg_init<T>, dim3(tile_grid(nt)), dim3(TILE), 0, stream, D.L, D.tiles_all, nt, b, fx,
                            fr, rT, fd, fq, prr, (int)MODE_N);
         check_launch();
@@ -537,6 +535,14 @@ struct Solver : SolverBase {
         int& hint = tol < 1e-11 ? hint_basis : hint_solve;
         int next_check = std::max(1, hint - 1);
         int last_it = 0;
+        // iterations after the first are the same launch sequence with the same arguments: with use_graph
+        // they replay one captured graph per tolerance (not while kernel events are recorded)
+        hipGraphExec_t* gx = nullptr;
+        if (plan->opt.use_graph && graphs_ok && !prof.on) {
+            auto& g = fcg_graphs[std::make_pair(tol, maxit)];
+            if (!g) g = capture_fcg_iteration(fuse_zq, tol, maxit);
+            if (g) gx = &g;
+        }
         for (int it = 0; it < maxit; ++it) {
             if (it == next_check) {
                 HIPCHECK(hipMemcpyAsync(h_nactive, nactive, sizeof(int), hipMemcpyDeviceToHost, stream));
@@ -545,29 +551,71 @@ struct Solver : SolverBase {
                 next_check = it + every;
             }
             last_it = it + 1;
-            if (fuse_zq && it > 0) {
-                vcycle(MODE_N, active, rT, zT, fq, pzq);
+            if (it > 0 && gx) {
+                HIPCHECK(hipGraphLaunch(*gx, stream));
             } else {
-                vcycle(MODE_N, active, rT, zT);
-                if (it > 0) {
-                    hipLaunchKernelGGL(k_fcg_zq<T>, dim3(tile_grid(nt)), dim3(TILE), 0, stream, D.L, D.tiles_all, nt,
-                                       zT, fq, pzq, active);
-                    check_launch();
-                }
+                fcg_iteration(it, fuse_zq, tol, maxit);
             }
-            hipLaunchKernelGGL(k_fcg_dir<T>, dim3(tile_grid(nt)), dim3(TILE), 0, stream, D.L, D.tiles_all, nt, zT, fd,
-                               pzq, tile_beg, tile_end, dq, it == 0 ? 1 : 0, (int)MODE_N, active);
-            check_launch();
-            stencil<double, double, double, EPI_DOTS>(0, false, MODE_N, coef64, fd, fq, nullptr, nullptr, active, 0.0,
-                                                      0, pdots, fr);
-            hipLaunchKernelGGL(k_fcg_update<T>, dim3(tile_grid(nt)), dim3(TILE), 0, stream, D.L, D.tiles_all, nt, fd,
-                               fq, fx, fr, rT, pdots, tile_beg, tile_end, dq, brk, prr, active);
-            check_launch();
-            hipLaunchKernelGGL(k_fcg_check, dim3(1), dim3(256), 0, stream, N, tile_beg, tile_end, prr, 0, bb, active,
-                               its, brk, tol * tol, maxit, nactive);
-            check_launch();
         }
         hint = last_it;
+    }
+    std::map<std::pair<double, int>, hipGraphExec_t> fcg_graphs;
+    bool graphs_ok = true;   // cleared when the stream cannot be captured (e.g. the legacy null stream)
+
+    hipGraphExec_t capture_fcg_iteration(bool fuse_zq, double tol, int maxit) {
+        if (stream == nullptr) {
+            graphs_ok = false;
+            return nullptr;
+        }
+        if (hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            (void)hipGetLastError();
+            graphs_ok = false;
+            return nullptr;
+        }
+        hipGraph_t graph = nullptr;
+        try {
+            fcg_iteration(1, fuse_zq, tol, maxit);
+        } catch (...) {
+            (void)hipStreamEndCapture(stream, &graph);
+            if (graph) (void)hipGraphDestroy(graph);
+            throw;
+        }
+        HIPCHECK(hipStreamEndCapture(stream, &graph));
+        hipGraphExec_t ex = nullptr;
+        const hipError_t e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        HIPCHECK(e);
+        return ex;
+    }
+
+    // one flexible-CG iteration on all active patches (it == 0: first direction)
+    void fcg_iteration(int it, bool fuse_zq, double tol, int maxit) {
+        DevLevel& D = lev[0];
+        const int nt = D.nt_all;
+        double* pzq = partial;              // nt
+        double* pdots = partial + nt;       // 2 nt
+        double* prr = partial + 3 * nt;     // nt
+        if (fuse_zq && it > 0) {
+            vcycle(MODE_N, active, rT, zT, fq, pzq);
+        } else {
+            vcycle(MODE_N, active, rT, zT);
+            if (it > 0) {
+                hipLaunchKernelGGL(k_fcg_zq<T>, dim3(tile_grid(nt)), dim3(TILE), 0, stream, D.L, D.tiles_all, nt, zT,
+                                   fq, pzq, active);
+                check_launch();
+            }
+        }
+        hipLaunchKernelGGL(k_fcg_dir<T>, dim3(tile_grid(nt)), dim3(TILE), 0, stream, D.L, D.tiles_all, nt, zT, fd,
+                           pzq, tile_beg, tile_end, dq, it == 0 ? 1 : 0, (int)MODE_N, active);
+        check_launch();
+        stencil<double, double, double, EPI_DOTS>(0, false, MODE_N, coef64, fd, fq, nullptr, nullptr, active, 0.0, 0,
+                                                  pdots, fr);
+        hipLaunchKernelGGL(k_fcg_update<T>, dim3(tile_grid(nt)), dim3(TILE), 0, stream, D.L, D.tiles_all, nt, fd, fq,
+                           fx, fr, rT, pdots, tile_beg, tile_end, dq, brk, prr, active);
+        check_launch();
+        hipLaunchKernelGGL(k_fcg_check, dim3(1), dim3(256), 0, stream, N, tile_beg, tile_end, prr, 0, bb, active, its,
+                           brk, tol * tol, maxit, nactive);
+        check_launch();
     }
 
     void band_solve(int mode, const double* rhs, double* x) {
@@ -771,6 +819,8 @@ struct Solver : SolverBase {
         }
     }
     ~Solver() override {
+        for (auto& g : fcg_graphs)
+            if (g.second) (void)hipGraphExecDestroy(g.second);
         if (h_nactive) (void)hipHostFree(h_nactive);
         if (h_sc) (void)hipHostFree(h_sc);
     }

@@ -116,3 +116,27 @@ def test_autotuned_smoother_matches_oracle(require_gpu):
     assert err <= 1e-9
     assert abs(st["cheb_degree"] - st0["cheb_degree"]) <= 1 and st["cheb_degree_coarse"] in (2, 3)
     assert st["cheb_lower"] in (0.67, 1.0, 1.5) and st0["cheb_lower"] == 1.0
+
+
+def test_graph_replay_equals_direct_launches(require_gpu):
+    """Flexible-CG iterations replayed from a captured HIP graph give bitwise the
+    same result as the same launches sent one by one, over several solves on one
+    handle (replays separated by the host's synchronisations and eager work)."""
+    import torch
+    from paper_1705_04531_amd import Solver, options_for
+    wl = W.deformed_square((3, 3), 3, 24, seed=0, name="graph3x3")
+    outs = {}
+    for g in (0, 1):
+        s = Solver(wl.patches, options_for(wl, tol=1e-10, coarse_dofs=0, use_graph=g))
+        x = s.quadrature(device=False)
+        f = torch.from_numpy(wl.f(x)).to("cuda")
+        us = []
+        for rep in range(3):
+            u, st = s.solve(f * (1.0 + rep))
+            torch.cuda.synchronize()
+            us.append(u.cpu().numpy())
+        outs[g] = us
+        s.close()
+    for a, b in zip(outs[0], outs[1]):
+        assert np.array_equal(a, b)
+    assert np.allclose(outs[1][2], 3.0 * outs[1][0], rtol=1e-8, atol=0)
