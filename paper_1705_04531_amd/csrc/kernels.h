@@ -1718,4 +1718,196 @@ __global__ __launch_bounds__(BAND_THREADS) void k_band_solve(const PatchLev* L, 
     for (int i = threadIdx.x; i < n; i += blockDim.x) x[P.voff + i] = xs[i];
 }
 
+// ------------------------------------------------------------------ dense SPD inverse on matrix cores
+//
+// S^{-1} of the assembled primal Schur complement (n x n, FP64) through the
+// Cholesky factor: S = L L^T, X = L^{-1}, S^{-1} = X^T X.  Row-major N x N
+// working matrices, N = n rounded up to 16 (identity padding); 16 x 16
+// blocks; one wave per work-group; every block product on
+// v_mfma_f64_16x16x4f64 (four k-steps per block).  Operand layout of that
+// instruction on gfx950: lane l supplies A[l % 16][k0 + l / 16] and
+// B[k0 + l / 16][l % 16]; result element r of lane l is C[l / 16 + 4 r][l % 16].
+// blockIdx.y selects the matrix of a batch (stride N * N).
+
+typedef double mf_d4 __attribute__((ext_vector_type(4)));
+constexpr int MB = 16;
+
+// c += A B for 16 x 16 blocks, A[i][k] at A[i * lda + k], B[k][j] at B[k * ldb + j];
+// with TA, A is read transposed (A[i][k] at A[k * lda + i]); sign -1 subtracts.
+template <bool TA>
+__device__ __forceinline__ mf_d4 mf_block(const double* __restrict__ A, int lda, const double* __restrict__ B, int ldb,
+                                          mf_d4 c, double sign) {
+    const int l = threadIdx.x & 63, i = l & 15, kq = l >> 4;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int k = 4 * s + kq;
+        const double a = sign * (TA ? A[k * lda + i] : A[i * lda + k]);
+        const double b = B[k * ldb + i];   // column j = l % 16 = i
+        c = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    return c;
+}
+
+__device__ __forceinline__ mf_d4 mf_load(const double* __restrict__ C, int ldc) {
+    const int l = threadIdx.x & 63;
+    mf_d4 c;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) c[r] = C[((l >> 4) + 4 * r) * ldc + (l & 15)];
+    return c;
+}
+
+__device__ __forceinline__ void mf_store(double* C, int ldc, mf_d4 c) {
+    const int l = threadIdx.x & 63;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) C[((l >> 4) + 4 * r) * ldc + (l & 15)] = c[r];
+}
+
+// Cholesky of the 16 x 16 block D (in LDS, lower triangle used) in place and
+// Dinv = its inverse (lower); one wave, lane r < 16 owns row r.  A non-positive
+// pivot sets *err.
+__device__ __forceinline__ void mf_diag_factor(double (*D)[MB + 1], double (*Dinv)[MB + 1], int* err) {
+    const int l = threadIdx.x;
+    for (int c = 0; c < MB; ++c) {
+        if (l == c) {
+            const double p = D[c][c];
+            if (!(p > 0.0)) atomicOr(err, 1);
+            D[c][c] = p > 0.0 ? sqrt(p) : 1.0;
+        }
+        __syncthreads();
+        if (l > c && l < MB) D[l][c] /= D[c][c];
+        __syncthreads();
+        if (l > c && l < MB)
+            for (int j = c + 1; j <= l; ++j) D[l][j] -= D[l][c] * D[j][c];
+        __syncthreads();
+    }
+    if (l < MB) {   // column l of the inverse, forward substitution
+        for (int i = 0; i < MB; ++i) {
+            double s = i == l ? 1.0 : 0.0;
+            for (int k = l; k < i; ++k) s -= D[i][k] * Dinv[k][l];
+            Dinv[i][l] = i < l ? 0.0 : s / D[i][i];
+        }
+    }
+    __syncthreads();
+}
+
+// Block step k: work-group b factors the diagonal block of A (every group, in
+// LDS); group 0 stores L_kk, group b > 0 stores L[k + b][k] = A[k + b][k] L_kk^{-T}.
+__global__ __launch_bounds__(64) void k_spd_panel(const double* A, double* L, int N, int k, int* err) {
+    __shared__ double D[MB][MB + 1], Dinv[MB][MB + 1];
+    const size_t off = (size_t)blockIdx.y * N * N;
+    A += off;
+    L += off;
+    const int l = threadIdx.x;
+    for (int e = l; e < MB * MB; e += 64) D[e / MB][e % MB] = A[(size_t)(k * MB + e / MB) * N + k * MB + e % MB];
+    __syncthreads();
+    mf_diag_factor(D, Dinv, err);
+    const int ib = k + (int)blockIdx.x;
+    if (blockIdx.x == 0) {
+        for (int e = l; e < MB * MB; e += 64) {
+            const int r = e / MB, c = e % MB;
+            L[(size_t)(k * MB + r) * N + k * MB + c] = c <= r ? D[r][c] : 0.0;
+        }
+        return;
+    }
+    // C = A_blk Dinv^T: B[kk][j] = Dinv[j][kk]
+    __shared__ double DinvT[MB][MB];
+    for (int e = l; e < MB * MB; e += 64) DinvT[e / MB][e % MB] = Dinv[e % MB][e / MB];
+    __syncthreads();
+    mf_d4 c = {0.0, 0.0, 0.0, 0.0};
+    c = mf_block<false>(A + (size_t)ib * MB * N + k * MB, N, &DinvT[0][0], MB, c, 1.0);
+    mf_store(L + (size_t)ib * MB * N + k * MB, N, c);
+}
+
+// Trailing update of step k: A[ib][jb] -= L[ib][k] L[jb][k]^T for k < jb <= ib,
+// one work-group per block pair (lower triangle, packed by rows).
+__global__ __launch_bounds__(64) void k_spd_update(double* A, const double* L, int N, int k) {
+    const size_t off = (size_t)blockIdx.y * N * N;
+    A += off;
+    L += off;
+    const int q = (int)blockIdx.x;
+    int p = (int)((sqrt(8.0 * q + 1.0) - 1.0) * 0.5);
+    while ((p + 1) * (p + 2) / 2 <= q) ++p;
+    while (p * (p + 1) / 2 > q) --p;
+    const int ib = k + 1 + p, jb = k + 1 + (q - p * (p + 1) / 2);
+    double* C = A + (size_t)ib * MB * N + jb * MB;
+    mf_d4 c = mf_load(C, N);
+    // B[kk][j] = L[jb][k][j][kk]: the transposed operand read as A^T of mf_block's B slot
+    const double* Li = L + (size_t)ib * MB * N + k * MB;
+    const double* Lj = L + (size_t)jb * MB * N + k * MB;
+    const int l = threadIdx.x & 63, i = l & 15, kq = l >> 4;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int kk = 4 * s + kq;
+        c = __builtin_amdgcn_mfma_f64_16x16x4f64(-Li[i * N + kk], Lj[i * N + kk], c, 0, 0, 0);
+    }
+    mf_store(C, N, c);
+}
+
+// X_ii = L_ii^{-1} for every diagonal block i (one work-group each).
+__global__ __launch_bounds__(64) void k_spd_diag_inv(const double* L, double* X, int N, int* err) {
+    __shared__ double D[MB][MB + 1], Dinv[MB][MB + 1];
+    const size_t off = (size_t)blockIdx.y * N * N;
+    L += off;
+    X += off;
+    const int b = (int)blockIdx.x, l = threadIdx.x;
+    for (int e = l; e < MB * MB; e += 64) {
+        const int r = e / MB, c = e % MB;
+        D[r][c] = c <= r ? L[(size_t)(b * MB + r) * N + b * MB + c] : 0.0;
+    }
+    __syncthreads();
+    // D is already the factor: invert it (lane-per-column forward substitution)
+    if (l < MB) {
+        for (int i = 0; i < MB; ++i) {
+            double s = i == l ? 1.0 : 0.0;
+            for (int k = l; k < i; ++k) s -= D[i][k] * Dinv[k][l];
+            if (i >= l && !(D[i][i] != 0.0)) atomicOr(err, 2);
+            Dinv[i][l] = i < l ? 0.0 : s / D[i][i];
+        }
+    }
+    __syncthreads();
+    for (int e = l; e < MB * MB; e += 64) X[(size_t)(b * MB + e / MB) * N + b * MB + e % MB] = Dinv[e / MB][e % MB];
+}
+
+// Block column j of X = L^{-1} below the diagonal: X[i][j] = -X_ii sum_{j <= m < i} L[i][m] X[m][j],
+// i = j + 1, j + 2, ... in order (one work-group per column; each block is written
+// before the wave reads it back).
+__global__ __launch_bounds__(64) void k_spd_tri_inv(const double* L, double* X, int N) {
+    __shared__ double T[MB][MB];
+    const size_t off = (size_t)blockIdx.y * N * N;
+    L += off;
+    X += off;
+    const int j = (int)blockIdx.x, nb = N / MB, l = threadIdx.x;
+    for (int i = j + 1; i < nb; ++i) {
+        mf_d4 c = {0.0, 0.0, 0.0, 0.0};
+        for (int m = j; m < i; ++m)
+            c = mf_block<false>(L + (size_t)i * MB * N + m * MB, N, X + (size_t)m * MB * N + j * MB, N, c, 1.0);
+        mf_store(&T[0][0], MB, c);
+        __syncthreads();
+        mf_d4 x = {0.0, 0.0, 0.0, 0.0};
+        x = mf_block<false>(X + (size_t)i * MB * N + i * MB, N, &T[0][0], MB, x, -1.0);
+        mf_store(X + (size_t)i * MB * N + j * MB, N, x);
+        __threadfence_block();
+        __syncthreads();
+        (void)l;
+    }
+}
+
+// S^{-1} = X^T X for the leading n x n, written by columns (entry (r, c) at out[c * n + r]);
+// one work-group per block pair.
+__global__ __launch_bounds__(64) void k_spd_xtx(const double* X, double* out, int N, int n) {
+    const size_t off = (size_t)blockIdx.y * N * N;
+    X += off;
+    out += (size_t)blockIdx.y * n * n;
+    const int nb = N / MB, ib = (int)blockIdx.x / nb, jb = (int)blockIdx.x % nb;
+    mf_d4 c = {0.0, 0.0, 0.0, 0.0};
+    for (int m = ib > jb ? ib : jb; m < nb; ++m)
+        c = mf_block<true>(X + (size_t)m * MB * N + ib * MB, N, X + (size_t)m * MB * N + jb * MB, N, c, 1.0);
+    const int l = threadIdx.x & 63;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int row = ib * MB + (l >> 4) + 4 * r, col = jb * MB + (l & 15);
+        if (row < n && col < n) out[(size_t)col * n + row] = c[r];
+    }
+}
+
 }  // namespace ieti

@@ -803,6 +803,38 @@ struct Solver : SolverBase {
         (void)hipEventDestroy(e1);
         set_smoother(best_m, best_mc, best_s);
     }
+    // Sinv = S^{-1} (n x n SPD, host row-major) by k_spd_* on the device, stored by columns
+    void spd_inverse(const std::vector<double>& S, int64_t n) {
+        const int N = (int)((n + MB - 1) / MB) * MB, nb = N / MB;
+        std::vector<double> Ah((size_t)N * N, 0.0);
+        for (int64_t i = 0; i < N; ++i)
+            for (int64_t j = 0; j < N; ++j)
+                Ah[(size_t)i * N + j] = (i < n && j < n) ? S[(size_t)i * n + j] : (i == j ? 1.0 : 0.0);
+        double* A = arena.upload(Ah, stream);
+        double* L = arena.alloc<double>((int64_t)N * N, stream);
+        double* X = arena.alloc<double>((int64_t)N * N, stream);
+        int* err = arena.alloc<int>(1, stream);
+        Sinv = arena.alloc<double>(n * n, stream, false);
+        for (int k = 0; k < nb; ++k) {
+            hipLaunchKernelGGL(k_spd_panel, dim3(nb - k, 1), dim3(64), 0, stream, A, L, N, k, err);
+            check_launch();
+            const int m = nb - k - 1;
+            if (m > 0) {
+                hipLaunchKernelGGL(k_spd_update, dim3(m * (m + 1) / 2, 1), dim3(64), 0, stream, A, L, N, k);
+                check_launch();
+            }
+        }
+        hipLaunchKernelGGL(k_spd_diag_inv, dim3(nb, 1), dim3(64), 0, stream, L, X, N, err);
+        check_launch();
+        hipLaunchKernelGGL(k_spd_tri_inv, dim3(nb, 1), dim3(64), 0, stream, L, X, N);
+        check_launch();
+        hipLaunchKernelGGL(k_spd_xtx, dim3(nb * nb, 1), dim3(64), 0, stream, X, Sinv, N, (int)n);
+        check_launch();
+        int herr = 0;
+        HIPCHECK(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, stream));
+        sync();
+        if (herr) throw Error(IETI_EINVAL, "coarse matrix S_PiPi is not positive definite");
+    }
     void setup() override;
     int solve(const double* f_qp, double* u, ieti_stats* st) override;
     void quadrature(double* x, bool on_device) override {
@@ -1383,38 +1415,8 @@ void Solver<T>::setup() {
                     S[(size_t)pa.primal_global[a] * npi + pa.primal_global[b]] +=
                         0.5 * (hS[((size_t)k * NPMAX + a) * NPMAX + b] + hS[((size_t)k * NPMAX + b) * NPMAX + a]);
         }
-        // Cholesky S = C C^T and explicit inverse (FP64)
-        const int64_t n = npi;
-        std::vector<double> Cf = S;
-        for (int64_t j = 0; j < n; ++j) {
-            double s = Cf[(size_t)j * n + j];
-            for (int64_t k = 0; k < j; ++k) s -= Cf[(size_t)j * n + k] * Cf[(size_t)j * n + k];
-            if (!(s > 0)) throw Error(IETI_EINVAL, "coarse matrix S_PiPi is not positive definite");
-            double c = std::sqrt(s);
-            Cf[(size_t)j * n + j] = c;
-            for (int64_t i = j + 1; i < n; ++i) {
-                double t = Cf[(size_t)i * n + j];
-                for (int64_t k = 0; k < j; ++k) t -= Cf[(size_t)i * n + k] * Cf[(size_t)j * n + k];
-                Cf[(size_t)i * n + j] = t / c;
-            }
-        }
-        std::vector<double> Si((size_t)n * n), z(n);
-        for (int64_t j = 0; j < n; ++j) {
-            std::fill(z.begin(), z.end(), 0.0);
-            z[j] = 1.0;
-            for (int64_t i = 0; i < n; ++i) {
-                double t = z[i];
-                for (int64_t k = 0; k < i; ++k) t -= Cf[(size_t)i * n + k] * z[k];
-                z[i] = t / Cf[(size_t)i * n + i];
-            }
-            for (int64_t i = n - 1; i >= 0; --i) {
-                double t = z[i];
-                for (int64_t k = i + 1; k < n; ++k) t -= Cf[(size_t)k * n + i] * z[k];
-                z[i] = t / Cf[(size_t)i * n + i];
-            }
-            for (int64_t i = 0; i < n; ++i) Si[(size_t)j * n + i] = z[i];   // by columns
-        }
-        Sinv = arena.upload(Si, st);
+        // S^{-1} on the matrix cores: blocked Cholesky, triangular inverse, X^T X (FP64 MFMA)
+        spd_inverse(S, npi);
         hipLaunchKernelGGL(k_psi_slots, dim3(nblk(std::max<int64_t>(nslots, 1), 256)), dim3(256), 0, st, nslots,
                            slot_patch, slot_dev, npk, psi, len0, psiG);
         check_launch();
@@ -1629,7 +1631,8 @@ static size_t estimate_device_bytes(const Plan& pl) {
         b += (double)(pa.band[0].size() + pa.band[1].size()) * 8.0;
         b += (double)pa.n_qp * (16.0 + 8.0 * pa.dim);
     }
-    b += (double)pl.n_lambda * 8.0 * 8.0 + (double)pl.n_primal * pl.n_primal * 8.0;
+    const double npad = (double)((pl.n_primal + 15) / 16 * 16);
+    b += (double)pl.n_lambda * 8.0 * 8.0 + (double)pl.n_primal * pl.n_primal * 8.0 + 3.0 * npad * npad * 8.0;
     return (size_t)(1.15 * b) + (16u << 20);
 }
 
