@@ -54,6 +54,11 @@ extern "C" {
 #define IETI_LOCAL_EXACT  1   /* exact local solves: banded Cholesky (D-D) */
 #define IETI_LOCAL_EXACT_MG 2 /* exact Neumann solves in F, d and the recovery; multigrid V-cycles for the
                                  Dirichlet problems of the preconditioner (D-MG, Sec. 3.3) */
+#define IETI_LOCAL_MG_SADDLE 3 /* MG-MG-S (Sec. 3.3): Bramble-Pasciak CG on the saddle-point system (2) with
+                                  three V-cycles (plus the exact primal coarse solve) as the preconditioner of
+                                  K~ and the scaled Dirichlet preconditioner for the Schur complement; no
+                                  inner solves. outer_iterations counts its iterations, the residuals are its
+                                  preconditioned energy norms */
 
 #define IETI_PRIMAL_VERTICES  1   /* primal unknowns at patch vertices */
 #define IETI_PRIMAL_EDGES     2   /* plus edge averages (3D: patch edges; 2D: patch sides) */
@@ -67,7 +72,8 @@ typedef struct ieti_patch {
 } ieti_patch;
 
 typedef struct ieti_options {
-    int32_t local_solver;      /* IETI_LOCAL_MG (default), IETI_LOCAL_EXACT or IETI_LOCAL_EXACT_MG */
+    int32_t local_solver;      /* IETI_LOCAL_MG (default), IETI_LOCAL_EXACT, IETI_LOCAL_EXACT_MG or
+                                  IETI_LOCAL_MG_SADDLE */
     int32_t mg_precision;      /* 32 or 64: arithmetic of V-cycles and their operator data (default 64) */
     int32_t primal;            /* IETI_PRIMAL_VERTICES (default) or IETI_PRIMAL_VERTICES|IETI_PRIMAL_EDGES */
     int32_t cheb_degree;       /* Chebyshev smoother degree per smoothing phase; 0 = tuned per spline degree */
@@ -115,6 +121,7 @@ typedef struct ieti_stats {
     int32_t cheb_degree;               /* smoother in use: Chebyshev degree on the finest level, */
     int32_t cheb_degree_coarse;        /* on the coarser levels, */
     double  cheb_lower;                /* and the interval's lower end over the tuned table's (1 = table) */
+    double  saddle_omega;              /* MG-MG-S: the scaling omega of the V-cycle block in use (0 otherwise) */
 } ieti_stats;
 
 typedef struct ieti_handle ieti_handle;

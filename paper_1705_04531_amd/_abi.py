@@ -20,6 +20,7 @@ IETI_PENDING = 1
 IETI_LOCAL_MG = 0
 IETI_LOCAL_EXACT = 1
 IETI_LOCAL_EXACT_MG = 2
+IETI_LOCAL_MG_SADDLE = 3
 IETI_PRIMAL_VERTICES = 1
 IETI_PRIMAL_EDGES = 2
 
@@ -94,6 +95,7 @@ class IetiStats(C.Structure):
         ("cheb_degree", C.c_int32),
         ("cheb_degree_coarse", C.c_int32),
         ("cheb_lower", C.c_double),
+        ("saddle_omega", C.c_double),
     ]
 
     def as_dict(self):

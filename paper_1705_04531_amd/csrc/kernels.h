@@ -1910,4 +1910,78 @@ __global__ __launch_bounds__(64) void k_spd_xtx(const double* X, double* out, in
     }
 }
 
+// ------------------------------------------------------------------ saddle-point iteration (MG-MG-S)
+//
+// Flat kernels over whole level-0 (guarded) or multiplier vectors: guards are
+// zero in every operand, so they stay zero.
+
+// partial[b] = sum over the block's slice of a . b (fixed order)
+__global__ __launch_bounds__(TILE) void k_dot_flat(int64_t n, const double* a, const double* b, double* partial) {
+    __shared__ double lds[TILE / WAVE];
+    double v[1] = {0.0};
+    for (int64_t i = (int64_t)blockIdx.x * TILE + threadIdx.x; i < n; i += (int64_t)gridDim.x * TILE) v[0] += a[i] * b[i];
+    block_sum<1>(v, lds);
+    if (threadIdx.x == 0) partial[blockIdx.x] = v[0];
+}
+
+// y += sign * s[idx] * x
+__global__ void k_axpy_dev(int64_t n, double* y, const double* x, const double* s, int idx, double sign) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] += sign * s[idx] * x[i];
+}
+
+// p = z + s[idx] * p
+__global__ void k_xpby_dev(int64_t n, double* p, const double* z, const double* s, int idx) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = z[i] + s[idx] * p[i];
+}
+
+// y = a * x (a host scalar)
+__global__ void k_scale_flat(int64_t n, double* y, const double* x, double a) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = a * x[i];
+}
+
+// out = g - C_E^T c_E per patch: every edge constraint j of patch k (edge list
+// [edge_ptr, edge_ptr + 1)) subtracts c[k][j] / |E_j| on its coefficients
+// (edge lists of one patch are disjoint; vertex constraints have none).  out
+// must already hold g.
+__global__ __launch_bounds__(TILE) void k_edge_scatter_sub(int npatch, const int32_t* npk, const int64_t* edge_ptr,
+                                                           const int64_t* edge_dev, const double* c, double* out) {
+    const int k = blockIdx.x;
+    if (k >= npatch) return;
+    for (int j = 0; j < npk[k]; ++j) {
+        const int64_t eb = edge_ptr[k * NPMAX + j], ee = edge_ptr[k * NPMAX + j + 1];
+        if (ee <= eb) continue;
+        const double v = c[k * NPMAX + j] / (double)(ee - eb);
+        for (int64_t r = eb + threadIdx.x; r < ee; r += blockDim.x) out[edge_dev[r]] -= v;
+    }
+}
+
+// Scalars of the Bramble-Pasciak iteration in sc (one thread):
+//   stage 0 (start): rho = sc[0] + sc[1]; rho0 = rho
+//   stage 1: gamma = sc[2] + sc[3]; alpha = rho / gamma (0 and a breakdown flag if gamma <= 0)
+//   stage 2: rho' = sc[0] + sc[1]; beta = rho' / rho; rho = rho'
+// layout: [0..3] dot sums, [4] rho, [5] rho0, [6] alpha, [7] beta, [8] breakdown
+__global__ void k_bp_scalars(int stage, double* sc) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (stage == 0) {
+        sc[4] = sc[0] + sc[1];
+        sc[5] = sc[4];
+        sc[8] = 0.0;
+    } else if (stage == 1) {
+        const double g = sc[2] + sc[3];
+        if (g > 0.0 && sc[4] > 0.0) {
+            sc[6] = sc[4] / g;
+        } else {
+            sc[6] = 0.0;
+            sc[8] = 1.0;
+        }
+    } else {
+        const double r = sc[0] + sc[1];
+        sc[7] = sc[4] > 0.0 ? r / sc[4] : 0.0;
+        sc[4] = r;
+    }
+}
+
 }  // namespace ieti

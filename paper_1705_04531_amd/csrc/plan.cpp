@@ -771,7 +771,7 @@ Plan* build_plan(const ieti_patch* in, int n, const double* pv, int n_pv, const 
     if (optp) opt = *optp; else default_options(&opt);
     if (opt.mg_precision != 32 && opt.mg_precision != 64) throw Error(IETI_EINVAL, "mg_precision must be 32 or 64");
     if (opt.local_solver != IETI_LOCAL_MG && opt.local_solver != IETI_LOCAL_EXACT &&
-        opt.local_solver != IETI_LOCAL_EXACT_MG)
+        opt.local_solver != IETI_LOCAL_EXACT_MG && opt.local_solver != IETI_LOCAL_MG_SADDLE)
         throw Error(IETI_EINVAL, "unknown local solver");
     if (!(opt.tol > 0) || !(opt.inner_tol > 0) || !(opt.basis_tol > 0) || opt.max_it <= 0 || opt.inner_max_it <= 0)
         throw Error(IETI_EINVAL, "tolerances and iteration limits must be positive");
@@ -1211,7 +1211,7 @@ Plan* build_plan(const ieti_patch* in, int n, const double* pv, int n_pv, const 
     }
     parallel_for(n, [&](int k) {
         const bool mg = opt.local_solver != IETI_LOCAL_EXACT;
-        const bool neumann_mg = opt.local_solver == IETI_LOCAL_MG;
+        const bool neumann_mg = opt.local_solver == IETI_LOCAL_MG || opt.local_solver == IETI_LOCAL_MG_SADDLE;
         Patch& pa = pl.patches[k];
         for (size_t l = 0; l < pa.lv.size(); ++l) assemble_level(pa, pa.lv[l], l == 0);
         for (size_t l = 0; l + 1 < pa.lv.size(); ++l) {

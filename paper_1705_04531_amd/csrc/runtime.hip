@@ -722,6 +722,180 @@ struct Solver : SolverBase {
         gather(s64, true, z);
     }
 
+    // ---------------------------------------------------------------- saddle-point iteration (MG-MG-S)
+    // Vectors of W~ (primal continuity built in) are level-0 torn vectors u = w + Psi R u_Pi; their dual
+    // (residuals) is any torn representative.  A = K~ acts as the patch stiffness (mode K), B~ as the jump.
+    bool saddle = false;
+    double bp_omega = 1.0;   // A0^{-1} = omega * (P_E V3 P_E^T + Psi R S^{-1} R^T Psi^T), A0 < A
+    double *bx = nullptr, *br = nullptr, *bz = nullptr, *bhz = nullptr, *bp = nullptr, *bs = nullptr, *bt = nullptr,
+           *bht = nullptr, *bg = nullptr, *bw = nullptr, *bg2 = nullptr;
+    double *lxx = nullptr, *lrr = nullptr, *lzz = nullptr, *lhz = nullptr, *lpp = nullptr, *lss = nullptr,
+           *ltt = nullptr, *lht = nullptr, *bsc = nullptr, *dpart = nullptr;
+    int ndpart = 0;
+
+    void flat_dot(int64_t n, const double* a, const double* b, double* out) {
+        if (n <= 0) {
+            fill<double>(out, 1, 0.0);
+            return;
+        }
+        const int g = (int)std::min<int64_t>(ndpart, nblk(n, TILE));
+        hipLaunchKernelGGL(k_dot_flat, dim3(g), dim3(TILE), 0, stream, n, a, b, dpart);
+        check_launch();
+        hipLaunchKernelGGL(k_sum, dim3(1), dim3(1024), 0, stream, dpart, (int64_t)g, out);
+        check_launch();
+    }
+    void axpy_dev(int64_t n, double* y, const double* x, int idx, double sign) {
+        if (n <= 0) return;
+        hipLaunchKernelGGL(k_axpy_dev, dim3(nblk(n, 256)), dim3(256), 0, stream, n, y, x, bsc, idx, sign);
+        check_launch();
+    }
+    void xpby_dev(int64_t n, double* p, const double* z, int idx) {
+        if (n <= 0) return;
+        hipLaunchKernelGGL(k_xpby_dev, dim3(nblk(n, 256)), dim3(256), 0, stream, n, p, z, bsc, idx);
+        check_launch();
+    }
+    void copy_dev(int64_t n, double* dst, const double* src) {
+        if (n <= 0) return;
+        HIPCHECK(hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyDeviceToDevice, stream));
+    }
+    void applyA(const double* v, double* out) {
+        stencil<double, double, double, EPI_APPLY>(0, false, MODE_K, coef64, v, out, nullptr, nullptr, nullptr, 1.0,
+                                                   0);
+    }
+    // out = omega [P_E V3 P_E^T g + Psi R S^{-1} sum_k R_k^T Psi_k^T g] (out must not alias g)
+    void A0inv(const double* g, double* out, double omega) {
+        DevLevel& D = lev[0];
+        if (npi > 0) {
+            hipLaunchKernelGGL(k_pri_dots, dim3(N), dim3(TILE), 0, stream, N, npk, row_ptr, slot_dev, lev[0].L, psi,
+                               len0, g, nullptr, edge_ptr, edge_dev, cbuf, ebuf);
+            check_launch();
+        }
+        // P_E^T g, masked to the K_rr space
+        hipLaunchKernelGGL((k_convert<double, double>), dim3(tile_grid(D.nt_all)), dim3(TILE), 0, stream, D.L,
+                           D.tiles_all, D.nt_all, g, bg, (int)MODE_N, 1.0);
+        check_launch();
+        if (npi > 0) {
+            hipLaunchKernelGGL(k_edge_scatter_sub, dim3(N), dim3(TILE), 0, stream, N, npk, edge_ptr, edge_dev, cbuf,
+                               bg);
+            check_launch();
+        }
+        // three V-cycles as a stationary iteration from zero
+        hipLaunchKernelGGL((k_convert<double, T>), dim3(tile_grid(D.nt_all)), dim3(TILE), 0, stream, D.L,
+                           D.tiles_all, D.nt_all, bg, bT, (int)MODE_N, 1.0);
+        check_launch();
+        vcycle(MODE_N, nullptr, bT, xIT);
+        for (int c = 1; c < 3; ++c) {
+            stencil<T, T, T, EPI_RESID>(0, false, MODE_N, D.coefT, xIT, r2T, bT, nullptr, nullptr, 0.0, 0);
+            vcycle(MODE_N, nullptr, r2T, x2T);
+            hipLaunchKernelGGL(k_add<T>, dim3(tile_grid(D.nt_all)), dim3(TILE), 0, stream, D.L, D.tiles_all, D.nt_all,
+                               (const T*)x2T, xIT);
+            check_launch();
+        }
+        hipLaunchKernelGGL((k_convert<T, double>), dim3(tile_grid(D.nt_all)), dim3(TILE), 0, stream, D.L,
+                           D.tiles_all, D.nt_all, (const T*)xIT, bw, (int)MODE_N, 1.0);
+        check_launch();
+        if (npi > 0) {
+            // edge means of the V-cycle result (P_E) and the primal part
+            hipLaunchKernelGGL(k_pri_dots, dim3(N), dim3(TILE), 0, stream, N, npk, row_ptr, slot_dev, lev[0].L, psi,
+                               len0, g, bw, edge_ptr, edge_dev, cbuf, ebuf);
+            check_launch();
+            hipLaunchKernelGGL(k_pri_coarse, dim3(nblk(npi, WAVE)), dim3(256), npi * sizeof(double), stream, npi,
+                               pri_ptr, pri_patch, pri_local, cbuf, Sinv, upi);
+            check_launch();
+            hipLaunchKernelGGL(k_pri_coef, dim3(nblk((int64_t)N * NPMAX, 256)), dim3(256), 0, stream, N, npk, Rk,
+                               upi, ebuf, coefbuf);
+            check_launch();
+            hipLaunchKernelGGL(k_pri_apply_full, dim3(tile_grid(D.nt_all)), dim3(TILE), 0, stream, D.L, D.tiles_all,
+                               D.nt_all, npk, psi, len0, coefbuf, bw, out);
+            check_launch();
+        } else {
+            copy_dev(len0, out, bw);
+        }
+        hipLaunchKernelGGL(k_scale_flat, dim3(nblk(len0, 256)), dim3(256), 0, stream, len0, out, out, omega);
+        check_launch();
+    }
+    // Smallest eigenvalue of a symmetric tridiagonal matrix (diagonal a, off-diagonal b) by bisection on
+    // the Sturm count (the number of negative pivots of T - x I).
+    static double tridiag_min_eig(const std::vector<double>& a, const std::vector<double>& b) {
+        const size_t k = a.size();
+        double lo = 1e300, hi = -1e300;
+        for (size_t i = 0; i < k; ++i) {   // Gershgorin bounds
+            const double r = (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i + 1 < k ? std::fabs(b[i]) : 0.0);
+            lo = std::min(lo, a[i] - r);
+            hi = std::max(hi, a[i] + r);
+        }
+        for (int step = 0; step < 200 && hi - lo > 1e-14 * std::max(1.0, std::fabs(hi)); ++step) {
+            const double x = 0.5 * (lo + hi);
+            int neg = 0;
+            double d = 1.0;
+            for (size_t i = 0; i < k; ++i) {
+                d = a[i] - x - (i > 0 ? b[i - 1] * b[i - 1] / d : 0.0);
+                if (d == 0.0) d = -1e-300;
+                if (d < 0.0) ++neg;
+            }
+            if (neg >= 1) hi = x;
+            else lo = x;
+        }
+        return 0.5 * (lo + hi);
+    }
+    // omega of the V-cycle block: A0 < A on W~ needs omega > 1 / lambda_min(T), T = A0^{-1} A at omega = 1.
+    // lambda_min is the smallest Ritz value of the Lanczos matrix that k steps of CG on A x = b (b seeded,
+    // preconditioner A0^{-1}) build from their step lengths alpha_j and ratios beta_j:
+    //   T_jj = 1/alpha_j + beta_{j-1}/alpha_{j-1},  T_j,j+1 = sqrt(beta_j)/alpha_j.
+    // Ritz values approach the spectrum's edge from inside, so the factor 1.1 covers the remaining gap; a
+    // too small omega that still slips through is caught by the iteration (a non-positive H-energy).
+    void estimate_omega() {
+        std::vector<double> h(len0);
+        uint64_t x = 0xD1B54A32D192ED03ull;
+        for (auto& v : h) {
+            x ^= x << 13; x ^= x >> 7; x ^= x << 17;
+            v = (double)(x >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+        }
+        HIPCHECK(hipMemcpyAsync(br, h.data(), len0 * sizeof(double), hipMemcpyHostToDevice, stream));
+        A0inv(br, bz, 1.0);
+        copy_dev(len0, bp, bz);
+        flat_dot(len0, br, bz, bsc + 10);
+        double rz = 0.0;
+        HIPCHECK(hipMemcpyAsync(&rz, bsc + 10, sizeof(double), hipMemcpyDeviceToHost, stream));
+        sync();
+        // stop well above the rounding floor of the CG residual: once it is reached the Lanczos vectors lose
+        // orthogonality and the coefficients no longer describe T (an FP32 V-cycle is symmetric only to FP32)
+        const double rz_floor = (std::is_same<T, float>::value ? 1e-8 : 1e-16) * rz;
+        std::vector<double> al, be, ta, tb;
+        double lmin = 1.0, lprev = 2.0;
+        for (int k = 0; k < 40 && rz > 0.0; ++k) {
+            applyA(bp, bs);
+            flat_dot(len0, bp, bs, bsc + 10);
+            double pap = 0.0;
+            HIPCHECK(hipMemcpyAsync(&pap, bsc + 10, sizeof(double), hipMemcpyDeviceToHost, stream));
+            sync();
+            if (!(pap > 0.0)) break;
+            const double alpha = rz / pap;
+            ta.push_back(1.0 / alpha + (k > 0 ? be.back() / al.back() : 0.0));
+            al.push_back(alpha);
+            fill<double>(bsc + 11, 1, alpha);
+            axpy_dev(len0, br, bs, 11, -1.0);
+            A0inv(br, bz, 1.0);
+            flat_dot(len0, br, bz, bsc + 10);
+            double rz1 = 0.0;
+            HIPCHECK(hipMemcpyAsync(&rz1, bsc + 10, sizeof(double), hipMemcpyDeviceToHost, stream));
+            sync();
+            lmin = tridiag_min_eig(ta, tb);
+            if (!(rz1 > rz_floor) || (k >= 3 && std::fabs(lmin - lprev) <= 1e-3 * lmin)) break;
+            const double beta = rz1 / rz;
+            rz = rz1;
+            be.push_back(beta);
+            tb.push_back(std::sqrt(beta) / alpha);
+            fill<double>(bsc + 11, 1, beta);
+            xpby_dev(len0, bp, bz, 11);
+            lprev = lmin;
+        }
+        if (!(lmin > 0.1)) throw Error(IETI_ENOCONV, "V-cycle preconditioner too weak for the saddle-point iteration");
+        bp_omega = 1.1 / std::min(lmin, 1.0);
+    }
+    int solve_saddle(ieti_stats& st);
+    void finish_solution(ieti_stats& st, double* u_out);
+
     // ---------------------------------------------------------------- setup
     // Chebyshev coefficients d_k = s1 d_{k-1} + s2 D^{-1} r_k on [lower_scale clo, hi] lambda_max,
     // per (patch-level, mode, step)
@@ -1117,7 +1291,7 @@ void Solver<T>::setup() {
         HIPCHECK(hipStreamSynchronize(st));
     }
     // ---- exact local solves
-    if (pl.opt.local_solver != IETI_LOCAL_MG) {
+    if (pl.opt.local_solver == IETI_LOCAL_EXACT || pl.opt.local_solver == IETI_LOCAL_EXACT_MG) {
         exact = true;
         prec_exact = pl.opt.local_solver == IETI_LOCAL_EXACT;
         int dev = 0, max_lds = 0;
@@ -1153,6 +1327,15 @@ void Solver<T>::setup() {
     for (double** p : {&f64, &b64, &e64, &w64, &s64, &u64, &fx, &fr, &fd, &fq}) *p = arena.alloc<double>(len0, st);
     for (T** p : {&rT, &zT, &bT, &xIT, &x2T, &r2T}) *p = arena.alloc<T>(len0, st);
     partial = arena.alloc<double>(4 * (int64_t)D0.nt_all + 4, st);
+    if (pl.opt.local_solver == IETI_LOCAL_MG_SADDLE) {
+        saddle = true;
+        for (double** p : {&bx, &br, &bz, &bhz, &bp, &bs, &bt, &bht, &bg, &bw, &bg2}) *p = arena.alloc<double>(len0, st);
+        const int64_t nlb = std::max<int64_t>(pl.n_lambda, 1);
+        for (double** p : {&lxx, &lrr, &lzz, &lhz, &lpp, &lss, &ltt, &lht}) *p = arena.alloc<double>(nlb, st);
+        bsc = arena.alloc<double>(16, st);
+        ndpart = 1024;
+        dpart = arena.alloc<double>(ndpart, st);
+    }
     {
         std::vector<int32_t> tb(N, 0), te(N, 0);
         for (size_t t = 0; t < D0.h_all.size(); ++t) {
@@ -1424,6 +1607,7 @@ void Solver<T>::setup() {
     }
     sync();
     if (pl.opt.autotune) autotune_smoother();
+    if (saddle) estimate_omega();
 }
 
 template <typename T>
@@ -1455,6 +1639,22 @@ int Solver<T>::solve(const double* f_qp, double* u_out, ieti_stats* stp) {
     check_launch();
     hipLaunchKernelGGL(k_sum, dim3(1), dim3(1024), 0, stream, partial, (int64_t)D0.nt_all, sc + 8);
     check_launch();
+    if (saddle) {
+        HIPCHECK(hipMemcpyAsync(h_sc, sc, 16 * sizeof(double), hipMemcpyDeviceToHost, stream));
+        sync();
+        if (!std::isfinite(h_sc[8])) throw Error(IETI_EINVAL, "right-hand side is not finite");
+        auto t1s = clk::now();
+        const int rc = solve_saddle(st);
+        auto t2s = clk::now();
+        st.time_rhs_ms = ms(t0, t1s);
+        st.time_pcg_ms = ms(t1s, t2s);
+        finish_solution(st, u_out);
+        st.time_recovery_ms = ms(t2s, clk::now());
+        st.time_total_ms = ms(t0, clk::now());
+        if (prof.on) prof.collect();
+        if (stp) *stp = st;
+        return rc;
+    }
     ktilde_inv(f64, true, pl.opt.inner_tol, u64);
     const int64_t nl = nlam;
     double r0 = 0.0, scale = 0.0;
@@ -1512,6 +1712,188 @@ int Solver<T>::solve(const double* f_qp, double* u_out, ieti_stats* stp) {
                        b64, w64);
     check_launch();
     ktilde_inv(w64, true, pl.opt.inner_tol, u64);
+    finish_solution(st, u_out);
+    sync();
+    auto t3 = clk::now();
+    if (prof.on) prof.collect();
+    st.time_rhs_ms = ms(t0, t1);
+    st.time_pcg_ms = ms(t1, t2);
+    st.time_recovery_ms = ms(t2, t3);
+    st.time_total_ms = ms(t0, t3);
+    {
+        int h4[4];
+        HIPCHECK(hipMemcpy(h4, nactive, sizeof(h4), hipMemcpyDeviceToHost));
+        inner_sum = h4[1];
+        inner_max = h4[2];
+        inner_calls = h4[3];
+    }
+    st.inner_iterations_max = inner_max;
+    st.inner_iterations_mean = inner_calls ? (double)inner_sum / (double)inner_calls : 0.0;
+    if (stp) *stp = st;
+    return conv ? IETI_OK : IETI_ENOCONV;
+}
+
+// Bramble-Pasciak CG on [A B^T; B 0] (u; lambda) = (f; 0) (the saddle-point system (2) in W~):
+// preconditioner P^{-1}(q_u; q_l) = (A0^{-1} q_u; S^-1 (B A0^{-1} q_u - q_l)), S^-1 the scaled Dirichlet
+// preconditioner; CG for P^{-1} [A B^T; B 0] in the inner product H = diag(A - A0, S).  For every vector
+// v = P^{-1} q the iteration keeps q beside it, so that H v = (A v_u - q_u; B v_u - q_l) needs no A0.
+// Iterates until sqrt(rho_k / rho_0) <= tol, rho = <z, z>_H.  The solution u lands in u64.
+template <typename T>
+int Solver<T>::solve_saddle(ieti_stats& st) {
+    const Plan& pl = *plan;
+    const int64_t nl = nlam, n = len0;
+    DevLevel& D0 = lev[0];
+    double w = bp_omega;
+    auto sub = [&](double* a, const double* b) {   // a -= b on the coefficients
+        hipLaunchKernelGGL(k_sub, dim3(tile_grid(D0.nt_all)), dim3(TILE), 0, stream, D0.L, D0.tiles_all, D0.nt_all,
+                           a, b, a);
+        check_launch();
+    };
+    // The recurrences' energy rho reaches a rounding floor (its H-product mixes A and A0 terms), and with
+    // FP32 V-cycles the preconditioner is linear only to FP32 rounding, which a (non-flexible) CG cannot
+    // absorb: each cycle reduces its own sqrt(rho) by restart_red (or stops when rho grows by 1e6 over
+    // its minimum), then the iteration restarts from the true FP64 residual r (mixed-precision
+    // refinement).  Convergence is decided there on eta = (z_u, r_u) + (z_l, S^ z_l), z = P^{-1} r, which
+    // is positive for any omega.  A non-positive H-energy (rho at a restart, or a breakdown in a cycle's
+    // first step) means A - A0 is not positive on W~: omega grows by 1.5 and the iteration starts over.
+    const double restart_red = std::is_same<T, float>::value ? 1e-4 : 1e-7;
+    fill<double>(bsc, 16, 0.0);
+    fill<double>(bsc + 12, 1, 1.0);
+    fill<double>(bx, n, 0.0);
+    if (nl > 0) fill<double>(lxx, nl, 0.0);
+    double hs[10];
+    double eta0 = -1.0, eta = 0.0;
+    int it = 0, raises = 0;
+    bool conv = false, fresh = true;
+    while (!conv && it < pl.opt.max_it) {
+        // true residual r = (f - A x_u - B^T x_l, -B x_u)
+        hipLaunchKernelGGL((k_convert<double, double>), dim3(tile_grid(D0.nt_all)), dim3(TILE), 0, stream, D0.L,
+                           D0.tiles_all, D0.nt_all, f64, br, (int)MODE_K, 1.0);   // Dirichlet rows out
+        check_launch();
+        if (!fresh) {
+            applyA(bx, bs);
+            sub(br, bs);
+            if (nl > 0) {
+                scatter(lxx, false, bg2);
+                sub(br, bg2);
+                gather(bx, false, lrr);
+                hipLaunchKernelGGL(k_scale_flat, dim3(nblk(nl, 256)), dim3(256), 0, stream, nl, lrr, lrr, -1.0);
+                check_launch();
+            }
+        } else if (nl > 0) {
+            fill<double>(lrr, nl, 0.0);
+        }
+        // z = P^{-1} r, Hz = (A z_u - r_u, B z_u - r_l)
+        A0inv(br, bz, w);
+        if (nl > 0) {
+            gather(bz, false, lhz);
+            axpy_dev(nl, lhz, lrr, 12, -1.0);
+            applyPrec(lhz, lzz);
+        }
+        applyA(bz, bhz);
+        sub(bhz, br);
+        flat_dot(n, bz, bhz, bsc + 0);
+        flat_dot(nl, lzz, lhz, bsc + 1);
+        flat_dot(n, bz, br, bsc + 9);
+        hipLaunchKernelGGL(k_bp_scalars, dim3(1), dim3(1), 0, stream, 0, bsc);
+        check_launch();
+        copy_dev(n, bp, bz);
+        copy_dev(nl, lpp, lzz);
+        HIPCHECK(hipMemcpyAsync(hs, bsc, 10 * sizeof(double), hipMemcpyDeviceToHost, stream));
+        sync();
+        const double rho_c = hs[5];   // H-energy at the start of this cycle
+        eta = hs[9] + hs[1];
+        if (eta0 < 0.0) {
+            eta0 = eta;
+            st.residual_initial = eta0 > 0.0 ? std::sqrt(eta0) : 0.0;
+            if (!(eta0 > 0.0)) {   // f vanishes on W~: u = 0
+                st.breakdown = 1;
+                conv = true;
+                break;
+            }
+        }
+        if (std::sqrt(std::max(eta, 0.0) / eta0) <= pl.opt.tol) {
+            conv = true;
+            break;
+        }
+        auto raise_omega = [&]() {
+            if (++raises > 8) throw Error(IETI_ENOCONV, "saddle-point iteration: no positive omega scaling found");
+            w *= 1.5;
+            bp_omega = w;
+            fill<double>(bx, n, 0.0);
+            if (nl > 0) fill<double>(lxx, nl, 0.0);
+            eta0 = -1.0;
+            fresh = true;
+        };
+        if (!(rho_c > 0.0)) {
+            raise_omega();
+            continue;
+        }
+        fresh = false;
+        const double cycle_goal = std::max(pl.opt.tol * std::sqrt(eta0 / eta), restart_red);
+        double rho_min = rho_c;
+        bool restart_over = false;
+        for (int cit = 0; it < pl.opt.max_it; ++cit) {
+            // s = A~ p, t = P^{-1} s, Ht
+            applyA(bp, bs);
+            if (nl > 0) {
+                scatter(lpp, false, bg2);
+                hipLaunchKernelGGL(k_add<double>, dim3(tile_grid(D0.nt_all)), dim3(TILE), 0, stream, D0.L,
+                                   D0.tiles_all, D0.nt_all, (const double*)bg2, bs);
+                check_launch();
+                gather(bp, false, lss);
+            }
+            A0inv(bs, bt, w);
+            if (nl > 0) {
+                gather(bt, false, lht);
+                axpy_dev(nl, lht, lss, 12, -1.0);   // Ht_l = B t_u - s_l
+                applyPrec(lht, ltt);
+            }
+            applyA(bt, bht);
+            sub(bht, bs);
+            flat_dot(n, bp, bht, bsc + 2);
+            flat_dot(nl, lpp, lht, bsc + 3);
+            hipLaunchKernelGGL(k_bp_scalars, dim3(1), dim3(1), 0, stream, 1, bsc);
+            check_launch();
+            axpy_dev(n, bx, bp, 6, 1.0);
+            axpy_dev(n, bz, bt, 6, -1.0);
+            axpy_dev(n, bhz, bht, 6, -1.0);
+            if (nl > 0) {
+                axpy_dev(nl, lxx, lpp, 6, 1.0);
+                axpy_dev(nl, lzz, ltt, 6, -1.0);
+                axpy_dev(nl, lhz, lht, 6, -1.0);
+            }
+            flat_dot(n, bz, bhz, bsc + 0);
+            flat_dot(nl, lzz, lhz, bsc + 1);
+            hipLaunchKernelGGL(k_bp_scalars, dim3(1), dim3(1), 0, stream, 2, bsc);
+            check_launch();
+            HIPCHECK(hipMemcpyAsync(hs, bsc, 10 * sizeof(double), hipMemcpyDeviceToHost, stream));
+            sync();
+            ++it;
+            const double rho = hs[4];
+            if (hs[8] != 0.0) {   // (p, H P^{-1} A~ p) <= 0 or rho <= 0: indefinite H, or rounding in a late step
+                if (cit == 0) restart_over = true;
+                break;
+            }
+            const double red = std::sqrt(std::max(rho, 0.0) / rho_c);
+            rho_min = std::min(rho_min, rho);
+            if (red <= cycle_goal || rho > 1e6 * rho_min) break;   // restart from the true residual
+            xpby_dev(n, bp, bz, 7);
+            xpby_dev(nl, lpp, lzz, 7);
+        }
+        if (restart_over) raise_omega();
+    }
+    copy_dev(n, u64, bx);
+    st.outer_iterations = it;
+    st.residual_final = std::sqrt(std::max(eta, 0.0));
+    st.saddle_omega = bp_omega;
+    return conv ? IETI_OK : IETI_ENOCONV;
+}
+
+// u64 (torn, level-0 layout) -> averaged interface copies, FP64 assembled residual, caller's torn output
+template <typename T>
+void Solver<T>::finish_solution(ieti_stats& st, double* u_out) {
+    DevLevel& D0 = lev[0];
     if (ngroups > 0) {
         hipLaunchKernelGGL(k_group_mean, dim3(nblk(ngroups, 256)), dim3(256), 0, stream, ngroups, grp_ptr, grp_dev,
                            u64);
@@ -1543,23 +1925,6 @@ int Solver<T>::solve(const double* f_qp, double* u_out, ieti_stats* stp) {
                        torn_off, u64, u_out);
     check_launch();
     sync();
-    auto t3 = clk::now();
-    if (prof.on) prof.collect();
-    st.time_rhs_ms = ms(t0, t1);
-    st.time_pcg_ms = ms(t1, t2);
-    st.time_recovery_ms = ms(t2, t3);
-    st.time_total_ms = ms(t0, t3);
-    {
-        int h4[4];
-        HIPCHECK(hipMemcpy(h4, nactive, sizeof(h4), hipMemcpyDeviceToHost));
-        inner_sum = h4[1];
-        inner_max = h4[2];
-        inner_calls = h4[3];
-    }
-    st.inner_iterations_max = inner_max;
-    st.inner_iterations_mean = inner_calls ? (double)inner_sum / (double)inner_calls : 0.0;
-    if (stp) *stp = st;
-    return conv ? IETI_OK : IETI_ENOCONV;
 }
 
 }  // namespace ieti

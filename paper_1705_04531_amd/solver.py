@@ -27,8 +27,8 @@ def default_options(**overrides) -> IetiOptions:
 def options_for(wl, **overrides) -> IetiOptions:
     """Options implied by a workload description (local solver, MG precision, primal set, tolerances)."""
     o = dict(
-        local_solver={"exact": _abi.IETI_LOCAL_EXACT, "exact_mg": _abi.IETI_LOCAL_EXACT_MG}.get(wl.local_solver,
-                                                                                            _abi.IETI_LOCAL_MG),
+        local_solver={"exact": _abi.IETI_LOCAL_EXACT, "exact_mg": _abi.IETI_LOCAL_EXACT_MG,
+                      "mg_saddle": _abi.IETI_LOCAL_MG_SADDLE}.get(wl.local_solver, _abi.IETI_LOCAL_MG),
         mg_precision=int(wl.mg_precision),
         primal=_abi.IETI_PRIMAL_VERTICES | (_abi.IETI_PRIMAL_EDGES if wl.primal == "vertices+edges" else 0),
         tol=float(wl.tol),

@@ -179,4 +179,4 @@ def test_exact_neumann_mg_dirichlet_plan(lib):
     with pytest.raises(_abi.IetiError):          # no factor at all
         pm.array(_abi.IETI_ARR_BAND, 0, 0)
     with pytest.raises(_abi.IetiError):
-        Plan(wl.patches, default_options(local_solver=3))
+        Plan(wl.patches, default_options(local_solver=4))
