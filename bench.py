@@ -250,6 +250,22 @@ def main():
                 "ms_per_step": round(dms, 3), "outer_iterations": dst["outer_iterations"],
                 "rel_l2_diff_vs_plain": float(torch.linalg.norm(ud - up) / torch.linalg.norm(up))}
             ds.close()
+        # MG-MG-S: Bramble-Pasciak CG on the saddle-point system, three V-cycles (FP64 and FP32) for K~
+        for prec in (64, 32):
+            bs_ = Solver(wl.patches, options_for(wl, local_solver=_abi.IETI_LOCAL_MG_SADDLE, mg_precision=prec))
+            ub = torch.empty_like(u)
+            bs_.solve(f, ub)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                _, bst = bs_.solve(f, ub)
+            torch.cuda.synchronize()
+            bms = (time.perf_counter() - t0) / args.steps * 1e3
+            plain[f"saddle_point_bpcg_mg{prec}"] = {
+                "ms_per_step": round(bms, 3), "outer_iterations": bst["outer_iterations"],
+                "omega": round(bst["saddle_omega"], 4),
+                "rel_l2_diff_vs_plain": float(torch.linalg.norm(ub - up) / torch.linalg.norm(up))}
+            bs_.close()
 
     dom = prof[_abi.IETI_KPROF_SMOOTH_FINE]
     achieved = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9 if dom["ms"] > 0 else 0.0
