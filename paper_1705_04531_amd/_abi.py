@@ -23,6 +23,8 @@ IETI_LOCAL_EXACT_MG = 2
 IETI_LOCAL_MG_SADDLE = 3
 IETI_PRIMAL_VERTICES = 1
 IETI_PRIMAL_EDGES = 2
+IETI_SMOOTHER_CHEBYSHEV = 0
+IETI_SMOOTHER_TENSOR = 1
 
 IETI_ARR_STENCIL = 1
 IETI_ARR_STENCIL_OFFS = 2
@@ -34,6 +36,9 @@ IETI_ARR_QP_WEIGHT = 7
 IETI_ARR_LMAX = 8
 IETI_ARR_PRIMAL_MAP = 9
 IETI_ARR_BAND = 10
+IETI_ARR_TENSOR_U = 11
+IETI_ARR_TENSOR_LAMBDA = 12
+IETI_ARR_TENSOR_PARAMS = 13
 
 IETI_KPROF_SMOOTH_FINE = 0
 IETI_KPROF_APPLY64 = 1
@@ -72,6 +77,8 @@ class IetiOptions(C.Structure):
         ("coarse_level", C.c_int32),
         ("autotune", C.c_int32),
         ("coarse_dofs", C.c_int32),
+        ("smoother", C.c_int32),
+        ("smoother_sigma", C.c_double),
     ]
 
 

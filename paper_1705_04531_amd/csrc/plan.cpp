@@ -52,6 +52,8 @@ void default_options(ieti_options* o) {
     o->coarse_level = 0;
     o->coarse_dofs = 600;
     o->autotune = 0;
+    o->smoother = IETI_SMOOTHER_CHEBYSHEV;
+    o->smoother_sigma = 0.3;
     o->device = -1;
     o->stream = nullptr;
     o->hbm_budget = 0;
@@ -344,6 +346,7 @@ static void assemble_level(Patch& P, Level& L, bool level0) {
         P.n_qp = (int64_t)Q0 * Q1 * Q2;
         P.qpw.assign(P.n_qp, 0.0);
         P.qpx.assign(P.n_qp * dim, 0.0);
+        for (int d = 0; d < dim; ++d) P.qpc[d].assign(P.n_qp, 0.0);
     }
     if (P.affine) {
         // constant Jacobian A: columns = ctrl(corner e_d) - ctrl(corner 0)
@@ -411,6 +414,7 @@ static void assemble_level(Patch& P, Level& L, bool level0) {
                         int64_t q = q0 + (int64_t)Q0 * (q1 + (int64_t)Q1 * q2);
                         double wq = dt[0].w[q0] * dt[1].w[q1] * (dim == 3 ? dt[2].w[q2] : 1.0);
                         P.qpw[q] = wq * det;
+                        for (int d = 0; d < dim; ++d) P.qpc[d][q] = Gh[d][d];
                         double xi[3] = {dt[0].xi[q0], dt[1].xi[q1], dim == 3 ? dt[2].xi[q2] : 0.0};
                         for (int c = 0; c < dim; ++c) {
                             double x = c0[c];
@@ -494,6 +498,7 @@ static void assemble_level(Patch& P, Level& L, bool level0) {
                                 int64_t q = qd[0] + (int64_t)Q0 * (qd[1] + (int64_t)Q1 * (dim == 3 ? qd[2] : 0));
                                 P.qpw[q] = wq * det;
                                 for (int c = 0; c < dim; ++c) P.qpx[q * dim + c] = x[c];
+                                for (int d = 0; d < dim; ++d) P.qpc[d][q] = Gm[d][d] / wq;
                             }
                             // space basis gradients (parameter domain) and G * grad
                             const double* Nv[3];
@@ -607,6 +612,301 @@ static double power_lmax(const Patch& P, const Level& L, int mode) {
         for (int64_t i = 0; i < L.n; ++i) x[i] = y[i] * sc;
     }
     return lam;
+}
+
+// ----------------------------------------------------------------------------
+// tensor-product smoother of the finest level (2D)
+
+// Best rank-one approximation g ~ a b^T of a positive Q0 x Q1 array g[q0 + Q0 q1]: the leading singular
+// pair by alternating power steps.
+static void rank_one(const std::vector<double>& g, int Q0, int Q1, std::vector<double>& a, std::vector<double>& b) {
+    a.assign(Q0, 0.0);
+    b.assign(Q1, 1.0);
+    std::vector<double> nb(Q1);
+    for (int it = 0; it < 200; ++it) {
+        double bb = 0.0;
+        for (double v : b) bb += v * v;
+        for (int i = 0; i < Q0; ++i) {
+            double t = 0.0;
+            for (int j = 0; j < Q1; ++j) t += g[i + (size_t)Q0 * j] * b[j];
+            a[i] = t / bb;
+        }
+        double aa = 0.0;
+        for (double v : a) aa += v * v;
+        double diff = 0.0, mx = 0.0;
+        for (int j = 0; j < Q1; ++j) {
+            double t = 0.0;
+            for (int i = 0; i < Q0; ++i) t += g[i + (size_t)Q0 * j] * a[i];
+            nb[j] = t / aa;
+            diff = std::max(diff, std::fabs(nb[j] - b[j]));
+            mx = std::max(mx, std::fabs(nb[j]));
+        }
+        b.swap(nb);
+        if (diff <= 1e-15 * mx) break;
+    }
+}
+
+// Symmetric eigenproblem A = Z diag(w) Z^T (A row-major n x n, destroyed; Z row-major, eigenvectors by
+// columns): Householder reduction to tridiagonal form, then implicit QL sweeps with the shift from the
+// leading 2 x 2 block; both accumulate their orthogonal transformations into Z.
+static void sym_eig(int n, std::vector<double>& A, std::vector<double>& w, std::vector<double>& Z) {
+    Z.assign((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) Z[(size_t)i * n + i] = 1.0;
+    std::vector<double> v(n, 0.0), pv(n, 0.0), qv(n, 0.0);
+    for (int k = 0; k + 2 < n; ++k) {
+        double alpha = 0.0;
+        for (int i = k + 1; i < n; ++i) alpha += A[(size_t)i * n + k] * A[(size_t)i * n + k];
+        alpha = std::sqrt(alpha);
+        if (alpha == 0.0) continue;
+        const double sg = A[(size_t)(k + 1) * n + k] >= 0.0 ? 1.0 : -1.0;
+        for (int i = k + 1; i < n; ++i) v[i] = A[(size_t)i * n + k];
+        v[k + 1] += sg * alpha;
+        double vn = 0.0;
+        for (int i = k + 1; i < n; ++i) vn += v[i] * v[i];
+        vn = std::sqrt(vn);
+        for (int i = k + 1; i < n; ++i) v[i] /= vn;
+        // H = I - 2 v v^T maps column k below the diagonal to -sg alpha e_{k+1}
+        for (int i = k + 1; i < n; ++i) A[(size_t)i * n + k] = A[(size_t)k * n + i] = 0.0;
+        A[(size_t)(k + 1) * n + k] = A[(size_t)k * n + k + 1] = -sg * alpha;
+        // trailing block: A <- H A H = A - v q^T - q v^T, q = 2 (A v - (v^T A v) v)
+        double K = 0.0;
+        for (int i = k + 1; i < n; ++i) {
+            double t = 0.0;
+            for (int j = k + 1; j < n; ++j) t += A[(size_t)i * n + j] * v[j];
+            pv[i] = t;
+            K += v[i] * t;
+        }
+        for (int i = k + 1; i < n; ++i) qv[i] = 2.0 * (pv[i] - K * v[i]);
+        for (int i = k + 1; i < n; ++i)
+            for (int j = k + 1; j < n; ++j) A[(size_t)i * n + j] -= v[i] * qv[j] + qv[i] * v[j];
+        // Z <- Z H
+        for (int r = 0; r < n; ++r) {
+            double t = 0.0;
+            for (int j = k + 1; j < n; ++j) t += Z[(size_t)r * n + j] * v[j];
+            for (int j = k + 1; j < n; ++j) Z[(size_t)r * n + j] -= 2.0 * t * v[j];
+        }
+    }
+    std::vector<double> d(n), e(n, 0.0);
+    for (int i = 0; i < n; ++i) d[i] = A[(size_t)i * n + i];
+    for (int i = 0; i + 1 < n; ++i) e[i] = A[(size_t)(i + 1) * n + i];   // e[i] couples d[i] and d[i+1]
+    for (int l = 0; l < n; ++l) {
+        for (int iter = 0;; ++iter) {
+            int m = l;
+            for (; m + 1 < n; ++m)
+                if (std::fabs(e[m]) <= 1e-16 * (std::fabs(d[m]) + std::fabs(d[m + 1]))) break;
+            if (m == l) break;
+            if (iter > 100) throw Error(IETI_EINVAL, "tensor smoother: eigenvalue iteration did not converge");
+            double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+            double r = std::hypot(g, 1.0);
+            g = d[m] - d[l] + e[l] / (g + (g >= 0.0 ? r : -r));
+            double sn = 1.0, cs = 1.0, pp = 0.0;
+            bool split = false;
+            for (int i = m - 1; i >= l; --i) {
+                const double f = sn * e[i], b = cs * e[i];
+                r = std::hypot(f, g);
+                e[i + 1] = r;
+                if (r == 0.0) {   // the rotation decouples the matrix: restart on the smaller block
+                    d[i + 1] -= pp;
+                    e[m] = 0.0;
+                    split = true;
+                    break;
+                }
+                sn = f / r;
+                cs = g / r;
+                g = d[i + 1] - pp;
+                r = (d[i] - g) * sn + 2.0 * cs * b;
+                pp = sn * r;
+                d[i + 1] = g + pp;
+                g = cs * r - b;
+                for (int k = 0; k < n; ++k) {
+                    const double z1 = Z[(size_t)k * n + i + 1], z0 = Z[(size_t)k * n + i];
+                    Z[(size_t)k * n + i + 1] = sn * z0 + cs * z1;
+                    Z[(size_t)k * n + i] = cs * z0 - sn * z1;
+                }
+            }
+            if (split) continue;
+            d[l] -= pp;
+            e[l] = g;
+            e[m] = 0.0;
+        }
+    }
+    w = d;
+}
+
+// Generalised eigenproblem A U = B U diag(lam), U^T B U = I (A symmetric, B SPD, n x n row-major):
+// B = L L^T, C = L^{-1} A L^{-T} = Z diag(lam) Z^T, U = L^{-T} Z.
+static void gen_eig(int n, const std::vector<double>& A, const std::vector<double>& B, std::vector<double>& U,
+                    std::vector<double>& lam) {
+    std::vector<double> L((size_t)n * n, 0.0);
+    for (int j = 0; j < n; ++j) {
+        double dd = B[(size_t)j * n + j];
+        for (int k = 0; k < j; ++k) dd -= L[(size_t)j * n + k] * L[(size_t)j * n + k];
+        if (!(dd > 0.0)) throw Error(IETI_EINVAL, "tensor smoother: 1D mass matrix not positive definite");
+        const double ljj = std::sqrt(dd);
+        L[(size_t)j * n + j] = ljj;
+        for (int i = j + 1; i < n; ++i) {
+            double t = B[(size_t)i * n + j];
+            for (int k = 0; k < j; ++k) t -= L[(size_t)i * n + k] * L[(size_t)j * n + k];
+            L[(size_t)i * n + j] = t / ljj;
+        }
+    }
+    // X = L^{-1} A (column by column), C = L^{-1} X^T
+    std::vector<double> X((size_t)n * n), C((size_t)n * n);
+    auto fwd = [&](const double* rhs, int stride, double* out) {   // out = L^{-1} rhs (rhs entries at stride)
+        for (int i = 0; i < n; ++i) {
+            double t = rhs[(size_t)i * stride];
+            for (int k = 0; k < i; ++k) t -= L[(size_t)i * n + k] * out[k];
+            out[i] = t / L[(size_t)i * n + i];
+        }
+    };
+    std::vector<double> col(n);
+    for (int j = 0; j < n; ++j) {
+        fwd(&A[j], n, col.data());
+        for (int i = 0; i < n; ++i) X[(size_t)i * n + j] = col[i];
+    }
+    for (int j = 0; j < n; ++j) {
+        fwd(&X[(size_t)j * n], 1, col.data());   // column j of X^T is row j of X
+        for (int i = 0; i < n; ++i) C[(size_t)i * n + j] = col[i];
+    }
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < i; ++j) C[(size_t)i * n + j] = C[(size_t)j * n + i] = 0.5 * (C[(size_t)i * n + j] + C[(size_t)j * n + i]);
+    std::vector<double> Z;
+    sym_eig(n, C, lam, Z);
+    // U = L^{-T} Z
+    U.assign((size_t)n * n, 0.0);
+    for (int j = 0; j < n; ++j)
+        for (int i = n - 1; i >= 0; --i) {
+            double t = Z[(size_t)i * n + j];
+            for (int k = i + 1; k < n; ++k) t -= L[(size_t)k * n + i] * U[(size_t)k * n + j];
+            U[(size_t)i * n + j] = t / L[(size_t)i * n + i];
+        }
+}
+
+// y = m U (Lambda_0 (+) Lambda_1 + c)^{-1} U^T m r on one patch (host, for the damping estimate)
+static void tensor_apply_host(const Patch::Tensor& T, int M0, int M1, const std::vector<uint8_t>& mask,
+                              const double* r, double* y) {
+    const int P0 = T.Pd[0], P1 = T.Pd[1];
+    std::vector<double> W((size_t)M1 * P0, 0.0), Z((size_t)P1 * P0, 0.0), V((size_t)M1 * P0, 0.0);
+    for (int i1 = 0; i1 < M1; ++i1)
+        for (int i0 = 0; i0 < M0; ++i0) {
+            const size_t i = (size_t)i0 + (size_t)M0 * i1;
+            if (mask[i]) continue;
+            const double x = r[i];
+            for (int a = 0; a < P0; ++a) W[(size_t)i1 * P0 + a] += x * T.U[0][(size_t)i0 * P0 + a];
+        }
+    for (int b = 0; b < P1; ++b)
+        for (int a = 0; a < P0; ++a) {
+            double t = 0.0;
+            for (int i1 = 0; i1 < M1; ++i1) t += T.U[1][(size_t)i1 * P1 + b] * W[(size_t)i1 * P0 + a];
+            Z[(size_t)b * P0 + a] = t / (T.lam[0][a] + T.lam[1][b] + T.shift);
+        }
+    for (int i1 = 0; i1 < M1; ++i1)
+        for (int a = 0; a < P0; ++a) {
+            double t = 0.0;
+            for (int b = 0; b < P1; ++b) t += T.U[1][(size_t)i1 * P1 + b] * Z[(size_t)b * P0 + a];
+            V[(size_t)i1 * P0 + a] = t;
+        }
+    for (int i1 = 0; i1 < M1; ++i1)
+        for (int i0 = 0; i0 < M0; ++i0) {
+            const size_t i = (size_t)i0 + (size_t)M0 * i1;
+            double t = 0.0;
+            if (!mask[i])
+                for (int a = 0; a < P0; ++a) t += V[(size_t)i1 * P0 + a] * T.U[0][(size_t)i0 * P0 + a];
+            y[i] = t;
+        }
+}
+
+// Finest-level tensor smoother of a 2D patch for the Neumann (if mode_n) and Dirichlet modes: rank-one
+// fits g_00 ~ a00 (x) b00 and g_11 ~ a11 (x) b11 of the metric diagonals on the quadrature grid (the mass
+// weights b00 and a11 scaled to unit mean), 1D matrices A_0 = (a00 u', v'), B_0 = (a11 u, v),
+// A_1 = (b11 u', v'), B_1 = (b00 u, v), so that K_sep = A_0 (x) B_1 + B_0 (x) A_1, and per mode the
+// generalised eigenvectors on the coefficients the mode keeps (its masked sides removed per direction;
+// masked corners stay in the tensor space and are cut by the mask).
+static void tensor_setup(Patch& P, const ieti_options& opt, bool mode_n) {
+    const Level& L0 = P.lv[0];
+    DirTable dt[2];
+    for (int d = 0; d < 2; ++d) dt[d] = make_dir(L0.knots[d], P.p[d], P.knots[d], P.p[d]);
+    const int Q0 = dt[0].Q, Q1 = dt[1].Q;
+    std::vector<double> a00, b00, a11, b11;
+    rank_one(P.qpc[0], Q0, Q1, a00, b00);
+    rank_one(P.qpc[1], Q0, Q1, a11, b11);
+    double m1 = 0.0, m0 = 0.0;
+    for (int q = 0; q < Q1; ++q) m1 += dt[1].w[q] * b00[q];
+    for (int q = 0; q < Q0; ++q) m0 += dt[0].w[q] * a11[q];
+    for (auto& v : b00) v /= m1;
+    for (auto& v : a00) v *= m1;
+    for (auto& v : a11) v /= m0;
+    for (auto& v : b11) v *= m0;
+    auto weighted = [](const DirTable& t, int M, const std::vector<double>& ws, const std::vector<double>& wm,
+                       std::vector<double>& A, std::vector<double>& B) {
+        A.assign((size_t)M * M, 0.0);
+        B.assign((size_t)M * M, 0.0);
+        const int p = t.p;
+        for (int q = 0; q < t.Q; ++q)
+            for (int a = 0; a <= p; ++a)
+                for (int b = 0; b <= p; ++b) {
+                    const int i = t.first[q] + a, j = t.first[q] + b;
+                    const size_t o = (size_t)q * (p + 1);
+                    A[(size_t)i * M + j] += t.w[q] * ws[q] * t.dN[o + a] * t.dN[o + b];
+                    B[(size_t)i * M + j] += t.w[q] * wm[q] * t.N[o + a] * t.N[o + b];
+                }
+    };
+    std::vector<double> A1d[2], B1d[2];
+    weighted(dt[0], L0.M[0], a00, a11, A1d[0], B1d[0]);
+    weighted(dt[1], L0.M[1], b11, b00, A1d[1], B1d[1]);
+    const double shift = opt.smoother_sigma * 0.5 * ((double)L0.nel[0] * L0.nel[0] + (double)L0.nel[1] * L0.nel[1]);
+    for (int mode = 0; mode < 2; ++mode) {
+        if (mode == MODE_N && !mode_n) continue;
+        Patch::Tensor& T = P.ts[mode];
+        const uint32_t sides = mode == MODE_D ? 0xFu : P.bside;
+        for (int d = 0; d < 2; ++d) {
+            const int M = L0.M[d];
+            std::vector<int> keep;
+            for (int i = 0; i < M; ++i) {
+                const bool cut = (i == 0 && (sides >> (2 * d) & 1u)) || (i == M - 1 && (sides >> (2 * d + 1) & 1u));
+                if (!cut) keep.push_back(i);
+            }
+            const int nk = (int)keep.size();
+            std::vector<double> Ak((size_t)nk * nk), Bk((size_t)nk * nk), Uk, lk;
+            for (int i = 0; i < nk; ++i)
+                for (int j = 0; j < nk; ++j) {
+                    Ak[(size_t)i * nk + j] = A1d[d][(size_t)keep[i] * M + keep[j]];
+                    Bk[(size_t)i * nk + j] = B1d[d][(size_t)keep[i] * M + keep[j]];
+                }
+            gen_eig(nk, Ak, Bk, Uk, lk);
+            const int Pd = (M + 15) / 16 * 16;
+            T.Pd[d] = Pd;
+            T.U[d].assign((size_t)Pd * Pd, 0.0);
+            T.lam[d].assign(Pd, 1e300);
+            for (int i = 0; i < nk; ++i)
+                for (int a = 0; a < nk; ++a) T.U[d][(size_t)keep[i] * Pd + a] = Uk[(size_t)i * nk + a];
+            for (int a = 0; a < nk; ++a) T.lam[d][a] = lk[a];
+        }
+        T.shift = shift;
+        // tau = 1 / lambda_max(m S^{-1} m K) by power steps
+        auto mask = level_mask(P, L0, mode);
+        std::vector<double> x(L0.n), y(L0.n), z(L0.n);
+        uint64_t sd = 0xBF58476D1CE4E5B9ull;
+        for (int64_t i = 0; i < L0.n; ++i) {
+            sd ^= sd << 13; sd ^= sd >> 7; sd ^= sd << 17;
+            x[i] = mask[i] ? 0.0 : ((sd >> 11) * (1.0 / 9007199254740992.0) - 0.5);
+        }
+        double lam = 1.0;
+        for (int it = 0; it < 20; ++it) {
+            host_apply(P, L0, mask, x.data(), y.data());
+            tensor_apply_host(T, L0.M[0], L0.M[1], mask, y.data(), z.data());
+            double nx = 0.0, nz = 0.0;
+            for (int64_t i = 0; i < L0.n; ++i) {
+                nx += x[i] * x[i];
+                nz += z[i] * z[i];
+            }
+            if (!(nz > 0.0) || !(nx > 0.0)) break;
+            lam = std::sqrt(nz / nx);
+            const double sc = 1.0 / std::sqrt(nz);
+            for (int64_t i = 0; i < L0.n; ++i) x[i] = z[i] * sc;
+        }
+        T.tau = 1.0 / lam;
+    }
 }
 
 // dense inverse of the masked level matrix (masked rows/cols zero) by Cholesky
@@ -781,7 +1081,13 @@ Plan* build_plan(const ieti_patch* in, int n, const double* pv, int n_pv, const 
     if (opt.coarse_dofs < 0) throw Error(IETI_EINVAL, "coarse_dofs must be >= 0");
     if (opt.cheb_degree < 0 || opt.cheb_degree > 8 || opt.cheb_degree_coarse < 0 || opt.cheb_degree_coarse > 8)
         throw Error(IETI_EINVAL, "Chebyshev degrees must be in 0..8");
+    if (opt.smoother != IETI_SMOOTHER_CHEBYSHEV && opt.smoother != IETI_SMOOTHER_TENSOR)
+        throw Error(IETI_EINVAL, "unknown smoother");
+    if (opt.smoother == IETI_SMOOTHER_TENSOR && !(opt.smoother_sigma > 0))
+        throw Error(IETI_EINVAL, "smoother_sigma must be positive");
     const int dim = in[0].dim;
+    if (opt.smoother == IETI_SMOOTHER_TENSOR && dim != 2)
+        throw Error(IETI_ENOTSUP, "the tensor smoother is built for 2D patches");
     for (int k = 0; k < n; ++k) validate_patch(in[k], dim, k);
     auto P = std::make_unique<Plan>();
     Plan& pl = *P;
@@ -1228,6 +1534,7 @@ Plan* build_plan(const ieti_patch* in, int n, const double* pv, int n_pv, const 
                 if (neumann_mg) pa.lv[l].lmax[MODE_N] = power_lmax(pa, pa.lv[l], MODE_N);
                 pa.lv[l].lmax[MODE_D] = power_lmax(pa, pa.lv[l], MODE_D);
             }
+        if (mg && opt.smoother == IETI_SMOOTHER_TENSOR && pa.lv.size() > 1) tensor_setup(pa, opt, neumann_mg);
         Level& cl = pa.lv.back();
         if (mg) {
             if (neumann_mg) cl.inv[MODE_N] = dense_inverse(pa, cl, MODE_N);
@@ -1318,6 +1625,18 @@ int ieti_plan_array(const ieti_plan* plan, int32_t which, int32_t patch, int32_t
     if (which == IETI_ARR_BAND) {
         if (level < 0 || level > 1 || pa.band[level].empty()) return IETI_EINVAL;
         return emit(pa.band[level].data(), (int64_t)pa.band[level].size(), sizeof(double));
+    }
+    if (which == IETI_ARR_TENSOR_U || which == IETI_ARR_TENSOR_LAMBDA || which == IETI_ARR_TENSOR_PARAMS) {
+        const int mode = which == IETI_ARR_TENSOR_PARAMS ? level : level >> 8, d = level & 255;
+        if (mode < 0 || mode > 1 || pa.ts[mode].U[0].empty()) return IETI_EINVAL;
+        const Patch::Tensor& T = pa.ts[mode];
+        if (which == IETI_ARR_TENSOR_PARAMS) {
+            double v[4] = {(double)T.Pd[0], (double)T.Pd[1], T.shift, T.tau};
+            return emit(v, 4, sizeof(double));
+        }
+        if (d < 0 || d >= p.dim) return IETI_EINVAL;
+        if (which == IETI_ARR_TENSOR_U) return emit(T.U[d].data(), (int64_t)T.U[d].size(), sizeof(double));
+        return emit(T.lam[d].data(), (int64_t)T.lam[d].size(), sizeof(double));
     }
     int lev = which == IETI_ARR_PROLONG ? (level & 255) : level;
     if (lev < 0 || lev >= (int)pa.lv.size()) return IETI_EINVAL;

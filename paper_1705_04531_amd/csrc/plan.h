@@ -56,6 +56,14 @@ struct Patch {
     std::vector<double> qpw;       // w_q |det J_q| at the level-0 quadrature points
     std::vector<double> qpx;       // physical quadrature points, n_qp * dim
     std::vector<double> qpN[3];    // level-0 space basis at the quadrature points, Q_d x (p_d+1)
+    std::vector<double> qpc[3];    // level 0: metric diagonal |det J| (J^{-1} J^{-T})_dd at the quadrature points
+    // tensor-product smoother of the finest level, per mode (N, D): generalised eigenvectors U_d (P_d x P_d,
+    // row-major, zero rows for coefficients the mode removes, zero padding) and eigenvalues (1e300 padding)
+    struct Tensor {
+        int Pd[3] = {0, 0, 0};
+        std::vector<double> U[3], lam[3];
+        double shift = 0.0, tau = 0.0;
+    } ts[2];
     int64_t n_qp = 0;
     int64_t torn_off = 0;          // first coefficient in the torn layout
     // exact local solves: banded Cholesky factor L of the masked stiffness (modes N, D) in

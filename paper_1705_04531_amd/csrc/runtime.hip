@@ -273,6 +273,13 @@ struct Solver : SolverBase {
     int cheb_mc = 2;    // coarse levels
     bool stage_all0 = false;   // every finest-level smoothing tile runs a staged (x window in LDS) instance
     double cheb_hi = 1.1;
+    // tensor-product smoother of the finest level (options.smoother): per mode and patch the factors of
+    // the fast diagonalisation, the forward transform's scratch, the largest padded sizes
+    bool fd_on = false;
+    FdInfo* fd_info[2] = {nullptr, nullptr};
+    double *fd_U = nullptr, *fd_lam = nullptr, *fd_z = nullptr;
+    int fd_p0max = 0, fd_p1max = 0;
+    size_t fd_lds = 0;
     // level 0 FP64
     double* coef64 = nullptr;
     int64_t len0 = 0;
@@ -412,6 +419,17 @@ struct Solver : SolverBase {
     // x0 = V(b0) on all patches (mode N or D); the result lands in x0.  Levels
     // below fuse_l0 run as batched launches over all patches; from fuse_l0 on,
     // one work-group per patch runs the rest of the cycle (k_vcoarse).
+    // finest level, patches with tensor-smoother data: x = tau P r (set) or x += tau P r
+    void fd_smooth(int mode, const int* act, const T* r, T* x, bool set) {
+        FdArgs a{lev[0].L, fd_info[mode], fd_U, fd_lam, fd_z, act, mode};
+        hipLaunchKernelGGL(k_fd_fwd<T>, dim3(fd_p0max / 16, N), dim3(FD_THREADS), fd_lds, stream, a, r);
+        check_launch();
+        if (set)
+            hipLaunchKernelGGL((k_fd_bwd<T, true>), dim3(fd_p0max / 16, N), dim3(FD_THREADS), fd_lds, stream, a, x);
+        else
+            hipLaunchKernelGGL((k_fd_bwd<T, false>), dim3(fd_p0max / 16, N), dim3(FD_THREADS), fd_lds, stream, a, x);
+        check_launch();
+    }
     void vcycle(int mode, const int* act, const T* b0, T* x0, const double* dotq = nullptr, double* dpart = nullptr) {
         std::vector<T*> cur(nlev, nullptr);
         int deepest = 0;
@@ -434,23 +452,30 @@ struct Solver : SolverBase {
             cur[l] = F;
             deepest = l;
             if (D.nt_smooth == 0) break;
-            // pre-smoothing: Chebyshev from zero (on the finest level the zero start is fused into step 1)
+            // pre-smoothing: Chebyshev from zero (on the finest level the zero start is fused into step 1),
+            // or one tensor-smoother step from zero on the finest level
             T* X = S;
             T* XA = F;
-            const int m = l == 0 ? cheb_m : cheb_mc;
-            int k1 = 1;
-            if (l == 0 && m >= 2 && stage_all0) {
-                stencil<T, T, T, EPI_CHEB0>(0, true, mode, D.coefT, nullptr, XA, B, D.vd, act, 0.0, 1);
-                std::swap(X, XA);
-                k1 = 2;
+            if (l == 0 && fd_on) {
+                fd_smooth(mode, act, B, F, true);
+                X = F;
             } else {
-                hipLaunchKernelGGL(k_cheb_zero<T>, dim3(tile_grid(D.nt_smooth)), dim3(TILE), 0, stream, D.L,
-                                   D.tiles_smooth, D.nt_smooth, (const T*)D.coefT, B, X, (T*)D.vd, mode, D.cheb, act);
-                check_launch();
-            }
-            for (int k = k1; k < m; ++k) {
-                stencil<T, T, T, EPI_CHEB>(l, true, mode, D.coefT, X, XA, B, D.vd, act, 0.0, k);
-                std::swap(X, XA);
+                const int m = l == 0 ? cheb_m : cheb_mc;
+                int k1 = 1;
+                if (l == 0 && m >= 2 && stage_all0) {
+                    stencil<T, T, T, EPI_CHEB0>(0, true, mode, D.coefT, nullptr, XA, B, D.vd, act, 0.0, 1);
+                    std::swap(X, XA);
+                    k1 = 2;
+                } else {
+                    hipLaunchKernelGGL(k_cheb_zero<T>, dim3(tile_grid(D.nt_smooth)), dim3(TILE), 0, stream, D.L,
+                                       D.tiles_smooth, D.nt_smooth, (const T*)D.coefT, B, X, (T*)D.vd, mode, D.cheb,
+                                       act);
+                    check_launch();
+                }
+                for (int k = k1; k < m; ++k) {
+                    stencil<T, T, T, EPI_CHEB>(l, true, mode, D.coefT, X, XA, B, D.vd, act, 0.0, k);
+                    std::swap(X, XA);
+                }
             }
             stencil<T, T, T, EPI_RESID>(l, true, mode, D.coefT, X, D.vr, B, nullptr, act, 0.0, 0);
             cur[l] = X;
@@ -473,12 +498,18 @@ struct Solver : SolverBase {
                                   (const T*)D.pval, (const T*)cur[l + 1], X, mode, act);
                 check_launch();
             }
-            const int m = l == 0 ? cheb_m : cheb_mc;
-            for (int k = 0; k < m; ++k) {
-                const bool last0 = l == 0 && k == m - 1;
-                stencil<T, T, T, EPI_CHEB>(l, true, mode, D.coefT, X, XA, B, D.vd, act, 0.0, k, nullptr, nullptr,
-                                           last0 ? dotq : nullptr, last0 ? dpart : nullptr);
-                std::swap(X, XA);
+            if (l == 0 && fd_on) {   // one tensor-smoother step
+                if (dotq) throw Error(IETI_ENOTSUP, "internal: fused dot with the tensor smoother");
+                stencil<T, T, T, EPI_RESID>(0, true, mode, D.coefT, X, D.vr, B, nullptr, act, 0.0, 0);
+                fd_smooth(mode, act, (const T*)D.vr, X, false);
+            } else {
+                const int m = l == 0 ? cheb_m : cheb_mc;
+                for (int k = 0; k < m; ++k) {
+                    const bool last0 = l == 0 && k == m - 1;
+                    stencil<T, T, T, EPI_CHEB>(l, true, mode, D.coefT, X, XA, B, D.vd, act, 0.0, k, nullptr, nullptr,
+                                               last0 ? dotq : nullptr, last0 ? dpart : nullptr);
+                    std::swap(X, XA);
+                }
             }
             cur[l] = X;
         }
@@ -528,7 +559,7 @@ struct Solver : SolverBase {
                            brk, tol * tol, maxit, nactive);
         check_launch();
         // patches whose finest level is also their coarsest cannot fuse z . q into the smoother
-        const bool fuse_zq = lev[0].n_coarse == 0;
+        const bool fuse_zq = lev[0].n_coarse == 0 && !fd_on;
         // host checks: first near the iteration count the previous solve at this tolerance needed, then
         // every check_every iterations (a sync costs more than an extra iteration of finished patches)
         const int every = std::max(1, plan->opt.check_every);
@@ -936,7 +967,7 @@ struct Solver : SolverBase {
     // Times one batched Neumann solve (a seeded right-hand side, to inner_tol) per
     // candidate smoother around the tuned table and keeps the fastest.
     void autotune_smoother() {
-        if (exact || nlev < 2) return;
+        if (exact || nlev < 2 || fd_on) return;
         std::vector<double> h(len0);
         uint64_t x = 0x9E3779B97F4A7C15ull;
         for (auto& v : h) {
@@ -1290,6 +1321,62 @@ void Solver<T>::setup() {
         }
         HIPCHECK(hipStreamSynchronize(st));
     }
+    // ---- tensor-product smoother of the finest level
+    if (pl.opt.smoother == IETI_SMOOTHER_TENSOR && pl.opt.local_solver != IETI_LOCAL_EXACT && nlev > 1) {
+        std::vector<double> hu, hl;
+        std::vector<FdInfo> info(2 * (size_t)N);
+        int64_t zlen = 0;
+        for (int k = 0; k < N; ++k) {
+            const Patch& pa = pl.patches[k];
+            if (lev[0].hL[k].patch != k) throw Error(IETI_EDEVICE, "internal: level-0 patch order");
+            int64_t zk = 0;
+            for (int m = 0; m < 2; ++m) {
+                const Patch::Tensor& Tz = pa.ts[m];
+                FdInfo& f = info[(size_t)m * N + k];
+                f = FdInfo{};
+                if (Tz.U[0].empty()) continue;
+                f.P0 = Tz.Pd[0];
+                f.P1 = Tz.Pd[1];
+                f.u0 = (int64_t)hu.size();
+                hu.insert(hu.end(), Tz.U[0].begin(), Tz.U[0].end());
+                f.u1 = (int64_t)hu.size();
+                hu.insert(hu.end(), Tz.U[1].begin(), Tz.U[1].end());
+                f.l0 = (int64_t)hl.size();
+                hl.insert(hl.end(), Tz.lam[0].begin(), Tz.lam[0].end());
+                f.l1 = (int64_t)hl.size();
+                hl.insert(hl.end(), Tz.lam[1].begin(), Tz.lam[1].end());
+                f.zoff = zlen;   // one scratch per patch: the two modes never run at the same time
+                f.shift = Tz.shift;
+                f.tau = Tz.tau;
+                zk = std::max(zk, (int64_t)f.P0 * f.P1);
+                fd_p0max = std::max(fd_p0max, f.P0);
+                fd_p1max = std::max(fd_p1max, f.P1);
+            }
+            zlen += zk;
+        }
+        if (fd_p0max > 0) {
+            fd_on = true;
+            fd_U = arena.upload(hu, st);
+            fd_lam = arena.upload(hl, st);
+            fd_z = arena.alloc<double>(zlen, st);
+            std::vector<FdInfo> i0(info.begin(), info.begin() + N), i1(info.begin() + N, info.end());
+            fd_info[0] = arena.upload(i0, st);
+            fd_info[1] = arena.upload(i1, st);
+            fd_lds = fd_lds_words(fd_p0max, fd_p1max) * sizeof(double);
+            int dev = 0, max_lds = 0;
+            HIPCHECK(hipGetDevice(&dev));
+            HIPCHECK(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+            if (fd_lds > (size_t)max_lds)
+                throw Error(IETI_ENOTSUP, "tensor smoother: patch too large for the transforms' LDS");
+            HIPCHECK(hipFuncSetAttribute((const void*)k_fd_fwd<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         (int)fd_lds));
+            HIPCHECK(hipFuncSetAttribute((const void*)k_fd_bwd<T, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         (int)fd_lds));
+            HIPCHECK(hipFuncSetAttribute((const void*)k_fd_bwd<T, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         (int)fd_lds));
+            HIPCHECK(hipStreamSynchronize(st));
+        }
+    }
     // ---- exact local solves
     if (pl.opt.local_solver == IETI_LOCAL_EXACT || pl.opt.local_solver == IETI_LOCAL_EXACT_MG) {
         exact = true;
@@ -1623,7 +1710,7 @@ int Solver<T>::solve(const double* f_qp, double* u_out, ieti_stats* stp) {
     st.ndof_global = pl.ndof_global;
     st.n_lambda = pl.n_lambda;
     st.n_primal = pl.n_primal;
-    st.cheb_degree = exact && prec_exact ? 0 : cheb_m;
+    st.cheb_degree = (exact && prec_exact) || fd_on ? 0 : cheb_m;
     st.cheb_degree_coarse = exact && prec_exact ? 0 : cheb_mc;
     st.cheb_lower = cheb_lower_scale;
     DevLevel& D0 = lev[0];
@@ -1995,6 +2082,9 @@ static size_t estimate_device_bytes(const Plan& pl) {
         b += 2.0 * npk * (double)(pa.lv[0].n + 2 * pa.lv[0].guard + 64) * 8.0;   // Psi + setup scratch
         b += (double)(pa.band[0].size() + pa.band[1].size()) * 8.0;
         b += (double)pa.n_qp * (16.0 + 8.0 * pa.dim);
+        for (int m = 0; m < 2; ++m)   // tensor smoother: U_d, lambda_d, scratch Z
+            if (!pa.ts[m].U[0].empty())
+                b += 8.0 * (double)(pa.ts[m].U[0].size() + pa.ts[m].U[1].size() + 2 * pa.ts[m].Pd[0] * pa.ts[m].Pd[1]);
     }
     const double npad = (double)((pl.n_primal + 15) / 16 * 16);
     b += (double)pl.n_lambda * 8.0 * 8.0 + (double)pl.n_primal * pl.n_primal * 8.0 + 3.0 * npad * npad * 8.0;

@@ -180,3 +180,54 @@ def test_exact_neumann_mg_dirichlet_plan(lib):
         pm.array(_abi.IETI_ARR_BAND, 0, 0)
     with pytest.raises(_abi.IetiError):
         Plan(wl.patches, default_options(local_solver=4))
+
+
+def test_tensor_smoother_factors_match_oracle(lib):
+    """The plan's tensor-smoother data (finest level, modes N and D) against the oracle's separable
+    matrices: U_d^T A_d U_d = Lambda_d and U_d^T B_d U_d = I on the coefficients the mode keeps, zero
+    rows where it removes them, the mass shift, and tau lambda_max(P K) in [0.99, 1.1] with lambda_max from
+    a dense eigenvalue solve of the oracle's smoother (power steps may overshoot it slightly)."""
+    from oracle import tensor_smoother as TS
+    wl = W.deformed_square((3, 3), [[2, 3, 4], [4, 2, 3]], [[12, 16, 24], [16, 12, 24]], amp_factor=1.0)
+    opt = default_options(smoother=_abi.IETI_SMOOTHER_TENSOR, coarse_dofs=0)
+    pl = Plan(wl.patches, opt)
+    for k in (0, 4, 5):
+        geo = wl.patches[k]
+        A0, B0, A1, B1 = TS.separable_matrices(geo)
+        bits = pl.array(_abi.IETI_ARR_MASKS, k, 0, dtype=np.int32)
+        K = assembly.assemble_patch(geo).K.toarray()
+        for mode in (0, 1):
+            sides = int(bits[0]) if mode == 0 else 0xF
+            kept = TS.kept_indices(geo, sides)
+            par = pl.array(_abi.IETI_ARR_TENSOR_PARAMS, k, mode)
+            assert par[2] == pytest.approx(TS.shift(geo, 0.3), rel=1e-14)
+            for d, (A, B) in enumerate(((A0, B0), (A1, B1))):
+                Pd = int(par[d])
+                U = pl.array(_abi.IETI_ARR_TENSOR_U, k, 256 * mode + d).reshape(Pd, Pd)
+                lam = pl.array(_abi.IETI_ARR_TENSOR_LAMBDA, k, 256 * mode + d)
+                kk = kept[d]
+                nk = len(kk)
+                Uk = U[kk][:, :nk]
+                Ak, Bk = A[np.ix_(kk, kk)], B[np.ix_(kk, kk)]
+                assert np.abs(Uk.T @ Bk @ Uk - np.eye(nk)).max() <= 1e-9
+                assert np.abs(Uk.T @ Ak @ Uk - np.diag(lam[:nk])).max() <= 1e-9 * lam[:nk].max()
+                rest = np.setdiff1d(np.arange(Pd), kk)
+                assert np.all(U[rest] == 0.0) and np.all(U[:, nk:] == 0.0) and np.all(lam[nk:] == 1e300)
+            m = _mask_from_bits(geo.shape, int(bits[0]), int(bits[1]), mode)
+            lmax = TS.damping(geo, sides, m, K, 0.3)
+            assert 0.99 <= par[3] * lmax <= 1.1, (k, mode, par[3] * lmax)
+
+
+def test_tensor_smoother_options(lib):
+    wl = W.deformed_square((2, 2), 2, 8, seed=0)
+    with pytest.raises(_abi.IetiError):
+        Plan(wl.patches, default_options(smoother=2))
+    with pytest.raises(_abi.IetiError):
+        Plan(wl.patches, default_options(smoother=_abi.IETI_SMOOTHER_TENSOR, smoother_sigma=0.0))
+    cube = W.unit_cube((2, 2, 2), 2, 4)
+    with pytest.raises(_abi.IetiError) as e:
+        Plan(cube.patches, default_options(smoother=_abi.IETI_SMOOTHER_TENSOR))
+    assert e.value.code == _abi.IETI_ENOTSUP
+    pl = Plan(wl.patches, default_options())
+    with pytest.raises(_abi.IetiError):         # no tensor data for the Chebyshev smoother
+        pl.array(_abi.IETI_ARR_TENSOR_PARAMS, 0, 0)

@@ -160,3 +160,24 @@ def test_saddle_point_bpcg_matches_oracle(require_gpu, name, make, prec):
           f"res={st['global_residual']:.2e} omega={st['saddle_omega']:.3f} breakdown={st['breakdown']}", flush=True)
     assert err <= 1e-8
     assert st["inner_iterations_mean"] == 0 and st["breakdown"] == 0 and st["saddle_omega"] > 1.0
+
+
+TENSOR_VARIANTS = [("mg", 0), ("exact_mg", 2), ("mg_saddle", 3)]
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+@pytest.mark.parametrize("variant,solver", TENSOR_VARIANTS, ids=[v[0] for v in TENSOR_VARIANTS])
+@pytest.mark.parametrize("name,make", CASES_2D, ids=[c[0] for c in CASES_2D])
+def test_tensor_smoother_matches_oracle(require_gpu, name, make, variant, solver, prec):
+    """The finest-level tensor smoother (p-robust multigrid, Sec. 4) in every multigrid variant: the
+    solution still matches the oracle's direct solution (the full h-hierarchy, so V-cycles are real)."""
+    from paper_1705_04531_amd import _abi
+    wl = make()
+    u_ref, lay, _ = oracle_solution(wl)
+    u, st = run_gpu(wl, local_solver=solver, mg_precision=prec, tol=1e-10, coarse_dofs=0,
+                    smoother=_abi.IETI_SMOOTHER_TENSOR)
+    err = rel_err(wl, u, u_ref, lay)
+    print(f"{name} tensor smoother {variant} prec={prec}: err={err:.3e} outer={st['outer_iterations']} "
+          f"inner={st['inner_iterations_mean']:.2f}", flush=True)
+    assert err <= 1e-8
+    assert st["cheb_degree"] == 0
