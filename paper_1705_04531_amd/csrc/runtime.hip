@@ -421,13 +421,14 @@ struct Solver : SolverBase {
     // one work-group per patch runs the rest of the cycle (k_vcoarse).
     // finest level, patches with tensor-smoother data: x = tau P r (set) or x += tau P r
     void fd_smooth(int mode, const int* act, const T* r, T* x, bool set) {
-        FdArgs a{lev[0].L, fd_info[mode], fd_U, fd_lam, fd_z, act, mode};
-        hipLaunchKernelGGL(k_fd_fwd<T>, dim3(fd_p0max / 16, N), dim3(FD_THREADS), fd_lds, stream, a, r);
+        FdArgs a{lev[0].L, fd_info[mode], fd_U, fd_lam, fd_z, act, mode, N, fd_p0max / 16};
+        const dim3 grid(8 * ((N + 7) / 8) * (fd_p0max / 16));
+        hipLaunchKernelGGL(k_fd_fwd<T>, grid, dim3(FD_THREADS), fd_lds, stream, a, r);
         check_launch();
         if (set)
-            hipLaunchKernelGGL((k_fd_bwd<T, true>), dim3(fd_p0max / 16, N), dim3(FD_THREADS), fd_lds, stream, a, x);
+            hipLaunchKernelGGL((k_fd_bwd<T, true>), grid, dim3(FD_THREADS), fd_lds, stream, a, x);
         else
-            hipLaunchKernelGGL((k_fd_bwd<T, false>), dim3(fd_p0max / 16, N), dim3(FD_THREADS), fd_lds, stream, a, x);
+            hipLaunchKernelGGL((k_fd_bwd<T, false>), grid, dim3(FD_THREADS), fd_lds, stream, a, x);
         check_launch();
     }
     void vcycle(int mode, const int* act, const T* b0, T* x0, const double* dotq = nullptr, double* dpart = nullptr) {
@@ -1354,6 +1355,8 @@ void Solver<T>::setup() {
             }
             zlen += zk;
         }
+        if (fd_p0max > 128 || fd_p1max > 128)
+            throw Error(IETI_ENOTSUP, "tensor smoother: more than 128 coefficients per direction");
         if (fd_p0max > 0) {
             fd_on = true;
             fd_U = arena.upload(hu, st);
