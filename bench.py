@@ -266,6 +266,25 @@ def main():
                 "omega": round(bst["saddle_omega"], 4),
                 "rel_l2_diff_vs_plain": float(torch.linalg.norm(ub - up) / torch.linalg.norm(up))}
             bs_.close()
+        # finest-level tensor-product smoother (p-robust multigrid) in place of Chebyshev: MG-MG and MG-MG-S
+        for label, extra in (("tensor_smoother_mg64", {}),
+                             ("tensor_smoother_saddle_mg64", {"local_solver": _abi.IETI_LOCAL_MG_SADDLE}),
+                             ("tensor_smoother_saddle_mg32", {"local_solver": _abi.IETI_LOCAL_MG_SADDLE,
+                                                              "mg_precision": 32})):
+            ts_ = Solver(wl.patches, options_for(wl, smoother=_abi.IETI_SMOOTHER_TENSOR, **extra))
+            ut = torch.empty_like(u)
+            ts_.solve(f, ut)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                _, tst = ts_.solve(f, ut)
+            torch.cuda.synchronize()
+            tms = (time.perf_counter() - t0) / args.steps * 1e3
+            plain[label] = {
+                "ms_per_step": round(tms, 3), "outer_iterations": tst["outer_iterations"],
+                "inner_iterations_mean": round(tst["inner_iterations_mean"], 2),
+                "rel_l2_diff_vs_plain": float(torch.linalg.norm(ut - up) / torch.linalg.norm(up))}
+            ts_.close()
 
     dom = prof[_abi.IETI_KPROF_SMOOTH_FINE]
     achieved = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9 if dom["ms"] > 0 else 0.0
