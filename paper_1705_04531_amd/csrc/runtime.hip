@@ -32,6 +32,7 @@
 #include <vector>
 
 #include "kernels.h"
+#include "tensor_smoother.h"
 #include "plan.h"
 
 namespace ieti {

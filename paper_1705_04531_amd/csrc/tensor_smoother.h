@@ -1,0 +1,193 @@
+// Tensor-product (fast-diagonalisation) smoother kernels of the finest multigrid level.  Uses the
+// FP64 MFMA block helpers and the mask helpers of kernels.h.
+#pragma once
+
+#include "kernels.h"
+
+namespace ieti {
+
+// ---------------------------------------------------------------------------
+// Tensor-product smoother of the finest level (2D): y = m U (Lambda_0 (+) Lambda_1 + c)^{-1} U^T m r per
+// patch, U = U_1 (x) U_0 the generalised eigenvectors of the separable stiffness.  With the residual of a
+// patch as the M1 x M0 matrix R[i1][i0] (i0 fastest, as stored):
+//   forward:   Z = (U_1^T R U_0) ./ (lambda_1[b] + lambda_0[a] + c)     (P1 x P0, into scratch)
+//   backward:  x[i1][i0] (+)= tau (U_1 Z U_0^T)[i1][i0] on unmasked coefficients
+// Both kernels take one work-group per (16-column block, patch), the work-groups of a patch on one XCD
+// (fd_block) so that they share its L2: the forward one forms the column block W = R U_0[:, blk] and then
+// U_1^T W, the backward one T = Z U_0[blk, :]^T and then U_1 T.  The operands are staged in LDS (U_1 in
+// the first matrix's space once the first product is done); each wave runs the block products of one
+// 16-row block on v_mfma_f64_16x16x4f64 in FP64 with two accumulation chains (T = float converts on load
+// and store).  Padded sizes up to 128.  Patches without smoother data (P0 = 0) and inactive patches
+// return.
+
+constexpr int FD_THREADS = 512;
+
+struct FdInfo {
+    int64_t u0, u1;        // offsets of U_0 (P0 x P0) and U_1 (P1 x P1), row-major, in the U array
+    int64_t l0, l1;        // offsets of lambda_0 and lambda_1 in the eigenvalue array
+    int64_t zoff;          // scratch Z of the patch (P1 x P0)
+    int32_t P0, P1;        // padded sizes (multiples of 16); 0: no tensor smoother on this patch
+    double shift, tau;
+};
+
+struct FdArgs {
+    const PatchLev* L;     // level-0 patch descriptors, index = patch
+    const FdInfo* info;    // of the mode, index = patch
+    const double* U;
+    const double* lam;
+    double* z;
+    const int* active;
+    int mode;
+    int N;                 // patches
+    int ncb;               // column blocks per patch in the grid (largest P0 / 16)
+};
+
+// LDS doubles of either kernel for the largest padded sizes
+__host__ __device__ inline size_t fd_lds_words(int p0max, int p1max) {
+    const int ld = (p0max > p1max ? p0max : p1max) + 1;
+    return (size_t)p1max * ld + (size_t)p1max * 17 + (size_t)p0max * 17;
+}
+
+// dst[i * ld + j] = get(i, j) for i < rows, j < cols (cols a multiple of 16): thread -> (row tid / 16 of a
+// step of 32 rows, column lane tid % 16); up to 8 column blocks' loads issued before their stores
+template <typename G>
+__device__ __forceinline__ void fd_stage(double* dst, int ld, int rows, int cols, G get) {
+    const int tr = threadIdx.x >> 4, tc = threadIdx.x & 15, ncb = cols >> 4;
+    for (int r0 = 0; r0 < rows; r0 += FD_THREADS / 16) {
+        const int i = r0 + tr;
+        if (i >= rows) break;
+        for (int c0 = 0; c0 < ncb; c0 += 8) {
+            double v[8];
+#pragma unroll
+            for (int c = 0; c < 8; ++c) v[c] = c0 + c < ncb ? get(i, (c0 + c) * 16 + tc) : 0.0;
+#pragma unroll
+            for (int c = 0; c < 8; ++c)
+                if (c0 + c < ncb) dst[i * ld + (c0 + c) * 16 + tc] = v[c];
+        }
+    }
+}
+
+// XCD-aware work-group -> (patch, 16-column block): consecutive work-groups go to consecutive XCDs, so
+// the work-groups of patch k are all placed on XCD k mod 8 and share its L2 for the patch's operands.
+// Grid: 8 * ceil(N / 8) * ncb one-dimensional; false for the unused tail.
+__device__ __forceinline__ bool fd_block(int N, int ncb, int& k, int& cb) {
+    const int L = blockIdx.x, x = L & 7, s = L >> 3;
+    k = (s / ncb) * 8 + x;
+    cb = s % ncb;
+    return k < N;
+}
+
+template <typename T>
+__global__ __launch_bounds__(FD_THREADS) void k_fd_fwd(FdArgs a, const T* __restrict__ r) {
+    int k, cb;
+    if (!fd_block(a.N, a.ncb, k, cb)) return;
+    const FdInfo f = a.info[k];
+    if (f.P0 == 0 || (a.active && !a.active[k])) return;
+    if (cb * 16 >= f.P0) return;
+    const PatchLev& P = a.L[k];
+    const int M0 = P.M[0], M1 = P.M[1], P0 = f.P0, P1 = f.P1, ld = (P0 > P1 ? P0 : P1) + 1;
+    extern __shared__ double fd_sm[];
+    double* Rg = fd_sm;                       // R (P1 x P0), then U_1 (P1 x P1); leading dimension ld
+    double* Wb = fd_sm + (size_t)P1 * ld;     // W (P1 x 16), ld 17
+    double* Ub = Wb + (size_t)P1 * 17;        // U_0[:, block cb] (P0 x 16), ld 17
+    const double* U0 = a.U + f.u0;
+    const double* U1 = a.U + f.u1;
+    const int wv = threadIdx.x / WAVE, l = threadIdx.x & (WAVE - 1);
+    const int mode = a.mode;
+    fd_stage(Rg, ld, P1, P0, [&](int i1, int i0) -> double {
+        return (i0 < M0 && i1 < M1 && !masked(P, mode, i0, i1, 0)) ? (double)r[P.voff + i0 + (int64_t)M0 * i1] : 0.0;
+    });
+    fd_stage(Ub, 17, P0, 16, [&](int i, int j) -> double { return U0[(int64_t)i * P0 + cb * 16 + j]; });
+    __syncthreads();
+    for (int w = wv; w < P1 / 16; w += FD_THREADS / WAVE) {   // W[block w] = R[block w, :] U_0[:, block cb]
+        mf_d4 c = {0.0, 0.0, 0.0, 0.0}, c1 = c;
+        int kb = 0;
+        for (; kb + 1 < P0 / 16; kb += 2) {   // two independent accumulation chains
+            c = mf_block<false>(Rg + (size_t)w * 16 * ld + kb * 16, ld, Ub + kb * 16 * 17, 17, c, 1.0);
+            c1 = mf_block<false>(Rg + (size_t)w * 16 * ld + kb * 16 + 16, ld, Ub + (kb + 1) * 16 * 17, 17, c1, 1.0);
+        }
+        if (kb < P0 / 16) c = mf_block<false>(Rg + (size_t)w * 16 * ld + kb * 16, ld, Ub + kb * 16 * 17, 17, c, 1.0);
+        c += c1;
+        mf_store(Wb + w * 16 * 17, 17, c);
+    }
+    __syncthreads();
+    fd_stage(Rg, ld, P1, P1, [&](int i, int j) -> double { return U1[(int64_t)i * P1 + j]; });
+    __syncthreads();
+    const double* l0 = a.lam + f.l0;
+    const double* l1 = a.lam + f.l1;
+    const int ac = cb * 16 + (l & 15);
+    for (int w = wv; w < P1 / 16; w += FD_THREADS / WAVE) {   // Z[block w, block cb] = U_1[:, block w]^T W, scaled
+        mf_d4 c = {0.0, 0.0, 0.0, 0.0}, c1 = c;
+        int kb = 0;
+        for (; kb + 1 < P1 / 16; kb += 2) {
+            c = mf_block<true>(Rg + (size_t)kb * 16 * ld + w * 16, ld, Wb + kb * 16 * 17, 17, c, 1.0);
+            c1 = mf_block<true>(Rg + (size_t)(kb + 1) * 16 * ld + w * 16, ld, Wb + (kb + 1) * 16 * 17, 17, c1, 1.0);
+        }
+        if (kb < P1 / 16) c = mf_block<true>(Rg + (size_t)kb * 16 * ld + w * 16, ld, Wb + kb * 16 * 17, 17, c, 1.0);
+        c += c1;
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+            const int b = w * 16 + (l >> 4) + 4 * rr;
+            a.z[f.zoff + (int64_t)b * P0 + ac] = c[rr] / (l1[b] + l0[ac] + f.shift);
+        }
+    }
+}
+
+// SET: x = tau y (masked coefficients 0); otherwise x += tau y
+template <typename T, bool SET>
+__global__ __launch_bounds__(FD_THREADS) void k_fd_bwd(FdArgs a, T* __restrict__ x) {
+    int k, jc;
+    if (!fd_block(a.N, a.ncb, k, jc)) return;
+    const FdInfo f = a.info[k];
+    if (f.P0 == 0 || (a.active && !a.active[k])) return;
+    const PatchLev& P = a.L[k];
+    const int M0 = P.M[0], M1 = P.M[1], P0 = f.P0, P1 = f.P1, ld = (P0 > P1 ? P0 : P1) + 1;
+    if (jc * 16 >= M0) return;
+    extern __shared__ double fd_sm[];
+    double* Zg = fd_sm;                       // Z (P1 x P0), then U_1 (P1 x P1); leading dimension ld
+    double* Tb = fd_sm + (size_t)P1 * ld;     // T (P1 x 16), ld 17
+    double* Ub = Tb + (size_t)P1 * 17;        // U_0[block jc, :]^T (P0 x 16), ld 17
+    const double* U0 = a.U + f.u0;
+    const double* U1 = a.U + f.u1;
+    const double* Z = a.z + f.zoff;
+    const int wv = threadIdx.x / WAVE, l = threadIdx.x & (WAVE - 1);
+    fd_stage(Zg, ld, P1, P0, [&](int i, int j) -> double { return Z[(int64_t)i * P0 + j]; });
+    fd_stage(Ub, 17, P0, 16, [&](int i, int j) -> double { return U0[(int64_t)(jc * 16 + j) * P0 + i]; });
+    __syncthreads();
+    for (int w = wv; w < P1 / 16; w += FD_THREADS / WAVE) {   // T[block w] = Z[block w, :] U_0[block jc, :]^T
+        mf_d4 c = {0.0, 0.0, 0.0, 0.0}, c1 = c;
+        int kb = 0;
+        for (; kb + 1 < P0 / 16; kb += 2) {
+            c = mf_block<false>(Zg + (size_t)w * 16 * ld + kb * 16, ld, Ub + kb * 16 * 17, 17, c, 1.0);
+            c1 = mf_block<false>(Zg + (size_t)w * 16 * ld + kb * 16 + 16, ld, Ub + (kb + 1) * 16 * 17, 17, c1, 1.0);
+        }
+        if (kb < P0 / 16) c = mf_block<false>(Zg + (size_t)w * 16 * ld + kb * 16, ld, Ub + kb * 16 * 17, 17, c, 1.0);
+        c += c1;
+        mf_store(Tb + w * 16 * 17, 17, c);
+    }
+    __syncthreads();
+    fd_stage(Zg, ld, P1, P1, [&](int i, int j) -> double { return U1[(int64_t)i * P1 + j]; });
+    __syncthreads();
+    for (int w = wv; w < P1 / 16; w += FD_THREADS / WAVE) {   // Y[block w, block jc] = U_1[block w, :] T
+        mf_d4 c = {0.0, 0.0, 0.0, 0.0}, c1 = c;
+        int kb = 0;
+        for (; kb + 1 < P1 / 16; kb += 2) {
+            c = mf_block<false>(Zg + (size_t)w * 16 * ld + kb * 16, ld, Tb + kb * 16 * 17, 17, c, 1.0);
+            c1 = mf_block<false>(Zg + (size_t)w * 16 * ld + kb * 16 + 16, ld, Tb + (kb + 1) * 16 * 17, 17, c1, 1.0);
+        }
+        if (kb < P1 / 16) c = mf_block<false>(Zg + (size_t)w * 16 * ld + kb * 16, ld, Tb + kb * 16 * 17, 17, c, 1.0);
+        c += c1;
+        const int i0 = jc * 16 + (l & 15);
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+            const int i1 = w * 16 + (l >> 4) + 4 * rr;
+            if (i0 >= M0 || i1 >= M1) continue;
+            const int64_t vi = P.voff + i0 + (int64_t)M0 * i1;
+            const bool m = masked(P, a.mode, i0, i1, 0);
+            if (SET) x[vi] = m ? T(0) : T(f.tau * c[rr]);
+            else if (!m) x[vi] = T((double)x[vi] + f.tau * c[rr]);
+        }
+    }
+}
+
+}  // namespace ieti
