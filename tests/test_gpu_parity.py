@@ -181,3 +181,25 @@ def test_tensor_smoother_matches_oracle(require_gpu, name, make, variant, solver
           f"inner={st['inner_iterations_mean']:.2f}", flush=True)
     assert err <= 1e-8
     assert st["cheb_degree"] == 0
+
+
+def test_tensor_smoother_p_robust(require_gpu):
+    """p-robustness (Sec. 4): on the same 2x2 deformed square with 32^2 elements per patch and the
+    full h-hierarchy, degrees 2..6, both smoothers reach the oracle's solution; the tensor smoother's
+    inner flexible-CG iteration count stays bounded as p grows (the Chebyshev smoother's is reported
+    beside it)."""
+    from paper_1705_04531_amd import _abi
+    rows = []
+    for p in (2, 3, 4, 5, 6):
+        wl = with_sine_rhs(W.deformed_square((2, 2), p, 32, seed=0, name=f"deformed2x2_p{p}"), 3)
+        u_ref, lay, _ = oracle_solution(wl)
+        its = {}
+        for name, sm in (("chebyshev", _abi.IETI_SMOOTHER_CHEBYSHEV), ("tensor", _abi.IETI_SMOOTHER_TENSOR)):
+            u, st = run_gpu(wl, tol=1e-10, coarse_dofs=0, smoother=sm)
+            err = rel_err(wl, u, u_ref, lay)
+            assert err <= 1e-8, (p, name, err)
+            its[name] = st["inner_iterations_mean"]
+        rows.append((p, its["chebyshev"], its["tensor"]))
+        print(f"p={p}: inner iterations Chebyshev {its['chebyshev']:.2f}, tensor {its['tensor']:.2f}", flush=True)
+    tens = [r[2] for r in rows]
+    assert max(tens) <= 16.0 and max(tens) <= 1.6 * min(tens), rows
