@@ -65,12 +65,14 @@ extern "C" {
 
 /* Finest-level multigrid smoother (options.smoother).  TENSOR is the p-robust smoother of Sec. 4 (a
  * subspace-corrected mass smoother variant with a rank-one approximation of the geometry): per patch,
- * x += tau m (K_sep + c M_sep)^{-1} m r, where K_sep = A_0 (x) B_1 + B_0 (x) A_1 is the stiffness with each
- * metric diagonal |det J| (J^{-1} J^{-T})_dd replaced by its best rank-one (separable) approximation on the
- * quadrature grid, M_sep = B_0 (x) B_1 the matching weighted mass, c = sigma * mean_d(n_el,d^2), m the mask of
- * the mode, tau = 1 / lambda_max(m (K_sep + c M_sep)^{-1} m K).  The inverse is applied by fast
- * diagonalisation (generalised eigenvectors of (A_d, B_d) per direction), one pre- and one post-smoothing
- * step per V-cycle. */
+ * x += tau m (K_sep + c M_sep)^{-1} m r, where K_sep is the stiffness with each metric diagonal
+ * |det J| (J^{-1} J^{-T})_dd replaced by its best rank-one (separable) approximation on the quadrature grid
+ * (2D: A_0 (x) B_1 + B_0 (x) A_1; 3D: A_0 (x) B_1 (x) B_2 + B_0 (x) A_1 (x) B_2 + B_0 (x) B_1 (x) A_2, the
+ * mass weight of a direction the geometric mean of its fitted factors), M_sep = B_0 (x) B_1 (x) B_2 the
+ * matching weighted mass, c = sigma * mean_d(n_el,d^2), m the mask of the mode,
+ * tau = 1 / lambda_max(m (K_sep + c M_sep)^{-1} m K).  The inverse is applied by fast diagonalisation
+ * (generalised eigenvectors of (A_d, B_d) per direction), one pre- and one post-smoothing step per
+ * V-cycle; at most 128 coefficients per direction. */
 #define IETI_SMOOTHER_CHEBYSHEV 0
 #define IETI_SMOOTHER_TENSOR    1
 
@@ -112,7 +114,7 @@ typedef struct ieti_options {
                                   coarsened further (dense exact solve there); 0 = no such limit. Coarsening
                                   also stops where a direction's element count is odd or below 6 (default 600) */
     int32_t smoother;          /* finest-level smoother: IETI_SMOOTHER_CHEBYSHEV (default) or
-                                  IETI_SMOOTHER_TENSOR (2D only; coarser levels keep Chebyshev) */
+                                  IETI_SMOOTHER_TENSOR (coarser levels keep Chebyshev) */
     double  smoother_sigma;    /* IETI_SMOOTHER_TENSOR: mass shift sigma of the tensor smoother, in units of the
                                   mean squared inverse element size of the patch (default 0.3) */
 } ieti_options;
@@ -185,7 +187,7 @@ int ieti_plan_sizes(const ieti_plan* plan, int64_t* ndof_torn, int64_t* ndof_glo
                                     rounded up to 16; row i = coefficient i (zero where the mode removes it), column a =
                                     eigenvector a (U_d^T B_d U_d = I on the kept coefficients; zero padding) */
 #define IETI_ARR_TENSOR_LAMBDA 12 /* double: the P_d generalised eigenvalues of the same block (1e300 in the padding) */
-#define IETI_ARR_TENSOR_PARAMS 13 /* double: [P_0, P_1, shift c, tau] of `patch`, level = mode */
+#define IETI_ARR_TENSOR_PARAMS 13 /* double: [P_0, P_1, shift c, tau, P_2 (0 in 2D)] of `patch`, level = mode */
 int ieti_plan_array(const ieti_plan* plan, int32_t which, int32_t patch, int32_t level, void* out,
                     int64_t* count);
 

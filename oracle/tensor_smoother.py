@@ -1,4 +1,4 @@
-"""Tensor-product smoother of the finest multigrid level, 2D (FP64, dense).
+"""Tensor-product smoother of the finest multigrid level (FP64, dense).
 
 TEST INFRASTRUCTURE ONLY, like the rest of this package.
 
@@ -23,7 +23,12 @@ The variant defined here, written from that description:
 * for a local problem whose mode removes some coefficients: sides removed
   from the tensor space direction by direction, removed corners (primal
   vertices) cut afterwards by the mask m:  P r = m S_kept^{-1} m r;
-* one smoothing step x <- x + tau P (b - K x), tau = 1 / lambda_max(P K).
+* one smoothing step x <- x + tau P (b - K x), tau = 1 / lambda_max(P K);
+* in 3D the same with three diagonals, each fitted by a rank-one three-way
+  product; a direction's mass weight is the geometric mean of the two unit-mean
+  factors the other diagonals give it (one mass matrix per direction, as the
+  Kronecker sum K_sep = A_0 (x) B_1 (x) B_2 + B_0 (x) A_1 (x) B_2 + B_0 (x) B_1 (x) A_2
+  requires), c = sigma * mean_d n_el,d^2.
 
 The functions below build these objects with plain dense NumPy/SciPy (no
 fast diagonalisation): the library's eigenvector factors are checked against
@@ -53,65 +58,96 @@ def gauss_grid(geo):
 
 
 def metric_diagonals(geo) -> Tuple[List[np.ndarray], list, list]:
-    """g_dd = |det J| (J^{-1} J^{-T})_dd on the Gauss grid, as Q0 x Q1 arrays (index [q0, q1])."""
-    if geo.dim != 2:
-        raise ValueError("2D patches only")
+    """g_dd = |det J| (J^{-1} J^{-T})_dd on the Gauss grid, as arrays indexed [q0, q1(, q2)]."""
     xs, ws = gauss_grid(geo)
     _, J = assembly.geometry_eval(geo, xs)
     det = np.linalg.det(J)
     Ji = np.linalg.inv(J)
     G = np.einsum("qac,qbc->qab", Ji, Ji) * det[:, None, None]
-    Q0, Q1 = len(xs[0]), len(xs[1])
+    Q = tuple(len(x) for x in xs)
     # the grid's flat index runs direction 0 fastest
-    g = [G[:, d, d].reshape(Q1, Q0).T.copy() for d in range(2)]
+    g = [G[:, d, d].reshape(Q, order="F").copy() for d in range(geo.dim)]
     return g, xs, ws
 
 
-def rank_one(g: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:
-    """Leading singular pair of a positive array, g ~ outer(a, b), both factors positive."""
-    u, s, vt = np.linalg.svd(g)
-    a = u[:, 0] * s[0]
-    b = vt[0].copy()
-    if b.sum() < 0:
-        a, b = -a, -b
-    return a, b
+def rank_one(g: np.ndarray):
+    """Best rank-one approximation of a positive array, all factors positive.
+
+    2D: the leading singular pair, returned as (a, b) with g ~ outer(a, b).  3D: alternating least-squares
+    updates of one factor with the other two fixed (the higher-order power method), returned as a list of
+    three factors with g ~ x0 (x) x1 (x) x2."""
+    if g.ndim == 2:
+        u, s, vt = np.linalg.svd(g)
+        a = u[:, 0] * s[0]
+        b = vt[0].copy()
+        if b.sum() < 0:
+            a, b = -a, -b
+        return a, b
+    x = [np.ones(n) for n in g.shape]
+    for _ in range(500):
+        old = [v.copy() for v in x]
+        x[0] = np.einsum("ijk,j,k->i", g, x[1], x[2]) / ((x[1] @ x[1]) * (x[2] @ x[2]))
+        x[1] = np.einsum("ijk,i,k->j", g, x[0], x[2]) / ((x[0] @ x[0]) * (x[2] @ x[2]))
+        x[2] = np.einsum("ijk,i,j->k", g, x[0], x[1]) / ((x[0] @ x[0]) * (x[1] @ x[1]))
+        if max(np.abs(v - o).max() / np.abs(v).max() for v, o in zip(x, old)) <= 1e-15:
+            break
+    return x
+
+
+def separable_pairs(geo) -> List[Tuple[np.ndarray, np.ndarray]]:
+    """[(A_d, B_d)] per direction: A_d weighted by the stiffness factor of g_dd, B_d by the (geometric mean
+    of the) unit-mean mass factors the other diagonals contribute to direction d."""
+    g, xs, ws = metric_diagonals(geo)
+    dim = geo.dim
+    f = []
+    for d in range(dim):
+        x = list(rank_one(g[d]))
+        for e in range(dim):
+            if e != d:
+                m = float(ws[e] @ x[e])
+                x[e] = x[e] / m
+                x[d] = x[d] * m
+        f.append(x)
+    pairs = []
+    for e in range(dim):
+        wm = np.prod([f[d][e] for d in range(dim) if d != e], axis=0) ** (1.0 / (dim - 1))
+        N, dN = bspline.basis(np.asarray(geo.knots[e]), geo.degree[e], xs[e], deriv=True)
+        N = N.toarray() if hasattr(N, "toarray") else np.asarray(N)
+        dN = dN.toarray() if hasattr(dN, "toarray") else np.asarray(dN)
+        pairs.append((dN.T @ np.diag(ws[e] * f[e][e]) @ dN, N.T @ np.diag(ws[e] * wm) @ N))
+    return pairs
 
 
 def separable_matrices(geo):
-    """(A_0, B_0, A_1, B_1) of the separable metric, with the unit-mean scaling of b00 and a11."""
-    g, xs, ws = metric_diagonals(geo)
-    a00, b00 = rank_one(g[0])
-    a11, b11 = rank_one(g[1])
-    m1 = float(ws[1] @ b00)
-    b00, a00 = b00 / m1, a00 * m1
-    m0 = float(ws[0] @ a11)
-    a11, b11 = a11 / m0, b11 * m0
-    mats = []
-    for d, (ws_d, wm_d) in enumerate(((a00, a11), (b11, b00))):
-        N, dN = bspline.basis(np.asarray(geo.knots[d]), geo.degree[d], xs[d], deriv=True)
-        N = N.toarray() if hasattr(N, "toarray") else np.asarray(N)
-        dN = dN.toarray() if hasattr(dN, "toarray") else np.asarray(dN)
-        A = dN.T @ np.diag(ws[d] * ws_d) @ dN
-        B = N.T @ np.diag(ws[d] * wm_d) @ N
-        mats += [A, B]
-    return tuple(mats)
+    """2D: (A_0, B_0, A_1, B_1)."""
+    (A0, B0), (A1, B1) = separable_pairs(geo)
+    return A0, B0, A1, B1
+
+
+def _kron_dirs(mats):
+    """Kronecker product with direction 0 fastest."""
+    out = mats[0]
+    for m in mats[1:]:
+        out = np.kron(m, out)
+    return out
 
 
 def k_sep(geo) -> np.ndarray:
-    """The separable stiffness A_0 (x) B_1 + B_0 (x) A_1 (dense, direction 0 fastest)."""
-    A0, B0, A1, B1 = separable_matrices(geo)
-    return np.kron(B1, A0) + np.kron(A1, B0)
+    """The separable stiffness sum_d B (x) .. A_d .. (x) B (dense, direction 0 fastest)."""
+    pairs = separable_pairs(geo)
+    dim = geo.dim
+    return sum(_kron_dirs([pairs[e][0] if e == d else pairs[e][1] for e in range(dim)]) for d in range(dim))
 
 
 def shift(geo, sigma: float) -> float:
-    nel = [len(np.unique(np.asarray(geo.knots[d]))) - 1 for d in range(2)]
-    return sigma * 0.5 * (nel[0] ** 2 + nel[1] ** 2)
+    nel = [len(np.unique(np.asarray(geo.knots[d]))) - 1 for d in range(geo.dim)]
+    return sigma * float(np.mean(np.square(nel)))
 
 
 def kept_indices(geo, sides: int) -> List[np.ndarray]:
     """Per direction, the coefficients left after removing the masked sides (bit 2d + e: side xi_d = e)."""
     out = []
-    for d in range(2):
+    for d in range(geo.dim):
         M = bspline.n_basis(np.asarray(geo.knots[d]), geo.degree[d])
         keep = np.ones(M, bool)
         if sides >> (2 * d) & 1:
@@ -124,15 +160,21 @@ def kept_indices(geo, sides: int) -> List[np.ndarray]:
 
 def smoother_matrix(geo, sides: int, sigma: float) -> Tuple[np.ndarray, np.ndarray]:
     """S = K_sep + c M_sep restricted to the tensor space of kept coefficients; returns (S_kept, flat kept index)."""
-    A0, B0, A1, B1 = separable_matrices(geo)
-    k0, k1 = kept_indices(geo, sides)
+    pairs = separable_pairs(geo)
+    dim = geo.dim
+    kk = kept_indices(geo, sides)
     c = shift(geo, sigma)
-    A0, B0 = A0[np.ix_(k0, k0)], B0[np.ix_(k0, k0)]
-    A1, B1 = A1[np.ix_(k1, k1)], B1[np.ix_(k1, k1)]
-    S = np.kron(B1, A0) + np.kron(A1, B0) + c * np.kron(B1, B0)
-    M0 = bspline.n_basis(np.asarray(geo.knots[0]), geo.degree[0])
-    flat = (k0[None, :] + M0 * k1[:, None]).ravel()
-    return S, flat
+    A = [pairs[d][0][np.ix_(kk[d], kk[d])] for d in range(dim)]
+    B = [pairs[d][1][np.ix_(kk[d], kk[d])] for d in range(dim)]
+    S = sum(_kron_dirs([A[e] if e == d else B[e] for e in range(dim)]) for d in range(dim)) + c * _kron_dirs(B)
+    M = [bspline.n_basis(np.asarray(geo.knots[d]), geo.degree[d]) for d in range(dim)]
+    grids = np.meshgrid(*kk, indexing="ij")
+    flat = grids[0].copy()
+    stride = 1
+    for d in range(1, dim):
+        stride *= M[d - 1]
+        flat = flat + stride * grids[d]
+    return S, flat.ravel(order="F")
 
 
 def apply(geo, sides: int, mask: np.ndarray, r: np.ndarray, sigma: float) -> np.ndarray:
@@ -146,7 +188,7 @@ def apply(geo, sides: int, mask: np.ndarray, r: np.ndarray, sigma: float) -> np.
 
 
 def apply_eig(geo, sides: int, mask: np.ndarray, r: np.ndarray, sigma: float) -> np.ndarray:
-    """The same operator by the eigenvectors of the pairs (A_d, B_d) (fast diagonalisation)."""
+    """The same operator by the eigenvectors of the pairs (A_d, B_d) (fast diagonalisation), 2D."""
     A0, B0, A1, B1 = separable_matrices(geo)
     k0, k1 = kept_indices(geo, sides)
     c = shift(geo, sigma)

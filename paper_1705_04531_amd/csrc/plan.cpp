@@ -909,6 +909,193 @@ static void tensor_setup(Patch& P, const ieti_options& opt, bool mode_n) {
     }
 }
 
+// Best rank-one approximation g ~ x0 (x) x1 (x) x2 of a positive Q0 x Q1 x Q2 array g[q0 + Q0 (q1 + Q1 q2)]
+// by alternating power steps (higher-order power method).
+static void rank_one3(const std::vector<double>& g, const int* Q, std::vector<double> (&x)[3]) {
+    for (int d = 0; d < 3; ++d) x[d].assign(Q[d], 1.0);
+    for (int it = 0; it < 200; ++it) {
+        double change = 0.0;
+        for (int d = 0; d < 3; ++d) {
+            const int e = (d + 1) % 3, f = (d + 2) % 3;
+            double ne = 0.0, nf = 0.0;
+            for (double v : x[e]) ne += v * v;
+            for (double v : x[f]) nf += v * v;
+            std::vector<double> nx(Q[d], 0.0);
+            for (int q2 = 0; q2 < Q[2]; ++q2)
+                for (int q1 = 0; q1 < Q[1]; ++q1)
+                    for (int q0 = 0; q0 < Q[0]; ++q0) {
+                        const int qq[3] = {q0, q1, q2};
+                        nx[qq[d]] += g[q0 + (size_t)Q[0] * (q1 + (size_t)Q[1] * q2)] * x[e][qq[e]] * x[f][qq[f]];
+                    }
+            double mx = 0.0;
+            for (int i = 0; i < Q[d]; ++i) {
+                nx[i] /= ne * nf;
+                change = std::max(change, std::fabs(nx[i] - x[d][i]));
+                mx = std::max(mx, std::fabs(nx[i]));
+            }
+            x[d].swap(nx);
+            change /= mx;
+        }
+        if (change <= 1e-15) break;
+    }
+}
+
+// y = m (U_2 (x) U_1 (x) U_0) (Lambda_0 (+) Lambda_1 (+) Lambda_2 + c)^{-1} (...)^T m r on one 3D patch (host)
+static void tensor_apply_host3(const Patch::Tensor& T, const int* M, const std::vector<uint8_t>& mask, const double* r,
+                               double* y) {
+    const int P0 = T.Pd[0], P1 = T.Pd[1], P2 = T.Pd[2];
+    // forward: contract i0, then i1, then i2
+    std::vector<double> A((size_t)P0 * M[1] * M[2], 0.0), B((size_t)P0 * P1 * M[2], 0.0), Z((size_t)P0 * P1 * P2, 0.0);
+    for (int i2 = 0; i2 < M[2]; ++i2)
+        for (int i1 = 0; i1 < M[1]; ++i1)
+            for (int i0 = 0; i0 < M[0]; ++i0) {
+                const size_t i = i0 + (size_t)M[0] * (i1 + (size_t)M[1] * i2);
+                if (mask[i]) continue;
+                for (int a = 0; a < P0; ++a) A[a + (size_t)P0 * (i1 + (size_t)M[1] * i2)] += r[i] * T.U[0][(size_t)i0 * P0 + a];
+            }
+    for (int i2 = 0; i2 < M[2]; ++i2)
+        for (int i1 = 0; i1 < M[1]; ++i1)
+            for (int b = 0; b < P1; ++b) {
+                const double u = T.U[1][(size_t)i1 * P1 + b];
+                if (u == 0.0) continue;
+                for (int a = 0; a < P0; ++a)
+                    B[a + (size_t)P0 * (b + (size_t)P1 * i2)] += u * A[a + (size_t)P0 * (i1 + (size_t)M[1] * i2)];
+            }
+    for (int i2 = 0; i2 < M[2]; ++i2)
+        for (int c = 0; c < P2; ++c) {
+            const double u = T.U[2][(size_t)i2 * P2 + c];
+            if (u == 0.0) continue;
+            for (size_t n = 0; n < (size_t)P0 * P1; ++n) Z[n + (size_t)P0 * P1 * c] += u * B[n + (size_t)P0 * P1 * i2];
+        }
+    for (int c = 0; c < P2; ++c)
+        for (int b = 0; b < P1; ++b)
+            for (int a = 0; a < P0; ++a)
+                Z[a + (size_t)P0 * (b + (size_t)P1 * c)] /= T.lam[0][a] + T.lam[1][b] + T.lam[2][c] + T.shift;
+    // backward
+    std::fill(B.begin(), B.end(), 0.0);
+    std::fill(A.begin(), A.end(), 0.0);
+    for (int i2 = 0; i2 < M[2]; ++i2)
+        for (int c = 0; c < P2; ++c) {
+            const double u = T.U[2][(size_t)i2 * P2 + c];
+            if (u == 0.0) continue;
+            for (size_t n = 0; n < (size_t)P0 * P1; ++n) B[n + (size_t)P0 * P1 * i2] += u * Z[n + (size_t)P0 * P1 * c];
+        }
+    for (int i2 = 0; i2 < M[2]; ++i2)
+        for (int i1 = 0; i1 < M[1]; ++i1)
+            for (int b = 0; b < P1; ++b) {
+                const double u = T.U[1][(size_t)i1 * P1 + b];
+                if (u == 0.0) continue;
+                for (int a = 0; a < P0; ++a)
+                    A[a + (size_t)P0 * (i1 + (size_t)M[1] * i2)] += u * B[a + (size_t)P0 * (b + (size_t)P1 * i2)];
+            }
+    for (int i2 = 0; i2 < M[2]; ++i2)
+        for (int i1 = 0; i1 < M[1]; ++i1)
+            for (int i0 = 0; i0 < M[0]; ++i0) {
+                const size_t i = i0 + (size_t)M[0] * (i1 + (size_t)M[1] * i2);
+                double t = 0.0;
+                if (!mask[i])
+                    for (int a = 0; a < P0; ++a) t += A[a + (size_t)P0 * (i1 + (size_t)M[1] * i2)] * T.U[0][(size_t)i0 * P0 + a];
+                y[i] = t;
+            }
+}
+
+// The 3D form of tensor_setup: each metric diagonal g_dd ~ f_d0 (x) f_d1 (x) f_d2 (rank one); the mass
+// factors f_de (e != d) scaled to unit mean, their scales moved into the stiffness factor f_dd; the mass
+// weight of direction e is the geometric mean of the two factors f_de (the Kronecker sum needs one mass
+// matrix per direction), the stiffness weight of direction d is f_dd:
+//   K_sep = A_0 (x) B_1 (x) B_2 + B_0 (x) A_1 (x) B_2 + B_0 (x) B_1 (x) A_2   (exact for tensor-product maps).
+static void tensor_setup3(Patch& P, const ieti_options& opt, bool mode_n) {
+    const Level& L0 = P.lv[0];
+    DirTable dt[3];
+    for (int d = 0; d < 3; ++d) dt[d] = make_dir(L0.knots[d], P.p[d], P.knots[d], P.p[d]);
+    const int Q[3] = {dt[0].Q, dt[1].Q, dt[2].Q};
+    std::vector<double> f[3][3];
+    for (int d = 0; d < 3; ++d) {
+        std::vector<double> x[3];
+        rank_one3(P.qpc[d], Q, x);
+        for (int e = 0; e < 3; ++e) {
+            if (e == d) continue;
+            double m = 0.0;
+            for (int q = 0; q < Q[e]; ++q) m += dt[e].w[q] * x[e][q];
+            for (auto& v : x[e]) v /= m;
+            for (auto& v : x[d]) v *= m;
+        }
+        for (int e = 0; e < 3; ++e) f[d][e] = x[e];
+    }
+    std::vector<double> A1d[3], B1d[3];
+    for (int e = 0; e < 3; ++e) {
+        const int d1 = (e + 1) % 3, d2 = (e + 2) % 3;
+        std::vector<double> wm(Q[e]);
+        for (int q = 0; q < Q[e]; ++q) wm[q] = std::sqrt(f[d1][e][q] * f[d2][e][q]);
+        const DirTable& t = dt[e];
+        const int M = L0.M[e], p = t.p;
+        A1d[e].assign((size_t)M * M, 0.0);
+        B1d[e].assign((size_t)M * M, 0.0);
+        for (int q = 0; q < t.Q; ++q)
+            for (int a = 0; a <= p; ++a)
+                for (int b = 0; b <= p; ++b) {
+                    const int i = t.first[q] + a, j = t.first[q] + b;
+                    const size_t o = (size_t)q * (p + 1);
+                    A1d[e][(size_t)i * M + j] += t.w[q] * f[e][e][q] * t.dN[o + a] * t.dN[o + b];
+                    B1d[e][(size_t)i * M + j] += t.w[q] * wm[q] * t.N[o + a] * t.N[o + b];
+                }
+    }
+    double msq = 0.0;
+    for (int d = 0; d < 3; ++d) msq += (double)L0.nel[d] * L0.nel[d];
+    const double shift = opt.smoother_sigma * msq / 3.0;
+    for (int mode = 0; mode < 2; ++mode) {
+        if (mode == MODE_N && !mode_n) continue;
+        Patch::Tensor& T = P.ts[mode];
+        const uint32_t sides = mode == MODE_D ? 0x3Fu : P.bside;
+        for (int d = 0; d < 3; ++d) {
+            const int M = L0.M[d];
+            std::vector<int> keep;
+            for (int i = 0; i < M; ++i) {
+                const bool cut = (i == 0 && (sides >> (2 * d) & 1u)) || (i == M - 1 && (sides >> (2 * d + 1) & 1u));
+                if (!cut) keep.push_back(i);
+            }
+            const int nk = (int)keep.size();
+            std::vector<double> Ak((size_t)nk * nk), Bk((size_t)nk * nk), Uk, lk;
+            for (int i = 0; i < nk; ++i)
+                for (int j = 0; j < nk; ++j) {
+                    Ak[(size_t)i * nk + j] = A1d[d][(size_t)keep[i] * M + keep[j]];
+                    Bk[(size_t)i * nk + j] = B1d[d][(size_t)keep[i] * M + keep[j]];
+                }
+            gen_eig(nk, Ak, Bk, Uk, lk);
+            const int Pd = (M + 15) / 16 * 16;
+            T.Pd[d] = Pd;
+            T.U[d].assign((size_t)Pd * Pd, 0.0);
+            T.lam[d].assign(Pd, 1e300);
+            for (int i = 0; i < nk; ++i)
+                for (int a = 0; a < nk; ++a) T.U[d][(size_t)keep[i] * Pd + a] = Uk[(size_t)i * nk + a];
+            for (int a = 0; a < nk; ++a) T.lam[d][a] = lk[a];
+        }
+        T.shift = shift;
+        auto mask = level_mask(P, L0, mode);
+        std::vector<double> x(L0.n), y(L0.n), z(L0.n);
+        uint64_t sd = 0xBF58476D1CE4E5B9ull;
+        for (int64_t i = 0; i < L0.n; ++i) {
+            sd ^= sd << 13; sd ^= sd >> 7; sd ^= sd << 17;
+            x[i] = mask[i] ? 0.0 : ((sd >> 11) * (1.0 / 9007199254740992.0) - 0.5);
+        }
+        double lam = 1.0;
+        for (int it = 0; it < 20; ++it) {
+            host_apply(P, L0, mask, x.data(), y.data());
+            tensor_apply_host3(T, L0.M, mask, y.data(), z.data());
+            double nx = 0.0, nz = 0.0;
+            for (int64_t i = 0; i < L0.n; ++i) {
+                nx += x[i] * x[i];
+                nz += z[i] * z[i];
+            }
+            if (!(nz > 0.0) || !(nx > 0.0)) break;
+            lam = std::sqrt(nz / nx);
+            const double sc = 1.0 / std::sqrt(nz);
+            for (int64_t i = 0; i < L0.n; ++i) x[i] = z[i] * sc;
+        }
+        T.tau = 1.0 / lam;
+    }
+}
+
 // dense inverse of the masked level matrix (masked rows/cols zero) by Cholesky
 static std::vector<double> dense_inverse(const Patch& P, const Level& L, int mode) {
     auto mask = level_mask(P, L, mode);
@@ -1086,8 +1273,6 @@ Plan* build_plan(const ieti_patch* in, int n, const double* pv, int n_pv, const 
     if (opt.smoother == IETI_SMOOTHER_TENSOR && !(opt.smoother_sigma > 0))
         throw Error(IETI_EINVAL, "smoother_sigma must be positive");
     const int dim = in[0].dim;
-    if (opt.smoother == IETI_SMOOTHER_TENSOR && dim != 2)
-        throw Error(IETI_ENOTSUP, "the tensor smoother is built for 2D patches");
     for (int k = 0; k < n; ++k) validate_patch(in[k], dim, k);
     auto P = std::make_unique<Plan>();
     Plan& pl = *P;
@@ -1534,7 +1719,10 @@ Plan* build_plan(const ieti_patch* in, int n, const double* pv, int n_pv, const 
                 if (neumann_mg) pa.lv[l].lmax[MODE_N] = power_lmax(pa, pa.lv[l], MODE_N);
                 pa.lv[l].lmax[MODE_D] = power_lmax(pa, pa.lv[l], MODE_D);
             }
-        if (mg && opt.smoother == IETI_SMOOTHER_TENSOR && pa.lv.size() > 1) tensor_setup(pa, opt, neumann_mg);
+        if (mg && opt.smoother == IETI_SMOOTHER_TENSOR && pa.lv.size() > 1) {
+            if (dim == 2) tensor_setup(pa, opt, neumann_mg);
+            else tensor_setup3(pa, opt, neumann_mg);
+        }
         Level& cl = pa.lv.back();
         if (mg) {
             if (neumann_mg) cl.inv[MODE_N] = dense_inverse(pa, cl, MODE_N);
@@ -1631,8 +1819,8 @@ int ieti_plan_array(const ieti_plan* plan, int32_t which, int32_t patch, int32_t
         if (mode < 0 || mode > 1 || pa.ts[mode].U[0].empty()) return IETI_EINVAL;
         const Patch::Tensor& T = pa.ts[mode];
         if (which == IETI_ARR_TENSOR_PARAMS) {
-            double v[4] = {(double)T.Pd[0], (double)T.Pd[1], T.shift, T.tau};
-            return emit(v, 4, sizeof(double));
+            double v[5] = {(double)T.Pd[0], (double)T.Pd[1], T.shift, T.tau, (double)T.Pd[2]};
+            return emit(v, 5, sizeof(double));
         }
         if (d < 0 || d >= p.dim) return IETI_EINVAL;
         if (which == IETI_ARR_TENSOR_U) return emit(T.U[d].data(), (int64_t)T.U[d].size(), sizeof(double));

@@ -278,8 +278,8 @@ struct Solver : SolverBase {
     // the fast diagonalisation, the forward transform's scratch, the largest padded sizes
     bool fd_on = false;
     FdInfo* fd_info[2] = {nullptr, nullptr};
-    double *fd_U = nullptr, *fd_lam = nullptr, *fd_z = nullptr;
-    int fd_p0max = 0, fd_p1max = 0;
+    double *fd_U = nullptr, *fd_lam = nullptr, *fd_z = nullptr, *fd_z2 = nullptr;
+    int fd_p0max = 0, fd_p1max = 0, fd_tiles3 = 0;
     size_t fd_lds = 0;
     // level 0 FP64
     double* coef64 = nullptr;
@@ -422,7 +422,25 @@ struct Solver : SolverBase {
     // one work-group per patch runs the rest of the cycle (k_vcoarse).
     // finest level, patches with tensor-smoother data: x = tau P r (set) or x += tau P r
     void fd_smooth(int mode, const int* act, const T* r, T* x, bool set) {
-        FdArgs a{lev[0].L, fd_info[mode], fd_U, fd_lam, fd_z, act, mode, N, fd_p0max / 16};
+        if (dim == 3) {   // six axis contractions through the two scratch buffers
+            FdArgs a{lev[0].L, fd_info[mode], fd_U, fd_lam, fd_z, act, mode, N, 0, fd_z2};
+            const dim3 g((fd_tiles3 + FD3_THREADS / WAVE - 1) / (FD3_THREADS / WAVE), N), b(FD3_THREADS);
+            hipLaunchKernelGGL(k_fd3_ax0_fwd<T>, g, b, 0, stream, a, r);
+            check_launch();
+            hipLaunchKernelGGL((k_fd3_axn<1, true, false>), g, b, 0, stream, a, (const double*)fd_z, fd_z2);
+            check_launch();
+            hipLaunchKernelGGL((k_fd3_axn<2, true, true>), g, b, 0, stream, a, (const double*)fd_z2, fd_z);
+            check_launch();
+            hipLaunchKernelGGL((k_fd3_axn<2, false, false>), g, b, 0, stream, a, (const double*)fd_z, fd_z2);
+            check_launch();
+            hipLaunchKernelGGL((k_fd3_axn<1, false, false>), g, b, 0, stream, a, (const double*)fd_z2, fd_z);
+            check_launch();
+            if (set) hipLaunchKernelGGL((k_fd3_ax0_bwd<T, true>), g, b, 0, stream, a, x);
+            else hipLaunchKernelGGL((k_fd3_ax0_bwd<T, false>), g, b, 0, stream, a, x);
+            check_launch();
+            return;
+        }
+        FdArgs a{lev[0].L, fd_info[mode], fd_U, fd_lam, fd_z, act, mode, N, fd_p0max / 16, nullptr};
         const dim3 grid(8 * ((N + 7) / 8) * (fd_p0max / 16));
         hipLaunchKernelGGL(k_fd_fwd<T>, grid, dim3(FD_THREADS), fd_lds, stream, a, r);
         check_launch();
@@ -1339,6 +1357,7 @@ void Solver<T>::setup() {
                 if (Tz.U[0].empty()) continue;
                 f.P0 = Tz.Pd[0];
                 f.P1 = Tz.Pd[1];
+                f.P2 = dim == 3 ? Tz.Pd[2] : 0;
                 f.u0 = (int64_t)hu.size();
                 hu.insert(hu.end(), Tz.U[0].begin(), Tz.U[0].end());
                 f.u1 = (int64_t)hu.size();
@@ -1347,10 +1366,17 @@ void Solver<T>::setup() {
                 hl.insert(hl.end(), Tz.lam[0].begin(), Tz.lam[0].end());
                 f.l1 = (int64_t)hl.size();
                 hl.insert(hl.end(), Tz.lam[1].begin(), Tz.lam[1].end());
+                if (dim == 3) {
+                    f.u2 = (int64_t)hu.size();
+                    hu.insert(hu.end(), Tz.U[2].begin(), Tz.U[2].end());
+                    f.l2 = (int64_t)hl.size();
+                    hl.insert(hl.end(), Tz.lam[2].begin(), Tz.lam[2].end());
+                    fd_tiles3 = std::max(fd_tiles3, f.P0 * f.P1 * f.P2 / 256);
+                }
                 f.zoff = zlen;   // one scratch per patch: the two modes never run at the same time
                 f.shift = Tz.shift;
                 f.tau = Tz.tau;
-                zk = std::max(zk, (int64_t)f.P0 * f.P1);
+                zk = std::max(zk, (int64_t)f.P0 * f.P1 * (dim == 3 ? f.P2 : 1));
                 fd_p0max = std::max(fd_p0max, f.P0);
                 fd_p1max = std::max(fd_p1max, f.P1);
             }
@@ -1363,21 +1389,25 @@ void Solver<T>::setup() {
             fd_U = arena.upload(hu, st);
             fd_lam = arena.upload(hl, st);
             fd_z = arena.alloc<double>(zlen, st);
+            if (dim == 3) fd_z2 = arena.alloc<double>(zlen, st);
             std::vector<FdInfo> i0(info.begin(), info.begin() + N), i1(info.begin() + N, info.end());
             fd_info[0] = arena.upload(i0, st);
             fd_info[1] = arena.upload(i1, st);
             fd_lds = fd_lds_words(fd_p0max, fd_p1max) * sizeof(double);
+            if (dim == 3) fd_lds = 0;   // the 3D contractions use no LDS
             int dev = 0, max_lds = 0;
             HIPCHECK(hipGetDevice(&dev));
             HIPCHECK(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
             if (fd_lds > (size_t)max_lds)
                 throw Error(IETI_ENOTSUP, "tensor smoother: patch too large for the transforms' LDS");
-            HIPCHECK(hipFuncSetAttribute((const void*)k_fd_fwd<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                         (int)fd_lds));
-            HIPCHECK(hipFuncSetAttribute((const void*)k_fd_bwd<T, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                         (int)fd_lds));
-            HIPCHECK(hipFuncSetAttribute((const void*)k_fd_bwd<T, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                         (int)fd_lds));
+            if (dim == 2) {
+                HIPCHECK(hipFuncSetAttribute((const void*)k_fd_fwd<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             (int)fd_lds));
+                HIPCHECK(hipFuncSetAttribute((const void*)k_fd_bwd<T, true>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)fd_lds));
+                HIPCHECK(hipFuncSetAttribute((const void*)k_fd_bwd<T, false>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)fd_lds));
+            }
             HIPCHECK(hipStreamSynchronize(st));
         }
     }
@@ -2086,9 +2116,10 @@ static size_t estimate_device_bytes(const Plan& pl) {
         b += 2.0 * npk * (double)(pa.lv[0].n + 2 * pa.lv[0].guard + 64) * 8.0;   // Psi + setup scratch
         b += (double)(pa.band[0].size() + pa.band[1].size()) * 8.0;
         b += (double)pa.n_qp * (16.0 + 8.0 * pa.dim);
-        for (int m = 0; m < 2; ++m)   // tensor smoother: U_d, lambda_d, scratch Z
+        for (int m = 0; m < 2; ++m)   // tensor smoother: U_d, lambda_d, scratch (two buffers in 3D)
             if (!pa.ts[m].U[0].empty())
-                b += 8.0 * (double)(pa.ts[m].U[0].size() + pa.ts[m].U[1].size() + 2 * pa.ts[m].Pd[0] * pa.ts[m].Pd[1]);
+                b += 8.0 * (double)(pa.ts[m].U[0].size() + pa.ts[m].U[1].size() + pa.ts[m].U[2].size() +
+                                    2.0 * pa.ts[m].Pd[0] * pa.ts[m].Pd[1] * std::max(1, pa.ts[m].Pd[2]));
     }
     const double npad = (double)((pl.n_primal + 15) / 16 * 16);
     b += (double)pl.n_lambda * 8.0 * 8.0 + (double)pl.n_primal * pl.n_primal * 8.0 + 3.0 * npad * npad * 8.0;

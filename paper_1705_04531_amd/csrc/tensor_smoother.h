@@ -23,10 +23,10 @@ namespace ieti {
 constexpr int FD_THREADS = 512;
 
 struct FdInfo {
-    int64_t u0, u1;        // offsets of U_0 (P0 x P0) and U_1 (P1 x P1), row-major, in the U array
-    int64_t l0, l1;        // offsets of lambda_0 and lambda_1 in the eigenvalue array
-    int64_t zoff;          // scratch Z of the patch (P1 x P0)
-    int32_t P0, P1;        // padded sizes (multiples of 16); 0: no tensor smoother on this patch
+    int64_t u0, u1, u2;    // offsets of U_d (P_d x P_d, row-major) in the U array (u2: 3D only)
+    int64_t l0, l1, l2;    // offsets of lambda_d in the eigenvalue array
+    int64_t zoff;          // scratch of the patch (P1 x P0, 3D: P2 x P1 x P0)
+    int32_t P0, P1, P2;    // padded sizes (multiples of 16); P0 = 0: no tensor smoother on this patch; P2 = 0 in 2D
     double shift, tau;
 };
 
@@ -39,7 +39,8 @@ struct FdArgs {
     const int* active;
     int mode;
     int N;                 // patches
-    int ncb;               // column blocks per patch in the grid (largest P0 / 16)
+    int ncb;               // 2D: column blocks per patch in the grid (largest P0 / 16)
+    double* z2;            // 3D: second scratch buffer (same offsets as z)
 };
 
 // LDS doubles of either kernel for the largest padded sizes
@@ -187,6 +188,114 @@ __global__ __launch_bounds__(FD_THREADS) void k_fd_bwd(FdArgs a, T* __restrict__
             if (SET) x[vi] = m ? T(0) : T(f.tau * c[rr]);
             else if (!m) x[vi] = T((double)x[vi] + f.tau * c[rr]);
         }
+    }
+}
+
+
+// ---------------------------------------------------------------------------
+// 3D: the transforms as three contractions along one axis each, on padded P2 x P1 x P0 arrays (index
+// a + P0 (b + P1 c)) in the two scratch buffers:
+//   forward   za = R x_0 U_0,  zb = za x_1 U_1,  za = (zb x_2 U_2) ./ (lambda_0 + lambda_1 + lambda_2 + c)
+//   backward  zb = za x_2 U_2^T,  za = zb x_1 U_1^T,  x (+)= tau (za x_0 U_0^T) on unmasked coefficients
+// (x_d U: contraction of the axis-d index i with U[i][.]).  One wave per 16 x 16 output tile, FD3_THREADS / 64
+// tiles per work-group, the contraction (P_d <= 128) read straight from memory; every entry of the padded
+// arrays is written (padding rows and columns come out zero), so no scratch needs clearing.
+
+constexpr int FD3_THREADS = 256;
+
+// tile t of patch k (grid: blockIdx.y = patch, FD3_THREADS / 64 tiles per work-group); false if t is past
+// the patch's tiles
+__device__ __forceinline__ bool fd3_tile(const FdArgs& a, int& k, FdInfo& f, int& t) {
+    k = blockIdx.y;
+    f = a.info[k];
+    if (f.P0 == 0 || (a.active && !a.active[k])) return false;
+    t = blockIdx.x * (FD3_THREADS / WAVE) + threadIdx.x / WAVE;
+    return t < (f.P0 / 16) * (f.P1 / 16) * (f.P2 / 16) * 16;
+}
+
+// forward axis 0: za[o][a] = sum_i0 m r[o][i0] U_0[i0][a], o = i1 + P1 i2
+template <typename T>
+__global__ __launch_bounds__(FD3_THREADS) void k_fd3_ax0_fwd(FdArgs a, const T* __restrict__ r) {
+    int k, t;
+    FdInfo f;
+    if (!fd3_tile(a, k, f, t)) return;
+    const PatchLev& P = a.L[k];
+    const int nco = f.P0 / 16, ro = t / nco, co = t % nco;
+    const int l = threadIdx.x & (WAVE - 1), i = l & 15, kq = l >> 4;
+    const int o = ro * 16 + i, i1 = o % f.P1, i2 = o / f.P1;
+    const bool rowok = i1 < P.M[1] && i2 < P.M[2];
+    const double* U0 = a.U + f.u0;
+    mf_d4 c = {0.0, 0.0, 0.0, 0.0};
+    for (int kb = 0; kb < f.P0 / 16; ++kb)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int i0 = kb * 16 + 4 * s + kq;
+            double av = 0.0;
+            if (rowok && i0 < P.M[0] && !masked(P, a.mode, i0, i1, i2))
+                av = (double)r[P.voff + i0 + (int64_t)P.M[0] * (i1 + (int64_t)P.M[1] * i2)];
+            c = __builtin_amdgcn_mfma_f64_16x16x4f64(av, U0[(int64_t)i0 * f.P0 + co * 16 + i], c, 0, 0, 0);
+        }
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+        const int orow = ro * 16 + (l >> 4) + 4 * rr;
+        a.z[f.zoff + (int64_t)orow * f.P0 + co * 16 + i] = c[rr];
+    }
+}
+
+// axis AX (1 or 2) viewed as [outer][P_AX][inner]: FWD out[o][c][n] = sum_i U[i][c] in[o][i][n],
+// otherwise sum_i U[c][i] in[o][i][n]; SCALE divides by lambda_0[a] + lambda_1[b] + lambda_2[c] + shift
+template <int AX, bool FWD, bool SCALE>
+__global__ __launch_bounds__(FD3_THREADS) void k_fd3_axn(FdArgs a, const double* __restrict__ in, double* __restrict__ out) {
+    int k, t;
+    FdInfo f;
+    if (!fd3_tile(a, k, f, t)) return;
+    const int Pax = AX == 1 ? f.P1 : f.P2;
+    const int inner = AX == 1 ? f.P0 : f.P0 * f.P1;
+    const int nci = inner / 16, ncr = Pax / 16;
+    const int o = t / (ncr * nci), rem = t % (ncr * nci), cr = rem / nci, ci = rem % nci;
+    const double* U = a.U + (AX == 1 ? f.u1 : f.u2);
+    const double* B = in + f.zoff + (int64_t)o * Pax * inner + ci * 16;
+    mf_d4 c = {0.0, 0.0, 0.0, 0.0};
+    for (int kb = 0; kb < ncr; ++kb)
+        c = FWD ? mf_block<true>(U + (int64_t)kb * 16 * Pax + cr * 16, Pax, B + (int64_t)kb * 16 * inner, inner, c, 1.0)
+                : mf_block<false>(U + (int64_t)cr * 16 * Pax + kb * 16, Pax, B + (int64_t)kb * 16 * inner, inner, c, 1.0);
+    const int l = threadIdx.x & (WAVE - 1);
+    const int n = ci * 16 + (l & 15);
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+        const int row = cr * 16 + (l >> 4) + 4 * rr;
+        double v = c[rr];
+        if (SCALE) {
+            const int ia = n % f.P0, ib = n / f.P0;
+            v /= a.lam[f.l0 + ia] + a.lam[f.l1 + ib] + a.lam[f.l2 + row] + f.shift;
+        }
+        out[f.zoff + (int64_t)o * Pax * inner + (int64_t)row * inner + n] = v;
+    }
+}
+
+// backward axis 0: y[o][i0] = sum_a za[o][a] U_0[i0][a]; SET: x = tau y (masked 0), else x += tau y
+template <typename T, bool SET>
+__global__ __launch_bounds__(FD3_THREADS) void k_fd3_ax0_bwd(FdArgs a, T* __restrict__ x) {
+    int k, t;
+    FdInfo f;
+    if (!fd3_tile(a, k, f, t)) return;
+    const PatchLev& P = a.L[k];
+    const int nco = f.P0 / 16, ro = t / nco, co = t % nco;
+    const double* U0 = a.U + f.u0;
+    mf_d4 c = {0.0, 0.0, 0.0, 0.0};
+    for (int kb = 0; kb < f.P0 / 16; ++kb)
+        c = mf_block<false, true>(a.z + f.zoff + (int64_t)ro * 16 * f.P0 + kb * 16, f.P0,
+                                  U0 + (int64_t)co * 16 * f.P0 + kb * 16, f.P0, c, 1.0);
+    const int l = threadIdx.x & (WAVE - 1);
+    const int i0 = co * 16 + (l & 15);
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+        const int o = ro * 16 + (l >> 4) + 4 * rr, i1 = o % f.P1, i2 = o / f.P1;
+        if (i0 >= P.M[0] || i1 >= P.M[1] || i2 >= P.M[2]) continue;
+        const int64_t vi = P.voff + i0 + (int64_t)P.M[0] * (i1 + (int64_t)P.M[1] * i2);
+        const bool m = masked(P, a.mode, i0, i1, i2);
+        if (SET) x[vi] = m ? T(0) : T(f.tau * c[rr]);
+        else if (!m) x[vi] = T((double)x[vi] + f.tau * c[rr]);
     }
 }
 

@@ -224,10 +224,35 @@ def test_tensor_smoother_options(lib):
         Plan(wl.patches, default_options(smoother=2))
     with pytest.raises(_abi.IetiError):
         Plan(wl.patches, default_options(smoother=_abi.IETI_SMOOTHER_TENSOR, smoother_sigma=0.0))
-    cube = W.unit_cube((2, 2, 2), 2, 4)
-    with pytest.raises(_abi.IetiError) as e:
-        Plan(cube.patches, default_options(smoother=_abi.IETI_SMOOTHER_TENSOR))
-    assert e.value.code == _abi.IETI_ENOTSUP
     pl = Plan(wl.patches, default_options())
     with pytest.raises(_abi.IetiError):         # no tensor data for the Chebyshev smoother
         pl.array(_abi.IETI_ARR_TENSOR_PARAMS, 0, 0)
+
+
+def test_tensor_smoother_factors_match_oracle_3d(lib):
+    """3D plans: the three eigenvector factors per mode against the oracle's separable matrices, the shift
+    (sigma times the mean squared element count) and tau."""
+    from oracle import tensor_smoother as TS
+    wl = W.unit_cube((2, 2, 2), 2, 6)
+    pl = Plan(wl.patches, default_options(smoother=_abi.IETI_SMOOTHER_TENSOR, coarse_dofs=0))
+    geo = wl.patches[0]
+    pairs = TS.separable_pairs(geo)
+    bits = pl.array(_abi.IETI_ARR_MASKS, 0, 0, dtype=np.int32)
+    K = assembly.assemble_patch(geo).K.toarray()
+    for mode in (0, 1):
+        sides = int(bits[0]) if mode == 0 else 0x3F
+        kept = TS.kept_indices(geo, sides)
+        par = pl.array(_abi.IETI_ARR_TENSOR_PARAMS, 0, mode)
+        assert par[2] == pytest.approx(TS.shift(geo, 0.3), rel=1e-14) and int(par[4]) == int(par[0])
+        for d, (A, B) in enumerate(pairs):
+            Pd = int(par[d] if d < 2 else par[4])
+            U = pl.array(_abi.IETI_ARR_TENSOR_U, 0, 256 * mode + d).reshape(Pd, Pd)
+            lam = pl.array(_abi.IETI_ARR_TENSOR_LAMBDA, 0, 256 * mode + d)
+            kk = kept[d]
+            nk = len(kk)
+            Uk = U[kk][:, :nk]
+            assert np.abs(Uk.T @ B[np.ix_(kk, kk)] @ Uk - np.eye(nk)).max() <= 1e-9
+            assert np.abs(Uk.T @ A[np.ix_(kk, kk)] @ Uk - np.diag(lam[:nk])).max() <= 1e-9 * lam[:nk].max()
+        m = _mask_from_bits(geo.shape, int(bits[0]), int(bits[1]), mode)
+        lmax = TS.damping(geo, sides, m, K, 0.3)
+        assert 0.99 <= par[3] * lmax <= 1.1, (mode, par[3] * lmax)

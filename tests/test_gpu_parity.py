@@ -203,3 +203,19 @@ def test_tensor_smoother_p_robust(require_gpu):
         print(f"p={p}: inner iterations Chebyshev {its['chebyshev']:.2f}, tensor {its['tensor']:.2f}", flush=True)
     tens = [r[2] for r in rows]
     assert max(tens) <= 16.0 and max(tens) <= 1.6 * min(tens), rows
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+@pytest.mark.parametrize("variant,solver", [("mg", 0), ("mg_saddle", 3)], ids=["mg", "mg_saddle"])
+@pytest.mark.parametrize("name,make", CASES_3D, ids=[c[0] for c in CASES_3D])
+def test_tensor_smoother_3d_matches_oracle(require_gpu, name, make, variant, solver, prec):
+    """The tensor smoother on 3D patches (three axis contractions per transform)."""
+    from paper_1705_04531_amd import _abi
+    wl = make()
+    u_ref, lay, _ = oracle_solution(wl)
+    u, st = run_gpu(wl, local_solver=solver, mg_precision=prec, tol=1e-10, coarse_dofs=0,
+                    smoother=_abi.IETI_SMOOTHER_TENSOR)
+    err = rel_err(wl, u, u_ref, lay)
+    print(f"{name} 3D tensor smoother {variant} prec={prec}: err={err:.3e} outer={st['outer_iterations']} "
+          f"inner={st['inner_iterations_mean']:.2f}", flush=True)
+    assert err <= 1e-8

@@ -76,3 +76,27 @@ def test_dense_solve_equals_eigenvector_form(sides):
     y2 = TS.apply_eig(geo, sides, mask, r, 0.3)
     assert np.abs(y1 - y2).max() <= 1e-10 * np.abs(y1).max()
     assert np.all(y1[mask] == 0.0)
+
+
+def test_rank_one_of_separable_3d_array():
+    rng = np.random.default_rng(4)
+    x = [rng.uniform(0.5, 2.0, n) for n in (7, 9, 11)]
+    g = np.einsum("i,j,k->ijk", *x)
+    y = TS.rank_one(g)
+    assert np.abs(np.einsum("i,j,k->ijk", *y) - g).max() <= 1e-12 * g.max()
+
+
+def test_separable_stiffness_equals_assembly_on_3d_tensor_map():
+    """x = (phi(xi_0), psi(xi_1), chi(xi_2)): g_00 = psi' chi' / phi' etc. are rank one and the mass factors
+    a direction receives from the two other diagonals agree, so K_sep = K."""
+    p, n = (2, 3, 2), (4, 3, 5)
+    k = [W.uniform_open_knots(n[d], p[d]) for d in range(3)]
+    g = [bspline.greville(k[d], p[d]) for d in range(3)]
+    phi = lambda t: 0.5 + 1.5 * t + 0.3 * t * t          # noqa: E731
+    psi = lambda t: -1.0 + 0.7 * t - 0.2 * np.sin(t)     # noqa: E731
+    chi = lambda t: 2.0 + t + 0.25 * t ** 3              # noqa: E731
+    X = np.meshgrid(phi(g[0]), psi(g[1]), chi(g[2]), indexing="ij")
+    ctrl = np.stack([x.ravel(order="F") for x in X], axis=1)
+    geo = W.Patch(degree=p, knots=tuple(k), ctrl=ctrl)
+    K = assembly.assemble_patch(geo).K.toarray()
+    assert np.abs(TS.k_sep(geo) - K).max() <= 1e-11 * np.abs(K).max()
