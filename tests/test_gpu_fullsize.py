@@ -57,3 +57,25 @@ def test_full_config_saddle_point_variant(require_gpu, name, prec):
           f"its {st['outer_iterations']}, omega {st['saddle_omega']:.3f}", flush=True)
     assert st["breakdown"] == 0
     assert err <= 1e-8 and nrm <= 1e-8
+
+
+@pytest.mark.parametrize("name", ["deformed8x8_p3_n64", "deformed16x16_mixed", "cube4x4x4_p2_n24"])
+def test_full_config_tensor_smoother(require_gpu, name):
+    """The finest-level tensor smoother at full size (MG-MG, the workload's precision): the same sampled
+    oracle values as the benchmark's solver."""
+    from paper_1705_04531_amd import _abi
+    path = os.path.join(HERE, "golden", f"full_{name}.json")
+    if not os.path.exists(path):
+        pytest.skip(f"golden file for {name} not generated")
+    g = json.load(open(path))
+    wl = W.CONFIGS[name]()
+    u, st = run_gpu(wl, smoother=_abi.IETI_SMOOTHER_TENSOR)
+    lay = conforming.layout(wl)
+    ug = conforming.global_from_torn(lay, split_torn(wl, u))
+    idx = np.array(g["indices"])
+    ref = np.array(g["values"])
+    err = np.linalg.norm(ug[idx] - ref) / np.linalg.norm(ref)
+    nrm = abs(np.linalg.norm(ug) - g["norm2"]) / g["norm2"]
+    print(f"{name} tensor smoother: sampled rel err {err:.3e}, norm rel diff {nrm:.3e}, "
+          f"outer {st['outer_iterations']}, inner {st['inner_iterations_mean']:.2f}", flush=True)
+    assert err <= 1e-8 and nrm <= 1e-8
