@@ -107,9 +107,10 @@ typedef struct ieti_options {
     size_t  hbm_budget;        /* bytes of device memory the handle may use, 0 = unlimited */
     int32_t coarse_level;      /* first multigrid level run by the per-patch fused coarse kernel: 0 = chosen
                                   from the LDS size (default), -1 = none (every level by batched launches) */
-    int32_t autotune;          /* 1: at setup, time one batched local solve per candidate smoother (finest and
-                                  coarse Chebyshev degrees, interval lower end) around the tuned table and keep
-                                  the fastest; 0: the table (default) */
+    int32_t autotune;          /* 1: at setup, time one batched local solve per candidate (finest and coarse
+                                  Chebyshev degrees, interval lower end, and the finest-level tile variant: x
+                                  window staged in LDS or read directly) around the tuned table and keep the
+                                  fastest; 0: the table (default) */
     int32_t coarse_dofs;       /* multigrid: a patch level with at most this many coefficients is not
                                   coarsened further (dense exact solve there); 0 = no such limit. Coarsening
                                   also stops where a direction's element count is odd or below 6 (default 600) */
@@ -117,6 +118,11 @@ typedef struct ieti_options {
                                   IETI_SMOOTHER_TENSOR (coarser levels keep Chebyshev) */
     double  smoother_sigma;    /* IETI_SMOOTHER_TENSOR: mass shift sigma of the tensor smoother, in units of the
                                   mean squared inverse element size of the patch (default 0.3) */
+    const char* tune_cache;    /* autotune = 1: path of a JSON-lines file of earlier choices (one object per line:
+                                  key, cheb_degree, cheb_degree_coarse, cheb_lower, stage), keyed by dimension,
+                                  MG precision, local solver, coarse_dofs and the set of patch shapes (degree /
+                                  elements per direction); a hit skips the timing, a miss appends the new choice.
+                                  Read at setup only; NULL = no cache (default) */
 } ieti_options;
 
 typedef struct ieti_stats {
@@ -139,6 +145,8 @@ typedef struct ieti_stats {
     int32_t cheb_degree_coarse;        /* on the coarser levels, */
     double  cheb_lower;                /* and the interval's lower end over the tuned table's (1 = table) */
     double  saddle_omega;              /* MG-MG-S: the scaling omega of the V-cycle block in use (0 otherwise) */
+    int32_t fine_tile_staged;          /* finest-level sweep tiles stage their x window in LDS (1) or not (0) */
+    int32_t tune_cached;               /* 1 if the autotuner's choice came from options.tune_cache */
 } ieti_stats;
 
 typedef struct ieti_handle ieti_handle;

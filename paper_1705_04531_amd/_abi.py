@@ -79,6 +79,7 @@ class IetiOptions(C.Structure):
         ("coarse_dofs", C.c_int32),
         ("smoother", C.c_int32),
         ("smoother_sigma", C.c_double),
+        ("tune_cache", C.c_char_p),
     ]
 
 
@@ -103,6 +104,8 @@ class IetiStats(C.Structure):
         ("cheb_degree_coarse", C.c_int32),
         ("cheb_lower", C.c_double),
         ("saddle_omega", C.c_double),
+        ("fine_tile_staged", C.c_int32),
+        ("tune_cached", C.c_int32),
     ]
 
     def as_dict(self):

@@ -68,12 +68,13 @@ void default_options(ieti_options* o) {
 int cheb_degree_for(const ieti_options& o, int pmax) {
     if (o.cheb_degree > 0) return o.cheb_degree;
     if (pmax <= 2) return 3;
-    if (pmax == 3) return 5;
+    if (pmax == 3) return 6;
     return 4;
 }
 int cheb_degree_coarse_for(const ieti_options& o, int pmax) {
+    (void)pmax;
     if (o.cheb_degree_coarse > 0) return o.cheb_degree_coarse;
-    return pmax == 3 ? 3 : 2;
+    return 2;
 }
 double cheb_lower_for(const ieti_options& o, int pmax) {
     if (o.cheb_lower > 0) return o.cheb_lower;
@@ -1279,6 +1280,10 @@ Plan* build_plan(const ieti_patch* in, int n, const double* pv, int n_pv, const 
     pl.dim = dim;
     pl.N = n;
     pl.opt = opt;
+    if (opt.tune_cache) {
+        pl.tune_cache = opt.tune_cache;
+        pl.opt.tune_cache = pl.tune_cache.c_str();
+    }
     pl.patches.resize(n);
     int64_t off = 0;
     double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};

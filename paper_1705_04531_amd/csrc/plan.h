@@ -80,6 +80,7 @@ struct Plan {
     int dim = 2;
     int N = 0;
     ieti_options opt{};
+    std::string tune_cache;        // owned copy of opt.tune_cache (opt.tune_cache points into it)
     std::vector<Patch> patches;
     int64_t ndof_torn = 0, ndof_global = 0, n_qp = 0;
     int64_t n_lambda = 0, n_primal = 0, n_primal_vertices = 0;

@@ -25,6 +25,7 @@
 #include <map>
 #include <mutex>
 #include <thread>
+#include <cstdio>
 #include <cstring>
 #include <memory>
 #include <string>
@@ -273,6 +274,7 @@ struct Solver : SolverBase {
     int cheb_m = 2;     // Chebyshev degree per smoothing phase, finest level
     int cheb_mc = 2;    // coarse levels
     bool stage_all0 = false;   // every finest-level smoothing tile runs a staged (x window in LDS) instance
+    bool stage_fine = true;    // finest-level tiles stage their x window in LDS where it fits (autotuned)
     double cheb_hi = 1.1;
     // tensor-product smoother of the finest level (options.smoother): per mode and patch the factors of
     // the fast diagonalisation, the forward transform's scratch, the largest padded sizes
@@ -379,7 +381,7 @@ struct Solver : SolverBase {
         const int* end = smooth_only ? D.cls_end_sm : D.cls_end_all;
         int reach2d = 0;
         for (int c = 0; c <= 8; ++c) reach2d = std::max(reach2d, D.reach[c]);
-        const bool multi = l == 0 && (size_t)(TILE + 2 * reach2d) * sizeof(TX) <= STAGE_X_MAX_BYTES;
+        const bool multi = l == 0 && stage_fine && (size_t)(TILE + 2 * reach2d) * sizeof(TX) <= STAGE_X_MAX_BYTES;
         for (const auto& g : launch_groups(beg, end, multi)) {
             const int c = g[0];
             a.tiles = base + g[1];
@@ -402,7 +404,7 @@ struct Solver : SolverBase {
             if constexpr (EPI == EPI_CHEB0) {   // staged finest-level instances only (vcycle checks stage_all0)
                 launch_stencil<TC, TX, TY, EPI, true>(c, stream, a, reach, ev.first, ev.second);
             } else {
-                if (l == 0 && window_fits)
+                if (l == 0 && window_fits && stage_fine)
                     launch_stencil<TC, TX, TY, EPI, true>(c, stream, a, reach, ev.first, ev.second);
                 else
                     launch_stencil<TC, TX, TY, EPI, false>(c, stream, a, reach, ev.first, ev.second);
@@ -482,7 +484,7 @@ struct Solver : SolverBase {
             } else {
                 const int m = l == 0 ? cheb_m : cheb_mc;
                 int k1 = 1;
-                if (l == 0 && m >= 2 && stage_all0) {
+                if (l == 0 && m >= 2 && stage_all0 && stage_fine) {
                     stencil<T, T, T, EPI_CHEB0>(0, true, mode, D.coefT, nullptr, XA, B, D.vd, act, 0.0, 1);
                     std::swap(X, XA);
                     k1 = 2;
@@ -974,6 +976,7 @@ struct Solver : SolverBase {
         return ch;
     }
     double cheb_lower_scale = 1.0;
+    bool tune_cached = false;   // the autotuner's choice came from opt.tune_cache
     void set_smoother(int m, int mc, double lower_scale) {
         cheb_m = m;
         cheb_mc = mc;
@@ -984,49 +987,160 @@ struct Solver : SolverBase {
         }
         sync();
     }
-    // Times one batched Neumann solve (a seeded right-hand side, to inner_tol) per
-    // candidate smoother around the tuned table and keeps the fastest.
+    // Smoother autotuner: candidates around the tuned table (finest degree +-1, coarse degree 2/3, interval
+    // lower end x0.67/1/1.5) and the tile variant of the finest-level sweeps (x window staged in LDS or read
+    // directly), ranked by complete solves of a smooth seeded load (a batched Neumann solve for the
+    // saddle-point variant); the fastest is kept.  With opt.tune_cache the choice is looked up in /
+    // appended to that file, keyed by tune_key().
+    std::string tune_key() const {
+        const Plan& pl = *plan;
+        std::vector<std::string> shapes;
+        for (const auto& pa : pl.patches) {
+            std::string t;
+            for (int d = 0; d < pl.dim; ++d)
+                t += (d ? "," : "") + std::to_string(pa.p[d]) + "/" + std::to_string(pa.lv[0].nel[d]);
+            shapes.push_back(t);
+        }
+        std::sort(shapes.begin(), shapes.end());
+        shapes.erase(std::unique(shapes.begin(), shapes.end()), shapes.end());
+        std::string k = "d" + std::to_string(pl.dim) + ";fp" + std::to_string(pl.opt.mg_precision) + ";ls" +
+                        std::to_string(pl.opt.local_solver) + ";cd" + std::to_string(pl.opt.coarse_dofs) + ";";
+        for (size_t i = 0; i < shapes.size(); ++i) k += (i ? " " : "") + shapes[i];
+        return k;
+    }
+    // cache line: {"key": "<key>", "cheb_degree": m, "cheb_degree_coarse": mc, "cheb_lower": s, "stage": 0|1}
+    bool tune_lookup(const std::string& key, int& m, int& mc, double& sc, int& stg) const {
+        const char* path = plan->opt.tune_cache;
+        if (!path) return false;
+        FILE* fp = std::fopen(path, "r");
+        if (!fp) return false;
+        char line[4096];
+        const std::string want = "{\"key\": \"" + key + "\", ";
+        bool found = false;
+        while (std::fgets(line, sizeof line, fp)) {
+            if (std::strncmp(line, want.c_str(), want.size()) != 0) continue;
+            int a = 0, b = 0, c = 0;
+            double d = 0.0;
+            if (std::sscanf(line + want.size(), "\"cheb_degree\": %d, \"cheb_degree_coarse\": %d, \"cheb_lower\": %lf, "
+                            "\"stage\": %d}", &a, &b, &d, &c) == 4 && a >= 2 && a < KMAX && b >= 2 && b < KMAX && d > 0) {
+                m = a; mc = b; sc = d; stg = c;
+                found = true;   // the last entry for a key wins
+            }
+        }
+        std::fclose(fp);
+        return found;
+    }
+    void tune_store(const std::string& key, int m, int mc, double sc, int stg) const {
+        const char* path = plan->opt.tune_cache;
+        if (!path) return;
+        FILE* fp = std::fopen(path, "a");
+        if (!fp) return;   // the cache is an optimisation: an unwritable path is not an error
+        std::fprintf(fp, "{\"key\": \"%s\", \"cheb_degree\": %d, \"cheb_degree_coarse\": %d, \"cheb_lower\": %.17g, "
+                     "\"stage\": %d}\n", key.c_str(), m, mc, sc, stg);
+        std::fclose(fp);
+    }
     void autotune_smoother() {
         if (exact || nlev < 2 || fd_on) return;
-        std::vector<double> h(len0);
-        uint64_t x = 0x9E3779B97F4A7C15ull;
-        for (auto& v : h) {
-            x ^= x << 13; x ^= x >> 7; x ^= x << 17;
-            v = (double)(x >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+        const std::string key = tune_key();
+        int cm = 0, cmc = 0, cstg = 1;
+        double csc = 1.0;
+        if (tune_lookup(key, cm, cmc, csc, cstg)) {
+            stage_fine = cstg != 0;
+            set_smoother(cm, cmc, csc);
+            tune_cached = true;
+            return;
         }
-        HIPCHECK(hipMemcpyAsync(e64, h.data(), len0 * sizeof(double), hipMemcpyHostToDevice, stream));
-        sync();
-        hipEvent_t e0, e1;
-        HIPCHECK(hipEventCreate(&e0));
-        HIPCHECK(hipEventCreate(&e1));
+        const Plan& pl = *plan;
         const int m0 = cheb_m, mc0 = cheb_mc;
-        int best_m = m0, best_mc = mc0;
-        double best_s = 1.0, best_ms = 1e300;
+        struct Cand {
+            double ms;
+            int m, mc, stg;
+            double sc;
+        };
+        std::vector<Cand> cands;
         const double scales[3] = {0.67, 1.0, 1.5};
-        for (int m = std::max(2, m0 - 1); m <= std::min(KMAX - 1, m0 + 1); ++m)
-            for (int mc = 2; mc <= 3; ++mc)
-                for (double sc : scales) {
-                    set_smoother(m, mc, sc);
-                    double ms = 1e300;
-                    for (int rep = 0; rep < 2; ++rep) {
-                        HIPCHECK(hipEventRecord(e0, stream));
-                        fcg(e64, plan->opt.inner_tol, plan->opt.inner_max_it);
-                        HIPCHECK(hipEventRecord(e1, stream));
-                        HIPCHECK(hipEventSynchronize(e1));
-                        float t = 0.f;
-                        HIPCHECK(hipEventElapsedTime(&t, e0, e1));
-                        ms = std::min(ms, (double)t);
+        for (int stg = 1; stg >= 0; --stg)
+            for (int m = std::max(2, m0 - 1); m <= std::min(KMAX - 1, m0 + 1); ++m)
+                for (int mc = 2; mc <= 3; ++mc)
+                    for (double sc : scales) cands.push_back({1e300, m, mc, stg, sc});
+        auto apply = [&](const Cand& c) {
+            stage_fine = c.stg != 0;
+            set_smoother(c.m, c.mc, c.sc);
+        };
+        if (!saddle) {
+            // complete solves with a smooth seeded load f = sum_{k_d <= 3} c_k prod_d sin(k_d pi x_d),
+            // c_k uniform in [-1, 1]: one per candidate, then two more for the best four
+            const int nk = pl.dim == 2 ? 9 : 27;
+            std::vector<double> coef(nk);
+            uint64_t y = 0xC2B2AE3D27D4EB4Full;
+            for (auto& v : coef) {
+                y ^= y << 13; y ^= y >> 7; y ^= y << 17;
+                v = 2.0 * (double)(y >> 11) * (1.0 / 9007199254740992.0) - 1.0;
+            }
+            std::vector<double> hf(pl.n_qp);
+            int64_t q = 0;
+            for (const auto& pa : pl.patches)
+                for (int64_t j = 0; j < pa.n_qp; ++j, ++q) {
+                    const double* x = &pa.qpx[(size_t)j * pl.dim];
+                    double v = 0.0;
+                    for (int t = 0; t < nk; ++t) {
+                        double term = coef[t];
+                        int r = t;
+                        for (int d = 0; d < pl.dim; ++d) {
+                            term *= std::sin((double)(r % 3 + 1) * M_PI * x[d]);
+                            r /= 3;
+                        }
+                        v += term;
                     }
-                    if (ms < best_ms) {
-                        best_ms = ms;
-                        best_m = m;
-                        best_mc = mc;
-                        best_s = sc;
-                    }
+                    hf[q] = v;
                 }
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
-        set_smoother(best_m, best_mc, best_s);
+            double* fq = arena.upload(hf, stream);
+            double* uq = arena.alloc<double>(pl.ndof_torn, stream);
+            sync();
+            auto timed = [&](const Cand& c) {
+                apply(c);
+                ieti_stats st{};
+                solve(fq, uq, &st);
+                return st.time_total_ms;
+            };
+            timed(cands.front());   // warm-up
+            for (auto& c : cands) c.ms = timed(c);
+            std::stable_sort(cands.begin(), cands.end(), [](const Cand& a, const Cand& b) { return a.ms < b.ms; });
+            for (int i = 0; i < std::min<int>(4, (int)cands.size()); ++i)
+                for (int rep = 0; rep < 2; ++rep) cands[i].ms = std::min(cands[i].ms, timed(cands[i]));
+        } else {
+            // saddle-point iteration (omega is estimated after this choice): one batched Neumann solve of a
+            // seeded right-hand side per candidate, best of three
+            std::vector<double> h(len0);
+            uint64_t x = 0x9E3779B97F4A7C15ull;
+            for (auto& v : h) {
+                x ^= x << 13; x ^= x >> 7; x ^= x << 17;
+                v = (double)(x >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+            }
+            HIPCHECK(hipMemcpyAsync(e64, h.data(), len0 * sizeof(double), hipMemcpyHostToDevice, stream));
+            sync();
+            hipEvent_t e0, e1;
+            HIPCHECK(hipEventCreate(&e0));
+            HIPCHECK(hipEventCreate(&e1));
+            for (auto& c : cands) {
+                apply(c);
+                for (int rep = 0; rep < 3; ++rep) {
+                    HIPCHECK(hipEventRecord(e0, stream));
+                    fcg(e64, pl.opt.inner_tol, pl.opt.inner_max_it);
+                    HIPCHECK(hipEventRecord(e1, stream));
+                    HIPCHECK(hipEventSynchronize(e1));
+                    float t = 0.f;
+                    HIPCHECK(hipEventElapsedTime(&t, e0, e1));
+                    c.ms = std::min(c.ms, (double)t);
+                }
+            }
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+        }
+        const Cand best = *std::min_element(cands.begin(), cands.end(),
+                                            [](const Cand& a, const Cand& b) { return a.ms < b.ms; });
+        apply(best);
+        tune_store(key, best.m, best.mc, best.sc, best.stg);
     }
     // Sinv = S^{-1} (n x n SPD, host row-major) by k_spd_* on the device, stored by columns
     void spd_inverse(const std::vector<double>& S, int64_t n) {
@@ -1747,6 +1861,8 @@ int Solver<T>::solve(const double* f_qp, double* u_out, ieti_stats* stp) {
     st.cheb_degree = (exact && prec_exact) || fd_on ? 0 : cheb_m;
     st.cheb_degree_coarse = exact && prec_exact ? 0 : cheb_mc;
     st.cheb_lower = cheb_lower_scale;
+    st.fine_tile_staged = stage_fine && !fd_on ? 1 : 0;
+    st.tune_cached = tune_cached ? 1 : 0;
     DevLevel& D0 = lev[0];
     sync();
     auto t0 = clk::now();
@@ -2232,6 +2348,7 @@ struct SrvReq {
 
 struct ieti_server {
     ieti_options opt{};
+    std::string tune_cache;   // owned copy of opt.tune_cache
     int slots = 1;
     size_t budget = 0;      // 0: unlimited
     size_t in_use = 0;

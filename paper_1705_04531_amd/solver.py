@@ -20,6 +20,8 @@ def default_options(**overrides) -> IetiOptions:
     for k, v in overrides.items():
         if not hasattr(opt, k):
             raise KeyError(k)
+        if k == "tune_cache" and isinstance(v, str):
+            v = v.encode()
         setattr(opt, k, v)
     return opt
 

@@ -219,3 +219,22 @@ def test_tensor_smoother_3d_matches_oracle(require_gpu, name, make, variant, sol
     print(f"{name} 3D tensor smoother {variant} prec={prec}: err={err:.3e} outer={st['outer_iterations']} "
           f"inner={st['inner_iterations_mean']:.2f}", flush=True)
     assert err <= 1e-8
+
+
+def test_autotune_cache(require_gpu, tmp_path):
+    """The autotuner's choice (smoother degrees, interval, finest-level tile variant) goes to the cache file
+    on a miss and comes back from it on the next setup with the same key; both solves match the oracle."""
+    wl = CASES_2D[2][1]()
+    u_ref, lay, _ = oracle_solution(wl)
+    cache = str(tmp_path / "tune.jsonl")
+    u1, st1 = run_gpu(wl, tol=1e-10, autotune=1, tune_cache=cache)
+    lines = open(cache).read().splitlines()
+    assert len(lines) == 1 and '"stage": ' in lines[0]
+    u2, st2 = run_gpu(wl, tol=1e-10, autotune=1, tune_cache=cache)
+    assert st1["tune_cached"] == 0 and st2["tune_cached"] == 1
+    for k in ("cheb_degree", "cheb_degree_coarse", "cheb_lower", "fine_tile_staged"):
+        assert st1[k] == st2[k], k
+    assert len(open(cache).read().splitlines()) == 1
+    for u in (u1, u2):
+        assert rel_err(wl, u, u_ref, lay) <= 1e-8
+    print(f"autotune cache: {lines[0]}", flush=True)
