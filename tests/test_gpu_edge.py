@@ -1,0 +1,43 @@
+"""Degenerate and ragged cases on the GPU against the oracle: a single patch (no interface, no
+multipliers, no primal unknowns), a zero load, a ragged multigrid hierarchy (patches whose odd element
+counts stop the coarsening at the finest level next to patches with three levels), degree-1 patches."""
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_util import oracle_solution, rel_err, run_gpu, with_sine_rhs
+
+pytestmark = pytest.mark.gpu
+
+VARIANTS = [("mg", {}), ("exact_mg", {"local_solver": 2}), ("mg_saddle", {"local_solver": 3}),
+            ("tensor", {"smoother": 1})]
+CASES = [
+    ("single_patch", lambda: with_sine_rhs(W.deformed_square((1, 1), 3, 16, seed=0, name="single"), 2)),
+    ("ragged_levels", lambda: with_sine_rhs(W.deformed_square((2, 2), 2, [[7, 16], [16, 9]], seed=0,
+                                                              name="ragged"), 3)),
+    ("degree1", lambda: with_sine_rhs(W.deformed_square((2, 2), 1, 16, seed=0, name="p1"), 4)),
+    ("single_cube", lambda: W.unit_cube((1, 1, 1), 2, 6, name="single_cube")),
+]
+
+
+@pytest.mark.parametrize("variant,opts", VARIANTS, ids=[v[0] for v in VARIANTS])
+@pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
+def test_edge_case_matches_oracle(require_gpu, name, make, variant, opts):
+    wl = make()
+    if wl.dim == 3 and variant == "exact_mg":
+        pytest.skip("exact local solves are built for 2D patches")
+    u_ref, lay, _ = oracle_solution(wl)
+    u, st = run_gpu(wl, tol=1e-10, coarse_dofs=0, **opts)
+    err = rel_err(wl, u, u_ref, lay)
+    print(f"{name} {variant}: err={err:.3e} outer={st['outer_iterations']} n_lambda={st['n_lambda']}", flush=True)
+    assert np.all(np.isfinite(u))
+    assert err <= 1e-8
+
+
+@pytest.mark.parametrize("variant,opts", VARIANTS, ids=[v[0] for v in VARIANTS])
+def test_zero_load_gives_zero(require_gpu, variant, opts):
+    wl = W.deformed_square((2, 2), 2, 16, seed=0, name="zero_load")
+    wl.f = lambda x: np.zeros(x.shape[0])
+    u, st = run_gpu(wl, coarse_dofs=0, **opts)
+    print(f"zero load {variant}: max|u|={np.abs(u).max():.3e} breakdown={st['breakdown']}", flush=True)
+    assert np.all(np.isfinite(u)) and np.abs(u).max() == 0.0
