@@ -152,6 +152,9 @@ def main():
     ap.add_argument("--serve", action="store_true", help="serving benchmark instead of the solve benchmark")
     ap.add_argument("--requests", type=int, default=64)
     ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--local-solver", choices=["mg", "exact_mg", "mg_saddle"], default="mg",
+                    help="variant of the measured solver: mg is the configuration (MG-MG); exact_mg (D-MG) and "
+                         "mg_saddle (MG-MG-S) profile the other variants on the same workload")
     ap.add_argument("--smoother", choices=["chebyshev", "tensor"], default="chebyshev",
                     help="finest-level smoother of the measured solver; the configuration names Chebyshev (default), "
                          "tensor profiles the p-robust variant on the same workload")
@@ -186,8 +189,10 @@ def main():
     # the configuration as named, Chebyshev degrees from the library's table (measured per spline degree;
     # the setup-time autotuner ranks candidates on a seeded load, whose best can differ from this load's)
     tensor = args.smoother == "tensor"
-    solver = Solver(wl.patches, options_for(wl, smoother=_abi.IETI_SMOOTHER_TENSOR) if tensor
-                    else options_for(wl))
+    variant = {"mg": _abi.IETI_LOCAL_MG, "exact_mg": _abi.IETI_LOCAL_EXACT_MG,
+               "mg_saddle": _abi.IETI_LOCAL_MG_SADDLE}[args.local_solver]
+    solver = Solver(wl.patches, options_for(wl, local_solver=variant,
+                                            **({"smoother": _abi.IETI_SMOOTHER_TENSOR} if tensor else {})))
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     x = solver.quadrature(device=False)
@@ -325,6 +330,7 @@ def main():
             "time_rhs_ms": round(st["time_rhs_ms"], 3),
             "time_recovery_ms": round(st["time_recovery_ms"], 3),
             "setup_s": round(setup_s, 3),
+            "local_solver": args.local_solver,
             "smoother": {"finest": args.smoother, "autotuned": False, "fine_tile_staged": st["fine_tile_staged"],
                          "cheb_degree": st["cheb_degree"],
                          "cheb_degree_coarse": st["cheb_degree_coarse"],
@@ -338,7 +344,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None if tensor else counter_traffic(),
+            "traffic": None if (tensor or args.local_solver != "mg") else counter_traffic(),
             "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "launches": dom["launches"],
             "avg_us": round(dom["ms"] / max(dom["launches"], 1) * 1e3, 3),

@@ -1718,6 +1718,120 @@ __global__ __launch_bounds__(BAND_THREADS) void k_band_solve(const PatchLev* L, 
     for (int i = threadIdx.x; i < n; i += blockDim.x) x[P.voff + i] = xs[i];
 }
 
+// The same solve for band widths b <= 256 with the next block's factor data in flight: 1024 threads, 16
+// per block row; while block r is reduced and its diagonal block applied, every thread already holds its
+// share of block r + 1 (off-diagonal row: b / 16 values, inverse diagonal: 4) in registers, so each block
+// step waits on LDS and barriers only, not on memory.
+constexpr int BAND_PF_THREADS = 1024;
+constexpr int BAND_PF_J = 16;   // off-diagonal values per thread and block
+
+__device__ __forceinline__ double sum16(double v) {
+    v += __shfl_xor(v, 1, WAVE);
+    v += __shfl_xor(v, 2, WAVE);
+    v += __shfl_xor(v, 4, WAVE);
+    v += __shfl_xor(v, 8, WAVE);
+    return v;
+}
+
+__global__ __launch_bounds__(BAND_PF_THREADS) void k_band_solve_pf(const PatchLev* L, const int64_t* band_off,
+                                                                 const int32_t* band_b, const double* band, int mode,
+                                                                 const double* rhs, double* x, const int* active) {
+    extern __shared__ double bs_lds[];
+    const int k = blockIdx.x;
+    if (active && !active[k]) return;
+    const PatchLev& P = L[k];
+    const int n = (int)P.n;
+    const int b = band_b[k];
+    const int nblk = (n + BNB - 1) / BNB;
+    const int64_t bsz = (int64_t)BNB * (2 * b + BNB);
+    const double* F = band + band_off[2 * k + mode];
+    double* xs = bs_lds + b;                    // xs[-b .. nblk*BNB + b)
+    double* t = bs_lds + 2 * b + nblk * BNB;    // BNB scratch
+    const int tot = 2 * b + nblk * BNB;
+    for (int i = threadIdx.x; i < tot; i += blockDim.x) {
+        const int j = i - b;
+        bs_lds[i] = (j >= 0 && j < n) ? rhs[P.voff + j] : 0.0;
+    }
+    __syncthreads();
+    const int ii = threadIdx.x >> 4, l16 = threadIdx.x & 15;
+    double rc[BAND_PF_J], rn[BAND_PF_J], ic[4], in4[4];
+    // forward: L y = rhs; block r needs row ii of L_off and of inv(L_diag)
+    auto load_fwd = [&](int r) {
+        const double* blk = F + (int64_t)r * bsz;
+        const double* row = blk + (int64_t)ii * b;
+#pragma unroll
+        for (int j = 0; j < BAND_PF_J; ++j) {
+            const int c = l16 + 16 * j;
+            rn[j] = c < b ? row[c] : 0.0;
+        }
+        const double* inv = blk + 2 * (int64_t)BNB * b + (int64_t)ii * BNB;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) in4[j] = inv[l16 + 16 * j];
+    };
+    if (nblk > 0) load_fwd(0);
+    for (int r = 0; r < nblk; ++r) {
+#pragma unroll
+        for (int j = 0; j < BAND_PF_J; ++j) rc[j] = rn[j];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) ic[j] = in4[j];
+        if (r + 1 < nblk) load_fwd(r + 1);
+        const double* xw = xs + r * BNB - b;
+        double acc = 0.0;
+#pragma unroll
+        for (int j = 0; j < BAND_PF_J; ++j) {
+            const int c = l16 + 16 * j;
+            if (c < b) acc += rc[j] * xw[c];
+        }
+        acc = sum16(acc);
+        if (l16 == 0) t[ii] = xs[r * BNB + ii] - acc;
+        __syncthreads();
+        double a2 = 0.0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) a2 += ic[j] * t[l16 + 16 * j];
+        a2 = sum16(a2);
+        if (l16 == 0) xs[r * BNB + ii] = a2;
+        __syncthreads();
+    }
+    // backward: L^T x = y; block r needs row ii of U_off and column ii of inv(L_diag)
+    auto load_bwd = [&](int r) {
+        const double* blk = F + (int64_t)r * bsz;
+        const double* row = blk + (int64_t)BNB * b + (int64_t)ii * b;
+#pragma unroll
+        for (int j = 0; j < BAND_PF_J; ++j) {
+            const int c = l16 + 16 * j;
+            rn[j] = c < b ? row[c] : 0.0;
+        }
+        const double* inv = blk + 2 * (int64_t)BNB * b;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) in4[j] = inv[(int64_t)(l16 + 16 * j) * BNB + ii];
+    };
+    if (nblk > 0) load_bwd(nblk - 1);
+    for (int r = nblk - 1; r >= 0; --r) {
+#pragma unroll
+        for (int j = 0; j < BAND_PF_J; ++j) rc[j] = rn[j];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) ic[j] = in4[j];
+        if (r > 0) load_bwd(r - 1);
+        const double* xw = xs + (r + 1) * BNB;
+        double acc = 0.0;
+#pragma unroll
+        for (int j = 0; j < BAND_PF_J; ++j) {
+            const int c = l16 + 16 * j;
+            if (c < b) acc += rc[j] * xw[c];
+        }
+        acc = sum16(acc);
+        if (l16 == 0) t[ii] = xs[r * BNB + ii] - acc;
+        __syncthreads();
+        double a2 = 0.0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) a2 += ic[j] * t[l16 + 16 * j];
+        a2 = sum16(a2);
+        if (l16 == 0) xs[r * BNB + ii] = a2;
+        __syncthreads();
+    }
+    for (int i = threadIdx.x; i < n; i += blockDim.x) x[P.voff + i] = xs[i];
+}
+
 // ------------------------------------------------------------------ dense SPD inverse on matrix cores
 //
 // S^{-1} of the assembled primal Schur complement (n x n, FP64) through the

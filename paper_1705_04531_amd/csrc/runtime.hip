@@ -329,6 +329,7 @@ struct Solver : SolverBase {
     int32_t* band_b = nullptr;
     double* band = nullptr;
     size_t band_lds = 0;
+    int band_bmax = 0;   // widest band of the exact local solves (the prefetching solve takes b <= 256)
     // fused coarse V-cycle: one work-group per patch for levels >= fuse_l0 (nlev: none)
     int fuse_l0 = 0;
     bool fuse_stage = false;
@@ -672,8 +673,12 @@ struct Solver : SolverBase {
     }
 
     void band_solve(int mode, const double* rhs, double* x) {
-        hipLaunchKernelGGL(k_band_solve, dim3(N), dim3(BAND_THREADS), band_lds, stream, lev[0].L, band_off, band_b,
-                           band, mode, rhs, x, nullptr);
+        if (band_bmax <= 16 * BAND_PF_J)
+            hipLaunchKernelGGL(k_band_solve_pf, dim3(N), dim3(BAND_PF_THREADS), band_lds, stream, lev[0].L, band_off,
+                               band_b, band, mode, rhs, x, nullptr);
+        else
+            hipLaunchKernelGGL(k_band_solve, dim3(N), dim3(BAND_THREADS), band_lds, stream, lev[0].L, band_off,
+                               band_b, band, mode, rhs, x, nullptr);
         check_launch();
     }
 
@@ -1538,6 +1543,7 @@ void Solver<T>::setup() {
         for (int k = 0; k < N; ++k) {
             const Patch& pa = pl.patches[k];
             bw[k] = (int32_t)pa.band_b;
+            band_bmax = std::max(band_bmax, (int)pa.band_b);
             for (int m = 0; m < 2; ++m) {
                 offs[2 * k + m] = tot;
                 tot += (int64_t)pa.band[m].size();
@@ -1554,6 +1560,8 @@ void Solver<T>::setup() {
         band_off = arena.upload(offs, st);
         band_b = arena.upload(bw, st);
         HIPCHECK(hipFuncSetAttribute((const void*)k_band_solve, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)band_lds));
+        HIPCHECK(hipFuncSetAttribute((const void*)k_band_solve_pf, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)band_lds));
         HIPCHECK(hipStreamSynchronize(st));
     }
