@@ -443,8 +443,9 @@ struct Solver : SolverBase {
             check_launch();
             return;
         }
-        FdArgs a{lev[0].L, fd_info[mode], fd_U, fd_lam, fd_z, act, mode, N, fd_p0max / 16, nullptr};
-        const dim3 grid(8 * ((N + 7) / 8) * (fd_p0max / 16));
+        const int ncp = (fd_p0max / 16 + 1) / 2;
+        FdArgs a{lev[0].L, fd_info[mode], fd_U, fd_lam, fd_z, act, mode, N, ncp, nullptr};
+        const dim3 grid(8 * ((N + 7) / 8) * ncp);
         hipLaunchKernelGGL(k_fd_fwd<T>, grid, dim3(FD_THREADS), fd_lds, stream, a, r);
         check_launch();
         if (set)

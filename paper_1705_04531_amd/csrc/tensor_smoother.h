@@ -12,13 +12,12 @@ namespace ieti {
 // patch as the M1 x M0 matrix R[i1][i0] (i0 fastest, as stored):
 //   forward:   Z = (U_1^T R U_0) ./ (lambda_1[b] + lambda_0[a] + c)     (P1 x P0, into scratch)
 //   backward:  x[i1][i0] (+)= tau (U_1 Z U_0^T)[i1][i0] on unmasked coefficients
-// Both kernels take one work-group per (16-column block, patch), the work-groups of a patch on one XCD
-// (fd_block) so that they share its L2: the forward one forms the column block W = R U_0[:, blk] and then
-// U_1^T W, the backward one T = Z U_0[blk, :]^T and then U_1 T.  The operands are staged in LDS (U_1 in
-// the first matrix's space once the first product is done); each wave runs the block products of one
-// 16-row block on v_mfma_f64_16x16x4f64 in FP64 with two accumulation chains (T = float converts on load
-// and store).  Padded sizes up to 128.  Patches without smoother data (P0 = 0) and inactive patches
-// return.
+// Both kernels take one work-group per (pair of 16-column blocks, patch), the work-groups of a patch on
+// one XCD (fd_block) so that they share its L2: the forward one forms the column blocks W = R U_0[:, blk]
+// and then U_1^T W, the backward one T = Z U_0[blk, :]^T and then U_1 T.  The operands are staged in LDS
+// (U_1 in the first matrix's space once the first product is done); each wave runs the block products of
+// one 16-row block for both columns on v_mfma_f64_16x16x4f64 in FP64 (T = float converts on load and
+// store).  Patches without smoother data (P0 = 0) and inactive patches return.
 
 constexpr int FD_THREADS = 512;
 
@@ -39,14 +38,15 @@ struct FdArgs {
     const int* active;
     int mode;
     int N;                 // patches
-    int ncb;               // 2D: column blocks per patch in the grid (largest P0 / 16)
+    int ncb;               // 2D: pairs of column blocks per patch in the grid (largest P0 / 32, rounded up)
     double* z2;            // 3D: second scratch buffer (same offsets as z)
 };
 
-// LDS doubles of either kernel for the largest padded sizes
+// LDS doubles of either kernel for the largest padded sizes: the first operand (P1 x ld), the pair of
+// products (P1 x 33) and the pair of U_0 blocks (P0 x 33)
 __host__ __device__ inline size_t fd_lds_words(int p0max, int p1max) {
     const int ld = (p0max > p1max ? p0max : p1max) + 1;
-    return (size_t)p1max * ld + (size_t)p1max * 17 + (size_t)p0max * 17;
+    return (size_t)p1max * ld + (size_t)33 * (p1max + p0max);
 }
 
 // dst[i * ld + j] = get(i, j) for i < rows, j < cols (cols a multiple of 16): thread -> (row tid / 16 of a
@@ -68,129 +68,130 @@ __device__ __forceinline__ void fd_stage(double* dst, int ld, int rows, int cols
     }
 }
 
-// XCD-aware work-group -> (patch, 16-column block): consecutive work-groups go to consecutive XCDs, so
-// the work-groups of patch k are all placed on XCD k mod 8 and share its L2 for the patch's operands.
-// Grid: 8 * ceil(N / 8) * ncb one-dimensional; false for the unused tail.
-__device__ __forceinline__ bool fd_block(int N, int ncb, int& k, int& cb) {
+// XCD-aware work-group -> (patch, pair of 16-column blocks): consecutive work-groups go to consecutive
+// XCDs, so the work-groups of patch k are all placed on XCD k mod 8 and share its L2 for the patch's
+// operands.  Grid: 8 * ceil(N / 8) * ncp one-dimensional (ncp pairs per patch); false for the unused tail.
+__device__ __forceinline__ bool fd_block(int N, int ncp, int& k, int& cp) {
     const int L = blockIdx.x, x = L & 7, s = L >> 3;
-    k = (s / ncb) * 8 + x;
-    cb = s % ncb;
+    k = (s / ncp) * 8 + x;
+    cp = s % ncp;
     return k < N;
 }
 
+// forward: column blocks 2 cp and 2 cp + 1 (if it exists) of Z; the shared R fragment feeds two
+// accumulation chains
 template <typename T>
 __global__ __launch_bounds__(FD_THREADS) void k_fd_fwd(FdArgs a, const T* __restrict__ r) {
-    int k, cb;
-    if (!fd_block(a.N, a.ncb, k, cb)) return;
+    int k, cp;
+    if (!fd_block(a.N, a.ncb, k, cp)) return;
     const FdInfo f = a.info[k];
     if (f.P0 == 0 || (a.active && !a.active[k])) return;
-    if (cb * 16 >= f.P0) return;
+    const int P0 = f.P0, P1 = f.P1, ncb = P0 / 16, cb = 2 * cp;
+    if (cb >= ncb) return;
+    const bool two = cb + 1 < ncb;
     const PatchLev& P = a.L[k];
-    const int M0 = P.M[0], M1 = P.M[1], P0 = f.P0, P1 = f.P1, ld = (P0 > P1 ? P0 : P1) + 1;
+    const int M0 = P.M[0], M1 = P.M[1], ld = (P0 > P1 ? P0 : P1) + 1;
     extern __shared__ double fd_sm[];
     double* Rg = fd_sm;                       // R (P1 x P0), then U_1 (P1 x P1); leading dimension ld
-    double* Wb = fd_sm + (size_t)P1 * ld;     // W (P1 x 16), ld 17
-    double* Ub = Wb + (size_t)P1 * 17;        // U_0[:, block cb] (P0 x 16), ld 17
+    double* Wb = fd_sm + (size_t)P1 * ld;     // W (P1 x 32), ld 33
+    double* Ub = Wb + (size_t)P1 * 33;        // U_0[:, blocks cb, cb + 1] (P0 x 32), ld 33
     const double* U0 = a.U + f.u0;
     const double* U1 = a.U + f.u1;
-    const int wv = threadIdx.x / WAVE, l = threadIdx.x & (WAVE - 1);
     const int mode = a.mode;
     fd_stage(Rg, ld, P1, P0, [&](int i1, int i0) -> double {
         return (i0 < M0 && i1 < M1 && !masked(P, mode, i0, i1, 0)) ? (double)r[P.voff + i0 + (int64_t)M0 * i1] : 0.0;
     });
-    fd_stage(Ub, 17, P0, 16, [&](int i, int j) -> double { return U0[(int64_t)i * P0 + cb * 16 + j]; });
+    fd_stage(Ub, 33, P0, two ? 32 : 16, [&](int i, int j) -> double { return U0[(int64_t)i * P0 + cb * 16 + j]; });
     __syncthreads();
-    for (int w = wv; w < P1 / 16; w += FD_THREADS / WAVE) {   // W[block w] = R[block w, :] U_0[:, block cb]
-        mf_d4 c = {0.0, 0.0, 0.0, 0.0}, c1 = c;
-        int kb = 0;
-        for (; kb + 1 < P0 / 16; kb += 2) {   // two independent accumulation chains
-            c = mf_block<false>(Rg + (size_t)w * 16 * ld + kb * 16, ld, Ub + kb * 16 * 17, 17, c, 1.0);
-            c1 = mf_block<false>(Rg + (size_t)w * 16 * ld + kb * 16 + 16, ld, Ub + (kb + 1) * 16 * 17, 17, c1, 1.0);
+    const int wv = threadIdx.x / WAVE, l = threadIdx.x & (WAVE - 1);
+    for (int w = wv; w < P1 / 16; w += FD_THREADS / WAVE) {   // W[block w] = R[block w, :] U_0[:, pair]
+        mf_d4 c0 = {0.0, 0.0, 0.0, 0.0}, c1 = c0;
+        for (int kb = 0; kb < P0 / 16; ++kb) {
+            c0 = mf_block<false>(Rg + (size_t)w * 16 * ld + kb * 16, ld, Ub + kb * 16 * 33, 33, c0, 1.0);
+            if (two) c1 = mf_block<false>(Rg + (size_t)w * 16 * ld + kb * 16, ld, Ub + kb * 16 * 33 + 16, 33, c1, 1.0);
         }
-        if (kb < P0 / 16) c = mf_block<false>(Rg + (size_t)w * 16 * ld + kb * 16, ld, Ub + kb * 16 * 17, 17, c, 1.0);
-        c += c1;
-        mf_store(Wb + w * 16 * 17, 17, c);
+        mf_store(Wb + w * 16 * 33, 33, c0);
+        if (two) mf_store(Wb + w * 16 * 33 + 16, 33, c1);
     }
     __syncthreads();
     fd_stage(Rg, ld, P1, P1, [&](int i, int j) -> double { return U1[(int64_t)i * P1 + j]; });
     __syncthreads();
     const double* l0 = a.lam + f.l0;
     const double* l1 = a.lam + f.l1;
-    const int ac = cb * 16 + (l & 15);
-    for (int w = wv; w < P1 / 16; w += FD_THREADS / WAVE) {   // Z[block w, block cb] = U_1[:, block w]^T W, scaled
-        mf_d4 c = {0.0, 0.0, 0.0, 0.0}, c1 = c;
-        int kb = 0;
-        for (; kb + 1 < P1 / 16; kb += 2) {
-            c = mf_block<true>(Rg + (size_t)kb * 16 * ld + w * 16, ld, Wb + kb * 16 * 17, 17, c, 1.0);
-            c1 = mf_block<true>(Rg + (size_t)(kb + 1) * 16 * ld + w * 16, ld, Wb + (kb + 1) * 16 * 17, 17, c1, 1.0);
+    for (int w = wv; w < P1 / 16; w += FD_THREADS / WAVE) {   // Z[block w, pair] = U_1[:, block w]^T W, scaled
+        mf_d4 c0 = {0.0, 0.0, 0.0, 0.0}, c1 = c0;
+        for (int kb = 0; kb < P1 / 16; ++kb) {
+            c0 = mf_block<true>(Rg + (size_t)kb * 16 * ld + w * 16, ld, Wb + kb * 16 * 33, 33, c0, 1.0);
+            if (two) c1 = mf_block<true>(Rg + (size_t)kb * 16 * ld + w * 16, ld, Wb + kb * 16 * 33 + 16, 33, c1, 1.0);
         }
-        if (kb < P1 / 16) c = mf_block<true>(Rg + (size_t)kb * 16 * ld + w * 16, ld, Wb + kb * 16 * 17, 17, c, 1.0);
-        c += c1;
+        const int a0 = cb * 16 + (l & 15), a1 = a0 + 16;
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) {
-            const int b = w * 16 + (l >> 4) + 4 * rr;
-            a.z[f.zoff + (int64_t)b * P0 + ac] = c[rr] / (l1[b] + l0[ac] + f.shift);
+            const int bb = w * 16 + (l >> 4) + 4 * rr;
+            a.z[f.zoff + (int64_t)bb * P0 + a0] = c0[rr] / (l1[bb] + l0[a0] + f.shift);
+            if (two) a.z[f.zoff + (int64_t)bb * P0 + a1] = c1[rr] / (l1[bb] + l0[a1] + f.shift);
         }
     }
 }
 
-// SET: x = tau y (masked coefficients 0); otherwise x += tau y
+// backward, column blocks 2 cp and 2 cp + 1 of x.  SET: x = tau y (masked coefficients 0); otherwise
+// x += tau y
 template <typename T, bool SET>
 __global__ __launch_bounds__(FD_THREADS) void k_fd_bwd(FdArgs a, T* __restrict__ x) {
-    int k, jc;
-    if (!fd_block(a.N, a.ncb, k, jc)) return;
+    int k, cp;
+    if (!fd_block(a.N, a.ncb, k, cp)) return;
     const FdInfo f = a.info[k];
     if (f.P0 == 0 || (a.active && !a.active[k])) return;
     const PatchLev& P = a.L[k];
-    const int M0 = P.M[0], M1 = P.M[1], P0 = f.P0, P1 = f.P1, ld = (P0 > P1 ? P0 : P1) + 1;
+    const int M0 = P.M[0], M1 = P.M[1], P0 = f.P0, P1 = f.P1, ld = (P0 > P1 ? P0 : P1) + 1, jc = 2 * cp;
     if (jc * 16 >= M0) return;
+    const bool two = (jc + 1) * 16 < M0;
     extern __shared__ double fd_sm[];
     double* Zg = fd_sm;                       // Z (P1 x P0), then U_1 (P1 x P1); leading dimension ld
-    double* Tb = fd_sm + (size_t)P1 * ld;     // T (P1 x 16), ld 17
-    double* Ub = Tb + (size_t)P1 * 17;        // U_0[block jc, :]^T (P0 x 16), ld 17
+    double* Tb = fd_sm + (size_t)P1 * ld;     // T (P1 x 32), ld 33
+    double* Ub = Tb + (size_t)P1 * 33;        // U_0[blocks jc, jc + 1, :]^T (P0 x 32), ld 33
     const double* U0 = a.U + f.u0;
     const double* U1 = a.U + f.u1;
     const double* Z = a.z + f.zoff;
     const int wv = threadIdx.x / WAVE, l = threadIdx.x & (WAVE - 1);
     fd_stage(Zg, ld, P1, P0, [&](int i, int j) -> double { return Z[(int64_t)i * P0 + j]; });
-    fd_stage(Ub, 17, P0, 16, [&](int i, int j) -> double { return U0[(int64_t)(jc * 16 + j) * P0 + i]; });
+    fd_stage(Ub, 33, P0, two ? 32 : 16, [&](int i, int j) -> double { return U0[(int64_t)(jc * 16 + j) * P0 + i]; });
     __syncthreads();
-    for (int w = wv; w < P1 / 16; w += FD_THREADS / WAVE) {   // T[block w] = Z[block w, :] U_0[block jc, :]^T
-        mf_d4 c = {0.0, 0.0, 0.0, 0.0}, c1 = c;
-        int kb = 0;
-        for (; kb + 1 < P0 / 16; kb += 2) {
-            c = mf_block<false>(Zg + (size_t)w * 16 * ld + kb * 16, ld, Ub + kb * 16 * 17, 17, c, 1.0);
-            c1 = mf_block<false>(Zg + (size_t)w * 16 * ld + kb * 16 + 16, ld, Ub + (kb + 1) * 16 * 17, 17, c1, 1.0);
+    for (int w = wv; w < P1 / 16; w += FD_THREADS / WAVE) {   // T[block w] = Z[block w, :] U_0[pair, :]^T
+        mf_d4 c0 = {0.0, 0.0, 0.0, 0.0}, c1 = c0;
+        for (int kb = 0; kb < P0 / 16; ++kb) {
+            c0 = mf_block<false>(Zg + (size_t)w * 16 * ld + kb * 16, ld, Ub + kb * 16 * 33, 33, c0, 1.0);
+            if (two) c1 = mf_block<false>(Zg + (size_t)w * 16 * ld + kb * 16, ld, Ub + kb * 16 * 33 + 16, 33, c1, 1.0);
         }
-        if (kb < P0 / 16) c = mf_block<false>(Zg + (size_t)w * 16 * ld + kb * 16, ld, Ub + kb * 16 * 17, 17, c, 1.0);
-        c += c1;
-        mf_store(Tb + w * 16 * 17, 17, c);
+        mf_store(Tb + w * 16 * 33, 33, c0);
+        if (two) mf_store(Tb + w * 16 * 33 + 16, 33, c1);
     }
     __syncthreads();
     fd_stage(Zg, ld, P1, P1, [&](int i, int j) -> double { return U1[(int64_t)i * P1 + j]; });
     __syncthreads();
-    for (int w = wv; w < P1 / 16; w += FD_THREADS / WAVE) {   // Y[block w, block jc] = U_1[block w, :] T
-        mf_d4 c = {0.0, 0.0, 0.0, 0.0}, c1 = c;
-        int kb = 0;
-        for (; kb + 1 < P1 / 16; kb += 2) {
-            c = mf_block<false>(Zg + (size_t)w * 16 * ld + kb * 16, ld, Tb + kb * 16 * 17, 17, c, 1.0);
-            c1 = mf_block<false>(Zg + (size_t)w * 16 * ld + kb * 16 + 16, ld, Tb + (kb + 1) * 16 * 17, 17, c1, 1.0);
+    for (int w = wv; w < P1 / 16; w += FD_THREADS / WAVE) {   // Y[block w, pair] = U_1[block w, :] T
+        mf_d4 c0 = {0.0, 0.0, 0.0, 0.0}, c1 = c0;
+        for (int kb = 0; kb < P1 / 16; ++kb) {
+            c0 = mf_block<false>(Zg + (size_t)w * 16 * ld + kb * 16, ld, Tb + kb * 16 * 33, 33, c0, 1.0);
+            if (two) c1 = mf_block<false>(Zg + (size_t)w * 16 * ld + kb * 16, ld, Tb + kb * 16 * 33 + 16, 33, c1, 1.0);
         }
-        if (kb < P1 / 16) c = mf_block<false>(Zg + (size_t)w * 16 * ld + kb * 16, ld, Tb + kb * 16 * 17, 17, c, 1.0);
-        c += c1;
-        const int i0 = jc * 16 + (l & 15);
 #pragma unroll
-        for (int rr = 0; rr < 4; ++rr) {
-            const int i1 = w * 16 + (l >> 4) + 4 * rr;
-            if (i0 >= M0 || i1 >= M1) continue;
-            const int64_t vi = P.voff + i0 + (int64_t)M0 * i1;
-            const bool m = masked(P, a.mode, i0, i1, 0);
-            if (SET) x[vi] = m ? T(0) : T(f.tau * c[rr]);
-            else if (!m) x[vi] = T((double)x[vi] + f.tau * c[rr]);
+        for (int q = 0; q < 2; ++q) {
+            if (q == 1 && !two) break;
+            const int i0 = (jc + q) * 16 + (l & 15);
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) {
+                const int i1 = w * 16 + (l >> 4) + 4 * rr;
+                if (i0 >= M0 || i1 >= M1) continue;
+                const double v = q ? c1[rr] : c0[rr];
+                const int64_t vi = P.voff + i0 + (int64_t)M0 * i1;
+                const bool m = masked(P, a.mode, i0, i1, 0);
+                if (SET) x[vi] = m ? T(0) : T(f.tau * v);
+                else if (!m) x[vi] = T((double)x[vi] + f.tau * v);
+            }
         }
     }
 }
-
 
 // ---------------------------------------------------------------------------
 // 3D: the transforms as three contractions along one axis each, on padded P2 x P1 x P0 arrays (index
