@@ -281,6 +281,7 @@ struct Solver : SolverBase {
     bool fd_on = false;
     FdInfo* fd_info[2] = {nullptr, nullptr};
     double *fd_U = nullptr, *fd_lam = nullptr, *fd_z = nullptr, *fd_z2 = nullptr;
+    float *fd_U32 = nullptr, *fd_z32 = nullptr;   // 2D with FP32 V-cycles: the transforms' FP32 copies
     int fd_p0max = 0, fd_p1max = 0, fd_tiles3 = 0;
     size_t fd_lds = 0;
     // level 0 FP64
@@ -426,7 +427,7 @@ struct Solver : SolverBase {
     // finest level, patches with tensor-smoother data: x = tau P r (set) or x += tau P r
     void fd_smooth(int mode, const int* act, const T* r, T* x, bool set) {
         if (dim == 3) {   // six axis contractions through the two scratch buffers
-            FdArgs a{lev[0].L, fd_info[mode], fd_U, fd_lam, fd_z, act, mode, N, 0, fd_z2};
+            FdArgs a{lev[0].L, fd_info[mode], fd_U, fd_lam, fd_z, act, mode, N, 0, fd_z2, nullptr, nullptr};
             const dim3 g((fd_tiles3 + FD3_THREADS / WAVE - 1) / (FD3_THREADS / WAVE), N), b(FD3_THREADS);
             hipLaunchKernelGGL(k_fd3_ax0_fwd<T>, g, b, 0, stream, a, r);
             check_launch();
@@ -444,7 +445,7 @@ struct Solver : SolverBase {
             return;
         }
         const int ncp = (fd_p0max / 16 + 1) / 2;
-        FdArgs a{lev[0].L, fd_info[mode], fd_U, fd_lam, fd_z, act, mode, N, ncp, nullptr};
+        FdArgs a{lev[0].L, fd_info[mode], fd_U, fd_lam, fd_z, act, mode, N, ncp, nullptr, fd_U32, fd_z32};
         const dim3 grid(8 * ((N + 7) / 8) * ncp);
         hipLaunchKernelGGL(k_fd_fwd<T>, grid, dim3(FD_THREADS), fd_lds, stream, a, r);
         check_launch();
@@ -1508,12 +1509,18 @@ void Solver<T>::setup() {
             fd_on = true;
             fd_U = arena.upload(hu, st);
             fd_lam = arena.upload(hl, st);
-            fd_z = arena.alloc<double>(zlen, st);
+            if (dim == 2 && std::is_same<T, float>::value) {   // the 2D transforms run in FP32
+                std::vector<float> hu32(hu.begin(), hu.end());
+                fd_U32 = arena.upload(hu32, st);
+                fd_z32 = arena.alloc<float>(zlen, st);
+            } else {
+                fd_z = arena.alloc<double>(zlen, st);
+            }
             if (dim == 3) fd_z2 = arena.alloc<double>(zlen, st);
             std::vector<FdInfo> i0(info.begin(), info.begin() + N), i1(info.begin() + N, info.end());
             fd_info[0] = arena.upload(i0, st);
             fd_info[1] = arena.upload(i1, st);
-            fd_lds = fd_lds_words(fd_p0max, fd_p1max) * sizeof(double);
+            fd_lds = fd_lds_words(fd_p0max, fd_p1max) * sizeof(T);
             if (dim == 3) fd_lds = 0;   // the 3D contractions use no LDS
             int dev = 0, max_lds = 0;
             HIPCHECK(hipGetDevice(&dev));

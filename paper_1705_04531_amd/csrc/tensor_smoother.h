@@ -2,6 +2,8 @@
 // FP64 MFMA block helpers and the mask helpers of kernels.h.
 #pragma once
 
+#include <type_traits>
+
 #include "kernels.h"
 
 namespace ieti {
@@ -16,8 +18,10 @@ namespace ieti {
 // one XCD (fd_block) so that they share its L2: the forward one forms the column blocks W = R U_0[:, blk]
 // and then U_1^T W, the backward one T = Z U_0[blk, :]^T and then U_1 T.  The operands are staged in LDS
 // (U_1 in the first matrix's space once the first product is done); each wave runs the block products of
-// one 16-row block for both columns on v_mfma_f64_16x16x4f64 in FP64 (T = float converts on load and
-// store).  Patches without smoother data (P0 = 0) and inactive patches return.
+// one 16-row block for both columns on the matrix cores in the multigrid precision: FP64
+// (v_mfma_f64_16x16x4f64) or, with FP32 V-cycles, FP32 (v_mfma_f32_16x16x4f32) with FP32 operands, LDS
+// and scratch; the eigenvalue scaling is done in FP64.  Patches without smoother data (P0 = 0) and
+// inactive patches return.
 
 constexpr int FD_THREADS = 512;
 
@@ -40,10 +44,49 @@ struct FdArgs {
     int N;                 // patches
     int ncb;               // 2D: pairs of column blocks per patch in the grid (largest P0 / 32, rounded up)
     double* z2;            // 3D: second scratch buffer (same offsets as z)
+    const float* U32;      // 2D, FP32 multigrid: U in FP32 (same offsets as U)
+    float* z32;            // 2D, FP32 multigrid: the scratch in FP32 (same offsets as z)
 };
 
-// LDS doubles of either kernel for the largest padded sizes: the first operand (P1 x ld), the pair of
-// products (P1 x 33) and the pair of U_0 blocks (P0 x 33)
+// Block products of the 2D transforms in the multigrid's precision CT: FP64 on v_mfma_f64_16x16x4f64,
+// FP32 on v_mfma_f32_16x16x4f32.  Both take A[l % 16][k0 + l / 16] and B[k0 + l / 16][l % 16] from lane l;
+// element r of lane l is C[l / 16 + 4 r][l % 16] for FP64 and C[4 (l / 16) + r][l % 16] for FP32 (both
+// checked on the device).
+typedef float mf_f4 __attribute__((ext_vector_type(4)));
+template <typename CT> struct FdMf;
+template <> struct FdMf<double> {
+    typedef mf_d4 acc;
+    __device__ static acc mfma(double a, double b, acc c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+    __device__ static int row(int l, int r) { return (l >> 4) + 4 * r; }
+};
+template <> struct FdMf<float> {
+    typedef mf_f4 acc;
+    __device__ static acc mfma(float a, float b, acc c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+    __device__ static int row(int l, int r) { return 4 * (l >> 4) + r; }
+};
+
+// c += A B on 16 x 16 blocks (A[i][k] at A[i * lda + k], TA: at A[k * lda + i]; B[k][j] at B[k * ldb + j])
+template <typename CT, bool TA>
+__device__ __forceinline__ typename FdMf<CT>::acc fd_mfb(const CT* A, int lda, const CT* B, int ldb,
+                                                         typename FdMf<CT>::acc c) {
+    const int l = threadIdx.x & 63, i = l & 15, kq = l >> 4;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int k = 4 * s + kq;
+        c = FdMf<CT>::mfma(TA ? A[k * lda + i] : A[i * lda + k], B[k * ldb + i], c);
+    }
+    return c;
+}
+
+template <typename CT>
+__device__ __forceinline__ void fd_mfs(CT* C, int ldc, typename FdMf<CT>::acc c) {
+    const int l = threadIdx.x & 63;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) C[FdMf<CT>::row(l, r) * ldc + (l & 15)] = c[r];
+}
+
+// LDS words (of the multigrid precision) of either kernel for the largest padded sizes: the first
+// operand (P1 x ld), the pair of products (P1 x 33) and the pair of U_0 blocks (P0 x 33)
 __host__ __device__ inline size_t fd_lds_words(int p0max, int p1max) {
     const int ld = (p0max > p1max ? p0max : p1max) + 1;
     return (size_t)p1max * ld + (size_t)33 * (p1max + p0max);
@@ -51,8 +94,8 @@ __host__ __device__ inline size_t fd_lds_words(int p0max, int p1max) {
 
 // dst[i * ld + j] = get(i, j) for i < rows, j < cols (cols a multiple of 16): thread -> (row tid / 16 of a
 // step of 32 rows, column lane tid % 16); up to 8 column blocks' loads issued before their stores
-template <typename G>
-__device__ __forceinline__ void fd_stage(double* dst, int ld, int rows, int cols, G get) {
+template <typename CT, typename G>
+__device__ __forceinline__ void fd_stage(CT* dst, int ld, int rows, int cols, G get) {
     const int tr = threadIdx.x >> 4, tc = threadIdx.x & 15, ncb = cols >> 4;
     for (int r0 = 0; r0 < rows; r0 += FD_THREADS / 16) {
         const int i = r0 + tr;
@@ -63,7 +106,7 @@ __device__ __forceinline__ void fd_stage(double* dst, int ld, int rows, int cols
             for (int c = 0; c < 8; ++c) v[c] = c0 + c < ncb ? get(i, (c0 + c) * 16 + tc) : 0.0;
 #pragma unroll
             for (int c = 0; c < 8; ++c)
-                if (c0 + c < ncb) dst[i * ld + (c0 + c) * 16 + tc] = v[c];
+                if (c0 + c < ncb) dst[i * ld + (c0 + c) * 16 + tc] = (CT)v[c];
         }
     }
 }
@@ -91,45 +134,49 @@ __global__ __launch_bounds__(FD_THREADS) void k_fd_fwd(FdArgs a, const T* __rest
     const bool two = cb + 1 < ncb;
     const PatchLev& P = a.L[k];
     const int M0 = P.M[0], M1 = P.M[1], ld = (P0 > P1 ? P0 : P1) + 1;
+    typedef T CT;
+    typedef typename FdMf<CT>::acc acc;
     extern __shared__ double fd_sm[];
-    double* Rg = fd_sm;                       // R (P1 x P0), then U_1 (P1 x P1); leading dimension ld
-    double* Wb = fd_sm + (size_t)P1 * ld;     // W (P1 x 32), ld 33
-    double* Ub = Wb + (size_t)P1 * 33;        // U_0[:, blocks cb, cb + 1] (P0 x 32), ld 33
-    const double* U0 = a.U + f.u0;
-    const double* U1 = a.U + f.u1;
+    CT* Rg = (CT*)fd_sm;                      // R (P1 x P0), then U_1 (P1 x P1); leading dimension ld
+    CT* Wb = Rg + (size_t)P1 * ld;            // W (P1 x 32), ld 33
+    CT* Ub = Wb + (size_t)P1 * 33;            // U_0[:, blocks cb, cb + 1] (P0 x 32), ld 33
+    const CT* Ua = std::is_same<CT, float>::value ? (const CT*)(const void*)a.U32 : (const CT*)(const void*)a.U;
+    const CT* U0 = Ua + f.u0;
+    const CT* U1 = Ua + f.u1;
     const int mode = a.mode;
     fd_stage(Rg, ld, P1, P0, [&](int i1, int i0) -> double {
         return (i0 < M0 && i1 < M1 && !masked(P, mode, i0, i1, 0)) ? (double)r[P.voff + i0 + (int64_t)M0 * i1] : 0.0;
     });
-    fd_stage(Ub, 33, P0, two ? 32 : 16, [&](int i, int j) -> double { return U0[(int64_t)i * P0 + cb * 16 + j]; });
+    fd_stage(Ub, 33, P0, two ? 32 : 16, [&](int i, int j) -> double { return (double)U0[(int64_t)i * P0 + cb * 16 + j]; });
     __syncthreads();
     const int wv = threadIdx.x / WAVE, l = threadIdx.x & (WAVE - 1);
     for (int w = wv; w < P1 / 16; w += FD_THREADS / WAVE) {   // W[block w] = R[block w, :] U_0[:, pair]
-        mf_d4 c0 = {0.0, 0.0, 0.0, 0.0}, c1 = c0;
+        acc c0 = {0, 0, 0, 0}, c1 = c0;
         for (int kb = 0; kb < P0 / 16; ++kb) {
-            c0 = mf_block<false>(Rg + (size_t)w * 16 * ld + kb * 16, ld, Ub + kb * 16 * 33, 33, c0, 1.0);
-            if (two) c1 = mf_block<false>(Rg + (size_t)w * 16 * ld + kb * 16, ld, Ub + kb * 16 * 33 + 16, 33, c1, 1.0);
+            c0 = fd_mfb<CT, false>(Rg + (size_t)w * 16 * ld + kb * 16, ld, Ub + kb * 16 * 33, 33, c0);
+            if (two) c1 = fd_mfb<CT, false>(Rg + (size_t)w * 16 * ld + kb * 16, ld, Ub + kb * 16 * 33 + 16, 33, c1);
         }
-        mf_store(Wb + w * 16 * 33, 33, c0);
-        if (two) mf_store(Wb + w * 16 * 33 + 16, 33, c1);
+        fd_mfs<CT>(Wb + w * 16 * 33, 33, c0);
+        if (two) fd_mfs<CT>(Wb + w * 16 * 33 + 16, 33, c1);
     }
     __syncthreads();
-    fd_stage(Rg, ld, P1, P1, [&](int i, int j) -> double { return U1[(int64_t)i * P1 + j]; });
+    fd_stage(Rg, ld, P1, P1, [&](int i, int j) -> double { return (double)U1[(int64_t)i * P1 + j]; });
     __syncthreads();
     const double* l0 = a.lam + f.l0;
     const double* l1 = a.lam + f.l1;
     for (int w = wv; w < P1 / 16; w += FD_THREADS / WAVE) {   // Z[block w, pair] = U_1[:, block w]^T W, scaled
-        mf_d4 c0 = {0.0, 0.0, 0.0, 0.0}, c1 = c0;
+        acc c0 = {0, 0, 0, 0}, c1 = c0;
         for (int kb = 0; kb < P1 / 16; ++kb) {
-            c0 = mf_block<true>(Rg + (size_t)kb * 16 * ld + w * 16, ld, Wb + kb * 16 * 33, 33, c0, 1.0);
-            if (two) c1 = mf_block<true>(Rg + (size_t)kb * 16 * ld + w * 16, ld, Wb + kb * 16 * 33 + 16, 33, c1, 1.0);
+            c0 = fd_mfb<CT, true>(Rg + (size_t)kb * 16 * ld + w * 16, ld, Wb + kb * 16 * 33, 33, c0);
+            if (two) c1 = fd_mfb<CT, true>(Rg + (size_t)kb * 16 * ld + w * 16, ld, Wb + kb * 16 * 33 + 16, 33, c1);
         }
+        CT* z = std::is_same<CT, float>::value ? (CT*)(void*)a.z32 : (CT*)(void*)a.z;
         const int a0 = cb * 16 + (l & 15), a1 = a0 + 16;
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) {
-            const int bb = w * 16 + (l >> 4) + 4 * rr;
-            a.z[f.zoff + (int64_t)bb * P0 + a0] = c0[rr] / (l1[bb] + l0[a0] + f.shift);
-            if (two) a.z[f.zoff + (int64_t)bb * P0 + a1] = c1[rr] / (l1[bb] + l0[a1] + f.shift);
+            const int bb = w * 16 + FdMf<CT>::row(l, rr);
+            z[f.zoff + (int64_t)bb * P0 + a0] = (CT)((double)c0[rr] / (l1[bb] + l0[a0] + f.shift));
+            if (two) z[f.zoff + (int64_t)bb * P0 + a1] = (CT)((double)c1[rr] / (l1[bb] + l0[a1] + f.shift));
         }
     }
 }
@@ -146,34 +193,37 @@ __global__ __launch_bounds__(FD_THREADS) void k_fd_bwd(FdArgs a, T* __restrict__
     const int M0 = P.M[0], M1 = P.M[1], P0 = f.P0, P1 = f.P1, ld = (P0 > P1 ? P0 : P1) + 1, jc = 2 * cp;
     if (jc * 16 >= M0) return;
     const bool two = (jc + 1) * 16 < M0;
+    typedef T CT;
+    typedef typename FdMf<CT>::acc acc;
     extern __shared__ double fd_sm[];
-    double* Zg = fd_sm;                       // Z (P1 x P0), then U_1 (P1 x P1); leading dimension ld
-    double* Tb = fd_sm + (size_t)P1 * ld;     // T (P1 x 32), ld 33
-    double* Ub = Tb + (size_t)P1 * 33;        // U_0[blocks jc, jc + 1, :]^T (P0 x 32), ld 33
-    const double* U0 = a.U + f.u0;
-    const double* U1 = a.U + f.u1;
-    const double* Z = a.z + f.zoff;
+    CT* Zg = (CT*)fd_sm;                      // Z (P1 x P0), then U_1 (P1 x P1); leading dimension ld
+    CT* Tb = Zg + (size_t)P1 * ld;            // T (P1 x 32), ld 33
+    CT* Ub = Tb + (size_t)P1 * 33;            // U_0[blocks jc, jc + 1, :]^T (P0 x 32), ld 33
+    const CT* Ua = std::is_same<CT, float>::value ? (const CT*)(const void*)a.U32 : (const CT*)(const void*)a.U;
+    const CT* U0 = Ua + f.u0;
+    const CT* U1 = Ua + f.u1;
+    const CT* Z = (std::is_same<CT, float>::value ? (const CT*)(const void*)a.z32 : (const CT*)(const void*)a.z) + f.zoff;
     const int wv = threadIdx.x / WAVE, l = threadIdx.x & (WAVE - 1);
-    fd_stage(Zg, ld, P1, P0, [&](int i, int j) -> double { return Z[(int64_t)i * P0 + j]; });
-    fd_stage(Ub, 33, P0, two ? 32 : 16, [&](int i, int j) -> double { return U0[(int64_t)(jc * 16 + j) * P0 + i]; });
+    fd_stage(Zg, ld, P1, P0, [&](int i, int j) -> double { return (double)Z[(int64_t)i * P0 + j]; });
+    fd_stage(Ub, 33, P0, two ? 32 : 16, [&](int i, int j) -> double { return (double)U0[(int64_t)(jc * 16 + j) * P0 + i]; });
     __syncthreads();
     for (int w = wv; w < P1 / 16; w += FD_THREADS / WAVE) {   // T[block w] = Z[block w, :] U_0[pair, :]^T
-        mf_d4 c0 = {0.0, 0.0, 0.0, 0.0}, c1 = c0;
+        acc c0 = {0, 0, 0, 0}, c1 = c0;
         for (int kb = 0; kb < P0 / 16; ++kb) {
-            c0 = mf_block<false>(Zg + (size_t)w * 16 * ld + kb * 16, ld, Ub + kb * 16 * 33, 33, c0, 1.0);
-            if (two) c1 = mf_block<false>(Zg + (size_t)w * 16 * ld + kb * 16, ld, Ub + kb * 16 * 33 + 16, 33, c1, 1.0);
+            c0 = fd_mfb<CT, false>(Zg + (size_t)w * 16 * ld + kb * 16, ld, Ub + kb * 16 * 33, 33, c0);
+            if (two) c1 = fd_mfb<CT, false>(Zg + (size_t)w * 16 * ld + kb * 16, ld, Ub + kb * 16 * 33 + 16, 33, c1);
         }
-        mf_store(Tb + w * 16 * 33, 33, c0);
-        if (two) mf_store(Tb + w * 16 * 33 + 16, 33, c1);
+        fd_mfs<CT>(Tb + w * 16 * 33, 33, c0);
+        if (two) fd_mfs<CT>(Tb + w * 16 * 33 + 16, 33, c1);
     }
     __syncthreads();
-    fd_stage(Zg, ld, P1, P1, [&](int i, int j) -> double { return U1[(int64_t)i * P1 + j]; });
+    fd_stage(Zg, ld, P1, P1, [&](int i, int j) -> double { return (double)U1[(int64_t)i * P1 + j]; });
     __syncthreads();
     for (int w = wv; w < P1 / 16; w += FD_THREADS / WAVE) {   // Y[block w, pair] = U_1[block w, :] T
-        mf_d4 c0 = {0.0, 0.0, 0.0, 0.0}, c1 = c0;
+        acc c0 = {0, 0, 0, 0}, c1 = c0;
         for (int kb = 0; kb < P1 / 16; ++kb) {
-            c0 = mf_block<false>(Zg + (size_t)w * 16 * ld + kb * 16, ld, Tb + kb * 16 * 33, 33, c0, 1.0);
-            if (two) c1 = mf_block<false>(Zg + (size_t)w * 16 * ld + kb * 16, ld, Tb + kb * 16 * 33 + 16, 33, c1, 1.0);
+            c0 = fd_mfb<CT, false>(Zg + (size_t)w * 16 * ld + kb * 16, ld, Tb + kb * 16 * 33, 33, c0);
+            if (two) c1 = fd_mfb<CT, false>(Zg + (size_t)w * 16 * ld + kb * 16, ld, Tb + kb * 16 * 33 + 16, 33, c1);
         }
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
@@ -181,7 +231,7 @@ __global__ __launch_bounds__(FD_THREADS) void k_fd_bwd(FdArgs a, T* __restrict__
             const int i0 = (jc + q) * 16 + (l & 15);
 #pragma unroll
             for (int rr = 0; rr < 4; ++rr) {
-                const int i1 = w * 16 + (l >> 4) + 4 * rr;
+                const int i1 = w * 16 + FdMf<CT>::row(l, rr);
                 if (i0 >= M0 || i1 >= M1) continue;
                 const double v = q ? c1[rr] : c0[rr];
                 const int64_t vi = P.voff + i0 + (int64_t)M0 * i1;
