@@ -1718,12 +1718,12 @@ __global__ __launch_bounds__(BAND_THREADS) void k_band_solve(const PatchLev* L, 
     for (int i = threadIdx.x; i < n; i += blockDim.x) x[P.voff + i] = xs[i];
 }
 
-// The same solve for band widths b <= 256 with the next block's factor data in flight: 1024 threads, 16
-// per block row; while block r is reduced and its diagonal block applied, every thread already holds its
-// share of block r + 1 (off-diagonal row: b / 16 values, inverse diagonal: 4) in registers, so each block
-// step waits on LDS and barriers only, not on memory.
+// The same solve with the factor rows of a block step in registers: 1024 threads, 16 per block row, J
+// off-diagonal values per thread (band width b <= 16 J).  With DB (J = 16, b <= 256) the next block's
+// share (J values and 4 of the inverse diagonal) is loaded while the current block is reduced and its
+// diagonal block applied, so a step waits on LDS and barriers only; without DB (J = 32, b <= 512, for
+// register room) all loads of a step are issued together at its start, one memory latency per step.
 constexpr int BAND_PF_THREADS = 1024;
-constexpr int BAND_PF_J = 16;   // off-diagonal values per thread and block
 
 __device__ __forceinline__ double sum16(double v) {
     v += __shfl_xor(v, 1, WAVE);
@@ -1733,6 +1733,7 @@ __device__ __forceinline__ double sum16(double v) {
     return v;
 }
 
+template <int J, bool DB>
 __global__ __launch_bounds__(BAND_PF_THREADS) void k_band_solve_pf(const PatchLev* L, const int64_t* band_off,
                                                                  const int32_t* band_b, const double* band, int mode,
                                                                  const double* rhs, double* x, const int* active) {
@@ -1754,68 +1755,26 @@ __global__ __launch_bounds__(BAND_PF_THREADS) void k_band_solve_pf(const PatchLe
     }
     __syncthreads();
     const int ii = threadIdx.x >> 4, l16 = threadIdx.x & 15;
-    double rc[BAND_PF_J], rn[BAND_PF_J], ic[4], in4[4];
-    // forward: L y = rhs; block r needs row ii of L_off and of inv(L_diag)
-    auto load_fwd = [&](int r) {
+    double rc[J], rn[DB ? J : 1], ic[4], in4[4];
+    // block r's share of the forward (L_off row ii, inv(L_diag) row ii) or backward (U_off row ii,
+    // inv(L_diag) column ii) factor data
+    auto load = [&](int r, bool fwd, double* rv, double* iv) {
         const double* blk = F + (int64_t)r * bsz;
-        const double* row = blk + (int64_t)ii * b;
+        const double* row = blk + (fwd ? 0 : (int64_t)BNB * b) + (int64_t)ii * b;
 #pragma unroll
-        for (int j = 0; j < BAND_PF_J; ++j) {
+        for (int j = 0; j < J; ++j) {
             const int c = l16 + 16 * j;
-            rn[j] = c < b ? row[c] : 0.0;
-        }
-        const double* inv = blk + 2 * (int64_t)BNB * b + (int64_t)ii * BNB;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) in4[j] = inv[l16 + 16 * j];
-    };
-    if (nblk > 0) load_fwd(0);
-    for (int r = 0; r < nblk; ++r) {
-#pragma unroll
-        for (int j = 0; j < BAND_PF_J; ++j) rc[j] = rn[j];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) ic[j] = in4[j];
-        if (r + 1 < nblk) load_fwd(r + 1);
-        const double* xw = xs + r * BNB - b;
-        double acc = 0.0;
-#pragma unroll
-        for (int j = 0; j < BAND_PF_J; ++j) {
-            const int c = l16 + 16 * j;
-            if (c < b) acc += rc[j] * xw[c];
-        }
-        acc = sum16(acc);
-        if (l16 == 0) t[ii] = xs[r * BNB + ii] - acc;
-        __syncthreads();
-        double a2 = 0.0;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) a2 += ic[j] * t[l16 + 16 * j];
-        a2 = sum16(a2);
-        if (l16 == 0) xs[r * BNB + ii] = a2;
-        __syncthreads();
-    }
-    // backward: L^T x = y; block r needs row ii of U_off and column ii of inv(L_diag)
-    auto load_bwd = [&](int r) {
-        const double* blk = F + (int64_t)r * bsz;
-        const double* row = blk + (int64_t)BNB * b + (int64_t)ii * b;
-#pragma unroll
-        for (int j = 0; j < BAND_PF_J; ++j) {
-            const int c = l16 + 16 * j;
-            rn[j] = c < b ? row[c] : 0.0;
+            rv[j] = c < b ? row[c] : 0.0;
         }
         const double* inv = blk + 2 * (int64_t)BNB * b;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) in4[j] = inv[(int64_t)(l16 + 16 * j) * BNB + ii];
+        for (int j = 0; j < 4; ++j)
+            iv[j] = fwd ? inv[(int64_t)ii * BNB + l16 + 16 * j] : inv[(int64_t)(l16 + 16 * j) * BNB + ii];
     };
-    if (nblk > 0) load_bwd(nblk - 1);
-    for (int r = nblk - 1; r >= 0; --r) {
-#pragma unroll
-        for (int j = 0; j < BAND_PF_J; ++j) rc[j] = rn[j];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) ic[j] = in4[j];
-        if (r > 0) load_bwd(r - 1);
-        const double* xw = xs + (r + 1) * BNB;
+    auto step = [&](int r, const double* xw) {
         double acc = 0.0;
 #pragma unroll
-        for (int j = 0; j < BAND_PF_J; ++j) {
+        for (int j = 0; j < J; ++j) {
             const int c = l16 + 16 * j;
             if (c < b) acc += rc[j] * xw[c];
         }
@@ -1828,6 +1787,34 @@ __global__ __launch_bounds__(BAND_PF_THREADS) void k_band_solve_pf(const PatchLe
         a2 = sum16(a2);
         if (l16 == 0) xs[r * BNB + ii] = a2;
         __syncthreads();
+    };
+    // forward: L y = rhs
+    if (DB && nblk > 0) load(0, true, rn, in4);
+    for (int r = 0; r < nblk; ++r) {
+        if (DB) {
+#pragma unroll
+            for (int j = 0; j < J; ++j) rc[j] = rn[DB ? j : 0];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) ic[j] = in4[j];
+            if (r + 1 < nblk) load(r + 1, true, rn, in4);
+        } else {
+            load(r, true, rc, ic);
+        }
+        step(r, xs + r * BNB - b);
+    }
+    // backward: L^T x = y
+    if (DB && nblk > 0) load(nblk - 1, false, rn, in4);
+    for (int r = nblk - 1; r >= 0; --r) {
+        if (DB) {
+#pragma unroll
+            for (int j = 0; j < J; ++j) rc[j] = rn[DB ? j : 0];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) ic[j] = in4[j];
+            if (r > 0) load(r - 1, false, rn, in4);
+        } else {
+            load(r, false, rc, ic);
+        }
+        step(r, xs + (r + 1) * BNB);
     }
     for (int i = threadIdx.x; i < n; i += blockDim.x) x[P.voff + i] = xs[i];
 }

@@ -330,7 +330,7 @@ struct Solver : SolverBase {
     int32_t* band_b = nullptr;
     double* band = nullptr;
     size_t band_lds = 0;
-    int band_bmax = 0;   // widest band of the exact local solves (the prefetching solve takes b <= 256)
+    int band_bmax = 0;   // widest band of the exact local solves (the register-resident solve takes b <= 512)
     // fused coarse V-cycle: one work-group per patch for levels >= fuse_l0 (nlev: none)
     int fuse_l0 = 0;
     bool fuse_stage = false;
@@ -675,9 +675,12 @@ struct Solver : SolverBase {
     }
 
     void band_solve(int mode, const double* rhs, double* x) {
-        if (band_bmax <= 16 * BAND_PF_J)
-            hipLaunchKernelGGL(k_band_solve_pf, dim3(N), dim3(BAND_PF_THREADS), band_lds, stream, lev[0].L, band_off,
-                               band_b, band, mode, rhs, x, nullptr);
+        if (band_bmax <= 256)
+            hipLaunchKernelGGL((k_band_solve_pf<16, true>), dim3(N), dim3(BAND_PF_THREADS), band_lds, stream, lev[0].L,
+                               band_off, band_b, band, mode, rhs, x, nullptr);
+        else if (band_bmax <= 512)
+            hipLaunchKernelGGL((k_band_solve_pf<32, false>), dim3(N), dim3(BAND_PF_THREADS), band_lds, stream,
+                               lev[0].L, band_off, band_b, band, mode, rhs, x, nullptr);
         else
             hipLaunchKernelGGL(k_band_solve, dim3(N), dim3(BAND_THREADS), band_lds, stream, lev[0].L, band_off,
                                band_b, band, mode, rhs, x, nullptr);
@@ -1569,8 +1572,10 @@ void Solver<T>::setup() {
         band_b = arena.upload(bw, st);
         HIPCHECK(hipFuncSetAttribute((const void*)k_band_solve, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)band_lds));
-        HIPCHECK(hipFuncSetAttribute((const void*)k_band_solve_pf, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)band_lds));
+        HIPCHECK(hipFuncSetAttribute((const void*)k_band_solve_pf<16, true>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)band_lds));
+        HIPCHECK(hipFuncSetAttribute((const void*)k_band_solve_pf<32, false>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)band_lds));
         HIPCHECK(hipStreamSynchronize(st));
     }
     DevLevel& D0 = lev[0];
