@@ -11,6 +11,8 @@ roofline of the dominant kernel (finest-level Chebyshev sweep: HIP events
 around each of its launches, on the solver's stream, over the same number of
 steps run right after the timed ones, since per-launch events serialise the
 launches) and the CPU oracle timed on a bounded sample of the same workload.
+With --workload the same measurement (without counter traffic and CPU
+baseline) runs on the 16x16 mixed-degree or the 4x4x4 cube workload.
 """
 import argparse
 import json
@@ -158,6 +160,10 @@ def main():
     ap.add_argument("--smoother", choices=["chebyshev", "tensor"], default="chebyshev",
                     help="finest-level smoother of the measured solver; the configuration names Chebyshev (default), "
                          "tensor profiles the p-robust variant on the same workload")
+    ap.add_argument("--workload", choices=["deformed8x8", "deformed16x16", "cube4"], default="deformed8x8",
+                    help="deformed8x8 is the measured configuration; deformed16x16 (16x16 patches of mixed size and "
+                         "degree, FP32 MG) and cube4 (4x4x4 cube, p=2, FP32 MG) price the same sweeps on the other "
+                         "full-size workloads (no counter traffic, no CPU baseline)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 512 MiB FP64 tensor 3 times (scale for the FETCH_SIZE/WRITE_SIZE counters)")
     args = ap.parse_args()
@@ -184,7 +190,9 @@ def main():
     import workloads as W
     from paper_1705_04531_amd import Solver, _abi, options_for
 
-    wl = W.deformed_8x8()
+    main_wl = args.workload == "deformed8x8"
+    wl = {"deformed8x8": W.deformed_8x8, "deformed16x16": W.deformed_16x16_mixed,
+          "cube4": W.cube_4x4x4}[args.workload]()
     t0 = time.perf_counter()
     # the configuration as named, Chebyshev degrees from the library's table (measured per spline degree;
     # the setup-time autotuner ranks candidates on a seeded load, whose best can differ from this load's)
@@ -227,7 +235,7 @@ def main():
 
     # the plain FP64 exact-local form (banded Cholesky local solves, D-D) on the same workload
     plain = None
-    if not args.no_plain:
+    if not args.no_plain and wl.dim == 2:   # the exact-local form is built for 2D patches
         t0 = time.perf_counter()
         ps = Solver(wl.patches, options_for(wl, local_solver=_abi.IETI_LOCAL_EXACT))
         torch.cuda.synchronize()
@@ -301,6 +309,7 @@ def main():
     if tensor:   # no finest-level Chebyshev sweeps to price: the profile comes from rocprofv3
         dom = prof[_abi.IETI_KPROF_RESID_FINE]
     achieved = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9 if dom["ms"] > 0 else 0.0
+    mgt = "double" if wl.mg_precision == 64 else "float"
     st = stats[-1]
     out = {
         "metric": "dual-PCG solve time & MDoF/s at rel. res 1e-8; solves/s + p50/p99 latency",
@@ -313,12 +322,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if wl.mg_precision == 64 else "f64 outer / f32 MG",
         "data": "synthetic",
         "config": {
-            "workload": "deformed square 8x8 patches, p=3, 64x64 elements/patch, inexact local solves by FP64 "
-                        "multigrid V-cycles with Chebyshev smoothing (degree 6 finest, 2 coarse levels), FP64 outer CG "
-                        "to 1e-8",
+            "workload": ("deformed square 8x8 patches, p=3, 64x64 elements/patch, inexact local solves by FP64 "
+                         "multigrid V-cycles with Chebyshev smoothing (degree 6 finest, 2 coarse levels), FP64 outer "
+                         "CG to 1e-8") if main_wl else wl.description + ", FP64 outer CG to 1e-8",
             "ndof_torn": wl.ndof_torn,
             "ndof_global": wl.ndof_global,
             "n_lambda": st["n_lambda"],
@@ -338,13 +347,13 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": ("k_stencil<double,double,double,EPI_RESID,FINE> (finest-level residual sweep)" if tensor else
-                       "k_stencil<double,double,double,EPI_CHEB,FINE> (finest-level Chebyshev sweep)"),
+            "kernel": (f"k_stencil<{mgt},{mgt},{mgt},EPI_RESID,FINE> (finest-level residual sweep)" if tensor else
+                       f"k_stencil<{mgt},{mgt},{mgt},EPI_CHEB,FINE> (finest-level Chebyshev sweep)"),
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None if (tensor or args.local_solver != "mg") else counter_traffic(),
+            "traffic": None if (tensor or args.local_solver != "mg" or not main_wl) else counter_traffic(),
             "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "launches": dom["launches"],
             "avg_us": round(dom["ms"] / max(dom["launches"], 1) * 1e3, 3),
@@ -357,7 +366,7 @@ def main():
     }
     if plain is not None:
         out["plain_form"] = plain
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and main_wl:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
 
