@@ -59,26 +59,29 @@ void default_options(ieti_options* o) {
     o->hbm_budget = 0;
 }
 
-// Smoother choice per spline degree (degree of the Chebyshev polynomial per
-// smoothing phase, lower end of its interval as a fraction of lambda_max),
-// from measured solve times on MI355X over a grid of both parameters: higher
-// degrees pay off because a V-cycle's coarse part costs about as much as
-// several finest-level sweeps; the coarse levels, whose sweeps are latency
-// bound, take a lower degree.
-int cheb_degree_for(const ieti_options& o, int pmax) {
+// Smoother choice per dimension and spline degree (degree of the Chebyshev
+// polynomial per smoothing phase, lower end of its interval as a fraction of
+// lambda_max), from measured solve times on MI355X over a grid of both
+// parameters: higher degrees pay off because a V-cycle's coarse part costs
+// about as much as several finest-level sweeps; the coarse levels, whose
+// sweeps are latency bound, take a lower degree.  In 3D (p <= 2) the weaker
+// point-Jacobi smoothing of the 27-point couplings wants a higher degree and
+// a wider interval than in 2D.
+int cheb_degree_for(const ieti_options& o, int dim, int pmax) {
     if (o.cheb_degree > 0) return o.cheb_degree;
-    if (pmax <= 2) return 3;
+    if (pmax <= 2) return dim == 3 ? 4 : 3;
     if (pmax == 3) return 6;
     return 4;
 }
-int cheb_degree_coarse_for(const ieti_options& o, int pmax) {
+int cheb_degree_coarse_for(const ieti_options& o, int dim, int pmax) {
+    (void)dim;
     (void)pmax;
     if (o.cheb_degree_coarse > 0) return o.cheb_degree_coarse;
     return 2;
 }
-double cheb_lower_for(const ieti_options& o, int pmax) {
+double cheb_lower_for(const ieti_options& o, int dim, int pmax) {
     if (o.cheb_lower > 0) return o.cheb_lower;
-    if (pmax <= 2) return 0.08;
+    if (pmax <= 2) return dim == 3 ? 0.05 : 0.08;
     if (pmax == 3) return 0.03;
     return 0.02;
 }

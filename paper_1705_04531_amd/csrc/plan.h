@@ -106,9 +106,9 @@ Plan* build_plan(const ieti_patch* patches, int n, const double* primal_vertices
 
 // helpers shared with the runtime
 void default_options(ieti_options* o);
-int cheb_degree_for(const ieti_options& o, int pmax);
-int cheb_degree_coarse_for(const ieti_options& o, int pmax);
-double cheb_lower_for(const ieti_options& o, int pmax);
+int cheb_degree_for(const ieti_options& o, int dim, int pmax);
+int cheb_degree_coarse_for(const ieti_options& o, int dim, int pmax);
+double cheb_lower_for(const ieti_options& o, int dim, int pmax);
 void set_last_error(const std::string& s);
 
 }  // namespace ieti

@@ -1218,8 +1218,8 @@ void Solver<T>::setup() {
     int pmax = 0;
     for (auto& pa : pl.patches)
         for (int d = 0; d < dim; ++d) pmax = std::max(pmax, pa.p[d]);
-    cheb_m = cheb_degree_for(pl.opt, pmax);
-    cheb_mc = cheb_degree_coarse_for(pl.opt, pmax);
+    cheb_m = cheb_degree_for(pl.opt, dim, pmax);
+    cheb_mc = cheb_degree_coarse_for(pl.opt, dim, pmax);
     if (cheb_m > KMAX || cheb_mc > KMAX) throw Error(IETI_ENOTSUP, "Chebyshev degree above 8");
     lev.resize(nlev);
     // ---- descriptors, layouts, tiles
@@ -1255,7 +1255,7 @@ void Solver<T>::setup() {
             P.lmax[1] = L.lmax[1];
             int pk = 0;
             for (int d = 0; d < dim; ++d) pk = std::max(pk, pa.p[d]);
-            P.clo = cheb_lower_for(pl.opt, pk);
+            P.clo = cheb_lower_for(pl.opt, dim, pk);
             D.hL.push_back(P);
         }
         D.len = align64(cur) + 64;
