@@ -89,7 +89,7 @@ typedef struct ieti_options {
                                   IETI_LOCAL_MG_SADDLE */
     int32_t mg_precision;      /* 32 or 64: arithmetic of V-cycles and their operator data (default 64) */
     int32_t primal;            /* IETI_PRIMAL_VERTICES (default) or IETI_PRIMAL_VERTICES|IETI_PRIMAL_EDGES */
-    int32_t cheb_degree;       /* Chebyshev smoother degree per smoothing phase; 0 = tuned per spline degree */
+    int32_t cheb_degree;       /* Chebyshev smoother degree per smoothing phase; 0 = tuned per dimension and spline degree */
     int32_t cheb_degree_coarse;/* the same on the coarser multigrid levels; 0 = tuned per spline degree */
     double  cheb_lower;        /* lower end of the smoothing interval as a fraction of lambda_max; 0 = tuned */
     int32_t prec_vcycles;      /* V-cycles for the Dirichlet problems in the preconditioner (default 2) */

@@ -71,7 +71,7 @@ int cheb_degree_for(const ieti_options& o, int dim, int pmax) {
     if (o.cheb_degree > 0) return o.cheb_degree;
     if (pmax <= 2) return dim == 3 ? 4 : 3;
     if (pmax == 3) return 6;
-    return 4;
+    return 7;
 }
 int cheb_degree_coarse_for(const ieti_options& o, int dim, int pmax) {
     (void)dim;
