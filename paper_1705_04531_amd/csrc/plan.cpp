@@ -71,7 +71,8 @@ int cheb_degree_for(const ieti_options& o, int dim, int pmax) {
     if (o.cheb_degree > 0) return o.cheb_degree;
     if (pmax <= 2) return dim == 3 ? 4 : 3;
     if (pmax == 3) return 6;
-    return 7;
+    if (pmax == 4) return 7;
+    return 8;
 }
 int cheb_degree_coarse_for(const ieti_options& o, int dim, int pmax) {
     (void)dim;
@@ -83,7 +84,8 @@ double cheb_lower_for(const ieti_options& o, int dim, int pmax) {
     if (o.cheb_lower > 0) return o.cheb_lower;
     if (pmax <= 2) return dim == 3 ? 0.05 : 0.08;
     if (pmax == 3) return 0.03;
-    return 0.02;
+    if (pmax == 4) return 0.02;
+    return 0.01;
 }
 
 // ----------------------------------------------------------------------------
