@@ -1333,6 +1333,12 @@ __global__ __launch_bounds__(TILE) void k_patch_gram(int npatch, const PatchLev*
 
 constexpr int LMAX = 12;     // multigrid levels per patch
 constexpr int VC_THREADS = 512;
+// FP32 3D levels (family 1): 1024 threads per work-group (those instances
+// fit in 128 registers), so that a level-1 sweep takes fewer rounds (4^3 cube
+// p=2: 215 -> 200 ms per solve); the 2D family measured slower with 1024
+// (16x16 mixed workload 183 -> 191 ms) and FP64 needs more registers: 512.
+template <typename T, int FAM>
+__host__ __device__ constexpr int vc_threads() { return sizeof(T) == 4 && FAM == 1 ? 2 * VC_THREADS : VC_THREADS; }
 
 struct CoarseArgs {
     const PatchLev* L[LMAX];
@@ -1609,7 +1615,7 @@ __device__ __forceinline__ void vcoarse_body(const CoarseArgs& a, int k, T* lds,
 __host__ __device__ constexpr int vcoarse_family(int cls) { return cls <= 8 ? 0 : 1; }
 
 template <typename T, bool STAGE, int FAM>
-__global__ __launch_bounds__(VC_THREADS) void k_vcoarse(CoarseArgs a) {
+__global__ __launch_bounds__((vc_threads<T, FAM>())) void k_vcoarse(CoarseArgs a) {
     extern __shared__ unsigned char vc_lds_raw[];
     __shared__ VcShared sh;
     if ((int)blockIdx.x >= a.nlist) return;

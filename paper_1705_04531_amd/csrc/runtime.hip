@@ -109,7 +109,7 @@ static void launch_vcoarse(hipStream_t st, const CoarseArgs& a, size_t lds_bytes
         HIPCHECK(hipFuncSetAttribute((const void*)k_vcoarse<T, STAGE, FAM>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes));
     else
-        hipLaunchKernelGGL((k_vcoarse<T, STAGE, FAM>), dim3(a.nlist), dim3(VC_THREADS), lds_bytes, st, a);
+        hipLaunchKernelGGL((k_vcoarse<T, STAGE, FAM>), dim3(a.nlist), dim3((vc_threads<T, FAM>())), lds_bytes, st, a);
 }
 
 template <typename T>
