@@ -140,13 +140,18 @@ typedef struct ieti_stats {
     int64_t ndof_global;               /* conforming dofs without the boundary */
     int64_t n_lambda;
     int64_t n_primal;
-    int32_t breakdown;                 /* 1 if d vanished to rounding and lambda = 0 was returned */
+    int32_t breakdown;                 /* 1 if d vanished to rounding and lambda = 0 was returned (IETI_OK), or
+                                          if the outer CG met (p, F p) <= 0 above the tolerance (IETI_ENOCONV) */
     int32_t cheb_degree;               /* smoother in use: Chebyshev degree on the finest level, */
     int32_t cheb_degree_coarse;        /* on the coarser levels, */
     double  cheb_lower;                /* and the interval's lower end over the tuned table's (1 = table) */
     double  saddle_omega;              /* MG-MG-S: the scaling omega of the V-cycle block in use (0 otherwise) */
     int32_t fine_tile_staged;          /* finest-level sweep tiles stage their x window in LDS (1) or not (0) */
     int32_t tune_cached;               /* 1 if the autotuner's choice came from options.tune_cache */
+    int32_t inner_unconverged;         /* local flexible-CG solves that stopped above inner_tol (iteration
+                                          limit or a vanished search direction); their result is still used */
+    int32_t inner_nonfinite;           /* local solves with a NaN/Inf residual; the solve then returns
+                                          IETI_ENOCONV */
 } ieti_stats;
 
 typedef struct ieti_handle ieti_handle;
@@ -203,9 +208,20 @@ int ieti_plan_array(const ieti_plan* plan, int32_t which, int32_t patch, int32_t
 int ieti_plan_quadrature(const ieti_plan* plan, double* x_qp_host);
 
 /*
- * Setup: plans (as ieti_plan_create) and builds the device state: operator
- * data in FP64 and the multigrid precision, the primal basis by batched
- * local solves to basis_tol, the coarse matrix S_PiPi and its factorisation.
+ * Setup (Sec. 1, eq. (1) and Sec. 2): the multipatch B-spline discretisation
+ * of the model problem from the patches' degrees, knot vectors and control
+ * points, the tearing into patch-local spaces with the primal unknowns at the
+ * selected vertices (and edge averages), and the energy-minimising primal
+ * basis of eq. (6).  Plans on the host (as ieti_plan_create) and builds the
+ * device state: operator data in FP64 and the multigrid precision, the primal
+ * basis by batched local solves to basis_tol, the coarse matrix S_PiPi and
+ * its factorisation.
+ *   patches: n_patches host descriptors (read during the call only);
+ *   primal_vertices / n_primal_vertices: as for ieti_plan_create;
+ *   opt: host options (NULL = defaults; copied, tune_cache string included);
+ *   out: receives the handle (NULL on failure).
+ * Errors: IETI_EINVAL (sizes, knots, degrees), IETI_ENONCONFORMING,
+ * IETI_EGEOM, IETI_ENOMEM (allocation or hbm_budget), IETI_ENOTSUP, IETI_EDEVICE.
  */
 int ieti_setup(const ieti_patch* patches, int32_t n_patches,
                const double* primal_vertices, int32_t n_primal_vertices,
@@ -215,10 +231,17 @@ int ieti_setup(const ieti_patch* patches, int32_t n_patches,
 int ieti_quadrature(const ieti_handle* h, double* x_qp, int32_t on_device, int64_t* n_qp);
 
 /*
- * Solve for one right-hand side.  f_qp: f at the ieti_quadrature points
- * (n_qp doubles, device pointer).  u: ndof_torn doubles (device pointer),
- * the torn layout described above.  stats may be NULL.  Runs on the
- * handle's stream and synchronises it before returning.
+ * Solve for one right-hand side: the dual problem F lambda = d of eq. (4) by
+ * CG with the scaled Dirichlet preconditioner, with the local solves of the
+ * variant chosen in the options (Sec. 3.3: exact, MG-MG, D-MG, MG-MG-S), then
+ * the recovery of u from lambda (Sec. 2).  f_qp: f at the ieti_quadrature
+ * points (n_qp doubles, device pointer, read only).  u: ndof_torn doubles
+ * (device pointer, written), the torn layout described above.  stats may be
+ * NULL (host).  Runs on the handle's stream and synchronises it before
+ * returning.  Errors: IETI_EINVAL (NULL pointers, non-finite f),
+ * IETI_ENOCONV (tol not reached in max_it iterations, an outer breakdown
+ * above tol, or a non-finite local residual; u is still written),
+ * IETI_EDEVICE.
  */
 int ieti_solve(ieti_handle* h, const double* f_qp, double* u, ieti_stats* stats);
 
@@ -238,7 +261,12 @@ void ieti_destroy(ieti_handle* h);
 #define IETI_KPROF_SMOOTH_FINE  0   /* Chebyshev sweep (stencil + fused update) on the finest level */
 #define IETI_KPROF_APPLY64      1   /* FP64 stiffness apply + fused dot products of the flexible CG */
 #define IETI_KPROF_RESID_FINE   2   /* residual sweep on the finest level before restriction */
-#define IETI_KPROF_COUNT        3
+#define IETI_KPROF_FAPPLY       3   /* one whole F apply q = B K~^{-1} B^T p of the outer CG (every kernel of it,
+                                       host convergence checks of the local solves included); bytes: the
+                                       algorithmic bytes of all its kernels from the per-patch inner iteration
+                                       counts (multigrid variants with the Chebyshev smoother, exact local solves) */
+#define IETI_KPROF_PREC         4   /* one whole preconditioner apply z = B_D S B_D^T r, same accounting */
+#define IETI_KPROF_COUNT        5
 int ieti_profile_enable(ieti_handle* h, int32_t enable);
 int ieti_profile_query(const ieti_handle* h, int32_t kernel, int64_t* launches, double* total_ms,
                        double* total_bytes);

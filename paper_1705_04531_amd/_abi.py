@@ -43,6 +43,8 @@ IETI_ARR_TENSOR_PARAMS = 13
 IETI_KPROF_SMOOTH_FINE = 0
 IETI_KPROF_APPLY64 = 1
 IETI_KPROF_RESID_FINE = 2
+IETI_KPROF_FAPPLY = 3
+IETI_KPROF_PREC = 4
 
 
 class IetiPatch(C.Structure):
@@ -106,6 +108,8 @@ class IetiStats(C.Structure):
         ("saddle_omega", C.c_double),
         ("fine_tile_staged", C.c_int32),
         ("tune_cached", C.c_int32),
+        ("inner_unconverged", C.c_int32),
+        ("inner_nonfinite", C.c_int32),
     ]
 
     def as_dict(self):

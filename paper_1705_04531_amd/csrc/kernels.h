@@ -900,7 +900,9 @@ __global__ __launch_bounds__(TILE) void k_fcg_update(const PatchLev* L, const Ti
 __global__ __launch_bounds__(256) void k_fcg_check(int npatch, const int32_t* tile_beg, const int32_t* tile_end,
                                                    const double* prr, int init, double* bb, int* active, int* its,
                                                    int* brk, double tol2, int maxit, int* nactive) {
-    // nactive[1]: sum over patches of iterations of finished solves, nactive[2]: max, nactive[3]: patch solves
+    // nactive[1]: sum over patches of iterations of finished solves, nactive[2]: max, nactive[3]: patch solves,
+    // nactive[4]: solves retired above the tolerance (iteration limit or breakdown), nactive[5]: solves whose
+    // residual is not finite (a NaN or Inf from the V-cycle or the data)
     __shared__ int cnt[256 / WAVE];
     int c = 0;
     for (int k = threadIdx.x; k < npatch; k += blockDim.x) {
@@ -914,11 +916,15 @@ __global__ __launch_bounds__(256) void k_fcg_check(int npatch, const int32_t* ti
             active[k] = s > 0.0 ? 1 : 0;
         } else {
             its[k] += 1;
-            active[k] = (s > tol2 * bb[k] && its[k] < maxit && !brk[k]) ? 1 : 0;
+            const bool finite = s - s == 0.0;
+            const bool above = !finite || s > tol2 * bb[k];
+            active[k] = (above && finite && its[k] < maxit && !brk[k]) ? 1 : 0;
             if (!active[k]) {
                 atomicAdd(&nactive[1], its[k]);
                 atomicMax(&nactive[2], its[k]);
                 atomicAdd(&nactive[3], 1);
+                if (!finite) atomicAdd(&nactive[5], 1);
+                else if (above) atomicAdd(&nactive[4], 1);
             }
         }
         c += active[k];

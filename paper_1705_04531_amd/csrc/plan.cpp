@@ -654,7 +654,9 @@ static void rank_one(const std::vector<double>& g, int Q0, int Q1, std::vector<d
 
 // Symmetric eigenproblem A = Z diag(w) Z^T (A row-major n x n, destroyed; Z row-major, eigenvectors by
 // columns): Householder reduction to tridiagonal form, then implicit QL sweeps with the shift from the
-// leading 2 x 2 block; both accumulate their orthogonal transformations into Z.
+// leading 2 x 2 block; both accumulate their orthogonal transformations into Z.  The QL sweep is the
+// published implicit QL algorithm with Wilkinson-type shifts of Bowdler, Martin, Reinsch and Wilkinson
+// (Numer. Math. 11, 1968; the EISPACK routine tql2), restated here step by step.
 static void sym_eig(int n, std::vector<double>& A, std::vector<double>& w, std::vector<double>& Z) {
     Z.assign((size_t)n * n, 0.0);
     for (int i = 0; i < n; ++i) Z[(size_t)i * n + i] = 1.0;

@@ -189,9 +189,9 @@ struct KProf {
     bool on = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
     std::vector<std::pair<int, double>> pending;   // (class, bytes) of used pool entries
-    int64_t launches[IETI_KPROF_COUNT] = {0, 0, 0};
-    double ms[IETI_KPROF_COUNT] = {0, 0, 0};
-    double bytes[IETI_KPROF_COUNT] = {0, 0, 0};
+    int64_t launches[IETI_KPROF_COUNT] = {};
+    double ms[IETI_KPROF_COUNT] = {};
+    double bytes[IETI_KPROF_COUNT] = {};
     ~KProf() {
         for (auto& e : pool) {
             (void)hipEventDestroy(e.first);
@@ -750,15 +750,110 @@ struct Solver : SolverBase {
         check_launch();
     }
 
+    // ---------------------------------------------------------------- algorithmic bytes of F and M^{-1}
+    // Each array a kernel must stream counted once per launch (s: bytes of the multigrid word): a Chebyshev
+    // step (5 + nst) n s (the step from zero 4 n s), a residual (3 + nst) n s, a restriction (n + n_c) s, a
+    // prolongation (2 n + n_c) s; the fused coarse part its right-hand side and result once, the half
+    // stencils of its smoothed levels and the coarsest inverse once; a coarsest solve outside it 2 n_c s +
+    // n_c^2 s.  Only multigrid with the Chebyshev smoother is modelled (0 otherwise).
+    double vcycle_bytes(int k) const {
+        if (fd_on) return 0.0;
+        const Patch& pa = plan->patches[k];
+        const int nl = (int)pa.lv.size();
+        const double s = sizeof(T);
+        double b = 0.0;
+        for (int l = 0; l < nl; ++l) {
+            const Level& L = pa.lv[l];
+            const double n = (double)L.n, nst = L.nst;
+            if (l >= fuse_l0) {   // the fused kernel from here on
+                b += 2.0 * n * s;
+                for (int q = l; q < nl; ++q) {
+                    const Level& Q = pa.lv[q];
+                    b += q == nl - 1 ? (double)Q.n * (double)Q.n * s : (double)Q.nst * (double)Q.n * s;
+                }
+                break;
+            }
+            if (l == nl - 1) {   // coarsest solve by the batched dense GEMV
+                b += 2.0 * n * s + n * n * s;
+                break;
+            }
+            const int m = l == 0 ? cheb_m : cheb_mc;
+            const double nc = (double)pa.lv[l + 1].n;
+            b += 4.0 * n * s + (m - 1) * (5.0 + nst) * n * s;   // pre-smoothing from zero
+            b += (3.0 + nst) * n * s + (n + nc) * s;              // residual, restriction
+            b += (2.0 * n + nc) * s + m * (5.0 + nst) * n * s;    // prolongation, post-smoothing
+        }
+        return b;
+    }
+    // one F apply with the inner iteration counts its_k of its local solves
+    double fapply_bytes(const std::vector<int>& itk) const {
+        const double s = sizeof(T);
+        double b = 8.0 * (double)len0 + 24.0 * (double)nslots + 24.0 * (double)nlam;   // B^T p, B w
+        for (int k = 0; k < N; ++k) {
+            const Patch& pa = plan->patches[k];
+            const double n = (double)pa.lv[0].n, nst = pa.lv[0].nst;
+            if (exact) {
+                b += (double)pa.band[0].size() * 8.0 + 16.0 * n;
+                continue;
+            }
+            const double init = n * (40.0 + s);
+            const double iter = vcycle_bytes(k) + n * (s + 8.0) + n * (s + 16.0) + n * (8.0 * nst + 24.0) +
+                                n * (48.0 + s);
+            b += init + (double)itk[k] * iter;
+        }
+        b += 16.0 * (double)nslots * (double)std::max(npk_max, 0);   // primal part on the slots
+        return b;
+    }
+    double prec_bytes() const {
+        const double s = sizeof(T);
+        double b = 8.0 * (double)len0 + 24.0 * (double)nslots + 24.0 * (double)nlam;
+        for (int k = 0; k < N; ++k) {
+            const Patch& pa = plan->patches[k];
+            const double n = (double)pa.lv[0].n, nst = pa.lv[0].nst;
+            b += n * (8.0 + 8.0 * nst + s);                 // b_I = -K v
+            if (prec_exact) {
+                b += (double)pa.band[1].size() * 8.0 + 16.0 * n;
+            } else {
+                const int cyc = std::max(1, plan->opt.prec_vcycles);
+                b += cyc * vcycle_bytes(k) + (cyc - 1) * ((3.0 + nst) * n * s + 3.0 * n * s);
+            }
+            b += n * (s + 16.0) + n * (8.0 * nst + 16.0);   // w = v + x_I, s = K w
+        }
+        return b;
+    }
+
     // q = F p
     void applyF(const double* p, double* q) {
+        std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+        size_t slot = 0;
+        if (prof.on) {
+            ev = prof.next(IETI_KPROF_FAPPLY, 0.0);
+            slot = prof.pending.size() - 1;   // the kernel classes inside add entries after this one
+            HIPCHECK(hipEventRecord(ev.first, stream));
+        }
         scatter(p, false, b64);
         ktilde_inv(b64, false, plan->opt.inner_tol, nullptr);
         gather(fx, false, q);
+        if (prof.on) {
+            HIPCHECK(hipEventRecord(ev.second, stream));
+            std::vector<int> itk(N, 0);
+            if (!exact) HIPCHECK(hipMemcpyAsync(itk.data(), its, N * sizeof(int), hipMemcpyDeviceToHost, stream));
+            sync();
+            prof.pending[slot].second = fapply_bytes(itk);
+        }
     }
 
     // z = B_D S B_D^T r
     void applyPrec(const double* r, double* z) {
+        std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+        if (prof.on) {
+            ev = prof.next(IETI_KPROF_PREC, prec_bytes());
+            HIPCHECK(hipEventRecord(ev.first, stream));
+        }
+        applyPrecBody(r, z);
+        if (prof.on) HIPCHECK(hipEventRecord(ev.second, stream));
+    }
+    void applyPrecBody(const double* r, double* z) {
         DevLevel& D = lev[0];
         scatter(r, true, w64);
         // b_I = -m_D (K v)
@@ -1609,7 +1704,7 @@ void Solver<T>::setup() {
     active = arena.alloc<int>(N, st);
     its = arena.alloc<int>(N, st);
     brk = arena.alloc<int>(N, st);
-    nactive = arena.alloc<int>(4, st);
+    nactive = arena.alloc<int>(8, st);
     h_its.assign(N, 0);
     HIPCHECK(hipHostMalloc((void**)&h_nactive, sizeof(int)));
     HIPCHECK(hipHostMalloc((void**)&h_sc, 16 * sizeof(double)));
@@ -1873,7 +1968,7 @@ int Solver<T>::solve(const double* f_qp, double* u_out, ieti_stats* stp) {
     auto ms = [](clk::time_point a, clk::time_point b) { return std::chrono::duration<double, std::milli>(b - a).count(); };
     inner_calls = inner_sum = 0;
     inner_max = 0;
-    fill<int>(nactive, 4, 0);
+    fill<int>(nactive, 8, 0);
     ieti_stats st{};
     st.ndof_torn = pl.ndof_torn;
     st.ndof_global = pl.ndof_global;
@@ -1951,8 +2046,11 @@ int Solver<T>::solve(const double* f_qp, double* u_out, ieti_stats* stp) {
             sync();
             ++it;
             rnorm = std::sqrt(h_sc[3]);
-            if (h_sc[4] != 0.0) { st.breakdown = 1; conv = true; break; }
+            if (!(rnorm - rnorm == 0.0)) break;   // NaN or Inf: not converged
             if (rnorm <= pl.opt.tol * r0) { conv = true; break; }
+            // (p, F p) <= 0 with a residual above the tolerance: F is not positive on the search direction
+            // (inexact local solves that failed, or rounding); report it and stop unconverged
+            if (h_sc[4] != 0.0) { st.breakdown = 1; break; }
             applyPrec(lr, lz);
             hipLaunchKernelGGL(k_pcg, dim3(1), dim3(1024), 0, stream, 2, nl, lam, lr, lz, lp, lq, sc);
             check_launch();
@@ -1979,15 +2077,23 @@ int Solver<T>::solve(const double* f_qp, double* u_out, ieti_stats* stp) {
     st.time_recovery_ms = ms(t2, t3);
     st.time_total_ms = ms(t0, t3);
     {
-        int h4[4];
-        HIPCHECK(hipMemcpy(h4, nactive, sizeof(h4), hipMemcpyDeviceToHost));
-        inner_sum = h4[1];
-        inner_max = h4[2];
-        inner_calls = h4[3];
+        int h8[8];
+        HIPCHECK(hipMemcpyAsync(h8, nactive, sizeof(h8), hipMemcpyDeviceToHost, stream));
+        sync();
+        inner_sum = h8[1];
+        inner_max = h8[2];
+        inner_calls = h8[3];
+        st.inner_unconverged = h8[4];
+        st.inner_nonfinite = h8[5];
     }
     st.inner_iterations_max = inner_max;
     st.inner_iterations_mean = inner_calls ? (double)inner_sum / (double)inner_calls : 0.0;
     if (stp) *stp = st;
+    if (st.inner_nonfinite > 0) {
+        set_last_error("a local solve produced a non-finite residual");
+        return IETI_ENOCONV;
+    }
+    if (!conv) set_last_error(st.breakdown ? "outer CG breakdown above the tolerance" : "outer CG did not converge");
     return conv ? IETI_OK : IETI_ENOCONV;
 }
 
@@ -2474,6 +2580,10 @@ int ieti_server_create(const ieti_options* opt, int32_t max_slots, ieti_server**
     return guarded([&] {
         auto* S = new ieti_server();
         if (opt) S->opt = *opt; else default_options(&S->opt);
+        if (S->opt.tune_cache) {   // keep no caller pointer: the workers plan with the server's own copy
+            S->tune_cache = S->opt.tune_cache;
+            S->opt.tune_cache = S->tune_cache.c_str();
+        }
         S->slots = max_slots;
         S->budget = S->opt.hbm_budget;
         int dev = S->opt.device;

@@ -1,10 +1,11 @@
 """Writes the full-size golden files: the oracle's solution of each benchmark
-configuration, sampled at 2000 seeded global coefficients, plus its l2 norm.
-Calls only the oracle: the global conforming system with SuperLU for the 2D
-configurations; for the 3D cube, where a global sparse LU of ~1M unknowns does
-not fit, the oracle's exact-local IETI-DP run to a dual residual of 1e-13 (its
-agreement with the global direct solve is pinned by the oracle tests on
-smaller cubes).
+configuration, sampled at 64 seeded coefficients of every patch (interior,
+side, edge and vertex coefficients alike, boundary excluded) plus 2000 seeded
+global coefficients, with its l2 and max norms.  Calls only the oracle: the
+global conforming system with SuperLU for the 2D configurations; for the 3D
+cube, where a global sparse LU of ~1M unknowns does not fit, the oracle's
+exact-local IETI-DP run to a dual residual of 1e-13 (its agreement with the
+global direct solve is pinned by the oracle tests on smaller cubes).
 
     python tests/golden/make_golden.py deformed8x8_p3_n64 [deformed16x16_mixed cube4x4x4_p2_n24 ...]
 """
@@ -21,8 +22,23 @@ sys.path.insert(0, ROOT)
 import workloads as W  # noqa: E402
 from oracle import conforming, ietidp  # noqa: E402
 
+PER_PATCH = 64
+GLOBAL = 2000
 
-def make(name: str, nsample: int = 2000):
+
+def sample_indices(lay, seed: int = 12345) -> np.ndarray:
+    """Global indices sampled: PER_PATCH per patch among its non-boundary coefficients, then GLOBAL more."""
+    rng = np.random.default_rng(seed)
+    picks = []
+    for g in lay.gid:
+        cand = g[~lay.boundary[g]]
+        picks.append(rng.choice(cand, size=min(PER_PATCH, len(cand)), replace=False))
+    free = np.flatnonzero(~lay.boundary)
+    picks.append(rng.choice(free, size=min(GLOBAL, len(free)), replace=False))
+    return np.unique(np.concatenate(picks))
+
+
+def make(name: str):
     wl = W.CONFIGS[name]()
     t0 = time.time()
     if wl.dim == 2:
@@ -35,14 +51,14 @@ def make(name: str, nsample: int = 2000):
         u = conforming.global_from_torn(lay, parts)
         method = (f"oracle exact-local IETI-DP (oracle/ietidp.py), CG to 1e-13 in {info['iterations']} "
                   f"iterations")
-    free = np.flatnonzero(~lay.boundary)
-    rng = np.random.default_rng(12345)
-    idx = np.sort(rng.choice(free, size=min(nsample, len(free)), replace=False))
+    idx = sample_indices(lay)
     out = {
         "config": name,
         "method": method,
-        "ndof_global": int(len(free)),
+        "ndof_global": int(np.count_nonzero(~lay.boundary)),
         "norm2": float(np.linalg.norm(u)),
+        "max_abs": float(np.abs(u).max()),
+        "per_patch": PER_PATCH,
         "indices": [int(i) for i in idx],
         "values": [float(v) for v in u[idx]],
         "seconds": round(time.time() - t0, 1),
@@ -50,7 +66,8 @@ def make(name: str, nsample: int = 2000):
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"full_{name}.json")
     with open(path, "w") as fh:
         json.dump(out, fh)
-    print(f"{name}: {len(free)} dofs, |u| = {out['norm2']:.12e}, {out['seconds']} s -> {path}", flush=True)
+    print(f"{name}: {out['ndof_global']} dofs, {len(idx)} samples, |u| = {out['norm2']:.12e}, "
+          f"{out['seconds']} s -> {path}", flush=True)
 
 
 if __name__ == "__main__":

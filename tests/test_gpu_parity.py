@@ -8,6 +8,7 @@ import pytest
 
 import workloads as W
 from gpu_util import oracle_solution, rel_err, run_gpu, split_torn, with_sine_rhs
+from oracle import conforming
 
 pytestmark = pytest.mark.gpu
 
@@ -34,18 +35,22 @@ def test_solution_matches_oracle(require_gpu, name, make, prec, hierarchy):
     patches are then solved on one level); "full": coarse_dofs = 0 forces the whole
     h-hierarchy, so the V-cycle kernels (smoothing, transfers, fused coarse levels) run."""
     wl = make()
-    u_ref, lay, _ = oracle_solution(wl)
+    u_ref, lay, systems = oracle_solution(wl)
     extra = {"coarse_dofs": 0} if hierarchy == "full" else {}
     u, st = run_gpu(wl, mg_precision=prec, tol=1e-10, **extra)
     err = rel_err(wl, u, u_ref, lay)
+    parts = split_torn(wl, u)
+    # the final FP64 residual ||F - K u|| / ||F|| of the conforming system: the library's value for its own u
+    # against the oracle's assembled system applied to the same u (copies averaged on both sides)
+    res_o = conforming.global_residual(wl, parts, lay, systems)
     print(f"{name} prec={prec} {hierarchy}: err={err:.3e} outer={st['outer_iterations']} "
           f"inner mean={st['inner_iterations_mean']:.1f} max={st['inner_iterations_max']} "
-          f"res={st['global_residual']:.2e}", flush=True)
+          f"res={st['global_residual']:.6e} oracle res={res_o:.6e}", flush=True)
     assert err <= 1e-8
-    # the assembled residual is dominated by 1e-10-level interface jumps times h^-2: a sanity bound only
-    assert 0.0 < st["global_residual"] <= 1e-6
+    assert st["inner_unconverged"] == 0 and st["inner_nonfinite"] == 0
+    # both sides evaluate K u to FP64 rounding: |K||u| / |F| ~ 1e3 here, so they agree to ~1e-13 absolute
+    assert abs(st["global_residual"] - res_o) <= 1e-4 * res_o + 1e-12
     # copies of every interface coefficient are identical after averaging
-    parts = split_torn(wl, u)
     lo = np.full(lay.nglobal, np.inf)
     hi = np.full(lay.nglobal, -np.inf)
     for g, v in zip(lay.gid, parts):
@@ -59,10 +64,15 @@ def test_config_tolerance(require_gpu, name, make):
     """At the configs' outer tolerance 1e-8 the solution error stays at the 1e-8 level."""
     wl = make()
     u_ref, lay, _ = oracle_solution(wl)
-    u, st = run_gpu(wl, mg_precision=32, tol=1e-8)
-    err = rel_err(wl, u, u_ref, lay)
-    print(f"{name} tol=1e-8: err={err:.3e} outer={st['outer_iterations']}", flush=True)
-    assert err <= 2e-8
+    errs = {}
+    for tol in (1e-8, 1e-10):
+        u, st = run_gpu(wl, mg_precision=32, tol=tol)
+        errs[tol] = rel_err(wl, u, u_ref, lay)
+        print(f"{name} tol={tol:.0e}: err={errs[tol]:.3e} outer={st['outer_iterations']}", flush=True)
+    # the dual residual bounds the solution error only up to a factor ~ cond(M^-1 F); both runs are reported,
+    # the configs' tolerance must still give 1e-8 and the tighter one must improve on it
+    assert errs[1e-8] <= 1e-8
+    assert errs[1e-10] <= 1e-9 and errs[1e-10] <= errs[1e-8]
 
 
 EXACT_CASES = [
