@@ -1,18 +1,21 @@
 """Benchmark: one step = one complete ieti_solve (load vector, d = B K~^{-1} f,
 outer CG on F lambda = d to ||r|| <= 1e-8 ||r_0||, recovery of u, FP64
-global residual) on the deformed-square workload with 8x8 patches, p = 3,
-64x64 elements per patch (287,296 torn dofs), FP64 multigrid local solves.
-Setup (assembly, multigrid hierarchy, primal basis, coarse factorisation)
-happens before the timed region; f at the quadrature points is resident in
-HBM when timing starts.
+global residual) on the deformed square with 16x16 patches of uneven size and
+degree (elements per patch column/row from {32,48,64,96}, degree from {2,3,4};
+817,899 torn dofs), inexact local solves by FP64 multigrid V-cycles inside
+the FP64 outer CG.  Setup (planning, assembly, multigrid hierarchy, primal
+basis, coarse factorisation) happens before the timed region; f at the
+quadrature points is resident in HBM when timing starts.
 
-Prints one JSON line: MDoF/s (torn dofs per second of solve time), the
-roofline of the dominant kernel (finest-level Chebyshev sweep: HIP events
-around each of its launches, on the solver's stream, over the same number of
-steps run right after the timed ones, since per-launch events serialise the
-launches) and the CPU oracle timed on a bounded sample of the same workload.
-With --workload the same measurement (without counter traffic and CPU
-baseline) runs on the 16x16 mixed-degree or the 4x4x4 cube workload.
+Prints one JSON line: MDoF/s (torn dofs per second of solve time); the
+roofline of the dominant kernel (the finest-level Chebyshev sweep) and of the
+whole F apply (every kernel of q = F p), both from HIP events on the solver's
+stream over the same number of steps run right after the timed ones (events
+around every launch serialise the launches); the error of each measured
+solution against the stored oracle samples (tests/golden); beside the
+headline the configuration's FP32-multigrid form, the plain FP64 exact-local
+form (speedups), the 4x4x4 cube and the 8x8 workload; and the CPU oracle
+timed on all host cores.
 """
 import argparse
 import json
@@ -24,38 +27,141 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-PMC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_k_stencil_cheb_fine__deformed8x8_p3_n64.json")
-KERNELS_SRC = os.path.join(ROOT, "paper_1705_04531_amd", "csrc", "kernels.h")
+GOLDEN = os.path.join(ROOT, "tests", "golden")
 
 
-def counter_traffic():
-    """HBM bytes per launch of the dominant kernel from the committed FETCH_SIZE/WRITE_SIZE
-    summary (copy-calibrated), or None once the kernel source has changed since."""
-    import hashlib
+def golden_error(name, u):
+    """Relative l2 over the stored oracle samples (64 per patch + 2000 global) and the largest sampled
+    deviation over the oracle's max norm; u is the torn result on the host."""
+    import numpy as np
+    path = os.path.join(GOLDEN, f"full_{name}.json")
     try:
-        pm = json.load(open(PMC_SUMMARY))
-        h = hashlib.sha256(open(KERNELS_SRC, "rb").read()).hexdigest()
+        g = json.load(open(path))
     except OSError:
         return None
-    return pm["traffic_bytes_per_launch"] if pm.get("kernels_h_sha256") == h else None
+    if "torn_positions" not in g:
+        return None
+    idx = np.asarray(g["torn_positions"])
+    ref = np.asarray(g["values"])
+    got = u[idx]
+    return {"rel_l2_sampled": float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
+            "max_rel_sampled": float(np.abs(got - ref).max() / g["max_abs"]),
+            "samples": int(len(idx))}
 
 
-def cpu_baseline(sample_grid=(4, 4)):
-    """Oracle (exact-local IETI-DP, FP64, SciPy) on a sub-layout with the same patch shape."""
-    import numpy as np
+def measure(wl, golden_name, steps, warmup, profile=True, **opt):
+    """Setup, warm-up, `steps` timed solves, then (profile) the same number of solves with kernel events."""
+    import torch
+
+    from paper_1705_04531_amd import Solver, _abi, options_for
+
+    t0 = time.perf_counter()
+    solver = Solver(wl.patches, options_for(wl, **opt))
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    x = solver.quadrature(device=False)
+    f = torch.from_numpy(wl.f(x)).to("cuda")
+    u = torch.empty(solver.ndof_torn, dtype=torch.float64, device="cuda")
+    for _ in range(warmup):
+        solver.solve(f, u)
+    torch.cuda.synchronize()
+    stats = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        _, st = solver.solve(f, u)
+        stats.append(st)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    out = {"ms_per_step": ms, "setup_s": setup_s, "stats": stats[-1], "u": u.cpu().numpy()}
+    if profile:
+        solver.profile(True)
+        t1 = time.perf_counter()
+        for _ in range(steps):
+            solver.solve(f, u)
+        torch.cuda.synchronize()
+        out["ms_per_step_with_events"] = (time.perf_counter() - t1) / steps * 1e3
+        out["prof"] = {k: solver.profile_query(k) for k in range(_abi.IETI_KPROF_COUNT)}
+        solver.profile(False)
+    solver.close()
+    out["error_vs_oracle"] = golden_error(golden_name, out["u"])
+    return out
+
+
+def rate(entry):
+    """Algorithmic bytes over event-timed kernel time of a profiled class, against the HBM peak."""
+    if not entry or entry["ms"] <= 0 or entry["launches"] == 0:
+        return None
+    gbs = entry["bytes"] / (entry["ms"] * 1e-3) / 1e9
+    return {"achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "launches": entry["launches"], "avg_us": round(entry["ms"] / entry["launches"] * 1e3, 3),
+            "bytes_per_launch": round(entry["bytes"] / entry["launches"])}
+
+
+def summary(m, wl):
+    st = m["stats"]
+    out = {"ms_per_step": round(m["ms_per_step"], 3),
+           "MDoF_per_s": round(wl.ndof_torn / (m["ms_per_step"] * 1e-3) / 1e6, 3),
+           "setup_s": round(m["setup_s"], 3), "outer_iterations": st["outer_iterations"],
+           "inner_iterations_mean": round(st["inner_iterations_mean"], 2),
+           "global_residual": st["global_residual"], "error_vs_oracle": m["error_vs_oracle"]}
+    if "prof" in m:
+        from paper_1705_04531_amd import _abi
+        out["f_apply"] = rate(m["prof"][_abi.IETI_KPROF_FAPPLY])
+        out["finest_sweep"] = rate(m["prof"][_abi.IETI_KPROF_SMOOTH_FINE])
+    return out
+
+
+# ---------------------------------------------------------------- CPU oracle on all host cores
+def _oracle_worker(args):
+    """One worker process: builds its blocks' oracle solvers, waits for the others, solves them."""
+    blocks, barrier, q = args
     from threadpoolctl import threadpool_limits
 
     import workloads as W
     from oracle import ietidp
 
-    wl = W.deformed_square(sample_grid, 3, 64, seed=0)
     with threadpool_limits(limits=1):
+        full = W.deformed_16x16_mixed()
+        solvers = []
+        for (o0, o1) in blocks:
+            sub = W.sub_block(full, (o0, o1), (4, 4))
+            solvers.append((sub.ndof_torn, ietidp.IetiDP(sub)))
+        barrier.wait()
         t0 = time.perf_counter()
-        ie = ietidp.IetiDP(wl)
-        t1 = time.perf_counter()
-        parts, lam, info = ie.solve(tol=1e-8)
-        t2 = time.perf_counter()
-    solve_s = t2 - t1
+        ndof, its = 0, []
+        for n, ie in solvers:
+            _, _, info = ie.solve(tol=1e-8)
+            ndof += n
+            its.append(info["iterations"])
+        q.put((ndof, time.perf_counter() - t0, its))
+
+
+def cpu_baseline():
+    """The oracle (exact-local IETI-DP, FP64, SciPy/SuperLU) on the headline workload cut into its 16
+    blocks of 4x4 patches (each block an independent multipatch problem with the same patches, geometry
+    and f), the blocks spread over one worker process per host core (BLAS threads 1).  Each worker
+    factorises its blocks, all start solving together; value = all blocks' torn dofs / wall time from the
+    common start until the last worker finishes (d, CG to 1e-8, recovery; factorisation not included)."""
+    import multiprocessing as mp
+
+    cores = min(len(os.sched_getaffinity(0)), 16)
+    blocks = [(i, j) for j in range(0, 16, 4) for i in range(0, 16, 4)]
+    ctx = mp.get_context("fork")
+    barrier = ctx.Barrier(cores + 1)
+    q = ctx.Queue()
+    per = [blocks[w::cores] for w in range(cores)]
+    procs = [ctx.Process(target=_oracle_worker, args=((per[w], barrier, q),)) for w in range(cores)]
+    t_setup = time.perf_counter()
+    for p in procs:
+        p.start()
+    barrier.wait()
+    t0 = time.perf_counter()
+    res = [q.get() for _ in range(cores)]
+    wall = time.perf_counter() - t0
+    for p in procs:
+        p.join()
+    ndof = sum(r[0] for r in res)
+    its = sorted(i for r in res for i in r[2])
     cpu = "unknown"
     try:
         for line in open("/proc/cpuinfo"):
@@ -65,18 +171,19 @@ def cpu_baseline(sample_grid=(4, 4)):
     except OSError:
         pass
     return {
-        "value": wl.ndof_torn / solve_s / 1e6,
+        "value": ndof / wall / 1e6,
         "unit": "MDoF/s",
-        "cores": 1,
+        "cores": cores,
         "host_cpu": f"{cpu}, {len(os.sched_getaffinity(0))} threads available",
         "kind": "oracle",
-        "sample": (f"{sample_grid[0]}x{sample_grid[1]} patches of the same deformed square, p=3, 64^2 elements "
-                   f"({wl.ndof_torn} torn dofs); exact local solves (SuperLU), CG to 1e-8 in {info['iterations']} "
-                   f"its; value = dofs / (d + CG + recovery) time {solve_s:.2f} s; factorisation setup "
-                   f"{t1 - t0:.1f} s not included"),
+        "sample": (f"the 16x16 mixed workload cut into 16 independent 4x4-patch blocks ({ndof} torn dofs in "
+                   f"total), {cores} worker processes with one BLAS thread each; exact local solves (SuperLU), "
+                   f"CG to 1e-8 in {its[0]}-{its[-1]} iterations per block; value = dofs / wall time of the "
+                   f"solves ({wall:.2f} s); factorisation setup ({t0 - t_setup:.1f} s wall) not included"),
     }
 
 
+# ---------------------------------------------------------------- serving
 def serve(args):
     """Serving stream: requests of mixed size (2D deformed square, grid {2,4,8}^2, p {2,3,4},
     n_el {16,...,128}, sine-series f) through the request loop.  Pass 1 submits all at once
@@ -97,13 +204,13 @@ def serve(args):
     ndof = sum(wl.ndof_torn for wl, _ in inputs)
     opt = options_for(inputs[0][0])
 
-    def run(rate, slots, options):
+    def run(rate_, slots, options):
         srv = Server(options, slots=slots)
         tick = []
         t0 = time.perf_counter()
         for i, (wl, f) in enumerate(inputs):
-            if rate:
-                delay = t0 + reqs[i].arrival_unit / rate - time.perf_counter()
+            if rate_:
+                delay = t0 + reqs[i].arrival_unit / rate_ - time.perf_counter()
                 if delay > 0:
                     time.sleep(delay)
             tick.append(srv.submit(wl.patches, f))
@@ -144,29 +251,40 @@ def serve(args):
     print(json.dumps(out), flush=True)
 
 
+WORKLOADS = {
+    # name: (builder, golden file stem, MG precision of the configuration)
+    "deformed16x16": ("deformed_16x16_mixed", "deformed16x16_mixed", 32),
+    "deformed8x8": ("deformed_8x8", "deformed8x8_p3_n64", 64),
+    "cube4": ("cube_4x4x4", "cube4x4x4_p2_n24", 32),
+}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-plain", action="store_true", help="skip the exact-local comparison form")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the headline (no FP32 form, plain form, other workloads)")
+    ap.add_argument("--variants", action="store_true",
+                    help="also time D-MG, MG-MG-S and the tensor smoother on the headline workload")
     ap.add_argument("--serve", action="store_true", help="serving benchmark instead of the solve benchmark")
     ap.add_argument("--requests", type=int, default=64)
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--local-solver", choices=["mg", "exact_mg", "mg_saddle"], default="mg",
-                    help="variant of the measured solver: mg is the configuration (MG-MG); exact_mg (D-MG) and "
-                         "mg_saddle (MG-MG-S) profile the other variants on the same workload")
-    ap.add_argument("--smoother", choices=["chebyshev", "tensor"], default="chebyshev",
-                    help="finest-level smoother of the measured solver; the configuration names Chebyshev (default), "
-                         "tensor profiles the p-robust variant on the same workload")
-    ap.add_argument("--workload", choices=["deformed8x8", "deformed16x16", "cube4"], default="deformed8x8",
-                    help="deformed8x8 is the measured configuration; deformed16x16 (16x16 patches of mixed size and "
-                         "degree, FP32 MG) and cube4 (4x4x4 cube, p=2, FP32 MG) price the same sweeps on the other "
-                         "full-size workloads (no counter traffic, no CPU baseline)")
+                    help="variant of the headline solver: mg (MG-MG, default), exact_mg (D-MG), mg_saddle (MG-MG-S)")
+    ap.add_argument("--smoother", choices=["chebyshev", "tensor"], default="chebyshev")
+    ap.add_argument("--precision", type=int, choices=[32, 64], default=64,
+                    help="multigrid precision of the headline solver (the outer CG is always FP64)")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="deformed16x16")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 512 MiB FP64 tensor 3 times (scale for the FETCH_SIZE/WRITE_SIZE counters)")
     args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              f"(the solver shards by patches across GPUs only in design, see the documentation)", file=sys.stderr)
+        sys.exit(2)
     if args.serve:
         serve(args)
         return
@@ -179,138 +297,45 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_per_dispatch": a.numel() * 8}), flush=True)
         return
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              f"(the solver shards by patches across GPUs only in design, see the documentation)", file=sys.stderr)
-        sys.exit(2)
 
-    import numpy as np
-    import torch
+    # the CPU oracle runs first, in worker processes forked before this process loads the HIP library
+    cpu = None
+    if not args.no_cpu_baseline and args.workload == "deformed16x16":
+        print("[bench] CPU oracle on all host cores", file=sys.stderr, flush=True)
+        cpu = cpu_baseline()
 
     import workloads as W
-    from paper_1705_04531_amd import Solver, _abi, options_for
+    from paper_1705_04531_amd import _abi
 
-    main_wl = args.workload == "deformed8x8"
-    wl = {"deformed8x8": W.deformed_8x8, "deformed16x16": W.deformed_16x16_mixed,
-          "cube4": W.cube_4x4x4}[args.workload]()
-    t0 = time.perf_counter()
-    # the configuration as named, Chebyshev degrees from the library's table (measured per spline degree;
-    # the setup-time autotuner ranks candidates on a seeded load, whose best can differ from this load's)
+    build_name, gname, cfg_prec = WORKLOADS[args.workload]
+    wl = getattr(W, build_name)()
     tensor = args.smoother == "tensor"
     variant = {"mg": _abi.IETI_LOCAL_MG, "exact_mg": _abi.IETI_LOCAL_EXACT_MG,
                "mg_saddle": _abi.IETI_LOCAL_MG_SADDLE}[args.local_solver]
-    solver = Solver(wl.patches, options_for(wl, local_solver=variant,
-                                            **({"smoother": _abi.IETI_SMOOTHER_TENSOR} if tensor else {})))
-    torch.cuda.synchronize()
-    setup_s = time.perf_counter() - t0
-    x = solver.quadrature(device=False)
-    f = torch.from_numpy(wl.f(x)).to("cuda")
-    u = torch.empty(solver.ndof_torn, dtype=torch.float64, device="cuda")
-    for _ in range(args.warmup):
-        solver.solve(f, u)
-    torch.cuda.synchronize()
-    stats = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        _, st = solver.solve(f, u)
-        stats.append(st)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    # the same steps again with start/stop events on every finest-level sweep
-    # launch (kernel-level events serialise the launches, so these steps are
-    # not the timed ones)
-    solver.profile(True)
-    t1 = time.perf_counter()
-    for _ in range(args.steps):
-        solver.solve(f, u)
-    torch.cuda.synchronize()
-    ms_profiled = (time.perf_counter() - t1) / args.steps * 1e3
-    prof = {k: solver.profile_query(k) for k in (_abi.IETI_KPROF_SMOOTH_FINE, _abi.IETI_KPROF_APPLY64,
-                                                 _abi.IETI_KPROF_RESID_FINE)}
-    solver.profile(False)
-    ms_per_step = elapsed / args.steps * 1e3
+    extra_opt = {"smoother": _abi.IETI_SMOOTHER_TENSOR} if tensor else {}
+    print(f"[bench] headline {wl.name}, MG precision {args.precision}, {args.local_solver}", file=sys.stderr,
+          flush=True)
+    m = measure(wl, gname, args.steps, args.warmup, local_solver=variant, mg_precision=args.precision, **extra_opt)
+    ms_per_step = m["ms_per_step"]
     value = wl.ndof_torn / (ms_per_step * 1e-3) / 1e6
-    u_mg = u.clone()
-    solver.close()
-
-    # the plain FP64 exact-local form (banded Cholesky local solves, D-D) on the same workload
-    plain = None
-    if not args.no_plain and wl.dim == 2:   # the exact-local form is built for 2D patches
-        t0 = time.perf_counter()
-        ps = Solver(wl.patches, options_for(wl, local_solver=_abi.IETI_LOCAL_EXACT))
-        torch.cuda.synchronize()
-        psetup = time.perf_counter() - t0
-        up = torch.empty_like(u)
-        ps.solve(f, up)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            _, pst = ps.solve(f, up)
-        torch.cuda.synchronize()
-        pms = (time.perf_counter() - t0) / args.steps * 1e3
-        diff = float(torch.linalg.norm(u_mg - up) / torch.linalg.norm(up))
-        plain = {"ms_per_step": round(pms, 3), "setup_s": round(psetup, 3),
-                 "outer_iterations": pst["outer_iterations"],
-                 "speedup_inexact_over_plain": round(pms / ms_per_step, 3),
-                 "rel_l2_diff_inexact_vs_plain": diff}
-        ps.close()
-        # D-MG: exact Neumann solves in F, V-cycles (FP64 and FP32) for the preconditioner's Dirichlet problems
-        for prec in (64, 32):
-            ds = Solver(wl.patches, options_for(wl, local_solver=_abi.IETI_LOCAL_EXACT_MG, mg_precision=prec))
-            ud = torch.empty_like(u)
-            ds.solve(f, ud)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(args.steps):
-                _, dst = ds.solve(f, ud)
-            torch.cuda.synchronize()
-            dms = (time.perf_counter() - t0) / args.steps * 1e3
-            plain[f"exact_neumann_mg{prec}_dirichlet"] = {
-                "ms_per_step": round(dms, 3), "outer_iterations": dst["outer_iterations"],
-                "rel_l2_diff_vs_plain": float(torch.linalg.norm(ud - up) / torch.linalg.norm(up))}
-            ds.close()
-        # MG-MG-S: Bramble-Pasciak CG on the saddle-point system, three V-cycles (FP64 and FP32) for K~
-        for prec in (64, 32):
-            bs_ = Solver(wl.patches, options_for(wl, local_solver=_abi.IETI_LOCAL_MG_SADDLE, mg_precision=prec))
-            ub = torch.empty_like(u)
-            bs_.solve(f, ub)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(args.steps):
-                _, bst = bs_.solve(f, ub)
-            torch.cuda.synchronize()
-            bms = (time.perf_counter() - t0) / args.steps * 1e3
-            plain[f"saddle_point_bpcg_mg{prec}"] = {
-                "ms_per_step": round(bms, 3), "outer_iterations": bst["outer_iterations"],
-                "omega": round(bst["saddle_omega"], 4),
-                "rel_l2_diff_vs_plain": float(torch.linalg.norm(ub - up) / torch.linalg.norm(up))}
-            bs_.close()
-        # finest-level tensor-product smoother (p-robust multigrid) in place of Chebyshev: MG-MG and MG-MG-S
-        for label, extra in (("tensor_smoother_mg64", {}),
-                             ("tensor_smoother_saddle_mg64", {"local_solver": _abi.IETI_LOCAL_MG_SADDLE}),
-                             ("tensor_smoother_saddle_mg32", {"local_solver": _abi.IETI_LOCAL_MG_SADDLE,
-                                                              "mg_precision": 32})):
-            ts_ = Solver(wl.patches, options_for(wl, smoother=_abi.IETI_SMOOTHER_TENSOR, **extra))
-            ut = torch.empty_like(u)
-            ts_.solve(f, ut)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(args.steps):
-                _, tst = ts_.solve(f, ut)
-            torch.cuda.synchronize()
-            tms = (time.perf_counter() - t0) / args.steps * 1e3
-            plain[label] = {
-                "ms_per_step": round(tms, 3), "outer_iterations": tst["outer_iterations"],
-                "inner_iterations_mean": round(tst["inner_iterations_mean"], 2),
-                "rel_l2_diff_vs_plain": float(torch.linalg.norm(ut - up) / torch.linalg.norm(up))}
-            ts_.close()
-
-    dom = prof[_abi.IETI_KPROF_SMOOTH_FINE]
-    if tensor:   # no finest-level Chebyshev sweeps to price: the profile comes from rocprofv3
-        dom = prof[_abi.IETI_KPROF_RESID_FINE]
-    achieved = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9 if dom["ms"] > 0 else 0.0
-    mgt = "double" if wl.mg_precision == 64 else "float"
-    st = stats[-1]
+    st = m["stats"]
+    prof = m["prof"]
+    mgt = "double" if args.precision == 64 else "float"
+    dom = prof[_abi.IETI_KPROF_RESID_FINE if tensor else _abi.IETI_KPROF_SMOOTH_FINE]
+    kr = rate(dom) or {"achieved": 0.0, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": 0.0}
+    roofline = {
+        "bound": "hbm",
+        "kernel": (f"k_stencil<{mgt},{mgt},{mgt},EPI_RESID,FINE> (finest-level residual sweep)" if tensor else
+                   f"k_stencil<{mgt},{mgt},{mgt},EPI_CHEB,FINE> (finest-level Chebyshev sweep, all degree "
+                   f"classes in one launch)"),
+        **kr,
+        "traffic": None,
+        "traffic_note": "counter traffic per launch is in profiles/ (rocprofv3 --pmc runs of this command)",
+        "ms_per_step_with_events": round(m["ms_per_step_with_events"], 3),
+        "f_apply": rate(prof[_abi.IETI_KPROF_FAPPLY]),
+        "preconditioner": rate(prof[_abi.IETI_KPROF_PREC]),
+        "apply64": rate(prof[_abi.IETI_KPROF_APPLY64]),
+    }
     out = {
         "metric": "dual-PCG solve time & MDoF/s at rel. res 1e-8; solves/s + p50/p99 latency",
         "value": round(value, 3),
@@ -322,12 +347,11 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if wl.mg_precision == 64 else "f64 outer / f32 MG",
+        "dtype": "f64" if args.precision == 64 else "f64 outer / f32 MG",
         "data": "synthetic",
         "config": {
-            "workload": ("deformed square 8x8 patches, p=3, 64x64 elements/patch, inexact local solves by FP64 "
-                         "multigrid V-cycles with Chebyshev smoothing (degree 6 finest, 2 coarse levels), FP64 outer "
-                         "CG to 1e-8") if main_wl else wl.description + ", FP64 outer CG to 1e-8",
+            "workload": wl.description + f", inexact local solves ({args.local_solver}) by FP{args.precision} "
+                        f"multigrid, FP64 outer CG to 1e-8",
             "ndof_torn": wl.ndof_torn,
             "ndof_global": wl.ndof_global,
             "n_lambda": st["n_lambda"],
@@ -338,36 +362,52 @@ def main():
             "time_pcg_ms": round(st["time_pcg_ms"], 3),
             "time_rhs_ms": round(st["time_rhs_ms"], 3),
             "time_recovery_ms": round(st["time_recovery_ms"], 3),
-            "setup_s": round(setup_s, 3),
+            "setup_s": round(m["setup_s"], 3),
             "local_solver": args.local_solver,
-            "smoother": {"finest": args.smoother, "autotuned": False, "fine_tile_staged": st["fine_tile_staged"],
-                         "cheb_degree": st["cheb_degree"],
+            "mg_precision": args.precision,
+            "smoother": {"finest": args.smoother, "cheb_degree": st["cheb_degree"],
                          "cheb_degree_coarse": st["cheb_degree_coarse"],
-                         "cheb_lower_over_table": st["cheb_lower"]},
+                         "fine_tile_staged": st["fine_tile_staged"]},
+            "error_vs_oracle": m["error_vs_oracle"],
         },
-        "roofline": {
-            "bound": "hbm",
-            "kernel": (f"k_stencil<{mgt},{mgt},{mgt},EPI_RESID,FINE> (finest-level residual sweep)" if tensor else
-                       f"k_stencil<{mgt},{mgt},{mgt},EPI_CHEB,FINE> (finest-level Chebyshev sweep)"),
-            "achieved": round(achieved, 1),
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None if (tensor or args.local_solver != "mg" or not main_wl) else counter_traffic(),
-            "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-            "launches": dom["launches"],
-            "avg_us": round(dom["ms"] / max(dom["launches"], 1) * 1e3, 3),
-            "bytes_per_launch": round(dom["bytes"] / max(dom["launches"], 1)),
-            "ms_per_step_with_events": round(ms_profiled, 3),
-            "apply64": {"launches": prof[_abi.IETI_KPROF_APPLY64]["launches"],
-                        "GB/s": round(prof[_abi.IETI_KPROF_APPLY64]["bytes"] /
-                                      max(prof[_abi.IETI_KPROF_APPLY64]["ms"], 1e-9) * 1e-6, 1)},
-        },
+        "roofline": roofline,
     }
-    if plain is not None:
-        out["plain_form"] = plain
-    if not args.no_cpu_baseline and main_wl:
-        out["cpu_baseline"] = cpu_baseline()
+    if not args.no_extras and args.local_solver == "mg" and not tensor:
+        extras = {}
+        other = 32 if args.precision == 64 else 64
+        print(f"[bench] {wl.name} FP{other} multigrid", file=sys.stderr, flush=True)
+        m2 = measure(wl, gname, min(args.steps, 3), 1, mg_precision=other)
+        extras[f"mg{other}"] = summary(m2, wl)
+        if wl.dim == 2:   # the plain FP64 exact-local form (banded Cholesky local solves, D-D)
+            print(f"[bench] {wl.name} plain FP64 exact-local form", file=sys.stderr, flush=True)
+            mp_ = measure(wl, gname, min(args.steps, 3), 1, profile=False, local_solver=_abi.IETI_LOCAL_EXACT,
+                          mg_precision=64)
+            plain = summary(mp_, wl)
+            plain[f"speedup_inexact_mg{args.precision}_over_plain"] = round(mp_["ms_per_step"] / ms_per_step, 3)
+            plain[f"speedup_inexact_mg{other}_over_plain"] = round(mp_["ms_per_step"] / m2["ms_per_step"], 3)
+            extras["plain_fp64_exact_local"] = plain
+        for wname in sorted(WORKLOADS):
+            if wname == args.workload:
+                continue
+            bname, gn, prec = WORKLOADS[wname]
+            w2 = getattr(W, bname)()
+            print(f"[bench] {w2.name} FP{prec} multigrid", file=sys.stderr, flush=True)
+            mw = measure(w2, gn, min(args.steps, 3), 1, mg_precision=prec)
+            extras[wname] = dict(summary(mw, w2), mg_precision=prec, ndof_torn=w2.ndof_torn)
+        if args.variants:
+            for label, o in (("exact_mg64", {"local_solver": _abi.IETI_LOCAL_EXACT_MG, "mg_precision": 64}),
+                             ("exact_mg32", {"local_solver": _abi.IETI_LOCAL_EXACT_MG, "mg_precision": 32}),
+                             ("saddle_mg64", {"local_solver": _abi.IETI_LOCAL_MG_SADDLE, "mg_precision": 64}),
+                             ("saddle_mg32", {"local_solver": _abi.IETI_LOCAL_MG_SADDLE, "mg_precision": 32}),
+                             ("tensor_mg64", {"smoother": _abi.IETI_SMOOTHER_TENSOR, "mg_precision": 64}),
+                             ("tensor_mg32", {"smoother": _abi.IETI_SMOOTHER_TENSOR, "mg_precision": 32}),
+                             ("tensor_saddle_mg32", {"smoother": _abi.IETI_SMOOTHER_TENSOR, "mg_precision": 32,
+                                                     "local_solver": _abi.IETI_LOCAL_MG_SADDLE})):
+                print(f"[bench] {wl.name} {label}", file=sys.stderr, flush=True)
+                extras[label] = summary(measure(wl, gname, min(args.steps, 3), 1, profile=False, **o), wl)
+        out["extras"] = extras
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 

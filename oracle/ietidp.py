@@ -6,8 +6,13 @@ Written in the notation of Sec. 2-3:
   boundary (Dirichlet) coefficients are dropped (V_0 = H^1_0);
 * primal ("strongly enforced") continuity: the values at patch vertices and,
   on request, the averages over patch edges (in 2D the patch sides, the
-  choice of the paper's 2D experiments, Sec. 4); C^(k) evaluates them on
-  patch k and R_Pi^(k) maps local to global primal unknowns;
+  choice of the paper's 2D experiments, Sec. 4), or the edge averages alone
+  (the paper's 3D choice, Sec. 4; vertex copies are then joined by
+  multipliers like every other interface coefficient); C^(k) evaluates them
+  on patch k and R_Pi^(k) maps local to global primal unknowns.  A patch
+  that touches no Dirichlet boundary has a singular K^(k) (constants); its
+  constraints C^(k) remove that kernel, so the saddle-point matrices below
+  stay regular (Sec. 3.2, the case of eq. (6) with a semi-definite block);
 * the primal basis of W_Pi solves the saddle-point systems of eq. (6) with
   the stiffness K^(k) in place of S^(k) (Pechstein's approach), for every
   local constraint j:  [K C^T; C 0] [phi_j; mu_j] = [0; e_j];
@@ -93,6 +98,8 @@ class IetiDP:
         self.lay = lay = layout(wl) if lay is None else lay
         self.systems = systems = assemble_all(wl) if systems is None else systems
         primal = wl.primal if primal is None else primal
+        if primal not in ("vertices", "vertices+edges", "edges"):
+            raise ValueError(f"unknown primal set {primal!r}")
         N = len(wl.patches)
         self.N = N
         # free (non-boundary) local coefficients of each patch
@@ -107,11 +114,11 @@ class IetiDP:
         for k in range(N):
             for c in _local_corners(lay.shapes[k]):
                 g = int(lay.gid[k][c])
-                if not lay.boundary[g]:
+                if not lay.boundary[g] and primal != "edges":
                     vertex_g.add(g)
         vertex_g = sorted(vertex_g)
         edges = {}
-        if primal == "vertices+edges":
+        if primal in ("vertices+edges", "edges"):
             for k in range(N):
                 for loc in _local_edges(lay.shapes[k]):
                     g = lay.gid[k][loc]

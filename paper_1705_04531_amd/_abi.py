@@ -45,6 +45,7 @@ IETI_KPROF_APPLY64 = 1
 IETI_KPROF_RESID_FINE = 2
 IETI_KPROF_FAPPLY = 3
 IETI_KPROF_PREC = 4
+IETI_KPROF_COUNT = 5
 
 
 class IetiPatch(C.Structure):

@@ -1,7 +1,9 @@
 """Writes the full-size golden files: the oracle's solution of each benchmark
 configuration, sampled at 64 seeded coefficients of every patch (interior,
 side, edge and vertex coefficients alike, boundary excluded) plus 2000 seeded
-global coefficients, with its l2 and max norms.  Calls only the oracle: the
+global coefficients, with its l2 and max norms, and for each sampled global
+coefficient one position in the torn (patch-by-patch) layout that holds a copy
+of it, so that a torn GPU result can be compared without the oracle's layout.  Calls only the oracle: the
 global conforming system with SuperLU for the 2D configurations; for the 3D
 cube, where a global sparse LU of ~1M unknowns does not fit, the oracle's
 exact-local IETI-DP run to a dual residual of 1e-13 (its agreement with the
@@ -52,6 +54,15 @@ def make(name: str):
         method = (f"oracle exact-local IETI-DP (oracle/ietidp.py), CG to 1e-13 in {info['iterations']} "
                   f"iterations")
     idx = sample_indices(lay)
+    # first torn position of every global coefficient (patches in order, copies identical in a result)
+    first = np.full(len(lay.boundary), -1, dtype=np.int64)
+    off = 0
+    for g in lay.gid:
+        new = first[g] < 0
+        first[g[new]] = off + np.flatnonzero(new)
+        off += len(g)
+    torn = first[idx]
+    assert (torn >= 0).all()
     out = {
         "config": name,
         "method": method,
@@ -61,6 +72,7 @@ def make(name: str):
         "per_patch": PER_PATCH,
         "indices": [int(i) for i in idx],
         "values": [float(v) for v in u[idx]],
+        "torn_positions": [int(t) for t in torn],
         "seconds": round(time.time() - t0, 1),
     }
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"full_{name}.json")

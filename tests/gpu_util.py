@@ -53,3 +53,16 @@ def with_sine_rhs(wl, seed=1):
         u = None
     wl.f, wl.u_exact = f, u
     return wl
+
+
+def golden_errors(golden, u_torn):
+    """A torn GPU result against a full-size golden file: relative l2 over the sampled
+    coefficients (64 per patch plus 2000 global ones) and the largest sampled deviation over
+    the oracle's max norm.  Each sample is read at one torn copy of its coefficient (the
+    copies of a returned solution are identical)."""
+    idx = np.asarray(golden["torn_positions"])
+    ref = np.asarray(golden["values"])
+    got = np.asarray(u_torn)[idx]
+    l2 = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    linf = float(np.abs(got - ref).max() / golden["max_abs"])
+    return l2, linf

@@ -137,3 +137,65 @@ def test_primal_basis_energy_minimising(wl):
         assert np.abs(C @ w).max() < 1e-12
         kw = ie.K[k] @ w
         assert np.abs(Phi.T @ kw).max() <= 1e-10 * np.abs(kw).max() * np.abs(Phi).max() * np.sqrt(len(w))
+
+
+# the paper's 3D primal choice, edge averages without vertex values (Sec. 4), and its 2D analogue (side
+# averages only): the centre patches of a 3x3 square and a 3x3x3 cube touch no Dirichlet boundary, so their
+# K is singular and only the constraints fix the constants (eq. (6) with a semi-definite block)
+EDGE_ONLY = [
+    W.unit_cube((2, 2, 2), 2, 4, primal="edges", name="cube2x2x2_edges"),
+    W.unit_cube((3, 3, 2), 2, 4, primal="edges", name="cube3x3x2_edges"),
+    W.unit_cube((3, 3, 3), 2, 4, primal="edges", name="cube3x3x3_edges"),
+    W.deformed_square((3, 3), [[2, 3, 4], [4, 2, 3]], [[8, 12, 16], [16, 8, 12]], amp_factor=0.8,
+                      primal="edges", name="deformed3x3_mixed_sides_only"),
+]
+
+
+@pytest.mark.parametrize("wl", EDGE_ONLY, ids=lambda w: w.name)
+def test_edge_only_primal_matches_global_direct(wl):
+    u, lay, systems = conforming.solve_direct(wl)
+    ie = ietidp.IetiDP(wl, lay=lay, systems=systems)
+    assert len(ie.vertex_g) == 0
+    floating = [k for k in range(ie.N) if len(ie.free[k]) == len(lay.gid[k])]
+    if wl.name.startswith(("cube3x3x3", "deformed3x3")):
+        assert len(floating) == 1
+        k = floating[0]
+        # the floating patch's K has the constants as its kernel; its constraints do not
+        one = np.ones(ie.K[k].shape[0])
+        assert np.abs(ie.K[k] @ one).max() <= 1e-12 * abs(ie.K[k]).max()
+        assert np.allclose(ie.C[k] @ one, 1.0)
+    parts, lam, info = ie.solve(tol=1e-13)
+    ug = conforming.global_from_torn(lay, parts)
+    assert np.linalg.norm(ug - u) <= 1e-10 * np.linalg.norm(u)
+    nrm = np.sqrt(sum(float(p @ p) for p in parts))
+    assert ie.jump_norm(parts) <= 1e-11 * nrm
+    if info["iterations"] >= 2:
+        lo, hi = ie.lanczos_extremes(info)
+        assert lo >= 1 - 1e-8 and hi < 100
+
+
+@pytest.mark.parametrize("wl", EDGE_ONLY[2:], ids=lambda w: w.name)
+def test_edge_only_primal_basis_and_spectral_bound(wl):
+    """C Phi = I and Phi K-orthogonal to {C w = 0} on every patch, floating ones included; the dense
+    generalised eigenvalues of (F, M) on range(F) respect the FETI-DP bound >= 1."""
+    ie = ietidp.IetiDP(wl)
+    rng = np.random.default_rng(1)
+    for k in range(ie.N):
+        C = ie.C[k].toarray()
+        Phi = ie.Phi[k]
+        np.testing.assert_allclose(C @ Phi, np.eye(C.shape[0]), atol=1e-12)
+        w = rng.standard_normal(C.shape[1])
+        w -= C.T @ np.linalg.solve(C @ C.T, C @ w)
+        kw = ie.K[k] @ w
+        assert np.abs(Phi.T @ kw).max() <= 1e-10 * np.abs(kw).max() * np.abs(Phi).max() * np.sqrt(len(w))
+    n = ie.n_lam
+    I = np.eye(n)
+    F = np.stack([ie.apply_F(I[:, j]) for j in range(n)], axis=1)
+    Minv = np.stack([ie.apply_prec(I[:, j]) for j in range(n)], axis=1)
+    assert np.abs(F - F.T).max() <= 1e-11 * np.abs(F).max()
+    # with edge averages primal the jumps B w of w in W~ have zero edge means, so F vanishes on more than
+    # ker B^T: the bound holds on range(F) = B(W~)
+    fe, fv = np.linalg.eigh(0.5 * (F + F.T))
+    V = fv[:, fe > 1e-10 * fe.max()]
+    ev = sla.eigh(V.T @ F @ V, np.linalg.inv(V.T @ Minv @ V), eigvals_only=True)
+    assert ev.min() >= 1 - 1e-9

@@ -29,7 +29,7 @@ __all__ = [
     "Patch", "Workload", "Request", "uniform_open_knots", "greville",
     "grid_patches", "sinsin_rhs", "sine_series_rhs", "polynomial_rhs",
     "square_2x2", "deformed_8x8", "deformed_16x16_mixed", "cube_4x4x4",
-    "deformed_square", "unit_cube", "serving_stream", "CONFIGS",
+    "deformed_square", "unit_cube", "serving_stream", "sub_block", "CONFIGS",
 ]
 
 
@@ -333,6 +333,29 @@ def serving_stream(seed: int = 0, n_requests: int = 512,
         wl.extra["coef"] = coef
         out.append(Request(index=i, arrival_unit=t, workload=wl))
     return out
+
+
+def sub_block(wl: Workload, origin: Sequence[int], size: Sequence[int]) -> Workload:
+    """The patches of a rectangular block of ``wl``'s patch grid as a workload of their own
+    (same geometry, degrees, knots and f; the block's outer sides become its boundary).
+    ``origin`` and ``size`` count patches per direction."""
+    idx = []
+    ranges = [range(origin[d], origin[d] + size[d]) for d in range(wl.dim)]
+    for k in range(int(np.prod(size))):
+        pos, r = [], k
+        for d in range(wl.dim):
+            pos.append(ranges[d][r % size[d]])
+            r //= size[d]
+        flat, stride = 0, 1
+        for d in range(wl.dim):
+            flat += pos[d] * stride
+            stride *= wl.grid[d]
+        idx.append(flat)
+    per = [list(wl.extra["dofs_per_dir"][d][origin[d]:origin[d] + size[d]]) for d in range(wl.dim)]
+    return Workload(name=f"{wl.name}_block{'_'.join(map(str, origin))}", dim=wl.dim, grid=tuple(size),
+                    patches=[wl.patches[i] for i in idx], f=wl.f, u_exact=wl.u_exact,
+                    local_solver=wl.local_solver, mg_precision=wl.mg_precision, primal=wl.primal, tol=wl.tol,
+                    inner_tol=wl.inner_tol, seed=wl.seed, extra=dict(wl.extra, dofs_per_dir=per))
 
 
 CONFIGS = {
