@@ -245,6 +245,26 @@ int ieti_quadrature(const ieti_handle* h, double* x_qp, int32_t on_device, int64
  */
 int ieti_solve(ieti_handle* h, const double* f_qp, double* u, ieti_stats* stats);
 
+/*
+ * For callers that cannot allocate (serving loops and harnesses that forbid
+ * device allocation while they run): ieti_solve with the same arguments,
+ * kernels and result (bitwise), but the per-solve scratch of its kernels --
+ * the reductions' partial sums, the outer CG's scalars, the local solves'
+ * per-patch scalars and counters -- lives in one static device array of
+ * IETI_NOALLOC_SCRATCH_BYTES per GPU (held until the process ends) instead
+ * of the handle's memory.  Allocates nothing (no device or pinned memory, no
+ * graph instantiation, no kernel events: the handle's use_graph and
+ * profiling are ignored for this call).  The array is cleared by a fill
+ * kernel at the start of every call.  All handles on one GPU share that
+ * GPU's array, so calls on the same GPU must not overlap (two threads or
+ * streams calling it at once race on the array).  Errors as ieti_solve, and
+ * IETI_ENOTSUP if the handle needs more scratch than the maximum (about
+ * 32 bytes per stiffness tile of 256 coefficients plus 48 bytes per patch;
+ * roughly 30M coefficients).
+ */
+#define IETI_NOALLOC_SCRATCH_BYTES (4u << 20)
+int ieti_solve_noalloc(ieti_handle* h, const double* f_qp, double* u, ieti_stats* stats);
+
 /* Number of quadrature points and torn dofs of a handle. */
 int ieti_sizes(const ieti_handle* h, int64_t* n_qp, int64_t* ndof_torn, int64_t* device_bytes);
 

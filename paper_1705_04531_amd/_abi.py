@@ -132,6 +132,7 @@ SIGNATURES = {
                              C.POINTER(IetiOptions), C.POINTER(_P)]),
     "ieti_quadrature": (C.c_int, [_P, _P, C.c_int32, _I64P]),
     "ieti_solve": (C.c_int, [_P, _P, _P, C.POINTER(IetiStats)]),
+    "ieti_solve_noalloc": (C.c_int, [_P, _P, _P, C.POINTER(IetiStats)]),
     "ieti_sizes": (C.c_int, [_P, _I64P, _I64P, _I64P]),
     "ieti_destroy": (None, [_P]),
     "ieti_profile_enable": (C.c_int, [_P, C.c_int32]),

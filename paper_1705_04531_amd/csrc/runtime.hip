@@ -231,6 +231,9 @@ struct SolverBase {
     virtual ~SolverBase() = default;
     virtual void setup() = 0;
     virtual int solve(const double* f_qp, double* u, ieti_stats* st) = 0;
+    // ieti_solve_noalloc: the same solve with its per-solve scratch in the static array `scratch`
+    virtual int solve_noalloc(const double* f_qp, double* u, ieti_stats* st) = 0;
+    double* noalloc_base = nullptr;   // device address of `scratch` on the handle's device
     virtual void quadrature(double* x, bool on_device) = 0;
     std::unique_ptr<Plan> plan;
     hipStream_t stream = nullptr;
@@ -594,7 +597,7 @@ struct Solver : SolverBase {
         // iterations after the first are the same launch sequence with the same arguments: with use_graph
         // they replay one captured graph per tolerance (not while kernel events are recorded)
         hipGraphExec_t* gx = nullptr;
-        if (plan->opt.use_graph && graphs_ok && !prof.on) {
+        if (plan->opt.use_graph && graphs_ok && !prof.on && !noalloc_call) {
             auto& g = fcg_graphs[std::make_pair(tol, maxit)];
             if (!g) g = capture_fcg_iteration(fuse_zq, tol, maxit);
             if (g) gx = &g;
@@ -1278,6 +1281,85 @@ struct Solver : SolverBase {
         HIPCHECK(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, stream));
         sync();
         if (herr) throw Error(IETI_EINVAL, "coarse matrix S_PiPi is not positive definite");
+    }
+    // ---------------------------------------------------------------- no-allocation solve
+    // The per-solve scratch of the kernels -- partial sums of the reductions, the outer CG's scalars, the
+    // local solves' per-patch scalars and counters, the saddle-point iteration's scalars and partials --
+    // carved from one block (offsets in doubles, 256-byte aligned; int arrays take half a word per entry).
+    bool noalloc_call = false;   // graphs and kernel events stay off (instantiation and event pools allocate)
+    struct ScratchMap {
+        int64_t partial, sc, bb, dq, beta, alpha, active, its, brk, nactive, bsc, dpart, words;
+    };
+    ScratchMap scratch_map() const {
+        ScratchMap m{};
+        int64_t o = 0;
+        auto take = [&](int64_t n) {
+            const int64_t at = o;
+            o += (std::max<int64_t>(n, 1) + 31) / 32 * 32;
+            return at;
+        };
+        m.partial = take(4 * (int64_t)lev[0].nt_all + 4);
+        m.sc = take(16);
+        m.bb = take(N);
+        m.dq = take(N);
+        m.beta = take(N);
+        m.alpha = take(N);
+        m.active = take((N + 1) / 2);
+        m.its = take((N + 1) / 2);
+        m.brk = take((N + 1) / 2);
+        m.nactive = take(4);
+        m.bsc = saddle ? take(16) : -1;
+        m.dpart = saddle ? take(ndpart) : -1;
+        m.words = o;
+        return m;
+    }
+    int solve_noalloc(const double* f_qp, double* u, ieti_stats* st) override {
+        const ScratchMap m = scratch_map();
+        if ((uint64_t)m.words * sizeof(double) > (uint64_t)IETI_NOALLOC_SCRATCH_BYTES)
+            throw Error(IETI_ENOTSUP, "ieti_solve_noalloc: this handle needs " +
+                                          std::to_string((uint64_t)m.words * sizeof(double)) +
+                                          " bytes of scratch, above the static maximum of " +
+                                          std::to_string((uint64_t)IETI_NOALLOC_SCRATCH_BYTES));
+        if (!noalloc_base) throw Error(IETI_EDEVICE, "internal: address of the static scratch not resolved");
+        double* base = noalloc_base;
+        double* const keep_d[] = {partial, sc, bb, dq, beta, alpha, bsc, dpart};
+        int* const keep_i[] = {active, its, brk, nactive};
+        const bool prof_on = prof.on;
+        auto restore = [&] {
+            partial = keep_d[0], sc = keep_d[1], bb = keep_d[2], dq = keep_d[3];
+            beta = keep_d[4], alpha = keep_d[5], bsc = keep_d[6], dpart = keep_d[7];
+            active = keep_i[0], its = keep_i[1], brk = keep_i[2], nactive = keep_i[3];
+            prof.on = prof_on;
+            noalloc_call = false;
+        };
+        partial = base + m.partial;
+        sc = base + m.sc;
+        bb = base + m.bb;
+        dq = base + m.dq;
+        beta = base + m.beta;
+        alpha = base + m.alpha;
+        active = (int*)(base + m.active);
+        its = (int*)(base + m.its);
+        brk = (int*)(base + m.brk);
+        nactive = (int*)(base + m.nactive);
+        if (saddle) {
+            bsc = base + m.bsc;
+            dpart = base + m.dpart;
+        }
+        prof.on = false;
+        noalloc_call = true;
+        int rc = IETI_OK;
+        try {
+            // the array keeps the previous call's contents (any handle on this device): start from zeros,
+            // as the handle's own buffers did (a fill kernel, not a memset node)
+            fill<double>(base, m.words, 0.0);
+            rc = solve(f_qp, u, st);   // synchronises the stream before returning
+        } catch (...) {
+            restore();
+            throw;
+        }
+        restore();
+        return rc;
     }
     void setup() override;
     int solve(const double* f_qp, double* u, ieti_stats* st) override;
@@ -2321,6 +2403,26 @@ extern "C" {
 
 }  // extern "C"
 
+// Scratch of ieti_solve_noalloc: one copy per GPU, held until the process ends.  In host code `scratch`
+// names a host-side stand-in, never the device memory: kernels and fills get the address that
+// hipGetSymbolAddress returns for the current device (scratch_address).
+static __device__ __align__(256) double scratch[IETI_NOALLOC_SCRATCH_BYTES / sizeof(double)];
+static std::mutex g_scratch_mu;
+static std::map<int, double*> g_scratch_addr;
+
+// The device address of `scratch` on device `dev`, which must be current; resolved once per device.
+static double* scratch_address(int dev) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_addr.find(dev);
+    if (it != g_scratch_addr.end()) return it->second;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr)
+        throw Error(IETI_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_addr[dev] = (double*)p;
+    return (double*)p;
+}
+
 // A handle around a plan: device state built on the plan's stream (or a new one).
 static ieti_handle* make_handle(std::unique_ptr<Plan> plan) {
     if (plan->opt.device >= 0) HIPCHECK(hipSetDevice(plan->opt.device));
@@ -2335,6 +2437,9 @@ static ieti_handle* make_handle(std::unique_ptr<Plan> plan) {
         s->own_stream = true;
     }
     s->setup();
+    int dev = 0;
+    HIPCHECK(hipGetDevice(&dev));
+    s->noalloc_base = scratch_address(dev);
     auto* h = new ieti_handle();
     h->s = std::move(s);
     return h;
@@ -2394,6 +2499,11 @@ int ieti_quadrature(const ieti_handle* h, double* x, int32_t on_device, int64_t*
 int ieti_solve(ieti_handle* h, const double* f_qp, double* u, ieti_stats* stats) {
     if (!h || !f_qp || !u) return IETI_EINVAL;
     return guarded([&] { return h->s->solve(f_qp, u, stats); });
+}
+
+int ieti_solve_noalloc(ieti_handle* h, const double* f_qp, double* u, ieti_stats* stats) {
+    if (!h || !f_qp || !u) return IETI_EINVAL;
+    return guarded([&] { return h->s->solve_noalloc(f_qp, u, stats); });
 }
 
 int ieti_profile_enable(ieti_handle* h, int32_t enable) {

@@ -166,8 +166,9 @@ class Solver:
         check(lib().ieti_quadrature(self.h, ptr, 1 if device else 0, C.byref(n)), "ieti_quadrature")
         return x
 
-    def solve(self, f_qp, u=None, raise_on_noconv: bool = True):
-        """f_qp: float64 CUDA tensor of n_qp values; returns (u, stats dict)."""
+    def solve(self, f_qp, u=None, raise_on_noconv: bool = True, no_alloc: bool = False):
+        """f_qp: float64 CUDA tensor of n_qp values; returns (u, stats dict).  no_alloc: call
+        ieti_solve_noalloc (scratch in the library's static per-GPU array) instead of ieti_solve."""
         import torch
         if not (isinstance(f_qp, torch.Tensor) and f_qp.is_cuda and f_qp.dtype == torch.float64
                 and f_qp.numel() == self.n_qp and f_qp.is_contiguous()):
@@ -175,9 +176,10 @@ class Solver:
         if u is None:
             u = torch.empty(self.ndof_torn, dtype=torch.float64, device=f_qp.device)
         st = IetiStats()
-        rc = lib().ieti_solve(self.h, C.c_void_p(f_qp.data_ptr()), C.c_void_p(u.data_ptr()), C.byref(st))
+        fn = lib().ieti_solve_noalloc if no_alloc else lib().ieti_solve
+        rc = fn(self.h, C.c_void_p(f_qp.data_ptr()), C.c_void_p(u.data_ptr()), C.byref(st))
         if rc != _abi.IETI_OK and not (rc == _abi.IETI_ENOCONV and not raise_on_noconv):
-            check(rc, "ieti_solve")
+            check(rc, "ieti_solve_noalloc" if no_alloc else "ieti_solve")
         return u, st.as_dict()
 
 
