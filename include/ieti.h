@@ -60,8 +60,16 @@ extern "C" {
                                   inner solves. outer_iterations counts its iterations, the residuals are its
                                   preconditioned energy norms */
 
-#define IETI_PRIMAL_VERTICES  1   /* primal unknowns at patch vertices */
-#define IETI_PRIMAL_EDGES     2   /* plus edge averages (3D: patch edges; 2D: patch sides) */
+#define IETI_PRIMAL_VERTICES  1   /* primal unknowns at patch vertices (eliminated from the local problems) */
+#define IETI_PRIMAL_EDGES     2   /* edge averages (3D: patch edges; 2D: patch sides); alone (without
+                                     IETI_PRIMAL_VERTICES) the paper's 3D primal set of Sec. 4: vertex copies are
+                                     then joined by multipliers, and a patch with no Dirichlet coefficient is
+                                     "floating" -- K is singular there and only its edge averages fix the
+                                     constants (Sec. 3.2, eq. (6) with a semi-definite block).  Floating patches
+                                     are supported by IETI_LOCAL_MG: the local solves run on K + gamma C^T C
+                                     (equal to K on {C w = 0}, gamma = 1e-2 / number of edge constraints) with
+                                     multigrid levels >= 1 on K + 1e-2 M^ (M^ the mass matrix of the parameter
+                                     domain); other local solvers return IETI_ENOTSUP for them */
 
 /* Finest-level multigrid smoother (options.smoother).  TENSOR is the p-robust smoother of Sec. 4 (a
  * subspace-corrected mass smoother variant with a rank-one approximation of the geometry): per patch,
@@ -88,7 +96,8 @@ typedef struct ieti_options {
     int32_t local_solver;      /* IETI_LOCAL_MG (default), IETI_LOCAL_EXACT, IETI_LOCAL_EXACT_MG or
                                   IETI_LOCAL_MG_SADDLE */
     int32_t mg_precision;      /* 32 or 64: arithmetic of V-cycles and their operator data (default 64) */
-    int32_t primal;            /* IETI_PRIMAL_VERTICES (default) or IETI_PRIMAL_VERTICES|IETI_PRIMAL_EDGES */
+    int32_t primal;            /* IETI_PRIMAL_VERTICES (default), IETI_PRIMAL_VERTICES|IETI_PRIMAL_EDGES or
+                                  IETI_PRIMAL_EDGES */
     int32_t cheb_degree;       /* Chebyshev smoother degree per smoothing phase; 0 = tuned per dimension and spline degree */
     int32_t cheb_degree_coarse;/* the same on the coarser multigrid levels; 0 = tuned per spline degree */
     double  cheb_lower;        /* lower end of the smoothing interval as a fraction of lambda_max; 0 = tuned */
@@ -166,8 +175,9 @@ void ieti_default_options(ieti_options* opt);
  * required), numbers boundary, primal and dual coefficients, builds the jump
  * operators and the multigrid hierarchy and assembles all operator data in
  * FP64.  primal_vertices: n_primal_vertices points (dim doubles each, host)
- * selecting which interior patch vertices are primal; NULL = all of them.
- * Every patch without a boundary side must keep at least one primal vertex.
+ * selecting which interior patch vertices are primal; NULL = all of them
+ * (none without IETI_PRIMAL_VERTICES).  A patch with no Dirichlet
+ * coefficient must keep a primal vertex or an edge-average constraint.
  */
 int ieti_plan_create(const ieti_patch* patches, int32_t n_patches,
                      const double* primal_vertices, int32_t n_primal_vertices,

@@ -1275,6 +1275,39 @@ __global__ void k_unit(int npatch, const int64_t* unit_dev, int j, double* v) {
 }
 
 // v = 1/n_e on the coefficients of edge constraint j of every patch
+// Floating patches (no Dirichlet and no primal-vertex coefficient, K singular on the constants): their local
+// Neumann operator is K + gamma sum_e c_e c_e^T, c_e the average over the coefficients of edge constraint e,
+// equal to K on {C w = 0}.  After the sweep q = K d with its per-tile dots (d . q): q += gamma sum_e c_e (c_e . d)
+// on the edge coefficients and (d . q) += gamma sum_e (c_e . d)^2 on the patch's first tile.  One work-group per
+// floating patch; its edges are disjoint, so the updates of q do not meet.
+__global__ __launch_bounds__(TILE) void k_float_penalty(int nfloat, const int32_t* flist, const int32_t* npk,
+                                                        const int64_t* edge_ptr, const int64_t* edge_dev,
+                                                        const double* gam, const double* d, double* q, double* pdots,
+                                                        const int32_t* tile_beg, const int* active) {
+    __shared__ double lds[TILE / WAVE];
+    __shared__ double mean_sh;
+    if ((int)blockIdx.x >= nfloat) return;
+    const int k = flist[blockIdx.x];
+    if (active && !active[k]) return;
+    const double g = gam[k];
+    double acc = 0.0;
+    for (int j = 0; j < npk[k]; ++j) {
+        const int64_t b = edge_ptr[k * NPMAX + j], e = edge_ptr[k * NPMAX + j + 1];
+        if (e <= b) continue;
+        double v[1] = {0.0};
+        for (int64_t r = b + threadIdx.x; r < e; r += blockDim.x) v[0] += d[edge_dev[r]];
+        block_sum<1>(v, lds);
+        if (threadIdx.x == 0) mean_sh = v[0] / (double)(e - b);
+        __syncthreads();
+        const double mean = mean_sh;
+        __syncthreads();
+        const double add = g * mean / (double)(e - b);
+        for (int64_t r = b + threadIdx.x; r < e; r += blockDim.x) q[edge_dev[r]] += add;
+        acc += g * mean * mean;
+    }
+    if (threadIdx.x == 0) pdots[2 * tile_beg[k]] += acc;
+}
+
 __global__ void k_edge_rhs(int npatch, const int64_t* edge_ptr, const int64_t* edge_dev, int j, double* v) {
     const int k = blockIdx.x;
     if (k >= npatch) return;

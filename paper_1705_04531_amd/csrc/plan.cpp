@@ -551,6 +551,28 @@ static void assemble_level(Patch& P, Level& L, bool level0) {
             }
 }
 
+// coef += alpha M^ on level L, M^ the mass matrix of the level's spline space on the parameter domain
+// (0,1)^d: the tensor product of the 1D parametric mass matrices (Gauss quadrature in parameter space).
+static void add_param_mass(const Patch& P, Level& L, double alpha) {
+    const int dim = P.dim;
+    std::vector<double> A1[3][2][2];
+    for (int d = 0; d < dim; ++d) one_d_matrices(make_dir(L.knots[d], P.p[d], P.knots[d], P.p[d]), L.M[d], A1[d]);
+    for (int i2 = 0; i2 < L.M[2]; ++i2)
+        for (int i1 = 0; i1 < L.M[1]; ++i1)
+            for (int i0 = 0; i0 < L.M[0]; ++i0) {
+                const int ii[3] = {i0, i1, i2};
+                const int64_t i = lin(L.M, i0, i1, i2);
+                for (int s = 0; s < L.nst; ++s) {
+                    double v = alpha;
+                    for (int d = 0; d < dim && v != 0.0; ++d) {
+                        const int j = ii[d] + L.offs[3 * s + d];
+                        v = (j < 0 || j >= L.M[d]) ? 0.0 : v * A1[d][0][0][(size_t)ii[d] * L.M[d] + j];
+                    }
+                    L.coef[(size_t)s * L.n + i] += v;
+                }
+            }
+}
+
 // y = m (K m x) with the half stencil, FP64, on the host.
 static void host_apply(const Patch& P, const Level& L, const std::vector<uint8_t>& mask, const double* x, double* y) {
     std::fill(y, y + L.n, 0.0);
@@ -1485,8 +1507,8 @@ Plan* build_plan(const ieti_patch* in, int n, const double* pv, int n_pv, const 
         for (int c = 0; c < ncorner; ++c) {
             int64_t g = group_of[pa.torn_off + corner_index(pa, c)];
             if (g < 0 || groups[g].dir || gprimal[g]) continue;
-            bool take = true;
-            if (pv) {
+            bool take = (opt.primal & IETI_PRIMAL_VERTICES) != 0;
+            if (pv && take) {
                 take = false;
                 int64_t li = corner_index(pa, c);
                 for (int v = 0; v < n_pv && !take; ++v) {
@@ -1578,10 +1600,28 @@ Plan* build_plan(const ieti_patch* in, int n, const double* pv, int n_pv, const 
         pa.primal_corner.push_back(-1);
         pa.primal_edge.push_back(le.loc);
     }
-    // floating patches need a primal vertex (K_rr must be definite)
-    for (int k = 0; k < n; ++k)
-        if (pl.patches[k].bside == 0 && pl.patches[k].pcorner == 0 && pl.patches[k].dcorner == 0)
-            throw Error(IETI_EINVAL, "patch " + std::to_string(k) + " has no boundary side and no primal vertex");
+    // floating patches: no Dirichlet coefficient and no eliminated primal vertex, so K is singular on the
+    // constants; edge-average constraints fix them (Sec. 3.2, eq. (6) with a semi-definite block).  The local
+    // Neumann solves run on K + gamma sum_e c_e c_e^T (c_e the edge-average functional): on {C w = 0} this is
+    // K, so the unconstrained solve followed by the energy-minimising projection gives the constrained
+    // minimiser; gamma = alpha / n_e gives the constants the energy alpha 1^T M^ 1 = alpha they have in the
+    // regularised multigrid operator K + alpha M^ of the coarser levels.
+    for (int k = 0; k < n; ++k) {
+        Patch& pa = pl.patches[k];
+        if (pa.bside != 0 || pa.pcorner != 0 || pa.dcorner != 0) continue;
+        int ne = 0;
+        for (size_t j = 0; j < pa.primal_corner.size(); ++j)
+            if (pa.primal_corner[j] < 0 && !pa.primal_edge[j].empty()) ++ne;
+        if (ne == 0)
+            throw Error(IETI_EINVAL, "patch " + std::to_string(k) +
+                                         " has no boundary side, no primal vertex and no edge-average constraint");
+        if (opt.local_solver != IETI_LOCAL_MG)
+            throw Error(IETI_ENOTSUP, "patch " + std::to_string(k) +
+                                          " floats (no Dirichlet or primal-vertex coefficient): only the MG-MG "
+                                          "variant supports floating patches");
+        pa.floating = true;
+        pa.float_gamma = FLOAT_ALPHA / (double)ne;
+    }
     {
         std::vector<std::vector<std::pair<int64_t, int64_t>>> contrib(pl.n_primal);
         for (int k = 0; k < n; ++k)
@@ -1717,6 +1757,10 @@ Plan* build_plan(const ieti_patch* in, int n, const double* pv, int n_pv, const 
         const bool neumann_mg = opt.local_solver == IETI_LOCAL_MG || opt.local_solver == IETI_LOCAL_MG_SADDLE;
         Patch& pa = pl.patches[k];
         for (size_t l = 0; l < pa.lv.size(); ++l) assemble_level(pa, pa.lv[l], l == 0);
+        // floating patches: the coarser levels of the multigrid carry K + alpha M^ (definite), the finest
+        // level keeps K (its stencil is also the exact operator of the local solves)
+        if (pa.floating)
+            for (size_t l = 1; l < pa.lv.size(); ++l) add_param_mass(pa, pa.lv[l], FLOAT_ALPHA);
         for (size_t l = 0; l + 1 < pa.lv.size(); ++l) {
             Level& f = pa.lv[l];
             const Level& c = pa.lv[l + 1];
@@ -1737,7 +1781,13 @@ Plan* build_plan(const ieti_patch* in, int n, const double* pv, int n_pv, const 
         }
         Level& cl = pa.lv.back();
         if (mg) {
-            if (neumann_mg) cl.inv[MODE_N] = dense_inverse(pa, cl, MODE_N);
+            if (neumann_mg && pa.floating && pa.lv.size() == 1) {   // a one-level floating patch: K + alpha M^
+                Level reg = cl;
+                add_param_mass(pa, reg, FLOAT_ALPHA);
+                cl.inv[MODE_N] = dense_inverse(pa, reg, MODE_N);
+            } else if (neumann_mg) {
+                cl.inv[MODE_N] = dense_inverse(pa, cl, MODE_N);
+            }
             cl.inv[MODE_D] = dense_inverse(pa, cl, MODE_D);
         }
         if (!neumann_mg) {

@@ -52,6 +52,12 @@ struct Patch {
     uint32_t pcorner = 0;          // bit c: corner c (c = e0 + 2 e1 + 4 e2) is a primal vertex
     uint32_t dcorner = 0;          // bit c: corner c is a boundary coefficient though on no boundary side
     bool affine = false;
+    // no Dirichlet coefficient and no primal vertex: K is singular (the constants) and only the edge-average
+    // constraints fix them.  The local Neumann solves then run on K + gamma C^T C (gamma = float_gamma), whose
+    // restriction to {C w = 0} is K, and the multigrid levels >= 1 carry K + alpha M^ (M^ the mass matrix of the
+    // parameter domain, alpha = FLOAT_ALPHA)
+    bool floating = false;
+    double float_gamma = 0.0;
     std::vector<Level> lv;         // lv[0] finest
     std::vector<double> qpw;       // w_q |det J_q| at the level-0 quadrature points
     std::vector<double> qpx;       // physical quadrature points, n_qp * dim
@@ -100,6 +106,7 @@ struct Plan {
 };
 
 constexpr int BAND_NB = 64;   // row block of the blocked banded triangular solves
+constexpr double FLOAT_ALPHA = 1e-2;   // mass shift of the regularised multigrid of floating patches (Sec. 3.2)
 
 Plan* build_plan(const ieti_patch* patches, int n, const double* primal_vertices, int n_pv,
                  const ieti_options* opt);

@@ -347,6 +347,11 @@ struct Solver : SolverBase {
     std::vector<int> h_its;
     int hint_solve = 1, hint_basis = 1;   // inner iterations of the last batched solve per tolerance
 
+    // floating patches (K singular, edge constraints only): their list and the penalty gamma per patch
+    int n_float = 0;
+    int32_t* float_list = nullptr;
+    double* float_gam = nullptr;
+
     // ---------------------------------------------------------------- launch helpers
     void sync() { HIPCHECK(hipStreamSynchronize(stream)); }
     void check_launch() { HIPCHECK(hipGetLastError()); }
@@ -669,6 +674,11 @@ struct Solver : SolverBase {
         check_launch();
         stencil<double, double, double, EPI_DOTS>(0, false, MODE_N, coef64, fd, fq, nullptr, nullptr, active, 0.0, 0,
                                                   pdots, fr);
+        if (n_float > 0) {   // floating patches: + gamma C^T C d
+            hipLaunchKernelGGL(k_float_penalty, dim3(n_float), dim3(TILE), 0, stream, n_float, float_list, npk,
+                               edge_ptr, edge_dev, float_gam, (const double*)fd, fq, pdots, tile_beg, active);
+            check_launch();
+        }
         hipLaunchKernelGGL(k_fcg_update<T>, dim3(tile_grid(nt)), dim3(TILE), 0, stream, D.L, D.tiles_all, nt, fd, fq,
                            fx, fr, rT, pdots, tile_beg, tile_end, dq, brk, prr, active);
         check_launch();
@@ -1922,6 +1932,18 @@ void Solver<T>::setup() {
         pri_ptr = arena.upload(pl.pri_ptr, st);
         pri_patch = arena.upload(pl.pri_patch, st);
         pri_local = arena.upload(pl.pri_local, st);
+        std::vector<int32_t> fl;
+        std::vector<double> fg(N, 0.0);
+        for (int k = 0; k < N; ++k)
+            if (pl.patches[k].floating) {
+                fl.push_back(k);
+                fg[k] = pl.patches[k].float_gamma;
+            }
+        n_float = (int)fl.size();
+        if (n_float) {
+            float_list = arena.upload(fl, st);
+            float_gam = arena.upload(fg, st);
+        }
         cbuf = arena.alloc<double>((int64_t)N * NPMAX, st);
         ebuf = arena.alloc<double>((int64_t)N * NPMAX, st);
         coefbuf = arena.alloc<double>((int64_t)N * NPMAX, st);

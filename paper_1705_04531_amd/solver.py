@@ -32,7 +32,8 @@ def options_for(wl, **overrides) -> IetiOptions:
         local_solver={"exact": _abi.IETI_LOCAL_EXACT, "exact_mg": _abi.IETI_LOCAL_EXACT_MG,
                       "mg_saddle": _abi.IETI_LOCAL_MG_SADDLE}.get(wl.local_solver, _abi.IETI_LOCAL_MG),
         mg_precision=int(wl.mg_precision),
-        primal=_abi.IETI_PRIMAL_VERTICES | (_abi.IETI_PRIMAL_EDGES if wl.primal == "vertices+edges" else 0),
+        primal={"vertices": _abi.IETI_PRIMAL_VERTICES, "edges": _abi.IETI_PRIMAL_EDGES,
+                "vertices+edges": _abi.IETI_PRIMAL_VERTICES | _abi.IETI_PRIMAL_EDGES}[wl.primal],
         tol=float(wl.tol),
         inner_tol=float(wl.inner_tol),
     )

@@ -256,3 +256,53 @@ def test_tensor_smoother_factors_match_oracle_3d(lib):
         m = _mask_from_bits(geo.shape, int(bits[0]), int(bits[1]), mode)
         lmax = TS.damping(geo, sides, m, K, 0.3)
         assert 0.99 <= par[3] * lmax <= 1.1, (mode, par[3] * lmax)
+
+
+@pytest.mark.parametrize("wl", [
+    W.unit_cube((3, 3, 3), 2, 8, primal="edges", name="cube3x3x3_edges"),
+    W.deformed_square((3, 3), [[2, 3, 4], [4, 2, 3]], [[8, 12, 16], [16, 8, 12]], amp_factor=0.8,
+                      primal="edges", name="deformed3x3_sides_only"),
+], ids=lambda w: w.name)
+def test_edge_only_plan_matches_oracle(lib, wl):
+    """The paper's edge-average-only primal set: the plan's primal and multiplier counts equal the oracle's
+    (vertex copies joined by fully redundant multipliers); the floating centre patch keeps the exact K on the
+    finest level and carries K + 1e-2 M^ (M^ the mass matrix of the parameter domain) on the coarser levels."""
+    from oracle import ietidp
+    from paper_1705_04531_amd import options_for
+    pl = Plan(wl.patches, options_for(wl, coarse_dofs=0))
+    sz = pl.sizes()
+    ie = ietidp.IetiDP(wl)
+    assert sz["n_primal"] == ie.n_pi and sz["n_lambda"] == ie.n_lam
+    k = len(wl.patches) // 2                        # the centre patch touches no boundary
+    masks = pl.array(_abi.IETI_ARR_MASKS, k, 0, dtype=np.int32)
+    assert masks[0] == 0 and masks[1] == 0           # no boundary side, no primal vertex
+    p = wl.patches[k]
+    Ko = assembly.assemble_patch(p).K.toarray()
+    assert np.abs(_dense_from_stencil(pl, k, 0) - Ko).max() <= 1e-13 * np.abs(Ko).max()
+    kn = [bspline.coarsen_knots(t, d) for t, d in zip(p.knots, p.degree)]
+    Kc = assembly.assemble_patch(p, knots=kn).K.toarray()
+    # the parametric mass: the same spline space on the identity map of (0,1)^d
+    ident = W.Patch(p.degree, p.knots, np.stack(np.meshgrid(
+        *[W.greville(t, d) for t, d in zip(p.knots, p.degree)], indexing="ij"), -1).reshape(-1, wl.dim, order="F"))
+    Mc = assembly.assemble_patch(ident, knots=kn).M.toarray()
+    K1 = _dense_from_stencil(pl, k, 1)
+    assert np.abs(K1 - (Kc + 1e-2 * Mc)).max() <= 1e-12 * np.abs(Kc).max()
+    # a boundary patch has no mass shift
+    K1b = _dense_from_stencil(pl, 0, 1)
+    Kcb = assembly.assemble_patch(wl.patches[0], knots=[bspline.coarsen_knots(t, d) for t, d in
+                                                        zip(wl.patches[0].knots, wl.patches[0].degree)]).K.toarray()
+    assert np.abs(K1b - Kcb).max() <= 1e-13 * np.abs(Kcb).max()
+
+
+def test_floating_patch_needs_a_constraint(lib):
+    """Without vertices and edge averages a patch with no Dirichlet coefficient has nothing fixing its
+    constants: planning refuses it; floating patches with another local solver than MG-MG are refused."""
+    from paper_1705_04531_amd import options_for
+    wl = W.deformed_square((3, 3), 2, 6, primal="edges")
+    with pytest.raises(_abi.IetiError) as e:
+        Plan(wl.patches, options_for(wl, primal=0))
+    assert e.value.code == _abi.IETI_EINVAL
+    with pytest.raises(_abi.IetiError) as e:
+        Plan(wl.patches, options_for(wl, local_solver=_abi.IETI_LOCAL_EXACT))
+    assert e.value.code == _abi.IETI_ENOTSUP
+    Plan(wl.patches, options_for(wl))
