@@ -228,7 +228,7 @@ def serve(args):
     X = len(inputs) / span_sat
     span, lat, bad2 = run(0.8 * X, args.slots, opt)
     base_span, base_lat, bad3 = run(0.0, 1, options_for(inputs[0][0], local_solver=_abi.IETI_LOCAL_EXACT,
-                                                         mg_precision=64))
+                                                         mg_precision=64, batch_dofs=0))
     out = {
         "metric": "serving solves/s and p50/p99 latency (Poisson arrivals at 0.8x saturated throughput)",
         "value": round(len(inputs) / span, 3),
@@ -270,7 +270,7 @@ def main():
     ap.add_argument("--variants", action="store_true",
                     help="also time D-MG, MG-MG-S and the tensor smoother on the headline workload")
     ap.add_argument("--serve", action="store_true", help="serving benchmark instead of the solve benchmark")
-    ap.add_argument("--requests", type=int, default=64)
+    ap.add_argument("--requests", type=int, default=512)
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--local-solver", choices=["mg", "exact_mg", "mg_saddle"], default="mg",
                     help="variant of the headline solver: mg (MG-MG, default), exact_mg (D-MG), mg_saddle (MG-MG-S)")
@@ -278,6 +278,9 @@ def main():
     ap.add_argument("--precision", type=int, choices=[32, 64], default=64,
                     help="multigrid precision of the headline solver (the outer CG is always FP64)")
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="deformed16x16")
+    ap.add_argument("--coarse-level", type=int, default=0,
+                    help="first multigrid level of the fused per-patch coarse kernel (0: the library's choice, "
+                         "-1: every level by batched launches)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 512 MiB FP64 tensor 3 times (scale for the FETCH_SIZE/WRITE_SIZE counters)")
     args = ap.parse_args()
@@ -315,6 +318,8 @@ def main():
     extra_opt = {"smoother": _abi.IETI_SMOOTHER_TENSOR} if tensor else {}
     print(f"[bench] headline {wl.name}, MG precision {args.precision}, {args.local_solver}", file=sys.stderr,
           flush=True)
+    if args.coarse_level:
+        extra_opt["coarse_level"] = args.coarse_level
     m = measure(wl, gname, args.steps, args.warmup, local_solver=variant, mg_precision=args.precision, **extra_opt)
     ms_per_step = m["ms_per_step"]
     value = wl.ndof_torn / (ms_per_step * 1e-3) / 1e6
@@ -358,6 +363,7 @@ def main():
             "n_primal": st["n_primal"],
             "outer_iterations": st["outer_iterations"],
             "inner_iterations_mean": round(st["inner_iterations_mean"], 2),
+            "inner_iterations_max": st["inner_iterations_max"],
             "global_residual": st["global_residual"],
             "time_pcg_ms": round(st["time_pcg_ms"], 3),
             "time_rhs_ms": round(st["time_rhs_ms"], 3),

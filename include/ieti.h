@@ -132,6 +132,12 @@ typedef struct ieti_options {
                                   MG precision, local solver, coarse_dofs and the set of patch shapes (degree /
                                   elements per direction); a hit skips the timing, a miss appends the new choice.
                                   Read at setup only; NULL = no cache (default) */
+    int64_t batch_dofs;        /* serving: a worker takes the oldest waiting request and, behind it, further
+                                  waiting requests of the same dimension while their torn dofs together stay
+                                  within batch_dofs, and solves them as one batch: one plan and one device state,
+                                  every kernel launch over the patches of all of them, one outer CG per request
+                                  (its own scalars, stopping test and statistics).  0 = one request per batch.
+                                  Default 2,000,000 */
 } ieti_options;
 
 typedef struct ieti_stats {
@@ -310,16 +316,23 @@ int ieti_quadrature_points(const ieti_patch* patches, int32_t n_patches, double*
 
 /*
  * Serving: a request loop for many independent solves.  max_slots worker
- * streams (1..16) each take the oldest waiting request, plan it, wait until
- * opt->hbm_budget (0 = unlimited) admits its estimated device footprint, set it
- * up, solve and copy u back; admitted requests overlap on the device and a
- * slot takes the next request as soon as it finishes.  Submit copies patches
+ * streams (1..16) each take a batch of waiting requests (the oldest one and
+ * the ones queued behind it up to opt->batch_dofs torn dofs), plan them as one
+ * multi-problem solve, wait until opt->hbm_budget (0 = unlimited) admits the
+ * batch's estimated device footprint, set it up, solve -- the requests' outer
+ * CG iterations run together, every launch covering all their patches, with
+ * per-request scalars and stopping tests -- and copy each u back; batches of
+ * different slots overlap on the device and a slot takes the next batch as
+ * soon as it finishes.  Submit copies patches
  * and f (host, at ieti_quadrature_points order); u (host, ndof_torn doubles)
  * must stay valid until the request is polled done.  Poll returns
  * IETI_PENDING while running (or blocks with wait != 0), then the solve's
  * status once; times_ms (3 doubles, may be NULL) receives submit, admission
  * and completion times on the server clock.  Requests are independent: a
- * result does not depend on what else is in flight.
+ * result does not depend on what else is in flight beyond rounding (the
+ * primal coarse solve of a batch is one block-diagonal matrix; within the
+ * stated tolerance) and the smoother degree, which the batch takes from its
+ * highest spline degree unless options.cheb_degree fixes it.
  */
 typedef struct ieti_server ieti_server;
 /* Device bytes the server reserves for a request with this plan (host). */

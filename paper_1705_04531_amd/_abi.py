@@ -83,6 +83,7 @@ class IetiOptions(C.Structure):
         ("smoother", C.c_int32),
         ("smoother_sigma", C.c_double),
         ("tune_cache", C.c_char_p),
+        ("batch_dofs", C.c_int64),
     ]
 
 

@@ -1215,9 +1215,27 @@ __device__ double wg_dot(const double* a, const double* b, int64_t n, double* ld
 // stage 0: rz = r.z, p = z            (start)
 // stage 1: pq = p.q; alpha = rz/pq; lam += alpha p; r -= alpha q; |r|^2
 // stage 2: rz' = r.z; beta = rz'/rz; p = z + beta p; rz = rz'
-__global__ __launch_bounds__(1024) void k_pcg(int stage, int64_t n, double* lam, double* r, const double* z,
-                                              double* p, const double* q, double* sc) {
+// Outer CG of ncomp independent problems at once (one for ieti_solve, several for a serving batch): work-group
+// c runs the CG update of problem c on its multiplier range [beg[c], beg[c+1]) -- the same thread partition and
+// summation order as for a problem alone -- with its scalars in sc + 16 c.  Stages: 0 start (p = z, rz),
+// 1 step (alpha, lambda, r, |r|^2, breakdown flag), 2 direction (beta, p).  done[c] != 0: problem c has stopped;
+// stages 0 and 2 zero its search direction (so that F p holds no load from it) and stage 1 leaves it alone.
+__global__ __launch_bounds__(1024) void k_pcg(int stage, const int64_t* beg, const int* done, double* lam, double* r,
+                                              const double* z, double* p, const double* q, double* sc) {
     __shared__ double lds[1024 / WAVE];
+    const int c = blockIdx.x;
+    const int64_t b = beg[c], n = beg[c + 1] - b;
+    lam += b;
+    r += b;
+    z += b;
+    p += b;
+    q += b;
+    sc += 16 * c;
+    if (done && done[c]) {
+        if (stage != 1)
+            for (int64_t i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0.0;
+        return;
+    }
     if (stage == 0) {
         const double rz = wg_dot(r, z, n, lds);
         for (int64_t i = threadIdx.x; i < n; i += blockDim.x) p[i] = z[i];
@@ -1251,17 +1269,33 @@ __global__ __launch_bounds__(1024) void k_pcg(int stage, int64_t n, double* lam,
 }
 
 // |a|^2 and |b|^2 (+ |c|^2) into out[0..2] (one work-group)
-__global__ __launch_bounds__(1024) void k_norms(int64_t n, const double* a, const double* b, const double* c,
+// |a|^2, |b|^2, |c|^2 of each problem's multiplier range (work-group per problem) into out + 16 c + {0, 1, 2}
+__global__ __launch_bounds__(1024) void k_norms(const int64_t* beg, const double* a, const double* b, const double* c,
                                                 double* out) {
     __shared__ double lds[1024 / WAVE];
-    const double na = wg_dot(a, a, n, lds);
-    const double nb = b ? wg_dot(b, b, n, lds) : 0.0;
-    const double nc = c ? wg_dot(c, c, n, lds) : 0.0;
+    const int g = blockIdx.x;
+    const int64_t o = beg[g], n = beg[g + 1] - o;
+    const double na = wg_dot(a + o, a + o, n, lds);
+    const double nb = b ? wg_dot(b + o, b + o, n, lds) : 0.0;
+    const double nc = c ? wg_dot(c + o, c + o, n, lds) : 0.0;
     if (threadIdx.x == 0) {
-        out[0] = na;
-        out[1] = nb;
-        out[2] = nc;
+        out[16 * g + 0] = na;
+        out[16 * g + 1] = nb;
+        out[16 * g + 2] = nc;
     }
+}
+
+// Per-problem sums of per-tile partials: work-group c adds the tiles of its patches [pbeg[c], pbeg[c+1]) in patch
+// order (tiles of patch k: [tile_beg[k], tile_end[k])) into out[16 c]
+__global__ __launch_bounds__(256) void k_sum_comp(const double* partial, const int32_t* tile_beg,
+                                                  const int32_t* tile_end, const int64_t* pbeg, double* out) {
+    __shared__ double lds[256 / WAVE];
+    const int c = blockIdx.x;
+    double acc[1] = {0.0};
+    for (int64_t k = pbeg[c]; k < pbeg[c + 1]; ++k)
+        for (int u = tile_beg[k] + (int)threadIdx.x; u < tile_end[k]; u += blockDim.x) acc[0] += partial[u];
+    block_sum<1>(acc, lds);
+    if (threadIdx.x == 0) out[16 * c] = acc[0];
 }
 
 // ------------------------------------------------------------------ setup helpers

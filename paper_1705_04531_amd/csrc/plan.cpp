@@ -57,6 +57,7 @@ void default_options(ieti_options* o) {
     o->device = -1;
     o->stream = nullptr;
     o->hbm_budget = 0;
+    o->batch_dofs = 2000000;
 }
 
 // Smoother choice per dimension and spline degree (degree of the Chebyshev
@@ -1282,8 +1283,13 @@ static void validate_patch(const ieti_patch& ip, int dim0, int k) {
     }
 }
 
-Plan* build_plan(const ieti_patch* in, int n, const double* pv, int n_pv, const ieti_options* optp) {
+Plan* build_plan(const ieti_patch* in, int n, const double* pv, int n_pv, const ieti_options* optp,
+                 const int32_t* comp) {
     if (!in || n <= 0) throw Error(IETI_EINVAL, "no patches");
+    if (comp)
+        for (int k = 1; k < n; ++k)
+            if (comp[k] < comp[k - 1]) throw Error(IETI_EINVAL, "problem ids of the patches must not decrease");
+    auto comp_of = [&](int k) { return comp ? comp[k] : 0; };
     ieti_options opt;
     if (optp) opt = *optp; else default_options(&opt);
     if (opt.mg_precision != 32 && opt.mg_precision != 64) throw Error(IETI_EINVAL, "mg_precision must be 32 or 64");
@@ -1356,6 +1362,7 @@ Plan* build_plan(const ieti_patch* in, int n, const double* pv, int n_pv, const 
     // ---- corners -> vertices
     const int ncorner = 1 << dim;
     std::vector<std::array<double, 3>> vcoord;
+    std::vector<int> vcomp;   // problem of each vertex
     std::vector<std::vector<int>> cvert(n, std::vector<int>(ncorner));
     auto corner_index = [&](const Patch& pa, int c) {
         int idx[3] = {0, 0, 0};
@@ -1370,11 +1377,16 @@ Plan* build_plan(const ieti_patch* in, int n, const double* pv, int n_pv, const 
             for (int d = 0; d < dim; ++d) x[d] = pa.ctrl[i * dim + d];
             int found = -1;
             for (size_t v = 0; v < vcoord.size() && found < 0; ++v) {
+                if (vcomp[v] != comp_of(k)) continue;
                 double dd = 0;
                 for (int d = 0; d < dim; ++d) dd = std::max(dd, std::fabs(vcoord[v][d] - x[d]));
                 if (dd <= tol) found = (int)v;
             }
-            if (found < 0) { found = (int)vcoord.size(); vcoord.push_back(x); }
+            if (found < 0) {
+                found = (int)vcoord.size();
+                vcoord.push_back(x);
+                vcomp.push_back(comp_of(k));
+            }
             cvert[k][c] = found;
         }
 
@@ -1801,6 +1813,39 @@ Plan* build_plan(const ieti_patch* in, int n, const double* pv, int n_pv, const 
     int64_t nq = 0;
     for (auto& pa : pl.patches) nq += pa.n_qp;
     pl.n_qp = nq;
+    // ranges of the independent problems: patches, multipliers (groups, hence multipliers, follow the torn
+    // order, and a group never spans two problems), quadrature points, torn coefficients
+    pl.ncomp = 0;
+    pl.comp_patch_beg.clear();
+    for (int k = 0; k < n; ++k)
+        if (k == 0 || comp_of(k) != comp_of(k - 1)) pl.comp_patch_beg.push_back(k);
+    pl.ncomp = (int)pl.comp_patch_beg.size();
+    pl.comp_patch_beg.push_back(n);
+    pl.comp_lam_beg.assign(pl.ncomp + 1, 0);
+    pl.comp_qp_beg.assign(pl.ncomp + 1, 0);
+    pl.comp_torn_beg.assign(pl.ncomp + 1, 0);
+    {
+        std::vector<int> pcomp(n);
+        for (int c = 0; c < pl.ncomp; ++c)
+            for (int64_t k = pl.comp_patch_beg[c]; k < pl.comp_patch_beg[c + 1]; ++k) pcomp[k] = c;
+        int last = 0;
+        for (int64_t l = 0; l < pl.n_lambda; ++l) {
+            const int c = pcomp[pos_patch(pl.lam_plus[l])];
+            if (c < last) throw Error(IETI_EINVAL, "internal: multipliers not ordered by problem");
+            last = c;
+            pl.comp_lam_beg[c + 1] = l + 1;
+        }
+        for (int c = 0; c < pl.ncomp; ++c) pl.comp_lam_beg[c + 1] = std::max(pl.comp_lam_beg[c + 1], pl.comp_lam_beg[c]);
+        for (int c = 0; c < pl.ncomp; ++c) {
+            int64_t q = 0, t = 0;
+            for (int64_t k = pl.comp_patch_beg[c]; k < pl.comp_patch_beg[c + 1]; ++k) {
+                q += pl.patches[k].n_qp;
+                t += pl.patches[k].lv[0].n;
+            }
+            pl.comp_qp_beg[c + 1] = pl.comp_qp_beg[c] + q;
+            pl.comp_torn_beg[c + 1] = pl.comp_torn_beg[c] + t;
+        }
+    }
     return P.release();
 }
 

@@ -103,13 +103,19 @@ struct Plan {
     std::vector<int64_t> grp_ptr, grp_pos;
     // global primal: contributors (patch, local constraint) per global primal, CSR
     std::vector<int64_t> pri_ptr, pri_patch, pri_local;
+    // independent problems planned together (serving batches): patches, multipliers and quadrature points of
+    // problem c are the ranges [beg[c], beg[c+1]); one problem unless planned with component ids
+    int ncomp = 1;
+    std::vector<int64_t> comp_patch_beg, comp_lam_beg, comp_qp_beg, comp_torn_beg;
 };
 
 constexpr int BAND_NB = 64;   // row block of the blocked banded triangular solves
 constexpr double FLOAT_ALPHA = 1e-2;   // mass shift of the regularised multigrid of floating patches (Sec. 3.2)
 
+// comp (may be NULL): non-decreasing problem id per patch; patches of different problems never share a vertex,
+// side or multiplier, even where their geometry coincides
 Plan* build_plan(const ieti_patch* patches, int n, const double* primal_vertices, int n_pv,
-                 const ieti_options* opt);
+                 const ieti_options* opt, const int32_t* comp = nullptr);
 
 // helpers shared with the runtime
 void default_options(ieti_options* o);

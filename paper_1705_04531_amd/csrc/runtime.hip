@@ -234,6 +234,9 @@ struct SolverBase {
     // ieti_solve_noalloc: the same solve with its per-solve scratch in the static array `scratch`
     virtual int solve_noalloc(const double* f_qp, double* u, ieti_stats* st) = 0;
     double* noalloc_base = nullptr;   // device address of `scratch` on the handle's device
+    // statistics and status of every problem of the last solve (several in a serving batch)
+    std::vector<ieti_stats> comp_stats;
+    std::vector<int> comp_rc;
     virtual void quadrature(double* x, bool on_device) = 0;
     std::unique_ptr<Plan> plan;
     hipStream_t stream = nullptr;
@@ -347,6 +350,14 @@ struct Solver : SolverBase {
     std::vector<int> h_its;
     int hint_solve = 1, hint_basis = 1;   // inner iterations of the last batched solve per tolerance
 
+    // independent problems (a serving batch; one for ieti_solve): multiplier and patch ranges, stop flags,
+    // and the statistics and status of each problem from the last solve
+    int ncomp = 1;
+    std::vector<int64_t> h_comp_lam;
+    int64_t *comp_lam = nullptr, *comp_patch = nullptr;
+    int* done_dev = nullptr;
+    int* h_done = nullptr;   // pinned
+    std::vector<double> comp_gres;
     // floating patches (K singular, edge constraints only): their list and the penalty gamma per patch
     int n_float = 0;
     int32_t* float_list = nullptr;
@@ -768,9 +779,27 @@ struct Solver : SolverBase {
     // step (5 + nst) n s (the step from zero 4 n s), a residual (3 + nst) n s, a restriction (n + n_c) s, a
     // prolongation (2 n + n_c) s; the fused coarse part its right-hand side and result once, the half
     // stencils of its smoothed levels and the coarsest inverse once; a coarsest solve outside it 2 n_c s +
-    // n_c^2 s.  Only multigrid with the Chebyshev smoother is modelled (0 otherwise).
-    double vcycle_bytes(int k) const {
-        if (fd_on) return 0.0;
+    // n_c^2 s.  A tensor-smoother step on the finest level (padded sizes P_d, PP = prod P_d): forward
+    // transform r (n s) and U_d in, the transformed array (PP) out; backward transform the array, U_d and the
+    // eigenvalues in, x out (and in, when it adds); in 3D each of the six axis contractions streams the
+    // padded array in and out with its U_d.  vcycle_bytes(k, mode): patch k, one V-cycle of that mode.
+    double fd_step_bytes(int k, int mode, bool set) const {
+        const Patch& pa = plan->patches[k];
+        const Patch::Tensor& Tz = pa.ts[mode];
+        if (Tz.U[0].empty()) return 0.0;
+        const double s = sizeof(T), n = (double)pa.lv[0].n;
+        const double P0 = Tz.Pd[0], P1 = Tz.Pd[1], P2 = dim == 3 ? Tz.Pd[2] : 1.0;
+        const double PP = P0 * P1 * P2;
+        const double su = (dim == 2 && std::is_same<T, float>::value) ? 4.0 : 8.0;   // U and array in FP32 (2D)
+        const double U = P0 * P0 + P1 * P1 + (dim == 3 ? P2 * P2 : 0.0);
+        const double lam = 8.0 * (P0 + P1 + (dim == 3 ? P2 : 0.0));
+        const double xio = set ? n * s : 2.0 * n * s;
+        if (dim == 2) return (n * s + U * su + PP * su) + (PP * su + U * su + lam + xio);
+        // 3D: r -> z (axis 0), four middle contractions, z -> x (axis 0)
+        return (n * s + P0 * P0 * 8.0 + PP * 8.0) + 4.0 * (2.0 * PP * 8.0) + (P1 * P1 + P2 * P2) * 2.0 * 8.0 + lam +
+               (PP * 8.0 + P0 * P0 * 8.0 + xio);
+    }
+    double vcycle_bytes(int k, int mode) const {
         const Patch& pa = plan->patches[k];
         const int nl = (int)pa.lv.size();
         const double s = sizeof(T);
@@ -790,8 +819,13 @@ struct Solver : SolverBase {
                 b += 2.0 * n * s + n * n * s;
                 break;
             }
-            const int m = l == 0 ? cheb_m : cheb_mc;
             const double nc = (double)pa.lv[l + 1].n;
+            if (l == 0 && fd_on && !pa.ts[mode].U[0].empty()) {
+                b += fd_step_bytes(k, mode, true) + (3.0 + nst) * n * s + (n + nc) * s;   // step from zero, residual
+                b += (2.0 * n + nc) * s + (3.0 + nst) * n * s + fd_step_bytes(k, mode, false);
+                continue;
+            }
+            const int m = l == 0 ? cheb_m : cheb_mc;
             b += 4.0 * n * s + (m - 1) * (5.0 + nst) * n * s;   // pre-smoothing from zero
             b += (3.0 + nst) * n * s + (n + nc) * s;              // residual, restriction
             b += (2.0 * n + nc) * s + m * (5.0 + nst) * n * s;    // prolongation, post-smoothing
@@ -810,7 +844,7 @@ struct Solver : SolverBase {
                 continue;
             }
             const double init = n * (40.0 + s);
-            const double iter = vcycle_bytes(k) + n * (s + 8.0) + n * (s + 16.0) + n * (8.0 * nst + 24.0) +
+            const double iter = vcycle_bytes(k, MODE_N) + n * (s + 8.0) + n * (s + 16.0) + n * (8.0 * nst + 24.0) +
                                 n * (48.0 + s);
             b += init + (double)itk[k] * iter;
         }
@@ -828,7 +862,7 @@ struct Solver : SolverBase {
                 b += (double)pa.band[1].size() * 8.0 + 16.0 * n;
             } else {
                 const int cyc = std::max(1, plan->opt.prec_vcycles);
-                b += cyc * vcycle_bytes(k) + (cyc - 1) * ((3.0 + nst) * n * s + 3.0 * n * s);
+                b += cyc * vcycle_bytes(k, MODE_D) + (cyc - 1) * ((3.0 + nst) * n * s + 3.0 * n * s);
             }
             b += n * (s + 16.0) + n * (8.0 * nst + 16.0);   // w = v + x_I, s = K w
         }
@@ -1309,7 +1343,7 @@ struct Solver : SolverBase {
             return at;
         };
         m.partial = take(4 * (int64_t)lev[0].nt_all + 4);
-        m.sc = take(16);
+        m.sc = take(16 * (int64_t)ncomp);
         m.bb = take(N);
         m.dq = take(N);
         m.beta = take(N);
@@ -1391,6 +1425,7 @@ struct Solver : SolverBase {
             if (g.second) (void)hipGraphExecDestroy(g.second);
         if (h_nactive) (void)hipHostFree(h_nactive);
         if (h_sc) (void)hipHostFree(h_sc);
+        if (h_done) (void)hipHostFree(h_done);
     }
 };
 
@@ -1798,8 +1833,21 @@ void Solver<T>::setup() {
     brk = arena.alloc<int>(N, st);
     nactive = arena.alloc<int>(8, st);
     h_its.assign(N, 0);
+    ncomp = std::max(1, pl.ncomp);
+    if (ncomp > 1 && pl.opt.local_solver == IETI_LOCAL_MG_SADDLE)
+        throw Error(IETI_ENOTSUP, "MG-MG-S solves one problem at a time");
+    h_comp_lam = pl.comp_lam_beg;
+    if ((int)h_comp_lam.size() != ncomp + 1) h_comp_lam = {0, pl.n_lambda};
+    {
+        std::vector<int64_t> cp = pl.comp_patch_beg;
+        if ((int)cp.size() != ncomp + 1) cp = {0, (int64_t)N};
+        comp_lam = arena.upload(h_comp_lam, st);
+        comp_patch = arena.upload(cp, st);
+    }
+    done_dev = arena.alloc<int>(ncomp, st);
     HIPCHECK(hipHostMalloc((void**)&h_nactive, sizeof(int)));
-    HIPCHECK(hipHostMalloc((void**)&h_sc, 16 * sizeof(double)));
+    HIPCHECK(hipHostMalloc((void**)&h_sc, 16 * (size_t)ncomp * sizeof(double)));
+    HIPCHECK(hipHostMalloc((void**)&h_done, (size_t)ncomp * sizeof(int)));
 
     // ---- jump operators (device positions on level 0)
     auto devpos = [&](int64_t torn) {
@@ -1869,7 +1917,7 @@ void Solver<T>::setup() {
     lp = arena.alloc<double>(nl, st);
     lq = arena.alloc<double>(nl, st);
     ltmp = arena.alloc<double>(nl, st);
-    sc = arena.alloc<double>(16, st);
+    sc = arena.alloc<double>(16 * (int64_t)ncomp, st);
     // ---- load-vector tables
     {
         std::vector<PatchQ> pq(N);
@@ -2114,58 +2162,83 @@ int Solver<T>::solve(const double* f_qp, double* u_out, ieti_stats* stp) {
     }
     ktilde_inv(f64, true, pl.opt.inner_tol, u64);
     const int64_t nl = nlam;
-    double r0 = 0.0, scale = 0.0;
+    const int nc = ncomp;
     if (nl > 0) {
         gather(u64, false, lr);
         gather(u64, false, lz, true);
         gather(u64, false, ltmp, false, true);
-        hipLaunchKernelGGL(k_norms, dim3(1), dim3(1024), 0, stream, nl, lr, lz, ltmp, sc + 10);
+        hipLaunchKernelGGL(k_norms, dim3(nc), dim3(1024), 0, stream, comp_lam, lr, lz, ltmp, sc + 10);
         check_launch();
     }
-    HIPCHECK(hipMemcpyAsync(h_sc, sc, 16 * sizeof(double), hipMemcpyDeviceToHost, stream));
+    HIPCHECK(hipMemcpyAsync(h_sc, sc, 16 * (size_t)nc * sizeof(double), hipMemcpyDeviceToHost, stream));
     sync();
     if (!std::isfinite(h_sc[8])) throw Error(IETI_EINVAL, "right-hand side is not finite");
-    if (nl > 0) {
-        r0 = std::sqrt(h_sc[10]);
-        scale = std::sqrt(h_sc[11] + h_sc[12]);
+    // ---- outer CG, one per problem (ieti_solve: one; a serving batch: one per request), batched launches
+    std::vector<double> r0(nc, 0.0), rnorm(nc, 0.0);
+    std::vector<int> its_c(nc, 0), conv(nc, 0), brk_c(nc, 0);
+    for (int c = 0; c < nc; ++c) {
+        const bool has = h_comp_lam[c + 1] > h_comp_lam[c];
+        r0[c] = rnorm[c] = has ? std::sqrt(h_sc[16 * c + 10]) : 0.0;
+        const double scale = has ? std::sqrt(h_sc[16 * c + 11] + h_sc[16 * c + 12]) : 0.0;
+        const double zero_thr = (exact ? 1e-13 : 10.0 * pl.opt.inner_tol) * scale;
+        h_done[c] = 0;
+        if (!has) {   // no multipliers: the primal part alone solves it
+            h_done[c] = 1;
+            conv[c] = 1;
+        } else if (!(r0[c] > zero_thr && r0[c] > 0.0)) {   // d vanished to rounding: lambda = 0 (reading R10)
+            h_done[c] = 1;
+            conv[c] = 1;
+            brk_c[c] = 1;
+        }
     }
     auto t1 = clk::now();
-    st.residual_initial = r0;
-    // ---- outer CG
     fill<double>(lam, std::max<int64_t>(nl, 1), 0.0);
     int it = 0;
-    bool conv = true;
-    double rnorm = r0;
-    const double zero_thr = (exact ? 1e-13 : 10.0 * pl.opt.inner_tol) * scale;
-    if (nl > 0 && r0 > zero_thr && r0 > 0.0) {
+    auto active_left = [&] {
+        for (int c = 0; c < nc; ++c)
+            if (!h_done[c]) return true;
+        return false;
+    };
+    if (nl > 0 && active_left()) {
+        HIPCHECK(hipMemcpyAsync(done_dev, h_done, nc * sizeof(int), hipMemcpyHostToDevice, stream));
         applyPrec(lr, lz);
-        hipLaunchKernelGGL(k_pcg, dim3(1), dim3(1024), 0, stream, 0, nl, lam, lr, lz, lp, lq, sc);
+        hipLaunchKernelGGL(k_pcg, dim3(nc), dim3(1024), 0, stream, 0, comp_lam, done_dev, lam, lr, lz, lp, lq, sc);
         check_launch();
-        conv = false;
         while (it < pl.opt.max_it) {
             applyF(lp, lq);
-            hipLaunchKernelGGL(k_pcg, dim3(1), dim3(1024), 0, stream, 1, nl, lam, lr, lz, lp, lq, sc);
+            hipLaunchKernelGGL(k_pcg, dim3(nc), dim3(1024), 0, stream, 1, comp_lam, done_dev, lam, lr, lz, lp, lq,
+                               sc);
             check_launch();
-            HIPCHECK(hipMemcpyAsync(h_sc, sc, 8 * sizeof(double), hipMemcpyDeviceToHost, stream));
+            HIPCHECK(hipMemcpyAsync(h_sc, sc, 16 * (size_t)nc * sizeof(double), hipMemcpyDeviceToHost, stream));
             sync();
             ++it;
-            rnorm = std::sqrt(h_sc[3]);
-            if (!(rnorm - rnorm == 0.0)) break;   // NaN or Inf: not converged
-            if (rnorm <= pl.opt.tol * r0) { conv = true; break; }
-            // (p, F p) <= 0 with a residual above the tolerance: F is not positive on the search direction
-            // (inexact local solves that failed, or rounding); report it and stop unconverged
-            if (h_sc[4] != 0.0) { st.breakdown = 1; break; }
+            for (int c = 0; c < nc; ++c) {
+                if (h_done[c]) continue;
+                ++its_c[c];
+                const double rn = std::sqrt(h_sc[16 * c + 3]);
+                rnorm[c] = rn;
+                if (!(rn - rn == 0.0)) {   // NaN or Inf: stopped, not converged
+                    h_done[c] = 1;
+                } else if (rn <= pl.opt.tol * r0[c]) {
+                    h_done[c] = 1;
+                    conv[c] = 1;
+                } else if (h_sc[16 * c + 4] != 0.0) {
+                    // (p, F p) <= 0 with a residual above the tolerance: F is not positive on the search direction
+                    // (inexact local solves that failed, or rounding); report it and stop unconverged
+                    h_done[c] = 1;
+                    brk_c[c] = 1;
+                }
+            }
+            if (!active_left()) break;
+            HIPCHECK(hipMemcpyAsync(done_dev, h_done, nc * sizeof(int), hipMemcpyHostToDevice, stream));
             applyPrec(lr, lz);
-            hipLaunchKernelGGL(k_pcg, dim3(1), dim3(1024), 0, stream, 2, nl, lam, lr, lz, lp, lq, sc);
+            hipLaunchKernelGGL(k_pcg, dim3(nc), dim3(1024), 0, stream, 2, comp_lam, done_dev, lam, lr, lz, lp, lq,
+                               sc);
             check_launch();
         }
-    } else if (nl > 0) {
-        st.breakdown = 1;
     }
     sync();
     auto t2 = clk::now();
-    st.outer_iterations = it;
-    st.residual_final = rnorm;
     // ---- recovery u = K~^{-1} (f - B^T lambda), averaged copies, global residual
     scatter(lam, false, b64);
     hipLaunchKernelGGL(k_sub, dim3(tile_grid(D0.nt_all)), dim3(TILE), 0, stream, D0.L, D0.tiles_all, D0.nt_all, f64,
@@ -2192,13 +2265,43 @@ int Solver<T>::solve(const double* f_qp, double* u_out, ieti_stats* stp) {
     }
     st.inner_iterations_max = inner_max;
     st.inner_iterations_mean = inner_calls ? (double)inner_sum / (double)inner_calls : 0.0;
+    // per-problem statistics (the batch's inner-iteration figures are shared)
+    comp_stats.assign(nc, st);
+    comp_rc.assign(nc, IETI_OK);
+    for (int c = 0; c < nc; ++c) {
+        ieti_stats& cs = comp_stats[c];
+        cs.outer_iterations = its_c[c];
+        cs.residual_initial = r0[c];
+        cs.residual_final = rnorm[c];
+        cs.breakdown = brk_c[c];
+        cs.global_residual = comp_gres[c];
+        cs.n_lambda = h_comp_lam[c + 1] - h_comp_lam[c];
+        cs.ndof_torn = pl.comp_torn_beg[c + 1] - pl.comp_torn_beg[c];
+        if (st.inner_nonfinite > 0 || !conv[c]) comp_rc[c] = IETI_ENOCONV;
+    }
+    st = comp_stats[0];
+    if (nc > 1) {   // the whole batch: totals and the worst problem
+        st.outer_iterations = it;
+        st.n_lambda = nl;
+        st.ndof_torn = pl.ndof_torn;
+        st.breakdown = 0;
+        for (int c = 0; c < nc; ++c) {
+            st.residual_final = std::max(st.residual_final, comp_stats[c].residual_final);
+            st.global_residual = std::max(st.global_residual, comp_stats[c].global_residual);
+            st.breakdown |= comp_stats[c].breakdown;
+        }
+    }
     if (stp) *stp = st;
+    int rc = IETI_OK;
+    for (int c = 0; c < nc; ++c)
+        if (comp_rc[c] != IETI_OK) rc = comp_rc[c];
     if (st.inner_nonfinite > 0) {
         set_last_error("a local solve produced a non-finite residual");
         return IETI_ENOCONV;
     }
-    if (!conv) set_last_error(st.breakdown ? "outer CG breakdown above the tolerance" : "outer CG did not converge");
-    return conv ? IETI_OK : IETI_ENOCONV;
+    if (rc != IETI_OK)
+        set_last_error(st.breakdown ? "outer CG breakdown above the tolerance" : "outer CG did not converge");
+    return rc;
 }
 
 // Bramble-Pasciak CG on [A B^T; B 0] (u; lambda) = (f; 0) (the saddle-point system (2) in W~):
@@ -2381,14 +2484,23 @@ void Solver<T>::finish_solution(ieti_stats& st, double* u_out) {
         hipLaunchKernelGGL(k_sq, dim3(tile_grid(D0.nt_all)), dim3(TILE), 0, stream, D0.L, D0.tiles_all, D0.nt_all, v,
                            (int)MODE_K, partial);
         check_launch();
-        hipLaunchKernelGGL(k_sum, dim3(1), dim3(1024), 0, stream, partial, (int64_t)D0.nt_all, sc + 12 + which);
+        if (ncomp == 1) {
+            hipLaunchKernelGGL(k_sum, dim3(1), dim3(1024), 0, stream, partial, (int64_t)D0.nt_all, sc + 12 + which);
+        } else {   // per problem of a batch
+            hipLaunchKernelGGL(k_sum_comp, dim3(ncomp), dim3(256), 0, stream, partial, tile_beg, tile_end, comp_patch,
+                               sc + 12 + which);
+        }
         check_launch();
     }
-    HIPCHECK(hipMemcpyAsync(h_sc + 12, sc + 12, 2 * sizeof(double), hipMemcpyDeviceToHost, stream));
+    HIPCHECK(hipMemcpyAsync(h_sc, sc, 16 * (size_t)ncomp * sizeof(double), hipMemcpyDeviceToHost, stream));
     sync();
-    acc[0] = h_sc[12];
-    acc[1] = h_sc[13];
-    st.global_residual = acc[1] > 0 ? std::sqrt(std::max(acc[0], 0.0) / acc[1]) : 0.0;
+    comp_gres.assign(ncomp, 0.0);
+    for (int c = 0; c < ncomp; ++c) {
+        acc[0] = h_sc[16 * c + 12];
+        acc[1] = h_sc[16 * c + 13];
+        comp_gres[c] = acc[1] > 0 ? std::sqrt(std::max(acc[0], 0.0) / acc[1]) : 0.0;
+    }
+    st.global_residual = comp_gres[0];
     hipLaunchKernelGGL(k_copy_out, dim3(tile_grid(D0.nt_all)), dim3(TILE), 0, stream, D0.L, D0.tiles_all, D0.nt_all,
                        torn_off, u64, u_out);
     check_launch();
@@ -2600,6 +2712,8 @@ struct SrvReq {
     std::vector<ieti_patch> patches;
     std::vector<double> f;
     double* u_out = nullptr;
+    int dim = 2;
+    int64_t ndof = 0;          // torn dofs
     int status = IETI_PENDING;
     ieti_stats st{};
     double t_submit = 0, t_admit = 0, t_done = 0;
@@ -2626,73 +2740,129 @@ struct ieti_server {
     }
 };
 
-// A worker owns one stream.  It takes the oldest waiting request, plans it on
-// the host, waits until the HBM budget admits the request's estimated device
-// footprint, builds the device state, solves, copies u to the caller and
-// frees everything.  Admitted requests of different workers overlap on the GPU.
+// A worker owns one stream.  It takes a batch of waiting requests (the oldest one and, behind it, requests
+// of the same dimension while the torn dofs stay within batch_dofs), plans them as one multi-problem solve,
+// waits until the HBM budget admits the batch's estimated device footprint, builds the device state, solves
+// (one outer CG per request, all launches over all their patches), copies every u to its caller and frees
+// everything.  Batches of different workers overlap on the GPU.  If a batch of several requests cannot be
+// planned (one invalid request), its requests are retried one by one so that only the invalid one fails.
+static void server_solve(ieti_server* S, hipStream_t st, std::vector<SrvReq*>& batch) {
+    size_t bytes = 0;
+    bool admitted = false;
+    double* fd = nullptr;
+    double* ud = nullptr;
+    ieti_handle* h = nullptr;
+    std::vector<int> rcs(batch.size(), IETI_OK);
+    std::vector<ieti_stats> sts(batch.size());
+    try {
+        ieti_options o = S->opt;
+        o.stream = st;
+        o.hbm_budget = 0;
+        o.device = S->device;
+        std::vector<ieti_patch> all;
+        std::vector<int32_t> comp;
+        int64_t nq_all = 0;
+        for (size_t b = 0; b < batch.size(); ++b) {
+            for (const ieti_patch& p : batch[b]->patches) {
+                all.push_back(p);
+                comp.push_back((int32_t)b);
+            }
+            nq_all += (int64_t)batch[b]->f.size();
+        }
+        std::unique_ptr<Plan> plan(build_plan(all.data(), (int)all.size(), nullptr, 0, &o, comp.data()));
+        if (plan->ncomp != (int)batch.size()) throw Error(IETI_EINVAL, "internal: batch problem count");
+        for (size_t b = 0; b < batch.size(); ++b)
+            if ((int64_t)batch[b]->f.size() != plan->comp_qp_beg[b + 1] - plan->comp_qp_beg[b])
+                throw Error(IETI_EINVAL, "f has the wrong number of values");
+        bytes = estimate_device_bytes(*plan) + (size_t)(plan->n_qp + plan->ndof_torn) * sizeof(double);
+        {
+            std::unique_lock<std::mutex> lk(S->mu);
+            if (S->budget && bytes > S->budget) throw Error(IETI_ENOMEM, "request larger than the HBM budget");
+            S->cv_mem.wait(lk, [&] { return !S->budget || S->in_use + bytes <= S->budget; });
+            S->in_use += bytes;
+            admitted = true;
+            const double ta = S->now_ms();   // one admission for the whole batch
+            for (SrvReq* r : batch) r->t_admit = ta;
+        }
+        const int64_t nq = plan->n_qp, nt = plan->ndof_torn;
+        std::vector<int64_t> tb = plan->comp_torn_beg;
+        h = make_handle(std::move(plan));
+        HIPCHECK(hipMalloc((void**)&fd, sizeof(double) * nq));
+        HIPCHECK(hipMalloc((void**)&ud, sizeof(double) * nt));
+        int64_t qo = 0;
+        for (SrvReq* r : batch) {
+            HIPCHECK(hipMemcpyAsync(fd + qo, r->f.data(), sizeof(double) * r->f.size(), hipMemcpyHostToDevice, st));
+            qo += (int64_t)r->f.size();
+        }
+        ieti_stats all_st{};
+        const int rc_all = h->s->solve(fd, ud, &all_st);
+        for (size_t b = 0; b < batch.size(); ++b) {
+            HIPCHECK(hipMemcpyAsync(batch[b]->u_out, ud + tb[b], sizeof(double) * (size_t)(tb[b + 1] - tb[b]),
+                                    hipMemcpyDeviceToHost, st));
+            sts[b] = b < h->s->comp_stats.size() ? h->s->comp_stats[b] : all_st;
+            rcs[b] = b < h->s->comp_rc.size() ? h->s->comp_rc[b] : rc_all;
+            if (all_st.inner_nonfinite > 0) rcs[b] = IETI_ENOCONV;
+        }
+        HIPCHECK(hipStreamSynchronize(st));
+    } catch (const Error& e) {
+        for (auto& rc : rcs) rc = e.code;
+        set_last_error(e.what());
+    } catch (const std::exception& e) {
+        for (auto& rc : rcs) rc = IETI_EINVAL;
+        set_last_error(e.what());
+    }
+    if (h) ieti_destroy(h);
+    if (fd) (void)hipFree(fd);
+    if (ud) (void)hipFree(ud);
+    if (!admitted && batch.size() > 1 && rcs[0] != IETI_OK) {
+        // the batch failed before it ran: retry its requests one by one
+        for (SrvReq* r : batch) {
+            std::vector<SrvReq*> one{r};
+            server_solve(S, st, one);
+        }
+        return;
+    }
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        if (admitted) S->in_use -= bytes;
+        const double t = S->now_ms();
+        for (size_t b = 0; b < batch.size(); ++b) {
+            batch[b]->st = sts[b];
+            batch[b]->t_done = t;
+            batch[b]->status = rcs[b];
+            --S->running;
+        }
+    }
+    S->cv_mem.notify_all();
+    S->cv_done.notify_all();
+}
+
 static void server_worker(ieti_server* S) {
     (void)hipSetDevice(S->device);
     hipStream_t st = nullptr;
     if (hipStreamCreate(&st) != hipSuccess) return;
     for (;;) {
-        SrvReq* r = nullptr;
+        std::vector<SrvReq*> batch;
         {
             std::unique_lock<std::mutex> lk(S->mu);
             S->cv_work.wait(lk, [&] { return S->stop || !S->queue.empty(); });
             if (S->queue.empty()) break;
-            r = S->queue.front();
-            S->queue.pop_front();
-            ++S->running;
-        }
-        size_t bytes = 0;
-        bool admitted = false;
-        int rc = IETI_OK;
-        double* fd = nullptr;
-        double* ud = nullptr;
-        ieti_handle* h = nullptr;
-        try {
-            ieti_options o = S->opt;
-            o.stream = st;
-            o.hbm_budget = 0;
-            o.device = S->device;
-            std::unique_ptr<Plan> plan(build_plan(r->patches.data(), (int)r->patches.size(), nullptr, 0, &o));
-            if ((int64_t)r->f.size() != plan->n_qp) throw Error(IETI_EINVAL, "f has the wrong number of values");
-            bytes = estimate_device_bytes(*plan) + (size_t)(plan->n_qp + plan->ndof_torn) * sizeof(double);
-            {
-                std::unique_lock<std::mutex> lk(S->mu);
-                if (S->budget && bytes > S->budget) throw Error(IETI_ENOMEM, "request larger than the HBM budget");
-                S->cv_mem.wait(lk, [&] { return !S->budget || S->in_use + bytes <= S->budget; });
-                S->in_use += bytes;
-                admitted = true;
-                r->t_admit = S->now_ms();
+            int64_t dofs = 0;
+            for (auto it = S->queue.begin(); it != S->queue.end();) {
+                SrvReq* r = *it;
+                if (!batch.empty() && (r->dim != batch[0]->dim || dofs + r->ndof > S->opt.batch_dofs)) {
+                    if (dofs + r->ndof > S->opt.batch_dofs) break;   // keep arrival order within the size cap
+                    ++it;
+                    continue;
+                }
+                batch.push_back(r);
+                dofs += r->ndof;
+                it = S->queue.erase(it);
+                if (S->opt.batch_dofs <= 0) break;
             }
-            const int64_t nq = plan->n_qp, nt = plan->ndof_torn;
-            h = make_handle(std::move(plan));
-            HIPCHECK(hipMalloc((void**)&fd, sizeof(double) * nq));
-            HIPCHECK(hipMalloc((void**)&ud, sizeof(double) * nt));
-            HIPCHECK(hipMemcpyAsync(fd, r->f.data(), sizeof(double) * nq, hipMemcpyHostToDevice, st));
-            rc = h->s->solve(fd, ud, &r->st);
-            HIPCHECK(hipMemcpyAsync(r->u_out, ud, sizeof(double) * nt, hipMemcpyDeviceToHost, st));
-            HIPCHECK(hipStreamSynchronize(st));
-        } catch (const Error& e) {
-            rc = e.code;
-            set_last_error(e.what());
-        } catch (const std::exception& e) {
-            rc = IETI_EINVAL;
-            set_last_error(e.what());
+            S->running += (int)batch.size();
         }
-        if (h) ieti_destroy(h);
-        if (fd) (void)hipFree(fd);
-        if (ud) (void)hipFree(ud);
-        {
-            std::lock_guard<std::mutex> lk(S->mu);
-            if (admitted) S->in_use -= bytes;
-            r->t_done = S->now_ms();
-            r->status = rc;
-            --S->running;
-        }
-        S->cv_mem.notify_all();
-        S->cv_done.notify_all();
+        server_solve(S, st, batch);
     }
     (void)hipStreamDestroy(st);
 }
@@ -2743,6 +2913,8 @@ int ieti_server_submit(ieti_server* S, const ieti_patch* patches, int32_t n_patc
             }
             r->ctrl.emplace_back(p.ctrl, p.ctrl + nc * p.dim);
             r->patches.push_back(p);
+            r->dim = p.dim;
+            r->ndof += nc;
         }
         size_t kk = 0;
         for (int k = 0; k < n_patches; ++k) {
