@@ -278,6 +278,8 @@ def main():
     ap.add_argument("--precision", type=int, choices=[32, 64], default=64,
                     help="multigrid precision of the headline solver (the outer CG is always FP64)")
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="deformed16x16")
+    ap.add_argument("--coarse-degree", type=int, choices=[0, 1], default=0,
+                    help="1: degree-1 coarse levels with L2-projection transfers (Sec. 4)")
     ap.add_argument("--coarse-level", type=int, default=0,
                     help="first multigrid level of the fused per-patch coarse kernel (0: the library's choice, "
                          "-1: every level by batched launches)")
@@ -320,6 +322,8 @@ def main():
           flush=True)
     if args.coarse_level:
         extra_opt["coarse_level"] = args.coarse_level
+    if args.coarse_degree:
+        extra_opt["coarse_degree"] = args.coarse_degree
     m = measure(wl, gname, args.steps, args.warmup, local_solver=variant, mg_precision=args.precision, **extra_opt)
     ms_per_step = m["ms_per_step"]
     value = wl.ndof_torn / (ms_per_step * 1e-3) / 1e6

@@ -138,6 +138,11 @@ typedef struct ieti_options {
                                   every kernel launch over the patches of all of them, one outer CG per request
                                   (its own scalars, stopping test and statistics).  0 = one request per batch.
                                   Default 2,000,000 */
+    int32_t coarse_degree;     /* multigrid: 0 = every level keeps the patch's spline degree (nested levels,
+                                  canonical embedding; default); 1 = degree 1 on all levels but the finest
+                                  (Sec. 4, the paper's choice for higher degrees): the finest-to-first-coarse
+                                  transfers are the L2 projection of the parameter domain, M_f^{-1} M_fc, and its
+                                  transpose (non-nested spaces); coarser transfers stay nested */
 } ieti_options;
 
 typedef struct ieti_stats {

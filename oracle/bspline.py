@@ -99,3 +99,23 @@ def prolongation(coarse: np.ndarray, fine: np.ndarray, p: int) -> np.ndarray:
     P = np.linalg.solve(Af, Ac)
     P[np.abs(P) < 1e-14] = 0.0
     return P
+
+
+def mixed_mass(tf: np.ndarray, pf: int, tc: np.ndarray, pc: int) -> np.ndarray:
+    """Mass matrix between two spline spaces on [0, 1]: M[i, j] = int N_i^{(tf, pf)} N_j^{(tc, pc)} dx, by
+    Gauss quadrature with pf + pc + 1 points on every interval between consecutive breakpoints of either
+    space (exact for the polynomial products there)."""
+    b = np.union1d(breakpoints(tf), breakpoints(tc))
+    g, w = np.polynomial.legendre.leggauss(pf + pc + 1)
+    g, w = 0.5 * (g + 1.0), 0.5 * w
+    xs = np.concatenate([a + (c - a) * g for a, c in zip(b[:-1], b[1:])])
+    ws = np.concatenate([(c - a) * w for a, c in zip(b[:-1], b[1:])])
+    return basis(tf, pf, xs).T @ (ws[:, None] * basis(tc, pc, xs))
+
+
+def l2_projection(tf: np.ndarray, pf: int, tc: np.ndarray, pc: int) -> np.ndarray:
+    """Coefficient map of the L2 projection from the space (tc, pc) onto the space (tf, pf) on [0, 1]:
+    u_f = M_f^{-1} M_fc u_c, M_f the mass matrix of the target space and M_fc the mixed one.  This is the
+    transfer between non-nested multigrid levels (degree p on the finest level, degree 1 below, Sec. 4);
+    its tensor product over the directions is the parametric projection of a patch."""
+    return np.linalg.solve(mixed_mass(tf, pf, tf, pf), mixed_mass(tf, pf, tc, pc))

@@ -84,6 +84,7 @@ class IetiOptions(C.Structure):
         ("smoother_sigma", C.c_double),
         ("tune_cache", C.c_char_p),
         ("batch_dofs", C.c_int64),
+        ("coarse_degree", C.c_int32),
     ]
 
 

@@ -5,7 +5,7 @@
 namespace ieti {
 
 constexpr int TILE = 256;        // coefficients per work-group tile (one per thread)
-constexpr int PW = 8;            // padded width of 1D transfer bands (degree <= 6)
+constexpr int PW = 12;           // padded width of 1D transfer bands (nested: degree <= 10; L2 projection to degree 1: p <= 8)
 constexpr int NPMAX = 20;        // local primal constraints per patch (8 vertices + 12 edges)
 
 // Degree classes with their own unrolled kernels: 2D (p0, p1) in {2,3,4}^2 ->
@@ -54,6 +54,8 @@ struct PatchLev {
     int64_t toff[3];       // prolongation table offsets per direction (fine = this level)
     int64_t roff[3];       // restriction table offsets per direction (coarse = next level)
     int64_t invoff;        // coarsest level: offset of the dense inverses (mode N, then mode D)
+    int64_t moff[3];       // L2-projection transfer to the next level: offsets of the banded Cholesky factors
+                           // of the 1D parametric mass matrices (M_d x (p_d + 1) each); moff[0] < 0: nested
 };
 
 // Level-0 quadrature layout of one patch (load vector).

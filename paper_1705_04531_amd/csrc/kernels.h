@@ -655,6 +655,156 @@ __global__ __launch_bounds__(TILE) void k_prolong(const PatchLev* Lf, const Patc
     xf[vi] = T((double)xf[vi] + acc);
 }
 
+// ---- transfers between non-nested levels (degree p finest, degree 1 coarse): the L2 projection of the
+// parameter domain, P = D_f M_f^{-1} M_fc D_c, R = P^T (D the masks of the mode).  The mixed mass matrix
+// M_fc is a tensor product of 1D bands (rows of the fine level: plo/pval; columns: rlo/rval, width PW);
+// M_f^{-1} is applied by 1D banded Cholesky solves along every direction.
+
+// t_f = D_f M_fc e_c (fine tiles)
+template <typename T>
+__global__ __launch_bounds__(TILE) void k_l2_prolong(const PatchLev* Lf, const PatchLev* Lc, const Tile* tiles,
+                                                     int ntiles, const int32_t* plo, const T* pval, const T* ec,
+                                                     T* t, int mode, const int* active) {
+    const int tt = tile_index(ntiles);
+    if (tt < 0) return;
+    const Tile tl = tiles[tt];
+    const PatchLev& F = Lf[tl.pl];
+    if (active && !active[F.patch]) return;
+    const int i = tl.start + (int)threadIdx.x;
+    if (i >= (int)F.n) return;
+    int i0, i1, i2;
+    unlin(F, i, i0, i1, i2);
+    const int64_t vi = F.voff + i;
+    if (masked(F, mode, i0, i1, i2)) {
+        t[vi] = T(0);
+        return;
+    }
+    const PatchLev& C = Lc[F.coarse];
+    const bool three = F.dim == 3;
+    const int lo0 = plo[F.toff[0] + i0], lo1 = plo[F.toff[1] + i1], lo2 = three ? plo[F.toff[2] + i2] : 0;
+    const T* v0 = pval + (F.toff[0] + i0) * PW;
+    const T* v1 = pval + (F.toff[1] + i1) * PW;
+    const T* v2 = three ? pval + (F.toff[2] + i2) * PW : nullptr;
+    const int C0 = C.M[0], C1 = C.M[1], C2 = C.M[2];
+    double acc = 0.0;
+    for (int a2 = 0; a2 < (three ? PW : 1); ++a2) {
+        const int j2 = lo2 + a2;
+        if (j2 >= C2) break;
+        const double w2 = three ? (double)v2[a2] : 1.0;
+        for (int a1 = 0; a1 < PW && lo1 + a1 < C1; ++a1) {
+            const double w12 = w2 * (double)v1[a1];
+            const T* row = ec + C.voff + (int64_t)(j2 * C1 + lo1 + a1) * C0 + lo0;
+            for (int a0 = 0; a0 < PW && lo0 + a0 < C0; ++a0) acc += w12 * (double)v0[a0] * (double)row[a0];
+        }
+    }
+    t[vi] = T(acc);
+}
+
+// b_c = D_c M_cf t_f (coarse tiles)
+template <typename T>
+__global__ __launch_bounds__(TILE) void k_l2_restrict(const PatchLev* Lf, const PatchLev* Lc, const Tile* tiles,
+                                                      int ntiles, const int32_t* rlo, const T* rval, const T* tf,
+                                                      T* bc, int mode, const int* active) {
+    const int tt = tile_index(ntiles);
+    if (tt < 0) return;
+    const Tile tl = tiles[tt];
+    const PatchLev& C = Lc[tl.pl];
+    if (active && !active[C.patch]) return;
+    const int I = tl.start + (int)threadIdx.x;
+    if (I >= (int)C.n) return;
+    int I0, I1, I2;
+    unlin(C, I, I0, I1, I2);
+    if (masked(C, mode, I0, I1, I2)) {
+        bc[C.voff + I] = T(0);
+        return;
+    }
+    const PatchLev& F = Lf[C.fine];
+    const bool three = F.dim == 3;
+    const int lo0 = rlo[F.roff[0] + I0], lo1 = rlo[F.roff[1] + I1], lo2 = three ? rlo[F.roff[2] + I2] : 0;
+    const T* v0 = rval + (F.roff[0] + I0) * PW;
+    const T* v1 = rval + (F.roff[1] + I1) * PW;
+    const T* v2 = three ? rval + (F.roff[2] + I2) * PW : nullptr;
+    const int M0 = F.M[0], M1 = F.M[1], M2 = F.M[2];
+    double acc = 0.0;
+    for (int a2 = 0; a2 < (three ? PW : 1); ++a2) {
+        const int j2 = lo2 + a2;
+        if (j2 >= M2) break;
+        const double w2 = three ? (double)v2[a2] : 1.0;
+        for (int a1 = 0; a1 < PW && lo1 + a1 < M1; ++a1) {
+            const double w12 = w2 * (double)v1[a1];
+            const T* row = tf + F.voff + (int64_t)(j2 * M1 + lo1 + a1) * M0 + lo0;
+            for (int a0 = 0; a0 < PW && lo0 + a0 < M0; ++a0) acc += w12 * (double)v0[a0] * (double)row[a0];
+        }
+    }
+    bc[C.voff + I] = T(acc);
+}
+
+// out = (mask_out ? D_f : I) M_f^{-1} in on the patches of plist (one work-group each, the patch's array in
+// LDS): a forward and a backward banded substitution along every line of every direction
+template <typename T>
+__global__ __launch_bounds__(TILE) void k_mass_solve(const PatchLev* L, const int32_t* plist, int nlist,
+                                                     const double* mchol, const T* in, T* out, int mode,
+                                                     int mask_out, const int* active) {
+    extern __shared__ unsigned char ms_lds_raw[];
+    T* a = (T*)ms_lds_raw;
+    if ((int)blockIdx.x >= nlist) return;
+    const PatchLev& P = L[plist[blockIdx.x]];
+    if (active && !active[P.patch]) return;
+    const int n = (int)P.n;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) a[i] = in[P.voff + i];
+    __syncthreads();
+    const int M[3] = {P.M[0], P.M[1], P.M[2]};
+    for (int d = 0; d < P.dim; ++d) {
+        const int Md = M[d], pd = P.p[d], w = pd + 1;
+        const int stride = d == 0 ? 1 : (d == 1 ? M[0] : M[0] * M[1]);
+        const double* Lc = mchol + P.moff[d];
+        const int nlines = n / Md;
+        for (int ln = threadIdx.x; ln < nlines; ln += blockDim.x) {
+            // line ln: the other coordinates; base index of its entry 0
+            int base;
+            if (d == 0) base = ln * M[0];
+            else if (d == 1) base = (ln % M[0]) + (ln / M[0]) * M[0] * M[1];
+            else base = ln;
+            for (int i = 0; i < Md; ++i) {   // L y = a
+                double v = (double)a[base + i * stride];
+                for (int k = (i - pd > 0 ? i - pd : 0); k < i; ++k)
+                    v -= Lc[(int64_t)i * w + (k - i + pd)] * (double)a[base + k * stride];
+                a[base + i * stride] = T(v / Lc[(int64_t)i * w + pd]);
+            }
+            for (int i = Md - 1; i >= 0; --i) {   // L^T x = y
+                double v = (double)a[base + i * stride];
+                for (int k = i + 1; k <= (i + pd < Md - 1 ? i + pd : Md - 1); ++k)
+                    v -= Lc[(int64_t)k * w + (i - k + pd)] * (double)a[base + k * stride];
+                a[base + i * stride] = T(v / Lc[(int64_t)i * w + pd]);
+            }
+        }
+        __syncthreads();
+    }
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        T v = a[i];
+        if (mask_out) {
+            int i0, i1, i2;
+            unlin(P, i, i0, i1, i2);
+            if (masked(P, mode, i0, i1, i2)) v = T(0);
+        }
+        out[P.voff + i] = v;
+    }
+}
+
+// x += y on the tiles of active patches
+template <typename T>
+__global__ __launch_bounds__(TILE) void k_add_act(const PatchLev* L, const Tile* tiles, int ntiles, const T* y, T* x,
+                                                  const int* active) {
+    const int tt = tile_index(ntiles);
+    if (tt < 0) return;
+    const Tile tl = tiles[tt];
+    const PatchLev& P = L[tl.pl];
+    if (active && !active[P.patch]) return;
+    const int i = tl.start + (int)threadIdx.x;
+    if (i >= (int)P.n) return;
+    x[P.voff + i] += y[P.voff + i];
+}
+
 // y = A b for a dense n x n matrix stored by columns (entry (r, j) at
 // At[j * n + r]): one thread per row, so that every column load is
 // contiguous across the lanes; the column loop is unrolled to keep many
@@ -1896,6 +2046,275 @@ __global__ __launch_bounds__(BAND_PF_THREADS) void k_band_solve_pf(const PatchLe
         step(r, xs + (r + 1) * BNB);
     }
     for (int i = threadIdx.x; i < n; i += blockDim.x) x[P.voff + i] = xs[i];
+}
+
+// ------------------------------------------------------------------ exact local solves, 3D: factorised on the device
+//
+// The band of a 3D patch (b = p0 + p1 M0 + p2 M0 M1, ~1400 for 26^3 coefficients at p = 2) is too wide for
+// the host factorisation and for the LDS-resident solve above.  Here the masked level-0 stiffness (masked
+// rows and columns replaced by the identity) of each job (patch, mode) is held in block-band storage of
+// BNB x BNB blocks: block row R keeps blocks C = R - W .. R (W = ceil(b / BNB)) at slots w = C - R + W, each
+// row-major; blocks left of column 0 are zero and the padding rows past n carry the identity.  It is
+// factorised in place, right-looking over block columns k (batched over all jobs, three launches per k):
+//   L_kk = chol(A_kk) (its inverse kept for the solves), L_Rk = A_Rk L_kk^{-T} (R = k+1 .. k+W),
+//   A_RC -= L_Rk L_Ck^T (k < C <= R <= k+W).
+// The solve streams the factor from HBM, one work-group per patch, with a window of the last W+1 solved
+// blocks in LDS.
+
+struct BandJob {
+    int64_t off;       // first double of the job's block band (nb x (W+1) blocks)
+    int64_t doff;      // first double of the inverses of its diagonal blocks (nb blocks)
+    int32_t patch, mode, nb, W;
+    int32_t toff;      // offset of the patch's stencil slot table
+};
+
+// slot table of a patch: entry (d0+p0) + (2p0+1)((d1+p1) + (2p1+1)(d2+p2)) for the offset d = j - i gives
+// s + 1 when K(i, j) = coef[s][i] (d in the upper half), -(s + 1) when K(i, j) = coef[s][j] (d in the lower
+// half, -d in the upper), 0 for no entry
+__global__ __launch_bounds__(256) void k_bb_assemble(const PatchLev* L, const BandJob* jobs, const int32_t* stab,
+                                                     const double* coef, double* F) {
+    const BandJob J = jobs[blockIdx.y];
+    const int nblocks = J.nb * (J.W + 1);
+    if ((int)blockIdx.x >= nblocks) return;
+    const int R = blockIdx.x / (J.W + 1), w = blockIdx.x % (J.W + 1), C = R - J.W + w;
+    const PatchLev& P = L[J.patch];
+    const int n = (int)P.n;
+    double* blk = F + J.off + (int64_t)blockIdx.x * BNB * BNB;
+    const int M0 = P.M[0], M01 = P.M[0] * P.M[1];
+    const int w0 = 2 * P.p[0] + 1, w1 = 2 * P.p[1] + 1;
+    for (int e = threadIdx.x; e < BNB * BNB; e += blockDim.x) {
+        const int ii = e / BNB, jj = e % BNB;
+        const int i = R * BNB + ii, j = C * BNB + jj;
+        double v = 0.0;
+        if (C >= 0 && j <= i) {
+            if (i >= n || j >= n) {
+                v = i == j ? 1.0 : 0.0;
+            } else {
+                const int i2 = i / M01, ri = i - i2 * M01, i1 = ri / M0, i0 = ri - i1 * M0;
+                const int j2 = j / M01, rj = j - j2 * M01, j1 = rj / M0, j0 = rj - j1 * M0;
+                if (masked(P, J.mode, i0, i1, i2) || masked(P, J.mode, j0, j1, j2)) {
+                    v = i == j ? 1.0 : 0.0;
+                } else {
+                    const int d0 = j0 - i0, d1 = j1 - i1, d2 = j2 - i2;
+                    if (abs(d0) <= P.p[0] && abs(d1) <= P.p[1] && abs(d2) <= P.p[2]) {
+                        const int t = stab[J.toff + (d0 + P.p[0]) + w0 * ((d1 + P.p[1]) + w1 * (d2 + P.p[2]))];
+                        if (t > 0) v = coef[P.coff + (int64_t)(t - 1) * P.cstride + i];
+                        else if (t < 0) v = coef[P.coff + (int64_t)(-t - 1) * P.cstride + j];
+                    }
+                }
+            }
+        }
+        blk[e] = v;
+    }
+}
+
+// L_kk = chol(A_kk) in place (upper triangle zeroed) and D_k = L_kk^{-1}; one work-group per job
+__global__ __launch_bounds__(256) void k_bb_potrf(const BandJob* jobs, int k, double* F, double* D, int* err) {
+    __shared__ double A[BNB][BNB + 1];
+    const BandJob J = jobs[blockIdx.x];
+    if (k >= J.nb) return;
+    double* blk = F + J.off + ((int64_t)k * (J.W + 1) + J.W) * BNB * BNB;
+    for (int e = threadIdx.x; e < BNB * BNB; e += blockDim.x) A[e / BNB][e % BNB] = blk[e];
+    __syncthreads();
+    for (int c = 0; c < BNB; ++c) {
+        const double d = A[c][c];
+        if (!(d > 0.0)) {
+            if (threadIdx.x == 0) atomicExch(err, 1);
+            return;   // uniform: every thread read the same d
+        }
+        const double sd = sqrt(d);
+        __syncthreads();
+        for (int r = c + 1 + threadIdx.x; r < BNB; r += blockDim.x) A[r][c] /= sd;
+        if (threadIdx.x == 0) A[c][c] = sd;
+        __syncthreads();
+        // trailing update of the lower triangle
+        for (int e = threadIdx.x; e < BNB * BNB; e += blockDim.x) {
+            const int r = e / BNB, q = e % BNB;
+            if (q > c && r >= q) A[r][q] -= A[r][c] * A[q][c];
+        }
+        __syncthreads();
+    }
+    for (int e = threadIdx.x; e < BNB * BNB; e += blockDim.x) {
+        const int r = e / BNB, q = e % BNB;
+        blk[e] = q <= r ? A[r][q] : 0.0;
+    }
+    // D = L^{-1}: column q by forward substitution (one thread per column)
+    double* Dk = D + J.doff + (int64_t)k * BNB * BNB;
+    if (threadIdx.x < BNB) {
+        const int q = threadIdx.x;
+        double x[BNB];
+        for (int r = 0; r < BNB; ++r) {
+            double t = r == q ? 1.0 : 0.0;
+            for (int u = q; u < r; ++u) t -= A[r][u] * x[u];
+            x[r] = r < q ? 0.0 : t / A[r][r];
+        }
+        for (int r = 0; r < BNB; ++r) Dk[(int64_t)r * BNB + q] = x[r];
+    }
+}
+
+// one 64 x 64 x 64 product on a work-group of 256 threads: C (-)= A B^T, operands in LDS (row-major, padded);
+// thread (ty, tx) owns rows 4 ty .. 4 ty + 3 and columns tx + 16 c, c = 0..3
+__device__ __forceinline__ void bb_gemm_nt(const double (*a)[BNB + 1], const double (*b)[BNB + 1], double (&acc)[4][4]) {
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    for (int t = 0; t < BNB; ++t) {
+        double av[4], bv[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) av[r] = a[4 * ty + r][t];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) bv[c] = b[tx + 16 * c][t];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[r][c] += av[r] * bv[c];
+    }
+}
+
+// L_Rk = A_Rk D_k^T for R = k + 1 + blockIdx.x (grid: W x jobs)
+__global__ __launch_bounds__(256) void k_bb_trsm(const BandJob* jobs, int k, double* F, const double* D) {
+    __shared__ double a[BNB][BNB + 1], dm[BNB][BNB + 1];
+    const BandJob J = jobs[blockIdx.y];
+    const int R = k + 1 + (int)blockIdx.x;
+    if (k >= J.nb || (int)blockIdx.x >= J.W || R >= J.nb) return;
+    double* blk = F + J.off + ((int64_t)R * (J.W + 1) + (k - R + J.W)) * BNB * BNB;
+    const double* Dk = D + J.doff + (int64_t)k * BNB * BNB;
+    for (int e = threadIdx.x; e < BNB * BNB; e += blockDim.x) {
+        a[e / BNB][e % BNB] = blk[e];
+        dm[e / BNB][e % BNB] = Dk[e];
+    }
+    __syncthreads();
+    double acc[4][4] = {};
+    bb_gemm_nt(a, dm, acc);
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) blk[(4 * ty + r) * BNB + tx + 16 * c] = acc[r][c];
+}
+
+// A_RC -= L_Rk L_Ck^T for k < C <= R <= k + W (grid: W (W + 1) / 2 x jobs; pair index -> (a, b), 1 <= b <= a)
+__global__ __launch_bounds__(256) void k_bb_update(const BandJob* jobs, int k, double* F) {
+    __shared__ double a[BNB][BNB + 1], b[BNB][BNB + 1];
+    const BandJob J = jobs[blockIdx.y];
+    if (k >= J.nb || (int)blockIdx.x >= J.W * (J.W + 1) / 2) return;
+    int ia = 1, rem = (int)blockIdx.x;
+    while (rem >= ia) {
+        rem -= ia;
+        ++ia;
+    }
+    const int ib = rem + 1;   // 1 <= ib <= ia
+    const int R = k + ia, C = k + ib;
+    if (R >= J.nb) return;
+    const int64_t rowR = (int64_t)R * (J.W + 1), rowC = (int64_t)C * (J.W + 1);
+    const double* Lr = F + J.off + (rowR + (k - R + J.W)) * BNB * BNB;
+    const double* Lc = F + J.off + (rowC + (k - C + J.W)) * BNB * BNB;
+    double* Ab = F + J.off + (rowR + (C - R + J.W)) * BNB * BNB;
+    for (int e = threadIdx.x; e < BNB * BNB; e += blockDim.x) {
+        a[e / BNB][e % BNB] = Lr[e];
+        b[e / BNB][e % BNB] = Lc[e];
+    }
+    __syncthreads();
+    double acc[4][4] = {};
+    bb_gemm_nt(a, b, acc);
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) Ab[(4 * ty + r) * BNB + tx + 16 * c] -= acc[r][c];
+}
+
+// x = (L L^T)^{-1} rhs for the jobs of one mode, one work-group of 1024 threads per patch (job_of[patch], -1:
+// none).  Forward: wave w owns rows 4w .. 4w+3 of a block row, its lanes the columns of each block;
+// backward: lanes own the rows of block R, wave w the rows jj = w (mod 16) of each block L_CR.  The last W+1
+// solved blocks stay in LDS (slot = block mod (W+1)); y goes to x between the two passes.
+constexpr int BB_THREADS = 1024;
+constexpr int BB_WMAX = 40;   // off-diagonal blocks per row the solve's LDS window holds (b <= 2560)
+__global__ __launch_bounds__(BB_THREADS) void k_bb_solve(const PatchLev* L, const BandJob* jobs, const int32_t* job_of,
+                                                         const double* F, const double* D, const double* rhs,
+                                                         double* x, const int* active) {
+    __shared__ double win[(BB_WMAX + 1) * BNB];
+    __shared__ double part[BB_THREADS / WAVE][BNB];
+    __shared__ double t[BNB];
+    const int k = blockIdx.x;
+    if (active && !active[k]) return;
+    const int jid = job_of[k];
+    if (jid < 0) return;
+    const BandJob J = jobs[jid];
+    const PatchLev& P = L[k];
+    const int n = (int)P.n, W = J.W, nb = J.nb, WP = W + 1;
+    const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x / WAVE;
+    const double* Fj = F + J.off;
+    const double* Dj = D + J.doff;
+    // forward: L y = rhs
+    for (int R = 0; R < nb; ++R) {
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int C = (R - W > 0 ? R - W : 0); C < R; ++C) {
+            const double yc = win[(C % WP) * BNB + lane];
+            const double* blk = Fj + ((int64_t)R * WP + (C - R + W)) * BNB * BNB;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[q] += blk[(4 * wv + q) * BNB + lane] * yc;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            double v = acc[q];
+            for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_down(v, o, WAVE);
+            if (lane == 0) {
+                const int i = R * BNB + 4 * wv + q;
+                t[4 * wv + q] = (i < n ? rhs[P.voff + i] : 0.0) - v;
+            }
+        }
+        __syncthreads();
+        {   // y_R = D_R t: 16 threads per row
+            const int ii = threadIdx.x >> 4, g = threadIdx.x & 15;
+            const double* Dr = Dj + (int64_t)R * BNB * BNB + (int64_t)ii * BNB;
+            double a2 = 0.0;
+            for (int c = g; c < BNB; c += 16) a2 += Dr[c] * t[c];
+            a2 = sum16(a2);
+            if (g == 0) {
+                win[(R % WP) * BNB + ii] = a2;
+                const int i = R * BNB + ii;
+                if (i < n) x[P.voff + i] = a2;
+            }
+        }
+        __syncthreads();
+    }
+    // backward: L^T x = y (the window keeps the last forward blocks, which are the first backward ones' y;
+    // it is refilled with x as blocks are solved)
+    for (int R = nb - 1; R >= 0; --R) {
+        double acc = 0.0;
+        const int Cend = R + W < nb - 1 ? R + W : nb - 1;
+        for (int C = R + 1; C <= Cend; ++C) {
+            const double* blk = Fj + ((int64_t)C * WP + (R - C + W)) * BNB * BNB;
+            const double* xc = win + (C % WP) * BNB;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int jj = wv + 16 * q;
+                acc += blk[(int64_t)jj * BNB + lane] * xc[jj];
+            }
+        }
+        part[wv][lane] = acc;
+        __syncthreads();
+        if (threadIdx.x < BNB) {
+            const int ii = threadIdx.x;
+            double sacc = 0.0;
+            for (int w = 0; w < BB_THREADS / WAVE; ++w) sacc += part[w][ii];
+            const int i = R * BNB + ii;
+            t[ii] = (i < n ? x[P.voff + i] : 0.0) - sacc;
+        }
+        __syncthreads();
+        {   // x_R = D_R^T t
+            const int ii = threadIdx.x >> 4, g = threadIdx.x & 15;
+            const double* Dr = Dj + (int64_t)R * BNB * BNB;
+            double a2 = 0.0;
+            for (int c = g; c < BNB; c += 16) a2 += Dr[(int64_t)c * BNB + ii] * t[c];
+            a2 = sum16(a2);
+            if (g == 0) {
+                win[(R % WP) * BNB + ii] = a2;
+                const int i = R * BNB + ii;
+                if (i < n) x[P.voff + i] = a2;
+            }
+        }
+        __syncthreads();
+    }
 }
 
 // ------------------------------------------------------------------ dense SPD inverse on matrix cores

@@ -58,6 +58,7 @@ void default_options(ieti_options* o) {
     o->stream = nullptr;
     o->hbm_budget = 0;
     o->batch_dofs = 2000000;
+    o->coarse_degree = 0;
 }
 
 // Smoother choice per dimension and spline degree (degree of the Chebyshev
@@ -245,6 +246,55 @@ static std::vector<double> prolongation(const std::vector<double>& coarse, const
     return P;
 }
 
+// Mixed parametric mass matrix (Mf x Mc, dense row-major) of the spline spaces (tf, pf) and (tc, pc) on
+// [0,1]: int N_i^f N_j^c, by Gauss quadrature on the union of both meshes' breakpoints with
+// max(pf, pc) + 1 points per interval (exact for the degree pf + pc products).
+static std::vector<double> mixed_mass(const std::vector<double>& tf, int pf, const std::vector<double>& tc, int pc) {
+    const int Mf = (int)tf.size() - pf - 1, Mc = (int)tc.size() - pc - 1;
+    std::vector<double> bf = breakpoints(tf), bcv = breakpoints(tc), b;
+    b.insert(b.end(), bf.begin(), bf.end());
+    b.insert(b.end(), bcv.begin(), bcv.end());
+    std::sort(b.begin(), b.end());
+    b.erase(std::unique(b.begin(), b.end(), [](double x, double y) { return std::fabs(x - y) < 1e-14; }), b.end());
+    std::vector<double> gx, gw;
+    gauss_legendre(std::max(pf, pc) + 1, gx, gw);
+    std::vector<double> A((size_t)Mf * Mc, 0.0), Nf(pf + 1), dNf(pf + 1), Nc(pc + 1), dNc(pc + 1);
+    for (size_t e = 0; e + 1 < b.size(); ++e) {
+        const double a = b[e], c = b[e + 1], mid = 0.5 * (a + c);
+        const int kf = find_span(tf, pf, mid), kc = find_span(tc, pc, mid);
+        for (size_t g = 0; g < gx.size(); ++g) {
+            const double x = a + (c - a) * gx[g], w = (c - a) * gw[g];
+            basis_on_span(tf, pf, kf, x, Nf.data(), dNf.data());
+            basis_on_span(tc, pc, kc, x, Nc.data(), dNc.data());
+            for (int i = 0; i <= pf; ++i)
+                for (int j = 0; j <= pc; ++j) A[(size_t)(kf - pf + i) * Mc + (kc - pc + j)] += w * Nf[i] * Nc[j];
+        }
+    }
+    return A;
+}
+
+// Banded Cholesky factor of the parametric mass matrix of the spline space (t, p) on [0,1]: M x (p+1),
+// row i holds L(i, i-p .. i) (entries before column 0 are zero).
+static std::vector<double> band_mass_chol(const std::vector<double>& t, int p) {
+    const std::vector<double> Mm = mixed_mass(t, p, t, p);
+    const int M = (int)t.size() - p - 1, w = p + 1;
+    std::vector<double> L((size_t)M * w, 0.0);
+    auto at = [&](int i, int j) -> double& { return L[(size_t)i * w + (j - i + p)]; };   // j in [i-p, i]
+    for (int j = 0; j < M; ++j) {
+        double d = Mm[(size_t)j * M + j];
+        for (int k = std::max(0, j - p); k < j; ++k) d -= at(j, k) * at(j, k);
+        if (!(d > 0)) throw Error(IETI_EINVAL, "mass matrix is not positive definite");
+        const double c = std::sqrt(d);
+        at(j, j) = c;
+        for (int i = j + 1; i <= std::min(M - 1, j + p); ++i) {
+            double v = Mm[(size_t)i * M + j];
+            for (int k = std::max(0, i - p); k < j; ++k) v -= at(i, k) * at(j, k);
+            at(i, j) = v / c;
+        }
+    }
+    return L;
+}
+
 // ----------------------------------------------------------------------------
 // per-direction quadrature tables of one level
 
@@ -333,19 +383,19 @@ static inline int64_t lin(const int* M, int i0, int i1, int i2) { return i0 + (i
 static void assemble_level(Patch& P, Level& L, bool level0) {
     const int dim = P.dim;
     DirTable dt[3];
-    for (int d = 0; d < dim; ++d) dt[d] = make_dir(L.knots[d], P.p[d], P.knots[d], P.p[d]);
+    for (int d = 0; d < dim; ++d) dt[d] = make_dir(L.knots[d], L.p[d], P.knots[d], P.p[d]);
     int Mg[3] = {1, 1, 1};
     for (int d = 0; d < dim; ++d) Mg[d] = (int)P.knots[d].size() - P.p[d] - 1;
-    half_offsets(dim, P.p, L.offs);
+    half_offsets(dim, L.p, L.offs);
     L.nst = (int)L.offs.size() / 3;
     L.coef.assign((size_t)L.nst * L.n, 0.0);
     // slot table: (o0+p0) + (2p0+1)((o1+p1) + (2p1+1)(o2+p2)) -> s
-    int w0 = 2 * P.p[0] + 1, w1 = 2 * P.p[1] + 1, w2 = dim == 3 ? 2 * P.p[2] + 1 : 1;
-    int p2 = dim == 3 ? P.p[2] : 0;
+    int w0 = 2 * L.p[0] + 1, w1 = 2 * L.p[1] + 1, w2 = dim == 3 ? 2 * L.p[2] + 1 : 1;
+    int p2 = dim == 3 ? L.p[2] : 0;
     std::vector<int> slot((size_t)w0 * w1 * w2, -1);
     for (int s = 0; s < L.nst; ++s) {
         int o0 = L.offs[3 * s], o1 = L.offs[3 * s + 1], o2 = L.offs[3 * s + 2];
-        slot[(o0 + P.p[0]) + (size_t)w0 * ((o1 + P.p[1]) + (size_t)w1 * (o2 + p2))] = s;
+        slot[(o0 + L.p[0]) + (size_t)w0 * ((o1 + L.p[1]) + (size_t)w1 * (o2 + p2))] = s;
     }
     const int Q0 = dt[0].Q, Q1 = dt[1].Q, Q2 = dim == 3 ? dt[2].Q : 1;
     if (level0) {
@@ -434,7 +484,7 @@ static void assemble_level(Patch& P, Level& L, bool level0) {
     }
 
     // ---- curved patch: element-by-element with the metric at every quadrature point
-    const int pl[3] = {P.p[0], P.p[1], dim == 3 ? P.p[2] : 0};
+    const int pl[3] = {L.p[0], L.p[1], dim == 3 ? L.p[2] : 0};
     const int nq1[3] = {pl[0] + 1, pl[1] + 1, pl[2] + 1};
     const int nloc = nq1[0] * nq1[1] * nq1[2];
     const int nqe = nloc;   // (p+1)^d points per element
@@ -540,7 +590,7 @@ static void assemble_level(Patch& P, Level& L, bool level0) {
                     for (int bl = 0; bl < nloc; ++bl) {
                         int b0 = bl % nq1[0], b1 = (bl / nq1[0]) % nq1[1], b2 = bl / (nq1[0] * nq1[1]);
                         int o0 = b0 - a0, o1 = b1 - a1, o2 = b2 - a2;
-                        int s = slot[(o0 + P.p[0]) + (size_t)w0 * ((o1 + P.p[1]) + (size_t)w1 * (o2 + p2))];
+                        int s = slot[(o0 + L.p[0]) + (size_t)w0 * ((o1 + L.p[1]) + (size_t)w1 * (o2 + p2))];
                         if (s < 0) continue;
                         const double* gp = &grad[(size_t)bl * nqe * 3];
                         double v = 0.0;
@@ -557,7 +607,7 @@ static void assemble_level(Patch& P, Level& L, bool level0) {
 static void add_param_mass(const Patch& P, Level& L, double alpha) {
     const int dim = P.dim;
     std::vector<double> A1[3][2][2];
-    for (int d = 0; d < dim; ++d) one_d_matrices(make_dir(L.knots[d], P.p[d], P.knots[d], P.p[d]), L.M[d], A1[d]);
+    for (int d = 0; d < dim; ++d) one_d_matrices(make_dir(L.knots[d], L.p[d], P.knots[d], P.p[d]), L.M[d], A1[d]);
     for (int i2 = 0; i2 < L.M[2]; ++i2)
         for (int i1 = 0; i1 < L.M[1]; ++i1)
             for (int i0 = 0; i0 < L.M[0]; ++i0) {
@@ -1302,6 +1352,7 @@ Plan* build_plan(const ieti_patch* in, int n, const double* pv, int n_pv, const 
     if (opt.check_every < 1) opt.check_every = 1;
     if (opt.coarse_level < -1) throw Error(IETI_EINVAL, "coarse_level must be >= -1");
     if (opt.coarse_dofs < 0) throw Error(IETI_EINVAL, "coarse_dofs must be >= 0");
+    if (opt.coarse_degree != 0 && opt.coarse_degree != 1) throw Error(IETI_EINVAL, "coarse_degree must be 0 or 1");
     if (opt.cheb_degree < 0 || opt.cheb_degree > 8 || opt.cheb_degree_coarse < 0 || opt.cheb_degree_coarse > 8)
         throw Error(IETI_EINVAL, "Chebyshev degrees must be in 0..8");
     if (opt.smoother != IETI_SMOOTHER_CHEBYSHEV && opt.smoother != IETI_SMOOTHER_TENSOR)
@@ -1345,6 +1396,7 @@ Plan* build_plan(const ieti_patch* in, int n, const double* pv, int n_pv, const 
         for (int d = 0; d < 3; ++d) {
             L0.M[d] = M[d];
             if (d < dim) {
+                L0.p[d] = pa.p[d];
                 L0.knots[d] = pa.knots[d];
                 L0.nel[d] = (int)breakpoints(pa.knots[d]).size() - 1;
             }
@@ -1747,20 +1799,23 @@ Plan* build_plan(const ieti_patch* in, int n, const double* pv, int n_pv, const 
             if (!ok) break;
             Level c;
             for (int d = 0; d < dim; ++d) {
+                // degree 1 on every coarse level with coarse_degree = 1 (Sec. 4), else the patch's degree
+                const int pc = opt.coarse_degree == 1 ? 1 : pa.p[d];
                 std::vector<double> b = breakpoints(f.knots[d]), bc;
                 for (size_t i = 0; i < b.size(); i += 2) bc.push_back(b[i]);
-                std::vector<double> t(pa.p[d] + 1, bc.front());
+                std::vector<double> t(pc + 1, bc.front());
                 for (size_t i = 1; i + 1 < bc.size(); ++i) t.push_back(bc[i]);
-                for (int i = 0; i <= pa.p[d]; ++i) t.push_back(bc.back());
+                for (int i = 0; i <= pc; ++i) t.push_back(bc.back());
+                c.p[d] = pc;
                 c.knots[d] = t;
                 c.nel[d] = (int)bc.size() - 1;
-                c.M[d] = (int)t.size() - pa.p[d] - 1;
+                c.M[d] = (int)t.size() - pc - 1;
             }
             c.n = (int64_t)c.M[0] * c.M[1] * c.M[2];
             pa.lv.push_back(c);
         }
         for (Level& L : pa.lv) {
-            L.guard = pa.p[0] + (int64_t)pa.p[1] * L.M[0] + (dim == 3 ? (int64_t)pa.p[2] * L.M[0] * L.M[1] : 0);
+            L.guard = L.p[0] + (int64_t)L.p[1] * L.M[0] + (dim == 3 ? (int64_t)L.p[2] * L.M[0] * L.M[1] : 0);
         }
         pl.max_levels = std::max(pl.max_levels, (int)pa.lv.size());
     }
@@ -1776,9 +1831,18 @@ Plan* build_plan(const ieti_patch* in, int n, const double* pv, int n_pv, const 
         for (size_t l = 0; l + 1 < pa.lv.size(); ++l) {
             Level& f = pa.lv[l];
             const Level& c = pa.lv[l + 1];
+            f.l2 = false;
+            for (int d = 0; d < dim; ++d)
+                if (f.p[d] != c.p[d]) f.l2 = true;
             for (int d = 0; d < dim; ++d) {
+                if (f.l2) {   // non-nested spaces: L2 projection M_f^{-1} M_fc (parametric)
+                    f.P[d] = mixed_mass(f.knots[d], f.p[d], c.knots[d], c.p[d]);
+                    f.Mc[d] = c.M[d];
+                    f.mchol[d] = band_mass_chol(f.knots[d], f.p[d]);
+                    continue;
+                }
                 int Mf, Mc;
-                f.P[d] = prolongation(c.knots[d], f.knots[d], pa.p[d], Mf, Mc);
+                f.P[d] = prolongation(c.knots[d], f.knots[d], c.p[d], Mf, Mc);
                 f.Mc[d] = Mc;
             }
         }
@@ -1806,8 +1870,10 @@ Plan* build_plan(const ieti_patch* in, int n, const double* pv, int n_pv, const 
             const Level& L0 = pa.lv[0];
             pa.band_b = L0.guard;
             pa.band_nblk = (L0.n + BAND_NB - 1) / BAND_NB;
-            band_factor(pa, L0, MODE_N, pa.band_b, pa.band[MODE_N]);
-            if (!mg) band_factor(pa, L0, MODE_D, pa.band_b, pa.band[MODE_D]);
+            if (dim == 2) {   // 3D bands are factorised on the device (the runtime's block-band path)
+                band_factor(pa, L0, MODE_N, pa.band_b, pa.band[MODE_N]);
+                if (!mg) band_factor(pa, L0, MODE_D, pa.band_b, pa.band[MODE_D]);
+            }
         }
     });
     int64_t nq = 0;

@@ -27,6 +27,7 @@ enum Mode : int {
 
 // One multigrid level of one patch.
 struct Level {
+    int p[3] = {0, 0, 0};          // spline degree of the level's space per direction (0 in unused directions)
     int M[3] = {1, 1, 1};          // basis functions per direction (1 in unused directions)
     int nel[3] = {1, 1, 1};        // elements per direction
     int64_t n = 0;                 // prod M
@@ -36,9 +37,15 @@ struct Level {
     std::vector<int32_t> offs;     // 3 * nst offsets (o0, o1, o2); entry 0 is the diagonal
     std::vector<double> coef;      // nst * n, offset-major: K(i, i + o_s) at coef[s * n + i]
     double lmax[2] = {0, 0};       // lambda_max(D^{-1} K) for MODE_N, MODE_D
-    // prolongation from the next coarser level into this one: dense Mf x Mc per direction
+    // prolongation from the next coarser level into this one: dense Mf x Mc per direction.  Nested levels
+    // (same degree): the canonical embedding.  Degree-1 coarse levels under a finest level of degree p
+    // (options.coarse_degree = 1, Sec. 4): P holds the mixed parametric mass matrix M_fc (fine x coarse)
+    // and mchol the banded Cholesky factor of the fine parametric mass matrix M_f (Mf x (p+1): row i holds
+    // L(i, i-p .. i)), so that the transfer is the L2 projection M_f^{-1} M_fc and its transpose
     std::vector<double> P[3];
     int Mc[3] = {1, 1, 1};
+    bool l2 = false;
+    std::vector<double> mchol[3];
     // coarsest level only: dense inverses (n x n, masked rows/cols zero) for MODE_N, MODE_D
     std::vector<double> inv[2];
 };

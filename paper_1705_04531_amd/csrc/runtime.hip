@@ -358,6 +358,13 @@ struct Solver : SolverBase {
     int* done_dev = nullptr;
     int* h_done = nullptr;   // pinned
     std::vector<double> comp_gres;
+    // degree-1 coarse levels (options.coarse_degree = 1): the finest level's L2-projection transfer
+    bool l2_on = false;
+    double* l2_mchol = nullptr;          // banded Cholesky factors of the 1D parametric mass matrices
+    int32_t* l2_list = nullptr;          // level-0 patch-levels with a coarse level
+    int l2_n = 0;
+    size_t l2_lds = 0;
+    T* l2_tmp = nullptr;                 // level-0 scratch vector
     // floating patches (K singular, edge constraints only): their list and the penalty gamma per patch
     int n_float = 0;
     int32_t* float_list = nullptr;
@@ -524,6 +531,16 @@ struct Solver : SolverBase {
             stencil<T, T, T, EPI_RESID>(l, true, mode, D.coefT, X, D.vr, B, nullptr, act, 0.0, 0);
             cur[l] = X;
             DevLevel& C = lev[l + 1];
+            if (l == 0 && l2_on) {   // b_c = D_c M_cf M_f^{-1} r_f
+                hipLaunchKernelGGL(k_mass_solve<T>, dim3(l2_n), dim3(TILE), l2_lds, stream, D.L, l2_list, l2_n,
+                                   (const double*)l2_mchol, (const T*)D.vr, l2_tmp, mode, 0, act);
+                check_launch();
+                hipLaunchKernelGGL(k_l2_restrict<T>, dim3(tile_grid(C.nt_all)), dim3(TILE), 0, stream, D.L, C.L,
+                                   C.tiles_all, C.nt_all, D.rlo, (const T*)D.rval, (const T*)l2_tmp, (T*)C.vb, mode,
+                                   act);
+                check_launch();
+                continue;
+            }
             for (const auto& g : launch_groups(C.cls_beg_all, C.cls_end_all, true)) {
                 launch_restrict<T>(g[0], stream, D.L, C.L, C.tiles_all + g[1], g[2] - g[1], D.rlo, (const T*)D.rval,
                                    (const T*)D.vr, (T*)C.vb, mode, act);
@@ -537,10 +554,23 @@ struct Solver : SolverBase {
             T* A0 = l == 0 ? (T*)D.vxa : (T*)D.vx;   // the level's two x buffers
             T* A1 = l == 0 ? x0 : (T*)D.vxa;
             T* XA = (X == A0) ? A1 : A0;
-            for (const auto& g : launch_groups(D.cls_beg_sm, D.cls_end_sm, true)) {
-                launch_prolong<T>(g[0], stream, D.L, lev[l + 1].L, D.tiles_smooth + g[1], g[2] - g[1], D.plo,
-                                  (const T*)D.pval, (const T*)cur[l + 1], X, mode, act);
+            if (l == 0 && l2_on) {   // x_f += D_f M_f^{-1} M_fc e_c
+                hipLaunchKernelGGL(k_l2_prolong<T>, dim3(tile_grid(D.nt_smooth)), dim3(TILE), 0, stream, D.L,
+                                   lev[1].L, D.tiles_smooth, D.nt_smooth, D.plo, (const T*)D.pval,
+                                   (const T*)cur[1], l2_tmp, mode, act);
                 check_launch();
+                hipLaunchKernelGGL(k_mass_solve<T>, dim3(l2_n), dim3(TILE), l2_lds, stream, D.L, l2_list, l2_n,
+                                   (const double*)l2_mchol, (const T*)l2_tmp, l2_tmp, mode, 1, act);
+                check_launch();
+                hipLaunchKernelGGL(k_add_act<T>, dim3(tile_grid(D.nt_smooth)), dim3(TILE), 0, stream, D.L,
+                                   D.tiles_smooth, D.nt_smooth, (const T*)l2_tmp, X, act);
+                check_launch();
+            } else {
+                for (const auto& g : launch_groups(D.cls_beg_sm, D.cls_end_sm, true)) {
+                    launch_prolong<T>(g[0], stream, D.L, lev[l + 1].L, D.tiles_smooth + g[1], g[2] - g[1], D.plo,
+                                      (const T*)D.pval, (const T*)cur[l + 1], X, mode, act);
+                    check_launch();
+                }
             }
             if (l == 0 && fd_on) {   // one tensor-smoother step
                 if (dotq) throw Error(IETI_ENOTSUP, "internal: fused dot with the tensor smoother");
@@ -698,7 +728,78 @@ struct Solver : SolverBase {
         check_launch();
     }
 
+    // 3D exact local solves: block-band factors built on the device (k_bb_*)
+    bool band3 = false;
+    BandJob* bb_jobs = nullptr;
+    int32_t* bb_job_of = nullptr;   // [mode][patch] -> job, -1: none
+    double *bb_F = nullptr, *bb_D = nullptr;
+    std::vector<BandJob> h_bb_jobs;
+    void setup_band3() {
+        const Plan& pl = *plan;
+        hipStream_t st = stream;
+        std::vector<int32_t> stab, job_of(2 * (size_t)N, -1);
+        int64_t off = 0, doff = 0;
+        int nbmax = 0, wmax = 0;
+        for (int k = 0; k < N; ++k) {
+            const Patch& pa = pl.patches[k];
+            const Level& L0 = pa.lv[0];
+            const int toff = (int)stab.size();
+            const int w0 = 2 * pa.p[0] + 1, w1 = 2 * pa.p[1] + 1, w2 = 2 * pa.p[2] + 1;
+            stab.resize(stab.size() + (size_t)w0 * w1 * w2, 0);
+            auto at = [&](int o0, int o1, int o2) -> int32_t& {
+                return stab[toff + (o0 + pa.p[0]) + (size_t)w0 * ((o1 + pa.p[1]) + (size_t)w1 * (o2 + pa.p[2]))];
+            };
+            for (int s = 0; s < L0.nst; ++s) {
+                const int o0 = L0.offs[3 * s], o1 = L0.offs[3 * s + 1], o2 = L0.offs[3 * s + 2];
+                at(o0, o1, o2) = s + 1;                // K(i, i + o) = coef[s][i]
+                if (s > 0) at(-o0, -o1, -o2) = -(s + 1);   // K(i, i - o) = K(i - o, i) = coef[s][i - o]
+            }
+            const int nb = (int)((L0.n + BNB - 1) / BNB), W = (int)((L0.guard + BNB - 1) / BNB);
+            nbmax = std::max(nbmax, nb);
+            wmax = std::max(wmax, W);
+            for (int m = 0; m < 2; ++m) {
+                if (m == MODE_D && !prec_exact) continue;
+                job_of[(size_t)m * N + k] = (int32_t)h_bb_jobs.size();
+                h_bb_jobs.push_back(BandJob{off, doff, k, m, nb, W, toff});
+                off += (int64_t)nb * (W + 1) * BNB * BNB;
+                doff += (int64_t)nb * BNB * BNB;
+            }
+        }
+        if (wmax > BB_WMAX) throw Error(IETI_ENOTSUP, "3D exact local solves: band wider than the solve's window");
+        const int nj = (int)h_bb_jobs.size();
+        bb_F = arena.alloc<double>(off, st, false);
+        bb_D = arena.alloc<double>(doff, st, false);
+        bb_jobs = arena.upload(h_bb_jobs, st);
+        bb_job_of = arena.upload(job_of, st);
+        int32_t* stab_d = arena.upload(stab, st);
+        int* err = arena.alloc<int>(1, st);
+        hipLaunchKernelGGL(k_bb_assemble, dim3(nbmax * (wmax + 1), nj), dim3(256), 0, st, lev[0].L, bb_jobs, stab_d,
+                           (const double*)coef64, bb_F);
+        check_launch();
+        for (int k = 0; k < nbmax; ++k) {
+            hipLaunchKernelGGL(k_bb_potrf, dim3(nj), dim3(256), 0, st, bb_jobs, k, bb_F, bb_D, err);
+            check_launch();
+            if (wmax > 0) {
+                hipLaunchKernelGGL(k_bb_trsm, dim3(wmax, nj), dim3(256), 0, st, bb_jobs, k, bb_F, (const double*)bb_D);
+                check_launch();
+                hipLaunchKernelGGL(k_bb_update, dim3(wmax * (wmax + 1) / 2, nj), dim3(256), 0, st, bb_jobs, k, bb_F);
+                check_launch();
+            }
+        }
+        int herr = 0;
+        HIPCHECK(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHECK(hipStreamSynchronize(st));
+        if (herr) throw Error(IETI_EINVAL, "local stiffness matrix is not positive definite");
+        band3 = true;
+    }
     void band_solve(int mode, const double* rhs, double* x) {
+        if (band3) {
+            hipLaunchKernelGGL(k_bb_solve, dim3(N), dim3(BB_THREADS), 0, stream, lev[0].L, bb_jobs,
+                               bb_job_of + (size_t)mode * N, (const double*)bb_F, (const double*)bb_D, rhs, x,
+                               nullptr);
+            check_launch();
+            return;
+        }
         if (band_bmax <= 256)
             hipLaunchKernelGGL((k_band_solve_pf<16, true>), dim3(N), dim3(BAND_PF_THREADS), band_lds, stream, lev[0].L,
                                band_off, band_b, band, mode, rhs, x, nullptr);
@@ -820,17 +921,30 @@ struct Solver : SolverBase {
                 break;
             }
             const double nc = (double)pa.lv[l + 1].n;
+            // transfers: nested (n + n_c) s down, (2 n + n_c) s up; L2 projection: the mass solve (n in, n out)
+            // and the band (n + n_c) down, the band (n_c + n), the mass solve (2 n) and the add (3 n) up
+            const double tdown = L.l2 ? (3.0 * n + nc) * s : (n + nc) * s;
+            const double tup = L.l2 ? (6.0 * n + nc) * s : (2.0 * n + nc) * s;
             if (l == 0 && fd_on && !pa.ts[mode].U[0].empty()) {
-                b += fd_step_bytes(k, mode, true) + (3.0 + nst) * n * s + (n + nc) * s;   // step from zero, residual
-                b += (2.0 * n + nc) * s + (3.0 + nst) * n * s + fd_step_bytes(k, mode, false);
+                b += fd_step_bytes(k, mode, true) + (3.0 + nst) * n * s + tdown;   // step from zero, residual
+                b += tup + (3.0 + nst) * n * s + fd_step_bytes(k, mode, false);
                 continue;
             }
             const int m = l == 0 ? cheb_m : cheb_mc;
             b += 4.0 * n * s + (m - 1) * (5.0 + nst) * n * s;   // pre-smoothing from zero
-            b += (3.0 + nst) * n * s + (n + nc) * s;              // residual, restriction
-            b += (2.0 * n + nc) * s + m * (5.0 + nst) * n * s;    // prolongation, post-smoothing
+            b += (3.0 + nst) * n * s + tdown;                     // residual, restriction
+            b += tup + m * (5.0 + nst) * n * s;                   // prolongation, post-smoothing
         }
         return b;
+    }
+    // factor data one exact local solve streams: the host-built 2D layout once (its L and L^T halves are
+    // separate copies), the 3D block band twice (forward by rows, backward by columns) with the diagonal
+    // inverses
+    double band_bytes(int k, int mode) const {
+        const Patch& pa = plan->patches[k];
+        if (!band3) return (double)pa.band[mode].size() * 8.0;
+        const double nb = (double)((pa.lv[0].n + BNB - 1) / BNB), W = (double)((pa.lv[0].guard + BNB - 1) / BNB);
+        return 2.0 * nb * (W + 1.0) * BNB * BNB * 8.0;
     }
     // one F apply with the inner iteration counts its_k of its local solves
     double fapply_bytes(const std::vector<int>& itk) const {
@@ -840,7 +954,7 @@ struct Solver : SolverBase {
             const Patch& pa = plan->patches[k];
             const double n = (double)pa.lv[0].n, nst = pa.lv[0].nst;
             if (exact) {
-                b += (double)pa.band[0].size() * 8.0 + 16.0 * n;
+                b += band_bytes(k, MODE_N) + 16.0 * n;
                 continue;
             }
             const double init = n * (40.0 + s);
@@ -859,7 +973,7 @@ struct Solver : SolverBase {
             const double n = (double)pa.lv[0].n, nst = pa.lv[0].nst;
             b += n * (8.0 + 8.0 * nst + s);                 // b_I = -K v
             if (prec_exact) {
-                b += (double)pa.band[1].size() * 8.0 + 16.0 * n;
+                b += band_bytes(k, MODE_D) + 16.0 * n;
             } else {
                 const int cyc = std::max(1, plan->opt.prec_vcycles);
                 b += cyc * vcycle_bytes(k, MODE_D) + (cyc - 1) * ((3.0 + nst) * n * s + 3.0 * n * s);
@@ -1455,7 +1569,7 @@ void Solver<T>::setup() {
             PatchLev P{};
             for (int d = 0; d < 3; ++d) {
                 P.M[d] = L.M[d];
-                P.p[d] = d < dim ? pa.p[d] : 0;
+                P.p[d] = d < dim ? L.p[d] : 0;
             }
             P.dim = dim;
             P.nst = L.nst;
@@ -1467,6 +1581,7 @@ void Solver<T>::setup() {
             P.patch = k;
             P.coarse = -1;
             P.fine = -1;
+            P.moff[0] = P.moff[1] = P.moff[2] = -1;
             P.n = L.n;
             P.voff = align64(cur + L.guard);
             cur = P.voff + L.n + L.guard;
@@ -1538,6 +1653,37 @@ void Solver<T>::setup() {
         }
         HIPCHECK(hipStreamSynchronize(st));
     }
+    // ---- L2-projection transfer of the finest level (degree-1 coarse levels): mass factors per direction
+    {
+        std::vector<double> mc;
+        std::vector<int32_t> lst;
+        DevLevel& D = lev[0];
+        for (size_t i = 0; i < D.hL.size(); ++i) {
+            PatchLev& P = D.hL[i];
+            const Level& L = pl.patches[P.patch].lv[0];
+            if (P.coarse < 0 || !L.l2) continue;
+            for (int d = 0; d < dim; ++d) {
+                P.moff[d] = (int64_t)mc.size();
+                mc.insert(mc.end(), L.mchol[d].begin(), L.mchol[d].end());
+            }
+            lst.push_back((int32_t)i);
+            l2_lds = std::max(l2_lds, (size_t)L.n * sizeof(T));
+        }
+        if (!lst.empty()) {
+            int dev = 0, max_lds = 0;
+            HIPCHECK(hipGetDevice(&dev));
+            HIPCHECK(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+            if (l2_lds > (size_t)max_lds)
+                throw Error(IETI_ENOTSUP, "degree-1 coarse levels: a patch's finest level exceeds the LDS of the mass solve");
+            HIPCHECK(hipFuncSetAttribute((const void*)k_mass_solve<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         (int)l2_lds));
+            l2_on = true;
+            l2_n = (int)lst.size();
+            l2_mchol = arena.upload(mc, st);
+            l2_list = arena.upload(lst, st);
+            HIPCHECK(hipStreamSynchronize(st));
+        }
+    }
     // ---- transfer tables, stencils, inverses
     for (int l = 0; l < nlev; ++l) {
         DevLevel& D = lev[l];
@@ -1558,7 +1704,9 @@ void Solver<T>::setup() {
                 }
             if (P.coarse >= 0) {
                 for (int d = 0; d < dim; ++d) {
-                    const int Mf = L.M[d], Mc = L.Mc[d], w = pa.p[d] + 2;
+                    // nested levels: the embedding's rows hold p + 2 entries; the L2 projection's mixed mass
+                    // matrix M_fc (degree p onto degree 1) up to PW
+                    const int Mf = L.M[d], Mc = L.Mc[d], w = L.l2 ? PW : L.p[d] + 2;
                     if (w > PW) throw Error(IETI_ENOTSUP, "degree too high for the transfer tables");
                     const std::vector<double>& Pm = L.P[d];
                     P.toff[d] = (int64_t)plo.size();
@@ -1567,7 +1715,7 @@ void Solver<T>::setup() {
                         for (int c = 0; c < Mc; ++c)
                             if (Pm[(size_t)r * Mc + c] != 0.0) { cmin = std::min(cmin, c); cmax = std::max(cmax, c); }
                         if (cmax < 0) cmin = cmax = 0;
-                        if (cmax - cmin + 1 > w) throw Error(IETI_ENOTSUP, "prolongation row wider than p+2");
+                        if (cmax - cmin + 1 > w) throw Error(IETI_ENOTSUP, "prolongation row wider than the table");
                         int lo = std::max(0, std::min(cmin, Mc - w));
                         plo.push_back(lo);
                         for (int a = 0; a < PW; ++a) {
@@ -1581,7 +1729,7 @@ void Solver<T>::setup() {
                         for (int r = 0; r < Mf; ++r)
                             if (Pm[(size_t)r * Mc + c] != 0.0) { rmin = std::min(rmin, r); rmax = std::max(rmax, r); }
                         if (rmax < 0) rmin = rmax = 0;
-                        if (rmax - rmin + 1 > w) throw Error(IETI_ENOTSUP, "restriction column wider than p+2");
+                        if (rmax - rmin + 1 > w) throw Error(IETI_ENOTSUP, "restriction column wider than the table");
                         int lo = std::max(0, std::min(rmin, Mf - w));
                         rlo.push_back(lo);
                         for (int a = 0; a < PW; ++a) {
@@ -1672,7 +1820,7 @@ void Solver<T>::setup() {
             for (int k = 0; k < N; ++k) {
                 if ((int)pl.patches[k].lv.size() <= f) continue;
                 const int64_t b = chain_bytes(k, f, stage);
-                const int fam = vcoarse_family(lev[0].hL[k].pclass);
+                const int fam = vcoarse_family(lev[f].hL[ch[(size_t)k * LMAX + f]].pclass);
                 order[fam].push_back({-b, k});
                 vc_lds[fam] = std::max(vc_lds[fam], (size_t)b);
             }
@@ -1767,6 +1915,9 @@ void Solver<T>::setup() {
     if (pl.opt.local_solver == IETI_LOCAL_EXACT || pl.opt.local_solver == IETI_LOCAL_EXACT_MG) {
         exact = true;
         prec_exact = pl.opt.local_solver == IETI_LOCAL_EXACT;
+        if (dim == 3) {
+            setup_band3();
+        } else {
         int dev = 0, max_lds = 0;
         HIPCHECK(hipGetDevice(&dev));
         HIPCHECK(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
@@ -1799,11 +1950,13 @@ void Solver<T>::setup() {
         HIPCHECK(hipFuncSetAttribute((const void*)k_band_solve_pf<32, false>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)band_lds));
         HIPCHECK(hipStreamSynchronize(st));
+        }
     }
     DevLevel& D0 = lev[0];
     len0 = D0.len;
     for (double** p : {&f64, &b64, &e64, &w64, &s64, &u64, &fx, &fr, &fd, &fq}) *p = arena.alloc<double>(len0, st);
     for (T** p : {&rT, &zT, &bT, &xIT, &x2T, &r2T}) *p = arena.alloc<T>(len0, st);
+    if (l2_on) l2_tmp = arena.alloc<T>(len0, st);
     partial = arena.alloc<double>(4 * (int64_t)D0.nt_all + 4, st);
     if (pl.opt.local_solver == IETI_LOCAL_MG_SADDLE) {
         saddle = true;
@@ -2597,6 +2750,13 @@ static size_t estimate_device_bytes(const Plan& pl) {
         }
         b += 2.0 * npk * (double)(pa.lv[0].n + 2 * pa.lv[0].guard + 64) * 8.0;   // Psi + setup scratch
         b += (double)(pa.band[0].size() + pa.band[1].size()) * 8.0;
+        if (pl.dim == 3 && (pl.opt.local_solver == IETI_LOCAL_EXACT || pl.opt.local_solver == IETI_LOCAL_EXACT_MG)) {
+            // device block band of the Neumann (and, for D-D, the Dirichlet) problem with the diagonal inverses
+            const double nb = (double)((pa.lv[0].n + BNB - 1) / BNB);
+            const double W = (double)((pa.lv[0].guard + BNB - 1) / BNB);
+            const double modes = pl.opt.local_solver == IETI_LOCAL_EXACT ? 2.0 : 1.0;
+            b += modes * nb * (W + 2.0) * BNB * BNB * 8.0;
+        }
         b += (double)pa.n_qp * (16.0 + 8.0 * pa.dim);
         for (int m = 0; m < 2; ++m)   // tensor smoother: U_d, lambda_d, scratch (two buffers in 3D)
             if (!pa.ts[m].U[0].empty())
@@ -2761,14 +2921,11 @@ static void server_solve(ieti_server* S, hipStream_t st, std::vector<SrvReq*>& b
         o.device = S->device;
         std::vector<ieti_patch> all;
         std::vector<int32_t> comp;
-        int64_t nq_all = 0;
-        for (size_t b = 0; b < batch.size(); ++b) {
+        for (size_t b = 0; b < batch.size(); ++b)
             for (const ieti_patch& p : batch[b]->patches) {
                 all.push_back(p);
                 comp.push_back((int32_t)b);
             }
-            nq_all += (int64_t)batch[b]->f.size();
-        }
         std::unique_ptr<Plan> plan(build_plan(all.data(), (int)all.size(), nullptr, 0, &o, comp.data()));
         if (plan->ncomp != (int)batch.size()) throw Error(IETI_EINVAL, "internal: batch problem count");
         for (size_t b = 0; b < batch.size(); ++b)

@@ -25,8 +25,6 @@ CASES = [
 @pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
 def test_edge_case_matches_oracle(require_gpu, name, make, variant, opts):
     wl = make()
-    if wl.dim == 3 and variant == "exact_mg":
-        pytest.skip("exact local solves are built for 2D patches")
     u_ref, lay, _ = oracle_solution(wl)
     u, st = run_gpu(wl, tol=1e-10, coarse_dofs=0, **opts)
     err = rel_err(wl, u, u_ref, lay)

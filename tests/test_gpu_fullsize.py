@@ -62,11 +62,30 @@ def test_full_config_tensor_smoother(require_gpu, name):
     path = os.path.join(HERE, "golden", f"full_{name}.json")
     g = json.load(open(path))
     wl = W.CONFIGS[name]()
-    u, st = run_gpu(wl, smoother=_abi.IETI_SMOOTHER_TENSOR)
+    # at the configurations' tolerance 1e-8 the worst sampled coefficient of the cube reaches 1.0e-8 with this
+    # smoother (the dual residual bounds the error only up to a factor, reading R1); run at 1e-9
+    u, st = run_gpu(wl, smoother=_abi.IETI_SMOOTHER_TENSOR, tol=1e-9)
     lay = conforming.layout(wl)
     ug = conforming.global_from_torn(lay, split_torn(wl, u))
     err, linf = golden_errors(g, u)
     nrm = abs(np.linalg.norm(ug) - g["norm2"]) / g["norm2"]
     print(f"{name} tensor smoother: sampled rel err {err:.3e}, max {linf:.3e}, norm rel diff {nrm:.3e}, "
           f"outer {st['outer_iterations']}, inner {st['inner_iterations_mean']:.2f}", flush=True)
+    assert err <= 1e-8 and linf <= 1e-8 and nrm <= 1e-8
+
+
+@pytest.mark.parametrize("name", ["deformed8x8_p3_n64", "cube4x4x4_p2_n24"])
+def test_full_config_plain_form(require_gpu, name):
+    """The plain FP64 exact-local form (D-D) at full size against the same oracle samples: 2D with the host's
+    banded factors, 3D with block-band factors built on the device."""
+    from paper_1705_04531_amd import _abi
+    g = json.load(open(os.path.join(HERE, "golden", f"full_{name}.json")))
+    wl = W.CONFIGS[name]()
+    u, st = run_gpu(wl, local_solver=_abi.IETI_LOCAL_EXACT, mg_precision=64)
+    lay = conforming.layout(wl)
+    ug = conforming.global_from_torn(lay, split_torn(wl, u))
+    err, linf = golden_errors(g, u)
+    nrm = abs(np.linalg.norm(ug) - g["norm2"]) / g["norm2"]
+    print(f"{name} plain form: sampled rel err {err:.3e}, max {linf:.3e}, norm rel diff {nrm:.3e}, "
+          f"outer {st['outer_iterations']}", flush=True)
     assert err <= 1e-8 and linf <= 1e-8 and nrm <= 1e-8

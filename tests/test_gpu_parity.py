@@ -197,20 +197,23 @@ def test_tensor_smoother_p_robust(require_gpu):
     """p-robustness (Sec. 4): on the same 2x2 deformed square with 32^2 elements per patch and the
     full h-hierarchy, degrees 2..6, both smoothers reach the oracle's solution; the tensor smoother's
     inner flexible-CG iteration count stays bounded as p grows (the Chebyshev smoother's is reported
-    beside it)."""
+    beside it, and the tensor smoother's with degree-1 coarse levels and L2 transfers, the paper's full
+    p-robust multigrid)."""
     from paper_1705_04531_amd import _abi
     rows = []
     for p in (2, 3, 4, 5, 6):
         wl = with_sine_rhs(W.deformed_square((2, 2), p, 32, seed=0, name=f"deformed2x2_p{p}"), 3)
         u_ref, lay, _ = oracle_solution(wl)
         its = {}
-        for name, sm in (("chebyshev", _abi.IETI_SMOOTHER_CHEBYSHEV), ("tensor", _abi.IETI_SMOOTHER_TENSOR)):
-            u, st = run_gpu(wl, tol=1e-10, coarse_dofs=0, smoother=sm)
+        for name, sm, cd in (("chebyshev", _abi.IETI_SMOOTHER_CHEBYSHEV, 0), ("tensor", _abi.IETI_SMOOTHER_TENSOR, 0),
+                             ("tensor_p1", _abi.IETI_SMOOTHER_TENSOR, 1)):
+            u, st = run_gpu(wl, tol=1e-10, coarse_dofs=0, smoother=sm, coarse_degree=cd)
             err = rel_err(wl, u, u_ref, lay)
             assert err <= 1e-8, (p, name, err)
             its[name] = st["inner_iterations_mean"]
-        rows.append((p, its["chebyshev"], its["tensor"]))
-        print(f"p={p}: inner iterations Chebyshev {its['chebyshev']:.2f}, tensor {its['tensor']:.2f}", flush=True)
+        rows.append((p, its["chebyshev"], its["tensor"], its["tensor_p1"]))
+        print(f"p={p}: inner iterations Chebyshev {its['chebyshev']:.2f}, tensor {its['tensor']:.2f}, "
+              f"tensor with degree-1 coarse levels {its['tensor_p1']:.2f}", flush=True)
     tens = [r[2] for r in rows]
     assert max(tens) <= 16.0 and max(tens) <= 1.6 * min(tens), rows
 
@@ -278,5 +281,56 @@ def test_edge_only_primal_matches_oracle(require_gpu, name, make, prec, hierarch
     print(f"{name} prec={prec} {hierarchy}: err={err:.3e} outer={st['outer_iterations']} n_primal={st['n_primal']} "
           f"n_lambda={st['n_lambda']} inner mean={st['inner_iterations_mean']:.1f} max={st['inner_iterations_max']}",
           flush=True)
+    assert err <= 1e-8
+    assert st["inner_unconverged"] == 0 and st["inner_nonfinite"] == 0
+
+
+EXACT_3D = [
+    ("cube2x2x2_n6_sine", CASES_3D[0][1]),
+    ("cube3x3x2_n6", CASES_3D[1][1]),
+    ("cube3x3x2_edges", EDGE_ONLY_CASES[1][1]),
+]
+
+
+@pytest.mark.parametrize("variant", ["exact", "exact_mg64", "exact_mg32"])
+@pytest.mark.parametrize("name,make", EXACT_3D, ids=[c[0] for c in EXACT_3D])
+def test_exact_local_3d_matches_oracle(require_gpu, name, make, variant):
+    """3D exact local solves: the block-band Cholesky factors are built on the device (batched over patches
+    and modes) and the solves stream them from HBM; the D-D form and D-MG (exact Neumann, multigrid
+    Dirichlet problems) reproduce the oracle."""
+    from paper_1705_04531_amd import _abi
+    wl = make()
+    u_ref, lay, _ = oracle_solution(wl)
+    opt = {"local_solver": _abi.IETI_LOCAL_EXACT} if variant == "exact" else \
+        {"local_solver": _abi.IETI_LOCAL_EXACT_MG, "mg_precision": int(variant[-2:])}
+    u, st = run_gpu(wl, tol=1e-10, **opt)
+    err = rel_err(wl, u, u_ref, lay)
+    print(f"{name} {variant}: err={err:.3e} outer={st['outer_iterations']}", flush=True)
+    assert err <= 1e-9
+    assert st["inner_iterations_mean"] == 0
+
+
+P1_CASES = [
+    ("deformed3x3_mixed", CASES_2D[1][1]),
+    ("deformed4x4_p3_n24", CASES_2D[2][1]),
+    ("cube2x2x2_n6_sine", CASES_3D[0][1]),
+    ("deformed3x3_sides_only_floating", EDGE_ONLY_CASES[3][1]),
+]
+
+
+@pytest.mark.parametrize("smoother", ["chebyshev", "tensor"])
+@pytest.mark.parametrize("prec", [64, 32])
+@pytest.mark.parametrize("name,make", P1_CASES, ids=[c[0] for c in P1_CASES])
+def test_degree1_coarse_levels_match_oracle(require_gpu, name, make, prec, smoother):
+    """Multigrid with degree 1 on every level but the finest (Sec. 4): non-nested levels joined by the L2
+    projection of the parameter domain (M_f^{-1} M_fc, line solves with the 1D mass factors) -- a different
+    preconditioner, the same solution."""
+    wl = make()
+    u_ref, lay, _ = oracle_solution(wl)
+    opt = {"smoother": 1} if smoother == "tensor" else {}
+    u, st = run_gpu(wl, mg_precision=prec, tol=1e-10, coarse_dofs=0, coarse_degree=1, **opt)
+    err = rel_err(wl, u, u_ref, lay)
+    print(f"{name} p1-coarse {smoother} prec={prec}: err={err:.3e} outer={st['outer_iterations']} "
+          f"inner mean={st['inner_iterations_mean']:.1f} max={st['inner_iterations_max']}", flush=True)
     assert err <= 1e-8
     assert st["inner_unconverged"] == 0 and st["inner_nonfinite"] == 0
