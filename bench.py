@@ -2,20 +2,23 @@
 outer CG on F lambda = d to ||r|| <= 1e-8 ||r_0||, recovery of u, FP64
 global residual) on the deformed square with 16x16 patches of uneven size and
 degree (elements per patch column/row from {32,48,64,96}, degree from {2,3,4};
-817,899 torn dofs), inexact local solves by FP64 multigrid V-cycles inside
-the FP64 outer CG.  Setup (planning, assembly, multigrid hierarchy, primal
-basis, coarse factorisation) happens before the timed region; f at the
-quadrature points is resident in HBM when timing starts.
+817,899 torn dofs), inexact local solves by flexible CG with FP64 multigrid
+V-cycles (the p-robust tensor smoother of Sec. 4 on the finest level, Chebyshev
+below) inside the FP64 outer CG.  Setup (planning, assembly, multigrid
+hierarchy, primal basis, coarse factorisation) happens before the timed region;
+f at the quadrature points is resident in HBM when timing starts.
 
 Prints one JSON line: MDoF/s (torn dofs per second of solve time); the
-roofline of the dominant kernel (the finest-level Chebyshev sweep) and of the
-whole F apply (every kernel of q = F p), both from HIP events on the solver's
-stream over the same number of steps run right after the timed ones (events
-around every launch serialise the launches); the error of each measured
-solution against the stored oracle samples (tests/golden); beside the
-headline the configuration's FP32-multigrid form, the plain FP64 exact-local
-form (speedups), the 4x4x4 cube and the 8x8 workload; and the CPU oracle
-timed on all host cores.
+roofline of the dominant kernel (with the tensor smoother the fused coarse part
+of the V-cycles, with Chebyshev the finest-level sweep) and of the whole F
+apply (every kernel of q = F p), from HIP events on the solver's stream over
+the same number of steps run right after the timed ones (events around every
+launch serialise the launches); the error of each measured solution against
+the stored oracle samples (tests/golden); beside the headline the FP32 form,
+the Chebyshev smoother, the plain FP64 exact-local form (speedups), the 4x4x4
+cube and the 8x8 workload in their configurations' form (with the tensor
+smoother and the plain form beside them); and the CPU oracle timed on all host
+cores.
 """
 import argparse
 import json
@@ -108,6 +111,7 @@ def summary(m, wl):
         from paper_1705_04531_amd import _abi
         out["f_apply"] = rate(m["prof"][_abi.IETI_KPROF_FAPPLY])
         out["finest_sweep"] = rate(m["prof"][_abi.IETI_KPROF_SMOOTH_FINE])
+        out["coarse_part"] = rate(m["prof"][_abi.IETI_KPROF_COARSE])
     return out
 
 
@@ -274,10 +278,14 @@ def main():
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--local-solver", choices=["mg", "exact_mg", "mg_saddle"], default="mg",
                     help="variant of the headline solver: mg (MG-MG, default), exact_mg (D-MG), mg_saddle (MG-MG-S)")
-    ap.add_argument("--smoother", choices=["chebyshev", "tensor"], default="chebyshev")
+    ap.add_argument("--smoother", choices=["chebyshev", "tensor"], default="tensor",
+                    help="finest-level smoother of the headline: tensor (the p-robust smoother of Sec. 4, default) or "
+                         "chebyshev")
     ap.add_argument("--precision", type=int, choices=[32, 64], default=64,
                     help="multigrid precision of the headline solver (the outer CG is always FP64)")
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="deformed16x16")
+    ap.add_argument("--cheb-coarse", type=int, default=0,
+                    help="Chebyshev degree on the coarser multigrid levels (0: the library's table)")
     ap.add_argument("--coarse-degree", type=int, choices=[0, 1], default=0,
                     help="1: degree-1 coarse levels with L2-projection transfers (Sec. 4)")
     ap.add_argument("--coarse-level", type=int, default=0,
@@ -324,17 +332,22 @@ def main():
         extra_opt["coarse_level"] = args.coarse_level
     if args.coarse_degree:
         extra_opt["coarse_degree"] = args.coarse_degree
+    if args.cheb_coarse:
+        extra_opt["cheb_degree_coarse"] = args.cheb_coarse
     m = measure(wl, gname, args.steps, args.warmup, local_solver=variant, mg_precision=args.precision, **extra_opt)
     ms_per_step = m["ms_per_step"]
     value = wl.ndof_torn / (ms_per_step * 1e-3) / 1e6
     st = m["stats"]
     prof = m["prof"]
     mgt = "double" if args.precision == 64 else "float"
-    dom = prof[_abi.IETI_KPROF_RESID_FINE if tensor else _abi.IETI_KPROF_SMOOTH_FINE]
+    # the kernel with the most time in the rocprofv3 trace of this command: with the tensor smoother the fused
+    # coarse part of the V-cycles (k_vcoarse), with Chebyshev the finest-level sweep
+    dom = prof[_abi.IETI_KPROF_COARSE if tensor else _abi.IETI_KPROF_SMOOTH_FINE]
     kr = rate(dom) or {"achieved": 0.0, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": 0.0}
     roofline = {
         "bound": "hbm",
-        "kernel": (f"k_stencil<{mgt},{mgt},{mgt},EPI_RESID,FINE> (finest-level residual sweep)" if tensor else
+        "kernel": (f"k_vcoarse<{mgt},false,0> (fused coarse levels of every patch, one work-group per patch; "
+                   f"events on the preconditioner's cycles, which run every patch)" if tensor else
                    f"k_stencil<{mgt},{mgt},{mgt},EPI_CHEB,FINE> (finest-level Chebyshev sweep, all degree "
                    f"classes in one launch)"),
         **kr,
@@ -344,6 +357,8 @@ def main():
         "f_apply": rate(prof[_abi.IETI_KPROF_FAPPLY]),
         "preconditioner": rate(prof[_abi.IETI_KPROF_PREC]),
         "apply64": rate(prof[_abi.IETI_KPROF_APPLY64]),
+        "finest_residual_sweep": rate(prof[_abi.IETI_KPROF_RESID_FINE]),
+        "finest_chebyshev_sweep": rate(prof[_abi.IETI_KPROF_SMOOTH_FINE]),
     }
     out = {
         "metric": "dual-PCG solve time & MDoF/s at rel. res 1e-8; solves/s + p50/p99 latency",
@@ -382,20 +397,29 @@ def main():
         },
         "roofline": roofline,
     }
-    if not args.no_extras and args.local_solver == "mg" and not tensor:
+    if not args.no_extras and args.local_solver == "mg":
         extras = {}
+        TENSOR = {"smoother": _abi.IETI_SMOOTHER_TENSOR}
+        # the same workload: the other precision with the headline's smoother, the other smoother at the headline's
+        # precision (each against the same oracle samples)
         other = 32 if args.precision == 64 else 64
         print(f"[bench] {wl.name} FP{other} multigrid", file=sys.stderr, flush=True)
-        m2 = measure(wl, gname, min(args.steps, 3), 1, mg_precision=other)
-        extras[f"mg{other}"] = summary(m2, wl)
-        if wl.dim == 2:   # the plain FP64 exact-local form (banded Cholesky local solves, D-D)
-            print(f"[bench] {wl.name} plain FP64 exact-local form", file=sys.stderr, flush=True)
-            mp_ = measure(wl, gname, min(args.steps, 3), 1, profile=False, local_solver=_abi.IETI_LOCAL_EXACT,
-                          mg_precision=64)
-            plain = summary(mp_, wl)
-            plain[f"speedup_inexact_mg{args.precision}_over_plain"] = round(mp_["ms_per_step"] / ms_per_step, 3)
-            plain[f"speedup_inexact_mg{other}_over_plain"] = round(mp_["ms_per_step"] / m2["ms_per_step"], 3)
-            extras["plain_fp64_exact_local"] = plain
+        m2 = measure(wl, gname, min(args.steps, 3), 1, mg_precision=other, **extra_opt)
+        extras[f"{args.smoother}_mg{other}"] = summary(m2, wl)
+        alt = "chebyshev" if tensor else "tensor"
+        print(f"[bench] {wl.name} {alt} smoother FP{args.precision}", file=sys.stderr, flush=True)
+        m3 = measure(wl, gname, min(args.steps, 3), 1, mg_precision=args.precision, **({} if tensor else TENSOR))
+        extras[f"{alt}_mg{args.precision}"] = summary(m3, wl)
+        # the plain FP64 exact-local form (D-D; 2D: host band factors, 3D: device block-band factors)
+        print(f"[bench] {wl.name} plain FP64 exact-local form", file=sys.stderr, flush=True)
+        mp_ = measure(wl, gname, min(args.steps, 3), 1, profile=False, local_solver=_abi.IETI_LOCAL_EXACT,
+                      mg_precision=64)
+        plain = summary(mp_, wl)
+        plain["speedup_inexact_headline_over_plain"] = round(mp_["ms_per_step"] / ms_per_step, 3)
+        plain[f"speedup_inexact_{args.smoother}_mg{other}_over_plain"] = round(mp_["ms_per_step"] / m2["ms_per_step"], 3)
+        extras["plain_fp64_exact_local"] = plain
+        # the other full-size workloads in their configurations' form (Chebyshev smoother, the named precision),
+        # with the tensor smoother and the plain form beside them
         for wname in sorted(WORKLOADS):
             if wname == args.workload:
                 continue
@@ -403,16 +427,25 @@ def main():
             w2 = getattr(W, bname)()
             print(f"[bench] {w2.name} FP{prec} multigrid", file=sys.stderr, flush=True)
             mw = measure(w2, gn, min(args.steps, 3), 1, mg_precision=prec)
-            extras[wname] = dict(summary(mw, w2), mg_precision=prec, ndof_torn=w2.ndof_torn)
+            e = dict(summary(mw, w2), mg_precision=prec, ndof_torn=w2.ndof_torn)
+            mt = measure(w2, gn, min(args.steps, 3), 1, profile=False, mg_precision=prec, **TENSOR)
+            e["tensor_smoother"] = summary(mt, w2)
+            print(f"[bench] {w2.name} plain FP64 exact-local form", file=sys.stderr, flush=True)
+            mpw = measure(w2, gn, min(args.steps, 3), 1, profile=False, local_solver=_abi.IETI_LOCAL_EXACT,
+                          mg_precision=64)
+            e["plain_fp64_exact_local"] = summary(mpw, w2)
+            e["speedup_inexact_over_plain"] = round(mpw["ms_per_step"] / mw["ms_per_step"], 3)
+            e["speedup_inexact_tensor_over_plain"] = round(mpw["ms_per_step"] / mt["ms_per_step"], 3)
+            extras[wname] = e
         if args.variants:
             for label, o in (("exact_mg64", {"local_solver": _abi.IETI_LOCAL_EXACT_MG, "mg_precision": 64}),
                              ("exact_mg32", {"local_solver": _abi.IETI_LOCAL_EXACT_MG, "mg_precision": 32}),
                              ("saddle_mg64", {"local_solver": _abi.IETI_LOCAL_MG_SADDLE, "mg_precision": 64}),
                              ("saddle_mg32", {"local_solver": _abi.IETI_LOCAL_MG_SADDLE, "mg_precision": 32}),
-                             ("tensor_mg64", {"smoother": _abi.IETI_SMOOTHER_TENSOR, "mg_precision": 64}),
-                             ("tensor_mg32", {"smoother": _abi.IETI_SMOOTHER_TENSOR, "mg_precision": 32}),
                              ("tensor_saddle_mg32", {"smoother": _abi.IETI_SMOOTHER_TENSOR, "mg_precision": 32,
-                                                     "local_solver": _abi.IETI_LOCAL_MG_SADDLE})):
+                                                     "local_solver": _abi.IETI_LOCAL_MG_SADDLE}),
+                             ("tensor_degree1_coarse_mg64", {"smoother": _abi.IETI_SMOOTHER_TENSOR,
+                                                             "mg_precision": 64, "coarse_degree": 1})):
                 print(f"[bench] {wl.name} {label}", file=sys.stderr, flush=True)
                 extras[label] = summary(measure(wl, gname, min(args.steps, 3), 1, profile=False, **o), wl)
         out["extras"] = extras

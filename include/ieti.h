@@ -307,7 +307,11 @@ void ieti_destroy(ieti_handle* h);
                                        algorithmic bytes of all its kernels from the per-patch inner iteration
                                        counts (multigrid variants with the Chebyshev smoother, exact local solves) */
 #define IETI_KPROF_PREC         4   /* one whole preconditioner apply z = B_D S B_D^T r, same accounting */
-#define IETI_KPROF_COUNT        5
+#define IETI_KPROF_COARSE       5   /* the fused per-patch coarse part of a V-cycle (levels >= 1), on the launches
+                                       that run every patch (the preconditioner's cycles); bytes: each patch's
+                                       right-hand side and correction, the half stencils of its smoothed coarse
+                                       levels and its coarsest inverse, once */
+#define IETI_KPROF_COUNT        6
 int ieti_profile_enable(ieti_handle* h, int32_t enable);
 int ieti_profile_query(const ieti_handle* h, int32_t kernel, int64_t* launches, double* total_ms,
                        double* total_bytes);

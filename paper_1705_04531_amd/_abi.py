@@ -45,7 +45,8 @@ IETI_KPROF_APPLY64 = 1
 IETI_KPROF_RESID_FINE = 2
 IETI_KPROF_FAPPLY = 3
 IETI_KPROF_PREC = 4
-IETI_KPROF_COUNT = 5
+IETI_KPROF_COARSE = 5
+IETI_KPROF_COUNT = 6
 
 
 class IetiPatch(C.Structure):

@@ -222,6 +222,7 @@ __device__ __forceinline__ TC stencil_sum_rows(const TC* __restrict__ c, const T
     TC acc = TC(0);
     int s = 0;
     for (int o2 = 0; o2 <= p2; ++o2)
+#pragma unroll 2
         for (int o1 = (o2 == 0 ? 0 : -p1); o1 <= p1; ++o1) {
             const int base = o1 * M0 + o2 * M01;
             if (o2 == 0 && o1 == 0) {
@@ -811,7 +812,7 @@ __global__ __launch_bounds__(TILE) void k_add_act(const PatchLev* L, const Tile*
 // loads in flight.  Accumulates in double.
 template <typename T, typename TB, typename TY>
 __device__ __forceinline__ void col_gemv(const T* __restrict__ At, int n, const TB* b, TY* y) {
-    constexpr int U = 16;
+    constexpr int U = 32;
     for (int r = threadIdx.x; r < n; r += blockDim.x) {
         double acc = 0.0;
         int j = 0;

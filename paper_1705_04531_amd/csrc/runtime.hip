@@ -104,22 +104,27 @@ static void launch_stencil(int cls, hipStream_t st, const StencilArgs& a, int re
 }
 
 template <typename T, bool STAGE, int FAM>
-static void launch_vcoarse(hipStream_t st, const CoarseArgs& a, size_t lds_bytes, bool set_attr) {
+static void launch_vcoarse(hipStream_t st, const CoarseArgs& a, size_t lds_bytes, bool set_attr, hipEvent_t ev0,
+                           hipEvent_t ev1) {
     if (set_attr)
         HIPCHECK(hipFuncSetAttribute((const void*)k_vcoarse<T, STAGE, FAM>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes));
+    else if (ev0)
+        hipExtLaunchKernelGGL((k_vcoarse<T, STAGE, FAM>), dim3(a.nlist), dim3((vc_threads<T, FAM>())), lds_bytes, st,
+                              ev0, ev1, 0, a);
     else
         hipLaunchKernelGGL((k_vcoarse<T, STAGE, FAM>), dim3(a.nlist), dim3((vc_threads<T, FAM>())), lds_bytes, st, a);
 }
 
 template <typename T>
-static void launch_vcoarse(int fam, bool stage, hipStream_t st, const CoarseArgs& a, size_t lds_bytes, bool set_attr) {
+static void launch_vcoarse(int fam, bool stage, hipStream_t st, const CoarseArgs& a, size_t lds_bytes, bool set_attr,
+                           hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
     if (fam == 0) {
-        if (stage) launch_vcoarse<T, true, 0>(st, a, lds_bytes, set_attr);
-        else launch_vcoarse<T, false, 0>(st, a, lds_bytes, set_attr);
+        if (stage) launch_vcoarse<T, true, 0>(st, a, lds_bytes, set_attr, ev0, ev1);
+        else launch_vcoarse<T, false, 0>(st, a, lds_bytes, set_attr, ev0, ev1);
     } else {
-        if (stage) launch_vcoarse<T, true, 1>(st, a, lds_bytes, set_attr);
-        else launch_vcoarse<T, false, 1>(st, a, lds_bytes, set_attr);
+        if (stage) launch_vcoarse<T, true, 1>(st, a, lds_bytes, set_attr, ev0, ev1);
+        else launch_vcoarse<T, false, 1>(st, a, lds_bytes, set_attr, ev0, ev1);
     }
 }
 
@@ -344,6 +349,7 @@ struct Solver : SolverBase {
     std::vector<int32_t> h_plist[2];   // patches of the fused kernel per class family, largest chain first
     int32_t* plist[2] = {nullptr, nullptr};
     size_t vc_lds[2] = {0, 0};
+    double vc_bytes[2] = {0.0, 0.0};   // algorithmic bytes of one launch over all patches of a family
     // statistics of the current solve
     int64_t inner_calls = 0, inner_sum = 0;
     int inner_max = 0;
@@ -615,7 +621,10 @@ struct Solver : SolverBase {
             if (h_plist[fam].empty()) continue;
             a.plist = plist[fam];
             a.nlist = (int)h_plist[fam].size();
-            launch_vcoarse<T>(fam, fuse_stage, stream, a, vc_lds[fam], false);
+            // kernel events on launches that run every patch (no activity mask: the preconditioner's cycles)
+            std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+            if (prof.on && act == nullptr) ev = prof.next(IETI_KPROF_COARSE, vc_bytes[fam]);
+            launch_vcoarse<T>(fam, fuse_stage, stream, a, vc_lds[fam], false, ev.first, ev.second);
             check_launch();
         }
     }
@@ -1823,6 +1832,14 @@ void Solver<T>::setup() {
                 const int fam = vcoarse_family(lev[f].hL[ch[(size_t)k * LMAX + f]].pclass);
                 order[fam].push_back({-b, k});
                 vc_lds[fam] = std::max(vc_lds[fam], (size_t)b);
+                // algorithmic bytes of the patch's fused part: its right-hand side in and correction out, every
+                // smoothed level's half stencil and the coarsest inverse once
+                const Patch& pa = pl.patches[k];
+                const int nl = (int)pa.lv.size();
+                double w = 2.0 * (double)pa.lv[f].n;
+                for (int q = f; q < nl; ++q)
+                    w += q == nl - 1 ? (double)pa.lv[q].n * (double)pa.lv[q].n : (double)pa.lv[q].nst * (double)pa.lv[q].n;
+                vc_bytes[fam] += w * sizeof(T);
             }
             for (int fam = 0; fam < 2; ++fam) {
                 std::sort(order[fam].begin(), order[fam].end());
