@@ -222,7 +222,6 @@ __device__ __forceinline__ TC stencil_sum_rows(const TC* __restrict__ c, const T
     TC acc = TC(0);
     int s = 0;
     for (int o2 = 0; o2 <= p2; ++o2)
-#pragma unroll 2
         for (int o1 = (o2 == 0 ? 0 : -p1); o1 <= p1; ++o1) {
             const int base = o1 * M0 + o2 * M01;
             if (o2 == 0 && o1 == 0) {
@@ -258,6 +257,67 @@ __device__ __forceinline__ TC stencil_sum_rows(const TC* __restrict__ c, const T
                 }
             }
         }
+    return acc;
+}
+
+// As stencil_sum_rows (same accumulation order) for compile-time degrees: after the diagonal row, the
+// NR = P1 + P2 (2 P1 + 1) further stencil rows in trips of R rows (a loop that is not unrolled, its body
+// unrolled), so that the loads of R rows are in flight together: a work-item waits on memory 1 + NR/R
+// times instead of 1 + NR, with the registers of R rows.  Used where the coarse-level kernel reads the
+// operator from memory.
+template <int P0, int P1, int P2>
+__host__ __device__ constexpr int chunk_rows() {
+    // the largest divisor of NR with at most 40 coefficient loads per trip
+    const int nr = P1 + P2 * (2 * P1 + 1);
+    int best = 1;
+    for (int r = 1; r <= nr; ++r)
+        if (nr % r == 0 && 2 * (2 * P0 + 1) * r <= 40) best = r;
+    return best;
+}
+
+template <int P0, int P1, int P2, typename TC, typename TX>
+__device__ __forceinline__ TC stencil_sum_chunked(const TC* __restrict__ c, const TX* __restrict__ xp, int cs,
+                                                  int M0, int M01, TC& diag) {
+    constexpr int W = 2 * P0 + 1, NR = P1 + P2 * (2 * P1 + 1), R = chunk_rows<P0, P1, P2>();
+    static_assert(NR % R == 0, "trips of whole row groups");
+    TC acc = TC(0);
+    const TC c0 = c[0];
+    diag = c0;
+    acc += c0 * TC(xp[0]);
+#pragma unroll
+    for (int o0 = 1; o0 <= P0; ++o0) acc += c[o0 * cs] * TC(xp[o0]) + c[o0 * cs - o0] * TC(xp[-o0]);
+#pragma unroll 1
+    for (int q0 = 0; q0 < NR; q0 += R) {
+        // the trip's coefficients into registers first, then the products: written this way the loads are
+        // issued together (interleaved with the products, the scheduler of a kernel near its register
+        // budget waits on each pair)
+        TC cu[R * W], cl[R * W];
+        int offs[R];
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr) {
+            // row q after the diagonal one: (o1, o2) = (q + 1, 0) in the o2 = 0 plane, then the planes o2 >= 1
+            // from o1 = -P1
+            const int q = q0 + rr;
+            const int t = q - P1;
+            const int o2 = q < P1 ? 0 : 1 + t / (2 * P1 + 1);
+            const int o1 = q < P1 ? q + 1 : t % (2 * P1 + 1) - P1;
+            offs[rr] = o1 * M0 + o2 * M01;
+            const int s = P0 + 1 + q * W;
+#pragma unroll
+            for (int o0 = -P0; o0 <= P0; ++o0) {
+                const int sj = s + o0 + P0;
+                cu[rr * W + o0 + P0] = c[sj * cs];
+                cl[rr * W + o0 + P0] = c[sj * cs - offs[rr] - o0];
+            }
+        }
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr)
+#pragma unroll
+            for (int o0 = -P0; o0 <= P0; ++o0) {
+                const int off = offs[rr] + o0;
+                acc += cu[rr * W + o0 + P0] * TC(xp[off]) + cl[rr * W + o0 + P0] * TC(xp[-off]);
+            }
+    }
     return acc;
 }
 
@@ -808,8 +868,11 @@ __global__ __launch_bounds__(TILE) void k_add_act(const PatchLev* L, const Tile*
 
 // y = A b for a dense n x n matrix stored by columns (entry (r, j) at
 // At[j * n + r]): one thread per row, so that every column load is
-// contiguous across the lanes; the column loop is unrolled to keep many
-// loads in flight.  Accumulates in double.
+// contiguous across the lanes and a wave streams whole columns; U loads per
+// thread in flight, the tail of the columns too (clamped to a valid column,
+// its products skipped).  Accumulates in double.  (Splitting the columns of a
+// row over four lanes balances the passes for n a little above the group
+// size but reads shorter runs and measured slower when few groups stream.)
 template <typename T, typename TB, typename TY>
 __device__ __forceinline__ void col_gemv(const T* __restrict__ At, int n, const TB* b, TY* y) {
     constexpr int U = 32;
@@ -823,7 +886,14 @@ __device__ __forceinline__ void col_gemv(const T* __restrict__ At, int n, const 
 #pragma unroll
             for (int u = 0; u < U; ++u) acc += (double)a[u] * (double)b[j + u];
         }
-        for (; j < n; ++j) acc += (double)At[(int64_t)j * n + r] * (double)b[j];
+        if (j < n) {
+            T a[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) a[u] = At[(int64_t)min(j + u, n - 1) * n + r];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (j + u < n) acc += (double)a[u] * (double)b[j + u];
+        }
         y[r] = TY(acc);
     }
 }
@@ -1594,11 +1664,21 @@ __host__ __device__ inline int64_t vcoarse_level_words(int64_t n, int64_t guard,
     return w;
 }
 
+// how vc_sweep sums a stencil: every load of a work-item in flight at once (2D
+// classes up to degree 3 read from memory); one stencil row at a time (operator
+// data in LDS, where the short latency needs no deep load queue and the full
+// unroll would spill registers; run-time degrees); chunks of rows (3D classes
+// and 2D classes with a degree 4 read from memory)
+enum VcForm : int { VC_FULL = 0, VC_ROWS = 1, VC_CHUNK = 2 };
+
+template <int P0, int P1, int P2, bool STAGE>
+__host__ __device__ constexpr int vc_form() {
+    return STAGE || P0 < 0 ? VC_ROWS : (P2 == 0 && P0 <= 3 && P1 <= 3 ? VC_FULL : VC_CHUNK);
+}
+
 // one Chebyshev step (or, with resid, the residual) on a level held in LDS;
-// c points at entry 0 of dof 0 of the half stencil, entries cs apart.  ROWS:
-// one stencil row at a time (operator data in LDS, where the short latency
-// needs no deep load queue and the full unroll would spill registers).
-template <int P0, int P1, int P2, typename T, bool ROWS>
+// c points at entry 0 of dof 0 of the half stencil, entries cs apart.
+template <int P0, int P1, int P2, typename T, int FORM>
 __device__ __forceinline__ void vc_sweep(const PatchLev& P, const T* c, int cs, const T* xs, T* ys, const T* bs,
                                          T* ds, int mode, const double* cc, int k, bool resid) {
     const int n = (int)P.n, M0 = P.M[0], M1 = P.M[1], M01 = M0 * M1;
@@ -1613,8 +1693,10 @@ __device__ __forceinline__ void vc_sweep(const PatchLev& P, const T* c, int cs, 
         T diag = T(1);
         // 2D from memory: every load of a coefficient in flight at once; else one stencil row at a time
         T acc;
-        if constexpr (P2 == 0 && !ROWS)
+        if constexpr (FORM == VC_FULL)
             acc = stencil_sum<P0, P1, P2>(c + i, xs + i, cs, M0, M01, P.p[0], P.p[1], P.p[2], diag);
+        else if constexpr (FORM == VC_CHUNK)
+            acc = stencil_sum_chunked<P0, P1, P2>(c + i, xs + i, cs, M0, M01, diag);
         else
             acc = stencil_sum_rows<P0>(c + i, xs + i, cs, M0, M01, P.p[0], P.p[1], P.p[2], diag);
         const T rr = bs[i] - acc;
@@ -1742,8 +1824,8 @@ __device__ __forceinline__ void vcoarse_body(const CoarseArgs& a, int k, T* lds,
         for (int step = 1; step <= a.m; ++step) {
             const bool resid = step == a.m;
             if (resid && threadIdx.x == 0) sh_cur[l] = c;
-            if constexpr (STAGE) vc_sweep<P0, P1, P2, T, true>(P, cl, n + g, X, Y, bl, dl, mode, cc, resid ? 0 : step, resid);
-            else vc_sweep<P0, P1, P2, T, (P0 > 3 || P1 > 3)>(P, cg, (int)P.cstride, X, Y, bl, dl, mode, cc, resid ? 0 : step, resid);
+            if constexpr (STAGE) vc_sweep<P0, P1, P2, T, VC_ROWS>(P, cl, n + g, X, Y, bl, dl, mode, cc, resid ? 0 : step, resid);
+            else vc_sweep<P0, P1, P2, T, vc_form<P0, P1, P2, false>()>(P, cg, (int)P.cstride, X, Y, bl, dl, mode, cc, resid ? 0 : step, resid);
             __syncthreads();
             if (!resid) {
                 T* tmp = X; X = Y; Y = tmp;
@@ -1816,8 +1898,8 @@ __device__ __forceinline__ void vcoarse_body(const CoarseArgs& a, int k, T* lds,
         __syncthreads();
         int c = cu;
         for (int step = 0; step < a.m; ++step) {
-            if constexpr (STAGE) vc_sweep<P0, P1, P2, T, true>(P, cl, n + g, X, Y, bl, dl, mode, cc, step, false);
-            else vc_sweep<P0, P1, P2, T, (P0 > 3 || P1 > 3)>(P, cg, (int)P.cstride, X, Y, bl, dl, mode, cc, step, false);
+            if constexpr (STAGE) vc_sweep<P0, P1, P2, T, VC_ROWS>(P, cl, n + g, X, Y, bl, dl, mode, cc, step, false);
+            else vc_sweep<P0, P1, P2, T, vc_form<P0, P1, P2, false>()>(P, cg, (int)P.cstride, X, Y, bl, dl, mode, cc, step, false);
             __syncthreads();
             T* tmp = X; X = Y; Y = tmp;
             c ^= 1;
