@@ -80,7 +80,7 @@ extern "C" {
  * matching weighted mass, c = sigma * mean_d(n_el,d^2), m the mask of the mode,
  * tau = 1 / lambda_max(m (K_sep + c M_sep)^{-1} m K).  The inverse is applied by fast diagonalisation
  * (generalised eigenvectors of (A_d, B_d) per direction), one pre- and one post-smoothing step per
- * V-cycle; at most 128 coefficients per direction. */
+ * V-cycle; 3D patches at most 128 coefficients per direction (IETI_ENOTSUP beyond), 2D no limit. */
 #define IETI_SMOOTHER_CHEBYSHEV 0
 #define IETI_SMOOTHER_TENSOR    1
 

@@ -292,9 +292,8 @@ struct Solver : SolverBase {
     bool fd_on = false;
     FdInfo* fd_info[2] = {nullptr, nullptr};
     double *fd_U = nullptr, *fd_lam = nullptr, *fd_z = nullptr, *fd_z2 = nullptr;
-    float *fd_U32 = nullptr, *fd_z32 = nullptr;   // 2D with FP32 V-cycles: the transforms' FP32 copies
-    int fd_p0max = 0, fd_p1max = 0, fd_tiles3 = 0;
-    size_t fd_lds = 0;
+    float *fd_U32 = nullptr, *fd_z32 = nullptr, *fd_z232 = nullptr;   // 2D with FP32 V-cycles: FP32 copies
+    int fd_p0max = 0, fd_p1max = 0, fd_tiles2 = 0, fd_tiles3 = 0;
     // level 0 FP64
     double* coef64 = nullptr;
     int64_t len0 = 0;
@@ -459,7 +458,7 @@ struct Solver : SolverBase {
     // finest level, patches with tensor-smoother data: x = tau P r (set) or x += tau P r
     void fd_smooth(int mode, const int* act, const T* r, T* x, bool set) {
         if (dim == 3) {   // six axis contractions through the two scratch buffers
-            FdArgs a{lev[0].L, fd_info[mode], fd_U, fd_lam, fd_z, act, mode, N, 0, fd_z2, nullptr, nullptr};
+            FdArgs a{lev[0].L, fd_info[mode], fd_U, fd_lam, fd_z, act, mode, N, fd_z2, nullptr, nullptr, nullptr};
             const dim3 g((fd_tiles3 + FD3_THREADS / WAVE - 1) / (FD3_THREADS / WAVE), N), b(FD3_THREADS);
             hipLaunchKernelGGL(k_fd3_ax0_fwd<T>, g, b, 0, stream, a, r);
             check_launch();
@@ -476,15 +475,19 @@ struct Solver : SolverBase {
             check_launch();
             return;
         }
-        const int ncp = (fd_p0max / 16 + 1) / 2;
-        FdArgs a{lev[0].L, fd_info[mode], fd_U, fd_lam, fd_z, act, mode, N, ncp, nullptr, fd_U32, fd_z32};
-        const dim3 grid(8 * ((N + 7) / 8) * ncp);
-        hipLaunchKernelGGL(k_fd_fwd<T>, grid, dim3(FD_THREADS), fd_lds, stream, a, r);
+        // 2D: four block products (W, Z, T, then the update of x), the blocks of all patches in each grid
+        FdArgs a{lev[0].L, fd_info[mode], fd_U, fd_lam, fd_z, act, mode, N, fd_z2, fd_U32, fd_z32, fd_z232};
+        const dim3 g((fd_tiles2 + FD2_THREADS / WAVE - 1) / (FD2_THREADS / WAVE), N), b(FD2_THREADS);
+        hipLaunchKernelGGL(k_fd2_w<T>, g, b, 0, stream, a, r);
+        check_launch();
+        hipLaunchKernelGGL(k_fd2_z<T>, g, b, 0, stream, a);
+        check_launch();
+        hipLaunchKernelGGL(k_fd2_t<T>, g, b, 0, stream, a);
         check_launch();
         if (set)
-            hipLaunchKernelGGL((k_fd_bwd<T, true>), grid, dim3(FD_THREADS), fd_lds, stream, a, x);
+            hipLaunchKernelGGL((k_fd2_y<T, true>), g, b, 0, stream, a, x);
         else
-            hipLaunchKernelGGL((k_fd_bwd<T, false>), grid, dim3(FD_THREADS), fd_lds, stream, a, x);
+            hipLaunchKernelGGL((k_fd2_y<T, false>), g, b, 0, stream, a, x);
         check_launch();
     }
     void vcycle(int mode, const int* act, const T* b0, T* x0, const double* dotq = nullptr, double* dpart = nullptr) {
@@ -904,7 +907,9 @@ struct Solver : SolverBase {
         const double U = P0 * P0 + P1 * P1 + (dim == 3 ? P2 * P2 : 0.0);
         const double lam = 8.0 * (P0 + P1 + (dim == 3 ? P2 : 0.0));
         const double xio = set ? n * s : 2.0 * n * s;
-        if (dim == 2) return (n * s + U * su + PP * su) + (PP * su + U * su + lam + xio);
+        // 2D: W = m R U_0, Z = U_1^T W (scaled), T = Z U_0^T, x (+)= U_1 T: each U twice, the three
+        // intermediates written once and read once
+        if (dim == 2) return n * s + 2.0 * U * su + 6.0 * PP * su + lam + xio;
         // 3D: r -> z (axis 0), four middle contractions, z -> x (axis 0)
         return (n * s + P0 * P0 * 8.0 + PP * 8.0) + 4.0 * (2.0 * PP * 8.0) + (P1 * P1 + P2 * P2) * 2.0 * 8.0 + lam +
                (PP * 8.0 + P0 * P0 * 8.0 + xio);
@@ -1326,7 +1331,7 @@ struct Solver : SolverBase {
             return;
         }
         const Plan& pl = *plan;
-        const int m0 = cheb_m, mc0 = cheb_mc;
+        const int m0 = cheb_m;
         struct Cand {
             double ms;
             int m, mc, stg;
@@ -1883,6 +1888,8 @@ void Solver<T>::setup() {
                     f.l2 = (int64_t)hl.size();
                     hl.insert(hl.end(), Tz.lam[2].begin(), Tz.lam[2].end());
                     fd_tiles3 = std::max(fd_tiles3, f.P0 * f.P1 * f.P2 / 256);
+                } else {
+                    fd_tiles2 = std::max(fd_tiles2, f.P0 * f.P1 / 256);
                 }
                 f.zoff = zlen;   // one scratch per patch: the two modes never run at the same time
                 f.shift = Tz.shift;
@@ -1893,8 +1900,8 @@ void Solver<T>::setup() {
             }
             zlen += zk;
         }
-        if (fd_p0max > 128 || fd_p1max > 128)
-            throw Error(IETI_ENOTSUP, "tensor smoother: more than 128 coefficients per direction");
+        if (dim == 3 && (fd_p0max > 128 || fd_p1max > 128))
+            throw Error(IETI_ENOTSUP, "tensor smoother: more than 128 coefficients per direction in 3D");
         if (fd_p0max > 0) {
             fd_on = true;
             fd_U = arena.upload(hu, st);
@@ -1903,28 +1910,14 @@ void Solver<T>::setup() {
                 std::vector<float> hu32(hu.begin(), hu.end());
                 fd_U32 = arena.upload(hu32, st);
                 fd_z32 = arena.alloc<float>(zlen, st);
+                fd_z232 = arena.alloc<float>(zlen, st);
             } else {
                 fd_z = arena.alloc<double>(zlen, st);
+                fd_z2 = arena.alloc<double>(zlen, st);
             }
-            if (dim == 3) fd_z2 = arena.alloc<double>(zlen, st);
             std::vector<FdInfo> i0(info.begin(), info.begin() + N), i1(info.begin() + N, info.end());
             fd_info[0] = arena.upload(i0, st);
             fd_info[1] = arena.upload(i1, st);
-            fd_lds = fd_lds_words(fd_p0max, fd_p1max) * sizeof(T);
-            if (dim == 3) fd_lds = 0;   // the 3D contractions use no LDS
-            int dev = 0, max_lds = 0;
-            HIPCHECK(hipGetDevice(&dev));
-            HIPCHECK(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-            if (fd_lds > (size_t)max_lds)
-                throw Error(IETI_ENOTSUP, "tensor smoother: patch too large for the transforms' LDS");
-            if (dim == 2) {
-                HIPCHECK(hipFuncSetAttribute((const void*)k_fd_fwd<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                             (int)fd_lds));
-                HIPCHECK(hipFuncSetAttribute((const void*)k_fd_bwd<T, true>,
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)fd_lds));
-                HIPCHECK(hipFuncSetAttribute((const void*)k_fd_bwd<T, false>,
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)fd_lds));
-            }
             HIPCHECK(hipStreamSynchronize(st));
         }
     }

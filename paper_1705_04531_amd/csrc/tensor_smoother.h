@@ -11,19 +11,20 @@ namespace ieti {
 // ---------------------------------------------------------------------------
 // Tensor-product smoother of the finest level (2D): y = m U (Lambda_0 (+) Lambda_1 + c)^{-1} U^T m r per
 // patch, U = U_1 (x) U_0 the generalised eigenvectors of the separable stiffness.  With the residual of a
-// patch as the M1 x M0 matrix R[i1][i0] (i0 fastest, as stored):
-//   forward:   Z = (U_1^T R U_0) ./ (lambda_1[b] + lambda_0[a] + c)     (P1 x P0, into scratch)
-//   backward:  x[i1][i0] (+)= tau (U_1 Z U_0^T)[i1][i0] on unmasked coefficients
-// Both kernels take one work-group per (pair of 16-column blocks, patch), the work-groups of a patch on
-// one XCD (fd_block) so that they share its L2: the forward one forms the column blocks W = R U_0[:, blk]
-// and then U_1^T W, the backward one T = Z U_0[blk, :]^T and then U_1 T.  The operands are staged in LDS
-// (U_1 in the first matrix's space once the first product is done); each wave runs the block products of
-// one 16-row block for both columns on the matrix cores in the multigrid precision: FP64
-// (v_mfma_f64_16x16x4f64) or, with FP32 V-cycles, FP32 (v_mfma_f32_16x16x4f32) with FP32 operands, LDS
-// and scratch; the eigenvalue scaling is done in FP64.  Patches without smoother data (P0 = 0) and
-// inactive patches return.
+// patch as the M1 x M0 matrix R[i1][i0] (i0 fastest, as stored), zero-padded to P1 x P0:
+//   W = (m R) U_0                                     (second scratch)
+//   Z = (U_1^T W) ./ (lambda_1[b] + lambda_0[a] + c)   (scratch)
+//   T = Z U_0^T                                       (second scratch)
+//   x (+)= tau m (U_1 T)                              on the M1 x M0 coefficients
+// Four batched block products, one wave per 16 x 16 output block of a patch's P1 x P0 array (grid:
+// blockIdx.y = patch, FD2_THREADS / 64 blocks per work-group), on the matrix cores in the multigrid
+// precision: FP64 (v_mfma_f64_16x16x4f64) or, with FP32 V-cycles, FP32 (v_mfma_f32_16x16x4f32) with FP32
+// operands and scratch; the eigenvalue scaling is done in FP64.  The operands come straight from memory
+// (mostly L2): no LDS, so a CU holds many work-groups that hide each other's load latency, and the blocks
+// of all patches spread over the chip.  Patches without smoother data (P0 = 0) and inactive patches
+// return.
 
-constexpr int FD_THREADS = 512;
+constexpr int FD2_THREADS = 256;
 
 struct FdInfo {
     int64_t u0, u1, u2;    // offsets of U_d (P_d x P_d, row-major) in the U array (u2: 3D only)
@@ -42,14 +43,14 @@ struct FdArgs {
     const int* active;
     int mode;
     int N;                 // patches
-    int ncb;               // 2D: pairs of column blocks per patch in the grid (largest P0 / 32, rounded up)
-    double* z2;            // 3D: second scratch buffer (same offsets as z)
+    double* z2;            // second scratch buffer (same offsets as z)
     const float* U32;      // 2D, FP32 multigrid: U in FP32 (same offsets as U)
     float* z32;            // 2D, FP32 multigrid: the scratch in FP32 (same offsets as z)
+    float* z232;           // 2D, FP32 multigrid: the second scratch in FP32
 };
 
-// Block products of the 2D transforms in the multigrid's precision CT: FP64 on v_mfma_f64_16x16x4f64,
-// FP32 on v_mfma_f32_16x16x4f32.  Both take A[l % 16][k0 + l / 16] and B[k0 + l / 16][l % 16] from lane l;
+// Block products in the multigrid's precision CT: FP64 on v_mfma_f64_16x16x4f64, FP32 on
+// v_mfma_f32_16x16x4f32.  Both take A[l % 16][k0 + l / 16] and B[k0 + l / 16][l % 16] from lane l;
 // element r of lane l is C[l / 16 + 4 r][l % 16] for FP64 and C[4 (l / 16) + r][l % 16] for FP32 (both
 // checked on the device).
 typedef float mf_f4 __attribute__((ext_vector_type(4)));
@@ -65,181 +66,204 @@ template <> struct FdMf<float> {
     __device__ static int row(int l, int r) { return 4 * (l >> 4) + r; }
 };
 
-// c += A B on 16 x 16 blocks (A[i][k] at A[i * lda + k], TA: at A[k * lda + i]; B[k][j] at B[k * ldb + j])
-template <typename CT, bool TA>
-__device__ __forceinline__ typename FdMf<CT>::acc fd_mfb(const CT* A, int lda, const CT* B, int ldb,
-                                                         typename FdMf<CT>::acc c) {
-    const int l = threadIdx.x & 63, i = l & 15, kq = l >> 4;
+// masked_bits without short-circuit evaluation (bitwise operations only), so that an operand getter that
+// calls it compiles without branches and its loads can be issued together
+__host__ __device__ __forceinline__ bool masked_nb(uint32_t mb, int dim, int M0, int M1, int M2, int i0, int i1,
+                                                   int i2) {
+    const uint32_t sides = mb & 0xFFu, corners = mb >> 8;
+    const uint32_t d3 = dim == 3;
+    const uint32_t lo0 = i0 == 0, hi0 = i0 == M0 - 1, lo1 = i1 == 0, hi1 = i1 == M1 - 1;
+    const uint32_t lo2 = d3 & (uint32_t)(i2 == 0), hi2 = d3 & (uint32_t)(i2 == M2 - 1);
+    const uint32_t side = (lo0 | (hi0 << 1) | (lo1 << 2) | (hi1 << 3) | (lo2 << 4) | (hi2 << 5)) & sides;
+    const uint32_t corner = (lo0 | hi0) & (lo1 | hi1) & ((d3 ^ 1u) | lo2 | hi2);
+    const uint32_t cb = hi0 | (hi1 << 1) | (hi2 << 2);
+    return (side | (corner & (corners >> cb))) != 0u;   // corner is 0 or 1
+}
+
+// the output block of this wave: patch k (blockIdx.y), block row bi and column bj of its P1 x P0 array;
+// false if the patch has no smoother data, is inactive, or the block is past its blocks
+__device__ __forceinline__ bool fd2_tile(const FdArgs& a, int& k, FdInfo& f, int& bi, int& bj) {
+    k = blockIdx.y;
+    f = a.info[k];
+    if (f.P0 == 0 || (a.active && !a.active[k])) return false;
+    const int t = blockIdx.x * (FD2_THREADS / WAVE) + threadIdx.x / WAVE, nb0 = f.P0 / 16;
+    if (t >= (f.P1 / 16) * nb0) return false;
+    bi = t / nb0;
+    bj = t % nb0;
+    return true;
+}
+
+// c = sum over K blocks kb < nkb of A[block][kb] B[kb][block].  Within a 16-wide K block, lane group
+// kq = l / 16 supplies k = 4 kq + s to the s-th of the four MFMAs, so that a lane's A values A[i][k0 .. k0+3]
+// and B values B[k0 .. k0+3][j] (k0 = 16 kb + 4 kq) are four consecutive K indices: ga(i, k0, v) and
+// gb(k0, j, v) fill v[0..3] (one 32-byte load where K is the contiguous index of the layout, four loads
+// that are contiguous across the lanes otherwise).  Steps of four K blocks: their operand loads are issued
+// before their products (a step past nkb re-reads the last block and skips its products).
+template <typename CT, typename GA, typename GB>
+__device__ __forceinline__ typename FdMf<CT>::acc fd2_product(int nkb, GA ga, GB gb) {
+    typedef typename FdMf<CT>::acc acc;
+    const int l = threadIdx.x & (WAVE - 1), i = l & 15, kq = l >> 4;
+    acc c = {0, 0, 0, 0};
+    for (int kb0 = 0; kb0 < nkb; kb0 += 4) {
+        CT av[16], bv[16];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-        const int k = 4 * s + kq;
-        c = FdMf<CT>::mfma(TA ? A[k * lda + i] : A[i * lda + k], B[k * ldb + i], c);
+        for (int q = 0; q < 4; ++q) {
+            const int k0 = min(kb0 + q, nkb - 1) * 16 + 4 * kq;
+            ga(i, k0, av + 4 * q);
+            gb(k0, i, bv + 4 * q);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (kb0 + q < nkb) {
+#pragma unroll
+                for (int s = 0; s < 4; ++s) c = FdMf<CT>::mfma(av[4 * q + s], bv[4 * q + s], c);
+            }
     }
     return c;
 }
 
+// four consecutive values p[0..3] by one vector load (p 4-element aligned: offsets that are multiples of 4
+// in arrays whose patch offsets are multiples of 256)
 template <typename CT>
-__device__ __forceinline__ void fd_mfs(CT* C, int ldc, typename FdMf<CT>::acc c) {
-    const int l = threadIdx.x & 63;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) C[FdMf<CT>::row(l, r) * ldc + (l & 15)] = c[r];
+__device__ __forceinline__ void load4(const CT* p, CT* v) {
+    typedef CT v4 __attribute__((ext_vector_type(4)));
+    const v4 t = *(const v4*)p;
+    v[0] = t[0];
+    v[1] = t[1];
+    v[2] = t[2];
+    v[3] = t[3];
 }
 
-// LDS words (of the multigrid precision) of either kernel for the largest padded sizes: the first
-// operand (P1 x ld), the pair of products (P1 x 33) and the pair of U_0 blocks (P0 x 33)
-__host__ __device__ inline size_t fd_lds_words(int p0max, int p1max) {
-    const int ld = (p0max > p1max ? p0max : p1max) + 1;
-    return (size_t)p1max * ld + (size_t)33 * (p1max + p0max);
+template <typename CT>
+__device__ __forceinline__ const CT* fd_u(const FdArgs& a) {
+    return std::is_same<CT, float>::value ? (const CT*)(const void*)a.U32 : (const CT*)(const void*)a.U;
+}
+template <typename CT>
+__device__ __forceinline__ CT* fd_scr(const FdArgs& a, bool second) {
+    if (std::is_same<CT, float>::value) return (CT*)(void*)(second ? a.z232 : a.z32);
+    return (CT*)(void*)(second ? a.z2 : a.z);
 }
 
-// dst[i * ld + j] = get(i, j) for i < rows, j < cols (cols a multiple of 16): thread -> (row tid / 16 of a
-// step of 32 rows, column lane tid % 16); up to 8 column blocks' loads issued before their stores
-template <typename CT, typename G>
-__device__ __forceinline__ void fd_stage(CT* dst, int ld, int rows, int cols, G get) {
-    const int tr = threadIdx.x >> 4, tc = threadIdx.x & 15, ncb = cols >> 4;
-    for (int r0 = 0; r0 < rows; r0 += FD_THREADS / 16) {
-        const int i = r0 + tr;
-        if (i >= rows) break;
-        for (int c0 = 0; c0 < ncb; c0 += 8) {
-            double v[8];
-#pragma unroll
-            for (int c = 0; c < 8; ++c) v[c] = c0 + c < ncb ? get(i, (c0 + c) * 16 + tc) : 0.0;
-#pragma unroll
-            for (int c = 0; c < 8; ++c)
-                if (c0 + c < ncb) dst[i * ld + (c0 + c) * 16 + tc] = (CT)v[c];
-        }
-    }
-}
-
-// XCD-aware work-group -> (patch, pair of 16-column blocks): consecutive work-groups go to consecutive
-// XCDs, so the work-groups of patch k are all placed on XCD k mod 8 and share its L2 for the patch's
-// operands.  Grid: 8 * ceil(N / 8) * ncp one-dimensional (ncp pairs per patch); false for the unused tail.
-__device__ __forceinline__ bool fd_block(int N, int ncp, int& k, int& cp) {
-    const int L = blockIdx.x, x = L & 7, s = L >> 3;
-    k = (s / ncp) * 8 + x;
-    cp = s % ncp;
-    return k < N;
-}
-
-// forward: column blocks 2 cp and 2 cp + 1 (if it exists) of Z; the shared R fragment feeds two
-// accumulation chains
+// W = (m R) U_0 into the second scratch
 template <typename T>
-__global__ __launch_bounds__(FD_THREADS) void k_fd_fwd(FdArgs a, const T* __restrict__ r) {
-    int k, cp;
-    if (!fd_block(a.N, a.ncb, k, cp)) return;
-    const FdInfo f = a.info[k];
-    if (f.P0 == 0 || (a.active && !a.active[k])) return;
-    const int P0 = f.P0, P1 = f.P1, ncb = P0 / 16, cb = 2 * cp;
-    if (cb >= ncb) return;
-    const bool two = cb + 1 < ncb;
-    const PatchLev& P = a.L[k];
-    const int M0 = P.M[0], M1 = P.M[1], ld = (P0 > P1 ? P0 : P1) + 1;
+__global__ __launch_bounds__(FD2_THREADS) void k_fd2_w(FdArgs a, const T* __restrict__ r) {
     typedef T CT;
-    typedef typename FdMf<CT>::acc acc;
-    extern __shared__ double fd_sm[];
-    CT* Rg = (CT*)fd_sm;                      // R (P1 x P0), then U_1 (P1 x P1); leading dimension ld
-    CT* Wb = Rg + (size_t)P1 * ld;            // W (P1 x 32), ld 33
-    CT* Ub = Wb + (size_t)P1 * 33;            // U_0[:, blocks cb, cb + 1] (P0 x 32), ld 33
-    const CT* Ua = std::is_same<CT, float>::value ? (const CT*)(const void*)a.U32 : (const CT*)(const void*)a.U;
-    const CT* U0 = Ua + f.u0;
-    const CT* U1 = Ua + f.u1;
-    const int mode = a.mode;
-    fd_stage(Rg, ld, P1, P0, [&](int i1, int i0) -> double {
-        return (i0 < M0 && i1 < M1 && !masked(P, mode, i0, i1, 0)) ? (double)r[P.voff + i0 + (int64_t)M0 * i1] : 0.0;
-    });
-    fd_stage(Ub, 33, P0, two ? 32 : 16, [&](int i, int j) -> double { return (double)U0[(int64_t)i * P0 + cb * 16 + j]; });
-    __syncthreads();
-    const int wv = threadIdx.x / WAVE, l = threadIdx.x & (WAVE - 1);
-    for (int w = wv; w < P1 / 16; w += FD_THREADS / WAVE) {   // W[block w] = R[block w, :] U_0[:, pair]
-        acc c0 = {0, 0, 0, 0}, c1 = c0;
-        for (int kb = 0; kb < P0 / 16; ++kb) {
-            c0 = fd_mfb<CT, false>(Rg + (size_t)w * 16 * ld + kb * 16, ld, Ub + kb * 16 * 33, 33, c0);
-            if (two) c1 = fd_mfb<CT, false>(Rg + (size_t)w * 16 * ld + kb * 16, ld, Ub + kb * 16 * 33 + 16, 33, c1);
+    int k, bi, bj;
+    FdInfo f;
+    if (!fd2_tile(a, k, f, bi, bj)) return;
+    const PatchLev& P = a.L[k];
+    const int M0 = P.M[0], M1 = P.M[1], P0 = f.P0, mode = a.mode;
+    const CT* U0 = fd_u<CT>(a) + f.u0;
+    const uint32_t mb = P.mbits[mode];
+    auto ga = [&](int i, int k0, CT* v) {
+        const int i1 = bi * 16 + i;
+        const T* row = r + P.voff + (int64_t)M0 * min(i1, M1 - 1);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int kk = k0 + s;
+            const CT x = (CT)row[min(kk, M0 - 1)];
+            const bool keep = (kk < M0) & (i1 < M1) & !masked_nb(mb, 2, M0, M1, 1, kk, i1, 0);
+            v[s] = keep ? x : CT(0);
         }
-        fd_mfs<CT>(Wb + w * 16 * 33, 33, c0);
-        if (two) fd_mfs<CT>(Wb + w * 16 * 33 + 16, 33, c1);
-    }
-    __syncthreads();
-    fd_stage(Rg, ld, P1, P1, [&](int i, int j) -> double { return (double)U1[(int64_t)i * P1 + j]; });
-    __syncthreads();
+    };
+    auto gb = [&](int k0, int j, CT* v) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) v[s] = U0[(int64_t)(k0 + s) * P0 + bj * 16 + j];
+    };
+    const auto c = fd2_product<CT>(P0 / 16, ga, gb);
+    CT* W = fd_scr<CT>(a, true) + f.zoff;
+    const int l = threadIdx.x & (WAVE - 1);
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) W[(int64_t)(bi * 16 + FdMf<CT>::row(l, rr)) * P0 + bj * 16 + (l & 15)] = c[rr];
+}
+
+// Z = (U_1^T W) ./ (lambda_1[b] + lambda_0[a] + c) into the scratch
+template <typename T>
+__global__ __launch_bounds__(FD2_THREADS) void k_fd2_z(FdArgs a) {
+    typedef T CT;
+    int k, bi, bj;
+    FdInfo f;
+    if (!fd2_tile(a, k, f, bi, bj)) return;
+    const int P0 = f.P0, P1 = f.P1;
+    const CT* U1 = fd_u<CT>(a) + f.u1;
+    const CT* W = fd_scr<CT>(a, true) + f.zoff;
+    auto ga = [&](int i, int k0, CT* v) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) v[s] = U1[(int64_t)(k0 + s) * P1 + bi * 16 + i];
+    };
+    auto gb = [&](int k0, int j, CT* v) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) v[s] = W[(int64_t)(k0 + s) * P0 + bj * 16 + j];
+    };
+    const auto c = fd2_product<CT>(P1 / 16, ga, gb);
+    CT* z = fd_scr<CT>(a, false) + f.zoff;
     const double* l0 = a.lam + f.l0;
     const double* l1 = a.lam + f.l1;
-    for (int w = wv; w < P1 / 16; w += FD_THREADS / WAVE) {   // Z[block w, pair] = U_1[:, block w]^T W, scaled
-        acc c0 = {0, 0, 0, 0}, c1 = c0;
-        for (int kb = 0; kb < P1 / 16; ++kb) {
-            c0 = fd_mfb<CT, true>(Rg + (size_t)kb * 16 * ld + w * 16, ld, Wb + kb * 16 * 33, 33, c0);
-            if (two) c1 = fd_mfb<CT, true>(Rg + (size_t)kb * 16 * ld + w * 16, ld, Wb + kb * 16 * 33 + 16, 33, c1);
-        }
-        CT* z = std::is_same<CT, float>::value ? (CT*)(void*)a.z32 : (CT*)(void*)a.z;
-        const int a0 = cb * 16 + (l & 15), a1 = a0 + 16;
+    const int l = threadIdx.x & (WAVE - 1), a0 = bj * 16 + (l & 15);
 #pragma unroll
-        for (int rr = 0; rr < 4; ++rr) {
-            const int bb = w * 16 + FdMf<CT>::row(l, rr);
-            z[f.zoff + (int64_t)bb * P0 + a0] = (CT)((double)c0[rr] / (l1[bb] + l0[a0] + f.shift));
-            if (two) z[f.zoff + (int64_t)bb * P0 + a1] = (CT)((double)c1[rr] / (l1[bb] + l0[a1] + f.shift));
-        }
+    for (int rr = 0; rr < 4; ++rr) {
+        const int bb = bi * 16 + FdMf<CT>::row(l, rr);
+        z[(int64_t)bb * P0 + a0] = (CT)((double)c[rr] / (l1[bb] + l0[a0] + f.shift));
     }
 }
 
-// backward, column blocks 2 cp and 2 cp + 1 of x.  SET: x = tau y (masked coefficients 0); otherwise
+// T = Z U_0^T into the second scratch (column blocks that reach past M0 are not needed)
+template <typename T>
+__global__ __launch_bounds__(FD2_THREADS) void k_fd2_t(FdArgs a) {
+    typedef T CT;
+    int k, bi, bj;
+    FdInfo f;
+    if (!fd2_tile(a, k, f, bi, bj)) return;
+    if (bj * 16 >= a.L[k].M[0]) return;
+    const int P0 = f.P0;
+    const CT* U0 = fd_u<CT>(a) + f.u0;
+    const CT* Z = fd_scr<CT>(a, false) + f.zoff;
+    auto ga = [&](int i, int k0, CT* v) { load4(Z + (int64_t)(bi * 16 + i) * P0 + k0, v); };
+    auto gb = [&](int k0, int j, CT* v) { load4(U0 + (int64_t)(bj * 16 + j) * P0 + k0, v); };
+    const auto c = fd2_product<CT>(P0 / 16, ga, gb);
+    CT* Tm = fd_scr<CT>(a, true) + f.zoff;
+    const int l = threadIdx.x & (WAVE - 1);
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) Tm[(int64_t)(bi * 16 + FdMf<CT>::row(l, rr)) * P0 + bj * 16 + (l & 15)] = c[rr];
+}
+
+// x (+)= tau m (U_1 T) on the M1 x M0 coefficients.  SET: x = tau y (masked coefficients 0); otherwise
 // x += tau y
 template <typename T, bool SET>
-__global__ __launch_bounds__(FD_THREADS) void k_fd_bwd(FdArgs a, T* __restrict__ x) {
-    int k, cp;
-    if (!fd_block(a.N, a.ncb, k, cp)) return;
-    const FdInfo f = a.info[k];
-    if (f.P0 == 0 || (a.active && !a.active[k])) return;
-    const PatchLev& P = a.L[k];
-    const int M0 = P.M[0], M1 = P.M[1], P0 = f.P0, P1 = f.P1, ld = (P0 > P1 ? P0 : P1) + 1, jc = 2 * cp;
-    if (jc * 16 >= M0) return;
-    const bool two = (jc + 1) * 16 < M0;
+__global__ __launch_bounds__(FD2_THREADS) void k_fd2_y(FdArgs a, T* __restrict__ x) {
     typedef T CT;
-    typedef typename FdMf<CT>::acc acc;
-    extern __shared__ double fd_sm[];
-    CT* Zg = (CT*)fd_sm;                      // Z (P1 x P0), then U_1 (P1 x P1); leading dimension ld
-    CT* Tb = Zg + (size_t)P1 * ld;            // T (P1 x 32), ld 33
-    CT* Ub = Tb + (size_t)P1 * 33;            // U_0[blocks jc, jc + 1, :]^T (P0 x 32), ld 33
-    const CT* Ua = std::is_same<CT, float>::value ? (const CT*)(const void*)a.U32 : (const CT*)(const void*)a.U;
-    const CT* U0 = Ua + f.u0;
-    const CT* U1 = Ua + f.u1;
-    const CT* Z = (std::is_same<CT, float>::value ? (const CT*)(const void*)a.z32 : (const CT*)(const void*)a.z) + f.zoff;
-    const int wv = threadIdx.x / WAVE, l = threadIdx.x & (WAVE - 1);
-    fd_stage(Zg, ld, P1, P0, [&](int i, int j) -> double { return (double)Z[(int64_t)i * P0 + j]; });
-    fd_stage(Ub, 33, P0, two ? 32 : 16, [&](int i, int j) -> double { return (double)U0[(int64_t)(jc * 16 + j) * P0 + i]; });
-    __syncthreads();
-    for (int w = wv; w < P1 / 16; w += FD_THREADS / WAVE) {   // T[block w] = Z[block w, :] U_0[pair, :]^T
-        acc c0 = {0, 0, 0, 0}, c1 = c0;
-        for (int kb = 0; kb < P0 / 16; ++kb) {
-            c0 = fd_mfb<CT, false>(Zg + (size_t)w * 16 * ld + kb * 16, ld, Ub + kb * 16 * 33, 33, c0);
-            if (two) c1 = fd_mfb<CT, false>(Zg + (size_t)w * 16 * ld + kb * 16, ld, Ub + kb * 16 * 33 + 16, 33, c1);
+    int k, bi, bj;
+    FdInfo f;
+    if (!fd2_tile(a, k, f, bi, bj)) return;
+    const PatchLev& P = a.L[k];
+    const int M0 = P.M[0], M1 = P.M[1], P0 = f.P0, P1 = f.P1;
+    if (bj * 16 >= M0 || bi * 16 >= M1) return;
+    const CT* U1 = fd_u<CT>(a) + f.u1;
+    const CT* Tm = fd_scr<CT>(a, true) + f.zoff;
+    auto ga = [&](int i, int k0, CT* v) { load4(U1 + (int64_t)(bi * 16 + i) * P1 + k0, v); };
+    auto gb = [&](int k0, int j, CT* v) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) v[s] = Tm[(int64_t)(k0 + s) * P0 + bj * 16 + j];
+    };
+    const auto c = fd2_product<CT>(P1 / 16, ga, gb);
+    const int l = threadIdx.x & (WAVE - 1), i0 = bj * 16 + (l & 15);
+    double old[4] = {0.0, 0.0, 0.0, 0.0};
+    if (!SET) {   // the four old values loaded together (clamped to valid coefficients)
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+            const int i1 = min(bi * 16 + FdMf<CT>::row(l, rr), M1 - 1);
+            old[rr] = (double)x[P.voff + min(i0, M0 - 1) + (int64_t)M0 * i1];
         }
-        fd_mfs<CT>(Tb + w * 16 * 33, 33, c0);
-        if (two) fd_mfs<CT>(Tb + w * 16 * 33 + 16, 33, c1);
     }
-    __syncthreads();
-    fd_stage(Zg, ld, P1, P1, [&](int i, int j) -> double { return (double)U1[(int64_t)i * P1 + j]; });
-    __syncthreads();
-    for (int w = wv; w < P1 / 16; w += FD_THREADS / WAVE) {   // Y[block w, pair] = U_1[block w, :] T
-        acc c0 = {0, 0, 0, 0}, c1 = c0;
-        for (int kb = 0; kb < P1 / 16; ++kb) {
-            c0 = fd_mfb<CT, false>(Zg + (size_t)w * 16 * ld + kb * 16, ld, Tb + kb * 16 * 33, 33, c0);
-            if (two) c1 = fd_mfb<CT, false>(Zg + (size_t)w * 16 * ld + kb * 16, ld, Tb + kb * 16 * 33 + 16, 33, c1);
-        }
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            if (q == 1 && !two) break;
-            const int i0 = (jc + q) * 16 + (l & 15);
-#pragma unroll
-            for (int rr = 0; rr < 4; ++rr) {
-                const int i1 = w * 16 + FdMf<CT>::row(l, rr);
-                if (i0 >= M0 || i1 >= M1) continue;
-                const double v = q ? c1[rr] : c0[rr];
-                const int64_t vi = P.voff + i0 + (int64_t)M0 * i1;
-                const bool m = masked(P, a.mode, i0, i1, 0);
-                if (SET) x[vi] = m ? T(0) : T(f.tau * v);
-                else if (!m) x[vi] = T((double)x[vi] + f.tau * v);
-            }
-        }
+    for (int rr = 0; rr < 4; ++rr) {
+        const int i1 = bi * 16 + FdMf<CT>::row(l, rr);
+        if (i0 >= M0 || i1 >= M1) continue;
+        const double v = c[rr];
+        const int64_t vi = P.voff + i0 + (int64_t)M0 * i1;
+        const bool m = masked(P, a.mode, i0, i1, 0);
+        if (SET) x[vi] = m ? T(0) : T(f.tau * v);
+        else if (!m) x[vi] = T(old[rr] + f.tau * v);
     }
 }
 

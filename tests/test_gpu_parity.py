@@ -193,6 +193,22 @@ def test_tensor_smoother_matches_oracle(require_gpu, name, make, variant, solver
     assert st["cheb_degree"] == 0
 
 
+@pytest.mark.parametrize("prec", [64, 32])
+def test_tensor_smoother_wide_patches(require_gpu, prec):
+    """2D patches with more than 128 coefficients per direction (2x1 deformed square, p = 4, 136 and 128
+    elements: 140 and 132 coefficients, padded to 144): the tensor smoother's block products have no size
+    limit in 2D, and the solve still matches the oracle."""
+    from paper_1705_04531_amd import _abi
+    wl = W.deformed_square((2, 1), 4, [[136, 128], [132]], amp_factor=0.8, name="wide2x1_p4")
+    u_ref, lay, _ = oracle_solution(wl)
+    u, st = run_gpu(wl, local_solver=0, mg_precision=prec, tol=1e-10, smoother=_abi.IETI_SMOOTHER_TENSOR)
+    err = rel_err(wl, u, u_ref, lay)
+    print(f"wide2x1_p4 tensor smoother prec={prec}: err={err:.3e} outer={st['outer_iterations']} "
+          f"inner={st['inner_iterations_mean']:.2f}", flush=True)
+    assert err <= 1e-8
+    assert st["cheb_degree"] == 0
+
+
 def test_tensor_smoother_p_robust(require_gpu):
     """p-robustness (Sec. 4): on the same 2x2 deformed square with 32^2 elements per patch and the
     full h-hierarchy, degrees 2..6, both smoothers reach the oracle's solution; the tensor smoother's
