@@ -219,10 +219,13 @@ def serve(args):
                     time.sleep(delay)
             tick.append(srv.submit(wl.patches, f))
         lat, bad = [], 0
-        for t in tick:
+        for i, t in enumerate(tick):
             rc, u, st, times = srv.poll(t, wait=True)
             bad += rc != 0
             lat.append(times[2] - times[0])
+            if (i + 1) % 64 == 0:
+                print(f"[serve] {i + 1}/{len(tick)} done, {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+                      flush=True)
         span = time.perf_counter() - t0
         srv.close()
         return span, np.array(lat), bad
@@ -275,7 +278,7 @@ def main():
                     help="also time D-MG, MG-MG-S and the tensor smoother on the headline workload")
     ap.add_argument("--serve", action="store_true", help="serving benchmark instead of the solve benchmark")
     ap.add_argument("--requests", type=int, default=512)
-    ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--slots", type=int, default=8)
     ap.add_argument("--local-solver", choices=["mg", "exact_mg", "mg_saddle"], default="mg",
                     help="variant of the headline solver: mg (MG-MG, default), exact_mg (D-MG), mg_saddle (MG-MG-S)")
     ap.add_argument("--smoother", choices=["chebyshev", "tensor"], default="tensor",

@@ -625,6 +625,20 @@ static void add_param_mass(const Patch& P, Level& L, double alpha) {
 }
 
 // y = m (K m x) with the half stencil, FP64, on the host.
+// sum_k a[k] b[k] in four interleaved partial sums (independent multiply-add chains)
+static inline double dot4(const double* a, const double* b, int64_t m) {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int64_t k = 0;
+    for (; k + 4 <= m; k += 4) {
+        s0 += a[k] * b[k];
+        s1 += a[k + 1] * b[k + 1];
+        s2 += a[k + 2] * b[k + 2];
+        s3 += a[k + 3] * b[k + 3];
+    }
+    for (; k < m; ++k) s0 += a[k] * b[k];
+    return (s0 + s1) + (s2 + s3);
+}
+
 static void host_apply(const Patch& P, const Level& L, const std::vector<uint8_t>& mask, const double* x, double* y) {
     std::fill(y, y + L.n, 0.0);
     for (int i2 = 0; i2 < L.M[2]; ++i2)
@@ -1190,32 +1204,31 @@ static std::vector<double> dense_inverse(const Patch& P, const Level& L, int mod
         e[j] = 0.0;
         for (int64_t i = 0; i < n; ++i) A[(size_t)i * n + j] = col[i];
     }
-    // Cholesky A = C C^T (lower, in place)
+    // Cholesky A = C C^T (lower, row-major, in place): every dot product runs over two contiguous rows
     for (int64_t j = 0; j < n; ++j) {
-        double s = A[(size_t)j * n + j];
-        for (int64_t k = 0; k < j; ++k) s -= A[(size_t)j * n + k] * A[(size_t)j * n + k];
+        const double* Cj = &A[(size_t)j * n];
+        const double s = A[(size_t)j * n + j] - dot4(Cj, Cj, j);
         if (!(s > 0)) throw Error(IETI_EINVAL, "coarsest-level matrix is not positive definite");
-        double c = std::sqrt(s);
+        const double c = std::sqrt(s);
         A[(size_t)j * n + j] = c;
-        for (int64_t i = j + 1; i < n; ++i) {
-            double t = A[(size_t)i * n + j];
-            for (int64_t k = 0; k < j; ++k) t -= A[(size_t)i * n + k] * A[(size_t)j * n + k];
-            A[(size_t)i * n + j] = t / c;
-        }
+        for (int64_t i = j + 1; i < n; ++i) A[(size_t)i * n + j] = (A[(size_t)i * n + j] - dot4(&A[(size_t)i * n], Cj, j)) / c;
     }
+    // C^T by rows, so that the backward substitutions read contiguous rows too
+    std::vector<double> CT((size_t)n * n, 0.0);
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t k = 0; k <= i; ++k) CT[(size_t)k * n + i] = A[(size_t)i * n + k];
     std::vector<double> inv((size_t)n * n, 0.0), z(n);
     for (int64_t j = 0; j < n; ++j) {
         if (mask[j]) continue;
+        // C y = e_j: y[i] = 0 for i < j
         std::fill(z.begin(), z.end(), 0.0);
-        z[j] = 1.0;
-        for (int64_t i = 0; i < n; ++i) {   // C y = e_j
-            double t = z[i];
-            for (int64_t k = 0; k < i; ++k) t -= A[(size_t)i * n + k] * z[k];
+        for (int64_t i = j; i < n; ++i) {
+            const double t = (i == j ? 1.0 : 0.0) - dot4(&A[(size_t)i * n + j], &z[j], i - j);
             z[i] = t / A[(size_t)i * n + i];
         }
-        for (int64_t i = n - 1; i >= 0; --i) {   // C^T x = y
-            double t = z[i];
-            for (int64_t k = i + 1; k < n; ++k) t -= A[(size_t)k * n + i] * z[k];
+        // C^T x = y
+        for (int64_t i = n - 1; i >= 0; --i) {
+            const double t = z[i] - dot4(&CT[(size_t)i * n + i + 1], &z[i + 1], n - 1 - i);
             z[i] = t / A[(size_t)i * n + i];
         }
         for (int64_t i = 0; i < n; ++i) inv[(size_t)i * n + j] = mask[i] ? 0.0 : z[i];
@@ -1255,7 +1268,7 @@ static void band_factor(const Patch& P, const Level& L, int mode, int64_t b, std
             const int64_t k0 = std::max(j0, j - b);
             const double* Li = &A[(size_t)i * w + (k0 - i + b)];
             const double* Lj = &A[(size_t)j * w + (k0 - j + b)];
-            for (int64_t k = 0; k < j - k0; ++k) s -= Li[k] * Lj[k];
+            s -= dot4(Li, Lj, j - k0);
             if (j == i) {
                 if (!(s > 0)) throw Error(IETI_EINVAL, "local stiffness is not positive definite");
                 A[(size_t)i * w + b] = std::sqrt(s);

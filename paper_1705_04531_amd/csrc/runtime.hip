@@ -30,6 +30,7 @@
 #include <memory>
 #include <string>
 #include <type_traits>
+#include <unordered_map>
 #include <vector>
 
 #include "kernels.h"
@@ -160,24 +161,133 @@ static void launch_prolong(int cls, hipStream_t st, const PatchLev* Lf, const Pa
 
 // ------------------------------------------------------------------ device memory arena
 
+// Device memory of a server: the blocks of a finished request are cached and handed to later requests, so
+// that a request costs no hipMalloc/hipFree once the pool has warmed up (hipFree waits for the whole device
+// and stalls the other slots).  Blocks come in size classes of 1/8 of a power of two (at least 64 KiB; at
+// most 12.5 % over the request) and are reused only for the same class.  When a new block would take the
+// pool's bytes past the cap (the server's HBM budget; 0: none), or hipMalloc fails, the cached blocks are
+// released first.  A block is returned only after the work that used it has finished (the server
+// synchronizes the request's stream before it destroys the request's state).
+struct DevicePool {
+    std::mutex mu;
+    std::multimap<size_t, void*> cached;
+    std::unordered_map<void*, size_t> size_of;
+    size_t total = 0, cap = 0;
+    static size_t size_class(size_t b) {
+        size_t c = std::max<size_t>(b, (size_t)64 << 10), pw = 1;
+        while (pw * 2 <= c) pw *= 2;
+        const size_t step = pw / 8;
+        return (c + step - 1) / step * step;
+    }
+    void release_locked() {
+        for (auto& kv : cached) {
+            (void)hipFree(kv.second);
+            total -= kv.first;
+            size_of.erase(kv.second);
+        }
+        cached.clear();
+    }
+    void* get(size_t b) {
+        const size_t c = size_class(b);
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            auto it = cached.find(c);
+            if (it != cached.end()) {
+                void* p = it->second;
+                cached.erase(it);
+                return p;
+            }
+            if (cap && total + c > cap) release_locked();
+        }
+        void* p = nullptr;
+        if (hipMalloc(&p, c) != hipSuccess) {
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                release_locked();
+            }
+            if (hipMalloc(&p, c) != hipSuccess) return nullptr;
+        }
+        std::lock_guard<std::mutex> lk(mu);
+        size_of[p] = c;
+        total += c;
+        return p;
+    }
+    void put(void* p) {
+        std::lock_guard<std::mutex> lk(mu);
+        cached.emplace(size_of.at(p), p);
+    }
+    // pinned host blocks (a request's scalars read back by the host), cached the same way (hipHostFree also
+    // waits for the device)
+    std::multimap<size_t, void*> cached_h;
+    std::unordered_map<void*, size_t> size_h;
+    void* get_host(size_t b) {
+        const size_t c = std::max<size_t>(b, 4096);
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            auto it = cached_h.lower_bound(c);
+            if (it != cached_h.end() && it->first <= 4 * c) {
+                void* p = it->second;
+                cached_h.erase(it);
+                return p;
+            }
+        }
+        void* p = nullptr;
+        if (hipHostMalloc(&p, c) != hipSuccess) return nullptr;
+        std::lock_guard<std::mutex> lk(mu);
+        size_h[p] = c;
+        return p;
+    }
+    void put_host(void* p) {
+        std::lock_guard<std::mutex> lk(mu);
+        cached_h.emplace(size_h.at(p), p);
+    }
+    ~DevicePool() {
+        for (auto& kv : size_of) (void)hipFree(kv.first);
+        for (auto& kv : size_h) (void)hipHostFree(kv.first);
+    }
+};
+
+// the pool of the server whose worker runs on this thread (null elsewhere: plain hipMalloc/hipFree)
+static thread_local DevicePool* t_pool = nullptr;
+
+static void* dev_alloc(size_t b) {
+    void* p = nullptr;
+    if (t_pool) return t_pool->get(b);
+    return hipMalloc(&p, b) == hipSuccess ? p : nullptr;
+}
+
 struct Arena {
     std::vector<void*> ptrs;
     size_t bytes = 0;
     size_t budget = 0;
+    DevicePool* pool = t_pool;
     ~Arena() {
-        for (void* p : ptrs) (void)hipFree(p);
+        for (void* p : ptrs) {
+            if (pool) pool->put(p);
+            else (void)hipFree(p);
+        }
     }
     template <typename T>
     T* alloc(int64_t n, hipStream_t st, bool zero = true) {
         if (n <= 0) n = 1;
         size_t b = (size_t)n * sizeof(T);
         if (budget && bytes + b > budget) throw Error(IETI_ENOMEM, "device memory budget exceeded");
-        void* p = nullptr;
-        if (hipMalloc(&p, b) != hipSuccess) throw Error(IETI_ENOMEM, "hipMalloc failed");
+        void* p = pool ? pool->get(b) : dev_alloc(b);
+        if (!p) throw Error(IETI_ENOMEM, "hipMalloc failed");
         ptrs.push_back(p);
         bytes += b;
         if (zero) HIPCHECK(hipMemsetAsync(p, 0, b, st));
         return (T*)p;
+    }
+    // gives one block back before the arena ends, once the work queued on st has finished
+    void release(void* p, size_t b, hipStream_t st) {
+        auto it = std::find(ptrs.begin(), ptrs.end(), p);
+        if (it == ptrs.end()) return;
+        HIPCHECK(hipStreamSynchronize(st));
+        ptrs.erase(it);
+        bytes -= b;
+        if (pool) pool->put(p);
+        else (void)hipFree(p);
     }
     template <typename T>
     T* upload(const std::vector<T>& v, hipStream_t st) {
@@ -1551,9 +1661,11 @@ struct Solver : SolverBase {
     ~Solver() override {
         for (auto& g : fcg_graphs)
             if (g.second) (void)hipGraphExecDestroy(g.second);
-        if (h_nactive) (void)hipHostFree(h_nactive);
-        if (h_sc) (void)hipHostFree(h_sc);
-        if (h_done) (void)hipHostFree(h_done);
+        for (void* p : {(void*)h_nactive, (void*)h_sc, (void*)h_done}) {
+            if (!p) continue;
+            if (arena.pool) arena.pool->put_host(p);
+            else (void)hipHostFree(p);
+        }
     }
 };
 
@@ -2008,9 +2120,16 @@ void Solver<T>::setup() {
         comp_patch = arena.upload(cp, st);
     }
     done_dev = arena.alloc<int>(ncomp, st);
-    HIPCHECK(hipHostMalloc((void**)&h_nactive, sizeof(int)));
-    HIPCHECK(hipHostMalloc((void**)&h_sc, 16 * (size_t)ncomp * sizeof(double)));
-    HIPCHECK(hipHostMalloc((void**)&h_done, (size_t)ncomp * sizeof(int)));
+    auto pinned = [&](size_t b) -> void* {
+        void* p = nullptr;
+        if (arena.pool) p = arena.pool->get_host(b);
+        else if (hipHostMalloc(&p, b) != hipSuccess) p = nullptr;
+        if (!p) throw Error(IETI_ENOMEM, "hipHostMalloc failed");
+        return p;
+    };
+    h_nactive = (int*)pinned(sizeof(int));
+    h_sc = (double*)pinned(16 * (size_t)ncomp * sizeof(double));
+    h_done = (int*)pinned((size_t)ncomp * sizeof(int));
 
     // ---- jump operators (device positions on level 0)
     auto devpos = [&](int64_t torn) {
@@ -2165,10 +2284,8 @@ void Solver<T>::setup() {
     if (npi > 0) {
         const int nj = npk_max;
         psi = arena.alloc<double>((int64_t)nj * len0, st);
-        // raw columns Y_j = K_rr^{-1} rhs_j (device scratch for setup)
-        double* Y = nullptr;
-        HIPCHECK(hipMalloc((void**)&Y, sizeof(double) * (size_t)nj * len0));
-        std::unique_ptr<double, void (*)(double*)> Yguard(Y, [](double* p) { (void)hipFree(p); });
+        // raw columns Y_j = K_rr^{-1} rhs_j (device scratch for setup, released below)
+        double* Y = arena.alloc<double>((int64_t)nj * len0, st, false);
         HIPCHECK(hipMemsetAsync(Y, 0, sizeof(double) * (size_t)nj * len0, st));
         for (int j = 0; j < nj; ++j) {
             fill<double>(e64, len0, 0.0);
@@ -2255,6 +2372,7 @@ void Solver<T>::setup() {
         std::vector<double> hS((size_t)N * NPMAX * NPMAX);
         HIPCHECK(hipMemcpyAsync(hS.data(), Sk, hS.size() * sizeof(double), hipMemcpyDeviceToHost, st));
         sync();
+        arena.release(Y, sizeof(double) * (size_t)nj * len0, st);
         std::vector<double> S((size_t)npi * npi, 0.0);
         for (int k = 0; k < N; ++k) {
             const Patch& pa = pl.patches[k];
@@ -2890,6 +3008,7 @@ struct SrvReq {
 };
 
 struct ieti_server {
+    DevicePool pool;          // device memory of the requests (declared first: released after the workers end)
     ieti_options opt{};
     std::string tune_cache;   // owned copy of opt.tune_cache
     int slots = 1;
@@ -2954,8 +3073,9 @@ static void server_solve(ieti_server* S, hipStream_t st, std::vector<SrvReq*>& b
         const int64_t nq = plan->n_qp, nt = plan->ndof_torn;
         std::vector<int64_t> tb = plan->comp_torn_beg;
         h = make_handle(std::move(plan));
-        HIPCHECK(hipMalloc((void**)&fd, sizeof(double) * nq));
-        HIPCHECK(hipMalloc((void**)&ud, sizeof(double) * nt));
+        fd = (double*)S->pool.get(sizeof(double) * nq);
+        ud = (double*)S->pool.get(sizeof(double) * nt);
+        if (!fd || !ud) throw Error(IETI_ENOMEM, "hipMalloc failed");
         int64_t qo = 0;
         for (SrvReq* r : batch) {
             HIPCHECK(hipMemcpyAsync(fd + qo, r->f.data(), sizeof(double) * r->f.size(), hipMemcpyHostToDevice, st));
@@ -2978,9 +3098,10 @@ static void server_solve(ieti_server* S, hipStream_t st, std::vector<SrvReq*>& b
         for (auto& rc : rcs) rc = IETI_EINVAL;
         set_last_error(e.what());
     }
+    (void)hipStreamSynchronize(st);   // nothing of this batch in flight before its memory goes back to the pool
     if (h) ieti_destroy(h);
-    if (fd) (void)hipFree(fd);
-    if (ud) (void)hipFree(ud);
+    if (fd) S->pool.put(fd);
+    if (ud) S->pool.put(ud);
     if (!admitted && batch.size() > 1 && rcs[0] != IETI_OK) {
         // the batch failed before it ran: retry its requests one by one
         for (SrvReq* r : batch) {
@@ -3006,6 +3127,7 @@ static void server_solve(ieti_server* S, hipStream_t st, std::vector<SrvReq*>& b
 
 static void server_worker(ieti_server* S) {
     (void)hipSetDevice(S->device);
+    t_pool = &S->pool;
     hipStream_t st = nullptr;
     if (hipStreamCreate(&st) != hipSuccess) return;
     for (;;) {
@@ -3055,6 +3177,7 @@ int ieti_server_create(const ieti_options* opt, int32_t max_slots, ieti_server**
         }
         S->slots = max_slots;
         S->budget = S->opt.hbm_budget;
+        S->pool.cap = S->budget;
         int dev = S->opt.device;
         if (dev < 0) HIPCHECK(hipGetDevice(&dev));
         S->device = dev;

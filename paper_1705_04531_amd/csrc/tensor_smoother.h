@@ -296,24 +296,30 @@ __global__ __launch_bounds__(FD3_THREADS) void k_fd3_ax0_fwd(FdArgs a, const T* 
     if (!fd3_tile(a, k, f, t)) return;
     const PatchLev& P = a.L[k];
     const int nco = f.P0 / 16, ro = t / nco, co = t % nco;
-    const int l = threadIdx.x & (WAVE - 1), i = l & 15, kq = l >> 4;
-    const int o = ro * 16 + i, i1 = o % f.P1, i2 = o / f.P1;
-    const bool rowok = i1 < P.M[1] && i2 < P.M[2];
+    const int l = threadIdx.x & (WAVE - 1);
+    const int M0 = P.M[0], M1 = P.M[1], M2 = P.M[2], P0 = f.P0, P1 = f.P1;
+    const uint32_t mb = P.mbits[a.mode];
     const double* U0 = a.U + f.u0;
-    mf_d4 c = {0.0, 0.0, 0.0, 0.0};
-    for (int kb = 0; kb < f.P0 / 16; ++kb)
+    auto ga = [&](int i, int k0, double* v) {
+        const int o = ro * 16 + i, i1 = o % P1, i2 = o / P1;
+        const bool rowok = (i1 < M1) & (i2 < M2);
+        const T* row = r + P.voff + (int64_t)M0 * (min(i1, M1 - 1) + (int64_t)M1 * min(i2, M2 - 1));
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
-            const int i0 = kb * 16 + 4 * s + kq;
-            double av = 0.0;
-            if (rowok && i0 < P.M[0] && !masked(P, a.mode, i0, i1, i2))
-                av = (double)r[P.voff + i0 + (int64_t)P.M[0] * (i1 + (int64_t)P.M[1] * i2)];
-            c = __builtin_amdgcn_mfma_f64_16x16x4f64(av, U0[(int64_t)i0 * f.P0 + co * 16 + i], c, 0, 0, 0);
+            const int i0 = k0 + s;
+            const double x = (double)row[min(i0, M0 - 1)];
+            v[s] = (rowok & (i0 < M0) & !masked_nb(mb, 3, M0, M1, M2, i0, i1, i2)) ? x : 0.0;
         }
+    };
+    auto gb = [&](int k0, int j, double* v) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) v[s] = U0[(int64_t)(k0 + s) * P0 + co * 16 + j];
+    };
+    const mf_d4 c = fd2_product<double>(P0 / 16, ga, gb);
 #pragma unroll
     for (int rr = 0; rr < 4; ++rr) {
         const int orow = ro * 16 + (l >> 4) + 4 * rr;
-        a.z[f.zoff + (int64_t)orow * f.P0 + co * 16 + i] = c[rr];
+        a.z[f.zoff + (int64_t)orow * f.P0 + co * 16 + (l & 15)] = c[rr];
     }
 }
 
@@ -330,10 +336,19 @@ __global__ __launch_bounds__(FD3_THREADS) void k_fd3_axn(FdArgs a, const double*
     const int o = t / (ncr * nci), rem = t % (ncr * nci), cr = rem / nci, ci = rem % nci;
     const double* U = a.U + (AX == 1 ? f.u1 : f.u2);
     const double* B = in + f.zoff + (int64_t)o * Pax * inner + ci * 16;
-    mf_d4 c = {0.0, 0.0, 0.0, 0.0};
-    for (int kb = 0; kb < ncr; ++kb)
-        c = FWD ? mf_block<true>(U + (int64_t)kb * 16 * Pax + cr * 16, Pax, B + (int64_t)kb * 16 * inner, inner, c, 1.0)
-                : mf_block<false>(U + (int64_t)cr * 16 * Pax + kb * 16, Pax, B + (int64_t)kb * 16 * inner, inner, c, 1.0);
+    auto ga = [&](int i, int k0, double* v) {   // A[c][i] = U[i][c] (FWD) or U[c][i]
+        if (FWD) {
+#pragma unroll
+            for (int s = 0; s < 4; ++s) v[s] = U[(int64_t)(k0 + s) * Pax + cr * 16 + i];
+        } else {
+            load4(U + (int64_t)(cr * 16 + i) * Pax + k0, v);
+        }
+    };
+    auto gb = [&](int k0, int j, double* v) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) v[s] = B[(int64_t)(k0 + s) * inner + j];
+    };
+    const mf_d4 c = fd2_product<double>(ncr, ga, gb);
     const int l = threadIdx.x & (WAVE - 1);
     const int n = ci * 16 + (l & 15);
 #pragma unroll
@@ -357,20 +372,28 @@ __global__ __launch_bounds__(FD3_THREADS) void k_fd3_ax0_bwd(FdArgs a, T* __rest
     const PatchLev& P = a.L[k];
     const int nco = f.P0 / 16, ro = t / nco, co = t % nco;
     const double* U0 = a.U + f.u0;
-    mf_d4 c = {0.0, 0.0, 0.0, 0.0};
-    for (int kb = 0; kb < f.P0 / 16; ++kb)
-        c = mf_block<false, true>(a.z + f.zoff + (int64_t)ro * 16 * f.P0 + kb * 16, f.P0,
-                                  U0 + (int64_t)co * 16 * f.P0 + kb * 16, f.P0, c, 1.0);
+    const double* Z = a.z + f.zoff;
+    auto ga = [&](int i, int k0, double* v) { load4(Z + (int64_t)(ro * 16 + i) * f.P0 + k0, v); };
+    auto gb = [&](int k0, int j, double* v) { load4(U0 + (int64_t)(co * 16 + j) * f.P0 + k0, v); };
+    const mf_d4 c = fd2_product<double>(f.P0 / 16, ga, gb);
     const int l = threadIdx.x & (WAVE - 1);
-    const int i0 = co * 16 + (l & 15);
+    const int i0 = co * 16 + (l & 15), M0 = P.M[0], M1 = P.M[1], M2 = P.M[2];
+    double old[4] = {0.0, 0.0, 0.0, 0.0};
+    if (!SET) {   // the four old values loaded together (clamped to valid coefficients)
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+            const int o = ro * 16 + (l >> 4) + 4 * rr, i1 = min(o % f.P1, M1 - 1), i2 = min(o / f.P1, M2 - 1);
+            old[rr] = (double)x[P.voff + min(i0, M0 - 1) + (int64_t)M0 * (i1 + (int64_t)M1 * i2)];
+        }
+    }
 #pragma unroll
     for (int rr = 0; rr < 4; ++rr) {
         const int o = ro * 16 + (l >> 4) + 4 * rr, i1 = o % f.P1, i2 = o / f.P1;
-        if (i0 >= P.M[0] || i1 >= P.M[1] || i2 >= P.M[2]) continue;
-        const int64_t vi = P.voff + i0 + (int64_t)P.M[0] * (i1 + (int64_t)P.M[1] * i2);
+        if (i0 >= M0 || i1 >= M1 || i2 >= M2) continue;
+        const int64_t vi = P.voff + i0 + (int64_t)M0 * (i1 + (int64_t)M1 * i2);
         const bool m = masked(P, a.mode, i0, i1, i2);
         if (SET) x[vi] = m ? T(0) : T(f.tau * c[rr]);
-        else if (!m) x[vi] = T((double)x[vi] + f.tau * c[rr]);
+        else if (!m) x[vi] = T(old[rr] + f.tau * c[rr]);
     }
 }
 
