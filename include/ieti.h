@@ -108,9 +108,10 @@ typedef struct ieti_options {
     double  inner_tol;         /* local Neumann solves in F, d and recovery (default 1e-10) */
     double  basis_tol;         /* local solves building the primal basis (default 1e-12) */
     int32_t check_every;       /* inner iterations between host convergence checks (default 4) */
-    int32_t use_graph;         /* 1: the local solves' flexible-CG iterations replay one captured HIP graph
-                                  (per tolerance) between the host's convergence checks; 0: the same launches
-                                  one by one (default: the kernels keep the queue full, replay gains nothing) */
+    int32_t use_graph;         /* 1: the local solves' flexible-CG iterations replay captured HIP graphs (per
+                                  tolerance: check_every iterations between two host convergence checks, one
+                                  iteration for the rest); results bitwise equal to 0: the same launches one
+                                  by one (the default) */
     int32_t device;            /* HIP device ordinal, -1 = current (default) */
     void*   stream;            /* hipStream_t for all work, NULL = the library's own stream */
     size_t  hbm_budget;        /* bytes of device memory the handle may use, 0 = unlimited */

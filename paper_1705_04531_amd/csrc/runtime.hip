@@ -763,33 +763,43 @@ struct Solver : SolverBase {
         int next_check = std::max(1, hint - 1);
         int last_it = 0;
         // iterations after the first are the same launch sequence with the same arguments: with use_graph
-        // they replay one captured graph per tolerance (not while kernel events are recorded)
-        hipGraphExec_t* gx = nullptr;
+        // they replay captured graphs per tolerance (not while kernel events are recorded): one of check_every
+        // iterations for the stretches between two host checks, one of a single iteration for the rest
+        FcgGraphs* gx = nullptr;
         if (plan->opt.use_graph && graphs_ok && !prof.on && !noalloc_call) {
             auto& g = fcg_graphs[std::make_pair(tol, maxit)];
-            if (!g) g = capture_fcg_iteration(fuse_zq, tol, maxit);
-            if (g) gx = &g;
+            if (!g.one) g.one = capture_fcg_iterations(fuse_zq, tol, maxit, 1);
+            if (!g.run && every > 1) g.run = capture_fcg_iterations(fuse_zq, tol, maxit, every);
+            if (g.one) gx = &g;
         }
-        for (int it = 0; it < maxit; ++it) {
+        for (int it = 0; it < maxit;) {
             if (it == next_check) {
                 HIPCHECK(hipMemcpyAsync(h_nactive, nactive, sizeof(int), hipMemcpyDeviceToHost, stream));
                 sync();
                 if (*h_nactive == 0) break;
                 next_check = it + every;
             }
-            last_it = it + 1;
-            if (it > 0 && gx) {
-                HIPCHECK(hipGraphLaunch(*gx, stream));
+            if (it > 0 && gx && gx->run && it + every <= next_check && it + every <= maxit) {
+                HIPCHECK(hipGraphLaunch(gx->run, stream));
+                it += every;
+            } else if (it > 0 && gx) {
+                HIPCHECK(hipGraphLaunch(gx->one, stream));
+                ++it;
             } else {
                 fcg_iteration(it, fuse_zq, tol, maxit);
+                ++it;
             }
+            last_it = it;
         }
         hint = last_it;
     }
-    std::map<std::pair<double, int>, hipGraphExec_t> fcg_graphs;
+    struct FcgGraphs {
+        hipGraphExec_t one = nullptr, run = nullptr;
+    };
+    std::map<std::pair<double, int>, FcgGraphs> fcg_graphs;
     bool graphs_ok = true;   // cleared when the stream cannot be captured (e.g. the legacy null stream)
 
-    hipGraphExec_t capture_fcg_iteration(bool fuse_zq, double tol, int maxit) {
+    hipGraphExec_t capture_fcg_iterations(bool fuse_zq, double tol, int maxit, int count) {
         if (stream == nullptr) {
             graphs_ok = false;
             return nullptr;
@@ -801,7 +811,7 @@ struct Solver : SolverBase {
         }
         hipGraph_t graph = nullptr;
         try {
-            fcg_iteration(1, fuse_zq, tol, maxit);
+            for (int c = 0; c < count; ++c) fcg_iteration(1, fuse_zq, tol, maxit);
         } catch (...) {
             (void)hipStreamEndCapture(stream, &graph);
             if (graph) (void)hipGraphDestroy(graph);
@@ -1660,7 +1670,8 @@ struct Solver : SolverBase {
     }
     ~Solver() override {
         for (auto& g : fcg_graphs)
-            if (g.second) (void)hipGraphExecDestroy(g.second);
+            for (hipGraphExec_t ex : {g.second.one, g.second.run})
+                if (ex) (void)hipGraphExecDestroy(ex);
         for (void* p : {(void*)h_nactive, (void*)h_sc, (void*)h_done}) {
             if (!p) continue;
             if (arena.pool) arena.pool->put_host(p);

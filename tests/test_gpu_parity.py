@@ -128,16 +128,17 @@ def test_autotuned_smoother_matches_oracle(require_gpu):
     assert st["cheb_lower"] in (0.67, 1.0, 1.5) and st0["cheb_lower"] == 1.0
 
 
-def test_graph_replay_equals_direct_launches(require_gpu):
-    """Flexible-CG iterations replayed from a captured HIP graph give bitwise the
-    same result as the same launches sent one by one, over several solves on one
+@pytest.mark.parametrize("smoother", [0, 1], ids=["chebyshev", "tensor"])
+def test_graph_replay_equals_direct_launches(require_gpu, smoother):
+    """Flexible-CG iterations replayed from captured HIP graphs (runs of check_every iterations and single
+    ones) give bitwise the same result as the same launches sent one by one, over several solves on one
     handle (replays separated by the host's synchronisations and eager work)."""
     import torch
     from paper_1705_04531_amd import Solver, options_for
     wl = W.deformed_square((3, 3), 3, 24, seed=0, name="graph3x3")
     outs = {}
     for g in (0, 1):
-        s = Solver(wl.patches, options_for(wl, tol=1e-10, coarse_dofs=0, use_graph=g))
+        s = Solver(wl.patches, options_for(wl, tol=1e-10, coarse_dofs=0, use_graph=g, smoother=smoother))
         x = s.quadrature(device=False)
         f = torch.from_numpy(wl.f(x)).to("cuda")
         us = []
