@@ -279,8 +279,9 @@ def main():
     ap.add_argument("--serve", action="store_true", help="serving benchmark instead of the solve benchmark")
     ap.add_argument("--requests", type=int, default=512)
     ap.add_argument("--slots", type=int, default=8)
-    ap.add_argument("--local-solver", choices=["mg", "exact_mg", "mg_saddle"], default="mg",
-                    help="variant of the headline solver: mg (MG-MG, default), exact_mg (D-MG), mg_saddle (MG-MG-S)")
+    ap.add_argument("--local-solver", choices=["mg", "exact_mg", "mg_saddle", "exact"], default="mg",
+                    help="variant of the headline solver: mg (MG-MG, default), exact_mg (D-MG), mg_saddle (MG-MG-S), "
+                         "exact (the plain FP64 exact-local form D-D, for profiling its kernels)")
     ap.add_argument("--smoother", choices=["chebyshev", "tensor"], default="tensor",
                     help="finest-level smoother of the headline: tensor (the p-robust smoother of Sec. 4, default) or "
                          "chebyshev")
@@ -327,7 +328,7 @@ def main():
     wl = getattr(W, build_name)()
     tensor = args.smoother == "tensor"
     variant = {"mg": _abi.IETI_LOCAL_MG, "exact_mg": _abi.IETI_LOCAL_EXACT_MG,
-               "mg_saddle": _abi.IETI_LOCAL_MG_SADDLE}[args.local_solver]
+               "mg_saddle": _abi.IETI_LOCAL_MG_SADDLE, "exact": _abi.IETI_LOCAL_EXACT}[args.local_solver]
     extra_opt = {"smoother": _abi.IETI_SMOOTHER_TENSOR} if tensor else {}
     print(f"[bench] headline {wl.name}, MG precision {args.precision}, {args.local_solver}", file=sys.stderr,
           flush=True)
@@ -349,7 +350,7 @@ def main():
     kr = rate(dom) or {"achieved": 0.0, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": 0.0}
     roofline = {
         "bound": "hbm",
-        "kernel": (f"k_vcoarse<{mgt},false,0> (fused coarse levels of every patch, one work-group per patch; "
+        "kernel": (f"k_vcoarse<{mgt},false,{1 if wl.patches[0].dim == 3 else 0}> (fused coarse levels of every patch, one work-group per patch; "
                    f"events on the preconditioner's cycles, which run every patch)" if tensor else
                    f"k_stencil<{mgt},{mgt},{mgt},EPI_CHEB,FINE> (finest-level Chebyshev sweep, all degree "
                    f"classes in one launch)"),
