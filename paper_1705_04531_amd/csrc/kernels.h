@@ -1264,8 +1264,17 @@ __global__ __launch_bounds__(256) void k_pri_coarse(int64_t npi, const int64_t* 
     const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
     const int64_t r = (int64_t)blockIdx.x * WAVE + lane;
     double s = 0.0;
-    if (r < npi)
-        for (int64_t K = w; K < npi; K += 4) s += Sinv[K * npi + r] * sg[K];
+    if (r < npi) {   // the wave's terms in K order, their loads eight at a time (same sums as one at a time)
+        int64_t K = w;
+        for (; K + 28 < npi; K += 32) {
+            double a[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) a[u] = Sinv[(K + 4 * u) * npi + r];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s += a[u] * sg[K + 4 * u];
+        }
+        for (; K < npi; K += 4) s += Sinv[K * npi + r] * sg[K];
+    }
     part[w][lane] = s;
     __syncthreads();
     if (w == 0 && r < npi) upi[r] = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
@@ -1421,8 +1430,21 @@ __global__ __launch_bounds__(1024) void k_sum(const double* v, int64_t n, double
 // ------------------------------------------------------------------ outer CG on lambda (one work-group)
 
 __device__ double wg_dot(const double* a, const double* b, int64_t n, double* lds) {
+    // a thread's terms in index order, their loads eight strides at a time (same sums as one at a time)
     double acc = 0.0;
-    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) acc += a[i] * b[i];
+    const int64_t st = blockDim.x;
+    int64_t i = threadIdx.x;
+    for (; i + 7 * st < n; i += 8 * st) {
+        double av[8], bv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            av[u] = a[i + u * st];
+            bv[u] = b[i + u * st];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += av[u] * bv[u];
+    }
+    for (; i < n; i += st) acc += a[i] * b[i];
     for (int o = WAVE / 2; o > 0; o >>= 1) acc += __shfl_down(acc, o, WAVE);
     if ((threadIdx.x & (WAVE - 1)) == 0) lds[threadIdx.x / WAVE] = acc;
     __syncthreads();
@@ -1466,7 +1488,25 @@ __global__ __launch_bounds__(1024) void k_pcg(int stage, const int64_t* beg, con
         double alpha = sc[0] / pq;
         const bool brk = !(pq > 0.0);
         if (brk) alpha = 0.0;
-        for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+        // four strides per trip, loads before stores (the arrays may not alias, but the compiler cannot know)
+        const int64_t st = blockDim.x;
+        int64_t i = threadIdx.x;
+        for (; i + 3 * st < n; i += 4 * st) {
+            double lv[4], pv[4], rv[4], qv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                lv[u] = lam[i + u * st];
+                pv[u] = p[i + u * st];
+                rv[u] = r[i + u * st];
+                qv[u] = q[i + u * st];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                lam[i + u * st] = lv[u] + alpha * pv[u];
+                r[i + u * st] = rv[u] - alpha * qv[u];
+            }
+        }
+        for (; i < n; i += st) {
             lam[i] += alpha * p[i];
             r[i] -= alpha * q[i];
         }
@@ -1481,7 +1521,19 @@ __global__ __launch_bounds__(1024) void k_pcg(int stage, const int64_t* beg, con
     } else {
         const double rzn = wg_dot(r, z, n, lds);
         const double beta = rzn / sc[0];
-        for (int64_t i = threadIdx.x; i < n; i += blockDim.x) p[i] = z[i] + beta * p[i];
+        const int64_t st = blockDim.x;
+        int64_t i = threadIdx.x;
+        for (; i + 3 * st < n; i += 4 * st) {
+            double zv[4], pv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                zv[u] = z[i + u * st];
+                pv[u] = p[i + u * st];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) p[i + u * st] = zv[u] + beta * pv[u];
+        }
+        for (; i < n; i += st) p[i] = z[i] + beta * p[i];
         if (threadIdx.x == 0) {
             sc[2] = beta;
             sc[0] = rzn;
