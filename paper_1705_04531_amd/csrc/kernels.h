@@ -1454,44 +1454,109 @@ __device__ double wg_dot(const double* a, const double* b, int64_t n, double* ld
     return s;
 }
 
-// sc: [0] rz, [1] alpha, [2] beta, [3] |r|^2, [4] breakdown flag, [5] |d|^2 (scale), [6] pq
-// stage 0: rz = r.z, p = z            (start)
-// stage 1: pq = p.q; alpha = rz/pq; lam += alpha p; r -= alpha q; |r|^2
-// stage 2: rz' = r.z; beta = rz'/rz; p = z + beta p; rz = rz'
-// Outer CG of ncomp independent problems at once (one for ieti_solve, several for a serving batch): work-group
-// c runs the CG update of problem c on its multiplier range [beg[c], beg[c+1]) -- the same thread partition and
-// summation order as for a problem alone -- with its scalars in sc + 16 c.  Stages: 0 start (p = z, rz),
-// 1 step (alpha, lambda, r, |r|^2, breakdown flag), 2 direction (beta, p).  done[c] != 0: problem c has stopped;
-// stages 0 and 2 zero its search direction (so that F p holds no load from it) and stage 1 leaves it alone.
-__global__ __launch_bounds__(1024) void k_pcg(int stage, const int64_t* beg, const int* done, double* lam, double* r,
-                                              const double* z, double* p, const double* q, double* sc) {
-    __shared__ double lds[1024 / WAVE];
-    const int c = blockIdx.x;
-    const int64_t b = beg[c], n = beg[c + 1] - b;
-    lam += b;
-    r += b;
-    z += b;
-    p += b;
-    q += b;
+// Outer CG of ncomp independent problems at once (one for ieti_solve, several for a serving batch), with the
+// scalars of problem c in sc + 16 c: [0] rz, [1] alpha, [2] beta, [3] |r|^2, [4] breakdown flag, [5] |d|^2
+// (scale), [6] pq, [7] the new rz before it replaces [0].  Stages: 0 start (p = z, rz), 1 step (pq, alpha,
+// lambda += alpha p, r -= alpha q, |r|^2, breakdown flag), 2 direction (rz' = r.z, beta = rz'/rz,
+// p = z + beta p, rz = rz').
+// The stages run over several work-groups per problem (the outer CG on ~10^5 multipliers would be one CU's
+// stream in a single work-group).  Problem c's range is cut into nb_c = pcg_blocks(n_c) chunks (a function of its own size
+// only, so that a problem gives the same result alone and in a serving batch); work-group b of problem c
+// (grid PCG_NB x ncomp, blocks past nb_c return) takes chunk b.  Partial sums go to part[c PCG_NB + b] and
+// are added in chunk order, every time in the same order.
+//   k_pcg_part:  part = chunk sums of x.y   (stage 0: r.z, 1: p.q, 2: r.z)
+//   k_pcg_apply: s = sum of part, then stage 0: p = z, sc[0] = s; stage 1: alpha = sc[0]/s, lambda += alpha p,
+//                r -= alpha q, part2 = chunk sums of r.r, sc[1] alpha, sc[4] breakdown flag, sc[6] pq;
+//                stage 2: beta = s/sc[0], p = z + beta p, sc[2] beta, sc[7] = s
+//   k_pcg_fin:   stage 1: sc[3] = sum of part2; stage 2: sc[0] = sc[7]
+// done[c] != 0: problem c has stopped; stages 0 and 2 zero its search direction (so that F p holds no load
+// from it) and stage 1 leaves it alone.
+constexpr int PCG_NB = 64, PCG_THREADS = 256;
+__host__ __device__ inline int pcg_blocks(int64_t n) {
+    const int64_t b = (n + 2047) / 2048;
+    return (int)(b < 1 ? 1 : b > PCG_NB ? PCG_NB : b);
+}
+
+// chunk sum of x.y over [lo, hi) (terms of a thread in index order, loads four strides at a time), reduced over
+// the work-group in a fixed order; valid in every thread
+__device__ double chunk_dot(const double* x, const double* y, int64_t lo, int64_t hi, double* lds) {
+    double acc = 0.0;
+    const int64_t st = blockDim.x;
+    int64_t i = lo + threadIdx.x;
+    for (; i + 3 * st < hi; i += 4 * st) {
+        double a[4], b[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            a[u] = x[i + u * st];
+            b[u] = y[i + u * st];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc += a[u] * b[u];
+    }
+    for (; i < hi; i += st) acc += x[i] * y[i];
+    for (int o = WAVE / 2; o > 0; o >>= 1) acc += __shfl_down(acc, o, WAVE);
+    if ((threadIdx.x & (WAVE - 1)) == 0) lds[threadIdx.x / WAVE] = acc;
+    __syncthreads();
+    double s = 0.0;
+    for (int j = 0; j < (int)(blockDim.x / WAVE); ++j) s += lds[j];
+    __syncthreads();
+    return s;
+}
+
+__device__ __forceinline__ bool pcg_chunk(const int64_t* beg, int c, int b, int64_t& lo, int64_t& hi) {
+    const int64_t b0 = beg[c], n = beg[c + 1] - b0;
+    const int nb = pcg_blocks(n);
+    if (b >= nb) return false;
+    const int64_t ch = (n + nb - 1) / nb;
+    lo = b0 + b * ch;
+    hi = lo + ch < b0 + n ? lo + ch : b0 + n;
+    return true;
+}
+
+__global__ __launch_bounds__(PCG_THREADS) void k_pcg_part(int stage, const int64_t* beg, const int* done,
+                                                          const double* r, const double* z, const double* p,
+                                                          const double* q, double* part) {
+    __shared__ double lds[PCG_THREADS / WAVE];
+    const int c = blockIdx.y, b = blockIdx.x;
+    int64_t lo, hi;
+    if (!pcg_chunk(beg, c, b, lo, hi) || (done && done[c])) return;
+    const double s = stage == 1 ? chunk_dot(p, q, lo, hi, lds) : chunk_dot(r, z, lo, hi, lds);
+    if (threadIdx.x == 0) part[c * PCG_NB + b] = s;
+}
+
+__global__ __launch_bounds__(PCG_THREADS) void k_pcg_apply(int stage, const int64_t* beg, const int* done,
+                                                           double* lam, double* r, const double* z, double* p,
+                                                           const double* q, double* sc, const double* part,
+                                                           double* part2) {
+    __shared__ double lds[PCG_THREADS / WAVE];
+    __shared__ double s_sum;
+    const int c = blockIdx.y, b = blockIdx.x;
+    int64_t lo, hi;
+    if (!pcg_chunk(beg, c, b, lo, hi)) return;
+    const int64_t st = blockDim.x;
     sc += 16 * c;
     if (done && done[c]) {
         if (stage != 1)
-            for (int64_t i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0.0;
+            for (int64_t i = lo + threadIdx.x; i < hi; i += st) p[i] = 0.0;
         return;
     }
+    if (threadIdx.x == 0) {
+        const int nb = pcg_blocks(beg[c + 1] - beg[c]);
+        double t = 0.0;
+        for (int j = 0; j < nb; ++j) t += part[c * PCG_NB + j];
+        s_sum = t;
+    }
+    __syncthreads();
+    const double s = s_sum;
     if (stage == 0) {
-        const double rz = wg_dot(r, z, n, lds);
-        for (int64_t i = threadIdx.x; i < n; i += blockDim.x) p[i] = z[i];
-        if (threadIdx.x == 0) sc[0] = rz;
+        for (int64_t i = lo + threadIdx.x; i < hi; i += st) p[i] = z[i];
+        if (b == 0 && threadIdx.x == 0) sc[0] = s;
     } else if (stage == 1) {
-        const double pq = wg_dot(p, q, n, lds);
-        double alpha = sc[0] / pq;
-        const bool brk = !(pq > 0.0);
+        double alpha = sc[0] / s;
+        const bool brk = !(s > 0.0);
         if (brk) alpha = 0.0;
-        // four strides per trip, loads before stores (the arrays may not alias, but the compiler cannot know)
-        const int64_t st = blockDim.x;
-        int64_t i = threadIdx.x;
-        for (; i + 3 * st < n; i += 4 * st) {
+        int64_t i = lo + threadIdx.x;
+        for (; i + 3 * st < hi; i += 4 * st) {
             double lv[4], pv[4], rv[4], qv[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
@@ -1506,24 +1571,24 @@ __global__ __launch_bounds__(1024) void k_pcg(int stage, const int64_t* beg, con
                 r[i + u * st] = rv[u] - alpha * qv[u];
             }
         }
-        for (; i < n; i += st) {
+        for (; i < hi; i += st) {
             lam[i] += alpha * p[i];
             r[i] -= alpha * q[i];
         }
         __syncthreads();
-        const double rr = wg_dot(r, r, n, lds);
+        const double rr = chunk_dot(r, r, lo, hi, lds);
         if (threadIdx.x == 0) {
-            sc[1] = alpha;
-            sc[3] = rr;
-            sc[4] = brk ? 1.0 : 0.0;
-            sc[6] = pq;
+            part2[c * PCG_NB + b] = rr;
+            if (b == 0) {
+                sc[1] = alpha;
+                sc[4] = brk ? 1.0 : 0.0;
+                sc[6] = s;
+            }
         }
     } else {
-        const double rzn = wg_dot(r, z, n, lds);
-        const double beta = rzn / sc[0];
-        const int64_t st = blockDim.x;
-        int64_t i = threadIdx.x;
-        for (; i + 3 * st < n; i += 4 * st) {
+        const double beta = s / sc[0];
+        int64_t i = lo + threadIdx.x;
+        for (; i + 3 * st < hi; i += 4 * st) {
             double zv[4], pv[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
@@ -1533,11 +1598,24 @@ __global__ __launch_bounds__(1024) void k_pcg(int stage, const int64_t* beg, con
 #pragma unroll
             for (int u = 0; u < 4; ++u) p[i + u * st] = zv[u] + beta * pv[u];
         }
-        for (; i < n; i += st) p[i] = z[i] + beta * p[i];
-        if (threadIdx.x == 0) {
+        for (; i < hi; i += st) p[i] = z[i] + beta * p[i];
+        if (b == 0 && threadIdx.x == 0) {
             sc[2] = beta;
-            sc[0] = rzn;
+            sc[7] = s;
         }
+    }
+}
+
+__global__ void k_pcg_fin(int stage, const int64_t* beg, const int* done, double* sc, const double* part2, int nc) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nc || (done && done[c])) return;
+    if (stage == 1) {
+        const int nb = pcg_blocks(beg[c + 1] - beg[c]);
+        double t = 0.0;
+        for (int j = 0; j < nb; ++j) t += part2[c * PCG_NB + j];
+        sc[16 * c + 3] = t;
+    } else {
+        sc[16 * c + 0] = sc[16 * c + 7];
     }
 }
 

@@ -442,6 +442,7 @@ struct Solver : SolverBase {
     // lambda space
     double *lam = nullptr, *lr = nullptr, *lz = nullptr, *lp = nullptr, *lq = nullptr, *ltmp = nullptr;
     double* sc = nullptr;
+    double* pcgp = nullptr;   // the multi-work-group outer CG's partial sums: 2 PCG_NB per problem
     double* h_sc = nullptr;    // pinned
     // exact local solves (banded Cholesky factors, blocked triangular solves): Neumann problems
     // (exact), also the preconditioner's Dirichlet problems (prec_exact)
@@ -1580,7 +1581,7 @@ struct Solver : SolverBase {
     // carved from one block (offsets in doubles, 256-byte aligned; int arrays take half a word per entry).
     bool noalloc_call = false;   // graphs and kernel events stay off (instantiation and event pools allocate)
     struct ScratchMap {
-        int64_t partial, sc, bb, dq, beta, alpha, active, its, brk, nactive, bsc, dpart, words;
+        int64_t partial, sc, pcgp, bb, dq, beta, alpha, active, its, brk, nactive, bsc, dpart, words;
     };
     ScratchMap scratch_map() const {
         ScratchMap m{};
@@ -1592,6 +1593,7 @@ struct Solver : SolverBase {
         };
         m.partial = take(4 * (int64_t)lev[0].nt_all + 4);
         m.sc = take(16 * (int64_t)ncomp);
+        m.pcgp = take(2 * (int64_t)PCG_NB * ncomp);
         m.bb = take(N);
         m.dq = take(N);
         m.beta = take(N);
@@ -1614,18 +1616,19 @@ struct Solver : SolverBase {
                                           std::to_string((uint64_t)IETI_NOALLOC_SCRATCH_BYTES));
         if (!noalloc_base) throw Error(IETI_EDEVICE, "internal: address of the static scratch not resolved");
         double* base = noalloc_base;
-        double* const keep_d[] = {partial, sc, bb, dq, beta, alpha, bsc, dpart};
+        double* const keep_d[] = {partial, sc, bb, dq, beta, alpha, bsc, dpart, pcgp};
         int* const keep_i[] = {active, its, brk, nactive};
         const bool prof_on = prof.on;
         auto restore = [&] {
             partial = keep_d[0], sc = keep_d[1], bb = keep_d[2], dq = keep_d[3];
-            beta = keep_d[4], alpha = keep_d[5], bsc = keep_d[6], dpart = keep_d[7];
+            beta = keep_d[4], alpha = keep_d[5], bsc = keep_d[6], dpart = keep_d[7], pcgp = keep_d[8];
             active = keep_i[0], its = keep_i[1], brk = keep_i[2], nactive = keep_i[3];
             prof.on = prof_on;
             noalloc_call = false;
         };
         partial = base + m.partial;
         sc = base + m.sc;
+        pcgp = base + m.pcgp;
         bb = base + m.bb;
         dq = base + m.dq;
         beta = base + m.beta;
@@ -1652,6 +1655,20 @@ struct Solver : SolverBase {
         }
         restore();
         return rc;
+    }
+    // one stage of the outer CG of every problem (k_pcg_part, k_pcg_apply, k_pcg_fin over PCG_NB work-groups per problem)
+    void pcg_stage(int stage, double* lam, double* lr, const double* lz, double* lp, const double* lq) {
+        const dim3 g(PCG_NB, ncomp);
+        hipLaunchKernelGGL(k_pcg_part, g, dim3(PCG_THREADS), 0, stream, stage, comp_lam, done_dev, lr, lz, lp, lq,
+                           pcgp);
+        check_launch();
+        hipLaunchKernelGGL(k_pcg_apply, g, dim3(PCG_THREADS), 0, stream, stage, comp_lam, done_dev, lam, lr, lz, lp,
+                           lq, sc, pcgp, pcgp + (int64_t)PCG_NB * ncomp);
+        check_launch();
+        if (stage == 0) return;
+        hipLaunchKernelGGL(k_pcg_fin, dim3(nblk(ncomp, 64)), dim3(64), 0, stream, stage, comp_lam, done_dev, sc,
+                           pcgp + (int64_t)PCG_NB * ncomp, ncomp);
+        check_launch();
     }
     void setup() override;
     int solve(const double* f_qp, double* u, ieti_stats* st) override;
@@ -2211,6 +2228,7 @@ void Solver<T>::setup() {
     lq = arena.alloc<double>(nl, st);
     ltmp = arena.alloc<double>(nl, st);
     sc = arena.alloc<double>(16 * (int64_t)ncomp, st);
+    pcgp = arena.alloc<double>(2 * (int64_t)PCG_NB * ncomp, st);
     // ---- load-vector tables
     {
         std::vector<PatchQ> pq(N);
@@ -2494,13 +2512,10 @@ int Solver<T>::solve(const double* f_qp, double* u_out, ieti_stats* stp) {
     if (nl > 0 && active_left()) {
         HIPCHECK(hipMemcpyAsync(done_dev, h_done, nc * sizeof(int), hipMemcpyHostToDevice, stream));
         applyPrec(lr, lz);
-        hipLaunchKernelGGL(k_pcg, dim3(nc), dim3(1024), 0, stream, 0, comp_lam, done_dev, lam, lr, lz, lp, lq, sc);
-        check_launch();
+        pcg_stage(0, lam, lr, lz, lp, lq);
         while (it < pl.opt.max_it) {
             applyF(lp, lq);
-            hipLaunchKernelGGL(k_pcg, dim3(nc), dim3(1024), 0, stream, 1, comp_lam, done_dev, lam, lr, lz, lp, lq,
-                               sc);
-            check_launch();
+            pcg_stage(1, lam, lr, lz, lp, lq);
             HIPCHECK(hipMemcpyAsync(h_sc, sc, 16 * (size_t)nc * sizeof(double), hipMemcpyDeviceToHost, stream));
             sync();
             ++it;
@@ -2524,9 +2539,7 @@ int Solver<T>::solve(const double* f_qp, double* u_out, ieti_stats* stp) {
             if (!active_left()) break;
             HIPCHECK(hipMemcpyAsync(done_dev, h_done, nc * sizeof(int), hipMemcpyHostToDevice, stream));
             applyPrec(lr, lz);
-            hipLaunchKernelGGL(k_pcg, dim3(nc), dim3(1024), 0, stream, 2, comp_lam, done_dev, lam, lr, lz, lp, lq,
-                               sc);
-            check_launch();
+            pcg_stage(2, lam, lr, lz, lp, lq);
         }
     }
     sync();
