@@ -99,7 +99,7 @@ typedef struct ieti_options {
     int32_t primal;            /* IETI_PRIMAL_VERTICES (default), IETI_PRIMAL_VERTICES|IETI_PRIMAL_EDGES or
                                   IETI_PRIMAL_EDGES */
     int32_t cheb_degree;       /* Chebyshev smoother degree per smoothing phase; 0 = tuned per dimension and spline degree */
-    int32_t cheb_degree_coarse;/* the same on the coarser multigrid levels; 0 = tuned per spline degree */
+    int32_t cheb_degree_coarse;/* the same on the coarser multigrid levels; 0 = the table: 2, or 1 under the tensor smoother */
     double  cheb_lower;        /* lower end of the smoothing interval as a fraction of lambda_max; 0 = tuned */
     int32_t prec_vcycles;      /* V-cycles for the Dirichlet problems in the preconditioner (default 2) */
     int32_t max_it;            /* outer CG iteration limit (default 300) */
