@@ -382,6 +382,7 @@ def main():
                         f"multigrid, FP64 outer CG to 1e-8",
             "ndof_torn": wl.ndof_torn,
             "ndof_global": wl.ndof_global,
+            "global_MDoF_per_s": round(wl.ndof_global / (ms_per_step * 1e-3) / 1e6, 3),
             "n_lambda": st["n_lambda"],
             "n_primal": st["n_primal"],
             "outer_iterations": st["outer_iterations"],
