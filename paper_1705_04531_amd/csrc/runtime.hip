@@ -589,6 +589,18 @@ struct Solver : SolverBase {
         // 2D: four block products (W, Z, T, then the update of x), the blocks of all patches in each grid
         FdArgs a{lev[0].L, fd_info[mode], fd_U, fd_lam, fd_z, act, mode, N, fd_z2, fd_U32, fd_z32, fd_z232};
         const dim3 g((fd_tiles2 + FD2_THREADS / WAVE - 1) / (FD2_THREADS / WAVE), N), b(FD2_THREADS);
+        if (fd_p1max <= FD2C_MAXP) {   // the products fused in pairs per column block (intermediate in LDS)
+            const dim3 gc(fd_p0max / 16, N);
+            const size_t lds = (size_t)fd_p1max * FD2C_LD * sizeof(T);
+            hipLaunchKernelGGL(k_fd2_fwd<T>, gc, b, lds, stream, a, r);
+            check_launch();
+            if (set)
+                hipLaunchKernelGGL((k_fd2_bwd<T, true>), gc, b, lds, stream, a, x);
+            else
+                hipLaunchKernelGGL((k_fd2_bwd<T, false>), gc, b, lds, stream, a, x);
+            check_launch();
+            return;
+        }
         hipLaunchKernelGGL(k_fd2_w<T>, g, b, 0, stream, a, r);
         check_launch();
         hipLaunchKernelGGL(k_fd2_z<T>, g, b, 0, stream, a);
@@ -1028,9 +1040,9 @@ struct Solver : SolverBase {
         const double U = P0 * P0 + P1 * P1 + (dim == 3 ? P2 * P2 : 0.0);
         const double lam = 8.0 * (P0 + P1 + (dim == 3 ? P2 : 0.0));
         const double xio = set ? n * s : 2.0 * n * s;
-        // 2D: W = m R U_0, Z = U_1^T W (scaled), T = Z U_0^T, x (+)= U_1 T: each U twice, the three
-        // intermediates written once and read once
-        if (dim == 2) return n * s + 2.0 * U * su + 6.0 * PP * su + lam + xio;
+        // 2D: W = m R U_0, Z = U_1^T W (scaled), T = Z U_0^T, x (+)= U_1 T: each U twice, Z written once and
+        // read once (W and T too where the products are not fused in pairs)
+        if (dim == 2) return n * s + 2.0 * U * su + (fd_p1max <= FD2C_MAXP ? 2.0 : 6.0) * PP * su + lam + xio;
         // 3D: r -> z (axis 0), four middle contractions, z -> x (axis 0)
         return (n * s + P0 * P0 * 8.0 + PP * 8.0) + 4.0 * (2.0 * PP * 8.0) + (P1 * P1 + P2 * P2) * 2.0 * 8.0 + lam +
                (PP * 8.0 + P0 * P0 * 8.0 + xio);

@@ -267,6 +267,137 @@ __global__ __launch_bounds__(FD2_THREADS) void k_fd2_y(FdArgs a, T* __restrict__
     }
 }
 
+// The same four products fused in pairs per column block: one work-group per (patch, 16-wide column block
+// bj) computes the intermediate column block (W[:, bj] = m R U_0[:, bj], or T[:, bj] = Z U_0[bj, :]^T) into
+// LDS, one 16 x 16 block per wave and pass, then the final column block from it (Z[:, bj] = U_1^T W[:, bj]
+// scaled, or the update of x with U_1 T[:, bj]).  Each block's sums run in the K order of the unfused
+// kernels, so the results are the same; the intermediates never go to memory and two launches are saved.
+// Grid: (largest P0 / 16, N) work-groups of FD2_THREADS, dynamic LDS of (largest P1) x FD2C_LD words; used while
+// the largest P1 is at most FD2C_MAXP (the unfused kernels above otherwise).
+constexpr int FD2C_LD = 17;     // LDS row length of an intermediate column block (P1 x 16, one word of padding)
+constexpr int FD2C_MAXP = 256;
+
+__device__ __forceinline__ bool fd2_colblock(const FdArgs& a, int& k, FdInfo& f, int& bj) {
+    k = blockIdx.y;
+    f = a.info[k];
+    if (f.P0 == 0 || (a.active && !a.active[k])) return false;
+    bj = blockIdx.x;
+    return bj < f.P0 / 16;
+}
+
+// forward: Z[:, bj] = (U_1^T (m R U_0)[:, bj]) ./ (lambda_1 + lambda_0 + c) into the scratch
+template <typename T>
+__global__ __launch_bounds__(FD2_THREADS) void k_fd2_fwd(FdArgs a, const T* __restrict__ r) {
+    typedef T CT;
+    extern __shared__ double fd2c_sm[];
+    CT* Wl = (CT*)fd2c_sm;
+    int k, bj;
+    FdInfo f;
+    if (!fd2_colblock(a, k, f, bj)) return;
+    const PatchLev& P = a.L[k];
+    const int M0 = P.M[0], M1 = P.M[1], P0 = f.P0, P1 = f.P1, nb1 = P1 / 16, mode = a.mode;
+    const CT* U0 = fd_u<CT>(a) + f.u0;
+    const CT* U1 = fd_u<CT>(a) + f.u1;
+    const uint32_t mb = P.mbits[mode];
+    const int wv = threadIdx.x / WAVE, l = threadIdx.x & (WAVE - 1);
+    for (int bi = wv; bi < nb1; bi += FD2_THREADS / WAVE) {
+        auto ga = [&](int i, int k0, CT* v) {
+            const int i1 = bi * 16 + i;
+            const T* row = r + P.voff + (int64_t)M0 * min(i1, M1 - 1);
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int kk = k0 + s;
+                const CT x = (CT)row[min(kk, M0 - 1)];
+                const bool keep = (kk < M0) & (i1 < M1) & !masked_nb(mb, 2, M0, M1, 1, kk, i1, 0);
+                v[s] = keep ? x : CT(0);
+            }
+        };
+        auto gb = [&](int k0, int j, CT* v) {
+#pragma unroll
+            for (int s = 0; s < 4; ++s) v[s] = U0[(int64_t)(k0 + s) * P0 + bj * 16 + j];
+        };
+        const auto c = fd2_product<CT>(P0 / 16, ga, gb);
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) Wl[(bi * 16 + FdMf<CT>::row(l, rr)) * FD2C_LD + (l & 15)] = c[rr];
+    }
+    __syncthreads();
+    CT* z = fd_scr<CT>(a, false) + f.zoff;
+    const double* l0 = a.lam + f.l0;
+    const double* l1 = a.lam + f.l1;
+    const int a0 = bj * 16 + (l & 15);
+    for (int bi = wv; bi < nb1; bi += FD2_THREADS / WAVE) {
+        auto ga = [&](int i, int k0, CT* v) {
+#pragma unroll
+            for (int s = 0; s < 4; ++s) v[s] = U1[(int64_t)(k0 + s) * P1 + bi * 16 + i];
+        };
+        auto gb = [&](int k0, int j, CT* v) {
+#pragma unroll
+            for (int s = 0; s < 4; ++s) v[s] = Wl[(k0 + s) * FD2C_LD + j];
+        };
+        const auto c = fd2_product<CT>(nb1, ga, gb);
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+            const int bb = bi * 16 + FdMf<CT>::row(l, rr);
+            z[(int64_t)bb * P0 + a0] = (CT)((double)c[rr] / (l1[bb] + l0[a0] + f.shift));
+        }
+    }
+}
+
+// backward: x[:, bj] (+)= tau m (U_1 (Z U_0^T)[:, bj]) on the M1 x M0 coefficients (SET: x = tau y, masked
+// coefficients 0); column blocks past M0 are skipped
+template <typename T, bool SET>
+__global__ __launch_bounds__(FD2_THREADS) void k_fd2_bwd(FdArgs a, T* __restrict__ x) {
+    typedef T CT;
+    extern __shared__ double fd2c_sm[];
+    CT* Tl = (CT*)fd2c_sm;
+    int k, bj;
+    FdInfo f;
+    if (!fd2_colblock(a, k, f, bj)) return;
+    const PatchLev& P = a.L[k];
+    const int M0 = P.M[0], M1 = P.M[1], P0 = f.P0, P1 = f.P1, nb1 = P1 / 16;
+    if (bj * 16 >= M0) return;
+    const CT* U0 = fd_u<CT>(a) + f.u0;
+    const CT* U1 = fd_u<CT>(a) + f.u1;
+    const CT* Z = fd_scr<CT>(a, false) + f.zoff;
+    const int wv = threadIdx.x / WAVE, l = threadIdx.x & (WAVE - 1);
+    for (int bi = wv; bi < nb1; bi += FD2_THREADS / WAVE) {
+        auto ga = [&](int i, int k0, CT* v) { load4(Z + (int64_t)(bi * 16 + i) * P0 + k0, v); };
+        auto gb = [&](int k0, int j, CT* v) { load4(U0 + (int64_t)(bj * 16 + j) * P0 + k0, v); };
+        const auto c = fd2_product<CT>(P0 / 16, ga, gb);
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) Tl[(bi * 16 + FdMf<CT>::row(l, rr)) * FD2C_LD + (l & 15)] = c[rr];
+    }
+    __syncthreads();
+    const int i0 = bj * 16 + (l & 15);
+    for (int bi = wv; bi < nb1; bi += FD2_THREADS / WAVE) {
+        if (bi * 16 >= M1) break;
+        auto ga = [&](int i, int k0, CT* v) { load4(U1 + (int64_t)(bi * 16 + i) * P1 + k0, v); };
+        auto gb = [&](int k0, int j, CT* v) {
+#pragma unroll
+            for (int s = 0; s < 4; ++s) v[s] = Tl[(k0 + s) * FD2C_LD + j];
+        };
+        const auto c = fd2_product<CT>(nb1, ga, gb);
+        double old[4] = {0.0, 0.0, 0.0, 0.0};
+        if (!SET) {
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) {
+                const int i1 = min(bi * 16 + FdMf<CT>::row(l, rr), M1 - 1);
+                old[rr] = (double)x[P.voff + min(i0, M0 - 1) + (int64_t)M0 * i1];
+            }
+        }
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+            const int i1 = bi * 16 + FdMf<CT>::row(l, rr);
+            if (i0 >= M0 || i1 >= M1) continue;
+            const double v = c[rr];
+            const int64_t vi = P.voff + i0 + (int64_t)M0 * i1;
+            const bool m = masked(P, a.mode, i0, i1, 0);
+            if (SET) x[vi] = m ? T(0) : T(f.tau * v);
+            else if (!m) x[vi] = T(old[rr] + f.tau * v);
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // 3D: the transforms as three contractions along one axis each, on padded P2 x P1 x P0 arrays (index
 // a + P0 (b + P1 c)) in the two scratch buffers:

@@ -194,13 +194,15 @@ def test_tensor_smoother_matches_oracle(require_gpu, name, make, variant, solver
     assert st["cheb_degree"] == 0
 
 
+@pytest.mark.parametrize("n1", [132, 260], ids=["fused", "unfused"])
 @pytest.mark.parametrize("prec", [64, 32])
-def test_tensor_smoother_wide_patches(require_gpu, prec):
+def test_tensor_smoother_wide_patches(require_gpu, prec, n1):
     """2D patches with more than 128 coefficients per direction (2x1 deformed square, p = 4, 136 and 128
-    elements: 140 and 132 coefficients, padded to 144): the tensor smoother's block products have no size
-    limit in 2D, and the solve still matches the oracle."""
+    elements along x: 140 and 132 coefficients, padded to 144; along y 136 coefficients (the products fused
+    in pairs per column block) or 264, padded to 272 (above the fused kernels' limit, the four separate
+    products): the tensor smoother has no size limit in 2D, and the solve still matches the oracle."""
     from paper_1705_04531_amd import _abi
-    wl = W.deformed_square((2, 1), 4, [[136, 128], [132]], amp_factor=0.8, name="wide2x1_p4")
+    wl = W.deformed_square((2, 1), 4, [[136, 128], [n1]], amp_factor=0.8, name="wide2x1_p4")
     u_ref, lay, _ = oracle_solution(wl)
     u, st = run_gpu(wl, local_solver=0, mg_precision=prec, tol=1e-10, smoother=_abi.IETI_SMOOTHER_TENSOR)
     err = rel_err(wl, u, u_ref, lay)
