@@ -403,7 +403,7 @@ struct Solver : SolverBase {
     FdInfo* fd_info[2] = {nullptr, nullptr};
     double *fd_U = nullptr, *fd_lam = nullptr, *fd_z = nullptr, *fd_z2 = nullptr;
     float *fd_U32 = nullptr, *fd_z32 = nullptr, *fd_z232 = nullptr;   // 2D with FP32 V-cycles: FP32 copies
-    int fd_p0max = 0, fd_p1max = 0, fd_tiles2 = 0, fd_tiles3 = 0;
+    int fd_p0max = 0, fd_p1max = 0, fd_p2max = 0, fd_tiles2 = 0, fd_tiles3 = 0;
     // level 0 FP64
     double* coef64 = nullptr;
     int64_t len0 = 0;
@@ -571,18 +571,18 @@ struct Solver : SolverBase {
         if (dim == 3) {   // six axis contractions through the two scratch buffers
             FdArgs a{lev[0].L, fd_info[mode], fd_U, fd_lam, fd_z, act, mode, N, fd_z2, nullptr, nullptr, nullptr};
             const dim3 g((fd_tiles3 + FD3_THREADS / WAVE - 1) / (FD3_THREADS / WAVE), N), b(FD3_THREADS);
-            hipLaunchKernelGGL(k_fd3_ax0_fwd<T>, g, b, 0, stream, a, r);
-            check_launch();
-            hipLaunchKernelGGL((k_fd3_axn<1, true, false>), g, b, 0, stream, a, (const double*)fd_z, fd_z2);
+            // axes 0 and 1 fused per plane and column block (intermediate column in LDS), axis 2 on its own
+            const int ncb = fd_p0max / 16;
+            const dim3 gp(ncb * fd_p2max, N);
+            const size_t lds = (size_t)fd_p1max * FD2C_LD * sizeof(double);
+            hipLaunchKernelGGL(k_fd3_fwd01<T>, gp, b, lds, stream, a, r, ncb);
             check_launch();
             hipLaunchKernelGGL((k_fd3_axn<2, true, true>), g, b, 0, stream, a, (const double*)fd_z2, fd_z);
             check_launch();
             hipLaunchKernelGGL((k_fd3_axn<2, false, false>), g, b, 0, stream, a, (const double*)fd_z, fd_z2);
             check_launch();
-            hipLaunchKernelGGL((k_fd3_axn<1, false, false>), g, b, 0, stream, a, (const double*)fd_z2, fd_z);
-            check_launch();
-            if (set) hipLaunchKernelGGL((k_fd3_ax0_bwd<T, true>), g, b, 0, stream, a, x);
-            else hipLaunchKernelGGL((k_fd3_ax0_bwd<T, false>), g, b, 0, stream, a, x);
+            if (set) hipLaunchKernelGGL((k_fd3_bwd10<T, true>), gp, b, lds, stream, a, x, ncb);
+            else hipLaunchKernelGGL((k_fd3_bwd10<T, false>), gp, b, lds, stream, a, x, ncb);
             check_launch();
             return;
         }
@@ -1043,9 +1043,9 @@ struct Solver : SolverBase {
         // 2D: W = m R U_0, Z = U_1^T W (scaled), T = Z U_0^T, x (+)= U_1 T: each U twice, Z written once and
         // read once (W and T too where the products are not fused in pairs)
         if (dim == 2) return n * s + 2.0 * U * su + (fd_p1max <= FD2C_MAXP ? 2.0 : 6.0) * PP * su + lam + xio;
-        // 3D: r -> z (axis 0), four middle contractions, z -> x (axis 0)
-        return (n * s + P0 * P0 * 8.0 + PP * 8.0) + 4.0 * (2.0 * PP * 8.0) + (P1 * P1 + P2 * P2) * 2.0 * 8.0 + lam +
-               (PP * 8.0 + P0 * P0 * 8.0 + xio);
+        // 3D: r -> zb (axes 0 and 1 fused), zb -> za (axis 2, scaled), za -> zb (axis 2), zb -> x (axes 1 and 0
+        // fused): each U twice, the padded array written and read three times
+        return n * s + 2.0 * U * 8.0 + 6.0 * PP * 8.0 + lam + xio;
     }
     double vcycle_bytes(int k, int mode) const {
         const Patch& pa = plan->patches[k];
@@ -2049,6 +2049,7 @@ void Solver<T>::setup() {
                 zk = std::max(zk, (int64_t)f.P0 * f.P1 * (dim == 3 ? f.P2 : 1));
                 fd_p0max = std::max(fd_p0max, f.P0);
                 fd_p1max = std::max(fd_p1max, f.P1);
+                fd_p2max = std::max(fd_p2max, f.P2);
             }
             zlen += zk;
         }

@@ -399,13 +399,13 @@ __global__ __launch_bounds__(FD2_THREADS) void k_fd2_bwd(FdArgs a, T* __restrict
 }
 
 // ---------------------------------------------------------------------------
-// 3D: the transforms as three contractions along one axis each, on padded P2 x P1 x P0 arrays (index
+// 3D: the transforms as contractions along one axis each, on padded P2 x P1 x P0 arrays (index
 // a + P0 (b + P1 c)) in the two scratch buffers:
-//   forward   za = R x_0 U_0,  zb = za x_1 U_1,  za = (zb x_2 U_2) ./ (lambda_0 + lambda_1 + lambda_2 + c)
-//   backward  zb = za x_2 U_2^T,  za = zb x_1 U_1^T,  x (+)= tau (za x_0 U_0^T) on unmasked coefficients
-// (x_d U: contraction of the axis-d index i with U[i][.]).  One wave per 16 x 16 output tile, FD3_THREADS / 64
-// tiles per work-group, the contraction (P_d <= 128) read straight from memory; every entry of the padded
-// arrays is written (padding rows and columns come out zero), so no scratch needs clearing.
+//   forward   zb = (R x_0 U_0) x_1 U_1 (k_fd3_fwd01),  za = (zb x_2 U_2) ./ (lambda_0 + lambda_1 + lambda_2 + c)
+//   backward  zb = za x_2 U_2^T,  x (+)= tau ((zb x_0 U_0^T) x_1 U_1^T) on unmasked coefficients (k_fd3_bwd10)
+// (x_d U: contraction of the axis-d index i with U[i][.]).  Axis 2: one wave per 16 x 16 output tile,
+// FD3_THREADS / 64 tiles per work-group, the contraction (P_d <= 128) read straight from memory; every entry
+// of the padded arrays is written (padding rows and columns come out zero), so no scratch needs clearing.
 
 constexpr int FD3_THREADS = 256;
 
@@ -417,41 +417,6 @@ __device__ __forceinline__ bool fd3_tile(const FdArgs& a, int& k, FdInfo& f, int
     if (f.P0 == 0 || (a.active && !a.active[k])) return false;
     t = blockIdx.x * (FD3_THREADS / WAVE) + threadIdx.x / WAVE;
     return t < (f.P0 / 16) * (f.P1 / 16) * (f.P2 / 16) * 16;
-}
-
-// forward axis 0: za[o][a] = sum_i0 m r[o][i0] U_0[i0][a], o = i1 + P1 i2
-template <typename T>
-__global__ __launch_bounds__(FD3_THREADS) void k_fd3_ax0_fwd(FdArgs a, const T* __restrict__ r) {
-    int k, t;
-    FdInfo f;
-    if (!fd3_tile(a, k, f, t)) return;
-    const PatchLev& P = a.L[k];
-    const int nco = f.P0 / 16, ro = t / nco, co = t % nco;
-    const int l = threadIdx.x & (WAVE - 1);
-    const int M0 = P.M[0], M1 = P.M[1], M2 = P.M[2], P0 = f.P0, P1 = f.P1;
-    const uint32_t mb = P.mbits[a.mode];
-    const double* U0 = a.U + f.u0;
-    auto ga = [&](int i, int k0, double* v) {
-        const int o = ro * 16 + i, i1 = o % P1, i2 = o / P1;
-        const bool rowok = (i1 < M1) & (i2 < M2);
-        const T* row = r + P.voff + (int64_t)M0 * (min(i1, M1 - 1) + (int64_t)M1 * min(i2, M2 - 1));
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const int i0 = k0 + s;
-            const double x = (double)row[min(i0, M0 - 1)];
-            v[s] = (rowok & (i0 < M0) & !masked_nb(mb, 3, M0, M1, M2, i0, i1, i2)) ? x : 0.0;
-        }
-    };
-    auto gb = [&](int k0, int j, double* v) {
-#pragma unroll
-        for (int s = 0; s < 4; ++s) v[s] = U0[(int64_t)(k0 + s) * P0 + co * 16 + j];
-    };
-    const mf_d4 c = fd2_product<double>(P0 / 16, ga, gb);
-#pragma unroll
-    for (int rr = 0; rr < 4; ++rr) {
-        const int orow = ro * 16 + (l >> 4) + 4 * rr;
-        a.z[f.zoff + (int64_t)orow * f.P0 + co * 16 + (l & 15)] = c[rr];
-    }
 }
 
 // axis AX (1 or 2) viewed as [outer][P_AX][inner]: FWD out[o][c][n] = sum_i U[i][c] in[o][i][n],
@@ -494,37 +459,119 @@ __global__ __launch_bounds__(FD3_THREADS) void k_fd3_axn(FdArgs a, const double*
     }
 }
 
-// backward axis 0: y[o][i0] = sum_a za[o][a] U_0[i0][a]; SET: x = tau y (masked 0), else x += tau y
-template <typename T, bool SET>
-__global__ __launch_bounds__(FD3_THREADS) void k_fd3_ax0_bwd(FdArgs a, T* __restrict__ x) {
-    int k, t;
+// Axes 0 and 1 fused per (patch, plane c, 16-wide column block bj), the 2D pairing applied to one plane:
+//   forward   zb[c][:, bj] = U_1^T (m R_c U_0)[:, bj]      (into the second scratch, unscaled; axis 2 follows)
+//   backward  x_c[:, bj] (+)= tau m (U_1 (zb_c U_0^T)[:, bj])   (zb from the second scratch, after axis 2)
+// The intermediate column block in LDS (P1 x FD2C_LD words), one 16 x 16 block per wave.  Grid:
+// (largest P0 / 16 x largest P2, N) work-groups of FD3_THREADS; the backward pass multiplies in the order
+// U_1 (zb U_0^T) rather than (U_1 zb) U_0^T of the separate contractions (equal up to rounding).
+__device__ __forceinline__ bool fd3_plane_block(const FdArgs& a, int ncbmax, int& k, FdInfo& f, int& c, int& bj) {
+    k = blockIdx.y;
+    f = a.info[k];
+    if (f.P0 == 0 || (a.active && !a.active[k])) return false;
+    c = blockIdx.x / ncbmax;
+    bj = blockIdx.x % ncbmax;
+    return bj < f.P0 / 16 && c < f.P2;
+}
+
+template <typename T>
+__global__ __launch_bounds__(FD3_THREADS) void k_fd3_fwd01(FdArgs a, const T* __restrict__ r, int ncbmax) {
+    extern __shared__ double fd3c_sm[];
+    double* Wl = fd3c_sm;
+    int k, c, bj;
     FdInfo f;
-    if (!fd3_tile(a, k, f, t)) return;
+    if (!fd3_plane_block(a, ncbmax, k, f, c, bj)) return;
     const PatchLev& P = a.L[k];
-    const int nco = f.P0 / 16, ro = t / nco, co = t % nco;
+    const int M0 = P.M[0], M1 = P.M[1], M2 = P.M[2], P0 = f.P0, P1 = f.P1, nb1 = P1 / 16;
+    const uint32_t mb = P.mbits[a.mode];
     const double* U0 = a.U + f.u0;
-    const double* Z = a.z + f.zoff;
-    auto ga = [&](int i, int k0, double* v) { load4(Z + (int64_t)(ro * 16 + i) * f.P0 + k0, v); };
-    auto gb = [&](int k0, int j, double* v) { load4(U0 + (int64_t)(co * 16 + j) * f.P0 + k0, v); };
-    const mf_d4 c = fd2_product<double>(f.P0 / 16, ga, gb);
-    const int l = threadIdx.x & (WAVE - 1);
-    const int i0 = co * 16 + (l & 15), M0 = P.M[0], M1 = P.M[1], M2 = P.M[2];
-    double old[4] = {0.0, 0.0, 0.0, 0.0};
-    if (!SET) {   // the four old values loaded together (clamped to valid coefficients)
+    const double* U1 = a.U + f.u1;
+    const int wv = threadIdx.x / WAVE, l = threadIdx.x & (WAVE - 1);
+    const bool planeok = c < M2;
+    for (int bi = wv; bi < nb1; bi += FD3_THREADS / WAVE) {
+        auto ga = [&](int i, int k0, double* v) {
+            const int i1 = bi * 16 + i;
+            const T* row = r + P.voff + (int64_t)M0 * (min(i1, M1 - 1) + (int64_t)M1 * min(c, M2 - 1));
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int i0 = k0 + s;
+                const double x = (double)row[min(i0, M0 - 1)];
+                v[s] = (planeok & (i1 < M1) & (i0 < M0) & !masked_nb(mb, 3, M0, M1, M2, i0, i1, c)) ? x : 0.0;
+            }
+        };
+        auto gb = [&](int k0, int j, double* v) {
+#pragma unroll
+            for (int s = 0; s < 4; ++s) v[s] = U0[(int64_t)(k0 + s) * P0 + bj * 16 + j];
+        };
+        const mf_d4 cc = fd2_product<double>(P0 / 16, ga, gb);
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) Wl[(bi * 16 + (l >> 4) + 4 * rr) * FD2C_LD + (l & 15)] = cc[rr];
+    }
+    __syncthreads();
+    double* zb = a.z2 + f.zoff + (int64_t)c * P1 * P0;
+    for (int bi = wv; bi < nb1; bi += FD3_THREADS / WAVE) {
+        auto ga = [&](int i, int k0, double* v) {
+#pragma unroll
+            for (int s = 0; s < 4; ++s) v[s] = U1[(int64_t)(k0 + s) * P1 + bi * 16 + i];
+        };
+        auto gb = [&](int k0, int j, double* v) {
+#pragma unroll
+            for (int s = 0; s < 4; ++s) v[s] = Wl[(k0 + s) * FD2C_LD + j];
+        };
+        const mf_d4 cc = fd2_product<double>(nb1, ga, gb);
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) zb[(int64_t)(bi * 16 + (l >> 4) + 4 * rr) * P0 + bj * 16 + (l & 15)] = cc[rr];
+    }
+}
+
+template <typename T, bool SET>
+__global__ __launch_bounds__(FD3_THREADS) void k_fd3_bwd10(FdArgs a, T* __restrict__ x, int ncbmax) {
+    extern __shared__ double fd3c_sm[];
+    double* Tl = fd3c_sm;
+    int k, c, bj;
+    FdInfo f;
+    if (!fd3_plane_block(a, ncbmax, k, f, c, bj)) return;
+    const PatchLev& P = a.L[k];
+    const int M0 = P.M[0], M1 = P.M[1], M2 = P.M[2], P0 = f.P0, P1 = f.P1, nb1 = P1 / 16;
+    if (bj * 16 >= M0 || c >= M2) return;
+    const double* U0 = a.U + f.u0;
+    const double* U1 = a.U + f.u1;
+    const double* zb = a.z2 + f.zoff + (int64_t)c * P1 * P0;
+    const int wv = threadIdx.x / WAVE, l = threadIdx.x & (WAVE - 1);
+    for (int bi = wv; bi < nb1; bi += FD3_THREADS / WAVE) {
+        auto ga = [&](int i, int k0, double* v) { load4(zb + (int64_t)(bi * 16 + i) * P0 + k0, v); };
+        auto gb = [&](int k0, int j, double* v) { load4(U0 + (int64_t)(bj * 16 + j) * P0 + k0, v); };
+        const mf_d4 cc = fd2_product<double>(P0 / 16, ga, gb);
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) Tl[(bi * 16 + (l >> 4) + 4 * rr) * FD2C_LD + (l & 15)] = cc[rr];
+    }
+    __syncthreads();
+    const int i0 = bj * 16 + (l & 15);
+    for (int bi = wv; bi < nb1; bi += FD3_THREADS / WAVE) {
+        if (bi * 16 >= M1) break;
+        auto ga = [&](int i, int k0, double* v) { load4(U1 + (int64_t)(bi * 16 + i) * P1 + k0, v); };
+        auto gb = [&](int k0, int j, double* v) {
+#pragma unroll
+            for (int s = 0; s < 4; ++s) v[s] = Tl[(k0 + s) * FD2C_LD + j];
+        };
+        const mf_d4 cc = fd2_product<double>(nb1, ga, gb);
+        double old[4] = {0.0, 0.0, 0.0, 0.0};
+        if (!SET) {
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) {
+                const int i1 = min(bi * 16 + (l >> 4) + 4 * rr, M1 - 1);
+                old[rr] = (double)x[P.voff + min(i0, M0 - 1) + (int64_t)M0 * (i1 + (int64_t)M1 * c)];
+            }
+        }
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) {
-            const int o = ro * 16 + (l >> 4) + 4 * rr, i1 = min(o % f.P1, M1 - 1), i2 = min(o / f.P1, M2 - 1);
-            old[rr] = (double)x[P.voff + min(i0, M0 - 1) + (int64_t)M0 * (i1 + (int64_t)M1 * i2)];
+            const int i1 = bi * 16 + (l >> 4) + 4 * rr;
+            if (i0 >= M0 || i1 >= M1) continue;
+            const int64_t vi = P.voff + i0 + (int64_t)M0 * (i1 + (int64_t)M1 * c);
+            const bool m = masked(P, a.mode, i0, i1, c);
+            if (SET) x[vi] = m ? T(0) : T(f.tau * cc[rr]);
+            else if (!m) x[vi] = T(old[rr] + f.tau * cc[rr]);
         }
-    }
-#pragma unroll
-    for (int rr = 0; rr < 4; ++rr) {
-        const int o = ro * 16 + (l >> 4) + 4 * rr, i1 = o % f.P1, i2 = o / f.P1;
-        if (i0 >= M0 || i1 >= M1 || i2 >= M2) continue;
-        const int64_t vi = P.voff + i0 + (int64_t)M0 * (i1 + (int64_t)M1 * i2);
-        const bool m = masked(P, a.mode, i0, i1, i2);
-        if (SET) x[vi] = m ? T(0) : T(f.tau * c[rr]);
-        else if (!m) x[vi] = T(old[rr] + f.tau * c[rr]);
     }
 }
 
