@@ -295,6 +295,8 @@ def main():
     ap.add_argument("--coarse-level", type=int, default=0,
                     help="first multigrid level of the fused per-patch coarse kernel (0: the library's choice, "
                          "-1: every level by batched launches)")
+    ap.add_argument("--coarse-dofs", type=int, default=0,
+                    help="largest multigrid level solved by its dense inverse (0: the library's default)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 512 MiB FP64 tensor 3 times (scale for the FETCH_SIZE/WRITE_SIZE counters)")
     args = ap.parse_args()
@@ -338,6 +340,8 @@ def main():
         extra_opt["coarse_degree"] = args.coarse_degree
     if args.cheb_coarse:
         extra_opt["cheb_degree_coarse"] = args.cheb_coarse
+    if args.coarse_dofs:
+        extra_opt["coarse_dofs"] = args.coarse_dofs
     m = measure(wl, gname, args.steps, args.warmup, local_solver=variant, mg_precision=args.precision, **extra_opt)
     ms_per_step = m["ms_per_step"]
     value = wl.ndof_torn / (ms_per_step * 1e-3) / 1e6

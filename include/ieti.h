@@ -123,7 +123,7 @@ typedef struct ieti_options {
                                   fastest; 0: the table (default) */
     int32_t coarse_dofs;       /* multigrid: a patch level with at most this many coefficients is not
                                   coarsened further (dense exact solve there); 0 = no such limit. Coarsening
-                                  also stops where a direction's element count is odd or below 6 (default 600) */
+                                  also stops where a direction's element count is odd or below 6 (default 512) */
     int32_t smoother;          /* finest-level smoother: IETI_SMOOTHER_CHEBYSHEV (default) or
                                   IETI_SMOOTHER_TENSOR (coarser levels keep Chebyshev) */
     double  smoother_sigma;    /* IETI_SMOOTHER_TENSOR: mass shift sigma of the tensor smoother, in units of the

@@ -866,35 +866,60 @@ __global__ __launch_bounds__(TILE) void k_add_act(const PatchLev* L, const Tile*
     x[P.voff + i] += y[P.voff + i];
 }
 
-// y = A b for a dense n x n matrix stored by columns (entry (r, j) at
-// At[j * n + r]): one thread per row, so that every column load is
-// contiguous across the lanes and a wave streams whole columns; U loads per
-// thread in flight, the tail of the columns too (clamped to a valid column,
-// its products skipped).  Accumulates in double.  (Splitting the columns of a
-// row over four lanes balances the passes for n a little above the group
-// size but reads shorter runs and measured slower when few groups stream.)
-template <typename T, typename TB, typename TY>
-__device__ __forceinline__ void col_gemv(const T* __restrict__ At, int n, const TB* b, TY* y) {
+// Partial dot product of row r of a dense matrix stored by columns (entry
+// (r, j) at At[j * n + r]) with b over the columns j0 .. j1-1: U loads in
+// flight, the last batch clamped to a valid column and its products skipped.
+template <typename T, typename TB>
+__device__ __forceinline__ double col_dot(const T* __restrict__ At, int n, const TB* b, int r, int j0, int j1) {
     constexpr int U = 32;
-    for (int r = threadIdx.x; r < n; r += blockDim.x) {
-        double acc = 0.0;
-        int j = 0;
-        for (; j + U <= n; j += U) {
-            T a[U];
+    double acc = 0.0;
+    int j = j0;
+    for (; j + U <= j1; j += U) {
+        T a[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) a[u] = At[(int64_t)(j + u) * n + r];
+        for (int u = 0; u < U; ++u) a[u] = At[(int64_t)(j + u) * n + r];
 #pragma unroll
-            for (int u = 0; u < U; ++u) acc += (double)a[u] * (double)b[j + u];
-        }
-        if (j < n) {
-            T a[U];
+        for (int u = 0; u < U; ++u) acc += (double)a[u] * (double)b[j + u];
+    }
+    if (j < j1) {
+        T a[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) a[u] = At[(int64_t)min(j + u, n - 1) * n + r];
+        for (int u = 0; u < U; ++u) a[u] = At[(int64_t)min(j + u, j1 - 1) * n + r];
 #pragma unroll
-            for (int u = 0; u < U; ++u)
-                if (j + u < n) acc += (double)a[u] * (double)b[j + u];
-        }
-        y[r] = TY(acc);
+        for (int u = 0; u < U; ++u)
+            if (j + u < j1) acc += (double)a[u] * (double)b[j + u];
+    }
+    return acc;
+}
+
+// y = A b for a dense n x n matrix stored by columns, by the whole work-group
+// (every thread calls it): whole passes of one row per thread, so that every
+// column load is contiguous across the lanes and a wave streams whole columns;
+// the rows left after the last whole pass (nt of them) are split into G column
+// groups, G = min(blockDim / nt, n / 32 rounded up), one (row, group) per
+// thread, whose partial sums go to part (at least blockDim doubles, shared) and
+// are added in group order.  The split depends only on n and the group size,
+// so every call with the same n rounds the same way.  Without part every row
+// is one thread's.  (Splitting the columns of every row over four lanes of a
+// wave reads shorter runs and measured slower when few groups stream.)
+template <typename T, typename TB, typename TY>
+__device__ __forceinline__ void col_gemv(const T* __restrict__ At, int n, const TB* b, TY* y, double* part) {
+    const int B = blockDim.x, t = threadIdx.x;
+    const int nfull = part ? n / B * B : n;
+    for (int r = t; r < nfull; r += B) y[r] = TY(col_dot(At, n, b, r, 0, n));
+    const int nt = n - nfull;
+    if (nt == 0) return;
+    const int G = max(1, min(B / nt, (n + 31) / 32));
+    const int cw = (n + G - 1) / G;
+    if (t < nt * G) {
+        const int g = t / nt, r = nfull + (t - g * nt);
+        part[t] = col_dot(At, n, b, r, g * cw, min(n, (g + 1) * cw));
+    }
+    __syncthreads();
+    if (t < nt) {
+        double acc = part[t];
+        for (int g = 1; g < G; ++g) acc += part[g * nt + t];
+        y[nfull + t] = TY(acc);
     }
 }
 
@@ -903,11 +928,12 @@ __device__ __forceinline__ void col_gemv(const T* __restrict__ At, int n, const 
 template <typename T>
 __global__ __launch_bounds__(TILE) void k_coarse(const PatchLev* L, const int32_t* list, int nlist, const T* inv,
                                                  const T* b, T* x, int mode, const int* active) {
+    __shared__ double part[TILE];
     if ((int)blockIdx.x >= nlist) return;
     const PatchLev& P = L[list[blockIdx.x]];
     if (active && !active[P.patch]) return;
     const int n = (int)P.n;
-    col_gemv(inv + P.invoff + (int64_t)mode * n * n, n, b + P.voff, x + P.voff);
+    col_gemv(inv + P.invoff + (int64_t)mode * n * n, n, b + P.voff, x + P.voff, part);
 }
 
 // ------------------------------------------------------------------ elementwise helpers
@@ -1785,11 +1811,13 @@ struct CoarseArgs {
 };
 
 // LDS words the kernel needs for one patch chain: per level x, y (guarded),
-// b, d; staged, also nst * (n + guard) stencil words per smoothed level and
-// n * n for the coarsest inverse.
+// b, d; for the coarsest level the GEMV's partial sums (part_words, and one
+// word for their alignment); staged, also nst * (n + guard) stencil words per
+// smoothed level and n * n for the coarsest inverse.
 __host__ __device__ inline int64_t vcoarse_level_words(int64_t n, int64_t guard, int nst, bool coarsest,
-                                                       bool stage) {
+                                                       bool stage, int64_t part_words) {
     int64_t w = 2 * (n + 2 * guard) + 2 * n;
+    if (coarsest) w += part_words + 1;
     if (stage) w += coarsest ? n * n : (int64_t)nst * (n + guard);
     return w;
 }
@@ -1845,7 +1873,7 @@ struct VcShared {
     int pl[LMAX];        // patch-level index per level
     int off[LMAX][5];    // LDS offsets of x, y (guarded, at entry 0), b, d, operator data
     int cur[LMAX];       // which of x (0) / y (1) holds the level's current iterate
-    int nl, vec;
+    int nl, vec, part;   // levels, vector words, LDS offset of the coarsest GEMV's partial sums
 };
 
 // the cycle of patch k from level a.l0 on, for the degree class P0..P2
@@ -1877,6 +1905,12 @@ __device__ __forceinline__ void vcoarse_body(const CoarseArgs& a, int k, T* lds,
             off += n;
             sh_off[l][3] = off;
             off += n;
+            if (l == nl - 1) {
+                // partial sums of the coarsest GEMV: blockDim doubles, 8-byte aligned
+                off += (int)((off * sizeof(T)) & 7) / (int)sizeof(T);
+                sh.part = off;
+                off += (int)(blockDim.x * sizeof(double) / sizeof(T));
+            }
         }
         sh_vec = off;
         for (int l = l0; l < nl && stage; ++l) {
@@ -1928,8 +1962,9 @@ __device__ __forceinline__ void vcoarse_body(const CoarseArgs& a, int k, T* lds,
         T* bl = lds + sh_off[l][2];
         T* dl = lds + sh_off[l][3];
         if (l == nl - 1) {
-            if constexpr (STAGE) col_gemv(cl, n, bl, xl);
-            else col_gemv((const T*)a.inv[l] + P.invoff + (int64_t)mode * n * n, n, bl, xl);
+            double* part = (double*)(lds + sh.part);
+            if constexpr (STAGE) col_gemv(cl, n, bl, xl, part);
+            else col_gemv((const T*)a.inv[l] + P.invoff + (int64_t)mode * n * n, n, bl, xl, part);
             if (threadIdx.x == 0) sh_cur[l] = 0;
             __syncthreads();
             break;
@@ -2052,7 +2087,7 @@ __host__ __device__ constexpr int vcoarse_family(int cls) { return cls <= 8 ? 0 
 
 template <typename T, bool STAGE, int FAM>
 __global__ __launch_bounds__((vc_threads<T, FAM>())) void k_vcoarse(CoarseArgs a) {
-    extern __shared__ unsigned char vc_lds_raw[];
+    extern __shared__ __align__(16) unsigned char vc_lds_raw[];
     __shared__ VcShared sh;
     if ((int)blockIdx.x >= a.nlist) return;
     const int k = a.plist[blockIdx.x];

@@ -50,7 +50,7 @@ void default_options(ieti_options* o) {
     o->check_every = 4;
     o->use_graph = 0;
     o->coarse_level = 0;
-    o->coarse_dofs = 600;
+    o->coarse_dofs = 512;
     o->autotune = 0;
     o->smoother = IETI_SMOOTHER_CHEBYSHEV;
     o->smoother_sigma = 0.3;

@@ -1947,13 +1947,16 @@ void Solver<T>::setup() {
         int max_lds = 0;
         HIPCHECK(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
         const int64_t budget = (int64_t)max_lds - 1024;   // static shared memory of the kernel
+        // the coarsest GEMV's partial sums: one double per thread of the wider family
+        const int64_t part_words =
+            (int64_t)std::max(vc_threads<T, 0>(), vc_threads<T, 1>()) * (int64_t)(sizeof(double) / sizeof(T));
         auto chain_bytes = [&](int k, int f, bool stage) -> int64_t {
             const Patch& pa = pl.patches[k];
             const int nl = (int)pa.lv.size();
             int64_t w = 0;
             for (int l = f; l < nl; ++l) {
                 const Level& L = pa.lv[l];
-                w += vcoarse_level_words(L.n, L.guard, L.nst, l == nl - 1, stage);
+                w += vcoarse_level_words(L.n, L.guard, L.nst, l == nl - 1, stage, part_words);
             }
             return w * (int64_t)sizeof(T);
         };

@@ -31,7 +31,7 @@ CASES_3D = [
 @pytest.mark.parametrize("prec", [64, 32])
 @pytest.mark.parametrize("name,make", CASES_2D + CASES_3D, ids=[c[0] for c in CASES_2D + CASES_3D])
 def test_solution_matches_oracle(require_gpu, name, make, prec, hierarchy):
-    """hierarchy "default": coarsening stops at 600 coefficients (most of these small
+    """hierarchy "default": coarsening stops at 512 coefficients (most of these small
     patches are then solved on one level); "full": coarse_dofs = 0 forces the whole
     h-hierarchy, so the V-cycle kernels (smoothing, transfers, fused coarse levels) run."""
     wl = make()
