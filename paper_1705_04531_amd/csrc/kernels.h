@@ -1930,6 +1930,8 @@ __device__ __forceinline__ void vcoarse_body(const CoarseArgs& a, int k, T* lds,
     __syncthreads();
     const int nl = sh_nl;
     for (int i = threadIdx.x; i < sh_vec; i += blockDim.x) lds[i] = T(0);
+    // the copies below write words that other waves zero above
+    __syncthreads();
     {
         const PatchLev& P = a.L[l0][sh_pl[l0]];
         group_copy<4>(lds + sh_off[l0][2], (const T*)a.b1 + P.voff, (int)P.n);
