@@ -153,6 +153,33 @@ def test_graph_replay_equals_direct_launches(require_gpu, smoother):
     assert np.allclose(outs[1][2], 3.0 * outs[1][0], rtol=1e-8, atol=0)
 
 
+def test_solves_reproducible_across_instances(require_gpu):
+    """Every solve of a handle, and of a second handle made the same way, gives bitwise the same result, also
+    when a handle with another multigrid hierarchy has run before it in the process (the fused coarse kernel
+    once lost right-hand-side entries to a late wave's clearing of its LDS, which showed as a one-ulp
+    difference in the first solve after such a handle)."""
+    import torch
+    from paper_1705_04531_amd import Solver, _abi, options_for
+    wl = W.deformed_square((4, 4), [[4, 4, 3, 2], [4, 3, 2, 4]], [[48, 32, 24, 16], [32, 48, 16, 24]],
+                           amp_factor=0.8, name="repro4x4_mixed")
+    def solves(cd, reps):
+        s = Solver(wl.patches, options_for(wl, coarse_dofs=cd, smoother=_abi.IETI_SMOOTHER_TENSOR))
+        x = s.quadrature(device=False)
+        f = torch.from_numpy(wl.f(x)).to("cuda")
+        us = []
+        for _ in range(reps):
+            u, _ = s.solve(f)
+            torch.cuda.synchronize()
+            us.append(u.cpu().numpy())
+        s.close()
+        return us
+    solves(900, 1)
+    a = solves(300, 3)
+    b = solves(300, 2)
+    for u in a[1:] + b:
+        assert np.array_equal(a[0], u)
+
+
 SADDLE_CASES = [CASES_2D[0], CASES_2D[2], CASES_2D[3], CASES_3D[0]]
 
 
