@@ -628,32 +628,46 @@ __global__ __launch_bounds__(TILE) void k_cheb_zero(const PatchLev* L, const Til
     d[vi] = T(v);
 }
 
-// Transfer band sum for the degree class of F: P0 = -2 selects the 2D class
-// of F at run time (launches over several classes), else as band_sum.
-template <int P0, int P1, int P2, typename T>
+// Width of a row of the nested prolongation (knot insertion at every element
+// midpoint): a fine B-spline of degree p is a combination of at most
+// (p + 1) / 2 + 1 consecutive coarse ones (a coarse one spans p + 2 fine ones:
+// the restriction's width).
+__host__ __device__ constexpr int prol_width(int p) { return (p + 1) / 2 + 1; }
+
+template <int PA, int PB, bool PROL, typename T>
+__device__ __forceinline__ double band_sum_2d(const T* v0, const T* v1, const T* src, int M0, int M01) {
+    constexpr int W0 = PROL ? prol_width(PA) : PA + 2, W1 = PROL ? prol_width(PB) : PB + 2;
+    return band_sum<W0, W1, 1>(v0, v1, v1, src, M0, M01, W0, W1, 1, 2);
+}
+
+// Transfer band sum for the degree class of F (PROL: a prolongation row, else
+// a restriction column): P0 = -2 selects the 2D class of F at run time
+// (launches over several classes), else as band_sum.
+template <int P0, int P1, int P2, bool PROL, typename T>
 __device__ __forceinline__ double band_sum_cls(const PatchLev& F, const T* v0, const T* v1, const T* v2, const T* src,
                                                int M0, int M01) {
     const bool three = F.dim == 3;
+    auto w = [](int p) { return PROL ? prol_width(p) : p + 2; };
     if constexpr (P0 == -2) {
         switch (F.pclass) {
-        case 0: return band_sum<4, 4, 1>(v0, v1, v2, src, M0, M01, 4, 4, 1, 2);
-        case 1: return band_sum<5, 4, 1>(v0, v1, v2, src, M0, M01, 5, 4, 1, 2);
-        case 2: return band_sum<6, 4, 1>(v0, v1, v2, src, M0, M01, 6, 4, 1, 2);
-        case 3: return band_sum<4, 5, 1>(v0, v1, v2, src, M0, M01, 4, 5, 1, 2);
-        case 4: return band_sum<5, 5, 1>(v0, v1, v2, src, M0, M01, 5, 5, 1, 2);
-        case 5: return band_sum<6, 5, 1>(v0, v1, v2, src, M0, M01, 6, 5, 1, 2);
-        case 6: return band_sum<4, 6, 1>(v0, v1, v2, src, M0, M01, 4, 6, 1, 2);
-        case 7: return band_sum<5, 6, 1>(v0, v1, v2, src, M0, M01, 5, 6, 1, 2);
-        case 8: return band_sum<6, 6, 1>(v0, v1, v2, src, M0, M01, 6, 6, 1, 2);
+        case 0: return band_sum_2d<2, 2, PROL>(v0, v1, src, M0, M01);
+        case 1: return band_sum_2d<3, 2, PROL>(v0, v1, src, M0, M01);
+        case 2: return band_sum_2d<4, 2, PROL>(v0, v1, src, M0, M01);
+        case 3: return band_sum_2d<2, 3, PROL>(v0, v1, src, M0, M01);
+        case 4: return band_sum_2d<3, 3, PROL>(v0, v1, src, M0, M01);
+        case 5: return band_sum_2d<4, 3, PROL>(v0, v1, src, M0, M01);
+        case 6: return band_sum_2d<2, 4, PROL>(v0, v1, src, M0, M01);
+        case 7: return band_sum_2d<3, 4, PROL>(v0, v1, src, M0, M01);
+        case 8: return band_sum_2d<4, 4, PROL>(v0, v1, src, M0, M01);
         default:
-            return band_sum<-1, -1, -1>(v0, v1, v2, src, M0, M01, F.p[0] + 2, F.p[1] + 2, three ? F.p[2] + 2 : 1,
+            return band_sum<-1, -1, -1>(v0, v1, v2, src, M0, M01, w(F.p[0]), w(F.p[1]), three ? w(F.p[2]) : 1,
                                         F.dim);
         }
     } else {
-        constexpr int W0 = P0 >= 0 ? P0 + 2 : -1, W1 = P0 >= 0 ? P1 + 2 : -1;
-        constexpr int W2 = P0 >= 0 ? (P2 > 0 ? P2 + 2 : 1) : -1;
-        return band_sum<W0, W1, W2>(v0, v1, v2, src, M0, M01, F.p[0] + 2, F.p[1] + 2, three ? F.p[2] + 2 : 1,
-                                    F.dim);
+        constexpr int W0 = P0 >= 0 ? (PROL ? prol_width(P0) : P0 + 2) : -1;
+        constexpr int W1 = P0 >= 0 ? (PROL ? prol_width(P1) : P1 + 2) : -1;
+        constexpr int W2 = P0 >= 0 ? (P2 > 0 ? (PROL ? prol_width(P2) : P2 + 2) : 1) : -1;
+        return band_sum<W0, W1, W2>(v0, v1, v2, src, M0, M01, w(F.p[0]), w(F.p[1]), three ? w(F.p[2]) : 1, F.dim);
     }
 }
 
@@ -684,7 +698,7 @@ __global__ __launch_bounds__(TILE) void k_restrict(const PatchLev* Lf, const Pat
     const T* v2 = three ? rval + (F.roff[2] + I2) * PW : v1;
     const int M0 = F.M[0], M01 = F.M[0] * F.M[1];
     const T* src = rf + F.voff + lo0 + (int64_t)lo1 * M0 + (int64_t)lo2 * M01;
-    bc[C.voff + I] = T(band_sum_cls<P0, P1, P2>(F, v0, v1, v2, src, M0, M01));
+    bc[C.voff + I] = T(band_sum_cls<P0, P1, P2, false>(F, v0, v1, v2, src, M0, M01));
 }
 
 // Prolongation x_f += m_f P e_c, one thread per fine coefficient (P0 = -2:
@@ -711,7 +725,7 @@ __global__ __launch_bounds__(TILE) void k_prolong(const PatchLev* Lf, const Patc
     const T* v2 = three ? pval + (F.toff[2] + i2) * PW : v1;
     const int M0 = C.M[0], M01 = C.M[0] * C.M[1];
     const T* src = ec + C.voff + lo0 + (int64_t)lo1 * M0 + (int64_t)lo2 * M01;
-    const double acc = band_sum_cls<P0, P1, P2>(F, v0, v1, v2, src, M0, M01);
+    const double acc = band_sum_cls<P0, P1, P2, true>(F, v0, v1, v2, src, M0, M01);
     const int64_t vi = F.voff + i;
     xf[vi] = T((double)xf[vi] + acc);
 }
@@ -2056,10 +2070,11 @@ __device__ __forceinline__ void vcoarse_body(const CoarseArgs& a, int k, T* lds,
                 const T* v0 = pval + (P.toff[0] + i0) * PW;
                 const T* v1 = pval + (P.toff[1] + i1) * PW;
                 const T* v2 = three ? pval + (P.toff[2] + i2) * PW : v1;
-                constexpr int W0 = P0 >= 0 ? P0 + 2 : -1, W1 = P0 >= 0 ? P1 + 2 : -1;
-                constexpr int W2 = P0 >= 0 ? (P2 > 0 ? P2 + 2 : 1) : -1;
-                X[i] += T(band_sum<W0, W1, W2>(v0, v1, v2, E + lo0 + lo1 * C0 + lo2 * C01, C0, C01, P.p[0] + 2,
-                                               P.p[1] + 2, three ? P.p[2] + 2 : 1, P.dim));
+                constexpr int W0 = P0 >= 0 ? prol_width(P0) : -1, W1 = P0 >= 0 ? prol_width(P1) : -1;
+                constexpr int W2 = P0 >= 0 ? (P2 > 0 ? prol_width(P2) : 1) : -1;
+                X[i] += T(band_sum<W0, W1, W2>(v0, v1, v2, E + lo0 + lo1 * C0 + lo2 * C01, C0, C01,
+                                               prol_width(P.p[0]), prol_width(P.p[1]),
+                                               three ? prol_width(P.p[2]) : 1, P.dim));
             }
         }
         __syncthreads();

@@ -1870,9 +1870,11 @@ void Solver<T>::setup() {
                 }
             if (P.coarse >= 0) {
                 for (int d = 0; d < dim; ++d) {
-                    // nested levels: the embedding's rows hold p + 2 entries; the L2 projection's mixed mass
-                    // matrix M_fc (degree p onto degree 1) up to PW
+                    // nested levels: the embedding's columns hold p + 2 entries, its rows at most
+                    // prol_width(p) (the kernels read that many); the L2 projection's mixed mass matrix M_fc
+                    // (degree p onto degree 1) up to PW both ways
                     const int Mf = L.M[d], Mc = L.Mc[d], w = L.l2 ? PW : L.p[d] + 2;
+                    const int wr = L.l2 ? PW : prol_width(L.p[d]);
                     if (w > PW) throw Error(IETI_ENOTSUP, "degree too high for the transfer tables");
                     const std::vector<double>& Pm = L.P[d];
                     P.toff[d] = (int64_t)plo.size();
@@ -1881,12 +1883,12 @@ void Solver<T>::setup() {
                         for (int c = 0; c < Mc; ++c)
                             if (Pm[(size_t)r * Mc + c] != 0.0) { cmin = std::min(cmin, c); cmax = std::max(cmax, c); }
                         if (cmax < 0) cmin = cmax = 0;
-                        if (cmax - cmin + 1 > w) throw Error(IETI_ENOTSUP, "prolongation row wider than the table");
-                        int lo = std::max(0, std::min(cmin, Mc - w));
+                        if (cmax - cmin + 1 > wr) throw Error(IETI_ENOTSUP, "prolongation row wider than the table");
+                        int lo = std::max(0, std::min(cmin, Mc - wr));
                         plo.push_back(lo);
                         for (int a = 0; a < PW; ++a) {
                             int c = lo + a;
-                            pval.push_back(a < w && c < Mc ? T(Pm[(size_t)r * Mc + c]) : T(0));
+                            pval.push_back(a < wr && c < Mc ? T(Pm[(size_t)r * Mc + c]) : T(0));
                         }
                     }
                     P.roff[d] = (int64_t)rlo.size();
