@@ -64,6 +64,7 @@ struct PatchQ {
     int32_t Q[3];          // quadrature points per direction
     int64_t qoff;          // first quadrature point of the patch
     int64_t boff[3];       // 1D basis tables: Q[d] x (p+1) values per direction
+    int64_t toff[2];       // load vector: the patch's intermediates after contracting direction 0 (and 1)
 };
 
 struct Tile {

@@ -1359,44 +1359,50 @@ __global__ __launch_bounds__(TILE) void k_pri_apply_full(const PatchLev* L, cons
 
 // ------------------------------------------------------------------ load vector, groups, output
 
-// f_i = sum_q w_q |det J_q| f(x_q) N_i(xi_q), one thread per coefficient (level 0)
-__global__ __launch_bounds__(TILE) void k_loadvec(const PatchLev* L, const PatchQ* PQ, const Tile* tiles, int ntiles,
-                                                  const double* basis, const double* qpw, const double* fq,
-                                                  double* fvec) {
-    const int t = tile_index(ntiles);
-    if (t < 0) return;
-    const Tile tl = tiles[t];
-    const PatchLev& P = L[tl.pl];
-    const PatchQ Q = PQ[P.patch];
-    const int64_t i = (int64_t)tl.start + threadIdx.x;
-    if (i >= P.n) return;
-    int ii[3];
-    unlin(P, i, ii[0], ii[1], ii[2]);
-    int elo[3] = {0, 0, 0}, ehi[3] = {0, 0, 0}, ng[3] = {1, 1, 1};
-    for (int d = 0; d < P.dim; ++d) {
-        elo[d] = ii[d] - P.p[d] > 0 ? ii[d] - P.p[d] : 0;
-        ehi[d] = ii[d] < Q.nel[d] - 1 ? ii[d] : Q.nel[d] - 1;
-        ng[d] = P.p[d] + 1;
+// Load vector f_i = sum_q w_q f(x_q) N_i(x_q) by sum factorisation over the
+// patch's tensor grid of Gauss points: pass d contracts direction d of the
+// patch's array (directions below d already in coefficients, d and above in
+// quadrature points; x0 fastest) with the 1D basis table,
+//   out[.., i, ..] = sum over elements e in [i - p, i] and their Gauss points g of N_{i-e}(q) in[.., q, ..],
+// q = e (p + 1) + g; pass 0 reads the weighted values w_q f(x_q), the last
+// pass writes the coefficients.  One thread per output entry; grid (largest
+// output of a patch / TILE, patches).
+__global__ __launch_bounds__(TILE) void k_qcontract(const PatchLev* L, const PatchQ* PQ, int d, const double* basis,
+                                                    const double* qpw, const double* in, double* out) {
+    const int k = blockIdx.y;
+    const PatchLev& P = L[k];
+    const PatchQ Q = PQ[k];
+    const int dim = P.dim;
+    int si[3], so[3];
+    for (int c = 0; c < 3; ++c) {
+        si[c] = c < dim ? (c < d ? P.M[c] : Q.Q[c]) : 1;
+        so[c] = c < dim ? (c <= d ? P.M[c] : Q.Q[c]) : 1;
     }
+    const int64_t nout = (int64_t)so[0] * so[1] * so[2];
+    const int64_t o = (int64_t)blockIdx.x * TILE + threadIdx.x;
+    if (o >= nout) return;
+    int a[3];
+    a[0] = (int)(o % so[0]);
+    a[1] = (int)((o / so[0]) % so[1]);
+    a[2] = (int)(o / ((int64_t)so[0] * so[1]));
+    const int p = P.p[d], np = p + 1, i = a[d];
+    const int64_t stride = d == 0 ? 1 : d == 1 ? (int64_t)si[0] : (int64_t)si[0] * si[1];
+    a[d] = 0;
+    const int64_t base = a[0] + (int64_t)si[0] * (a[1] + (int64_t)si[1] * a[2]);
+    const double* src = d == 0 ? in + Q.qoff : in + Q.toff[d - 1];
+    const double* wq = d == 0 ? qpw + Q.qoff : nullptr;
+    const double* bt = basis + Q.boff[d];
+    const int elo = i - p > 0 ? i - p : 0, ehi = i < Q.nel[d] - 1 ? i : Q.nel[d] - 1;
     double acc = 0.0;
-    for (int e2 = elo[2]; e2 <= ehi[2]; ++e2)
-        for (int g2 = 0; g2 < ng[2]; ++g2) {
-            const int q2 = e2 * ng[2] + g2;
-            const double b2 = P.dim == 3 ? basis[Q.boff[2] + (int64_t)q2 * ng[2] + (ii[2] - e2)] : 1.0;
-            for (int e1 = elo[1]; e1 <= ehi[1]; ++e1)
-                for (int g1 = 0; g1 < ng[1]; ++g1) {
-                    const int q1 = e1 * ng[1] + g1;
-                    const double b12 = b2 * basis[Q.boff[1] + (int64_t)q1 * ng[1] + (ii[1] - e1)];
-                    const int64_t qrow = Q.qoff + ((int64_t)(P.dim == 3 ? q2 : 0) * Q.Q[1] + q1) * Q.Q[0];
-                    for (int e0 = elo[0]; e0 <= ehi[0]; ++e0)
-                        for (int g0 = 0; g0 < ng[0]; ++g0) {
-                            const int q0 = e0 * ng[0] + g0;
-                            const double b = b12 * basis[Q.boff[0] + (int64_t)q0 * ng[0] + (ii[0] - e0)];
-                            acc += b * qpw[qrow + q0] * fq[qrow + q0];
-                        }
-                }
+    for (int e = elo; e <= ehi; ++e)
+        for (int g = 0; g < np; ++g) {
+            const int q = e * np + g;
+            const int64_t at = base + q * stride;
+            const double v = d == 0 ? wq[at] * src[at] : src[at];
+            acc += bt[(int64_t)q * np + (i - e)] * v;
         }
-    fvec[P.voff + i] = acc;
+    double* dst = d == dim - 1 ? out + P.voff : out + Q.toff[d];
+    dst[o] = acc;
 }
 
 // mean of every group of copies, written back to all copies

@@ -438,6 +438,9 @@ struct Solver : SolverBase {
     // load vector
     PatchQ* PQ = nullptr;
     double *basis = nullptr, *qpw = nullptr;
+    double* qtmp = nullptr;            // load vector: intermediates of the sum factorisation
+    int64_t qtmp_len = 0;
+    int64_t qc_grid[3] = {1, 1, 1};    // work-groups per patch of the contraction passes
     double* qpx = nullptr;
     // lambda space
     double *lam = nullptr, *lr = nullptr, *lz = nullptr, *lp = nullptr, *lq = nullptr, *ltmp = nullptr;
@@ -2265,7 +2268,18 @@ void Solver<T>::setup() {
             qo += pa.n_qp;
             w.insert(w.end(), pa.qpw.begin(), pa.qpw.end());
             x.insert(x.end(), pa.qpx.begin(), pa.qpx.end());
+            // sum factorisation of the load vector: direction 0 contracted (M0 Q1 Q2), then direction 1
+            // (M0 M1 Q2, 3D); the last pass writes the coefficients
+            const int64_t M0 = pa.lv[0].M[0], M1 = pa.lv[0].M[1];
+            const int64_t t1 = M0 * Q.Q[1] * Q.Q[2], t2 = dim == 3 ? M0 * M1 * Q.Q[2] : 0;
+            Q.toff[0] = qtmp_len;
+            Q.toff[1] = qtmp_len + t1;
+            qtmp_len += t1 + t2;
+            qc_grid[0] = std::max(qc_grid[0], (t1 + TILE - 1) / TILE);
+            qc_grid[1] = std::max(qc_grid[1], ((dim == 3 ? t2 : pa.lv[0].n) + TILE - 1) / TILE);
+            qc_grid[2] = std::max(qc_grid[2], (pa.lv[0].n + TILE - 1) / TILE);
         }
+        qtmp = arena.alloc<double>(qtmp_len, st);
         PQ = arena.upload(pq, st);
         basis = arena.upload(bas, st);
         qpw = arena.upload(w, st);
@@ -2463,9 +2477,13 @@ int Solver<T>::solve(const double* f_qp, double* u_out, ieti_stats* stp) {
     sync();
     auto t0 = clk::now();
     // ---- load vector and d = B K~^{-1} f
-    hipLaunchKernelGGL(k_loadvec, dim3(tile_grid(D0.nt_all)), dim3(TILE), 0, stream, D0.L, PQ, D0.tiles_all,
-                       D0.nt_all, basis, qpw, f_qp, f64);
-    check_launch();
+    for (int d = 0; d < dim; ++d) {
+        const double* in = d == 0 ? f_qp : qtmp;
+        double* out = d == dim - 1 ? f64 : qtmp;
+        hipLaunchKernelGGL(k_qcontract, dim3((unsigned)qc_grid[d], N), dim3(TILE), 0, stream, D0.L, PQ, d, basis, qpw,
+                           in, out);
+        check_launch();
+    }
     // reject non-finite data: |f|^2 must be finite
     hipLaunchKernelGGL(k_sq, dim3(tile_grid(D0.nt_all)), dim3(TILE), 0, stream, D0.L, D0.tiles_all, D0.nt_all, f64,
                        (int)MODE_K, partial);
