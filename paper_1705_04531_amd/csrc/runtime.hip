@@ -593,14 +593,14 @@ struct Solver : SolverBase {
         FdArgs a{lev[0].L, fd_info[mode], fd_U, fd_lam, fd_z, act, mode, N, fd_z2, fd_U32, fd_z32, fd_z232};
         const dim3 g((fd_tiles2 + FD2_THREADS / WAVE - 1) / (FD2_THREADS / WAVE), N), b(FD2_THREADS);
         if (fd_p1max <= FD2C_MAXP) {   // the products fused in pairs per column block (intermediate in LDS)
-            const dim3 gc(fd_p0max / 16, N);
+            const dim3 gc(fd_p0max / 16, N), bc(FD2C_THREADS);
             const size_t lds = (size_t)fd_p1max * FD2C_LD * sizeof(T);
-            hipLaunchKernelGGL(k_fd2_fwd<T>, gc, b, lds, stream, a, r);
+            hipLaunchKernelGGL(k_fd2_fwd<T>, gc, bc, lds, stream, a, r);
             check_launch();
             if (set)
-                hipLaunchKernelGGL((k_fd2_bwd<T, true>), gc, b, lds, stream, a, x);
+                hipLaunchKernelGGL((k_fd2_bwd<T, true>), gc, bc, lds, stream, a, x);
             else
-                hipLaunchKernelGGL((k_fd2_bwd<T, false>), gc, b, lds, stream, a, x);
+                hipLaunchKernelGGL((k_fd2_bwd<T, false>), gc, bc, lds, stream, a, x);
             check_launch();
             return;
         }

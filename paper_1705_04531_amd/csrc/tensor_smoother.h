@@ -97,23 +97,24 @@ __device__ __forceinline__ bool fd2_tile(const FdArgs& a, int& k, FdInfo& f, int
 // kq = l / 16 supplies k = 4 kq + s to the s-th of the four MFMAs, so that a lane's A values A[i][k0 .. k0+3]
 // and B values B[k0 .. k0+3][j] (k0 = 16 kb + 4 kq) are four consecutive K indices: ga(i, k0, v) and
 // gb(k0, j, v) fill v[0..3] (one 32-byte load where K is the contiguous index of the layout, four loads
-// that are contiguous across the lanes otherwise).  Steps of four K blocks: their operand loads are issued
+// that are contiguous across the lanes otherwise).  Steps of FD2_KG K blocks: their operand loads are issued
 // before their products (a step past nkb re-reads the last block and skips its products).
+constexpr int FD2_KG = 4;   // 16-wide K blocks whose operands are loaded before their products (8: fewer waves fit, 16x16 workload 120.6 -> 134 ms)
 template <typename CT, typename GA, typename GB>
 __device__ __forceinline__ typename FdMf<CT>::acc fd2_product(int nkb, GA ga, GB gb) {
     typedef typename FdMf<CT>::acc acc;
     const int l = threadIdx.x & (WAVE - 1), i = l & 15, kq = l >> 4;
     acc c = {0, 0, 0, 0};
-    for (int kb0 = 0; kb0 < nkb; kb0 += 4) {
-        CT av[16], bv[16];
+    for (int kb0 = 0; kb0 < nkb; kb0 += FD2_KG) {
+        CT av[4 * FD2_KG], bv[4 * FD2_KG];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < FD2_KG; ++q) {
             const int k0 = min(kb0 + q, nkb - 1) * 16 + 4 * kq;
             ga(i, k0, av + 4 * q);
             gb(k0, i, bv + 4 * q);
         }
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
+        for (int q = 0; q < FD2_KG; ++q)
             if (kb0 + q < nkb) {
 #pragma unroll
                 for (int s = 0; s < 4; ++s) c = FdMf<CT>::mfma(av[4 * q + s], bv[4 * q + s], c);
@@ -272,10 +273,11 @@ __global__ __launch_bounds__(FD2_THREADS) void k_fd2_y(FdArgs a, T* __restrict__
 // LDS, one 16 x 16 block per wave and pass, then the final column block from it (Z[:, bj] = U_1^T W[:, bj]
 // scaled, or the update of x with U_1 T[:, bj]).  Each block's sums run in the K order of the unfused
 // kernels, so the results are the same; the intermediates never go to memory and two launches are saved.
-// Grid: (largest P0 / 16, N) work-groups of FD2_THREADS, dynamic LDS of (largest P1) x FD2C_LD words; used while
+// Grid: (largest P0 / 16, N) work-groups of FD2C_THREADS, dynamic LDS of (largest P1) x FD2C_LD words; used while
 // the largest P1 is at most FD2C_MAXP (the unfused kernels above otherwise).
 constexpr int FD2C_LD = 17;     // LDS row length of an intermediate column block (P1 x 16, one word of padding)
 constexpr int FD2C_MAXP = 256;
+constexpr int FD2C_THREADS = 512;   // eight waves: one 16-row block each for patches up to 128 coefficients
 
 __device__ __forceinline__ bool fd2_colblock(const FdArgs& a, int& k, FdInfo& f, int& bj) {
     k = blockIdx.y;
@@ -287,7 +289,7 @@ __device__ __forceinline__ bool fd2_colblock(const FdArgs& a, int& k, FdInfo& f,
 
 // forward: Z[:, bj] = (U_1^T (m R U_0)[:, bj]) ./ (lambda_1 + lambda_0 + c) into the scratch
 template <typename T>
-__global__ __launch_bounds__(FD2_THREADS) void k_fd2_fwd(FdArgs a, const T* __restrict__ r) {
+__global__ __launch_bounds__(FD2C_THREADS) void k_fd2_fwd(FdArgs a, const T* __restrict__ r) {
     typedef T CT;
     extern __shared__ double fd2c_sm[];
     CT* Wl = (CT*)fd2c_sm;
@@ -300,7 +302,7 @@ __global__ __launch_bounds__(FD2_THREADS) void k_fd2_fwd(FdArgs a, const T* __re
     const CT* U1 = fd_u<CT>(a) + f.u1;
     const uint32_t mb = P.mbits[mode];
     const int wv = threadIdx.x / WAVE, l = threadIdx.x & (WAVE - 1);
-    for (int bi = wv; bi < nb1; bi += FD2_THREADS / WAVE) {
+    for (int bi = wv; bi < nb1; bi += FD2C_THREADS / WAVE) {
         auto ga = [&](int i, int k0, CT* v) {
             const int i1 = bi * 16 + i;
             const T* row = r + P.voff + (int64_t)M0 * min(i1, M1 - 1);
@@ -325,7 +327,7 @@ __global__ __launch_bounds__(FD2_THREADS) void k_fd2_fwd(FdArgs a, const T* __re
     const double* l0 = a.lam + f.l0;
     const double* l1 = a.lam + f.l1;
     const int a0 = bj * 16 + (l & 15);
-    for (int bi = wv; bi < nb1; bi += FD2_THREADS / WAVE) {
+    for (int bi = wv; bi < nb1; bi += FD2C_THREADS / WAVE) {
         auto ga = [&](int i, int k0, CT* v) {
 #pragma unroll
             for (int s = 0; s < 4; ++s) v[s] = U1[(int64_t)(k0 + s) * P1 + bi * 16 + i];
@@ -346,7 +348,7 @@ __global__ __launch_bounds__(FD2_THREADS) void k_fd2_fwd(FdArgs a, const T* __re
 // backward: x[:, bj] (+)= tau m (U_1 (Z U_0^T)[:, bj]) on the M1 x M0 coefficients (SET: x = tau y, masked
 // coefficients 0); column blocks past M0 are skipped
 template <typename T, bool SET>
-__global__ __launch_bounds__(FD2_THREADS) void k_fd2_bwd(FdArgs a, T* __restrict__ x) {
+__global__ __launch_bounds__(FD2C_THREADS) void k_fd2_bwd(FdArgs a, T* __restrict__ x) {
     typedef T CT;
     extern __shared__ double fd2c_sm[];
     CT* Tl = (CT*)fd2c_sm;
@@ -360,7 +362,7 @@ __global__ __launch_bounds__(FD2_THREADS) void k_fd2_bwd(FdArgs a, T* __restrict
     const CT* U1 = fd_u<CT>(a) + f.u1;
     const CT* Z = fd_scr<CT>(a, false) + f.zoff;
     const int wv = threadIdx.x / WAVE, l = threadIdx.x & (WAVE - 1);
-    for (int bi = wv; bi < nb1; bi += FD2_THREADS / WAVE) {
+    for (int bi = wv; bi < nb1; bi += FD2C_THREADS / WAVE) {
         auto ga = [&](int i, int k0, CT* v) { load4(Z + (int64_t)(bi * 16 + i) * P0 + k0, v); };
         auto gb = [&](int k0, int j, CT* v) { load4(U0 + (int64_t)(bj * 16 + j) * P0 + k0, v); };
         const auto c = fd2_product<CT>(P0 / 16, ga, gb);
@@ -369,7 +371,7 @@ __global__ __launch_bounds__(FD2_THREADS) void k_fd2_bwd(FdArgs a, T* __restrict
     }
     __syncthreads();
     const int i0 = bj * 16 + (l & 15);
-    for (int bi = wv; bi < nb1; bi += FD2_THREADS / WAVE) {
+    for (int bi = wv; bi < nb1; bi += FD2C_THREADS / WAVE) {
         if (bi * 16 >= M1) break;
         auto ga = [&](int i, int k0, CT* v) { load4(U1 + (int64_t)(bi * 16 + i) * P1 + k0, v); };
         auto gb = [&](int k0, int j, CT* v) {
