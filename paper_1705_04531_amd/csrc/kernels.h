@@ -55,6 +55,29 @@ __device__ __forceinline__ void unlin(const PatchLev& P, int64_t i, int& i0, int
     i0 = r - i1 * M0;
 }
 
+// sum of the per-tile partials v[S u + c], u = beg .. end-1, for c < NS, added in
+// index order (as a plain loop would) with eight loads in flight
+template <int NS>
+__device__ __forceinline__ void ordered_sums(const double* __restrict__ v, int beg, int end, double (&s)[NS]) {
+#pragma unroll
+    for (int c = 0; c < NS; ++c) s[c] = 0.0;
+    int u = beg;
+    for (; u + 8 <= end; u += 8) {
+        double t[8][NS];
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+#pragma unroll
+            for (int c = 0; c < NS; ++c) t[j][c] = v[NS * (u + j) + c];
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+#pragma unroll
+            for (int c = 0; c < NS; ++c) s[c] += t[j][c];
+    }
+    for (; u < end; ++u)
+#pragma unroll
+        for (int c = 0; c < NS; ++c) s[c] += v[NS * u + c];
+}
+
 // deterministic block sum of NV doubles (blockDim.x == TILE); result valid in thread 0
 template <int NV>
 __device__ __forceinline__ void block_sum(double (&v)[NV], double* lds) {
@@ -1099,9 +1122,9 @@ __global__ __launch_bounds__(TILE) void k_fcg_dir(const PatchLev* L, const Tile*
     if (!active[k]) return;
     double bt = 0.0;
     if (!first) {
-        double s = 0.0;
-        for (int u = tile_beg[k]; u < tile_end[k]; ++u) s += pzq[u];
-        bt = s / dq[k];
+        double s[1];
+        ordered_sums<1>(pzq, tile_beg[k], tile_end[k], s);
+        bt = s[0] / dq[k];
     }
     const int i = tl.start + (int)threadIdx.x;
     if (i >= (int)P.n) return;
@@ -1130,11 +1153,9 @@ __global__ __launch_bounds__(TILE) void k_fcg_update(const PatchLev* L, const Ti
     const PatchLev& P = L[tl.pl];
     const int k = P.patch;
     if (!active[k]) return;
-    double sdq = 0.0, sdr = 0.0;
-    for (int u = tile_beg[k]; u < tile_end[k]; ++u) {
-        sdq += pdots[2 * u];
-        sdr += pdots[2 * u + 1];
-    }
+    double sd[2];
+    ordered_sums<2>(pdots, tile_beg[k], tile_end[k], sd);
+    const double sdq = sd[0], sdr = sd[1];
     const bool ok = sdq > 0.0;
     const double al = ok ? sdr / sdq : 0.0;
     if (threadIdx.x == 0 && tl.gid == tile_beg[k]) {
@@ -1168,8 +1189,9 @@ __global__ __launch_bounds__(256) void k_fcg_check(int npatch, const int32_t* ti
     int c = 0;
     for (int k = threadIdx.x; k < npatch; k += blockDim.x) {
         if (!init && !active[k]) continue;
-        double s = 0.0;
-        for (int u = tile_beg[k]; u < tile_end[k]; ++u) s += prr[u];
+        double ss[1];
+        ordered_sums<1>(prr, tile_beg[k], tile_end[k], ss);
+        const double s = ss[0];
         if (init) {
             bb[k] = s;
             its[k] = 0;
