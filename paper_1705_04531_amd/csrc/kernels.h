@@ -652,9 +652,10 @@ __global__ __launch_bounds__(TILE) void k_cheb_zero(const PatchLev* L, const Til
 }
 
 // Width of a row of the nested prolongation (knot insertion at every element
-// midpoint): a fine B-spline of degree p is a combination of at most
-// (p + 1) / 2 + 1 consecutive coarse ones (a coarse one spans p + 2 fine ones:
-// the restriction's width).
+// midpoint): a fine coefficient of degree p is a combination of at most
+// (p + 1) / 2 + 1 consecutive coarse coefficients, while a coarse B-spline is
+// a combination of p + 2 fine ones (a column of the prolongation: the
+// restriction's width).
 __host__ __device__ constexpr int prol_width(int p) { return (p + 1) / 2 + 1; }
 
 template <int PA, int PB, bool PROL, typename T>
