@@ -91,6 +91,32 @@ def test_prolongation_is_exact_refinement(p):
     np.testing.assert_allclose(nz, [comb(p + 1, j) / 2 ** p for j in range(p + 2)], atol=1e-13)
 
 
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("graded", [False, True])
+def test_prolongation_band_widths(p, graded):
+    """Midpoint refinement: a row of the prolongation (one fine coefficient) has at most (p + 1) // 2 + 1
+    consecutive nonzero entries, a column (one coarse B-spline) p + 2: the widths the device transfer tables
+    hold, also for non-uniform breakpoints."""
+    for nel in (6, 8, 12, 16):
+        if graded:
+            b = np.linspace(0.0, 1.0, nel // 2 + 1) ** 2          # coarse breakpoints, graded
+            mids = 0.5 * (b[1:] + b[:-1])
+            br = np.sort(np.concatenate([b, mids]))
+            fine = np.concatenate([np.zeros(p), br, np.ones(p)])
+        else:
+            fine = uniform_open_knots(nel, p)
+        coarse = bspline.coarsen_knots(fine, p)
+        P = bspline.prolongation(coarse, fine, p)
+        nz = np.abs(P) > 1e-14
+        for row in nz:
+            idx = np.nonzero(row)[0]
+            assert idx.max() - idx.min() + 1 <= (p + 1) // 2 + 1
+            assert len(idx) == idx.max() - idx.min() + 1
+        for col in nz.T:
+            idx = np.nonzero(col)[0]
+            assert idx.max() - idx.min() + 1 <= p + 2
+
+
 @pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 8])
 def test_gauss_exactness(n):
     x, w = assembly.gauss01(n)
