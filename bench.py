@@ -297,6 +297,8 @@ def main():
                          "-1: every level by batched launches)")
     ap.add_argument("--coarse-dofs", type=int, default=0,
                     help="largest multigrid level solved by its dense inverse (0: the library's default)")
+    ap.add_argument("--prec-vcycles", type=int, default=0,
+                    help="V-cycles per Dirichlet solve in the preconditioner (0: the library's default)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 512 MiB FP64 tensor 3 times (scale for the FETCH_SIZE/WRITE_SIZE counters)")
     args = ap.parse_args()
@@ -342,6 +344,8 @@ def main():
         extra_opt["cheb_degree_coarse"] = args.cheb_coarse
     if args.coarse_dofs:
         extra_opt["coarse_dofs"] = args.coarse_dofs
+    if args.prec_vcycles:
+        extra_opt["prec_vcycles"] = args.prec_vcycles
     m = measure(wl, gname, args.steps, args.warmup, local_solver=variant, mg_precision=args.precision, **extra_opt)
     ms_per_step = m["ms_per_step"]
     value = wl.ndof_torn / (ms_per_step * 1e-3) / 1e6
